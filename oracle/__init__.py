@@ -1,0 +1,279 @@
+"""Oracle: plain FP64 CPU PIC step (test infrastructure only).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The product library never loads it and
+it shares no code with the HIP path; both sides take their inputs from the
+seeded workload generator, which holds none of the method's arithmetic.
+
+The C source ``orc.c`` is the oracle; this module is a ctypes wrapper around
+it.  ``build()`` compiles it with gcc (plain ``-O2``, no fast-math).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "orc.c")
+_LIB = os.path.join(_HERE, "liborc.so")
+
+COMPONENTS = ("Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz")
+
+
+def build(force: bool = True) -> str:
+    """Compile orc.c into liborc.so next to it and return the path."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Desc(C.Structure):
+    _fields_ = [
+        ("ndim", C.c_int),
+        ("n", C.c_int * 3),
+        ("d", C.c_double * 3),
+        ("dt", C.c_double),
+        ("patch", C.c_int * 3),
+        ("periodic", C.c_int * 3),
+        ("q", C.c_double),
+        ("m", C.c_double),
+    ]
+
+
+_lib = None
+_D = C.POINTER(C.c_double)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build(force=False)
+    lib = C.CDLL(_LIB)
+    vp = C.c_void_p
+    sig = {
+        "orc_create": (vp, [C.POINTER(_Desc)]),
+        "orc_destroy": (None, [vp]),
+        "orc_fsize": (C.c_int64, [vp]),
+        "orc_npatch": (C.c_int, [vp]),
+        "orc_npart": (C.c_int64, [vp]),
+        "orc_step_index": (C.c_int64, [vp]),
+        "orc_removed": (C.c_int64, [vp]),
+        "orc_set_step": (None, [vp, C.c_int64]),
+        "orc_set_particles": (C.c_int, [vp, C.c_int64, _D * 3, _D * 3, _D]),
+        "orc_get_particles": (None, [vp, _D * 3, _D * 3, _D, C.POINTER(C.c_int64)]),
+        "orc_get_counts": (None, [vp, C.POINTER(C.c_int32)]),
+        "orc_get_field": (None, [vp, C.c_int, _D]),
+        "orc_set_field": (None, [vp, C.c_int, _D]),
+        "orc_set_laser": (None, [vp, C.c_int64, _D, _D]),
+        "orc_step": (None, [vp, C.c_int64]),
+        "orc_energy": (None, [vp, _D, _D]),
+        "orc_field_energy": (C.c_double, [vp]),
+        "orc_rho": (None, [vp, _D]),
+        "orc_maxwell": (None, [vp]),
+        "orc_deposit": (None, [vp, _D, _D, C.c_double, C.c_double]),
+        "orc_gather": (None, [vp, _D, _D]),
+        "orc_boris": (None, [_D, _D, _D, C.c_double, C.c_double, C.c_double]),
+        "orc_shape": (None, [C.c_double, C.c_int, C.POINTER(C.c_int64), _D]),
+        "orc_s2": (C.c_double, [C.c_double]),
+        "orc_patch_of": (C.c_int, [vp, _D]),
+        "orc_rebin": (None, [C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                             C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(_D)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ---------------------------------------------------------------------------
+# operator-level entry points (used by the pins)
+
+def s2(delta: float) -> float:
+    """Quadratic B-spline S2(delta) from its piecewise definition."""
+    return _load().orc_s2(float(delta))
+
+
+def shape(xi: float, stag: int):
+    """(i0, [w-1, w0, w+1]) for a sample staggered by stag/2 cells."""
+    i0 = C.c_int64()
+    w = np.zeros(3)
+    _load().orc_shape(float(xi), int(stag), C.byref(i0), _dp(w))
+    return i0.value, w
+
+
+def boris(u, E, B, q: float, m: float, dt: float) -> np.ndarray:
+    """One relativistic Boris update of u = p/(mc) under fields E, B."""
+    uu = _f64(np.array(u, dtype=np.float64).copy())
+    EE = _f64(E)
+    BB = _f64(B)
+    _load().orc_boris(_dp(uu), _dp(EE), _dp(BB), float(q), float(m), float(dt))
+    return uu
+
+
+def rebin(counts, dest):
+    """Canonical re-binning.  Returns (newcount, src) with src[k'] the old
+    flat index of the particle placed at new flat index k'."""
+    counts = np.ascontiguousarray(counts, dtype=np.int32)
+    dest = np.ascontiguousarray(dest, dtype=np.int32)
+    npatch = counts.size
+    newcount = np.zeros(npatch, dtype=np.int32)
+    kept = int(np.count_nonzero(dest >= 0))
+    src = np.full(max(kept, 1), -1, dtype=np.int64)
+    _load().orc_rebin(npatch, counts.ctypes.data_as(C.POINTER(C.c_int32)),
+                      dest.ctypes.data_as(C.POINTER(C.c_int32)),
+                      newcount.ctypes.data_as(C.POINTER(C.c_int32)),
+                      src.ctypes.data_as(C.POINTER(C.c_int64)))
+    return newcount, src[:kept]
+
+
+class Sim:
+    """One oracle simulation (FP64, global arrays, patch-list particle view).
+
+    Geometry keys of ``cfg``: ndim, n (cells per axis), d (cell sizes), dt,
+    patch (cells per patch per axis), periodic (per axis; only x may be open),
+    q, m.  Particle arrays are given in id order.
+    """
+
+    def __init__(self, cfg: dict):
+        lib = _load()
+        nd = int(cfg["ndim"])
+        n = list(cfg["n"]) + [1] * (3 - len(cfg["n"]))
+        d = list(cfg["d"]) + [1.0] * (3 - len(cfg["d"]))
+        patch = list(cfg["patch"]) + [1] * (3 - len(cfg["patch"]))
+        per = list(cfg.get("periodic", [1, 1, 1])) + [1] * 3
+        desc = _Desc(nd, (C.c_int * 3)(*n), (C.c_double * 3)(*d), float(cfg["dt"]),
+                     (C.c_int * 3)(*patch), (C.c_int * 3)(*[int(p) for p in per[:3]]),
+                     float(cfg.get("q", -1.0)), float(cfg.get("m", 1.0)))
+        self._p = lib.orc_create(C.byref(desc))
+        if not self._p:
+            raise ValueError("oracle: invalid geometry")
+        self.cfg = dict(cfg)
+        self.ndim = nd
+        self.n = n
+        self.periodic = per[:3]
+        self.fn = [n[a] if (a >= nd or per[a]) else n[a] + 1 for a in range(3)]
+        if nd == 2:
+            self.fn[2] = 1
+        self.fsize = lib.orc_fsize(self._p)
+        self.npatch = lib.orc_npatch(self._p)
+
+    def __del__(self):
+        p = getattr(self, "_p", None)
+        if p and _lib is not None:
+            _lib.orc_destroy(p)
+            self._p = None
+
+    # -- state ----------------------------------------------------------
+    def set_particles(self, x, u, w):
+        x = [_f64(a) for a in x] + [np.zeros(len(w))] * (3 - len(x))
+        u = [_f64(a) for a in u]
+        w = _f64(w)
+        rc = _load().orc_set_particles(self._p, len(w), (_D * 3)(*[_dp(a) for a in x]),
+                                       (_D * 3)(*[_dp(a) for a in u]), _dp(w))
+        if rc != 0:
+            raise ValueError("oracle: particle outside the domain")
+        self._keep = (x, u, w)
+
+    def particles(self):
+        """(x[3], u[3], w, id) in canonical (patch, slot) order."""
+        n = _load().orc_npart(self._p)
+        x = [np.zeros(n) for _ in range(3)]
+        u = [np.zeros(n) for _ in range(3)]
+        w = np.zeros(n)
+        ids = np.zeros(n, dtype=np.int64)
+        _load().orc_get_particles(self._p, (_D * 3)(*[_dp(a) for a in x]),
+                                  (_D * 3)(*[_dp(a) for a in u]), _dp(w),
+                                  ids.ctypes.data_as(C.POINTER(C.c_int64)))
+        return x, u, w, ids
+
+    def counts(self) -> np.ndarray:
+        c = np.zeros(self.npatch, dtype=np.int32)
+        _load().orc_get_counts(self._p, c.ctypes.data_as(C.POINTER(C.c_int32)))
+        return c
+
+    def field(self, comp) -> np.ndarray:
+        """Field component as an array shaped (fn_z, fn_y, fn_x) (x fastest)."""
+        c = COMPONENTS.index(comp) if isinstance(comp, str) else int(comp)
+        out = np.zeros(self.fsize)
+        _load().orc_get_field(self._p, c, _dp(out))
+        return out.reshape(self.fn[2], self.fn[1], self.fn[0])
+
+    def set_field(self, comp, values):
+        c = COMPONENTS.index(comp) if isinstance(comp, str) else int(comp)
+        v = _f64(np.asarray(values).reshape(-1))
+        assert v.size == self.fsize
+        _load().orc_set_field(self._p, c, _dp(v))
+
+    def set_laser(self, ey=None, ez=None):
+        """Incident-field table, shape (steps, transverse nodes)."""
+        arrs = [None if a is None else _f64(a) for a in (ey, ez)]
+        nsteps = next(a.shape[0] for a in arrs if a is not None)
+        ptrs = [None if a is None else _dp(a) for a in arrs]
+        _load().orc_set_laser(self._p, nsteps, ptrs[0], ptrs[1])
+
+    def rho(self) -> np.ndarray:
+        out = np.zeros(self.fsize)
+        _load().orc_rho(self._p, _dp(out))
+        return out.reshape(self.fn[2], self.fn[1], self.fn[0])
+
+    # -- evolution --------------------------------------------------------
+    def step(self, nsteps: int = 1):
+        _load().orc_step(self._p, int(nsteps))
+
+    def maxwell(self):
+        """Three-sweep Yee update with the current J and laser row."""
+        _load().orc_maxwell(self._p)
+
+    def deposit(self, xa, xb, w, vz):
+        a = _f64(list(xa) + [0.0] * (3 - len(xa)))
+        b = _f64(list(xb) + [0.0] * (3 - len(xb)))
+        _load().orc_deposit(self._p, _dp(a), _dp(b), float(w), float(vz))
+
+    def gather(self, xi) -> np.ndarray:
+        a = _f64(list(xi) + [0.0] * (3 - len(xi)))
+        out = np.zeros(6)
+        _load().orc_gather(self._p, _dp(a), _dp(out))
+        return out
+
+    def patch_of(self, xi) -> int:
+        a = _f64(list(xi) + [0.0] * (3 - len(xi)))
+        return _load().orc_patch_of(self._p, _dp(a))
+
+    @property
+    def step_index(self) -> int:
+        return _load().orc_step_index(self._p)
+
+    def set_step(self, n: int):
+        _load().orc_set_step(self._p, int(n))
+
+    @property
+    def removed(self) -> int:
+        return _load().orc_removed(self._p)
+
+    def energy(self):
+        """(U(E^n, B^n), K^n) of the last completed step n."""
+        U = C.c_double()
+        K = C.c_double()
+        _load().orc_energy(self._p, C.byref(U), C.byref(K))
+        return U.value, K.value
+
+    def field_energy(self) -> float:
+        return _load().orc_field_energy(self._p)

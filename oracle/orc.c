@@ -1,0 +1,731 @@
+/*
+ * Oracle: a plain, slow FP64 CPU implementation of one electromagnetic
+ * particle-in-cell step on a patch-decomposed Yee grid.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the tests, the smoke check and the CPU-baseline leg
+ * of the benchmark do.  It shares no code, header or table with the HIP path.
+ *
+ * What the paper fixes and what it leaves open.  The paper (Beck, Frederiksen
+ * and Derouillat, sections 3 and 3.1) describes the load-balancing problem and
+ * the patch data structure (fields and super-particles of a sub-domain held in
+ * small independent patches), but never writes down the PIC step itself.  The
+ * step implemented here is therefore the standard explicit scheme, each piece
+ * following its published method:
+ *   - quadratic B-spline shape factors for gather and charge (Birdsall and
+ *     Langdon, "Plasma Physics via Computer Simulation", ch. 8);
+ *   - the relativistic Boris rotation (Boris 1970);
+ *   - charge-conserving current deposition (Esirkepov 2001, Comput. Phys.
+ *     Commun. 135, 144), written as the time integral of linearly
+ *     interpolated shape products;
+ *   - the Yee staggered-grid FDTD update (Yee 1966, IEEE TAP 14, 302), as a
+ *     half B step, a full E step and a half B step;
+ *   - first-order Silver-Mueller characteristic boundaries on the x faces,
+ *     with an incident-field table driving the x = 0 face (the laser of the
+ *     paper's LWFA runs, section 2.2);
+ *   - a canonical per-patch re-binning rule (see orc_rebin) that fixes the
+ *     patch occupancy and the slot of every particle bit for bit.
+ *
+ * Units: c = eps0 = e = m_e = 1; lengths in c/omega_r, time in 1/omega_r
+ * (section 2.2 quotes resolutions in c/omega_0 and 1/omega_0).  Positions are
+ * kept in cell units xi = x / dx, global, in FP64.
+ *
+ * Functions follow the step order: gather, Boris, move, deposit, boundary,
+ * Maxwell, re-bin.  Everything is plain loops in FP64.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_NCOMP 9 /* Ex Ey Ez Bx By Bz Jx Jy Jz */
+
+typedef struct {
+    int ndim;         /* 2 or 3 */
+    int n[3];         /* cells per axis (n[2] = 1 in 2-D) */
+    double d[3];      /* cell size per axis */
+    double dt;
+    int patch[3];     /* patch size in cells per axis */
+    int periodic[3];  /* 1 periodic; 0 open (x only): Silver-Mueller fields, absorbing particles */
+    double q, m;      /* species charge and mass (electrons: -1, 1) */
+} orc_desc;
+
+typedef struct {
+    orc_desc g;
+    int fn[3];        /* nodes stored per axis: n (periodic) or n + 1 (open) */
+    int np[3];        /* patches per axis */
+    int npatch;
+    int64_t fsize;
+    double *F[ORC_NCOMP];
+    int64_t npart;
+    double *x[3], *u[3], *w;
+    int64_t *id;
+    int32_t *count;
+    int64_t laser_steps;
+    int laser_n1;     /* transverse nodes per table row (n[1] * n[2]) */
+    double *laser_ey, *laser_ez;
+    int64_t step;
+    double U_last, K_last;
+    int64_t removed;
+} orc_sim;
+
+/* Staggering of Ex Ey Ez Bx By Bz (J shares E's): 1 = half a cell up. */
+static const int STAG[6][3] = {
+    {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {0, 1, 1}, {1, 0, 1}, {1, 1, 0}};
+
+static int stag_of(const orc_sim *s, int comp, int a)
+{
+    if (a >= s->g.ndim) return 0;
+    return STAG[comp < 6 ? comp : comp - 6][a];
+}
+
+/* Map a node index on axis a to storage, or -1 when it lies outside an open
+ * axis (values there read as zero, deposits there are dropped). */
+static int64_t node_index(const orc_sim *s, int a, int64_t i, int stag)
+{
+    int n = s->g.n[a];
+    if (a >= s->g.ndim) return 0;
+    if (s->g.periodic[a]) {
+        i %= n;
+        if (i < 0) i += n;
+        return i;
+    }
+    if (i < 0) return -1;
+    if (stag ? i > n - 1 : i > n) return -1;
+    return i;
+}
+
+static int64_t flat3(const orc_sim *s, int comp, int64_t i, int64_t j, int64_t k)
+{
+    int64_t a = node_index(s, 0, i, stag_of(s, comp, 0));
+    int64_t b = node_index(s, 1, j, stag_of(s, comp, 1));
+    int64_t c = node_index(s, 2, k, stag_of(s, comp, 2));
+    if (a < 0 || b < 0 || c < 0) return -1;
+    return a + (int64_t)s->fn[0] * (b + (int64_t)s->fn[1] * c);
+}
+
+static double fget(const orc_sim *s, int comp, int64_t i, int64_t j, int64_t k)
+{
+    int64_t f = flat3(s, comp, i, j, k);
+    return f < 0 ? 0.0 : s->F[comp][f];
+}
+
+/* ---------------------------------------------------------------------- */
+/* Quadratic B-spline shape (Birdsall-Langdon).                            */
+
+/* S2(delta): 3/4 - d^2 for |d| <= 1/2; (3/2 - |d|)^2 / 2 for 1/2 <= |d| <= 3/2. */
+double orc_s2(double dl)
+{
+    double a = fabs(dl);
+    if (a <= 0.5) return 0.75 - a * a;
+    if (a <= 1.5) return 0.5 * (1.5 - a) * (1.5 - a);
+    return 0.0;
+}
+
+/* Nearest node and the three weights for a sample staggered by stag/2. */
+void orc_shape(double xi, int stag, int64_t *i0, double w[3])
+{
+    double p = xi - 0.5 * stag;
+    int64_t c = (int64_t)floor(p + 0.5);
+    double dl = p - (double)c;
+    *i0 = c;
+    w[0] = 0.5 * (0.5 - dl) * (0.5 - dl);
+    w[1] = 0.75 - dl * dl;
+    w[2] = 0.5 * (0.5 + dl) * (0.5 + dl);
+}
+
+/* Field gather: F_c(x_p) = sum over the 3^ndim nearest nodes of the
+ * component's own staggered grid of F * product of shape weights. */
+void orc_gather(const orc_sim *s, const double xi[3], double EB[6])
+{
+    for (int c = 0; c < 6; ++c) {
+        int64_t i0[3] = {0, 0, 0};
+        double w[3][3];
+        for (int a = 0; a < 3; ++a) {
+            if (a < s->g.ndim) {
+                orc_shape(xi[a], stag_of(s, c, a), &i0[a], w[a]);
+            } else {
+                w[a][0] = 0.0; w[a][1] = 1.0; w[a][2] = 0.0;
+            }
+        }
+        double acc = 0.0;
+        int kz0 = s->g.ndim == 3 ? -1 : 0, kz1 = s->g.ndim == 3 ? 1 : 0;
+        for (int kz = kz0; kz <= kz1; ++kz)
+            for (int ky = -1; ky <= 1; ++ky)
+                for (int kx = -1; kx <= 1; ++kx)
+                    acc += fget(s, c, i0[0] + kx, i0[1] + ky, i0[2] + kz)
+                         * w[0][kx + 1] * w[1][ky + 1] * w[2][kz + 1];
+        EB[c] = acc;
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Relativistic Boris push (Boris 1970): half electric kick, magnetic
+ * rotation, half electric kick.  u = p / (m c). */
+void orc_boris(double u[3], const double E[3], const double B[3],
+               double q, double m, double dt)
+{
+    double eps = q * dt / (2.0 * m);
+    double um[3], t[3], sv[3], up[3], uq[3];
+    for (int a = 0; a < 3; ++a) um[a] = u[a] + eps * E[a];
+    double g = sqrt(1.0 + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
+    for (int a = 0; a < 3; ++a) t[a] = eps * B[a] / g;
+    double t2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+    for (int a = 0; a < 3; ++a) sv[a] = 2.0 * t[a] / (1.0 + t2);
+    /* u' = u- + u- x t */
+    up[0] = um[0] + (um[1] * t[2] - um[2] * t[1]);
+    up[1] = um[1] + (um[2] * t[0] - um[0] * t[2]);
+    up[2] = um[2] + (um[0] * t[1] - um[1] * t[0]);
+    /* u+ = u- + u' x s */
+    uq[0] = um[0] + (up[1] * sv[2] - up[2] * sv[1]);
+    uq[1] = um[1] + (up[2] * sv[0] - up[0] * sv[2]);
+    uq[2] = um[2] + (up[0] * sv[1] - up[1] * sv[0]);
+    for (int a = 0; a < 3; ++a) u[a] = uq[a] + eps * E[a];
+}
+
+/* ---------------------------------------------------------------------- */
+/* Esirkepov charge-conserving deposition.
+ *
+ * Per axis, i0 is the nearest primal node of the old position; on the
+ * five-node window i0-2..i0+2, S0 holds the old weights and S1 the new ones
+ * (shifted by the change of nearest node), DS = S1 - S0.  The W factors are
+ * the time integrals over the step of the products of linearly interpolated
+ * shape factors; the current along an axis is the running sum of -q w
+ * (dx/dt) W along that axis.  In 2-D the out-of-plane current is
+ * q w v_z W_z with W_z the time-averaged shape product. */
+static void window_weights(double x0, double x1, int64_t *i0, double S0[5], double DS[5])
+{
+    int64_t c0, c1;
+    double w0[3], w1[3], S1[5];
+    orc_shape(x0, 0, &c0, w0);
+    orc_shape(x1, 0, &c1, w1);
+    int64_t sh = c1 - c0; /* -1, 0 or +1 when the move is under one cell */
+    for (int k = 0; k < 5; ++k) { S0[k] = 0.0; S1[k] = 0.0; }
+    for (int k = -1; k <= 1; ++k) S0[k + 2] = w0[k + 1];
+    for (int k = -1; k <= 1; ++k) {
+        int64_t slot = k + sh + 2;
+        if (slot >= 0 && slot < 5) S1[slot] = w1[k + 1];
+    }
+    for (int k = 0; k < 5; ++k) DS[k] = S1[k] - S0[k];
+    *i0 = c0;
+}
+
+static void jadd(orc_sim *s, int comp, int64_t i, int64_t j, int64_t k, double v)
+{
+    int64_t f = flat3(s, comp, i, j, k);
+    if (f >= 0) s->F[comp][f] += v;
+}
+
+void orc_deposit(orc_sim *s, const double xa[3], const double xb[3], double w, double vz)
+{
+    const int nd = s->g.ndim;
+    const double q = s->g.q, dt = s->g.dt;
+    int64_t i0[3] = {0, 0, 0};
+    double S0[3][5], DS[3][5];
+    for (int a = 0; a < nd; ++a) window_weights(xa[a], xb[a], &i0[a], S0[a], DS[a]);
+    if (nd == 2) {
+        double Wx[5][5], Wy[5][5], Wz[5][5];
+        for (int i = 0; i < 5; ++i)
+            for (int j = 0; j < 5; ++j) {
+                Wx[i][j] = DS[0][i] * (S0[1][j] + 0.5 * DS[1][j]);
+                Wy[i][j] = DS[1][j] * (S0[0][i] + 0.5 * DS[0][i]);
+                Wz[i][j] = S0[0][i] * S0[1][j] + 0.5 * DS[0][i] * S0[1][j]
+                         + 0.5 * S0[0][i] * DS[1][j] + DS[0][i] * DS[1][j] / 3.0;
+            }
+        double cx = -q * w * s->g.d[0] / dt, cy = -q * w * s->g.d[1] / dt;
+        for (int j = 0; j < 5; ++j) {
+            double acc = 0.0;
+            for (int i = 0; i < 4; ++i) { /* dual node i0 + (i - 2) + 1/2 */
+                acc += cx * Wx[i][j];
+                jadd(s, 6, i0[0] + i - 2, i0[1] + j - 2, 0, acc);
+            }
+        }
+        for (int i = 0; i < 5; ++i) {
+            double acc = 0.0;
+            for (int j = 0; j < 4; ++j) {
+                acc += cy * Wy[i][j];
+                jadd(s, 7, i0[0] + i - 2, i0[1] + j - 2, 0, acc);
+            }
+        }
+        for (int i = 0; i < 5; ++i)
+            for (int j = 0; j < 5; ++j)
+                jadd(s, 8, i0[0] + i - 2, i0[1] + j - 2, 0, q * w * vz * Wz[i][j]);
+        return;
+    }
+    /* 3-D: W_a = DS_a (S0_b S0_c + DS_b S0_c / 2 + S0_b DS_c / 2 + DS_b DS_c / 3) */
+    for (int a = 0; a < 3; ++a) {
+        int b = (a + 1) % 3, c = (a + 2) % 3;
+        double coef = -q * w * s->g.d[a] / dt;
+        for (int kb = 0; kb < 5; ++kb)
+            for (int kc = 0; kc < 5; ++kc) {
+                double tr = S0[b][kb] * S0[c][kc] + 0.5 * DS[b][kb] * S0[c][kc]
+                          + 0.5 * S0[b][kb] * DS[c][kc] + DS[b][kb] * DS[c][kc] / 3.0;
+                double acc = 0.0;
+                for (int ka = 0; ka < 4; ++ka) {
+                    acc += coef * DS[a][ka] * tr;
+                    int64_t idx[3];
+                    idx[a] = i0[a] + ka - 2;
+                    idx[b] = i0[b] + kb - 2;
+                    idx[c] = i0[c] + kc - 2;
+                    jadd(s, 6 + a, idx[0], idx[1], idx[2], acc);
+                }
+            }
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Yee update.  E updates use backward differences of B, B updates forward
+ * differences of E.  On an open x axis the E update at x = 0 and x = L
+ * needs By and Bz half a cell outside the domain; they come from the
+ * first-order characteristic (Silver-Mueller) condition written at the face
+ * and at time n + 1/2, combined with the 1-D part of the E update:
+ *   x = 0 (incoming E_inc):  Ey + Bz = 2 Ey_inc,  Ez - By = 2 Ez_inc
+ *   x = L (outflow):         Ey - Bz = 0,         Ez + By = 0
+ * With r = dt/dx, B_1 the first interior dual B and E^n the face E:
+ *   Bz_ghost(0) = (4 Ey_inc - 2 Ey^n - (1 - r) Bz_1) / (1 + r)
+ *   By_ghost(0) = (2 Ez^n - (1 - r) By_1 - 4 Ez_inc) / (1 + r)
+ *   Bz_ghost(L) = (2 Ey^n - (1 - r) Bz_1) / (1 + r)
+ *   By_ghost(L) = (-2 Ez^n - (1 - r) By_1) / (1 + r)
+ * (transverse derivative terms are left out of the condition). */
+
+static void b_half(orc_sim *s)
+{
+    const double h = 0.5 * s->g.dt;
+    const double ix = 1.0 / s->g.d[0], iy = 1.0 / s->g.d[1];
+    const double iz = s->g.ndim == 3 ? 1.0 / s->g.d[2] : 0.0;
+    const int nz = s->fn[2];
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < s->fn[1]; ++j)
+            for (int64_t i = 0; i < s->fn[0]; ++i) {
+                int64_t f;
+                /* Bx -= h (dEz/dy - dEy/dz) */
+                if ((f = flat3(s, 3, i, j, k)) >= 0)
+                    s->F[3][f] -= h * ((fget(s, 2, i, j + 1, k) - fget(s, 2, i, j, k)) * iy
+                                     - (fget(s, 1, i, j, k + 1) - fget(s, 1, i, j, k)) * iz);
+                /* By -= h (dEx/dz - dEz/dx) */
+                if ((f = flat3(s, 4, i, j, k)) >= 0)
+                    s->F[4][f] -= h * ((fget(s, 0, i, j, k + 1) - fget(s, 0, i, j, k)) * iz
+                                     - (fget(s, 2, i + 1, j, k) - fget(s, 2, i, j, k)) * ix);
+                /* Bz -= h (dEy/dx - dEx/dy) */
+                if ((f = flat3(s, 5, i, j, k)) >= 0)
+                    s->F[5][f] -= h * ((fget(s, 1, i + 1, j, k) - fget(s, 1, i, j, k)) * ix
+                                     - (fget(s, 0, i, j + 1, k) - fget(s, 0, i, j, k)) * iy);
+            }
+}
+
+static double laser_row(const orc_sim *s, const double *tab, int64_t j, int64_t k)
+{
+    if (!tab || s->step >= s->laser_steps) return 0.0;
+    return tab[s->step * s->laser_n1 + j + (int64_t)s->g.n[1] * k];
+}
+
+void orc_maxwell(orc_sim *s)
+{
+    const double dt = s->g.dt;
+    const double ix = 1.0 / s->g.d[0], iy = 1.0 / s->g.d[1];
+    const double iz = s->g.ndim == 3 ? 1.0 / s->g.d[2] : 0.0;
+    const int nx = s->g.n[0], nz = s->fn[2];
+    const int64_t ntr = (int64_t)s->fn[1] * nz;
+
+    b_half(s);
+
+    /* ghost By, Bz half a cell outside each open x face, at time n + 1/2 */
+    double *gby0 = NULL, *gbz0 = NULL, *gby1 = NULL, *gbz1 = NULL;
+    if (!s->g.periodic[0]) {
+        const double r = dt * ix;
+        gby0 = calloc(ntr, sizeof(double)); gbz0 = calloc(ntr, sizeof(double));
+        gby1 = calloc(ntr, sizeof(double)); gbz1 = calloc(ntr, sizeof(double));
+        for (int64_t k = 0; k < nz; ++k)
+            for (int64_t j = 0; j < s->fn[1]; ++j) {
+                int64_t t = j + s->fn[1] * k;
+                double eyi = laser_row(s, s->laser_ey, j, k);
+                double ezi = laser_row(s, s->laser_ez, j, k);
+                gbz0[t] = (4.0 * eyi - 2.0 * fget(s, 1, 0, j, k) - (1.0 - r) * fget(s, 5, 0, j, k)) / (1.0 + r);
+                gby0[t] = (2.0 * fget(s, 2, 0, j, k) - (1.0 - r) * fget(s, 4, 0, j, k) - 4.0 * ezi) / (1.0 + r);
+                gbz1[t] = (2.0 * fget(s, 1, nx, j, k) - (1.0 - r) * fget(s, 5, nx - 1, j, k)) / (1.0 + r);
+                gby1[t] = (-2.0 * fget(s, 2, nx, j, k) - (1.0 - r) * fget(s, 4, nx - 1, j, k)) / (1.0 + r);
+            }
+    }
+    /* B accessor that supplies the ghosts for the dual-x components */
+#define BGET(c, i, j, k) ( (!s->g.periodic[0] && ((c) == 4 || (c) == 5) && ((i) < 0 || (i) > nx - 1)) \
+        ? ((i) < 0 ? ((c) == 4 ? gby0 : gbz0)[(j) + s->fn[1] * (k)]                                  \
+                   : ((c) == 4 ? gby1 : gbz1)[(j) + s->fn[1] * (k)])                                 \
+        : fget(s, (c), (i), (j), (k)) )
+
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < s->fn[1]; ++j)
+            for (int64_t i = 0; i < s->fn[0]; ++i) {
+                int64_t f;
+                int64_t km = k - 1;
+                /* Ex += dt (dBz/dy - dBy/dz - Jx) */
+                if ((f = flat3(s, 0, i, j, k)) >= 0)
+                    s->F[0][f] += dt * ((BGET(5, i, j, k) - BGET(5, i, j - 1, k)) * iy
+                                      - (s->g.ndim == 3 ? (BGET(4, i, j, k) - BGET(4, i, j, km)) * iz : 0.0)
+                                      - s->F[6][f]);
+                /* Ey += dt (dBx/dz - dBz/dx - Jy) */
+                if ((f = flat3(s, 1, i, j, k)) >= 0)
+                    s->F[1][f] += dt * ((s->g.ndim == 3 ? (BGET(3, i, j, k) - BGET(3, i, j, km)) * iz : 0.0)
+                                      - (BGET(5, i, j, k) - BGET(5, i - 1, j, k)) * ix
+                                      - s->F[7][f]);
+                /* Ez += dt (dBy/dx - dBx/dy - Jz) */
+                if ((f = flat3(s, 2, i, j, k)) >= 0)
+                    s->F[2][f] += dt * ((BGET(4, i, j, k) - BGET(4, i - 1, j, k)) * ix
+                                      - (BGET(3, i, j, k) - BGET(3, i, j - 1, k)) * iy
+                                      - s->F[8][f]);
+            }
+#undef BGET
+    free(gby0); free(gbz0); free(gby1); free(gbz1);
+
+    b_half(s);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Canonical re-binning.
+ *
+ * Patch P holds slots 0..n-1.  Lv are the slots whose particle leaves P
+ * (or is removed), L = |Lv|; Ar are the particles arriving at P ordered by
+ * (source patch id, source slot); n' = n - L + A.  H are the leaver slots
+ * below n' (ascending), T the stayer slots in [n', n) (ascending).  The
+ * fill sequence F = Ar followed by T goes into H in order, and what is left
+ * of F goes to slots n, n+1, ...  Stayers below n' that are not holes keep
+ * their slots.
+ *
+ * count[p] old occupancy; dest[k] for every old particle k (flat,
+ * patch-major order) is its new patch id, or -1 when removed.  On return
+ * newcount[q] is the new occupancy and src[k'] gives, for every new flat
+ * index k', the old flat index of the particle placed there. */
+void orc_rebin(int npatch, const int32_t *count, const int32_t *dest,
+               int32_t *newcount, int64_t *src)
+{
+    int64_t *off = malloc(sizeof(int64_t) * (npatch + 1));
+    int64_t *arr_n = calloc(npatch, sizeof(int64_t));
+    off[0] = 0;
+    for (int p = 0; p < npatch; ++p) off[p + 1] = off[p] + count[p];
+    int64_t N = off[npatch];
+    /* arrivals per destination, in (source patch, source slot) order */
+    for (int p = 0; p < npatch; ++p)
+        for (int64_t k = off[p]; k < off[p + 1]; ++k)
+            if (dest[k] >= 0 && dest[k] != p) arr_n[dest[k]]++;
+    int64_t *arr_off = malloc(sizeof(int64_t) * (npatch + 1));
+    arr_off[0] = 0;
+    for (int p = 0; p < npatch; ++p) arr_off[p + 1] = arr_off[p] + arr_n[p];
+    int64_t *arr = malloc(sizeof(int64_t) * (arr_off[npatch] + 1));
+    int64_t *fillpos = calloc(npatch, sizeof(int64_t));
+    for (int p = 0; p < npatch; ++p)
+        for (int64_t k = off[p]; k < off[p + 1]; ++k)
+            if (dest[k] >= 0 && dest[k] != p) {
+                int q = dest[k];
+                arr[arr_off[q] + fillpos[q]++] = k;
+            }
+    (void)N;
+    int64_t *newoff = malloc(sizeof(int64_t) * (npatch + 1));
+    newoff[0] = 0;
+    for (int q = 0; q < npatch; ++q) {
+        int64_t n = count[q], L = 0;
+        for (int64_t sl = 0; sl < n; ++sl)
+            if (dest[off[q] + sl] != q) ++L;
+        int64_t A = arr_n[q];
+        newcount[q] = (int32_t)(n - L + A);
+        newoff[q + 1] = newoff[q] + newcount[q];
+    }
+    for (int q = 0; q < npatch; ++q) {
+        int64_t n = count[q], np = newcount[q], A = arr_n[q];
+        int64_t *slot_src = src + newoff[q];
+        /* H: leaver slots below n'; T: stayer slots in [n', n) */
+        int64_t *H = malloc(sizeof(int64_t) * (n + 1));
+        int64_t *T = malloc(sizeof(int64_t) * (n + 1));
+        int64_t nh = 0, nt = 0;
+        for (int64_t sl = 0; sl < n; ++sl) {
+            int stays = dest[off[q] + sl] == q;
+            if (!stays && sl < np) H[nh++] = sl;
+            if (stays && sl >= np) T[nt++] = sl;
+            if (stays && sl < np) slot_src[sl] = off[q] + sl;
+        }
+        /* F = Ar ++ T */
+        int64_t nf = A + nt;
+        for (int64_t f = 0; f < nf; ++f) {
+            int64_t from = f < A ? arr[arr_off[q] + f] : off[q] + T[f - A];
+            int64_t to = f < nh ? H[f] : n + (f - nh);
+            slot_src[to] = from;
+        }
+        free(H);
+        free(T);
+    }
+    free(off); free(arr_n); free(arr_off); free(arr); free(fillpos); free(newoff);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Simulation object.                                                      */
+
+orc_sim *orc_create(const orc_desc *d)
+{
+    if (d->ndim != 2 && d->ndim != 3) return NULL;
+    orc_sim *s = calloc(1, sizeof(orc_sim));
+    s->g = *d;
+    if (s->g.ndim == 2) { s->g.n[2] = 1; s->g.patch[2] = 1; s->g.periodic[2] = 1; s->g.d[2] = 1.0; }
+    for (int a = 0; a < 3; ++a) {
+        if (s->g.n[a] <= 0 || s->g.patch[a] <= 0 || s->g.n[a] % s->g.patch[a]) { free(s); return NULL; }
+        if (a > 0 && !s->g.periodic[a]) { free(s); return NULL; } /* open faces only on x */
+        s->fn[a] = s->g.periodic[a] ? s->g.n[a] : s->g.n[a] + 1;
+        if (a >= s->g.ndim) s->fn[a] = 1;
+        s->np[a] = s->g.n[a] / s->g.patch[a];
+    }
+    s->npatch = s->np[0] * s->np[1] * s->np[2];
+    s->fsize = (int64_t)s->fn[0] * s->fn[1] * s->fn[2];
+    for (int c = 0; c < ORC_NCOMP; ++c) s->F[c] = calloc(s->fsize, sizeof(double));
+    s->count = calloc(s->npatch, sizeof(int32_t));
+    s->laser_n1 = s->g.n[1] * (s->g.ndim == 3 ? s->g.n[2] : 1);
+    return s;
+}
+
+static void free_particles(orc_sim *s)
+{
+    for (int a = 0; a < 3; ++a) { free(s->x[a]); free(s->u[a]); s->x[a] = s->u[a] = NULL; }
+    free(s->w); free(s->id); s->w = NULL; s->id = NULL;
+}
+
+void orc_destroy(orc_sim *s)
+{
+    if (!s) return;
+    for (int c = 0; c < ORC_NCOMP; ++c) free(s->F[c]);
+    free_particles(s);
+    free(s->count);
+    free(s->laser_ey); free(s->laser_ez);
+    free(s);
+}
+
+int64_t orc_fsize(const orc_sim *s) { return s->fsize; }
+int orc_npatch(const orc_sim *s) { return s->npatch; }
+int64_t orc_npart(const orc_sim *s) { return s->npart; }
+int64_t orc_step_index(const orc_sim *s) { return s->step; }
+int64_t orc_removed(const orc_sim *s) { return s->removed; }
+void orc_set_step(orc_sim *s, int64_t n) { s->step = n; }
+
+/* Patch of a position: floor of the cell coordinate divided by the patch
+ * size, row-major with x fastest. */
+static int patch_of(const orc_sim *s, const double xi[3])
+{
+    int pc[3] = {0, 0, 0};
+    for (int a = 0; a < s->g.ndim; ++a) {
+        int64_t c = (int64_t)floor(xi[a]);
+        if (c < 0) c = 0;
+        if (c > s->g.n[a] - 1) c = s->g.n[a] - 1;
+        pc[a] = (int)(c / s->g.patch[a]);
+    }
+    return pc[0] + s->np[0] * (pc[1] + s->np[1] * pc[2]);
+}
+
+int orc_patch_of(const orc_sim *s, const double xi[3]) { return patch_of(s, xi); }
+
+/* Load particles given in id order; the initial binning is the re-binning
+ * rule applied from empty patches, which keeps id order inside a patch. */
+int orc_set_particles(orc_sim *s, int64_t n, const double *const xs[3],
+                      const double *const us[3], const double *w)
+{
+    for (int64_t k = 0; k < n; ++k)
+        for (int a = 0; a < s->g.ndim; ++a)
+            if (!(xs[a][k] >= 0.0 && xs[a][k] < (double)s->g.n[a])) return -1;
+    free_particles(s);
+    s->npart = n;
+    for (int a = 0; a < 3; ++a) {
+        s->x[a] = malloc(sizeof(double) * (n + 1));
+        s->u[a] = malloc(sizeof(double) * (n + 1));
+    }
+    s->w = malloc(sizeof(double) * (n + 1));
+    s->id = malloc(sizeof(int64_t) * (n + 1));
+    memset(s->count, 0, sizeof(int32_t) * s->npatch);
+    int32_t *pid = malloc(sizeof(int32_t) * (n + 1));
+    for (int64_t k = 0; k < n; ++k) {
+        double xi[3] = {xs[0][k], xs[1][k], s->g.ndim == 3 ? xs[2][k] : 0.0};
+        pid[k] = patch_of(s, xi);
+        s->count[pid[k]]++;
+    }
+    int64_t *pos = malloc(sizeof(int64_t) * (s->npatch + 1));
+    pos[0] = 0;
+    for (int p = 0; p < s->npatch; ++p) pos[p + 1] = pos[p] + s->count[p];
+    for (int64_t k = 0; k < n; ++k) {
+        int64_t t = pos[pid[k]]++;
+        for (int a = 0; a < 3; ++a) {
+            s->x[a][t] = (a < s->g.ndim) ? xs[a][k] : 0.0;
+            s->u[a][t] = us[a][k];
+        }
+        s->w[t] = w[k];
+        s->id[t] = k;
+    }
+    free(pos);
+    free(pid);
+    return 0;
+}
+
+void orc_get_particles(const orc_sim *s, double *xo[3], double *uo[3], double *wo, int64_t *ido)
+{
+    for (int64_t k = 0; k < s->npart; ++k) {
+        for (int a = 0; a < 3; ++a) {
+            if (xo[a]) xo[a][k] = s->x[a][k];
+            if (uo[a]) uo[a][k] = s->u[a][k];
+        }
+        if (wo) wo[k] = s->w[k];
+        if (ido) ido[k] = s->id[k];
+    }
+}
+
+void orc_get_counts(const orc_sim *s, int32_t *out)
+{
+    memcpy(out, s->count, sizeof(int32_t) * s->npatch);
+}
+
+void orc_get_field(const orc_sim *s, int comp, double *out)
+{
+    memcpy(out, s->F[comp], sizeof(double) * s->fsize);
+}
+
+void orc_set_field(orc_sim *s, int comp, const double *in)
+{
+    memcpy(s->F[comp], in, sizeof(double) * s->fsize);
+}
+
+/* Incident-field table for the x = 0 face: row t holds the incident Ey and
+ * Ez on the transverse nodes at time (t + 1/2) dt (Ey sampled on its dual y
+ * positions, Ez on primal ones). */
+void orc_set_laser(orc_sim *s, int64_t nsteps, const double *ey, const double *ez)
+{
+    free(s->laser_ey); free(s->laser_ez);
+    s->laser_ey = s->laser_ez = NULL;
+    s->laser_steps = nsteps;
+    size_t sz = sizeof(double) * (size_t)(nsteps * s->laser_n1);
+    if (ey) { s->laser_ey = malloc(sz); memcpy(s->laser_ey, ey, sz); }
+    if (ez) { s->laser_ez = malloc(sz); memcpy(s->laser_ez, ez, sz); }
+}
+
+double orc_cell_volume(const orc_sim *s)
+{
+    double v = 1.0;
+    for (int a = 0; a < s->g.ndim; ++a) v *= s->g.d[a];
+    return v;
+}
+
+/* Field energy 1/2 sum (E^2 + B^2) V_cell over the stored (valid) nodes. */
+double orc_field_energy(const orc_sim *s)
+{
+    double acc = 0.0;
+    for (int c = 0; c < 6; ++c)
+        for (int64_t k = 0; k < s->fn[2]; ++k)
+            for (int64_t j = 0; j < s->fn[1]; ++j)
+                for (int64_t i = 0; i < s->fn[0]; ++i) {
+                    int64_t f = flat3(s, c, i, j, k);
+                    if (f >= 0) acc += s->F[c][f] * s->F[c][f];
+                }
+    return 0.5 * acc * orc_cell_volume(s);
+}
+
+/* Charge density q sum_p w_p prod_a S2 on primal nodes. */
+static int64_t primal_flat(const orc_sim *s, int64_t i, int64_t j, int64_t k)
+{
+    int64_t a = node_index(s, 0, i, 0), b = node_index(s, 1, j, 0), c = node_index(s, 2, k, 0);
+    if (a < 0 || b < 0 || c < 0) return -1;
+    return a + (int64_t)s->fn[0] * (b + (int64_t)s->fn[1] * c);
+}
+
+void orc_rho(const orc_sim *s, double *out)
+{
+    memset(out, 0, sizeof(double) * s->fsize);
+    for (int64_t p = 0; p < s->npart; ++p) {
+        int64_t i0[3] = {0, 0, 0};
+        double w[3][3];
+        for (int a = 0; a < 3; ++a) {
+            if (a < s->g.ndim) orc_shape(s->x[a][p], 0, &i0[a], w[a]);
+            else { w[a][0] = 0.0; w[a][1] = 1.0; w[a][2] = 0.0; }
+        }
+        int kz0 = s->g.ndim == 3 ? -1 : 0, kz1 = s->g.ndim == 3 ? 1 : 0;
+        for (int kz = kz0; kz <= kz1; ++kz)
+            for (int ky = -1; ky <= 1; ++ky)
+                for (int kx = -1; kx <= 1; ++kx) {
+                    int64_t f = primal_flat(s, i0[0] + kx, i0[1] + ky, i0[2] + kz);
+                    if (f >= 0) out[f] += s->g.q * s->w[p] * w[0][kx + 1] * w[1][ky + 1] * w[2][kz + 1];
+                }
+    }
+}
+
+/* One full step n -> n+1 (state x^n, u^{n-1/2}, E^n, B^n on entry). */
+static void one_step(orc_sim *s)
+{
+    const int nd = s->g.ndim;
+    const double dt = s->g.dt, q = s->g.q, m = s->g.m, vol = orc_cell_volume(s);
+    s->U_last = orc_field_energy(s);
+    for (int c = 6; c < 9; ++c) memset(s->F[c], 0, sizeof(double) * s->fsize);
+    int32_t *dest = malloc(sizeof(int32_t) * (s->npart + 1));
+    double K = 0.0;
+    int64_t k = 0;
+    for (int p = 0; p < s->npatch; ++p)
+        for (int32_t sl = 0; sl < s->count[p]; ++sl, ++k) {
+            double x0[3] = {s->x[0][k], s->x[1][k], s->x[2][k]};
+            double u[3] = {s->u[0][k], s->u[1][k], s->u[2][k]};
+            double EB[6];
+            orc_gather(s, x0, EB);
+            double g0 = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            orc_boris(u, EB, EB + 3, q, m, dt);
+            double g1 = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            K += s->w[k] * m * (0.5 * (g0 + g1) - 1.0) * vol;
+            double x1[3] = {x0[0], x0[1], x0[2]};
+            for (int a = 0; a < nd; ++a) x1[a] = x0[a] + dt * u[a] / (g1 * s->g.d[a]);
+            orc_deposit(s, x0, x1, s->w[k], u[2] / g1);
+            int removed = 0;
+            for (int a = 0; a < nd; ++a) {
+                double n = (double)s->g.n[a];
+                if (s->g.periodic[a]) {
+                    if (x1[a] >= n) x1[a] -= n;
+                    else if (x1[a] < 0.0) x1[a] += n;
+                    if (x1[a] == n) x1[a] = 0.0;
+                } else if (x1[a] < 0.0 || x1[a] >= n) {
+                    removed = 1;
+                }
+            }
+            for (int a = 0; a < 3; ++a) { s->x[a][k] = x1[a]; s->u[a][k] = u[a]; }
+            dest[k] = removed ? -1 : patch_of(s, x1);
+        }
+    s->K_last = K;
+
+    orc_maxwell(s);
+
+    /* re-bin */
+    int32_t *newcount = malloc(sizeof(int32_t) * s->npatch);
+    int64_t *src = malloc(sizeof(int64_t) * (s->npart + 1));
+    orc_rebin(s->npatch, s->count, dest, newcount, src);
+    int64_t nnew = 0;
+    for (int p = 0; p < s->npatch; ++p) nnew += newcount[p];
+    double *nx[3], *nu[3], *nw = malloc(sizeof(double) * (nnew + 1));
+    int64_t *nid = malloc(sizeof(int64_t) * (nnew + 1));
+    for (int a = 0; a < 3; ++a) {
+        nx[a] = malloc(sizeof(double) * (nnew + 1));
+        nu[a] = malloc(sizeof(double) * (nnew + 1));
+    }
+    for (int64_t t = 0; t < nnew; ++t) {
+        int64_t f = src[t];
+        for (int a = 0; a < 3; ++a) { nx[a][t] = s->x[a][f]; nu[a][t] = s->u[a][f]; }
+        nw[t] = s->w[f];
+        nid[t] = s->id[f];
+    }
+    s->removed += s->npart - nnew;
+    free_particles(s);
+    for (int a = 0; a < 3; ++a) { s->x[a] = nx[a]; s->u[a] = nu[a]; }
+    s->w = nw;
+    s->id = nid;
+    s->npart = nnew;
+    memcpy(s->count, newcount, sizeof(int32_t) * s->npatch);
+    free(newcount);
+    free(src);
+    free(dest);
+    s->step += 1;
+}
+
+void orc_step(orc_sim *s, int64_t nsteps)
+{
+    for (int64_t t = 0; t < nsteps; ++t) one_step(s);
+}
+
+/* Energies of the last completed step: U(E^n, B^n) and K^n. */
+void orc_energy(const orc_sim *s, double *U, double *K)
+{
+    *U = s->U_last;
+    *K = s->K_last;
+}
