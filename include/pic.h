@@ -1,0 +1,227 @@
+/*
+ * pic.h -- C ABI of the MI355X patch-PIC library (libpic.so).
+ *
+ * The library runs the data-parallel hot path of a patch-decomposed
+ * electromagnetic particle-in-cell step on one gfx950 GPU: quadratic-shape
+ * field gather, relativistic Boris push, charge-conserving (Esirkepov)
+ * current deposition, Yee FDTD update with periodic or Silver-Mueller faces,
+ * and the per-patch particle re-binning whose cost spread across patches is
+ * the load imbalance studied in the paper (Beck, Frederiksen, Derouillat,
+ * "Load management strategy for Particle-In-Cell simulations in high energy
+ * particle acceleration", sections 3 and 3.1: patches of fields and
+ * super-particles, dynamic exchange of patches to even out load).
+ *
+ * Conventions
+ *  - Units: c = eps0 = e = m_e = 1; lengths in c/omega_r, time in
+ *    1/omega_r (section 2.2 quotes its resolutions this way).
+ *  - Grid: n[a] cells of size d[a] per axis, x fastest.  Field component
+ *    arrays exchanged with the host are FP64, row-major with x fastest,
+ *    fn[a] nodes per axis: fn = n on a periodic axis, n + 1 on an open axis
+ *    (only x may be open).  Yee staggering (half a cell up): Ex (1/2,0,0),
+ *    Ey (0,1/2,0), Ez (0,0,1/2), Bx (0,1/2,1/2), By (1/2,0,1/2),
+ *    Bz (1/2,1/2,0); J shares E's positions.  In 2-D the z offsets vanish.
+ *    On an open x axis the dual-x components use nodes 0..n-1 and entry n
+ *    is unused (reads back as 0).
+ *  - Time levels: after k completed steps the library holds x^k, u^{k-1/2},
+ *    E^k and B^k (B at integer time), and J^{k-1/2} (the last deposit).
+ *  - Particles are held in patches of patch[a] cells; a particle's patch is
+ *    floor(x/d / patch) per axis, patch id row-major with x fastest.  Inside
+ *    a patch particles occupy slots 0..count-1 in a canonical order: the
+ *    initial order is id order; after every step the re-binning fills
+ *    vacated slots below the new count with arrivals (ordered by source
+ *    patch id, then source slot) and then with the stayers beyond the new
+ *    count, and appends what remains.  Getters return particles in
+ *    (patch, slot) order.
+ *  - Status: every int-returning call returns PIC_OK (0) or a negative
+ *    PIC_E* code; pic_last_error() gives a thread-local message.  Arguments
+ *    are validated before any device work, so bad descriptors fail without
+ *    touching the GPU.  No C++ exception crosses this interface.
+ *  - Host pointers are borrowed for the duration of the call only.  Device
+ *    memory is owned by the handle and obtained through the allocator hook
+ *    given at creation (NULL: hipMalloc / hipFree).
+ *  - All device work of a handle is ordered on the HIP stream given at
+ *    creation (NULL: the default stream).  Handles are not thread-safe.
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    PIC_OK = 0,
+    PIC_EINVAL = -1,    /* invalid argument or descriptor */
+    PIC_ENOMEM = -2,    /* allocation through the hook failed */
+    PIC_EBUDGET = -3,   /* a memory budget would be exceeded */
+    PIC_EHIP = -4,      /* a HIP runtime call failed */
+    PIC_EOVERFLOW = -5, /* patch capacity could not be grown */
+    PIC_ENAN = -6,      /* a particle produced a non-finite momentum */
+    PIC_ECFL = -7,      /* a particle moved one cell or more in a step */
+    PIC_ESTATE = -8,    /* call not valid in the handle's current state */
+    PIC_ENOTSUP = -9    /* configuration not supported by this build */
+};
+
+/* Field component ids for pic_fields_set / pic_fields_get. */
+enum {
+    PIC_EX = 0, PIC_EY = 1, PIC_EZ = 2,
+    PIC_BX = 3, PIC_BY = 4, PIC_BZ = 5,
+    PIC_JX = 6, PIC_JY = 7, PIC_JZ = 8,
+    PIC_RHO = 9 /* charge density of the particles on primal nodes (get only) */
+};
+
+typedef struct PicSim PicSim;
+typedef struct PicBatch PicBatch;
+
+/* Device-memory hook: alloc returns device memory of at least `bytes`
+ * (256-byte aligned) or NULL; free releases it.  Called only from the
+ * creating thread.  Python routes these to torch's caching allocator. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *ctx);
+    void (*free)(void *ptr, void *ctx);
+    void *ctx;
+} PicAllocator;
+
+/* Simulation descriptor.  One electron-like species per simulation
+ * (immobile neutralising ions enter only diagnostics). */
+typedef struct {
+    int32_t ndim;          /* 2 */
+    int32_t precision;     /* 32 or 64: storage and arithmetic of fields and particles */
+    int32_t n[3];          /* cells per axis (n[2] ignored in 2-D) */
+    double d[3];           /* cell size per axis */
+    double dt;             /* time step; must satisfy dt < (sum 1/d^2)^(-1/2) */
+    int32_t patch[3];      /* cells per patch per axis; must divide n; at most 64 */
+    int32_t periodic[3];   /* 1 periodic; 0 open: Silver-Mueller fields, absorbing
+                              particles (x axis only) */
+    double q, m;           /* species charge and mass */
+    double capacity_factor;/* slots per patch = max(min_capacity, factor * count); 0 = 1.5 */
+    int32_t min_capacity;  /* 0 = 64 */
+    int32_t chunk;         /* max particles per work item; 0 = chosen from the load */
+    int32_t block;         /* threads per particle workgroup: 0, 256 or 512 */
+} PicSimDesc;
+
+/* Diagnostics of a simulation (pic_diag_get synchronises the stream). */
+typedef struct {
+    int64_t step;          /* completed steps */
+    int64_t particles;     /* live particles */
+    int64_t removed;       /* particles absorbed at open faces so far */
+    double field_energy;   /* U(E^{k-1}, B^{k-1}) of the last completed step */
+    double kinetic_energy; /* K^{k-1} = sum w m (gamma^{k-3/2} + gamma^{k-1/2}) / 2 - 1) V_cell */
+    int32_t occupancy_min, occupancy_max; /* particles per patch */
+    double occupancy_mean;
+    int32_t flags;         /* sticky device error bits (see pic_sync) */
+    int32_t relayouts;     /* capacity re-layouts performed so far */
+} PicDiag;
+
+/* Per-kernel timing accumulated while timing is enabled (HIP events on the
+ * handle's stream around every launch). */
+typedef struct {
+    int32_t nkernels;
+    const char *name[8];
+    double total_ms[8];
+    int64_t launches[8];
+} PicTiming;
+
+/* ---- lifetime ---------------------------------------------------------- */
+
+/* Create a simulation: allocate E, B (zero) and two J buffers on the device.
+ * `d` is validated (ndim, precision, divisibility, CFL, open axes) before
+ * any device call.  *out receives the handle. */
+int pic_sim_create(const PicSimDesc *d, const PicAllocator *a, void *hip_stream, PicSim **out);
+void pic_sim_destroy(PicSim *s);
+
+/* ---- state in ------------------------------------------------------------ */
+
+/* Load n particles given in id order (ids 0..n-1): positions in cell units
+ * (x/d, global, each in [0, n_cells)), momenta u = p/(m c) at time -1/2,
+ * weights (density contributed, in units of the reference density).  z and
+ * uz may be NULL in 2-D (uz NULL = 0).  Replaces any previous particles and
+ * resets the step counter to 0.  Values are rounded to the handle's
+ * precision; positions are stored as offsets from their patch origin. */
+int pic_particles_set(PicSim *s, int64_t n, const double *x, const double *y, const double *z,
+                      const double *ux, const double *uy, const double *uz, const double *w);
+
+/* Incident field driving the open x = 0 face: row t (t = 0..nsteps-1) holds
+ * the incident Ey (at y = (j + 1/2) d_y) and Ez (at y = j d_y) at time
+ * (t + 1/2) dt, n[1] values per row.  ey or ez may be NULL (zero).  Steps
+ * beyond the table see no incident field. */
+int pic_laser_set(PicSim *s, int64_t nsteps, const double *ey, const double *ez);
+
+/* Overwrite one field component (E or B) from a host FP64 array of
+ * count = fn[0]*fn[1]*fn[2] values. */
+int pic_fields_set(PicSim *s, int comp, const double *host, size_t count);
+
+/* ---- stepping -------------------------------------------------------------- */
+
+/* Enqueue nsteps full PIC steps on the handle's stream: work-queue build,
+ * fused gather / Boris / move / Esirkepov deposit, Yee update with face
+ * conditions, re-binning.  Returns after the steps are enqueued; it blocks
+ * only to grow patch capacity when a patch overflows (checked every few
+ * steps).  Device errors are sticky and reported by pic_sync. */
+int pic_step(PicSim *s, int64_t nsteps);
+
+/* Wait for the handle's stream; return PIC_ENAN / PIC_ECFL if a particle
+ * error was raised since creation, else PIC_OK. */
+int pic_sync(PicSim *s);
+
+/* ---- state out ------------------------------------------------------------- */
+
+int pic_fields_get(PicSim *s, int comp, double *host, size_t count);
+int pic_num_particles(PicSim *s, int64_t *n);
+/* Particles in canonical (patch, slot) order; each non-NULL array holds at
+ * least `count` >= live particles entries.  Positions are global cell units. */
+int pic_particles_get(PicSim *s, double *x, double *y, double *z, double *ux, double *uy,
+                      double *uz, double *w, int64_t *id, size_t count);
+int pic_patch_counts_get(PicSim *s, int32_t *counts, size_t count);
+int pic_diag_get(PicSim *s, PicDiag *out);
+/* Energy history of completed steps first..first+n-1 (the last 4096 steps
+ * are kept): U^k and K^k of step k and the particles it pushed. */
+int pic_history_get(PicSim *s, int64_t first, int64_t n, double *U, double *K, int64_t *pushed);
+
+/* ---- re-binning as a function (test hook) ---------------------------------- */
+
+/* Apply only the re-binning to the current particles, with the destination
+ * of each particle given in (patch, slot) order as a direction code:
+ * (dx+1) + 3 (dy+1) for a move to the neighbour patch (dx, dy) in
+ * {-1,0,1}^2 (4 = stay), or 255 = removed.  Local positions are left as
+ * they are.  The step counter is not advanced. */
+int pic_rebin_codes(PicSim *s, const uint8_t *codes, size_t count);
+
+/* ---- timing ------------------------------------------------------------------ */
+
+int pic_timing_enable(PicSim *s, int on);
+int pic_timing_get(PicSim *s, PicTiming *out); /* synchronises */
+
+/* ---- batches of simulations stepped together ------------------------------- */
+
+/* A batch steps many simulations of the same ndim and precision together:
+ * one work queue over all their patches (ordered by particle count), one
+ * persistent particle launch, one Maxwell and one re-binning pass per step.
+ * Member simulations keep their own state and results and can be read with
+ * the pic_* getters between batch steps.  All members must share the
+ * batch's stream. */
+int pic_batch_create(int32_t ndim, int32_t precision, void *hip_stream, PicBatch **out);
+void pic_batch_destroy(PicBatch *b);
+/* Add a simulation that will be advanced by `nsteps` more steps. */
+int pic_batch_add(PicBatch *b, PicSim *s, int64_t nsteps);
+int pic_batch_remove(PicBatch *b, PicSim *s);
+/* Advance every member by up to `max_steps` steps (members stop when their
+ * own step budget is used up).  *done receives the number of members that
+ * finished their budget during this call. */
+int pic_batch_step(PicBatch *b, int64_t max_steps, int32_t *done);
+/* Members whose step budget is used up (they stay members until removed). */
+int pic_batch_finished(PicBatch *b, PicSim **out, int32_t cap, int32_t *n);
+int pic_batch_size(PicBatch *b, int32_t *n);
+
+/* ---- errors ------------------------------------------------------------------ */
+
+const char *pic_strerror(int code);
+const char *pic_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PIC_H */

@@ -1,0 +1,190 @@
+// Fused Yee update of the 2-D patch-PIC step.
+//
+// One workgroup updates a TX x TY tile of nodes with all three sweeps held in
+// LDS: B^{n+1/2} = B^n - dt/2 curl E^n, E^{n+1} = E^n + dt (curl B^{n+1/2} -
+// J^{n+1/2}), B^{n+1} = B^{n+1/2} - dt/2 curl E^{n+1}.  B updates use forward
+// differences of E and E updates backward differences of B, so a one-node
+// halo on every side is enough for the three sweeps.  On an open x axis the
+// E update at the faces needs By and Bz half a cell outside; they follow from
+// the first-order characteristic (Silver-Mueller) condition at the face and
+// time n + 1/2 combined with the 1-D Yee update (r = dt/dx, B_1 the first
+// inside dual B, E^n the face E):
+//   x = 0, incident Ey_i, Ez_i:  Bz = (4 Ey_i - 2 Ey^n - (1 - r) B_1) / (1 + r)
+//                                By = (2 Ez^n - (1 - r) B_1 - 4 Ez_i) / (1 + r)
+//   x = L, outflow:              Bz = (2 Ey^n - (1 - r) B_1) / (1 + r)
+//                                By = (-2 Ez^n - (1 - r) B_1) / (1 + r)
+// The kernel also accumulates the field energy of E^n, B^n over the tile's own
+// nodes and clears the tile of the J buffer the next step deposits into.
+#include "kernels.h"
+
+namespace pic {
+
+namespace {
+
+template <typename T, int TX, int TY>
+__global__ __launch_bounds__(256) void k_maxwell2d(const SimDev<T> *__restrict__ sims, int nsims,
+                                                   const int *__restrict__ tile_prefix, int total)
+{
+    constexpr int W = TX + 3, H = TY + 3, NB = W * H;
+    __shared__ T sE[3][NB], sB[3][NB], sJ[3][NB];
+    __shared__ double s_red[4];
+    const int tid = threadIdx.x;
+
+    for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+        const int s = find_sim(tile_prefix, nsims, tile);
+        const SimDev<T> &S = sims[s];
+        if (!S.st->active) continue;
+        const int lt = tile - tile_prefix[s];
+        const int n0 = S.n[0], n1 = S.n[1], fn0 = S.fn[0], fn1 = S.fn[1];
+        const int per0 = S.periodic[0], per1 = S.periodic[1];
+        const int ntx = (fn0 + TX - 1) / TX;
+        const int X0 = (lt % ntx) * TX, Y0 = (lt / ntx) * TY;
+        const int64_t stepn = S.st->step;
+        T *const *Jc = S.J[stepn & 1];
+        T *const *Jn = S.J[(stepn + 1) & 1];
+
+        // ---- load nodes [X0-1, X0+TX+1] x [Y0-1, Y0+TY+1] -------------------
+        double esum = 0.0;
+        for (int t = tid; t < NB; t += 256) {
+            const int a = t % W, b = t / W;
+            const int gi = X0 - 1 + a, gj = Y0 - 1 + b;
+            const int ip = axis_node(gi, n0, per0, 0), id = axis_node(gi, n0, per0, 1);
+            const int jp = axis_node(gj, n1, per1, 0), jd = axis_node(gj, n1, per1, 1);
+            const bool own = a >= 1 && a <= TX && b >= 1 && b <= TY && gi < fn0 && gj < fn1;
+            // staggering: Ex (d,p) Ey (p,d) Ez (p,p) Bx (p,d) By (d,p) Bz (d,d)
+            const int64_t kdp = (id >= 0 && jp >= 0) ? id + (int64_t)fn0 * jp : -1;
+            const int64_t kpd = (ip >= 0 && jd >= 0) ? ip + (int64_t)fn0 * jd : -1;
+            const int64_t kpp = (ip >= 0 && jp >= 0) ? ip + (int64_t)fn0 * jp : -1;
+            const int64_t kdd = (id >= 0 && jd >= 0) ? id + (int64_t)fn0 * jd : -1;
+            const T ex = kdp >= 0 ? S.F[0][kdp] : T(0);
+            const T ey = kpd >= 0 ? S.F[1][kpd] : T(0);
+            const T ez = kpp >= 0 ? S.F[2][kpp] : T(0);
+            const T bx = kpd >= 0 ? S.F[3][kpd] : T(0);
+            const T by = kdp >= 0 ? S.F[4][kdp] : T(0);
+            const T bz = kdd >= 0 ? S.F[5][kdd] : T(0);
+            sE[0][t] = ex; sE[1][t] = ey; sE[2][t] = ez;
+            sB[0][t] = bx; sB[1][t] = by; sB[2][t] = bz;
+            sJ[0][t] = kdp >= 0 ? Jc[0][kdp] : T(0);
+            sJ[1][t] = kpd >= 0 ? Jc[1][kpd] : T(0);
+            sJ[2][t] = kpp >= 0 ? Jc[2][kpp] : T(0);
+            if (own) {
+                // invalid (outside) nodes were loaded as zero, so they add nothing
+                esum += (double)ex * ex + (double)ey * ey + (double)ez * ez + (double)bx * bx +
+                        (double)by * by + (double)bz * bz;
+            }
+        }
+        __syncthreads();
+
+        const T dt = S.dt, h = T(0.5) * S.dt;
+        const T ix = T(1) / S.d[0], iy = T(1) / S.d[1];
+
+        // ---- sweep 1: B^{n+1/2} on a in [0, TX+1], b in [0, TY+1] -----------
+        for (int t = tid; t < (TX + 2) * (TY + 2); t += 256) {
+            const int a = t % (TX + 2), b = t / (TX + 2);
+            const int c = b * W + a;
+            sB[0][c] -= h * (sE[2][c + W] - sE[2][c]) * iy;
+            sB[1][c] += h * (sE[2][c + 1] - sE[2][c]) * ix;
+            sB[2][c] -= h * ((sE[1][c + 1] - sE[1][c]) * ix - (sE[0][c + W] - sE[0][c]) * iy);
+        }
+        __syncthreads();
+
+        // ---- Silver-Mueller ghosts on an open x axis -------------------------
+        if (!per0) {
+            const T r = dt * ix;
+            const T ir = T(1) / (T(1) + r);
+            if (X0 == 0) {
+                const int64_t ls = stepn;
+                for (int b = tid; b < H; b += 256) {
+                    const int gj = wrap_idx(Y0 - 1 + b, n1);
+                    T eyi = T(0), ezi = T(0);
+                    if (ls < S.laser_steps) {
+                        if (S.laser_ey) eyi = S.laser_ey[ls * n1 + gj];
+                        if (S.laser_ez) ezi = S.laser_ez[ls * n1 + gj];
+                    }
+                    const int c = b * W;  // a = 0 is x-node -1 (dual -1/2 for By, Bz)
+                    sB[2][c] = (T(4) * eyi - T(2) * sE[1][c + 1] - (T(1) - r) * sB[2][c + 1]) * ir;
+                    sB[1][c] = (T(2) * sE[2][c + 1] - (T(1) - r) * sB[1][c + 1] - T(4) * ezi) * ir;
+                }
+            }
+            const int ag = n0 - X0 + 1;  // local column of dual x index n0 (x = L + 1/2)
+            if (ag >= 1 && ag <= TX + 1) {
+                for (int b = tid; b < H; b += 256) {
+                    const int c = b * W + ag;
+                    sB[2][c] = (T(2) * sE[1][c] - (T(1) - r) * sB[2][c - 1]) * ir;
+                    sB[1][c] = (-T(2) * sE[2][c] - (T(1) - r) * sB[1][c - 1]) * ir;
+                }
+            }
+            __syncthreads();
+        }
+
+        // ---- sweep 2: E^{n+1} on a in [1, TX+1], b in [1, TY+1] -------------
+        for (int t = tid; t < (TX + 1) * (TY + 1); t += 256) {
+            const int a = 1 + t % (TX + 1), b = 1 + t / (TX + 1);
+            const int c = b * W + a;
+            sE[0][c] += dt * ((sB[2][c] - sB[2][c - W]) * iy - sJ[0][c]);
+            sE[1][c] += dt * (-(sB[2][c] - sB[2][c - 1]) * ix - sJ[1][c]);
+            sE[2][c] += dt * ((sB[1][c] - sB[1][c - 1]) * ix - (sB[0][c] - sB[0][c - W]) * iy - sJ[2][c]);
+        }
+        __syncthreads();
+
+        // ---- sweep 3: B^{n+1} on the tile's own nodes, then write back -------
+        for (int t = tid; t < TX * TY; t += 256) {
+            const int a = 1 + t % TX, b = 1 + t / TX;
+            const int gi = X0 + a - 1, gj = Y0 + b - 1;
+            if (gi >= fn0 || gj >= fn1) continue;
+            const int c = b * W + a;
+            const T bx = sB[0][c] - h * (sE[2][c + W] - sE[2][c]) * iy;
+            const T by = sB[1][c] + h * (sE[2][c + 1] - sE[2][c]) * ix;
+            const T bz = sB[2][c] - h * ((sE[1][c + 1] - sE[1][c]) * ix - (sE[0][c + W] - sE[0][c]) * iy);
+            // own nodes are inside the periodic range; on an open axis the dual
+            // components stop one node short
+            const bool dx_ok = per0 || gi <= n0 - 1;
+            const int64_t k = gi + (int64_t)fn0 * gj;
+            S.F[1][k] = sE[1][c];
+            S.F[2][k] = sE[2][c];
+            S.F[3][k] = bx;
+            Jn[1][k] = T(0);
+            Jn[2][k] = T(0);
+            if (dx_ok) {
+                S.F[0][k] = sE[0][c];
+                S.F[4][k] = by;
+                S.F[5][k] = bz;
+                Jn[0][k] = T(0);
+            }
+        }
+
+        // ---- field energy of E^n, B^n ----------------------------------------
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) esum += __shfl_xor(esum, o, 64);
+        if ((tid & 63) == 0) s_red[tid >> 6] = esum;
+        __syncthreads();
+        if (tid == 0)
+            atomicAdd(&S.st->U, 0.5 * S.vcell * (s_red[0] + s_red[1] + s_red[2] + s_red[3]));
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+template <>
+void maxwell_tile<float>(int &tx, int &ty) { tx = 64; ty = 16; }
+template <>
+void maxwell_tile<double>(int &tx, int &ty) { tx = 32; ty = 16; }
+
+template <typename T>
+void launch_maxwell(const SimDev<T> *sims, int nsims, const int *tile_prefix, int total_tiles,
+                    int grid, hipStream_t st)
+{
+    if constexpr (sizeof(T) == 4)
+        hipLaunchKernelGGL((k_maxwell2d<T, 64, 16>), dim3(grid), dim3(256), 0, st, sims, nsims,
+                           tile_prefix, total_tiles);
+    else
+        hipLaunchKernelGGL((k_maxwell2d<T, 32, 16>), dim3(grid), dim3(256), 0, st, sims, nsims,
+                           tile_prefix, total_tiles);
+}
+
+template void launch_maxwell<float>(const SimDev<float> *, int, const int *, int, int, hipStream_t);
+template void launch_maxwell<double>(const SimDev<double> *, int, const int *, int, int,
+                                     hipStream_t);
+
+}  // namespace pic

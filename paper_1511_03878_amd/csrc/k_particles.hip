@@ -1,0 +1,336 @@
+// Fused particle kernel of the 2-D patch-PIC step (one work item = a chunk of
+// one patch): stage the patch's E and B into LDS, then per particle gather
+// with quadratic shapes, relativistic Boris push, move, classify the
+// destination patch, and deposit the charge-conserving (Esirkepov) current
+// into an LDS tile that is flushed to the global current once per item.
+//
+// The paper's patches (section 3.1) are small independent structures of
+// fields and particles; here one workgroup owns one patch chunk at a time,
+// and workgroups pull items from a queue ordered by particle count (the
+// single-GPU form of exchanging patches to even out load).
+#include <math.h>
+
+#include "kernels.h"
+
+namespace pic {
+
+namespace {
+
+constexpr int kWave = 64;
+
+// Quadratic B-spline weights of the nodes i0-1, i0, i0+1 for the offset
+// dl = xi - i0 in [-1/2, 1/2).
+template <typename A>
+__device__ __forceinline__ void qweights(A dl, A &wm, A &w0, A &wp)
+{
+    A a = A(0.5) - dl, b = A(0.5) + dl;
+    wm = A(0.5) * a * a;
+    w0 = A(0.75) - dl * dl;
+    wp = A(0.5) * b * b;
+}
+
+template <typename T>
+__device__ __forceinline__ T gather9(const T *tile, int fw, int i0, int j0, const T wx[3],
+                                     const T wy[3])
+{
+    // tile entry of node (i, j) is (j + 1) * fw + (i + 1)
+    const T *r = tile + j0 * fw + i0;
+    T acc = T(0);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        T row = r[b * fw] * wx[0] + r[b * fw + 1] * wx[1] + r[b * fw + 2] * wx[2];
+        acc += row * wy[b];
+    }
+    return acc;
+}
+
+// Window of four nodes per axis that holds both the old and the new
+// quadratic supports of a move shorter than one cell.  On return S0/DS are
+// the old weights and the weight change at nodes m..m+3.  The new offset is
+// formed from the exact old offset and the displacement in FP64, so the
+// weight change keeps full relative accuracy even for FP32 storage.
+template <typename T>
+__device__ __forceinline__ void window4(T xl, double disp, int &m, double S0[4], double DS[4])
+{
+    int i0 = (int)floor(xl + T(0.5));
+    double d0 = (double)(xl - (T)i0);  // exact
+    double a = d0 + disp;
+    int sg = (int)floor(a + 0.5);       // -1, 0 or +1
+    double d1 = a - (double)sg;
+    double o0m, o00, o0p, o1m, o10, o1p;
+    qweights(d0, o0m, o00, o0p);
+    qweights(d1, o1m, o10, o1p);
+    int lo = sg < 0 ? sg : 0;
+    m = i0 - 1 + lo;
+    bool s0 = lo < 0;   // old support starts at window slot 1
+    bool s1 = sg > 0;   // new support starts at window slot 1
+    double A0[4] = {s0 ? 0.0 : o0m, s0 ? o0m : o00, s0 ? o00 : o0p, s0 ? o0p : 0.0};
+    double A1[4] = {s1 ? 0.0 : o1m, s1 ? o1m : o10, s1 ? o10 : o1p, s1 ? o1p : 0.0};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        S0[k] = A0[k];
+        DS[k] = A1[k] - A0[k];
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T below(T v);
+template <>
+__device__ __forceinline__ float below<float>(float v) { return nextafterf(v, 0.0f); }
+template <>
+__device__ __forceinline__ double below<double>(double v) { return nextafter(v, 0.0); }
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+template <typename T, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restrict__ sims,
+                                                       const Item *__restrict__ items,
+                                                       const int *__restrict__ nitems,
+                                                       int *__restrict__ head, int fstride,
+                                                       int jstride)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *Ft = reinterpret_cast<T *>(smem_raw);
+    T *Jt = Ft + 6 * fstride;
+    __shared__ int s_item;
+    __shared__ double s_red[BLOCK / kWave];
+
+    const int tid = threadIdx.x;
+    const int total = *nitems;
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(head, 1);
+        __syncthreads();
+        const int idx = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();
+        if (idx >= total) break;
+        const Item it = items[idx];
+        const SimDev<T> &S = sims[__builtin_amdgcn_readfirstlane(it.x)];
+        const int p = __builtin_amdgcn_readfirstlane(it.y);
+        const int first = __builtin_amdgcn_readfirstlane(it.z);
+        const int cnt = __builtin_amdgcn_readfirstlane(it.w);
+        const int P0 = S.P[0], P1 = S.P[1];
+        const int pxi = p % S.np[0], pyi = p / S.np[0];
+        const int ox = pxi * P0, oy = pyi * P1;
+        const int fw = P0 + 3, fh = P1 + 3, jw = P0 + 5, jh = P1 + 5;
+        const int n0 = S.n[0], n1 = S.n[1], fn0 = S.fn[0];
+        const int per0 = S.periodic[0], per1 = S.periodic[1];
+
+        // ---- stage E, B of nodes [ox-1, ox+P0+1] x [oy-1, oy+P1+1] --------
+        for (int t = tid; t < fw * fh; t += BLOCK) {
+            const int gi = ox - 1 + t % fw, gj = oy - 1 + t / fw;
+            const int ip = axis_node(gi, n0, per0, 0), id = axis_node(gi, n0, per0, 1);
+            const int jp = axis_node(gj, n1, per1, 0), jd = axis_node(gj, n1, per1, 1);
+            // staggering: Ex (d,p) Ey (p,d) Ez (p,p) Bx (p,d) By (d,p) Bz (d,d)
+            Ft[0 * fstride + t] = (id >= 0 && jp >= 0) ? S.F[0][id + fn0 * jp] : T(0);
+            Ft[1 * fstride + t] = (ip >= 0 && jd >= 0) ? S.F[1][ip + fn0 * jd] : T(0);
+            Ft[2 * fstride + t] = (ip >= 0 && jp >= 0) ? S.F[2][ip + fn0 * jp] : T(0);
+            Ft[3 * fstride + t] = (ip >= 0 && jd >= 0) ? S.F[3][ip + fn0 * jd] : T(0);
+            Ft[4 * fstride + t] = (id >= 0 && jp >= 0) ? S.F[4][id + fn0 * jp] : T(0);
+            Ft[5 * fstride + t] = (id >= 0 && jd >= 0) ? S.F[5][id + fn0 * jd] : T(0);
+        }
+        for (int t = tid; t < 3 * jstride; t += BLOCK) Jt[t] = T(0);
+        __syncthreads();
+
+        const int64_t base = S.off[p] + first;
+        const T dt = S.dt, q = S.q, m = S.m;
+        const T eps = q * dt / (T(2) * m);
+        const T rdx = dt / S.d[0], rdy = dt / S.d[1];
+        const double cx = -(double)q * (double)S.d[0] / (double)dt;
+        const double cy = -(double)q * (double)S.d[1] / (double)dt;
+        const T Pmax0 = below((T)P0), Pmax1 = below((T)P1);
+        const bool edge_lo = !per0 && pxi == 0, edge_hi = !per0 && pxi == S.np[0] - 1;
+        double kin = 0.0;
+        uint32_t err = 0;
+
+        for (int k = tid; k < cnt; k += BLOCK) {
+            const int64_t g = base + k;
+            const T xl = S.x[0][g], yl = S.x[1][g];
+            T ux = S.u[0][g], uy = S.u[1][g], uz = S.u[2][g];
+            const T wgt = S.w[g];
+
+            // ---- gather ---------------------------------------------------
+            const int ipx = (int)floor(xl + T(0.5)), idx_ = (int)floor(xl);
+            const int ipy = (int)floor(yl + T(0.5)), idy = (int)floor(yl);
+            T wpx[3], wdx[3], wpy[3], wdy[3];
+            qweights(xl - (T)ipx, wpx[0], wpx[1], wpx[2]);
+            qweights(xl - (T)idx_ - T(0.5), wdx[0], wdx[1], wdx[2]);
+            qweights(yl - (T)ipy, wpy[0], wpy[1], wpy[2]);
+            qweights(yl - (T)idy - T(0.5), wdy[0], wdy[1], wdy[2]);
+            // node i0-1 sits at tile column i0, so the window starts at i0
+            const T Ex = gather9(Ft + 0 * fstride, fw, idx_, ipy, wdx, wpy);
+            const T Ey = gather9(Ft + 1 * fstride, fw, ipx, idy, wpx, wdy);
+            const T Ez = gather9(Ft + 2 * fstride, fw, ipx, ipy, wpx, wpy);
+            const T Bx = gather9(Ft + 3 * fstride, fw, ipx, idy, wpx, wdy);
+            const T By = gather9(Ft + 4 * fstride, fw, idx_, ipy, wdx, wpy);
+            const T Bz = gather9(Ft + 5 * fstride, fw, idx_, idy, wdx, wdy);
+
+            // ---- Boris ------------------------------------------------------
+            const T usq0 = ux * ux + uy * uy + uz * uz;
+            const T g0 = sqrt(T(1) + usq0);
+            T umx = ux + eps * Ex, umy = uy + eps * Ey, umz = uz + eps * Ez;
+            const T gm = sqrt(T(1) + umx * umx + umy * umy + umz * umz);
+            const T tx = eps * Bx / gm, ty = eps * By / gm, tz = eps * Bz / gm;
+            const T t2 = tx * tx + ty * ty + tz * tz;
+            const T s2 = T(2) / (T(1) + t2);
+            const T sx = s2 * tx, sy = s2 * ty, sz = s2 * tz;
+            const T upx = umx + (umy * tz - umz * ty);
+            const T upy = umy + (umz * tx - umx * tz);
+            const T upz = umz + (umx * ty - umy * tx);
+            umx += upy * sz - upz * sy;
+            umy += upz * sx - upx * sz;
+            umz += upx * sy - upy * sx;
+            ux = umx + eps * Ex;
+            uy = umy + eps * Ey;
+            uz = umz + eps * Ez;
+            const T usq1 = ux * ux + uy * uy + uz * uz;
+            const T g1 = sqrt(T(1) + usq1);
+            const T ig1 = T(1) / g1;
+            kin += (double)wgt * (double)m * 0.5 *
+                   ((double)usq0 / ((double)g0 + 1.0) + (double)usq1 / ((double)g1 + 1.0));
+
+            // ---- move and classify -------------------------------------------
+            const T dxl = rdx * ux * ig1, dyl = rdy * uy * ig1;
+            uint8_t code;
+            T x1 = xl + dxl, y1 = yl + dyl;
+            if (!(fabs(dxl) < T(1) && fabs(dyl) < T(1))) {
+                err |= (isfinite(ux) && isfinite(uy) && isfinite(uz)) ? kFlagCFL : kFlagNaN;
+                code = kRemoved;
+                x1 = xl;
+                y1 = yl;
+            } else {
+                // ---- Esirkepov deposit on a 4x4 node window ------------------
+                int mx, my;
+                double S0x[4], DSx[4], S0y[4], DSy[4];
+                window4(xl, (double)dxl, mx, S0x, DSx);
+                window4(yl, (double)dyl, my, S0y, DSy);
+                const double qw = (double)wgt;
+                const double ax = cx * qw, ay = cy * qw;
+                const double az = (double)q * qw * (double)(uz * ig1);
+                T *Jxt = Jt, *Jyt = Jt + jstride, *Jzt = Jt + 2 * jstride;
+                const int r0 = (my + 2) * jw + (mx + 2);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const double wy = S0y[j] + 0.5 * DSy[j];
+                    double acc = 0.0;
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        acc += DSx[i] * wy;
+                        atomicAdd(&Jxt[r0 + j * jw + i], (T)(ax * acc));
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const double wx = S0x[i] + 0.5 * DSx[i];
+                    double acc = 0.0;
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        acc += DSy[j] * wx;
+                        atomicAdd(&Jyt[r0 + j * jw + i], (T)(ay * acc));
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const double wz = S0x[i] * S0y[j] + 0.5 * (DSx[i] * S0y[j] + S0x[i] * DSy[j]) +
+                                          DSx[i] * DSy[j] * (1.0 / 3.0);
+                        atomicAdd(&Jzt[r0 + j * jw + i], (T)(az * wz));
+                    }
+
+                const int sx_ = x1 < T(0) ? -1 : (x1 >= (T)P0 ? 1 : 0);
+                const int sy_ = y1 < T(0) ? -1 : (y1 >= (T)P1 ? 1 : 0);
+                const bool gone = (sx_ < 0 && edge_lo) || (sx_ > 0 && edge_hi);
+                x1 -= (T)(sx_ * P0);
+                y1 -= (T)(sy_ * P1);
+                if (x1 > Pmax0) x1 = Pmax0;
+                if (y1 > Pmax1) y1 = Pmax1;
+                code = gone ? kRemoved : (uint8_t)((sx_ + 1) + 3 * (sy_ + 1));
+            }
+            S.x[0][g] = x1;
+            S.x[1][g] = y1;
+            S.u[0][g] = ux;
+            S.u[1][g] = uy;
+            S.u[2][g] = uz;
+            S.code[g] = code;
+        }
+        if (err) atomicOr(&S.st->flags, err);
+        __syncthreads();
+
+        // ---- flush the current tile -------------------------------------------
+        {
+            T *const *Jg = S.J[S.st->step & 1];
+            for (int t = tid; t < jw * jh; t += BLOCK) {
+                const int gi = ox - 2 + t % jw, gj = oy - 2 + t / jw;
+                const int ip = axis_node(gi, n0, per0, 0), id = axis_node(gi, n0, per0, 1);
+                const int jp = axis_node(gj, n1, per1, 0), jd = axis_node(gj, n1, per1, 1);
+                const T vx = Jt[t], vy = Jt[jstride + t], vz = Jt[2 * jstride + t];
+                if (vx != T(0) && id >= 0 && jp >= 0) atomicAdd(&Jg[0][id + fn0 * jp], vx);
+                if (vy != T(0) && ip >= 0 && jd >= 0) atomicAdd(&Jg[1][ip + fn0 * jd], vy);
+                if (vz != T(0) && ip >= 0 && jp >= 0) atomicAdd(&Jg[2][ip + fn0 * jp], vz);
+            }
+        }
+        // ---- kinetic energy and pushed count --------------------------------
+        kin = wave_sum(kin);
+        if ((tid & (kWave - 1)) == 0) s_red[tid / kWave] = kin;
+        __syncthreads();
+        if (tid == 0) {
+            double tot = 0.0;
+            for (int wv = 0; wv < BLOCK / kWave; ++wv) tot += s_red[wv];
+            atomicAdd(&S.st->K, tot * S.vcell);
+            atomicAdd((unsigned long long *)&S.st->pushed, (unsigned long long)cnt);
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+size_t lds_bytes(int maxP0, int maxP1, int &fstride, int &jstride)
+{
+    fstride = (maxP0 + 3) * (maxP1 + 3);
+    jstride = (maxP0 + 5) * (maxP1 + 5);
+    return sizeof(T) * (size_t)(6 * fstride + 3 * jstride);
+}
+
+}  // namespace
+
+template <typename T>
+void launch_particles(const SimDev<T> *sims, const Item *items, const int *nitems, int *head,
+                      int grid, int block, int maxP0, int maxP1, hipStream_t st)
+{
+    int fs, js;
+    size_t lds = lds_bytes<T>(maxP0, maxP1, fs, js);
+    if (block == 512)
+        hipLaunchKernelGGL((k_particles2d<T, 512>), dim3(grid), dim3(512), lds, st, sims, items,
+                           nitems, head, fs, js);
+    else
+        hipLaunchKernelGGL((k_particles2d<T, 256>), dim3(grid), dim3(256), lds, st, sims, items,
+                           nitems, head, fs, js);
+}
+
+template <typename T>
+int particles_occupancy(int block, int maxP0, int maxP1)
+{
+    int fs, js, nb = 0;
+    size_t lds = lds_bytes<T>(maxP0, maxP1, fs, js);
+    hipError_t e;
+    if (block == 512)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particles2d<T, 512>, 512, lds);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particles2d<T, 256>, 256, lds);
+    if (e != hipSuccess) return 0;
+    return nb;
+}
+
+template void launch_particles<float>(const SimDev<float> *, const Item *, const int *, int *, int,
+                                      int, int, int, hipStream_t);
+template void launch_particles<double>(const SimDev<double> *, const Item *, const int *, int *,
+                                       int, int, int, int, hipStream_t);
+template int particles_occupancy<float>(int, int, int);
+template int particles_occupancy<double>(int, int, int);
+
+}  // namespace pic

@@ -1,0 +1,487 @@
+// Per-patch re-binning, work-queue build and small service kernels of the
+// 2-D patch-PIC step.
+//
+// Re-binning keeps every patch's particles in slots 0..count-1 and moves only
+// the particles that change patch, under a canonical rule that fixes every
+// slot bit for bit: in patch P with n old slots, L leavers (sent elsewhere or
+// removed) and A arrivals, the new count is n' = n - L + A; the leaver slots
+// below n' (ascending) are filled first by the arrivals, ordered by (source
+// patch id, source slot), then by the stayers found in [n', n) (ascending);
+// what remains of the arrivals is appended from slot n on.  The paper's
+// patches (section 3.1) move particles between patches every step; this rule
+// is the deterministic in-patch order adopted for that exchange.
+//
+// Three passes:
+//  count   (one workgroup per source patch): per destination key, stable
+//          ranks of the leavers by wave ballots; leavers are copied to a
+//          staging area grouped by destination; vacated slots are listed;
+//  check   (one thread per patch): arrivals, new count, vacated slots below
+//          it; a patch that would exceed its capacity raises the pending flag
+//          and the scatter of that simulation is skipped (state stays valid:
+//          the host grows capacities and re-runs the three passes);
+//  scatter (one workgroup per destination patch): arrivals into holes / the
+//          tail, tail stayers into the remaining holes, new count; the
+//          workgroup of patch 0 closes the step (counter, energy history).
+#include "kernels.h"
+
+namespace pic {
+
+namespace {
+
+constexpr int kRB = 256;  // threads per re-binning workgroup
+constexpr int kNW = kRB / 64;
+constexpr int kKeys = kNDir2 + 1;  // 9 direction keys + removed
+
+// Canonical key of each direction of patch p: the smallest direction that
+// reaches the same neighbour; -1 when the neighbour is p itself (the particle
+// stays); kNDir2 when the direction leaves an open face (removed).
+template <typename T>
+__device__ void direction_keys(const SimDev<T> &S, int p, int *key)
+{
+    int nb[kNDir2];
+    for (int d = 0; d < kNDir2; ++d) nb[d] = neighbour2(S, p, d);
+    for (int d = 0; d < kNDir2; ++d) {
+        if (d == kStay2 || nb[d] == p) { key[d] = -1; continue; }
+        if (nb[d] < 0) { key[d] = kNDir2; continue; }
+        int k = d;
+        for (int e = 0; e < d; ++e)
+            if (nb[e] == nb[d] && e != kStay2) { k = e; break; }
+        key[d] = k;
+    }
+}
+
+__device__ __forceinline__ int code_key(const int *key, uint8_t c)
+{
+    return c == kRemoved ? kNDir2 : key[c];
+}
+
+template <typename T>
+__device__ __forceinline__ void copy_particle(const SimDev<T> &S, int64_t from, int64_t to,
+                                              bool from_stage, bool to_stage)
+{
+    T *const *fx = from_stage ? S.sx : S.x;
+    T *const *fu = from_stage ? S.su : S.u;
+    const T *fw = from_stage ? S.sw : S.w;
+    const int64_t *fi = from_stage ? S.sid : S.id;
+    T *const *tx = to_stage ? S.sx : S.x;
+    T *const *tu = to_stage ? S.su : S.u;
+    T *tw = to_stage ? S.sw : S.w;
+    int64_t *ti = to_stage ? S.sid : S.id;
+    tx[0][to] = fx[0][from];
+    tx[1][to] = fx[1][from];
+    tu[0][to] = fu[0][from];
+    tu[1][to] = fu[1][from];
+    tu[2][to] = fu[2][from];
+    tw[to] = fw[from];
+    ti[to] = fi[from];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRB) void k_rebin_count(const SimDev<T> *__restrict__ sims, int nsims,
+                                                     const int *__restrict__ patch_prefix, int total)
+{
+    __shared__ int s_key[kNDir2];
+    __shared__ int s_cnt[kKeys];
+    __shared__ int s_koff[kKeys];
+    __shared__ int s_wc[kNW][kKeys + 1];
+    __shared__ int s_run[kKeys + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+
+    for (int gp = blockIdx.x; gp < total; gp += gridDim.x) {
+        const int s = find_sim(patch_prefix, nsims, gp);
+        const SimDev<T> &S = sims[s];
+        if (!S.st->active) continue;
+        const int p = gp - patch_prefix[s];
+        const int n = S.count[p];
+        const int64_t base = S.off[p];
+        if (tid == 0) direction_keys(S, p, s_key);
+        if (tid < kKeys) s_cnt[tid] = 0;
+        if (tid <= kKeys) s_run[tid] = 0;
+        __syncthreads();
+        for (int k = tid; k < n; k += kRB) {
+            const int key = code_key(s_key, S.code[base + k]);
+            if (key >= 0) atomicAdd(&s_cnt[key], 1);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int acc = 0;
+            for (int k = 0; k < kKeys; ++k) { s_koff[k] = acc; acc += s_cnt[k]; }
+        }
+        __syncthreads();
+        for (int c0 = 0; c0 < n; c0 += kRB) {
+            const int k = c0 + tid;
+            const int key = k < n ? code_key(s_key, S.code[base + k]) : -1;
+            const bool leaver = key >= 0;
+            const uint64_t ball = __ballot(leaver);
+            int rank_key = 0;
+#pragma unroll
+            for (int kk = 0; kk < kKeys; ++kk) {
+                const uint64_t b = __ballot(key == kk);
+                if (key == kk) rank_key = __popcll(b & lt);
+                if (lane == 0) s_wc[wave][kk] = __popcll(b);
+            }
+            if (lane == 0) s_wc[wave][kKeys] = __popcll(ball);
+            __syncthreads();
+            if (leaver) {
+                int rk = s_run[key] + rank_key, ra = s_run[kKeys] + __popcll(ball & lt);
+                for (int w = 0; w < wave; ++w) { rk += s_wc[w][key]; ra += s_wc[w][kKeys]; }
+                S.holes[base + ra] = k;
+                if (key < kNDir2) copy_particle(S, base + k, base + s_koff[key] + rk, false, true);
+            }
+            __syncthreads();
+            if (tid <= kKeys) {
+                int add = 0;
+                for (int w = 0; w < kNW; ++w) add += s_wc[w][tid];
+                s_run[tid] += add;
+            }
+            __syncthreads();
+        }
+        if (tid < kNDir2) S.kcnt[p * kNDir2 + tid] = s_cnt[tid];
+        if (tid == 0) {
+            int L = 0;
+            for (int k = 0; k < kKeys; ++k) L += s_cnt[k];
+            S.nleave[p] = L;
+        }
+        __syncthreads();
+    }
+}
+
+// Distinct source patches of destination q in ascending id, with the key
+// under which each source staged its particles for q.
+template <typename T>
+__device__ int sources_of(const SimDev<T> &S, int q, int *src, int *skey)
+{
+    int ns = 0;
+    for (int d = 0; d < kNDir2; ++d) {
+        if (d == kStay2) continue;
+        const int s = neighbour2(S, q, d);
+        if (s < 0 || s == q) continue;
+        bool seen = false;
+        for (int i = 0; i < ns; ++i) seen |= src[i] == s;
+        if (!seen) src[ns++] = s;
+    }
+    for (int i = 1; i < ns; ++i)  // insertion sort, at most 8 entries
+        for (int j = i; j > 0 && src[j - 1] > src[j]; --j) {
+            const int t = src[j]; src[j] = src[j - 1]; src[j - 1] = t;
+        }
+    for (int i = 0; i < ns; ++i) {
+        int k = -1;
+        for (int d = 0; d < kNDir2 && k < 0; ++d)
+            if (d != kStay2 && neighbour2(S, src[i], d) == q) k = d;
+        skey[i] = k;
+    }
+    return ns;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_rebin_check(const SimDev<T> *__restrict__ sims, int nsims,
+                                                     const int *__restrict__ patch_prefix, int total)
+{
+    const int gp = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gp >= total) return;
+    const int s = find_sim(patch_prefix, nsims, gp);
+    const SimDev<T> &S = sims[s];
+    if (!S.st->active) return;
+    const int q = gp - patch_prefix[s];
+    int src[8], skey[8];
+    const int ns = sources_of(S, q, src, skey);
+    int A = 0;
+    for (int i = 0; i < ns; ++i) A += S.kcnt[src[i] * kNDir2 + skey[i]];
+    const int n = S.count[q], L = S.nleave[q];
+    const int np = n - L + A;
+    // vacated slots below the new count (the list is ascending)
+    const int32_t *h = S.holes + S.off[q];
+    int lo = 0, hi = L;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (h[mid] < np) lo = mid + 1; else hi = mid;
+    }
+    S.newcount[q] = np;
+    S.narrive[q] = A;
+    S.nhole[q] = lo;
+    if (np > S.cap[q]) atomicOr(&S.st->flags, kFlagPending);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRB) void k_rebin_scatter(const SimDev<T> *__restrict__ sims, int nsims,
+                                                       const int *__restrict__ patch_prefix,
+                                                       int total, int finalize)
+{
+    __shared__ int s_src[8], s_skey[8], s_scnt[8];
+    __shared__ int64_t s_sbase[8];
+    __shared__ int s_ns;
+    __shared__ int s_key[kNDir2];
+    __shared__ int s_wc[kNW];
+    __shared__ int s_run;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+
+    for (int gp = blockIdx.x; gp < total; gp += gridDim.x) {
+        const int s = find_sim(patch_prefix, nsims, gp);
+        const SimDev<T> &S = sims[s];
+        if (!S.st->active || (S.st->flags & kFlagPending)) continue;
+        const int q = gp - patch_prefix[s];
+        const int n = S.count[q], np = S.newcount[q], nH = S.nhole[q], A = S.narrive[q];
+        const int64_t base = S.off[q];
+        if (tid == 0) {
+            int src[8], skey[8];
+            const int ns = sources_of(S, q, src, skey);
+            for (int i = 0; i < ns; ++i) {
+                const int sp = src[i], k = skey[i];
+                int koff = 0;
+                for (int e = 0; e < k; ++e) koff += S.kcnt[sp * kNDir2 + e];
+                s_src[i] = sp;
+                s_skey[i] = k;
+                s_scnt[i] = S.kcnt[sp * kNDir2 + k];
+                s_sbase[i] = S.off[sp] + koff;
+            }
+            s_ns = ns;
+            direction_keys(S, q, s_key);
+            s_run = 0;
+        }
+        __syncthreads();
+        // arrivals: holes first, then appended from slot n
+        int abase = 0;
+        for (int i = 0; i < s_ns; ++i) {
+            const int c = s_scnt[i];
+            for (int j = tid; j < c; j += kRB) {
+                const int a = abase + j;
+                const int target = a < nH ? S.holes[base + a] : n + (a - nH);
+                copy_particle(S, s_sbase[i] + j, base + target, true, false);
+            }
+            abase += c;
+        }
+        // stayers in [n', n) fill the remaining holes
+        if (np < n) {
+            for (int c0 = np; c0 < n; c0 += kRB) {
+                const int k = c0 + tid;
+                bool stay = false;
+                if (k < n) {
+                    const uint8_t c = S.code[base + k];
+                    stay = c != kRemoved && s_key[c] < 0;
+                }
+                const uint64_t b = __ballot(stay);
+                if (lane == 0) s_wc[wave] = __popcll(b);
+                __syncthreads();
+                if (stay) {
+                    int r = s_run + __popcll(b & lt);
+                    for (int w = 0; w < wave; ++w) r += s_wc[w];
+                    copy_particle(S, base + k, base + S.holes[base + A + r], false, false);
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    int add = 0;
+                    for (int w = 0; w < kNW; ++w) add += s_wc[w];
+                    s_run += add;
+                }
+                __syncthreads();
+            }
+        }
+        if (tid == 0) {
+            S.count[q] = np;
+            int staged = 0;
+            for (int k = 0; k < kNDir2; ++k) staged += S.kcnt[q * kNDir2 + k];
+            const int removed = S.nleave[q] - staged;
+            if (removed) atomicAdd((unsigned long long *)&S.st->removed, (unsigned long long)removed);
+        }
+        __syncthreads();
+    }
+}
+
+// Close the step of every active simulation whose re-binning was applied.
+template <typename T>
+__global__ void k_step_end(const SimDev<T> *__restrict__ sims, int nsims)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsims) return;
+    SimState *st = sims[s].st;
+    if (!st->active || (st->flags & kFlagPending)) return;
+    const int64_t k = st->step;
+    double *h = sims[s].hist + (k % kHistLen) * 4;
+    h[0] = st->U;
+    h[1] = st->K;
+    h[2] = (double)st->pushed;
+    h[3] = (double)st->removed;
+    st->U = 0.0;
+    st->K = 0.0;
+    st->pushed = 0;
+    st->step = k + 1;
+    if (st->steps_left > 0) st->steps_left -= 1;
+    st->active = 0;
+}
+
+// ---- work queue ---------------------------------------------------------------
+
+constexpr int kQB = 1024;   // threads of the single queue workgroup
+constexpr int kBuckets = 1024;
+
+template <typename T>
+__global__ __launch_bounds__(kQB) void k_queue(const SimDev<T> *__restrict__ sims, QueueArgs qa)
+{
+    __shared__ int s_hist[kBuckets];
+    __shared__ uint8_t s_act[4096];
+    __shared__ int s_wsum[kQB / 64];
+    const int tid = threadIdx.x;
+    const int nsims = qa.nsims;
+    const int total = qa.patch_prefix[nsims];
+    const int chunk = qa.chunk;
+    for (int b = tid; b < kBuckets; b += kQB) s_hist[b] = 0;
+    for (int s = tid; s < nsims; s += kQB) {
+        SimState *st = sims[s].st;
+        const uint32_t act = st->steps_left > 0 && !(st->flags & (kFlagPending | kFlagErrMask));
+        st->active = act;
+        s_act[s] = (uint8_t)act;
+    }
+    __syncthreads();
+    // bucket of a chunk of c particles: larger chunks first
+    auto bucket = [&](int c) { return kBuckets - 1 - (int)(((int64_t)(c - 1) * kBuckets) / chunk); };
+    for (int gp = tid; gp < total; gp += kQB) {
+        const int s = find_sim(qa.patch_prefix, nsims, gp);
+        if (!s_act[s]) continue;
+        const int n = sims[s].count[gp - qa.patch_prefix[s]];
+        for (int c0 = 0; c0 < n; c0 += chunk) atomicAdd(&s_hist[bucket(min(chunk, n - c0))], 1);
+    }
+    __syncthreads();
+    // exclusive scan of the histogram (one bucket per thread)
+    int v = tid < kBuckets ? s_hist[tid] : 0;
+    int incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o, 64);
+        if ((tid & 63) >= o) incl += y;
+    }
+    if ((tid & 63) == 63) s_wsum[tid >> 6] = incl;
+    __syncthreads();
+    int woff = 0;
+    for (int w = 0; w < (tid >> 6); ++w) woff += s_wsum[w];
+    const int excl = woff + incl - v;
+    __syncthreads();
+    if (tid < kBuckets) s_hist[tid] = excl;
+    int ntot = 0;
+    for (int w = 0; w < kQB / 64; ++w) ntot += s_wsum[w];
+    __syncthreads();
+    for (int gp = tid; gp < total; gp += kQB) {
+        const int s = find_sim(qa.patch_prefix, nsims, gp);
+        if (!s_act[s]) continue;
+        const int p = gp - qa.patch_prefix[s];
+        const int n = sims[s].count[p];
+        for (int c0 = 0; c0 < n; c0 += chunk) {
+            const int c = min(chunk, n - c0);
+            const int pos = atomicAdd(&s_hist[bucket(c)], 1);
+            if (pos < qa.max_items) qa.items[pos] = make_int4(s, p, c0, c);
+        }
+    }
+    if (tid == 0) {
+        *qa.nitems = min(ntot, qa.max_items);
+        *qa.head = 0;
+    }
+}
+
+// ---- capacity growth ------------------------------------------------------------
+
+template <typename T>
+__global__ void k_relayout(const SimDev<T> *__restrict__ src, const SimDev<T> *__restrict__ dst)
+{
+    const int p = blockIdx.x;
+    const int n = src->count[p];
+    const int64_t a = src->off[p], b = dst->off[p];
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        dst->x[0][b + k] = src->x[0][a + k];
+        dst->x[1][b + k] = src->x[1][a + k];
+        dst->u[0][b + k] = src->u[0][a + k];
+        dst->u[1][b + k] = src->u[1][a + k];
+        dst->u[2][b + k] = src->u[2][a + k];
+        dst->w[b + k] = src->w[a + k];
+        dst->id[b + k] = src->id[a + k];
+        dst->code[b + k] = src->code[a + k];
+    }
+}
+
+// ---- diagnostics ------------------------------------------------------------------
+
+template <typename T>
+__global__ void k_rho(const SimDev<T> *__restrict__ S, double *__restrict__ out)
+{
+    const int p = blockIdx.x;
+    const int n = S->count[p];
+    const int64_t base = S->off[p];
+    const int ox = (p % S->np[0]) * S->P[0], oy = (p / S->np[0]) * S->P[1];
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        const double x = (double)S->x[0][base + k], y = (double)S->x[1][base + k];
+        const double qw = (double)S->q * (double)S->w[base + k];
+        const int ix = (int)floor(x + 0.5), iy = (int)floor(y + 0.5);
+        const double dx = x - ix, dy = y - iy;
+        const double wx[3] = {0.5 * (0.5 - dx) * (0.5 - dx), 0.75 - dx * dx, 0.5 * (0.5 + dx) * (0.5 + dx)};
+        const double wy[3] = {0.5 * (0.5 - dy) * (0.5 - dy), 0.75 - dy * dy, 0.5 * (0.5 + dy) * (0.5 + dy)};
+        for (int b = 0; b < 3; ++b)
+            for (int a = 0; a < 3; ++a) {
+                const int gi = axis_node(ox + ix + a - 1, S->n[0], S->periodic[0], 0);
+                const int gj = axis_node(oy + iy + b - 1, S->n[1], S->periodic[1], 0);
+                if (gi >= 0 && gj >= 0) atomicAdd(&out[gi + (int64_t)S->fn[0] * gj], qw * wx[a] * wy[b]);
+            }
+    }
+}
+
+__global__ void k_scatter_codes(const uint8_t *__restrict__ packed,
+                                const int64_t *__restrict__ packed_off,
+                                const int64_t *__restrict__ off, const int32_t *__restrict__ count,
+                                uint8_t *__restrict__ code)
+{
+    const int p = blockIdx.x;
+    const int n = count[p];
+    for (int k = threadIdx.x; k < n; k += blockDim.x) code[off[p] + k] = packed[packed_off[p] + k];
+}
+
+}  // namespace
+
+template <typename T>
+void launch_queue(const SimDev<T> *sims, const QueueArgs &q, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_queue<T>), dim3(1), dim3(kQB), 0, st, sims, q);
+}
+
+template <typename T>
+void launch_rebin(const SimDev<T> *sims, int nsims, const int *patch_prefix, int total_patches,
+                  int grid, bool finalize, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_rebin_count<T>), dim3(grid), dim3(kRB), 0, st, sims, nsims, patch_prefix,
+                       total_patches);
+    hipLaunchKernelGGL((k_rebin_check<T>), dim3((total_patches + 255) / 256), dim3(256), 0, st, sims,
+                       nsims, patch_prefix, total_patches);
+    hipLaunchKernelGGL((k_rebin_scatter<T>), dim3(grid), dim3(kRB), 0, st, sims, nsims,
+                       patch_prefix, total_patches, finalize ? 1 : 0);
+    if (finalize)
+        hipLaunchKernelGGL((k_step_end<T>), dim3((nsims + 63) / 64), dim3(64), 0, st, sims, nsims);
+}
+
+template <typename T>
+void launch_relayout(const SimDev<T> *src, const SimDev<T> *dst, int npatch, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_relayout<T>), dim3(npatch), dim3(256), 0, st, src, dst);
+}
+
+template <typename T>
+void launch_rho(const SimDev<T> *sim, int npatch, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_rho<T>), dim3(npatch), dim3(256), 0, st, sim, out);
+}
+
+void launch_scatter_codes(const uint8_t *packed, const int64_t *packed_off, const int64_t *off,
+                          const int32_t *count, uint8_t *code, int npatch, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_scatter_codes, dim3(npatch), dim3(256), 0, st, packed, packed_off, off,
+                       count, code);
+}
+
+#define PIC_INST(T)                                                                              \
+    template void launch_queue<T>(const SimDev<T> *, const QueueArgs &, hipStream_t);            \
+    template void launch_rebin<T>(const SimDev<T> *, int, const int *, int, int, bool,           \
+                                  hipStream_t);                                                  \
+    template void launch_relayout<T>(const SimDev<T> *, const SimDev<T> *, int, hipStream_t);    \
+    template void launch_rho<T>(const SimDev<T> *, int, double *, hipStream_t);
+PIC_INST(float)
+PIC_INST(double)
+#undef PIC_INST
+
+}  // namespace pic

@@ -1,0 +1,59 @@
+// Launch wrappers of the 2-D patch-PIC kernels (defined in the .hip files).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "pic_dev.h"
+
+namespace pic {
+
+// Work item of the particle kernel: simulation slot, patch, first slot, count.
+using Item = int4;
+
+struct QueueArgs {
+    int nsims;
+    const int *patch_prefix;  // nsims + 1 entries (global patch numbering)
+    Item *items;
+    int *nitems;
+    int *head;
+    int max_items;
+    int chunk;                // max particles per item
+};
+
+template <typename T>
+void launch_queue(const SimDev<T> *sims, const QueueArgs &q, hipStream_t st);
+
+// Persistent particle kernel: gather, Boris, move, classify, Esirkepov deposit.
+template <typename T>
+void launch_particles(const SimDev<T> *sims, const Item *items, const int *nitems, int *head,
+                      int grid, int block, int maxP0, int maxP1, hipStream_t st);
+template <typename T>
+int particles_occupancy(int block, int maxP0, int maxP1);
+
+// Fused Yee update (half B, E, half B) with face conditions; clears the
+// other J buffer and accumulates the field energy of the incoming E, B.
+template <typename T>
+void launch_maxwell(const SimDev<T> *sims, int nsims, const int *tile_prefix, int total_tiles,
+                    int grid, hipStream_t st);
+template <typename T>
+void maxwell_tile(int &tx, int &ty);
+
+// Re-binning: count and stage leavers; check capacity; scatter.
+template <typename T>
+void launch_rebin(const SimDev<T> *sims, int nsims, const int *patch_prefix, int total_patches,
+                  int grid, bool finalize, hipStream_t st);
+
+// Copy particles into a new per-patch layout (capacity growth).
+template <typename T>
+void launch_relayout(const SimDev<T> *src, const SimDev<T> *dst, int npatch, hipStream_t st);
+
+// Charge density on primal nodes (diagnostic).
+template <typename T>
+void launch_rho(const SimDev<T> *sim, int npatch, double *out, hipStream_t st);
+
+// Set the destination codes of all live particles from a packed host-supplied
+// array in (patch, slot) order.
+void launch_scatter_codes(const uint8_t *packed, const int64_t *packed_off, const int64_t *off,
+                          const int32_t *count, uint8_t *code, int npatch, hipStream_t st);
+
+}  // namespace pic

@@ -1,0 +1,124 @@
+// Device-side data layout and shared device helpers of the patch-PIC library.
+//
+// Layout in HBM (per simulation):
+//  - fields: one array per component (Ex Ey Ez Bx By Bz, and two J buffers of
+//    three components), row-major with x fastest, fn[a] nodes per axis;
+//  - particles: structure of arrays (local position per axis, u_x, u_y, u_z,
+//    weight, 64-bit id, 1-byte destination code) grouped by patch: patch p owns
+//    slots [off[p], off[p] + cap[p]) of every array and uses the first count[p];
+//    positions are offsets from the patch origin in cell units;
+//  - re-binning scratch with the same per-patch layout: a staging copy of the
+//    particle arrays for leavers and a list of vacated slots;
+//  - a small state block (step counter, remaining step budget, sticky flags,
+//    energy accumulators) and an energy-history ring.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pic {
+
+constexpr int kMaxPatch = 64;      // cells per patch per axis
+constexpr int kHistLen = 4096;     // energy-history ring length
+constexpr int kNDir2 = 9;          // neighbour directions in 2-D (4 = stay)
+constexpr int kStay2 = 4;
+constexpr uint8_t kRemoved = 255;
+
+// sticky state flags
+constexpr uint32_t kFlagPending = 1u;  // a patch overflowed: re-binning of the last step not applied
+constexpr uint32_t kFlagNaN = 2u;      // non-finite momentum
+constexpr uint32_t kFlagCFL = 4u;      // a particle moved a cell or more
+constexpr uint32_t kFlagErrMask = kFlagNaN | kFlagCFL;
+
+struct SimState {
+    int64_t step;        // completed steps
+    int64_t steps_left;  // step budget; kernels skip the simulation at 0
+    uint32_t flags;
+    uint32_t active;     // set by the queue kernel for the step in flight
+    int64_t removed;
+    int64_t pushed;      // particles pushed in the step in flight
+    double U, K;         // energy accumulators of the step in flight
+};
+
+template <typename T>
+struct SimDev {
+    int n[3], P[3], np[3], fn[3], periodic[3];
+    int npatch;
+    int ndim;
+    T d[3];
+    T dt;
+    T q, m;
+    double vcell;
+    // fields
+    T *F[6];
+    T *J[2][3];
+    // particles
+    T *x[3], *u[3], *w;
+    int64_t *id;
+    uint8_t *code;
+    // staging copy for leavers
+    T *sx[3], *su[3], *sw;
+    int64_t *sid;
+    int32_t *holes;
+    const int32_t *cap;
+    const int64_t *off;
+    int32_t *count;
+    int32_t *newcount;
+    int32_t *kcnt;     // per patch: leavers per canonical direction key (kNDir2)
+    int32_t *nleave;   // per patch: all leavers (incl. removed)
+    int32_t *narrive;  // per patch: arrivals (set by the capacity check)
+    int32_t *nhole;    // per patch: vacated slots below the new count
+    const T *laser_ey, *laser_ez;
+    int64_t laser_steps;
+    SimState *st;
+    double *hist;      // [kHistLen][4]: U, K, pushed, removed
+};
+
+// ---- small helpers ----------------------------------------------------------
+
+__device__ __forceinline__ int wrap_idx(int i, int n)
+{
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+// Storage index of node i on an axis, or -1 outside an open axis.  stag = 1
+// for dual (half-cell) positions, which exist only up to n-1 on an open axis.
+__device__ __forceinline__ int axis_node(int i, int n, int periodic, int stag)
+{
+    if (periodic) return wrap_idx(i, n);
+    if (i < 0 || i > n - stag) return -1;
+    return i;
+}
+
+// Neighbour patch of patch p in direction dir (2-D, (dx+1) + 3 (dy+1)), with
+// periodic wrap; -1 when it falls off an open axis.
+template <typename T>
+__device__ __forceinline__ int neighbour2(const SimDev<T> &S, int p, int dir)
+{
+    int px = p % S.np[0], py = p / S.np[0];
+    int qx = px + (dir % 3) - 1, qy = py + (dir / 3) - 1;
+    if (qx < 0 || qx >= S.np[0]) {
+        if (!S.periodic[0]) return -1;
+        qx = wrap_idx(qx, S.np[0]);
+    }
+    if (qy < 0 || qy >= S.np[1]) {
+        if (!S.periodic[1]) return -1;
+        qy = wrap_idx(qy, S.np[1]);
+    }
+    return qx + S.np[0] * qy;
+}
+
+// Locate the simulation of a global work index through an exclusive prefix
+// table of per-simulation work counts (nsims + 1 entries).
+__device__ __forceinline__ int find_sim(const int *prefix, int nsims, int g)
+{
+    int lo = 0, hi = nsims - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+}  // namespace pic

@@ -1,0 +1,884 @@
+// Host runtime of the patch-PIC library: simulation and batch objects, device
+// memory through the allocator hook, step orchestration on a HIP stream, and
+// capacity growth when a patch overflows.  Exposed through the C ABI in
+// capi.cpp.
+#include "runtime.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+namespace pic {
+
+thread_local std::string g_last_error;
+
+void set_error(const std::string &m) { g_last_error = m; }
+
+// ---------------------------------------------------------------------------
+// device memory
+
+void *Allocator::get(size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) & ~size_t(255);
+    void *p = nullptr;
+    if (hook.alloc) {
+        p = hook.alloc(bytes, hook.ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+    }
+    if (!p) throw Error(PIC_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    live_bytes += bytes;
+    sizes[p] = bytes;
+    return p;
+}
+
+void Allocator::put(void *p)
+{
+    if (!p) return;
+    auto it = sizes.find(p);
+    if (it != sizes.end()) {
+        live_bytes -= it->second;
+        sizes.erase(it);
+    }
+    if (hook.free) hook.free(p, hook.ctx);
+    else (void)hipFree(p);
+}
+
+void hipcheck(hipError_t e, const char *what)
+{
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error(PIC_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+    }
+}
+
+static int cu_count()
+{
+    static int cached = 0;
+    if (!cached) {
+        int dev = 0, n = 0;
+        hipcheck(hipGetDevice(&dev), "hipGetDevice");
+        hipcheck(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev),
+                 "hipDeviceGetAttribute");
+        cached = n > 0 ? n : 1;
+    }
+    return cached;
+}
+
+// ---------------------------------------------------------------------------
+// descriptor validation (host only, before any device call)
+
+int validate_desc(const PicSimDesc &d, std::string &why)
+{
+    if (d.ndim != 2) { why = "ndim must be 2"; return PIC_ENOTSUP; }
+    if (d.precision != 32 && d.precision != 64) { why = "precision must be 32 or 64"; return PIC_EINVAL; }
+    double inv2 = 0.0;
+    for (int a = 0; a < d.ndim; ++a) {
+        if (d.n[a] <= 0 || d.patch[a] <= 0) { why = "cell and patch counts must be positive"; return PIC_EINVAL; }
+        if (d.patch[a] > kMaxPatch) { why = "patch size above 64 cells"; return PIC_EINVAL; }
+        if (d.n[a] % d.patch[a]) { why = "patch size must divide the cell count"; return PIC_EINVAL; }
+        if (!(d.d[a] > 0.0) || !std::isfinite(d.d[a])) { why = "cell sizes must be positive"; return PIC_EINVAL; }
+        if (a > 0 && !d.periodic[a]) { why = "only the x axis may be open"; return PIC_EINVAL; }
+        inv2 += 1.0 / (d.d[a] * d.d[a]);
+    }
+    if ((int64_t)d.n[0] * d.n[1] > (int64_t)1 << 30) { why = "grid too large"; return PIC_EINVAL; }
+    if (!(d.dt > 0.0) || d.dt >= 1.0 / std::sqrt(inv2)) { why = "dt must be positive and below the Yee limit"; return PIC_EINVAL; }
+    if (!(d.m > 0.0) || !std::isfinite(d.q)) { why = "species mass must be positive"; return PIC_EINVAL; }
+    if (d.capacity_factor != 0.0 && !(d.capacity_factor >= 1.0)) { why = "capacity_factor must be >= 1"; return PIC_EINVAL; }
+    if (d.min_capacity < 0 || d.chunk < 0) { why = "negative min_capacity or chunk"; return PIC_EINVAL; }
+    if (d.block != 0 && d.block != 256 && d.block != 512) { why = "block must be 0, 256 or 512"; return PIC_EINVAL; }
+    return PIC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// SimImpl
+
+template <typename T>
+SimImpl<T>::SimImpl(const PicSimDesc &d, const PicAllocator *a, hipStream_t s)
+{
+    desc = d;
+    if (desc.capacity_factor == 0.0) desc.capacity_factor = 1.5;
+    if (desc.min_capacity == 0) desc.min_capacity = 64;
+    precision = d.precision;
+    stream = s;
+    if (a) alloc.hook = *a;
+    for (int ax = 0; ax < 3; ++ax) {
+        n[ax] = ax < 2 ? d.n[ax] : 1;
+        P[ax] = ax < 2 ? d.patch[ax] : 1;
+        periodic[ax] = ax < 2 ? (d.periodic[ax] ? 1 : 0) : 1;
+        np[ax] = n[ax] / P[ax];
+        fn[ax] = (ax < 2 && !periodic[ax]) ? n[ax] + 1 : n[ax];
+    }
+    npatch = np[0] * np[1];
+    fsize = (int64_t)fn[0] * fn[1];
+    std::memset(&v, 0, sizeof(v));
+    try {
+        for (int c = 0; c < 6; ++c) F[c] = (T *)alloc.get(sizeof(T) * fsize);
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < 3; ++c) J[b][c] = (T *)alloc.get(sizeof(T) * fsize);
+        st = (SimState *)alloc.get(sizeof(SimState));
+        hist = (double *)alloc.get(sizeof(double) * kHistLen * 4);
+        counts_d = (int32_t *)alloc.get(sizeof(int32_t) * npatch);
+        newcount_d = (int32_t *)alloc.get(sizeof(int32_t) * npatch);
+        kcnt_d = (int32_t *)alloc.get(sizeof(int32_t) * npatch * kNDir2);
+        nleave_d = (int32_t *)alloc.get(sizeof(int32_t) * npatch);
+        narrive_d = (int32_t *)alloc.get(sizeof(int32_t) * npatch);
+        nhole_d = (int32_t *)alloc.get(sizeof(int32_t) * npatch);
+        prefix_d = (int *)alloc.get(sizeof(int) * 2);
+        view_d = (SimDev<T> *)alloc.get(sizeof(SimDev<T>));
+        for (int c = 0; c < 6; ++c) hipcheck(hipMemsetAsync(F[c], 0, sizeof(T) * fsize, stream), "memset F");
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < 3; ++c)
+                hipcheck(hipMemsetAsync(J[b][c], 0, sizeof(T) * fsize, stream), "memset J");
+        hipcheck(hipMemsetAsync(st, 0, sizeof(SimState), stream), "memset state");
+        hipcheck(hipMemsetAsync(hist, 0, sizeof(double) * kHistLen * 4, stream), "memset hist");
+        hipcheck(hipMemsetAsync(counts_d, 0, sizeof(int32_t) * npatch, stream), "memset counts");
+        int pre[2] = {0, npatch};
+        hipcheck(hipMemcpyAsync(prefix_d, pre, sizeof(pre), hipMemcpyHostToDevice, stream), "prefix");
+        // an empty particle layout so that every kernel sees valid pointers
+        std::vector<int32_t> cnt0(npatch, 0);
+        layout_particles(cnt0);
+        hipcheck(hipStreamSynchronize(stream), "create sync");
+    } catch (...) {
+        release();
+        throw;
+    }
+}
+
+template <typename T>
+SimImpl<T>::~SimImpl()
+{
+    if (stream) (void)hipStreamSynchronize(stream);
+    if (batch) {
+        try { batch->remove(this); } catch (...) {}
+    }
+    delete solo;
+    solo = nullptr;
+    release();
+}
+
+template <typename T>
+void SimImpl<T>::step(int64_t nsteps)
+{
+    check_free();
+    if (nsteps < 0) throw Error(PIC_EINVAL, "negative step count");
+    if (nsteps == 0) return;
+    SimState s = read_state();
+    if (s.flags & kFlagErrMask) throw Error((s.flags & kFlagNaN) ? PIC_ENAN : PIC_ECFL, "simulation stopped by a particle error");
+    if (!solo) {
+        solo = new BatchImpl<T>(stream);
+        solo->solo_mode = true;
+        solo->members.push_back(this);
+        solo->dirty = true;
+    }
+    s.steps_left = nsteps;
+    hipcheck(hipMemcpy(&st->steps_left, &s.steps_left, sizeof(int64_t), hipMemcpyHostToDevice), "budget");
+    if (solo->dirty) solo->build_tables();
+    else solo->refresh_member_views();
+    if (solo->dirty) solo->build_tables();
+    solo->run(0, true);
+}
+
+template <typename T>
+void SimImpl<T>::free_particles()
+{
+    for (void *p : part_bufs) alloc.put(p);
+    part_bufs.clear();
+}
+
+template <typename T>
+void SimImpl<T>::release()
+{
+    free_particles();
+    for (int c = 0; c < 6; ++c) alloc.put(F[c]);
+    for (int b = 0; b < 2; ++b)
+        for (int c = 0; c < 3; ++c) alloc.put(J[b][c]);
+    alloc.put(st);
+    alloc.put(hist);
+    alloc.put(counts_d);
+    alloc.put(newcount_d);
+    alloc.put(kcnt_d);
+    alloc.put(nleave_d);
+    alloc.put(narrive_d);
+    alloc.put(nhole_d);
+    alloc.put(prefix_d);
+    alloc.put(view_d);
+    alloc.put(laser_ey);
+    alloc.put(laser_ez);
+    for (auto &e : timing.events) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    timing.events.clear();
+}
+
+// Allocate a particle layout whose patch capacities hold `need` particles
+// with slack, and point the view at it.  The previous buffers are kept in
+// `old` (caller frees them) so their contents can be copied over.
+template <typename T>
+std::vector<void *> SimImpl<T>::layout_particles(const std::vector<int32_t> &need)
+{
+    std::vector<int32_t> cap(npatch);
+    std::vector<int64_t> off(npatch + 1, 0);
+    for (int p = 0; p < npatch; ++p) {
+        int64_t c = (int64_t)std::ceil(desc.capacity_factor * need[p]);
+        c = std::max<int64_t>(c, desc.min_capacity);
+        c = std::max<int64_t>(c, need[p]);
+        c = (c + 63) & ~int64_t(63);
+        if (p < (int)cap_h.size()) c = std::max<int64_t>(c, cap_h[p]);  // never shrink
+        if (c > INT32_MAX / 2) throw Error(PIC_EOVERFLOW, "patch capacity overflow");
+        cap[p] = (int32_t)c;
+        off[p + 1] = off[p] + c;
+    }
+    const int64_t total = off[npatch];
+    std::vector<void *> old;
+    old.swap(part_bufs);
+    try {
+        auto get = [&](size_t bytes) {
+            void *p = alloc.get(bytes);
+            part_bufs.push_back(p);
+            return p;
+        };
+        for (int a = 0; a < 2; ++a) {
+            px[a] = (T *)get(sizeof(T) * total);
+            sx[a] = (T *)get(sizeof(T) * total);
+        }
+        for (int a = 0; a < 3; ++a) {
+            pu[a] = (T *)get(sizeof(T) * total);
+            su[a] = (T *)get(sizeof(T) * total);
+        }
+        pw = (T *)get(sizeof(T) * total);
+        sw = (T *)get(sizeof(T) * total);
+        pid = (int64_t *)get(sizeof(int64_t) * total);
+        sid = (int64_t *)get(sizeof(int64_t) * total);
+        code = (uint8_t *)get(total);
+        holes = (int32_t *)get(sizeof(int32_t) * total);
+        cap_d = (int32_t *)get(sizeof(int32_t) * npatch);
+        off_d = (int64_t *)get(sizeof(int64_t) * (npatch + 1));
+        hipcheck(hipMemcpyAsync(cap_d, cap.data(), sizeof(int32_t) * npatch, hipMemcpyHostToDevice, stream), "cap");
+        hipcheck(hipMemcpyAsync(off_d, off.data(), sizeof(int64_t) * (npatch + 1), hipMemcpyHostToDevice, stream), "off");
+    } catch (...) {
+        for (void *p : part_bufs) alloc.put(p);
+        part_bufs.swap(old);
+        throw;
+    }
+    cap_h = cap;
+    off_h = off;
+    total_cap = total;
+    max_items_cache = -1;
+    refresh_view();
+    return old;
+}
+
+template <typename T>
+void SimImpl<T>::refresh_view()
+{
+    SimDev<T> &V = v;
+    for (int a = 0; a < 3; ++a) {
+        V.n[a] = n[a];
+        V.P[a] = P[a];
+        V.np[a] = np[a];
+        V.fn[a] = fn[a];
+        V.periodic[a] = periodic[a];
+        V.d[a] = (T)(a < 2 ? desc.d[a] : 1.0);
+    }
+    V.npatch = npatch;
+    V.ndim = 2;
+    V.dt = (T)desc.dt;
+    V.q = (T)desc.q;
+    V.m = (T)desc.m;
+    V.vcell = desc.d[0] * desc.d[1];
+    for (int c = 0; c < 6; ++c) V.F[c] = F[c];
+    for (int b = 0; b < 2; ++b)
+        for (int c = 0; c < 3; ++c) V.J[b][c] = J[b][c];
+    V.x[0] = px[0]; V.x[1] = px[1]; V.x[2] = nullptr;
+    V.sx[0] = sx[0]; V.sx[1] = sx[1]; V.sx[2] = nullptr;
+    for (int a = 0; a < 3; ++a) { V.u[a] = pu[a]; V.su[a] = su[a]; }
+    V.w = pw; V.sw = sw; V.id = pid; V.sid = sid; V.code = code; V.holes = holes;
+    V.cap = cap_d; V.off = off_d; V.count = counts_d; V.newcount = newcount_d;
+    V.kcnt = kcnt_d; V.nleave = nleave_d; V.narrive = narrive_d; V.nhole = nhole_d;
+    V.laser_ey = laser_ey; V.laser_ez = laser_ez; V.laser_steps = laser_steps;
+    V.st = st; V.hist = hist;
+    hipcheck(hipMemcpyAsync(view_d, &v, sizeof(v), hipMemcpyHostToDevice, stream), "view upload");
+    ++layout_version;
+}
+
+template <typename T>
+void SimImpl<T>::set_particles(int64_t cnt, const double *const xs[3], const double *const us[3],
+                               const double *w)
+{
+    check_free();
+    for (int64_t k = 0; k < cnt; ++k)
+        for (int a = 0; a < 2; ++a)
+            if (!(xs[a][k] >= 0.0 && xs[a][k] < (double)n[a]))
+                throw Error(PIC_EINVAL, "particle " + std::to_string(k) + " outside the domain");
+    // patch of each particle and counts
+    std::vector<int32_t> pp(cnt), counts(npatch, 0);
+    for (int64_t k = 0; k < cnt; ++k) {
+        int cx = std::min((int)std::floor(xs[0][k]), n[0] - 1) / P[0];
+        int cy = std::min((int)std::floor(xs[1][k]), n[1] - 1) / P[1];
+        pp[k] = cx + np[0] * cy;
+        counts[pp[k]]++;
+    }
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    std::vector<void *> old = layout_particles(counts);
+    for (void *p : old) alloc.put(p);
+    // canonical initial order: id order inside each patch
+    std::vector<int64_t> pos(off_h.begin(), off_h.end() - 1);
+    const int64_t tot = total_cap;
+    std::vector<T> hx[2], hu[3];
+    for (auto &a : hx) a.assign(tot, T(0));
+    for (auto &a : hu) a.assign(tot, T(0));
+    std::vector<T> hw(tot, T(0));
+    std::vector<int64_t> hid(tot, -1);
+    const T pmax[2] = {std::nextafter((T)P[0], (T)0), std::nextafter((T)P[1], (T)0)};
+    for (int64_t k = 0; k < cnt; ++k) {
+        const int p = pp[k];
+        const int64_t t = pos[p]++;
+        const int o[2] = {(p % np[0]) * P[0], (p / np[0]) * P[1]};
+        for (int a = 0; a < 2; ++a) {
+            T loc = (T)(xs[a][k] - (double)o[a]);
+            if (loc > pmax[a]) loc = pmax[a];
+            if (loc < T(0)) loc = T(0);
+            hx[a][t] = loc;
+        }
+        for (int a = 0; a < 3; ++a) hu[a][t] = us[a] ? (T)us[a][k] : T(0);
+        hw[t] = (T)w[k];
+        hid[t] = k;
+    }
+    for (int a = 0; a < 2; ++a)
+        hipcheck(hipMemcpyAsync(px[a], hx[a].data(), sizeof(T) * tot, hipMemcpyHostToDevice, stream), "x");
+    for (int a = 0; a < 3; ++a)
+        hipcheck(hipMemcpyAsync(pu[a], hu[a].data(), sizeof(T) * tot, hipMemcpyHostToDevice, stream), "u");
+    hipcheck(hipMemcpyAsync(pw, hw.data(), sizeof(T) * tot, hipMemcpyHostToDevice, stream), "w");
+    hipcheck(hipMemcpyAsync(pid, hid.data(), sizeof(int64_t) * tot, hipMemcpyHostToDevice, stream), "id");
+    hipcheck(hipMemsetAsync(code, kStay2, tot, stream), "code");
+    hipcheck(hipMemcpyAsync(counts_d, counts.data(), sizeof(int32_t) * npatch, hipMemcpyHostToDevice, stream), "counts");
+    SimState s0;
+    std::memset(&s0, 0, sizeof(s0));
+    hipcheck(hipMemcpyAsync(st, &s0, sizeof(s0), hipMemcpyHostToDevice, stream), "state");
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    relayouts = 0;
+    if (solo) solo->dirty = true;
+}
+
+template <typename T>
+void SimImpl<T>::set_laser(int64_t nsteps, const double *ey, const double *ez)
+{
+    check_free();
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    alloc.put(laser_ey);
+    alloc.put(laser_ez);
+    laser_ey = laser_ez = nullptr;
+    laser_steps = nsteps;
+    const size_t cnt = (size_t)nsteps * n[1];
+    std::vector<T> tmp(cnt);
+    if (ey) {
+        for (size_t k = 0; k < cnt; ++k) tmp[k] = (T)ey[k];
+        laser_ey = (T *)alloc.get(sizeof(T) * cnt);
+        hipcheck(hipMemcpyAsync(laser_ey, tmp.data(), sizeof(T) * cnt, hipMemcpyHostToDevice, stream), "laser");
+        hipcheck(hipStreamSynchronize(stream), "sync");
+    }
+    if (ez) {
+        for (size_t k = 0; k < cnt; ++k) tmp[k] = (T)ez[k];
+        laser_ez = (T *)alloc.get(sizeof(T) * cnt);
+        hipcheck(hipMemcpyAsync(laser_ez, tmp.data(), sizeof(T) * cnt, hipMemcpyHostToDevice, stream), "laser");
+        hipcheck(hipStreamSynchronize(stream), "sync");
+    }
+    refresh_view();
+    hipcheck(hipStreamSynchronize(stream), "sync");
+}
+
+template <typename T>
+void SimImpl<T>::set_field(int comp, const double *h)
+{
+    check_free();
+    if (comp < 0 || comp > 5) throw Error(PIC_EINVAL, "only E and B components can be set");
+    std::vector<T> tmp(fsize);
+    for (int64_t k = 0; k < fsize; ++k) tmp[k] = (T)h[k];
+    hipcheck(hipMemcpyAsync(F[comp], tmp.data(), sizeof(T) * fsize, hipMemcpyHostToDevice, stream), "field");
+    hipcheck(hipStreamSynchronize(stream), "sync");
+}
+
+template <typename T>
+void SimImpl<T>::get_field(int comp, double *h)
+{
+    if (comp < 0 || comp > 9) throw Error(PIC_EINVAL, "bad component");
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    if (comp == PIC_RHO) {
+        double *tmp = (double *)alloc.get(sizeof(double) * fsize);
+        hipcheck(hipMemsetAsync(tmp, 0, sizeof(double) * fsize, stream), "memset rho");
+        launch_rho<T>(view_d, npatch, tmp, stream);
+        hipcheck(hipGetLastError(), "rho launch");
+        hipcheck(hipMemcpyAsync(h, tmp, sizeof(double) * fsize, hipMemcpyDeviceToHost, stream), "rho");
+        hipcheck(hipStreamSynchronize(stream), "sync");
+        alloc.put(tmp);
+        return;
+    }
+    SimState s;
+    hipcheck(hipMemcpy(&s, st, sizeof(s), hipMemcpyDeviceToHost), "state");
+    const T *src = comp < 6 ? F[comp] : J[(s.step + 1) & 1][comp - 6];
+    std::vector<T> tmp(fsize);
+    hipcheck(hipMemcpyAsync(tmp.data(), src, sizeof(T) * fsize, hipMemcpyDeviceToHost, stream), "field");
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    for (int64_t k = 0; k < fsize; ++k) h[k] = (double)tmp[k];
+}
+
+template <typename T>
+SimState SimImpl<T>::read_state()
+{
+    SimState s;
+    hipcheck(hipMemcpyAsync(&s, st, sizeof(s), hipMemcpyDeviceToHost, stream), "state");
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    return s;
+}
+
+template <typename T>
+std::vector<int32_t> SimImpl<T>::read_counts()
+{
+    std::vector<int32_t> c(npatch);
+    hipcheck(hipMemcpyAsync(c.data(), counts_d, sizeof(int32_t) * npatch, hipMemcpyDeviceToHost, stream), "counts");
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    return c;
+}
+
+template <typename T>
+int64_t SimImpl<T>::num_particles()
+{
+    auto c = read_counts();
+    return std::accumulate(c.begin(), c.end(), int64_t(0));
+}
+
+template <typename T>
+void SimImpl<T>::get_particles(double *xo[3], double *uo[3], double *wo, int64_t *ido, size_t cnt)
+{
+    auto c = read_counts();
+    const int64_t live = std::accumulate(c.begin(), c.end(), int64_t(0));
+    if ((int64_t)cnt < live) throw Error(PIC_EINVAL, "output arrays too small");
+    const int64_t tot = total_cap;
+    std::vector<T> tmp(tot);
+    std::vector<int64_t> itmp;
+    auto fetch = [&](const T *src, double *dst, int axis) {
+        hipcheck(hipMemcpyAsync(tmp.data(), src, sizeof(T) * tot, hipMemcpyDeviceToHost, stream), "particles");
+        hipcheck(hipStreamSynchronize(stream), "sync");
+        int64_t o = 0;
+        for (int p = 0; p < npatch; ++p) {
+            const double org = axis == 0 ? (double)((p % np[0]) * P[0])
+                             : axis == 1 ? (double)((p / np[0]) * P[1]) : 0.0;
+            for (int k = 0; k < c[p]; ++k) dst[o++] = org + (double)tmp[off_h[p] + k];
+        }
+    };
+    for (int a = 0; a < 2; ++a) if (xo[a]) fetch(px[a], xo[a], a);
+    if (xo[2]) std::fill(xo[2], xo[2] + live, 0.0);
+    for (int a = 0; a < 3; ++a) if (uo[a]) fetch(pu[a], uo[a], 3);
+    if (wo) fetch(pw, wo, 3);
+    if (ido) {
+        itmp.resize(tot);
+        hipcheck(hipMemcpyAsync(itmp.data(), pid, sizeof(int64_t) * tot, hipMemcpyDeviceToHost, stream), "ids");
+        hipcheck(hipStreamSynchronize(stream), "sync");
+        int64_t o = 0;
+        for (int p = 0; p < npatch; ++p)
+            for (int k = 0; k < c[p]; ++k) ido[o++] = itmp[off_h[p] + k];
+    }
+}
+
+template <typename T>
+void SimImpl<T>::history(int64_t first, int64_t cnt, double *U, double *K, int64_t *pushed)
+{
+    SimState s = read_state();
+    if (first < 0 || cnt < 0 || first + cnt > s.step || s.step - first > kHistLen)
+        throw Error(PIC_EINVAL, "history range not available");
+    std::vector<double> h(kHistLen * 4);
+    hipcheck(hipMemcpyAsync(h.data(), hist, sizeof(double) * h.size(), hipMemcpyDeviceToHost, stream), "hist");
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    for (int64_t k = 0; k < cnt; ++k) {
+        const double *r = &h[((first + k) % kHistLen) * 4];
+        if (U) U[k] = r[0];
+        if (K) K[k] = r[1];
+        if (pushed) pushed[k] = (int64_t)r[2];
+    }
+}
+
+// Grow patch capacities (only ever grows) so that every patch holds both its
+// current particles and the count the pending re-binning needs, and copy the
+// particles into the new layout.
+template <typename T>
+void SimImpl<T>::grow_capacity()
+{
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    std::vector<int32_t> cur = read_counts(), nxt(npatch);
+    hipcheck(hipMemcpyAsync(nxt.data(), newcount_d, sizeof(int32_t) * npatch, hipMemcpyDeviceToHost, stream), "newcount");
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    std::vector<int32_t> need(npatch);
+    for (int p = 0; p < npatch; ++p) need[p] = std::max(cur[p], nxt[p]);
+    SimDev<T> oldv = v;
+    SimDev<T> *oldv_d = (SimDev<T> *)alloc.get(sizeof(SimDev<T>));
+    hipcheck(hipMemcpyAsync(oldv_d, &oldv, sizeof(oldv), hipMemcpyHostToDevice, stream), "old view");
+    std::vector<void *> old;
+    try {
+        old = layout_particles(need);
+    } catch (...) {
+        alloc.put(oldv_d);
+        throw;
+    }
+    launch_relayout<T>(oldv_d, view_d, npatch, stream);
+    hipcheck(hipGetLastError(), "relayout launch");
+    hipcheck(hipStreamSynchronize(stream), "relayout");
+    for (void *p : old) alloc.put(p);
+    alloc.put(oldv_d);
+    ++relayouts;
+}
+
+// Re-run the re-binning of the step whose scatter was skipped by the
+// capacity check, after growing capacities.
+template <typename T>
+void SimImpl<T>::recover_pending(bool finalize)
+{
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        grow_capacity();
+        SimState s = read_state();
+        s.flags &= ~kFlagPending;
+        s.active = 1;
+        hipcheck(hipMemcpyAsync(&st->flags, &s.flags, sizeof(uint32_t) * 2, hipMemcpyHostToDevice, stream), "flags");
+        launch_rebin<T>(view_d, 1, prefix_d, npatch, std::min(npatch, 4 * cu_count()), finalize, stream);
+        hipcheck(hipGetLastError(), "rebin launch");
+        s = read_state();
+        if (!(s.flags & kFlagPending)) {
+            if (!finalize) {
+                uint32_t zero = 0;
+                hipcheck(hipMemcpyAsync(&st->active, &zero, sizeof(zero), hipMemcpyHostToDevice, stream), "active");
+                hipcheck(hipStreamSynchronize(stream), "sync");
+            }
+            return;
+        }
+    }
+    throw Error(PIC_EOVERFLOW, "patch capacity could not be grown enough");
+}
+
+template <typename T>
+void SimImpl<T>::rebin_codes(const uint8_t *codes_h, size_t cnt)
+{
+    check_free();
+    auto c = read_counts();
+    const int64_t live = std::accumulate(c.begin(), c.end(), int64_t(0));
+    if ((int64_t)cnt != live) throw Error(PIC_EINVAL, "code count must equal the live particle count");
+    for (size_t k = 0; k < cnt; ++k)
+        if (codes_h[k] >= kNDir2 && codes_h[k] != kRemoved) throw Error(PIC_EINVAL, "bad direction code");
+    std::vector<int64_t> poff(npatch + 1, 0);
+    for (int p = 0; p < npatch; ++p) poff[p + 1] = poff[p] + c[p];
+    uint8_t *pk = (uint8_t *)alloc.get(std::max<size_t>(cnt, 1));
+    int64_t *po = (int64_t *)alloc.get(sizeof(int64_t) * (npatch + 1));
+    hipcheck(hipMemcpyAsync(pk, codes_h, cnt, hipMemcpyHostToDevice, stream), "codes");
+    hipcheck(hipMemcpyAsync(po, poff.data(), sizeof(int64_t) * (npatch + 1), hipMemcpyHostToDevice, stream), "codes off");
+    launch_scatter_codes(pk, po, off_d, counts_d, code, npatch, stream);
+    hipcheck(hipGetLastError(), "codes launch");
+    SimState s = read_state();
+    s.active = 1;
+    hipcheck(hipMemcpyAsync(&st->active, &s.active, sizeof(uint32_t), hipMemcpyHostToDevice, stream), "active");
+    launch_rebin<T>(view_d, 1, prefix_d, npatch, std::min(npatch, 4 * cu_count()), false, stream);
+    hipcheck(hipGetLastError(), "rebin launch");
+    s = read_state();
+    alloc.put(pk);
+    alloc.put(po);
+    if (s.flags & kFlagPending) {
+        recover_pending(false);
+        return;
+    }
+    uint32_t zero = 0;
+    hipcheck(hipMemcpyAsync(&st->active, &zero, sizeof(zero), hipMemcpyHostToDevice, stream), "active");
+    hipcheck(hipStreamSynchronize(stream), "sync");
+}
+
+template <typename T>
+int SimImpl<T>::max_items(int chunk)
+{
+    if (max_items_cache >= 0 && chunk == chunk_cache) return max_items_cache;
+    int64_t m = 0;
+    for (int p = 0; p < npatch; ++p) m += (cap_h[p] + chunk - 1) / chunk;
+    max_items_cache = (int)std::min<int64_t>(m, INT32_MAX / 2);
+    chunk_cache = chunk;
+    return max_items_cache;
+}
+
+template <typename T>
+void SimImpl<T>::check_free()
+{
+    if (batch) throw Error(PIC_ESTATE, "simulation is a member of a batch");
+}
+
+// ---------------------------------------------------------------------------
+// timing
+
+void Timing::record(hipStream_t s, int k, bool begin)
+{
+    if (!enabled) return;
+    if (begin) {
+        Ev e;
+        e.kind = k;
+        hipcheck(hipEventCreate(&e.a), "event");
+        hipcheck(hipEventCreate(&e.b), "event");
+        hipcheck(hipEventRecord(e.a, s), "event record");
+        events.push_back(e);
+    } else {
+        hipcheck(hipEventRecord(events.back().b, s), "event record");
+    }
+}
+
+void Timing::collect()
+{
+    for (auto &e : events) {
+        float ms = 0.f;
+        hipcheck(hipEventSynchronize(e.b), "event sync");
+        hipcheck(hipEventElapsedTime(&ms, e.a, e.b), "event time");
+        total_ms[e.kind] += ms;
+        launches[e.kind] += 1;
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    events.clear();
+}
+
+const char *const Timing::names[kKinds] = {"queue", "particles", "maxwell", "rebin"};
+
+// ---------------------------------------------------------------------------
+// BatchImpl
+
+template <typename T>
+BatchImpl<T>::BatchImpl(hipStream_t s) { stream = s; precision = sizeof(T) == 4 ? 32 : 64; }
+
+template <typename T>
+BatchImpl<T>::~BatchImpl()
+{
+    if (!solo_mode)
+        for (auto *m : members) m->batch = nullptr;
+    free_tables();
+}
+
+template <typename T>
+void BatchImpl<T>::free_tables()
+{
+    for (void *p : table_bufs) {
+        if (p) (void)hipFree(p);
+    }
+    table_bufs.clear();
+    sims_d = nullptr;
+    patch_prefix_d = tile_prefix_d = nullptr;
+    items_d = nullptr;
+    nitems_d = head_d = nullptr;
+    table_cap_items = 0;
+}
+
+template <typename T>
+void BatchImpl<T>::add(SimImpl<T> *s, int64_t nsteps)
+{
+    if (s->batch) throw Error(PIC_ESTATE, "simulation already in a batch");
+    if (s->stream != stream) throw Error(PIC_EINVAL, "simulation and batch must share a stream");
+    SimState st = s->read_state();
+    st.steps_left = nsteps;
+    hipcheck(hipMemcpyAsync(&s->st->steps_left, &st.steps_left, sizeof(int64_t), hipMemcpyHostToDevice, stream), "budget");
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    s->batch = this;
+    members.push_back(s);
+    dirty = true;
+}
+
+template <typename T>
+void BatchImpl<T>::remove(SimImpl<T> *s)
+{
+    auto it = std::find(members.begin(), members.end(), s);
+    if (it == members.end()) throw Error(PIC_EINVAL, "not a member");
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    int64_t zero = 0;
+    hipcheck(hipMemcpyAsync(&s->st->steps_left, &zero, sizeof(zero), hipMemcpyHostToDevice, stream), "budget");
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    s->batch = nullptr;
+    members.erase(it);
+    dirty = true;
+}
+
+template <typename T>
+void BatchImpl<T>::build_tables()
+{
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    const int ns = (int)members.size();
+    std::vector<int> pp(ns + 1, 0), tp(ns + 1, 0);
+    int tx, ty;
+    maxwell_tile<T>(tx, ty);
+    maxP0 = maxP1 = 1;
+    int64_t items = 0;
+    int64_t particles = 0;
+    int min_block = 512;
+    for (int i = 0; i < ns; ++i) {
+        SimImpl<T> *m = members[i];
+        pp[i + 1] = pp[i] + m->npatch;
+        const int ntx = (m->fn[0] + tx - 1) / tx, nty = (m->fn[1] + ty - 1) / ty;
+        tp[i + 1] = tp[i] + ntx * nty;
+        maxP0 = std::max(maxP0, m->P[0]);
+        maxP1 = std::max(maxP1, m->P[1]);
+        particles += m->num_particles();
+        if (m->desc.block) min_block = std::min(min_block, (int)m->desc.block);
+    }
+    total_patches = pp[ns];
+    total_tiles = tp[ns];
+    // chunk: enough items to fill every CU several times over
+    chunk = 0;
+    for (auto *m : members) chunk = std::max(chunk, (int)m->desc.chunk);
+    if (chunk == 0) {
+        const int64_t target = (int64_t)cu_count() * 8;
+        int64_t c = particles / std::max<int64_t>(target, 1);
+        c = std::max<int64_t>(c, 256);
+        c = std::min<int64_t>(c, 4096);
+        chunk = (int)c;
+    }
+    for (auto *m : members) items += m->max_items(chunk);
+    items = std::max<int64_t>(items, 1);
+    block = (sizeof(T) == 8 && maxP0 * maxP1 >= 32 * 32) ? 512 : 256;
+    if (min_block != 512 || std::any_of(members.begin(), members.end(), [](SimImpl<T> *m) { return m->desc.block == 512; }))
+        for (auto *m : members) if (m->desc.block) block = m->desc.block;
+    const int occ = std::max(1, particles_occupancy<T>(block, maxP0, maxP1));
+    grid_particles = cu_count() * occ;
+    grid_maxwell = std::max(1, std::min(total_tiles, cu_count() * 8));
+    grid_rebin = std::max(1, std::min(total_patches, cu_count() * 8));
+
+    // device tables (hipMalloc directly: small, batch-owned)
+    free_tables();
+    auto get = [&](size_t bytes) {
+        void *p = nullptr;
+        hipcheck(hipMalloc(&p, std::max<size_t>(bytes, 256)), "batch tables");
+        table_bufs.push_back(p);
+        return p;
+    };
+    sims_d = (SimDev<T> *)get(sizeof(SimDev<T>) * std::max(ns, 1));
+    patch_prefix_d = (int *)get(sizeof(int) * (ns + 1));
+    tile_prefix_d = (int *)get(sizeof(int) * (ns + 1));
+    items_d = (Item *)get(sizeof(Item) * items);
+    nitems_d = (int *)get(sizeof(int) * 2);
+    head_d = nitems_d + 1;
+    table_cap_items = (int)items;
+    std::vector<SimDev<T>> views(ns);
+    for (int i = 0; i < ns; ++i) {
+        views[i] = members[i]->v;
+        seen_version.resize(ns);
+        seen_version[i] = members[i]->layout_version;
+    }
+    if (ns) hipcheck(hipMemcpyAsync(sims_d, views.data(), sizeof(SimDev<T>) * ns, hipMemcpyHostToDevice, stream), "views");
+    hipcheck(hipMemcpyAsync(patch_prefix_d, pp.data(), sizeof(int) * (ns + 1), hipMemcpyHostToDevice, stream), "prefix");
+    hipcheck(hipMemcpyAsync(tile_prefix_d, tp.data(), sizeof(int) * (ns + 1), hipMemcpyHostToDevice, stream), "prefix");
+    hipcheck(hipMemsetAsync(nitems_d, 0, sizeof(int) * 2, stream), "nitems");
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    dirty = false;
+}
+
+template <typename T>
+void BatchImpl<T>::refresh_member_views()
+{
+    bool changed = false;
+    for (size_t i = 0; i < members.size(); ++i) {
+        if (seen_version[i] != members[i]->layout_version) {
+            hipcheck(hipMemcpyAsync(sims_d + i, &members[i]->v, sizeof(SimDev<T>), hipMemcpyHostToDevice, stream), "view");
+            seen_version[i] = members[i]->layout_version;
+            changed = true;
+        }
+    }
+    if (changed) {
+        // capacities grew: the item buffer may need to be larger
+        int64_t items = 0;
+        for (auto *m : members) items += m->max_items(chunk);
+        if (items > table_cap_items) dirty = true;
+    }
+}
+
+template <typename T>
+void BatchImpl<T>::launch_one_step()
+{
+    QueueArgs qa;
+    qa.nsims = (int)members.size();
+    qa.patch_prefix = patch_prefix_d;
+    qa.items = items_d;
+    qa.nitems = nitems_d;
+    qa.head = head_d;
+    qa.max_items = table_cap_items;
+    qa.chunk = chunk;
+    Timing &tm = timing();
+    tm.record(stream, 0, true);
+    launch_queue<T>(sims_d, qa, stream);
+    tm.record(stream, 0, false);
+    tm.record(stream, 1, true);
+    launch_particles<T>(sims_d, items_d, nitems_d, head_d, grid_particles, block, maxP0, maxP1, stream);
+    tm.record(stream, 1, false);
+    tm.record(stream, 2, true);
+    launch_maxwell<T>(sims_d, qa.nsims, tile_prefix_d, total_tiles, grid_maxwell, stream);
+    tm.record(stream, 2, false);
+    tm.record(stream, 3, true);
+    launch_rebin<T>(sims_d, qa.nsims, patch_prefix_d, total_patches, grid_rebin, true, stream);
+    tm.record(stream, 3, false);
+    hipcheck(hipGetLastError(), "step launch");
+}
+
+template <typename T>
+Timing &BatchImpl<T>::timing()
+{
+    // a batch of one reports into its simulation; larger batches into the first member
+    return members.empty() ? own_timing : members[0]->timing;
+}
+
+// Run up to max_steps step passes; each member advances while it has budget.
+// Returns the number of members that used up their budget in this call.
+template <typename T>
+int BatchImpl<T>::run(int64_t max_steps, bool until_done)
+{
+    if (members.empty()) return 0;
+    if (dirty) build_tables();
+    std::vector<int64_t> before(members.size());
+    for (size_t i = 0; i < members.size(); ++i) before[i] = members[i]->read_state().steps_left;
+    int64_t launched = 0;
+    const int64_t K = 16;
+    int finished = 0;
+    for (;;) {
+        int64_t todo = until_done ? K : std::min<int64_t>(K, max_steps - launched);
+        if (todo <= 0) break;
+        for (int64_t k = 0; k < todo; ++k) launch_one_step();
+        launched += todo;
+        // poll member states
+        bool any_left = false;
+        bool recovered = false;
+        for (size_t i = 0; i < members.size(); ++i) {
+            SimImpl<T> *m = members[i];
+            SimState s = m->read_state();
+            if (s.flags & kFlagPending) {
+                m->recover_pending(true);
+                recovered = true;
+                s = m->read_state();
+            }
+            if (s.steps_left > 0 && !(s.flags & kFlagErrMask)) any_left = true;
+        }
+        if (recovered) refresh_member_views();
+        if (dirty) build_tables();
+        if (!any_left) break;
+        if (!until_done && launched >= max_steps) break;
+    }
+    for (size_t i = 0; i < members.size(); ++i) {
+        SimState s = members[i]->read_state();
+        if (before[i] > 0 && (s.steps_left == 0 || (s.flags & kFlagErrMask))) ++finished;
+    }
+    return finished;
+}
+
+template <typename T>
+void BatchImpl<T>::finished(std::vector<SimBase *> &out)
+{
+    for (auto *m : members) {
+        SimState s = m->read_state();
+        if (s.steps_left == 0 || (s.flags & kFlagErrMask)) out.push_back(m);
+    }
+}
+
+template struct SimImpl<float>;
+template struct SimImpl<double>;
+template struct BatchImpl<float>;
+template struct BatchImpl<double>;
+
+}  // namespace pic

@@ -1,0 +1,174 @@
+// Host runtime declarations of the patch-PIC library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/pic.h"
+#include "kernels.h"
+#include "pic_dev.h"
+
+namespace pic {
+
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+void set_error(const std::string &m);
+extern thread_local std::string g_last_error;
+void hipcheck(hipError_t e, const char *what);
+int validate_desc(const PicSimDesc &d, std::string &why);
+
+struct Allocator {
+    PicAllocator hook{nullptr, nullptr, nullptr};
+    size_t live_bytes = 0;
+    std::map<void *, size_t> sizes;
+    void *get(size_t bytes);
+    void put(void *p);
+};
+
+struct Timing {
+    static constexpr int kKinds = 4;
+    static const char *const names[kKinds];
+    struct Ev {
+        int kind;
+        hipEvent_t a, b;
+    };
+    bool enabled = false;
+    std::vector<Ev> events;
+    double total_ms[kKinds] = {0, 0, 0, 0};
+    int64_t launches[kKinds] = {0, 0, 0, 0};
+    void record(hipStream_t s, int kind, bool begin);
+    void collect();
+};
+
+struct SimBase {
+    virtual ~SimBase() {}
+    PicSimDesc desc{};
+    int precision = 64;
+    hipStream_t stream = nullptr;
+    Timing timing;
+    int relayouts = 0;
+    void *handle = nullptr;  // the C handle wrapping this object
+
+    virtual void set_particles(int64_t n, const double *const xs[3], const double *const us[3],
+                               const double *w) = 0;
+    virtual void set_laser(int64_t nsteps, const double *ey, const double *ez) = 0;
+    virtual void set_field(int comp, const double *h) = 0;
+    virtual void get_field(int comp, double *h) = 0;
+    virtual SimState read_state() = 0;
+    virtual std::vector<int32_t> read_counts() = 0;
+    virtual int64_t num_particles() = 0;
+    virtual void get_particles(double *xo[3], double *uo[3], double *wo, int64_t *ido, size_t n) = 0;
+    virtual void history(int64_t first, int64_t n, double *U, double *K, int64_t *pushed) = 0;
+    virtual void rebin_codes(const uint8_t *codes, size_t n) = 0;
+    virtual void step(int64_t nsteps) = 0;
+    virtual bool in_batch() const = 0;
+    virtual size_t device_bytes() const = 0;
+};
+
+template <typename T>
+struct BatchImpl;
+
+template <typename T>
+struct SimImpl : SimBase {
+    Allocator alloc;
+    int n[3], P[3], np[3], fn[3], periodic[3];
+    int npatch = 0;
+    int64_t fsize = 0;
+    T *F[6] = {};
+    T *J[2][3] = {};
+    SimState *st = nullptr;
+    double *hist = nullptr;
+    int32_t *counts_d = nullptr, *newcount_d = nullptr, *kcnt_d = nullptr, *nleave_d = nullptr;
+    int32_t *narrive_d = nullptr, *nhole_d = nullptr;
+    int *prefix_d = nullptr;
+    T *laser_ey = nullptr, *laser_ez = nullptr;
+    int64_t laser_steps = 0;
+    // particle layout
+    std::vector<void *> part_bufs;
+    T *px[2] = {}, *sx[2] = {}, *pu[3] = {}, *su[3] = {}, *pw = nullptr, *sw = nullptr;
+    int64_t *pid = nullptr, *sid = nullptr;
+    uint8_t *code = nullptr;
+    int32_t *holes = nullptr, *cap_d = nullptr;
+    int64_t *off_d = nullptr;
+    std::vector<int32_t> cap_h;
+    std::vector<int64_t> off_h;
+    int64_t total_cap = 0;
+    int max_items_cache = -1, chunk_cache = -1;
+    int64_t layout_version = 0;
+    SimDev<T> v;
+    SimDev<T> *view_d = nullptr;
+    BatchImpl<T> *batch = nullptr;  // user batch this simulation belongs to
+    BatchImpl<T> *solo = nullptr;   // private batch used by step()
+
+    SimImpl(const PicSimDesc &d, const PicAllocator *a, hipStream_t s);
+    ~SimImpl() override;
+    void release();
+    void free_particles();
+    std::vector<void *> layout_particles(const std::vector<int32_t> &need);
+    void refresh_view();
+    void grow_capacity();
+    void recover_pending(bool finalize);
+    int max_items(int chunk);
+    void check_free();
+
+    void set_particles(int64_t n, const double *const xs[3], const double *const us[3],
+                       const double *w) override;
+    void set_laser(int64_t nsteps, const double *ey, const double *ez) override;
+    void set_field(int comp, const double *h) override;
+    void get_field(int comp, double *h) override;
+    SimState read_state() override;
+    std::vector<int32_t> read_counts() override;
+    int64_t num_particles() override;
+    void get_particles(double *xo[3], double *uo[3], double *wo, int64_t *ido, size_t n) override;
+    void history(int64_t first, int64_t n, double *U, double *K, int64_t *pushed) override;
+    void rebin_codes(const uint8_t *codes, size_t n) override;
+    void step(int64_t nsteps) override;
+    bool in_batch() const override { return batch != nullptr; }
+    size_t device_bytes() const override { return alloc.live_bytes; }
+};
+
+struct BatchBase {
+    virtual ~BatchBase() {}
+    int precision = 64;
+    hipStream_t stream = nullptr;
+};
+
+template <typename T>
+struct BatchImpl : BatchBase {
+    std::vector<SimImpl<T> *> members;
+    std::vector<int64_t> seen_version;
+    bool dirty = true;
+    bool solo_mode = false;
+    std::vector<void *> table_bufs;
+    SimDev<T> *sims_d = nullptr;
+    int *patch_prefix_d = nullptr, *tile_prefix_d = nullptr;
+    Item *items_d = nullptr;
+    int *nitems_d = nullptr, *head_d = nullptr;
+    int table_cap_items = 0;
+    int total_patches = 0, total_tiles = 0;
+    int maxP0 = 1, maxP1 = 1;
+    int chunk = 256, block = 256;
+    int grid_particles = 1, grid_maxwell = 1, grid_rebin = 1;
+    Timing own_timing;
+
+    explicit BatchImpl(hipStream_t s);
+    ~BatchImpl() override;
+    void free_tables();
+    void add(SimImpl<T> *s, int64_t nsteps);
+    void remove(SimImpl<T> *s);
+    void build_tables();
+    void refresh_member_views();
+    void launch_one_step();
+    Timing &timing();
+    int run(int64_t max_steps, bool until_done);
+    void finished(std::vector<SimBase *> &out);
+};
+
+}  // namespace pic

@@ -1,0 +1,242 @@
+"""Thin Python binding over the C ABI (include/pic.h): argument marshalling only.
+
+Every step of the PIC path runs in the HIP kernels of libpic.so.  PyTorch is
+used for plumbing: device memory comes from torch's caching allocator through
+the library's allocator hook, and work is ordered on torch's current HIP
+stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _capi
+from ._capi import check
+
+_D = C.POINTER(C.c_double)
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(_D)
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+class _TorchAllocator:
+    """Allocator hook that routes device allocations to torch's caching allocator."""
+
+    def __init__(self, stream_handle: int):
+        import torch
+        self._torch = torch
+        self._stream = stream_handle
+        self._dev = torch.cuda.current_device()
+
+        def _alloc(nbytes, ctx):
+            try:
+                return int(torch.cuda.caching_allocator_alloc(int(nbytes), self._dev, self._stream))
+            except Exception:  # out of memory: report NULL to the library
+                return None
+
+        def _free(ptr, ctx):
+            torch.cuda.caching_allocator_delete(int(ptr))
+
+        self._cb_alloc = _capi.ALLOC_FN(_alloc)
+        self._cb_free = _capi.FREE_FN(_free)
+        self.struct = _capi.Allocator(self._cb_alloc, self._cb_free, None)
+
+
+def current_stream_handle() -> int:
+    import torch
+    return int(torch.cuda.current_stream().cuda_stream)
+
+
+def make_desc(grid: dict, precision: int, chunk: int = 0, block: int = 0,
+              capacity_factor: float = 0.0, min_capacity: int = 0) -> _capi.SimDesc:
+    nd = int(grid["ndim"])
+    n = list(grid["n"]) + [1] * (3 - len(grid["n"]))
+    d = list(grid["d"]) + [1.0] * (3 - len(grid["d"]))
+    patch = list(grid["patch"]) + [1] * (3 - len(grid["patch"]))
+    per = list(grid.get("periodic", [1, 1, 1])) + [1] * 3
+    return _capi.SimDesc(nd, int(precision), (C.c_int32 * 3)(*n), (C.c_double * 3)(*d),
+                         float(grid["dt"]), (C.c_int32 * 3)(*patch),
+                         (C.c_int32 * 3)(*[int(p) for p in per[:3]]),
+                         float(grid.get("q", -1.0)), float(grid.get("m", 1.0)),
+                         float(capacity_factor), int(min_capacity), int(chunk), int(block))
+
+
+class Sim:
+    """One simulation on the GPU (a handle of the C library)."""
+
+    def __init__(self, grid: dict, precision: int = 64, stream: int | None = None,
+                 torch_alloc: bool = True, **tune):
+        lib = _capi.load()
+        self.grid = dict(grid)
+        self.precision = int(precision)
+        self.stream = current_stream_handle() if stream is None else int(stream)
+        self._alloc = _TorchAllocator(self.stream) if torch_alloc else None
+        desc = make_desc(grid, precision, **tune)
+        h = C.c_void_p()
+        check(lib.pic_sim_create(C.byref(desc), C.byref(self._alloc.struct) if self._alloc else None,
+                                 C.c_void_p(self.stream), C.byref(h)))
+        self._h = h
+        n = list(grid["n"])
+        per = list(grid.get("periodic", [1, 1]))
+        self.fn = [n[a] if per[a] else n[a] + 1 for a in range(2)]
+        self.npatch = (n[0] // grid["patch"][0]) * (n[1] // grid["patch"][1])
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _capi.load().pic_sim_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- state in ----------------------------------------------------------
+    def set_particles(self, x, u, w):
+        x = [_f64(a) for a in x]
+        u = [_f64(a) for a in u]
+        w = _f64(w)
+        n = w.size
+        check(_capi.load().pic_particles_set(self._h, n, _dp(x[0]), _dp(x[1]), None,
+                                             _dp(u[0]), _dp(u[1]), _dp(u[2]), _dp(w)))
+
+    def set_laser(self, ey=None, ez=None):
+        ey, ez = _f64(ey), _f64(ez)
+        nsteps = (ey if ey is not None else ez).shape[0]
+        check(_capi.load().pic_laser_set(self._h, nsteps, _dp(ey), _dp(ez)))
+
+    def set_field(self, comp, values):
+        c = _capi.COMPONENTS.index(comp) if isinstance(comp, str) else int(comp)
+        v = _f64(np.asarray(values).reshape(-1))
+        check(_capi.load().pic_fields_set(self._h, c, _dp(v), v.size))
+
+    @classmethod
+    def from_workload(cls, wl: dict, precision: int = 64, **kw) -> "Sim":
+        s = cls(wl["grid"], precision, **kw)
+        s.set_particles(wl["x"], wl["u"], wl["w"])
+        if wl.get("laser"):
+            s.set_laser(wl["laser"].get("ey"), wl["laser"].get("ez"))
+        return s
+
+    # -- stepping ------------------------------------------------------------
+    def step(self, nsteps: int = 1):
+        check(_capi.load().pic_step(self._h, int(nsteps)))
+
+    def sync(self):
+        check(_capi.load().pic_sync(self._h))
+
+    # -- state out -------------------------------------------------------------
+    def field(self, comp) -> np.ndarray:
+        c = _capi.COMPONENTS.index(comp) if isinstance(comp, str) else int(comp)
+        out = np.zeros(self.fn[0] * self.fn[1])
+        check(_capi.load().pic_fields_get(self._h, c, _dp(out), out.size))
+        return out.reshape(self.fn[1], self.fn[0])
+
+    def num_particles(self) -> int:
+        n = C.c_int64()
+        check(_capi.load().pic_num_particles(self._h, C.byref(n)))
+        return n.value
+
+    def particles(self):
+        """(x[2], u[3], w, id) in canonical (patch, slot) order, positions global."""
+        n = self.num_particles()
+        x = [np.zeros(n) for _ in range(2)]
+        u = [np.zeros(n) for _ in range(3)]
+        w = np.zeros(n)
+        ids = np.zeros(n, dtype=np.int64)
+        check(_capi.load().pic_particles_get(
+            self._h, _dp(x[0]), _dp(x[1]), None, _dp(u[0]), _dp(u[1]), _dp(u[2]), _dp(w),
+            ids.ctypes.data_as(C.POINTER(C.c_int64)), n))
+        return x, u, w, ids
+
+    def counts(self) -> np.ndarray:
+        c = np.zeros(self.npatch, dtype=np.int32)
+        check(_capi.load().pic_patch_counts_get(self._h, c.ctypes.data_as(C.POINTER(C.c_int32)),
+                                                c.size))
+        return c
+
+    def diag(self) -> dict:
+        d = _capi.Diag()
+        check(_capi.load().pic_diag_get(self._h, C.byref(d)))
+        return {k: getattr(d, k) for k, _ in _capi.Diag._fields_}
+
+    def history(self, first: int, n: int):
+        U = np.zeros(n)
+        K = np.zeros(n)
+        P = np.zeros(n, dtype=np.int64)
+        check(_capi.load().pic_history_get(self._h, int(first), int(n), _dp(U), _dp(K),
+                                           P.ctypes.data_as(C.POINTER(C.c_int64))))
+        return U, K, P
+
+    def rebin_codes(self, codes):
+        c = np.ascontiguousarray(codes, dtype=np.uint8)
+        check(_capi.load().pic_rebin_codes(self._h, c.ctypes.data_as(C.POINTER(C.c_uint8)), c.size))
+
+    def timing_enable(self, on: bool = True):
+        check(_capi.load().pic_timing_enable(self._h, 1 if on else 0))
+
+    def timing(self) -> dict:
+        t = _capi.Timing()
+        check(_capi.load().pic_timing_get(self._h, C.byref(t)))
+        return {t.name[k].decode(): (t.total_ms[k], t.launches[k]) for k in range(t.nkernels)}
+
+
+class Batch:
+    """Simulations of one precision stepped together (one queue, one launch per kernel)."""
+
+    def __init__(self, precision: int = 32, stream: int | None = None):
+        lib = _capi.load()
+        self.stream = current_stream_handle() if stream is None else int(stream)
+        h = C.c_void_p()
+        check(lib.pic_batch_create(2, int(precision), C.c_void_p(self.stream), C.byref(h)))
+        self._h = h
+        self.members = {}
+
+    def add(self, sim: Sim, nsteps: int):
+        check(_capi.load().pic_batch_add(self._h, sim.handle, int(nsteps)))
+        self.members[sim.handle.value] = sim
+
+    def remove(self, sim: Sim):
+        check(_capi.load().pic_batch_remove(self._h, sim.handle))
+        self.members.pop(sim.handle.value, None)
+
+    def step(self, max_steps: int) -> int:
+        done = C.c_int32()
+        check(_capi.load().pic_batch_step(self._h, int(max_steps), C.byref(done)))
+        return done.value
+
+    def finished(self):
+        n = C.c_int32()
+        cap = max(1, len(self.members))
+        arr = (C.c_void_p * cap)()
+        check(_capi.load().pic_batch_finished(self._h, arr, cap, C.byref(n)))
+        return [self.members[arr[i]] for i in range(min(n.value, cap))]
+
+    def __len__(self):
+        n = C.c_int32()
+        check(_capi.load().pic_batch_size(self._h, C.byref(n)))
+        return n.value
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _capi.load().pic_batch_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,59 @@
+"""Shared test helpers: running the oracle and the HIP path on the same seeded
+inputs and comparing what they produce."""
+from __future__ import annotations
+
+import numpy as np
+
+E_COMPS = ("Ex", "Ey", "Ez")
+B_COMPS = ("Bx", "By", "Bz")
+
+
+def rel_l2(a_list, b_list):
+    num = sum(float(np.sum((np.asarray(a) - np.asarray(b)) ** 2)) for a, b in zip(a_list, b_list))
+    den = sum(float(np.sum(np.asarray(b) ** 2)) for b in b_list)
+    return np.sqrt(num / den) if den > 0 else np.sqrt(num)
+
+
+def oracle_run(wl, nsteps, laser=True):
+    import oracle
+    s = oracle.Sim(wl["grid"])
+    s.set_particles(wl["x"], wl["u"], wl["w"])
+    if laser and wl.get("laser"):
+        s.set_laser(ey=wl["laser"].get("ey"), ez=wl["laser"].get("ez"))
+    s.step(nsteps)
+    return s
+
+
+def gpu_sim(wl, precision, **kw):
+    from paper_1511_03878_amd.sim import Sim
+    return Sim.from_workload(wl, precision=precision, **kw)
+
+
+def fields_of(sim, comps, oracle_layout=False):
+    out = []
+    for c in comps:
+        f = sim.field(c)
+        out.append(f[0] if oracle_layout else f)
+    return out
+
+
+def compare_fields(gpu, orc):
+    """(rel-L2 of the E group, rel-L2 of the B group) between a GPU sim and an oracle sim."""
+    e = rel_l2(fields_of(gpu, E_COMPS), fields_of(orc, E_COMPS, True))
+    b = rel_l2(fields_of(gpu, B_COMPS), fields_of(orc, B_COMPS, True))
+    return e, b
+
+
+def neighbour_patch(p, code, np_, periodic):
+    """Destination patch of direction code (dx+1) + 3 (dy+1) from patch p."""
+    px, py = p % np_[0], p // np_[0]
+    qx, qy = px + code % 3 - 1, py + code // 3 - 1
+    if not (0 <= qx < np_[0]):
+        if not periodic[0]:
+            return -1
+        qx %= np_[0]
+    if not (0 <= qy < np_[1]):
+        if not periodic[1]:
+            return -1
+        qy %= np_[1]
+    return qx + np_[0] * qy

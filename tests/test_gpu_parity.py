@@ -1,0 +1,152 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on MI355X.
+
+Tolerances: FP64 fields within 1e-11 relative L2 after 10 steps; FP32 within
+1e-5 after one step; patch occupancy and the slot of every particle (its id)
+bit-exact.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1511_03878_amd import workloads as W
+from tests.helpers import compare_fields, gpu_sim, neighbour_patch, oracle_run, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _announce(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return W.uniform_2d()
+
+
+def test_uniform_fp64_ten_steps_match_oracle(c1):
+    _announce("uniform 128x128 16ppc fp64, 10 steps")
+    g = gpu_sim(c1, 64)
+    g.step(10)
+    o = oracle_run(c1, 10)
+    e, b = compare_fields(g, o)
+    assert e < 1e-11 and b < 1e-11, (e, b)
+    assert np.array_equal(g.counts(), o.counts())
+    gx, gu, gw, gid = g.particles()
+    ox, ou, ow, oid = o.particles()
+    assert np.array_equal(gid, oid)
+    for a in range(2):
+        assert np.abs(gx[a] - ox[a]).max() < 1e-11
+    for a in range(3):
+        assert np.abs(gu[a] - ou[a]).max() < 1e-12
+    d = g.diag()
+    assert d["step"] == 10 and d["particles"] == c1["w"].size
+
+
+def test_uniform_fp32_one_step_matches_oracle(c1):
+    _announce("uniform 128x128 16ppc fp32, 1 step")
+    wl = W.to_float32_state(c1)
+    g = gpu_sim(wl, 32)
+    g.step(1)
+    o = oracle_run(wl, 1)
+    e, b = compare_fields(g, o)
+    assert e < 1e-5 and b < 1e-5, (e, b)
+    assert np.array_equal(g.counts(), o.counts())
+    jg = [g.field(c) for c in ("Jx", "Jy", "Jz")]
+    jo = [o.field(c)[0] for c in ("Jx", "Jy", "Jz")]
+    assert rel_l2(jg, jo) < 1e-5
+
+
+def test_maxwell_only_matches_oracle_fp64():
+    _announce("vacuum fields 96x64 fp64, 20 steps")
+    grid = dict(ndim=2, n=[96, 64], d=[0.1, 0.13], dt=W.cfl_dt((0.1, 0.13)), patch=[16, 16],
+                periodic=[1, 1], q=-1.0, m=1.0)
+    from paper_1511_03878_amd.sim import Sim
+    g = Sim(grid, 64)
+    g.set_particles([np.zeros(0), np.zeros(0)], [np.zeros(0)] * 3, np.zeros(0))
+    o = oracle.Sim(grid)
+    rng = np.random.default_rng(11)
+    for c in ("Ex", "Ey", "Ez", "Bx", "By", "Bz"):
+        f = rng.standard_normal((64, 96))
+        g.set_field(c, f)
+        o.set_field(c, f)
+    g.step(20)
+    o.step(20)
+    e, b = compare_fields(g, o)
+    assert e < 1e-12 and b < 1e-12, (e, b)
+
+
+def _rebin_case(grid, wl_kw, seed):
+    wl = W.uniform_2d(**wl_kw)
+    wl["grid"].update(grid)
+    from paper_1511_03878_amd.sim import Sim
+    g = Sim(wl["grid"], 64)
+    g.set_particles(wl["x"], wl["u"], wl["w"])
+    counts = g.counts()
+    _, _, _, ids = g.particles()
+    rng = np.random.default_rng(seed)
+    N = ids.size
+    codes = np.full(N, 4, dtype=np.uint8)
+    r = rng.random(N)
+    moving = r < 0.3
+    codes[moving] = rng.integers(0, 9, moving.sum())
+    codes[r > 0.97] = 255
+    n = wl["grid"]["n"]
+    P = wl["grid"]["patch"]
+    np_ = (n[0] // P[0], n[1] // P[1])
+    owner = np.repeat(np.arange(counts.size), counts)
+    dest = np.array([-1 if c == 255 else neighbour_patch(p, int(c), np_, (1, 1))
+                     for p, c in zip(owner, codes)], dtype=np.int32)
+    newcount, src = oracle.rebin(counts, dest)
+    g.rebin_codes(codes)
+    assert np.array_equal(g.counts(), newcount)
+    _, _, _, gids = g.particles()
+    assert np.array_equal(gids, ids[src])
+
+
+@pytest.mark.parametrize("case", ["4x4_patches", "self_neighbour_1x2", "two_patch_periodic"])
+def test_rebin_as_a_function_bit_exact(case):
+    _announce(f"re-binning as a function: {case}")
+    if case == "4x4_patches":
+        _rebin_case(dict(patch=[16, 16]), dict(n=(64, 64), patch=(16, 16), ppc=4), 1)
+    elif case == "self_neighbour_1x2":
+        _rebin_case(dict(patch=[32, 16]), dict(n=(32, 32), patch=(32, 16), ppc=4), 2)
+    else:
+        _rebin_case(dict(patch=[16, 32]), dict(n=(32, 32), patch=(16, 32), ppc=4), 3)
+
+
+def test_lwfa_small_fp64_matches_oracle():
+    _announce("lwfa 512x128 fp64, 60 steps (laser through x=0, open x)")
+    wl = W.lwfa_2d_small(nsteps=60)
+    g = gpu_sim(wl, 64)
+    g.step(60)
+    o = oracle_run(wl, 60)
+    e, b = compare_fields(g, o)
+    assert e < 1e-11 and b < 1e-11, (e, b)
+    assert np.array_equal(g.counts(), o.counts())
+    assert g.diag()["removed"] == o.removed
+
+
+def test_capacity_growth_keeps_state_exact():
+    _announce("capacity growth: tiny slack, 12 steps fp64")
+    wl = W.uniform_2d(n=(64, 64), patch=(16, 16), ppc=8, T_keV=200.0)
+    g = gpu_sim(wl, 64, capacity_factor=1.0, min_capacity=64)
+    g.step(12)
+    o = oracle_run(wl, 12)
+    e, b = compare_fields(g, o)
+    assert e < 1e-11 and b < 1e-11
+    assert np.array_equal(g.counts(), o.counts())
+    assert np.array_equal(g.particles()[3], o.particles()[3])
+    assert g.diag()["relayouts"] >= 1
+
+
+def test_empty_simulation_steps():
+    _announce("empty simulation")
+    grid = dict(ndim=2, n=[64, 32], d=[0.1, 0.1], dt=0.05, patch=[16, 16], periodic=[1, 1],
+                q=-1.0, m=1.0)
+    from paper_1511_03878_amd.sim import Sim
+    g = Sim(grid, 32)
+    g.set_particles([np.zeros(0), np.zeros(0)], [np.zeros(0)] * 3, np.zeros(0))
+    g.step(3)
+    assert g.diag()["step"] == 3 and g.num_particles() == 0
