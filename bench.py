@@ -1,0 +1,159 @@
+"""Benchmark: particle-steps/s of the full 2-D patch-PIC step on one MI355X.
+
+A step is one pass of the whole hot path over the resident state: work-queue
+build, fused gather / Boris / move / Esirkepov deposit, fused Yee update with
+the laser-driven and outflow faces, and the per-patch re-binning.  The
+workload is the laser-wakefield box (4096 x 1024 cells, 32 x 32-cell patches,
+4 electrons per plasma cell behind a linear density ramp, a0 = 4 Gaussian
+laser driven through x = 0), all inputs seeded and synthetic.
+
+Prints one JSON line.  The timed region covers exactly --steps steps of a
+freshly loaded simulation (inputs already in HBM), bracketed by device
+synchronisations; --warmup steps run first on a separate instance.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/sec (gather+push+deposit+Maxwell) & % HBM peak; batched p50/p99"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per particle-step of the fused particle kernel: read the
+# position (2 components), momentum (3) and weight, write position and momentum
+BYTES_PER_PARTICLE_STEP = {32: 44, 64: 88}
+
+
+def _workload(name, steps):
+    from paper_1511_03878_amd import workloads as W
+    if name == "lwfa":
+        wl = W.lwfa_2d(nsteps=max(steps, 1))
+        desc = ("lwfa_2d: 4096x1024 cells (dx=lambda/32, dy=lambda/8), 32x32-cell patches, "
+                "4 ppc electrons behind a 2->12 lambda ramp to 0.003 n_c (16.5M particles), "
+                "a0=4 w0=12 lambda Gaussian laser through x=0, open x / periodic y")
+    elif name == "lwfa_small":
+        wl = W.lwfa_2d_small(nsteps=max(steps, 1))
+        desc = "lwfa_2d_small: 512x128 cells, 32x32-cell patches, 4 ppc"
+    elif name == "uniform":
+        wl = W.uniform_2d()
+        desc = "uniform_2d: 128x128 cells, 16x16-cell patches, 16 ppc, 1 keV, periodic"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return wl, desc
+
+
+def _cpu_baseline(name, budget_s=25.0):
+    """Time the FP64 oracle (single-threaded C, as it stands) on one step of
+    the same workload on this host."""
+    import oracle
+    wl, _ = _workload(name, 1)
+    if not os.path.exists(os.path.join(ROOT, "oracle", "liborc.so")):
+        oracle.build(force=False)
+    o = oracle.Sim(wl["grid"])
+    o.set_particles(wl["x"], wl["u"], wl["w"])
+    if wl.get("laser"):
+        o.set_laser(ey=wl["laser"]["ey"], ez=wl["laser"].get("ez"))
+    n = wl["w"].size
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        o.step(1)
+        steps += 1
+        if time.perf_counter() - t0 > budget_s / 2 or steps >= 3:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": n * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} step(s) of the full workload ({n} particles), FP64 oracle, "
+                      f"{dt:.1f} s on one host core"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--precision", type=int, default=32, choices=(32, 64))
+    ap.add_argument("--workload", default="lwfa")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-kernel-timing", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1511_03878_amd.sim import Sim
+
+    torch.cuda.set_device(0)
+    wl, desc = _workload(args.workload, args.steps)
+    print(f"[bench] workload ready: {desc}", file=sys.stderr, flush=True)
+
+    if args.warmup > 0:
+        w = Sim.from_workload(wl, precision=args.precision)
+        w.step(args.warmup)
+        w.sync()
+        w.close()
+        del w
+    sim = Sim.from_workload(wl, precision=args.precision)
+    if not args.no_kernel_timing:
+        sim.timing_enable(True)
+    torch.cuda.synchronize()
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sim.sync()
+    wall = t1 - t0
+    _, _, pushed = sim.history(0, args.steps)
+    total = int(pushed.sum())
+    value = total / wall
+    timing = sim.timing() if not args.no_kernel_timing else {}
+    d = sim.diag()
+
+    roof = None
+    if timing:
+        ms, launches = timing["particles"]
+        avg_s = ms / 1e3 / max(launches, 1)
+        per_launch_bytes = BYTES_PER_PARTICLE_STEP[args.precision] * total / max(launches, 1)
+        achieved = per_launch_bytes / avg_s / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_particles2d",
+                "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in timing.items()}}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == 32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "steps_timed": args.steps,
+                   "particles_start": int(wl["w"].size), "particles_end": int(d["particles"]),
+                   "occupancy_max_end": d["occupancy_max"], "relayouts": d["relayouts"]},
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = _cpu_baseline(args.workload)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

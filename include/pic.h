@@ -90,17 +90,20 @@ typedef struct {
 typedef struct {
     int32_t ndim;          /* 2 */
     int32_t precision;     /* 32 or 64: storage and arithmetic of fields and particles */
-    int32_t n[3];          /* cells per axis (n[2] ignored in 2-D) */
+    int32_t n[3];          /* cells per axis, at least 4 (n[2] ignored in 2-D) */
     double d[3];           /* cell size per axis */
     double dt;             /* time step; must satisfy dt < (sum 1/d^2)^(-1/2) */
     int32_t patch[3];      /* cells per patch per axis; must divide n; at most 64 */
     int32_t periodic[3];   /* 1 periodic; 0 open: Silver-Mueller fields, absorbing
                               particles (x axis only) */
     double q, m;           /* species charge and mass */
-    double capacity_factor;/* slots per patch = max(min_capacity, factor * count); 0 = 1.5 */
-    int32_t min_capacity;  /* 0 = 64 */
+    double capacity_factor;/* slots per patch = max(min_capacity, factor * count); 0 = 2 */
+    int32_t min_capacity;  /* 0 = the mean patch occupancy (at least 64) */
     int32_t chunk;         /* max particles per work item; 0 = chosen from the load */
-    int32_t block;         /* threads per particle workgroup: 0, 256 or 512 */
+    int32_t block;         /* threads per particle workgroup: 256, 512 or 1024; 0 = 512 (FP32) / 1024 (FP64) */
+    int32_t field_tile;    /* Yee tile shape preset 0..5 (0 = default for the precision) */
+    int32_t lane_stride;   /* particles between adjacent lanes of the particle kernel, 1..64;
+                              0 = about two cells' worth (from the loaded particles) */
 } PicSimDesc;
 
 /* Diagnostics of a simulation (pic_diag_get synchronises the stream). */

@@ -44,33 +44,52 @@ __global__ __launch_bounds__(256) void k_maxwell2d(const SimDev<T> *__restrict__
         T *const *Jn = S.J[(stepn + 1) & 1];
 
         // ---- load nodes [X0-1, X0+TX+1] x [Y0-1, Y0+TY+1] -------------------
+        // all loads of the tile are issued before the first LDS write, so each
+        // thread keeps NIT x 9 requests in flight
+        constexpr int NIT = (NB + 255) / 256;
+        T v[NIT][9];
         double esum = 0.0;
-        for (int t = tid; t < NB; t += 256) {
+#pragma unroll
+        for (int r = 0; r < NIT; ++r) {
+            const int t = tid + 256 * r;
             const int a = t % W, b = t / W;
             const int gi = X0 - 1 + a, gj = Y0 - 1 + b;
-            const int ip = axis_node(gi, n0, per0, 0), id = axis_node(gi, n0, per0, 1);
-            const int jp = axis_node(gj, n1, per1, 0), jd = axis_node(gj, n1, per1, 1);
-            const bool own = a >= 1 && a <= TX && b >= 1 && b <= TY && gi < fn0 && gj < fn1;
+            // nodes more than one past the last stored node feed no update
+            // (tiles may be wider than the grid); they stay zero
+            const bool need = t < NB && gi <= fn0 + 1 && gj <= fn1 + 1;
+            const int ip = need ? axis_node(gi, n0, per0, 0) : -1;
+            const int id = need ? axis_node(gi, n0, per0, 1) : -1;
+            const int jp = need ? axis_node(gj, n1, per1, 0) : -1;
+            const int jd = need ? axis_node(gj, n1, per1, 1) : -1;
             // staggering: Ex (d,p) Ey (p,d) Ez (p,p) Bx (p,d) By (d,p) Bz (d,d)
             const int64_t kdp = (id >= 0 && jp >= 0) ? id + (int64_t)fn0 * jp : -1;
             const int64_t kpd = (ip >= 0 && jd >= 0) ? ip + (int64_t)fn0 * jd : -1;
             const int64_t kpp = (ip >= 0 && jp >= 0) ? ip + (int64_t)fn0 * jp : -1;
             const int64_t kdd = (id >= 0 && jd >= 0) ? id + (int64_t)fn0 * jd : -1;
-            const T ex = kdp >= 0 ? S.F[0][kdp] : T(0);
-            const T ey = kpd >= 0 ? S.F[1][kpd] : T(0);
-            const T ez = kpp >= 0 ? S.F[2][kpp] : T(0);
-            const T bx = kpd >= 0 ? S.F[3][kpd] : T(0);
-            const T by = kdp >= 0 ? S.F[4][kdp] : T(0);
-            const T bz = kdd >= 0 ? S.F[5][kdd] : T(0);
-            sE[0][t] = ex; sE[1][t] = ey; sE[2][t] = ez;
-            sB[0][t] = bx; sB[1][t] = by; sB[2][t] = bz;
-            sJ[0][t] = kdp >= 0 ? Jc[0][kdp] : T(0);
-            sJ[1][t] = kpd >= 0 ? Jc[1][kpd] : T(0);
-            sJ[2][t] = kpp >= 0 ? Jc[2][kpp] : T(0);
+            v[r][0] = kdp >= 0 ? S.F[0][kdp] : T(0);
+            v[r][1] = kpd >= 0 ? S.F[1][kpd] : T(0);
+            v[r][2] = kpp >= 0 ? S.F[2][kpp] : T(0);
+            v[r][3] = kpd >= 0 ? S.F[3][kpd] : T(0);
+            v[r][4] = kdp >= 0 ? S.F[4][kdp] : T(0);
+            v[r][5] = kdd >= 0 ? S.F[5][kdd] : T(0);
+            v[r][6] = kdp >= 0 ? Jc[0][kdp] : T(0);
+            v[r][7] = kpd >= 0 ? Jc[1][kpd] : T(0);
+            v[r][8] = kpp >= 0 ? Jc[2][kpp] : T(0);
+        }
+#pragma unroll
+        for (int r = 0; r < NIT; ++r) {
+            const int t = tid + 256 * r;
+            if (t >= NB) break;
+            const int a = t % W, b = t / W;
+            const int gi = X0 - 1 + a, gj = Y0 - 1 + b;
+            const bool own = a >= 1 && a <= TX && b >= 1 && b <= TY && gi < fn0 && gj < fn1;
+            sE[0][t] = v[r][0]; sE[1][t] = v[r][1]; sE[2][t] = v[r][2];
+            sB[0][t] = v[r][3]; sB[1][t] = v[r][4]; sB[2][t] = v[r][5];
+            sJ[0][t] = v[r][6]; sJ[1][t] = v[r][7]; sJ[2][t] = v[r][8];
             if (own) {
                 // invalid (outside) nodes were loaded as zero, so they add nothing
-                esum += (double)ex * ex + (double)ey * ey + (double)ez * ez + (double)bx * bx +
-                        (double)by * by + (double)bz * bz;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) esum += (double)v[r][c] * (double)v[r][c];
             }
         }
         __syncthreads();
@@ -159,32 +178,63 @@ __global__ __launch_bounds__(256) void k_maxwell2d(const SimDev<T> *__restrict__
         if ((tid & 63) == 0) s_red[tid >> 6] = esum;
         __syncthreads();
         if (tid == 0)
-            atomicAdd(&S.st->U, 0.5 * S.vcell * (s_red[0] + s_red[1] + s_red[2] + s_red[3]));
+            S.upart[lt] = 0.5 * S.vcell * (s_red[0] + s_red[1] + s_red[2] + s_red[3]);
         __syncthreads();
     }
 }
 
 }  // namespace
 
-template <>
-void maxwell_tile<float>(int &tx, int &ty) { tx = 64; ty = 16; }
-template <>
-void maxwell_tile<double>(int &tx, int &ty) { tx = 32; ty = 16; }
+// Tile shapes (TX x TY nodes per workgroup) the tuner can choose from.
+// FP32 tiles hold 9 x (TX+3)(TY+3) floats of LDS, FP64 tiles doubles.
+namespace {
+constexpr int kTiles32[6][2] = {{64, 16}, {64, 8}, {128, 8}, {32, 16}, {32, 32}, {128, 4}};
+constexpr int kTiles64[6][2] = {{32, 16}, {64, 8}, {32, 8}, {16, 16}, {64, 4}, {128, 4}};
+}  // namespace
+
+template <typename T>
+void maxwell_tile(int preset, int &tx, int &ty)
+{
+    const int p = (preset >= 0 && preset < 6) ? preset : 0;
+    tx = sizeof(T) == 4 ? kTiles32[p][0] : kTiles64[p][0];
+    ty = sizeof(T) == 4 ? kTiles32[p][1] : kTiles64[p][1];
+}
 
 template <typename T>
 void launch_maxwell(const SimDev<T> *sims, int nsims, const int *tile_prefix, int total_tiles,
-                    int grid, hipStream_t st)
+                    int grid, int preset, hipStream_t st)
 {
-    if constexpr (sizeof(T) == 4)
-        hipLaunchKernelGGL((k_maxwell2d<T, 64, 16>), dim3(grid), dim3(256), 0, st, sims, nsims,
-                           tile_prefix, total_tiles);
-    else
-        hipLaunchKernelGGL((k_maxwell2d<T, 32, 16>), dim3(grid), dim3(256), 0, st, sims, nsims,
-                           tile_prefix, total_tiles);
+#define PIC_MW(TX, TY)                                                                          \
+    hipLaunchKernelGGL((k_maxwell2d<T, TX, TY>), dim3(grid), dim3(256), 0, st, sims, nsims,    \
+                       tile_prefix, total_tiles)
+    const int p = (preset >= 0 && preset < 6) ? preset : 0;
+    if constexpr (sizeof(T) == 4) {
+        switch (p) {
+        case 1: PIC_MW(64, 8); break;
+        case 2: PIC_MW(128, 8); break;
+        case 3: PIC_MW(32, 16); break;
+        case 4: PIC_MW(32, 32); break;
+        case 5: PIC_MW(128, 4); break;
+        default: PIC_MW(64, 16); break;
+        }
+    } else {
+        switch (p) {
+        case 1: PIC_MW(64, 8); break;
+        case 2: PIC_MW(32, 8); break;
+        case 3: PIC_MW(16, 16); break;
+        case 4: PIC_MW(64, 4); break;
+        case 5: PIC_MW(128, 4); break;
+        default: PIC_MW(32, 16); break;
+        }
+    }
+#undef PIC_MW
 }
 
-template void launch_maxwell<float>(const SimDev<float> *, int, const int *, int, int, hipStream_t);
-template void launch_maxwell<double>(const SimDev<double> *, int, const int *, int, int,
+template void maxwell_tile<float>(int, int &, int &);
+template void maxwell_tile<double>(int, int &, int &);
+template void launch_maxwell<float>(const SimDev<float> *, int, const int *, int, int, int,
+                                    hipStream_t);
+template void launch_maxwell<double>(const SimDev<double> *, int, const int *, int, int, int,
                                      hipStream_t);
 
 }  // namespace pic

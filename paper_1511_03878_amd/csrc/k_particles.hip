@@ -95,8 +95,10 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
                                                        int jstride)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *Ft = reinterpret_cast<T *>(smem_raw);
-    T *Jt = Ft + 6 * fstride;
+    // current tile first (FP64 accumulation for either storage precision:
+    // LDS float atomics are much slower here than FP64 ones), then fields
+    double *Jt = reinterpret_cast<double *>(smem_raw);
+    T *Ft = reinterpret_cast<T *>(Jt + 3 * jstride);
     __shared__ int s_item;
     __shared__ double s_red[BLOCK / kWave];
 
@@ -121,19 +123,35 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
         const int per0 = S.periodic[0], per1 = S.periodic[1];
 
         // ---- stage E, B of nodes [ox-1, ox+P0+1] x [oy-1, oy+P1+1] --------
-        for (int t = tid; t < fw * fh; t += BLOCK) {
-            const int gi = ox - 1 + t % fw, gj = oy - 1 + t / fw;
-            const int ip = axis_node(gi, n0, per0, 0), id = axis_node(gi, n0, per0, 1);
-            const int jp = axis_node(gj, n1, per1, 0), jd = axis_node(gj, n1, per1, 1);
-            // staggering: Ex (d,p) Ey (p,d) Ez (p,p) Bx (p,d) By (d,p) Bz (d,d)
-            Ft[0 * fstride + t] = (id >= 0 && jp >= 0) ? S.F[0][id + fn0 * jp] : T(0);
-            Ft[1 * fstride + t] = (ip >= 0 && jd >= 0) ? S.F[1][ip + fn0 * jd] : T(0);
-            Ft[2 * fstride + t] = (ip >= 0 && jp >= 0) ? S.F[2][ip + fn0 * jp] : T(0);
-            Ft[3 * fstride + t] = (ip >= 0 && jd >= 0) ? S.F[3][ip + fn0 * jd] : T(0);
-            Ft[4 * fstride + t] = (id >= 0 && jp >= 0) ? S.F[4][id + fn0 * jp] : T(0);
-            Ft[5 * fstride + t] = (id >= 0 && jd >= 0) ? S.F[5][id + fn0 * jd] : T(0);
+        // four nodes per thread per round, all loads issued before the stores
+        for (int t0 = 0; t0 < fw * fh; t0 += 4 * BLOCK) {
+            T v[4][6];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int t = t0 + r * BLOCK + tid;
+                const int gi = ox - 1 + t % fw, gj = oy - 1 + t / fw;
+                const bool in = t < fw * fh;
+                const int ip = in ? axis_node(gi, n0, per0, 0) : -1;
+                const int id = in ? axis_node(gi, n0, per0, 1) : -1;
+                const int jp = in ? axis_node(gj, n1, per1, 0) : -1;
+                const int jd = in ? axis_node(gj, n1, per1, 1) : -1;
+                // staggering: Ex (d,p) Ey (p,d) Ez (p,p) Bx (p,d) By (d,p) Bz (d,d)
+                v[r][0] = (id >= 0 && jp >= 0) ? S.F[0][id + fn0 * jp] : T(0);
+                v[r][1] = (ip >= 0 && jd >= 0) ? S.F[1][ip + fn0 * jd] : T(0);
+                v[r][2] = (ip >= 0 && jp >= 0) ? S.F[2][ip + fn0 * jp] : T(0);
+                v[r][3] = (ip >= 0 && jd >= 0) ? S.F[3][ip + fn0 * jd] : T(0);
+                v[r][4] = (id >= 0 && jp >= 0) ? S.F[4][id + fn0 * jp] : T(0);
+                v[r][5] = (id >= 0 && jd >= 0) ? S.F[5][id + fn0 * jd] : T(0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int t = t0 + r * BLOCK + tid;
+                if (t < fw * fh)
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) Ft[c * fstride + t] = v[r][c];
+            }
         }
-        for (int t = tid; t < 3 * jstride; t += BLOCK) Jt[t] = T(0);
+        for (int t = tid; t < 3 * jstride; t += BLOCK) Jt[t] = 0.0;
         __syncthreads();
 
         const int64_t base = S.off[p] + first;
@@ -147,11 +165,44 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
         double kin = 0.0;
         uint32_t err = 0;
 
-        for (int k = tid; k < cnt; k += BLOCK) {
+        // Lane mapping.  Particles of one cell sit next to each other in a
+        // patch, and LDS atomics of lanes that hit one address (or bank)
+        // serialise.  The chunk is cut into units of 64 lanes: unit u takes
+        // particles 64 S (u / S) + l S + (u % S) for lanes l = 0..63, so with
+        // S about two cells' worth of particles the lanes of one wave sit two
+        // cells apart and their shape windows start at distinct nodes.  Waves
+        // take units round-robin; the next unit's particle is loaded before
+        // the current one is pushed.
+        constexpr int NW = BLOCK / kWave;
+        const int S_ = S.lane_stride;
+        const int wv = tid / kWave, ln = tid % kWave;
+        auto unit_particle = [&](int u) { return kWave * S_ * (u / S_) + ln * S_ + (u % S_); };
+        T nx_ = T(0), ny_ = T(0), nux = T(0), nuy = T(0), nuz = T(0), nw_ = T(0);
+        {
+            const int kn = unit_particle(wv);
+            if (kn < cnt) {
+                const int64_t g = base + kn;
+                nx_ = S.x[0][g]; ny_ = S.x[1][g];
+                nux = S.u[0][g]; nuy = S.u[1][g]; nuz = S.u[2][g]; nw_ = S.w[g];
+            }
+        }
+        // units past the last full pass may map outside [0, cnt): skipped
+        const int uend = ((cnt + kWave * S_ - 1) / (kWave * S_)) * S_;
+        for (int u = wv; u < uend; u += NW) {
+            const int k = unit_particle(u);
+            const T xl = nx_, yl = ny_;
+            T ux = nux, uy = nuy, uz = nuz;
+            const T wgt = nw_;
+            if (u + NW < uend) {
+                const int kn = unit_particle(u + NW);
+                if (kn < cnt) {
+                    const int64_t gn = base + kn;
+                    nx_ = S.x[0][gn]; ny_ = S.x[1][gn];
+                    nux = S.u[0][gn]; nuy = S.u[1][gn]; nuz = S.u[2][gn]; nw_ = S.w[gn];
+                }
+            }
+            if (k >= cnt) continue;
             const int64_t g = base + k;
-            const T xl = S.x[0][g], yl = S.x[1][g];
-            T ux = S.u[0][g], uy = S.u[1][g], uz = S.u[2][g];
-            const T wgt = S.w[g];
 
             // ---- gather ---------------------------------------------------
             const int ipx = (int)floor(xl + T(0.5)), idx_ = (int)floor(xl);
@@ -211,7 +262,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
                 const double qw = (double)wgt;
                 const double ax = cx * qw, ay = cy * qw;
                 const double az = (double)q * qw * (double)(uz * ig1);
-                T *Jxt = Jt, *Jyt = Jt + jstride, *Jzt = Jt + 2 * jstride;
+                double *Jxt = Jt, *Jyt = Jt + jstride, *Jzt = Jt + 2 * jstride;
                 const int r0 = (my + 2) * jw + (mx + 2);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
@@ -220,7 +271,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
 #pragma unroll
                     for (int i = 0; i < 3; ++i) {
                         acc += DSx[i] * wy;
-                        atomicAdd(&Jxt[r0 + j * jw + i], (T)(ax * acc));
+                        atomicAdd(&Jxt[r0 + j * jw + i], ax * acc);
                     }
                 }
 #pragma unroll
@@ -230,7 +281,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
 #pragma unroll
                     for (int j = 0; j < 3; ++j) {
                         acc += DSy[j] * wx;
-                        atomicAdd(&Jyt[r0 + j * jw + i], (T)(ay * acc));
+                        atomicAdd(&Jyt[r0 + j * jw + i], ay * acc);
                     }
                 }
 #pragma unroll
@@ -239,7 +290,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
                     for (int i = 0; i < 4; ++i) {
                         const double wz = S0x[i] * S0y[j] + 0.5 * (DSx[i] * S0y[j] + S0x[i] * DSy[j]) +
                                           DSx[i] * DSy[j] * (1.0 / 3.0);
-                        atomicAdd(&Jzt[r0 + j * jw + i], (T)(az * wz));
+                        atomicAdd(&Jzt[r0 + j * jw + i], az * wz);
                     }
 
                 const int sx_ = x1 < T(0) ? -1 : (x1 >= (T)P0 ? 1 : 0);
@@ -268,7 +319,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
                 const int gi = ox - 2 + t % jw, gj = oy - 2 + t / jw;
                 const int ip = axis_node(gi, n0, per0, 0), id = axis_node(gi, n0, per0, 1);
                 const int jp = axis_node(gj, n1, per1, 0), jd = axis_node(gj, n1, per1, 1);
-                const T vx = Jt[t], vy = Jt[jstride + t], vz = Jt[2 * jstride + t];
+                const T vx = (T)Jt[t], vy = (T)Jt[jstride + t], vz = (T)Jt[2 * jstride + t];
                 if (vx != T(0) && id >= 0 && jp >= 0) atomicAdd(&Jg[0][id + fn0 * jp], vx);
                 if (vy != T(0) && ip >= 0 && jd >= 0) atomicAdd(&Jg[1][ip + fn0 * jd], vy);
                 if (vz != T(0) && ip >= 0 && jp >= 0) atomicAdd(&Jg[2][ip + fn0 * jp], vz);
@@ -279,10 +330,12 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
         if ((tid & (kWave - 1)) == 0) s_red[tid / kWave] = kin;
         __syncthreads();
         if (tid == 0) {
+            // per-patch partial (chunks of one patch rarely collide); a single
+            // per-simulation accumulator would serialise every item on one
+            // L2 address
             double tot = 0.0;
             for (int wv = 0; wv < BLOCK / kWave; ++wv) tot += s_red[wv];
-            atomicAdd(&S.st->K, tot * S.vcell);
-            atomicAdd((unsigned long long *)&S.st->pushed, (unsigned long long)cnt);
+            atomicAdd(&S.kpart[p], tot * S.vcell);
         }
         __syncthreads();
     }
@@ -293,7 +346,7 @@ size_t lds_bytes(int maxP0, int maxP1, int &fstride, int &jstride)
 {
     fstride = (maxP0 + 3) * (maxP1 + 3);
     jstride = (maxP0 + 5) * (maxP1 + 5);
-    return sizeof(T) * (size_t)(6 * fstride + 3 * jstride);
+    return sizeof(double) * (size_t)(3 * jstride) + sizeof(T) * (size_t)(6 * fstride);
 }
 
 }  // namespace
@@ -304,7 +357,10 @@ void launch_particles(const SimDev<T> *sims, const Item *items, const int *nitem
 {
     int fs, js;
     size_t lds = lds_bytes<T>(maxP0, maxP1, fs, js);
-    if (block == 512)
+    if (block == 1024)
+        hipLaunchKernelGGL((k_particles2d<T, 1024>), dim3(grid), dim3(1024), lds, st, sims, items,
+                           nitems, head, fs, js);
+    else if (block == 512)
         hipLaunchKernelGGL((k_particles2d<T, 512>), dim3(grid), dim3(512), lds, st, sims, items,
                            nitems, head, fs, js);
     else
@@ -318,7 +374,9 @@ int particles_occupancy(int block, int maxP0, int maxP1)
     int fs, js, nb = 0;
     size_t lds = lds_bytes<T>(maxP0, maxP1, fs, js);
     hipError_t e;
-    if (block == 512)
+    if (block == 1024)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particles2d<T, 1024>, 1024, lds);
+    else if (block == 512)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particles2d<T, 512>, 512, lds);
     else
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particles2d<T, 256>, 256, lds);

@@ -109,10 +109,14 @@ __global__ __launch_bounds__(kRB) void k_rebin_count(const SimDev<T> *__restrict
             for (int k = 0; k < kKeys; ++k) { s_koff[k] = acc; acc += s_cnt[k]; }
         }
         __syncthreads();
-        for (int c0 = 0; c0 < n; c0 += kRB) {
+        int nleavers = 0;
+        for (int k = 0; k < kKeys; ++k) nleavers += s_cnt[k];
+        for (int c0 = 0; c0 < n && nleavers > 0; c0 += kRB) {
             const int k = c0 + tid;
             const int key = k < n ? code_key(s_key, S.code[base + k]) : -1;
             const bool leaver = key >= 0;
+            // most chunks hold no leaver: skip the ranking entirely
+            if (!__syncthreads_or(leaver)) continue;
             const uint64_t ball = __ballot(leaver);
             int rank_key = 0;
 #pragma unroll
@@ -289,26 +293,47 @@ __global__ __launch_bounds__(kRB) void k_rebin_scatter(const SimDev<T> *__restri
     }
 }
 
-// Close the step of every active simulation whose re-binning was applied.
+// Close the step of every active simulation whose re-binning was applied:
+// reduce the per-tile field energies and per-patch kinetic energies, record
+// the history entry, advance the step counter.  One workgroup per simulation.
 template <typename T>
-__global__ void k_step_end(const SimDev<T> *__restrict__ sims, int nsims)
+__global__ __launch_bounds__(256) void k_step_end(const SimDev<T> *__restrict__ sims,
+                                                  const int *__restrict__ tile_prefix)
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nsims) return;
-    SimState *st = sims[s].st;
+    __shared__ double s_u[4], s_k[4];
+    const int s = blockIdx.x, tid = threadIdx.x;
+    const SimDev<T> &S = sims[s];
+    SimState *st = S.st;
     if (!st->active || (st->flags & kFlagPending)) return;
-    const int64_t k = st->step;
-    double *h = sims[s].hist + (k % kHistLen) * 4;
-    h[0] = st->U;
-    h[1] = st->K;
-    h[2] = (double)st->pushed;
-    h[3] = (double)st->removed;
-    st->U = 0.0;
-    st->K = 0.0;
-    st->pushed = 0;
-    st->step = k + 1;
-    if (st->steps_left > 0) st->steps_left -= 1;
-    st->active = 0;
+    const int nt = tile_prefix[s + 1] - tile_prefix[s];
+    double u = 0.0, k = 0.0;
+    for (int i = tid; i < nt; i += 256) u += S.upart[i];
+    for (int i = tid; i < S.npatch; i += 256) {
+        k += S.kpart[i];
+        S.kpart[i] = 0.0;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        u += __shfl_xor(u, o, 64);
+        k += __shfl_xor(k, o, 64);
+    }
+    if ((tid & 63) == 0) { s_u[tid >> 6] = u; s_k[tid >> 6] = k; }
+    __syncthreads();
+    if (tid == 0) {
+        const double U = s_u[0] + s_u[1] + s_u[2] + s_u[3];
+        const double K = s_k[0] + s_k[1] + s_k[2] + s_k[3];
+        const int64_t n = st->step;
+        double *h = S.hist + (n % kHistLen) * 4;
+        h[0] = U;
+        h[1] = K;
+        h[2] = (double)st->pushed;
+        h[3] = (double)st->removed;
+        st->U = U;
+        st->K = K;
+        st->step = n + 1;
+        if (st->steps_left > 0) st->steps_left -= 1;
+        st->active = 0;
+    }
 }
 
 // ---- work queue ---------------------------------------------------------------
@@ -320,7 +345,8 @@ template <typename T>
 __global__ __launch_bounds__(kQB) void k_queue(const SimDev<T> *__restrict__ sims, QueueArgs qa)
 {
     __shared__ int s_hist[kBuckets];
-    __shared__ uint8_t s_act[4096];
+    __shared__ uint8_t s_act[kMaxBatch];
+    __shared__ int s_pushed[kMaxBatch];
     __shared__ int s_wsum[kQB / 64];
     const int tid = threadIdx.x;
     const int nsims = qa.nsims;
@@ -332,6 +358,7 @@ __global__ __launch_bounds__(kQB) void k_queue(const SimDev<T> *__restrict__ sim
         const uint32_t act = st->steps_left > 0 && !(st->flags & (kFlagPending | kFlagErrMask));
         st->active = act;
         s_act[s] = (uint8_t)act;
+        s_pushed[s] = 0;
     }
     __syncthreads();
     // bucket of a chunk of c particles: larger chunks first
@@ -340,9 +367,12 @@ __global__ __launch_bounds__(kQB) void k_queue(const SimDev<T> *__restrict__ sim
         const int s = find_sim(qa.patch_prefix, nsims, gp);
         if (!s_act[s]) continue;
         const int n = sims[s].count[gp - qa.patch_prefix[s]];
+        if (n) atomicAdd(&s_pushed[s], n);
         for (int c0 = 0; c0 < n; c0 += chunk) atomicAdd(&s_hist[bucket(min(chunk, n - c0))], 1);
     }
     __syncthreads();
+    for (int s = tid; s < nsims; s += kQB)
+        if (s_act[s]) sims[s].st->pushed = s_pushed[s];
     // exclusive scan of the histogram (one bucket per thread)
     int v = tid < kBuckets ? s_hist[tid] : 0;
     int incl = v;
@@ -443,7 +473,7 @@ void launch_queue(const SimDev<T> *sims, const QueueArgs &q, hipStream_t st)
 
 template <typename T>
 void launch_rebin(const SimDev<T> *sims, int nsims, const int *patch_prefix, int total_patches,
-                  int grid, bool finalize, hipStream_t st)
+                  int grid, bool finalize, const int *tile_prefix, hipStream_t st)
 {
     hipLaunchKernelGGL((k_rebin_count<T>), dim3(grid), dim3(kRB), 0, st, sims, nsims, patch_prefix,
                        total_patches);
@@ -452,7 +482,7 @@ void launch_rebin(const SimDev<T> *sims, int nsims, const int *patch_prefix, int
     hipLaunchKernelGGL((k_rebin_scatter<T>), dim3(grid), dim3(kRB), 0, st, sims, nsims,
                        patch_prefix, total_patches, finalize ? 1 : 0);
     if (finalize)
-        hipLaunchKernelGGL((k_step_end<T>), dim3((nsims + 63) / 64), dim3(64), 0, st, sims, nsims);
+        hipLaunchKernelGGL((k_step_end<T>), dim3(nsims), dim3(256), 0, st, sims, tile_prefix);
 }
 
 template <typename T>
@@ -477,7 +507,7 @@ void launch_scatter_codes(const uint8_t *packed, const int64_t *packed_off, cons
 #define PIC_INST(T)                                                                              \
     template void launch_queue<T>(const SimDev<T> *, const QueueArgs &, hipStream_t);            \
     template void launch_rebin<T>(const SimDev<T> *, int, const int *, int, int, bool,           \
-                                  hipStream_t);                                                  \
+                                  const int *, hipStream_t);                                     \
     template void launch_relayout<T>(const SimDev<T> *, const SimDev<T> *, int, hipStream_t);    \
     template void launch_rho<T>(const SimDev<T> *, int, double *, hipStream_t);
 PIC_INST(float)

@@ -34,14 +34,17 @@ int particles_occupancy(int block, int maxP0, int maxP1);
 // other J buffer and accumulates the field energy of the incoming E, B.
 template <typename T>
 void launch_maxwell(const SimDev<T> *sims, int nsims, const int *tile_prefix, int total_tiles,
-                    int grid, hipStream_t st);
+                    int grid, int preset, hipStream_t st);
 template <typename T>
-void maxwell_tile(int &tx, int &ty);
+void maxwell_tile(int preset, int &tx, int &ty);
 
 // Re-binning: count and stage leavers; check capacity; scatter.
+// finalize: also close the step (energy reduction over the per-tile and
+// per-patch partials, history, step counter); tile_prefix gives the Yee
+// tile count of each simulation.
 template <typename T>
 void launch_rebin(const SimDev<T> *sims, int nsims, const int *patch_prefix, int total_patches,
-                  int grid, bool finalize, hipStream_t st);
+                  int grid, bool finalize, const int *tile_prefix, hipStream_t st);
 
 // Copy particles into a new per-patch layout (capacity growth).
 template <typename T>

@@ -20,6 +20,7 @@ namespace pic {
 
 constexpr int kMaxPatch = 64;      // cells per patch per axis
 constexpr int kHistLen = 4096;     // energy-history ring length
+constexpr int kMaxBatch = 2048;    // simulations per batch
 constexpr int kNDir2 = 9;          // neighbour directions in 2-D (4 = stay)
 constexpr int kStay2 = 4;
 constexpr uint8_t kRemoved = 255;
@@ -37,7 +38,7 @@ struct SimState {
     uint32_t active;     // set by the queue kernel for the step in flight
     int64_t removed;
     int64_t pushed;      // particles pushed in the step in flight
-    double U, K;         // energy accumulators of the step in flight
+    double U, K;         // energies of the last completed step
 };
 
 template <typename T>
@@ -45,6 +46,7 @@ struct SimDev {
     int n[3], P[3], np[3], fn[3], periodic[3];
     int npatch;
     int ndim;
+    int lane_stride;   // particles between consecutive lanes of a wave (power of 2)
     T d[3];
     T dt;
     T q, m;
@@ -72,6 +74,8 @@ struct SimDev {
     int64_t laser_steps;
     SimState *st;
     double *hist;      // [kHistLen][4]: U, K, pushed, removed
+    double *upart;     // per Yee tile: field energy of the step in flight
+    double *kpart;     // per patch: kinetic energy of the step in flight
 };
 
 // ---- small helpers ----------------------------------------------------------
@@ -84,9 +88,11 @@ __device__ __forceinline__ int wrap_idx(int i, int n)
 
 // Storage index of node i on an axis, or -1 outside an open axis.  stag = 1
 // for dual (half-cell) positions, which exist only up to n-1 on an open axis.
+// Callers pass indices within a few nodes of [0, n), so one conditional
+// shift replaces the modulo on a periodic axis.
 __device__ __forceinline__ int axis_node(int i, int n, int periodic, int stag)
 {
-    if (periodic) return wrap_idx(i, n);
+    if (periodic) return i < 0 ? i + n : (i >= n ? i - n : i);
     if (i < 0 || i > n - stag) return -1;
     return i;
 }

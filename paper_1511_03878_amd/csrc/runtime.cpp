@@ -77,7 +77,7 @@ int validate_desc(const PicSimDesc &d, std::string &why)
     if (d.precision != 32 && d.precision != 64) { why = "precision must be 32 or 64"; return PIC_EINVAL; }
     double inv2 = 0.0;
     for (int a = 0; a < d.ndim; ++a) {
-        if (d.n[a] <= 0 || d.patch[a] <= 0) { why = "cell and patch counts must be positive"; return PIC_EINVAL; }
+        if (d.n[a] < 4 || d.patch[a] <= 0) { why = "at least 4 cells per axis and positive patch sizes"; return PIC_EINVAL; }
         if (d.patch[a] > kMaxPatch) { why = "patch size above 64 cells"; return PIC_EINVAL; }
         if (d.n[a] % d.patch[a]) { why = "patch size must divide the cell count"; return PIC_EINVAL; }
         if (!(d.d[a] > 0.0) || !std::isfinite(d.d[a])) { why = "cell sizes must be positive"; return PIC_EINVAL; }
@@ -89,7 +89,9 @@ int validate_desc(const PicSimDesc &d, std::string &why)
     if (!(d.m > 0.0) || !std::isfinite(d.q)) { why = "species mass must be positive"; return PIC_EINVAL; }
     if (d.capacity_factor != 0.0 && !(d.capacity_factor >= 1.0)) { why = "capacity_factor must be >= 1"; return PIC_EINVAL; }
     if (d.min_capacity < 0 || d.chunk < 0) { why = "negative min_capacity or chunk"; return PIC_EINVAL; }
-    if (d.block != 0 && d.block != 256 && d.block != 512) { why = "block must be 0, 256 or 512"; return PIC_EINVAL; }
+    if (d.field_tile < 0 || d.field_tile > 5) { why = "field_tile must be 0..5"; return PIC_EINVAL; }
+    if (d.lane_stride < 0 || d.lane_stride > 64) { why = "lane_stride must be 0..64"; return PIC_EINVAL; }
+    if (d.block != 0 && d.block != 256 && d.block != 512 && d.block != 1024) { why = "block must be 0, 256, 512 or 1024"; return PIC_EINVAL; }
     return PIC_OK;
 }
 
@@ -100,8 +102,7 @@ template <typename T>
 SimImpl<T>::SimImpl(const PicSimDesc &d, const PicAllocator *a, hipStream_t s)
 {
     desc = d;
-    if (desc.capacity_factor == 0.0) desc.capacity_factor = 1.5;
-    if (desc.min_capacity == 0) desc.min_capacity = 64;
+    if (desc.capacity_factor == 0.0) desc.capacity_factor = 2.0;
     precision = d.precision;
     stream = s;
     if (a) alloc.hook = *a;
@@ -128,7 +129,14 @@ SimImpl<T>::SimImpl(const PicSimDesc &d, const PicAllocator *a, hipStream_t s)
         narrive_d = (int32_t *)alloc.get(sizeof(int32_t) * npatch);
         nhole_d = (int32_t *)alloc.get(sizeof(int32_t) * npatch);
         prefix_d = (int *)alloc.get(sizeof(int) * 2);
+        tprefix_d = (int *)alloc.get(sizeof(int) * 2);
         view_d = (SimDev<T> *)alloc.get(sizeof(SimDev<T>));
+        // per-tile energy partials, sized for the smallest Yee tile preset (16 x 4)
+        max_tiles = (int64_t)((fn[0] + 15) / 16) * ((fn[1] + 3) / 4);
+        upart = (double *)alloc.get(sizeof(double) * max_tiles);
+        kpart = (double *)alloc.get(sizeof(double) * npatch);
+        hipcheck(hipMemsetAsync(upart, 0, sizeof(double) * max_tiles, stream), "memset upart");
+        hipcheck(hipMemsetAsync(kpart, 0, sizeof(double) * npatch, stream), "memset kpart");
         for (int c = 0; c < 6; ++c) hipcheck(hipMemsetAsync(F[c], 0, sizeof(T) * fsize, stream), "memset F");
         for (int b = 0; b < 2; ++b)
             for (int c = 0; c < 3; ++c)
@@ -205,6 +213,9 @@ void SimImpl<T>::release()
     alloc.put(narrive_d);
     alloc.put(nhole_d);
     alloc.put(prefix_d);
+    alloc.put(tprefix_d);
+    alloc.put(upart);
+    alloc.put(kpart);
     alloc.put(view_d);
     alloc.put(laser_ey);
     alloc.put(laser_ez);
@@ -212,7 +223,9 @@ void SimImpl<T>::release()
         (void)hipEventDestroy(e.a);
         (void)hipEventDestroy(e.b);
     }
+    for (auto &e : timing.pool) (void)hipEventDestroy(e);
     timing.events.clear();
+    timing.pool.clear();
 }
 
 // Allocate a particle layout whose patch capacities hold `need` particles
@@ -223,9 +236,16 @@ std::vector<void *> SimImpl<T>::layout_particles(const std::vector<int32_t> &nee
 {
     std::vector<int32_t> cap(npatch);
     std::vector<int64_t> off(npatch + 1, 0);
+    // floor of every patch: the given minimum, or else the mean occupancy
+    int64_t floor_cap = desc.min_capacity;
+    if (floor_cap == 0) {
+        int64_t tot = 0;
+        for (int p = 0; p < npatch; ++p) tot += need[p];
+        floor_cap = std::max<int64_t>(64, (tot + npatch - 1) / std::max(npatch, 1));
+    }
     for (int p = 0; p < npatch; ++p) {
         int64_t c = (int64_t)std::ceil(desc.capacity_factor * need[p]);
-        c = std::max<int64_t>(c, desc.min_capacity);
+        c = std::max<int64_t>(c, floor_cap);
         c = std::max<int64_t>(c, need[p]);
         c = (c + 63) & ~int64_t(63);
         if (p < (int)cap_h.size()) c = std::max<int64_t>(c, cap_h[p]);  // never shrink
@@ -287,6 +307,7 @@ void SimImpl<T>::refresh_view()
     }
     V.npatch = npatch;
     V.ndim = 2;
+    V.lane_stride = lane_stride;
     V.dt = (T)desc.dt;
     V.q = (T)desc.q;
     V.m = (T)desc.m;
@@ -301,7 +322,7 @@ void SimImpl<T>::refresh_view()
     V.cap = cap_d; V.off = off_d; V.count = counts_d; V.newcount = newcount_d;
     V.kcnt = kcnt_d; V.nleave = nleave_d; V.narrive = narrive_d; V.nhole = nhole_d;
     V.laser_ey = laser_ey; V.laser_ez = laser_ez; V.laser_steps = laser_steps;
-    V.st = st; V.hist = hist;
+    V.st = st; V.hist = hist; V.upart = upart; V.kpart = kpart;
     hipcheck(hipMemcpyAsync(view_d, &v, sizeof(v), hipMemcpyHostToDevice, stream), "view upload");
     ++layout_version;
 }
@@ -322,6 +343,20 @@ void SimImpl<T>::set_particles(int64_t cnt, const double *const xs[3], const dou
         int cy = std::min((int)std::floor(xs[1][k]), n[1] - 1) / P[1];
         pp[k] = cx + np[0] * cy;
         counts[pp[k]]++;
+    }
+    {
+        // lane stride of the particle kernel: particles per occupied cell,
+        // rounded down to a power of two (cells hold their particles in a run)
+        std::vector<uint8_t> occupied((size_t)n[0] * n[1], 0);
+        for (int64_t k = 0; k < cnt; ++k)
+            occupied[(size_t)std::min((int)xs[0][k], n[0] - 1) +
+                     (size_t)n[0] * std::min((int)xs[1][k], n[1] - 1)] = 1;
+        int64_t cells = 0;
+        for (uint8_t o : occupied) cells += o;
+        const double ppc = cells ? (double)cnt / cells : 1.0;
+        // about two cells' worth of particles between lanes
+        lane_stride = desc.lane_stride ? desc.lane_stride
+                                       : (int)std::max(1.0, std::min(64.0, std::round(2.0 * ppc)));
     }
     hipcheck(hipStreamSynchronize(stream), "sync");
     std::vector<void *> old = layout_particles(counts);
@@ -543,7 +578,7 @@ void SimImpl<T>::recover_pending(bool finalize)
         s.flags &= ~kFlagPending;
         s.active = 1;
         hipcheck(hipMemcpyAsync(&st->flags, &s.flags, sizeof(uint32_t) * 2, hipMemcpyHostToDevice, stream), "flags");
-        launch_rebin<T>(view_d, 1, prefix_d, npatch, std::min(npatch, 4 * cu_count()), finalize, stream);
+        launch_rebin<T>(view_d, 1, prefix_d, npatch, std::min(npatch, 4 * cu_count()), finalize, tprefix_d, stream);
         hipcheck(hipGetLastError(), "rebin launch");
         s = read_state();
         if (!(s.flags & kFlagPending)) {
@@ -578,7 +613,7 @@ void SimImpl<T>::rebin_codes(const uint8_t *codes_h, size_t cnt)
     SimState s = read_state();
     s.active = 1;
     hipcheck(hipMemcpyAsync(&st->active, &s.active, sizeof(uint32_t), hipMemcpyHostToDevice, stream), "active");
-    launch_rebin<T>(view_d, 1, prefix_d, npatch, std::min(npatch, 4 * cu_count()), false, stream);
+    launch_rebin<T>(view_d, 1, prefix_d, npatch, std::min(npatch, 4 * cu_count()), false, tprefix_d, stream);
     hipcheck(hipGetLastError(), "rebin launch");
     s = read_state();
     alloc.put(pk);
@@ -618,8 +653,16 @@ void Timing::record(hipStream_t s, int k, bool begin)
     if (begin) {
         Ev e;
         e.kind = k;
-        hipcheck(hipEventCreate(&e.a), "event");
-        hipcheck(hipEventCreate(&e.b), "event");
+        auto take = [&](hipEvent_t &ev) {
+            if (!pool.empty()) {
+                ev = pool.back();
+                pool.pop_back();
+            } else {
+                hipcheck(hipEventCreate(&ev), "event");
+            }
+        };
+        take(e.a);
+        take(e.b);
         hipcheck(hipEventRecord(e.a, s), "event record");
         events.push_back(e);
     } else {
@@ -635,8 +678,8 @@ void Timing::collect()
         hipcheck(hipEventElapsedTime(&ms, e.a, e.b), "event time");
         total_ms[e.kind] += ms;
         launches[e.kind] += 1;
-        (void)hipEventDestroy(e.a);
-        (void)hipEventDestroy(e.b);
+        pool.push_back(e.a);
+        pool.push_back(e.b);
     }
     events.clear();
 }
@@ -705,21 +748,24 @@ void BatchImpl<T>::build_tables()
     hipcheck(hipStreamSynchronize(stream), "sync");
     const int ns = (int)members.size();
     std::vector<int> pp(ns + 1, 0), tp(ns + 1, 0);
+    tile_preset = 0;
+    for (auto *m : members) if (m->desc.field_tile) tile_preset = m->desc.field_tile;
     int tx, ty;
-    maxwell_tile<T>(tx, ty);
+    maxwell_tile<T>(tile_preset, tx, ty);
     maxP0 = maxP1 = 1;
     int64_t items = 0;
     int64_t particles = 0;
-    int min_block = 512;
+    if (ns > kMaxBatch) throw Error(PIC_EINVAL, "too many simulations in one batch");
     for (int i = 0; i < ns; ++i) {
         SimImpl<T> *m = members[i];
         pp[i + 1] = pp[i] + m->npatch;
         const int ntx = (m->fn[0] + tx - 1) / tx, nty = (m->fn[1] + ty - 1) / ty;
         tp[i + 1] = tp[i] + ntx * nty;
+        const int own[2] = {0, ntx * nty};
+        hipcheck(hipMemcpyAsync(m->tprefix_d, own, sizeof(own), hipMemcpyHostToDevice, stream), "tile count");
         maxP0 = std::max(maxP0, m->P[0]);
         maxP1 = std::max(maxP1, m->P[1]);
         particles += m->num_particles();
-        if (m->desc.block) min_block = std::min(min_block, (int)m->desc.block);
     }
     total_patches = pp[ns];
     total_tiles = tp[ns];
@@ -735,9 +781,8 @@ void BatchImpl<T>::build_tables()
     }
     for (auto *m : members) items += m->max_items(chunk);
     items = std::max<int64_t>(items, 1);
-    block = (sizeof(T) == 8 && maxP0 * maxP1 >= 32 * 32) ? 512 : 256;
-    if (min_block != 512 || std::any_of(members.begin(), members.end(), [](SimImpl<T> *m) { return m->desc.block == 512; }))
-        for (auto *m : members) if (m->desc.block) block = m->desc.block;
+    block = sizeof(T) == 8 ? 1024 : 512;
+    for (auto *m : members) if (m->desc.block) block = m->desc.block;
     const int occ = std::max(1, particles_occupancy<T>(block, maxP0, maxP1));
     grid_particles = cu_count() * occ;
     grid_maxwell = std::max(1, std::min(total_tiles, cu_count() * 8));
@@ -810,10 +855,10 @@ void BatchImpl<T>::launch_one_step()
     launch_particles<T>(sims_d, items_d, nitems_d, head_d, grid_particles, block, maxP0, maxP1, stream);
     tm.record(stream, 1, false);
     tm.record(stream, 2, true);
-    launch_maxwell<T>(sims_d, qa.nsims, tile_prefix_d, total_tiles, grid_maxwell, stream);
+    launch_maxwell<T>(sims_d, qa.nsims, tile_prefix_d, total_tiles, grid_maxwell, tile_preset, stream);
     tm.record(stream, 2, false);
     tm.record(stream, 3, true);
-    launch_rebin<T>(sims_d, qa.nsims, patch_prefix_d, total_patches, grid_rebin, true, stream);
+    launch_rebin<T>(sims_d, qa.nsims, patch_prefix_d, total_patches, grid_rebin, true, tile_prefix_d, stream);
     tm.record(stream, 3, false);
     hipcheck(hipGetLastError(), "step launch");
 }
@@ -833,18 +878,26 @@ int BatchImpl<T>::run(int64_t max_steps, bool until_done)
     if (members.empty()) return 0;
     if (dirty) build_tables();
     std::vector<int64_t> before(members.size());
-    for (size_t i = 0; i < members.size(); ++i) before[i] = members[i]->read_state().steps_left;
+    int64_t budget = 0;  // largest remaining step budget among the members
+    for (size_t i = 0; i < members.size(); ++i) {
+        SimState s = members[i]->read_state();
+        before[i] = s.steps_left;
+        if (!(s.flags & kFlagErrMask)) budget = std::max(budget, s.steps_left);
+    }
     int64_t launched = 0;
-    const int64_t K = 16;
+    const int64_t K = 32;
     int finished = 0;
     for (;;) {
-        int64_t todo = until_done ? K : std::min<int64_t>(K, max_steps - launched);
+        // never launch more passes than the largest budget still needs
+        int64_t todo = std::min<int64_t>(K, budget);
+        if (!until_done) todo = std::min<int64_t>(todo, max_steps - launched);
         if (todo <= 0) break;
         for (int64_t k = 0; k < todo; ++k) launch_one_step();
         launched += todo;
         // poll member states
         bool any_left = false;
         bool recovered = false;
+        budget = 0;
         for (size_t i = 0; i < members.size(); ++i) {
             SimImpl<T> *m = members[i];
             SimState s = m->read_state();
@@ -853,7 +906,10 @@ int BatchImpl<T>::run(int64_t max_steps, bool until_done)
                 recovered = true;
                 s = m->read_state();
             }
-            if (s.steps_left > 0 && !(s.flags & kFlagErrMask)) any_left = true;
+            if (s.steps_left > 0 && !(s.flags & kFlagErrMask)) {
+                any_left = true;
+                budget = std::max(budget, s.steps_left);
+            }
         }
         if (recovered) refresh_member_views();
         if (dirty) build_tables();

@@ -41,6 +41,7 @@ struct Timing {
     };
     bool enabled = false;
     std::vector<Ev> events;
+    std::vector<hipEvent_t> pool;
     double total_ms[kKinds] = {0, 0, 0, 0};
     int64_t launches[kKinds] = {0, 0, 0, 0};
     void record(hipStream_t s, int kind, bool begin);
@@ -87,7 +88,9 @@ struct SimImpl : SimBase {
     double *hist = nullptr;
     int32_t *counts_d = nullptr, *newcount_d = nullptr, *kcnt_d = nullptr, *nleave_d = nullptr;
     int32_t *narrive_d = nullptr, *nhole_d = nullptr;
-    int *prefix_d = nullptr;
+    int *prefix_d = nullptr, *tprefix_d = nullptr;
+    double *upart = nullptr, *kpart = nullptr;
+    int64_t max_tiles = 0;
     T *laser_ey = nullptr, *laser_ez = nullptr;
     int64_t laser_steps = 0;
     // particle layout
@@ -102,6 +105,7 @@ struct SimImpl : SimBase {
     int64_t total_cap = 0;
     int max_items_cache = -1, chunk_cache = -1;
     int64_t layout_version = 0;
+    int lane_stride = 1;
     SimDev<T> v;
     SimDev<T> *view_d = nullptr;
     BatchImpl<T> *batch = nullptr;  // user batch this simulation belongs to
@@ -154,7 +158,7 @@ struct BatchImpl : BatchBase {
     int table_cap_items = 0;
     int total_patches = 0, total_tiles = 0;
     int maxP0 = 1, maxP1 = 1;
-    int chunk = 256, block = 256;
+    int chunk = 256, block = 256, tile_preset = 0;
     int grid_particles = 1, grid_maxwell = 1, grid_rebin = 1;
     Timing own_timing;
 

@@ -39,7 +39,7 @@ def test_every_declared_symbol_is_exported(lib):
 def _desc(**kw):
     d = dict(ndim=2, precision=32, n=(64, 64, 1), d=(0.1, 0.1, 1.0), dt=0.05, patch=(16, 16, 1),
              periodic=(1, 1, 1), q=-1.0, m=1.0, capacity_factor=0.0, min_capacity=0, chunk=0,
-             block=0)
+             block=0, field_tile=0, lane_stride=0)
     d.update(kw)
     s = _capi.SimDesc()
     s.ndim, s.precision = d["ndim"], d["precision"]
@@ -49,8 +49,9 @@ def _desc(**kw):
     s.patch = (C.c_int32 * 3)(*d["patch"])
     s.periodic = (C.c_int32 * 3)(*d["periodic"])
     s.q, s.m = d["q"], d["m"]
-    s.capacity_factor, s.min_capacity, s.chunk, s.block = (
-        d["capacity_factor"], d["min_capacity"], d["chunk"], d["block"])
+    s.capacity_factor, s.min_capacity, s.chunk, s.block, s.field_tile, s.lane_stride = (
+        d["capacity_factor"], d["min_capacity"], d["chunk"], d["block"], d["field_tile"],
+        d["lane_stride"])
     return s
 
 
@@ -64,6 +65,9 @@ def _desc(**kw):
     (dict(m=0.0), -1),
     (dict(capacity_factor=0.5), -1),
     (dict(block=128), -1),
+    (dict(field_tile=9), -1),
+    (dict(lane_stride=65), -1),
+    (dict(n=(2, 64, 1), patch=(2, 16, 1)), -1),  # fewer than 4 cells
 ])
 def test_bad_descriptors_fail_before_device_work(lib, bad, code):
     h = C.c_void_p()

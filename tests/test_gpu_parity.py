@@ -42,6 +42,11 @@ def test_uniform_fp64_ten_steps_match_oracle(c1):
         assert np.abs(gu[a] - ou[a]).max() < 1e-12
     d = g.diag()
     assert d["step"] == 10 and d["particles"] == c1["w"].size
+    # energies of the last step: field energy of E^9, B^9 and K^9
+    U, K, pushed = g.history(9, 1)
+    Uo, Ko = o.energy()
+    assert abs(U[0] - Uo) <= 1e-10 * abs(Uo) and abs(K[0] - Ko) <= 1e-12 * abs(Ko)
+    assert pushed[0] == c1["w"].size
 
 
 def test_uniform_fp32_one_step_matches_oracle(c1):
