@@ -32,22 +32,15 @@ constexpr int kRB = 256;  // threads per re-binning workgroup
 constexpr int kNW = kRB / 64;
 constexpr int kKeys = kNDir2 + 1;  // 9 direction keys + removed
 
-// Canonical key of each direction of patch p: the smallest direction that
-// reaches the same neighbour; -1 when the neighbour is p itself (the particle
-// stays); kNDir2 when the direction leaves an open face (removed).
-template <typename T>
-__device__ void direction_keys(const SimDev<T> &S, int p, int *key)
+// The neighbour table of a simulation (built once on the host from the patch
+// grid) holds per patch: the canonical key of each of the 9 directions (the
+// smallest direction reaching the same neighbour; -1 when the neighbour is the
+// patch itself, i.e. the particle stays; kNDir2 when it leaves an open face),
+// then the number of distinct source patches, the sources in ascending id and
+// the key under which each source stages the particles it sends here.
+__device__ __forceinline__ const int32_t *nb_row(const int32_t *nbt, int p)
 {
-    int nb[kNDir2];
-    for (int d = 0; d < kNDir2; ++d) nb[d] = neighbour2(S, p, d);
-    for (int d = 0; d < kNDir2; ++d) {
-        if (d == kStay2 || nb[d] == p) { key[d] = -1; continue; }
-        if (nb[d] < 0) { key[d] = kNDir2; continue; }
-        int k = d;
-        for (int e = 0; e < d; ++e)
-            if (nb[e] == nb[d] && e != kStay2) { k = e; break; }
-        key[d] = k;
-    }
+    return nbt + (int64_t)p * kNbStride;
 }
 
 __device__ __forceinline__ int code_key(const int *key, uint8_t c)
@@ -95,7 +88,7 @@ __global__ __launch_bounds__(kRB) void k_rebin_count(const SimDev<T> *__restrict
         const int p = gp - patch_prefix[s];
         const int n = S.count[p];
         const int64_t base = S.off[p];
-        if (tid == 0) direction_keys(S, p, s_key);
+        if (tid < kNDir2) s_key[tid] = nb_row(S.nbt, p)[tid];
         if (tid < kKeys) s_cnt[tid] = 0;
         if (tid <= kKeys) s_run[tid] = 0;
         __syncthreads();
@@ -151,33 +144,6 @@ __global__ __launch_bounds__(kRB) void k_rebin_count(const SimDev<T> *__restrict
     }
 }
 
-// Distinct source patches of destination q in ascending id, with the key
-// under which each source staged its particles for q.
-template <typename T>
-__device__ int sources_of(const SimDev<T> &S, int q, int *src, int *skey)
-{
-    int ns = 0;
-    for (int d = 0; d < kNDir2; ++d) {
-        if (d == kStay2) continue;
-        const int s = neighbour2(S, q, d);
-        if (s < 0 || s == q) continue;
-        bool seen = false;
-        for (int i = 0; i < ns; ++i) seen |= src[i] == s;
-        if (!seen) src[ns++] = s;
-    }
-    for (int i = 1; i < ns; ++i)  // insertion sort, at most 8 entries
-        for (int j = i; j > 0 && src[j - 1] > src[j]; --j) {
-            const int t = src[j]; src[j] = src[j - 1]; src[j - 1] = t;
-        }
-    for (int i = 0; i < ns; ++i) {
-        int k = -1;
-        for (int d = 0; d < kNDir2 && k < 0; ++d)
-            if (d != kStay2 && neighbour2(S, src[i], d) == q) k = d;
-        skey[i] = k;
-    }
-    return ns;
-}
-
 template <typename T>
 __global__ __launch_bounds__(256) void k_rebin_check(const SimDev<T> *__restrict__ sims, int nsims,
                                                      const int *__restrict__ patch_prefix, int total)
@@ -188,10 +154,10 @@ __global__ __launch_bounds__(256) void k_rebin_check(const SimDev<T> *__restrict
     const SimDev<T> &S = sims[s];
     if (!S.st->active) return;
     const int q = gp - patch_prefix[s];
-    int src[8], skey[8];
-    const int ns = sources_of(S, q, src, skey);
+    const int32_t *row = nb_row(S.nbt, q);
+    const int ns = row[kNDir2];
     int A = 0;
-    for (int i = 0; i < ns; ++i) A += S.kcnt[src[i] * kNDir2 + skey[i]];
+    for (int i = 0; i < ns; ++i) A += S.kcnt[row[kNDir2 + 1 + i] * kNDir2 + row[kNDir2 + 9 + i]];
     const int n = S.count[q], L = S.nleave[q];
     const int np = n - L + A;
     // vacated slots below the new count (the list is ascending)
@@ -210,7 +176,7 @@ __global__ __launch_bounds__(256) void k_rebin_check(const SimDev<T> *__restrict
 template <typename T>
 __global__ __launch_bounds__(kRB) void k_rebin_scatter(const SimDev<T> *__restrict__ sims, int nsims,
                                                        const int *__restrict__ patch_prefix,
-                                                       int total, int finalize)
+                                                       int total)
 {
     __shared__ int s_src[8], s_skey[8], s_scnt[8];
     __shared__ int64_t s_sbase[8];
@@ -228,21 +194,26 @@ __global__ __launch_bounds__(kRB) void k_rebin_scatter(const SimDev<T> *__restri
         const int q = gp - patch_prefix[s];
         const int n = S.count[q], np = S.newcount[q], nH = S.nhole[q], A = S.narrive[q];
         const int64_t base = S.off[q];
-        if (tid == 0) {
-            int src[8], skey[8];
-            const int ns = sources_of(S, q, src, skey);
-            for (int i = 0; i < ns; ++i) {
-                const int sp = src[i], k = skey[i];
+        const int32_t *row = nb_row(S.nbt, q);
+        if (tid < 8) {
+            // one thread per source: its count and staging base for this patch
+            const int ns = row[kNDir2];
+            if (tid < ns) {
+                const int sp = row[kNDir2 + 1 + tid], k = row[kNDir2 + 9 + tid];
                 int koff = 0;
                 for (int e = 0; e < k; ++e) koff += S.kcnt[sp * kNDir2 + e];
-                s_src[i] = sp;
-                s_skey[i] = k;
-                s_scnt[i] = S.kcnt[sp * kNDir2 + k];
-                s_sbase[i] = S.off[sp] + koff;
+                s_src[tid] = sp;
+                s_skey[tid] = k;
+                s_scnt[tid] = S.kcnt[sp * kNDir2 + k];
+                s_sbase[tid] = S.off[sp] + koff;
             }
-            s_ns = ns;
-            direction_keys(S, q, s_key);
-            s_run = 0;
+            if (tid == 0) {
+                s_ns = ns;
+                s_run = 0;
+                if (q == 0) S.st->rebinned = 1u;
+            }
+        } else if (tid < 8 + kNDir2) {
+            s_key[tid - 8] = row[tid - 8];
         }
         __syncthreads();
         // arrivals: holes first, then appended from slot n
@@ -293,113 +264,168 @@ __global__ __launch_bounds__(kRB) void k_rebin_scatter(const SimDev<T> *__restri
     }
 }
 
-// Close the step of every active simulation whose re-binning was applied:
-// reduce the per-tile field energies and per-patch kinetic energies, record
-// the history entry, advance the step counter.  One workgroup per simulation.
-template <typename T>
-__global__ __launch_bounds__(256) void k_step_end(const SimDev<T> *__restrict__ sims,
-                                                  const int *__restrict__ tile_prefix)
-{
-    __shared__ double s_u[4], s_k[4];
-    const int s = blockIdx.x, tid = threadIdx.x;
-    const SimDev<T> &S = sims[s];
-    SimState *st = S.st;
-    if (!st->active || (st->flags & kFlagPending)) return;
-    const int nt = tile_prefix[s + 1] - tile_prefix[s];
-    double u = 0.0, k = 0.0;
-    for (int i = tid; i < nt; i += 256) u += S.upart[i];
-    for (int i = tid; i < S.npatch; i += 256) {
-        k += S.kpart[i];
-        S.kpart[i] = 0.0;
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        u += __shfl_xor(u, o, 64);
-        k += __shfl_xor(k, o, 64);
-    }
-    if ((tid & 63) == 0) { s_u[tid >> 6] = u; s_k[tid >> 6] = k; }
-    __syncthreads();
-    if (tid == 0) {
-        const double U = s_u[0] + s_u[1] + s_u[2] + s_u[3];
-        const double K = s_k[0] + s_k[1] + s_k[2] + s_k[3];
-        const int64_t n = st->step;
-        double *h = S.hist + (n % kHistLen) * 4;
-        h[0] = U;
-        h[1] = K;
-        h[2] = (double)st->pushed;
-        h[3] = (double)st->removed;
-        st->U = U;
-        st->K = K;
-        st->step = n + 1;
-        if (st->steps_left > 0) st->steps_left -= 1;
-        st->active = 0;
-    }
-}
-
-// ---- work queue ---------------------------------------------------------------
+// ---- step close and work queue --------------------------------------------------
+//
+// One workgroup.  Phase A closes the step of every simulation whose
+// re-binning was applied (one wave per simulation: reduce the per-tile field
+// energies and per-patch kinetic energies, write the history entry, advance
+// the step counter and spend one step of its budget) and decides which
+// simulations take part in the next step.  Phase B builds the work queue of
+// that step: every patch is cut into chunks of at most `chunk` particles and
+// the chunks are placed in order of decreasing size, so that persistent
+// workgroups pulling from the queue start with the largest items (the
+// single-GPU counterpart of evening out load by exchanging patches).
 
 constexpr int kQB = 1024;   // threads of the single queue workgroup
+constexpr int kQW = kQB / 64;
 constexpr int kBuckets = 1024;
 
 template <typename T>
-__global__ __launch_bounds__(kQB) void k_queue(const SimDev<T> *__restrict__ sims, QueueArgs qa)
+__global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict__ sims,
+                                                     QueueArgs qa)
 {
     __shared__ int s_hist[kBuckets];
     __shared__ uint8_t s_act[kMaxBatch];
     __shared__ int s_pushed[kMaxBatch];
-    __shared__ int s_wsum[kQB / 64];
-    const int tid = threadIdx.x;
+    __shared__ int s_wsum[kQW];
+    __shared__ double s_red[kQW][2];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int nsims = qa.nsims;
+
+    // ---- phase A: close steps, decide participation -------------------------------
+    // G waves work on one simulation (all 16 for a single simulation, one each
+    // for batches of 16 or more); rounds cover the batch.
+    int G = kQW;
+    while (G > 1 && G * nsims > kQW) G >>= 1;
+    const int per_round = kQW / G;
+    const int sub = wave % G;
+    for (int r0 = 0; r0 < nsims; r0 += per_round) {
+        const int s = r0 + wave / G;
+        bool closing = false;
+        int64_t left = 0;
+        uint32_t flags = 0;
+        if (s < nsims) {
+            const SimDev<T> &S = sims[s];
+            SimState *st = S.st;
+            flags = st->flags;
+            left = st->steps_left;
+            closing = st->active && st->rebinned && !(flags & kFlagPending);
+            double u = 0.0, k = 0.0;
+            if (closing) {
+                const int nt = qa.tile_prefix[s + 1] - qa.tile_prefix[s];
+                for (int i = sub * 64 + lane; i < nt; i += G * 64) u += S.upart[i];
+                for (int i = sub * 64 + lane; i < S.npatch; i += G * 64) {
+                    k += S.kpart[i];
+                    S.kpart[i] = 0.0;
+                }
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    u += __shfl_xor(u, o, 64);
+                    k += __shfl_xor(k, o, 64);
+                }
+            }
+            if (lane == 0) { s_red[wave][0] = u; s_red[wave][1] = k; }
+        }
+        __syncthreads();
+        if (s < nsims && sub == 0 && lane == 0) {
+            const SimDev<T> &S = sims[s];
+            SimState *st = S.st;
+            if (closing) {
+                double u = 0.0, k = 0.0;
+                for (int w = wave; w < wave + G; ++w) { u += s_red[w][0]; k += s_red[w][1]; }
+                if (left > 0) left -= 1;
+                const int64_t n = st->step;
+                double *h = S.hist + (n % kHistLen) * 4;
+                h[0] = u;
+                h[1] = k;
+                h[2] = (double)st->pushed;
+                h[3] = (double)st->removed;
+                st->U = u;
+                st->K = k;
+                st->step = n + 1;
+                st->steps_left = left;
+                st->rebinned = 0u;
+            }
+            const uint32_t act = left > 0 && !(flags & (kFlagPending | kFlagErrMask));
+            st->active = act;
+            s_act[s] = (uint8_t)act;
+            s_pushed[s] = 0;
+        }
+        __syncthreads();
+    }
+    for (int b = tid; b < kBuckets; b += kQB) s_hist[b] = 0;
+    __syncthreads();
+
+    // ---- phase B: chunk histogram (bucket 0 = largest chunks) ------------------------
     const int total = qa.patch_prefix[nsims];
     const int chunk = qa.chunk;
-    for (int b = tid; b < kBuckets; b += kQB) s_hist[b] = 0;
-    for (int s = tid; s < nsims; s += kQB) {
-        SimState *st = sims[s].st;
-        const uint32_t act = st->steps_left > 0 && !(st->flags & (kFlagPending | kFlagErrMask));
-        st->active = act;
-        s_act[s] = (uint8_t)act;
-        s_pushed[s] = 0;
-    }
-    __syncthreads();
-    // bucket of a chunk of c particles: larger chunks first
     auto bucket = [&](int c) { return kBuckets - 1 - (int)(((int64_t)(c - 1) * kBuckets) / chunk); };
-    for (int gp = tid; gp < total; gp += kQB) {
-        const int s = find_sim(qa.patch_prefix, nsims, gp);
-        if (!s_act[s]) continue;
-        const int n = sims[s].count[gp - qa.patch_prefix[s]];
-        if (n) atomicAdd(&s_pushed[s], n);
-        for (int c0 = 0; c0 < n; c0 += chunk) atomicAdd(&s_hist[bucket(min(chunk, n - c0))], 1);
+    // lanes adding to one bucket are combined into a single LDS atomic
+    auto aggregated_add = [&](bool has, int b, int *counter_base, bool want_slot) {
+        uint64_t todo = __ballot(has);
+        int slot = -1;
+        while (todo) {
+            const int leader = __ffsll((unsigned long long)todo) - 1;
+            const int bl = __shfl(b, leader, 64);
+            const uint64_t same = __ballot(has && b == bl);
+            int base = 0;
+            if (lane == leader) base = atomicAdd(&counter_base[bl], __popcll(same));
+            if (want_slot) {
+                base = __shfl(base, leader, 64);
+                if (has && b == bl) slot = base + __popcll(same & lt);
+            }
+            todo &= ~same;
+        }
+        return slot;
+    };
+    for (int g0 = 0; g0 < total; g0 += kQB) {
+        const int gp = g0 + tid;
+        int s = 0, n = 0;
+        if (gp < total) {
+            s = find_sim(qa.patch_prefix, nsims, gp);
+            if (s_act[s]) n = sims[s].count[gp - qa.patch_prefix[s]];
+            if (n) atomicAdd(&s_pushed[s], n);
+        }
+        for (int c0 = 0; __any(c0 < n); c0 += chunk) {
+            const bool has = c0 < n;
+            aggregated_add(has, has ? bucket(min(chunk, n - c0)) : 0, s_hist, false);
+        }
     }
     __syncthreads();
     for (int s = tid; s < nsims; s += kQB)
         if (s_act[s]) sims[s].st->pushed = s_pushed[s];
     // exclusive scan of the histogram (one bucket per thread)
-    int v = tid < kBuckets ? s_hist[tid] : 0;
+    const int v = s_hist[tid];
     int incl = v;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
         const int y = __shfl_up(incl, o, 64);
-        if ((tid & 63) >= o) incl += y;
+        if (lane >= o) incl += y;
     }
-    if ((tid & 63) == 63) s_wsum[tid >> 6] = incl;
+    if (lane == 63) s_wsum[wave] = incl;
     __syncthreads();
     int woff = 0;
-    for (int w = 0; w < (tid >> 6); ++w) woff += s_wsum[w];
-    const int excl = woff + incl - v;
-    __syncthreads();
-    if (tid < kBuckets) s_hist[tid] = excl;
+    for (int w = 0; w < wave; ++w) woff += s_wsum[w];
     int ntot = 0;
-    for (int w = 0; w < kQB / 64; ++w) ntot += s_wsum[w];
+    for (int w = 0; w < kQW; ++w) ntot += s_wsum[w];
     __syncthreads();
-    for (int gp = tid; gp < total; gp += kQB) {
-        const int s = find_sim(qa.patch_prefix, nsims, gp);
-        if (!s_act[s]) continue;
-        const int p = gp - qa.patch_prefix[s];
-        const int n = sims[s].count[p];
-        for (int c0 = 0; c0 < n; c0 += chunk) {
-            const int c = min(chunk, n - c0);
-            const int pos = atomicAdd(&s_hist[bucket(c)], 1);
-            if (pos < qa.max_items) qa.items[pos] = make_int4(s, p, c0, c);
+    s_hist[tid] = woff + incl - v;
+    __syncthreads();
+    // ---- phase B: placement ------------------------------------------------------
+    for (int g0 = 0; g0 < total; g0 += kQB) {
+        const int gp = g0 + tid;
+        int s = 0, p = 0, n = 0;
+        if (gp < total) {
+            s = find_sim(qa.patch_prefix, nsims, gp);
+            p = gp - qa.patch_prefix[s];
+            if (s_act[s]) n = sims[s].count[p];
+        }
+        for (int c0 = 0; __any(c0 < n); c0 += chunk) {
+            const bool has = c0 < n;
+            const int c = has ? min(chunk, n - c0) : 0;
+            const int pos = aggregated_add(has, has ? bucket(c) : 0, s_hist, true);
+            if (has && pos < qa.max_items) qa.items[pos] = make_int4(s, p, c0, c);
         }
     }
     if (tid == 0) {
@@ -466,23 +492,21 @@ __global__ void k_scatter_codes(const uint8_t *__restrict__ packed,
 }  // namespace
 
 template <typename T>
-void launch_queue(const SimDev<T> *sims, const QueueArgs &q, hipStream_t st)
+void launch_close_queue(const SimDev<T> *sims, const QueueArgs &q, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_queue<T>), dim3(1), dim3(kQB), 0, st, sims, q);
+    hipLaunchKernelGGL((k_close_queue<T>), dim3(1), dim3(kQB), 0, st, sims, q);
 }
 
 template <typename T>
 void launch_rebin(const SimDev<T> *sims, int nsims, const int *patch_prefix, int total_patches,
-                  int grid, bool finalize, const int *tile_prefix, hipStream_t st)
+                  int grid, hipStream_t st)
 {
     hipLaunchKernelGGL((k_rebin_count<T>), dim3(grid), dim3(kRB), 0, st, sims, nsims, patch_prefix,
                        total_patches);
     hipLaunchKernelGGL((k_rebin_check<T>), dim3((total_patches + 255) / 256), dim3(256), 0, st, sims,
                        nsims, patch_prefix, total_patches);
     hipLaunchKernelGGL((k_rebin_scatter<T>), dim3(grid), dim3(kRB), 0, st, sims, nsims,
-                       patch_prefix, total_patches, finalize ? 1 : 0);
-    if (finalize)
-        hipLaunchKernelGGL((k_step_end<T>), dim3(nsims), dim3(256), 0, st, sims, tile_prefix);
+                       patch_prefix, total_patches);
 }
 
 template <typename T>
@@ -505,9 +529,8 @@ void launch_scatter_codes(const uint8_t *packed, const int64_t *packed_off, cons
 }
 
 #define PIC_INST(T)                                                                              \
-    template void launch_queue<T>(const SimDev<T> *, const QueueArgs &, hipStream_t);            \
-    template void launch_rebin<T>(const SimDev<T> *, int, const int *, int, int, bool,           \
-                                  const int *, hipStream_t);                                     \
+    template void launch_close_queue<T>(const SimDev<T> *, const QueueArgs &, hipStream_t);      \
+    template void launch_rebin<T>(const SimDev<T> *, int, const int *, int, int, hipStream_t);   \
     template void launch_relayout<T>(const SimDev<T> *, const SimDev<T> *, int, hipStream_t);    \
     template void launch_rho<T>(const SimDev<T> *, int, double *, hipStream_t);
 PIC_INST(float)

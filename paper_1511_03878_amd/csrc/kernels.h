@@ -13,6 +13,7 @@ using Item = int4;
 struct QueueArgs {
     int nsims;
     const int *patch_prefix;  // nsims + 1 entries (global patch numbering)
+    const int *tile_prefix;   // nsims + 1 entries (Yee tiles of each simulation)
     Item *items;
     int *nitems;
     int *head;
@@ -20,8 +21,10 @@ struct QueueArgs {
     int chunk;                // max particles per item
 };
 
+// Close the steps whose re-binning was applied (energy reduction, history,
+// step counter, budget) and build the work queue of the next step.
 template <typename T>
-void launch_queue(const SimDev<T> *sims, const QueueArgs &q, hipStream_t st);
+void launch_close_queue(const SimDev<T> *sims, const QueueArgs &q, hipStream_t st);
 
 // Persistent particle kernel: gather, Boris, move, classify, Esirkepov deposit.
 template <typename T>
@@ -39,12 +42,9 @@ template <typename T>
 void maxwell_tile(int preset, int &tx, int &ty);
 
 // Re-binning: count and stage leavers; check capacity; scatter.
-// finalize: also close the step (energy reduction over the per-tile and
-// per-patch partials, history, step counter); tile_prefix gives the Yee
-// tile count of each simulation.
 template <typename T>
 void launch_rebin(const SimDev<T> *sims, int nsims, const int *patch_prefix, int total_patches,
-                  int grid, bool finalize, const int *tile_prefix, hipStream_t st);
+                  int grid, hipStream_t st);
 
 // Copy particles into a new per-patch layout (capacity growth).
 template <typename T>

@@ -23,6 +23,7 @@ constexpr int kHistLen = 4096;     // energy-history ring length
 constexpr int kMaxBatch = 2048;    // simulations per batch
 constexpr int kNDir2 = 9;          // neighbour directions in 2-D (4 = stay)
 constexpr int kStay2 = 4;
+constexpr int kNbStride = 26;      // neighbour-table entries per patch (9 keys, count, 8 sources, 8 keys)
 constexpr uint8_t kRemoved = 255;
 
 // sticky state flags
@@ -39,6 +40,8 @@ struct SimState {
     int64_t removed;
     int64_t pushed;      // particles pushed in the step in flight
     double U, K;         // energies of the last completed step
+    uint32_t rebinned;   // the step in flight has applied its re-binning
+    uint32_t pad;
 };
 
 template <typename T>
@@ -74,6 +77,7 @@ struct SimDev {
     int64_t laser_steps;
     SimState *st;
     double *hist;      // [kHistLen][4]: U, K, pushed, removed
+    const int32_t *nbt; // neighbour table, kNbStride entries per patch
     double *upart;     // per Yee tile: field energy of the step in flight
     double *kpart;     // per patch: kinetic energy of the step in flight
 };

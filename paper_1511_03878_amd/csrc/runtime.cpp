@@ -146,6 +146,7 @@ SimImpl<T>::SimImpl(const PicSimDesc &d, const PicAllocator *a, hipStream_t s)
         hipcheck(hipMemsetAsync(counts_d, 0, sizeof(int32_t) * npatch, stream), "memset counts");
         int pre[2] = {0, npatch};
         hipcheck(hipMemcpyAsync(prefix_d, pre, sizeof(pre), hipMemcpyHostToDevice, stream), "prefix");
+        build_neighbour_table();
         // an empty particle layout so that every kernel sees valid pointers
         std::vector<int32_t> cnt0(npatch, 0);
         layout_particles(cnt0);
@@ -190,6 +191,56 @@ void SimImpl<T>::step(int64_t nsteps)
     solo->run(0, true);
 }
 
+// Patch topology used by the re-binning (static for a grid): per patch the
+// canonical key of each direction, and the distinct source patches in
+// ascending id with the key each of them stages its particles under.
+template <typename T>
+void SimImpl<T>::build_neighbour_table()
+{
+    auto nbr = [&](int p, int d) {
+        int qx = p % np[0] + d % 3 - 1, qy = p / np[0] + d / 3 - 1;
+        if (qx < 0 || qx >= np[0]) {
+            if (!periodic[0]) return -1;
+            qx = (qx + np[0]) % np[0];
+        }
+        if (qy < 0 || qy >= np[1]) {
+            if (!periodic[1]) return -1;
+            qy = (qy + np[1]) % np[1];
+        }
+        return qx + np[0] * qy;
+    };
+    auto key_of = [&](int p, int target) {
+        for (int d = 0; d < kNDir2; ++d)
+            if (d != kStay2 && nbr(p, d) == target) return d;
+        return -1;
+    };
+    std::vector<int32_t> t((size_t)npatch * kNbStride, -1);
+    for (int p = 0; p < npatch; ++p) {
+        int32_t *row = &t[(size_t)p * kNbStride];
+        int nb[kNDir2];
+        for (int d = 0; d < kNDir2; ++d) nb[d] = nbr(p, d);
+        for (int d = 0; d < kNDir2; ++d) {
+            if (d == kStay2 || nb[d] == p) row[d] = -1;
+            else if (nb[d] < 0) row[d] = kNDir2;
+            else row[d] = key_of(p, nb[d]);
+        }
+        std::vector<int> src;
+        for (int d = 0; d < kNDir2; ++d)
+            if (d != kStay2 && nb[d] >= 0 && nb[d] != p &&
+                std::find(src.begin(), src.end(), nb[d]) == src.end())
+                src.push_back(nb[d]);
+        std::sort(src.begin(), src.end());
+        row[kNDir2] = (int32_t)src.size();
+        for (size_t i = 0; i < src.size(); ++i) {
+            row[kNDir2 + 1 + i] = src[i];
+            row[kNDir2 + 9 + i] = key_of(src[i], p);
+        }
+    }
+    nbt_d = (int32_t *)alloc.get(sizeof(int32_t) * t.size());
+    hipcheck(hipMemcpyAsync(nbt_d, t.data(), sizeof(int32_t) * t.size(), hipMemcpyHostToDevice, stream), "neighbour table");
+    hipcheck(hipStreamSynchronize(stream), "sync");
+}
+
 template <typename T>
 void SimImpl<T>::free_particles()
 {
@@ -214,6 +265,7 @@ void SimImpl<T>::release()
     alloc.put(nhole_d);
     alloc.put(prefix_d);
     alloc.put(tprefix_d);
+    alloc.put(nbt_d);
     alloc.put(upart);
     alloc.put(kpart);
     alloc.put(view_d);
@@ -322,7 +374,7 @@ void SimImpl<T>::refresh_view()
     V.cap = cap_d; V.off = off_d; V.count = counts_d; V.newcount = newcount_d;
     V.kcnt = kcnt_d; V.nleave = nleave_d; V.narrive = narrive_d; V.nhole = nhole_d;
     V.laser_ey = laser_ey; V.laser_ez = laser_ez; V.laser_steps = laser_steps;
-    V.st = st; V.hist = hist; V.upart = upart; V.kpart = kpart;
+    V.st = st; V.hist = hist; V.upart = upart; V.kpart = kpart; V.nbt = nbt_d;
     hipcheck(hipMemcpyAsync(view_d, &v, sizeof(v), hipMemcpyHostToDevice, stream), "view upload");
     ++layout_version;
 }
@@ -568,9 +620,10 @@ void SimImpl<T>::grow_capacity()
 }
 
 // Re-run the re-binning of the step whose scatter was skipped by the
-// capacity check, after growing capacities.
+// capacity check, after growing capacities.  The step is then closed by the
+// next close/queue pass of the batch that runs the simulation.
 template <typename T>
-void SimImpl<T>::recover_pending(bool finalize)
+void SimImpl<T>::recover_pending()
 {
     for (int attempt = 0; attempt < 4; ++attempt) {
         grow_capacity();
@@ -578,17 +631,10 @@ void SimImpl<T>::recover_pending(bool finalize)
         s.flags &= ~kFlagPending;
         s.active = 1;
         hipcheck(hipMemcpyAsync(&st->flags, &s.flags, sizeof(uint32_t) * 2, hipMemcpyHostToDevice, stream), "flags");
-        launch_rebin<T>(view_d, 1, prefix_d, npatch, std::min(npatch, 4 * cu_count()), finalize, tprefix_d, stream);
+        launch_rebin<T>(view_d, 1, prefix_d, npatch, std::min(npatch, 4 * cu_count()), stream);
         hipcheck(hipGetLastError(), "rebin launch");
         s = read_state();
-        if (!(s.flags & kFlagPending)) {
-            if (!finalize) {
-                uint32_t zero = 0;
-                hipcheck(hipMemcpyAsync(&st->active, &zero, sizeof(zero), hipMemcpyHostToDevice, stream), "active");
-                hipcheck(hipStreamSynchronize(stream), "sync");
-            }
-            return;
-        }
+        if (!(s.flags & kFlagPending)) return;
     }
     throw Error(PIC_EOVERFLOW, "patch capacity could not be grown enough");
 }
@@ -613,17 +659,16 @@ void SimImpl<T>::rebin_codes(const uint8_t *codes_h, size_t cnt)
     SimState s = read_state();
     s.active = 1;
     hipcheck(hipMemcpyAsync(&st->active, &s.active, sizeof(uint32_t), hipMemcpyHostToDevice, stream), "active");
-    launch_rebin<T>(view_d, 1, prefix_d, npatch, std::min(npatch, 4 * cu_count()), false, tprefix_d, stream);
+    launch_rebin<T>(view_d, 1, prefix_d, npatch, std::min(npatch, 4 * cu_count()), stream);
     hipcheck(hipGetLastError(), "rebin launch");
     s = read_state();
     alloc.put(pk);
     alloc.put(po);
-    if (s.flags & kFlagPending) {
-        recover_pending(false);
-        return;
-    }
-    uint32_t zero = 0;
-    hipcheck(hipMemcpyAsync(&st->active, &zero, sizeof(zero), hipMemcpyHostToDevice, stream), "active");
+    if (s.flags & kFlagPending) recover_pending();
+    // only the re-binning was asked for: the step is not closed
+    const uint32_t zero[1] = {0};
+    hipcheck(hipMemcpyAsync(&st->active, zero, sizeof(uint32_t), hipMemcpyHostToDevice, stream), "active");
+    hipcheck(hipMemcpyAsync(&st->rebinned, zero, sizeof(uint32_t), hipMemcpyHostToDevice, stream), "rebinned");
     hipcheck(hipStreamSynchronize(stream), "sync");
 }
 
@@ -684,7 +729,7 @@ void Timing::collect()
     events.clear();
 }
 
-const char *const Timing::names[kKinds] = {"queue", "particles", "maxwell", "rebin"};
+const char *const Timing::names[kKinds] = {"close_queue", "particles", "maxwell", "rebin"};
 
 // ---------------------------------------------------------------------------
 // BatchImpl
@@ -837,30 +882,47 @@ void BatchImpl<T>::refresh_member_views()
 }
 
 template <typename T>
-void BatchImpl<T>::launch_one_step()
+QueueArgs BatchImpl<T>::queue_args() const
 {
     QueueArgs qa;
     qa.nsims = (int)members.size();
     qa.patch_prefix = patch_prefix_d;
+    qa.tile_prefix = tile_prefix_d;
     qa.items = items_d;
     qa.nitems = nitems_d;
     qa.head = head_d;
     qa.max_items = table_cap_items;
     qa.chunk = chunk;
+    return qa;
+}
+
+// Close whatever steps are complete and queue the next one.
+template <typename T>
+void BatchImpl<T>::launch_close_queue_pass()
+{
     Timing &tm = timing();
     tm.record(stream, 0, true);
-    launch_queue<T>(sims_d, qa, stream);
+    launch_close_queue<T>(sims_d, queue_args(), stream);
     tm.record(stream, 0, false);
+    hipcheck(hipGetLastError(), "queue launch");
+}
+
+// One step pass: particles, Yee, re-binning, then close + next queue.
+template <typename T>
+void BatchImpl<T>::launch_one_step()
+{
+    const int ns = (int)members.size();
+    Timing &tm = timing();
     tm.record(stream, 1, true);
     launch_particles<T>(sims_d, items_d, nitems_d, head_d, grid_particles, block, maxP0, maxP1, stream);
     tm.record(stream, 1, false);
     tm.record(stream, 2, true);
-    launch_maxwell<T>(sims_d, qa.nsims, tile_prefix_d, total_tiles, grid_maxwell, tile_preset, stream);
+    launch_maxwell<T>(sims_d, ns, tile_prefix_d, total_tiles, grid_maxwell, tile_preset, stream);
     tm.record(stream, 2, false);
     tm.record(stream, 3, true);
-    launch_rebin<T>(sims_d, qa.nsims, patch_prefix_d, total_patches, grid_rebin, true, tile_prefix_d, stream);
+    launch_rebin<T>(sims_d, ns, patch_prefix_d, total_patches, grid_rebin, stream);
     tm.record(stream, 3, false);
-    hipcheck(hipGetLastError(), "step launch");
+    launch_close_queue_pass();
 }
 
 template <typename T>
@@ -887,6 +949,7 @@ int BatchImpl<T>::run(int64_t max_steps, bool until_done)
     int64_t launched = 0;
     const int64_t K = 32;
     int finished = 0;
+    launch_close_queue_pass();  // queue of the first step
     for (;;) {
         // never launch more passes than the largest budget still needs
         int64_t todo = std::min<int64_t>(K, budget);
@@ -902,17 +965,29 @@ int BatchImpl<T>::run(int64_t max_steps, bool until_done)
             SimImpl<T> *m = members[i];
             SimState s = m->read_state();
             if (s.flags & kFlagPending) {
-                m->recover_pending(true);
+                m->recover_pending();
                 recovered = true;
-                s = m->read_state();
             }
             if (s.steps_left > 0 && !(s.flags & kFlagErrMask)) {
                 any_left = true;
                 budget = std::max(budget, s.steps_left);
             }
         }
-        if (recovered) refresh_member_views();
-        if (dirty) build_tables();
+        if (recovered) {
+            refresh_member_views();
+            if (dirty) build_tables();
+            // close the recovered steps and queue the next step for everyone
+            launch_close_queue_pass();
+            budget = 0;
+            any_left = false;
+            for (auto *m : members) {
+                SimState s = m->read_state();
+                if (s.steps_left > 0 && !(s.flags & kFlagErrMask)) {
+                    any_left = true;
+                    budget = std::max(budget, s.steps_left);
+                }
+            }
+        }
         if (!any_left) break;
         if (!until_done && launched >= max_steps) break;
     }

@@ -89,6 +89,7 @@ struct SimImpl : SimBase {
     int32_t *counts_d = nullptr, *newcount_d = nullptr, *kcnt_d = nullptr, *nleave_d = nullptr;
     int32_t *narrive_d = nullptr, *nhole_d = nullptr;
     int *prefix_d = nullptr, *tprefix_d = nullptr;
+    int32_t *nbt_d = nullptr;
     double *upart = nullptr, *kpart = nullptr;
     int64_t max_tiles = 0;
     T *laser_ey = nullptr, *laser_ez = nullptr;
@@ -118,7 +119,8 @@ struct SimImpl : SimBase {
     std::vector<void *> layout_particles(const std::vector<int32_t> &need);
     void refresh_view();
     void grow_capacity();
-    void recover_pending(bool finalize);
+    void recover_pending();
+    void build_neighbour_table();
     int max_items(int chunk);
     void check_free();
 
@@ -169,6 +171,8 @@ struct BatchImpl : BatchBase {
     void remove(SimImpl<T> *s);
     void build_tables();
     void refresh_member_views();
+    QueueArgs queue_args() const;
+    void launch_close_queue_pass();
     void launch_one_step();
     Timing &timing();
     int run(int64_t max_steps, bool until_done);
