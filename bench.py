@@ -49,6 +49,30 @@ def _workload(name, steps):
     return wl, desc
 
 
+def _kernel_source_sha():
+    """Hash of the sources the particle kernel is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("k_particles.hip", "pic_dev.h", "kernels.h"):
+        with open(os.path.join(ROOT, "paper_1511_03878_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _measured_traffic(precision, workload):
+    """HBM bytes per launch of the particle kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE measurement, if it was taken on the current
+    kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f).get(f"k_particles2d/{workload}/f{precision}")
+    if not rec or rec.get("source_sha") != _kernel_source_sha():
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
 def _cpu_baseline(name, budget_s=25.0):
     """Time the FP64 oracle (single-threaded C, as it stands) on one step of
     the same workload on this host."""
@@ -83,6 +107,9 @@ def main():
     ap.add_argument("--workload", default="lwfa")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="before the run, time a plain device copy of MIB MiB (calibrates "
+                         "rocprofv3 FETCH_SIZE / WRITE_SIZE against a known byte count)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -94,6 +121,22 @@ def main():
     from paper_1511_03878_amd.sim import Sim
 
     torch.cuda.set_device(0)
+    copy_cal = None
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, device="cuda", dtype=torch.float32)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        copy_cal = {"bytes_read": 4 * n, "bytes_written": 4 * n, "ms": ms,
+                    "GBps": 8 * n / ms / 1e6}
+        del a, b
     wl, desc = _workload(args.workload, args.steps)
     print(f"[bench] workload ready: {desc}", file=sys.stderr, flush=True)
 
@@ -127,8 +170,10 @@ def main():
         per_launch_bytes = BYTES_PER_PARTICLE_STEP[args.precision] * total / max(launches, 1)
         achieved = per_launch_bytes / avg_s / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": _measured_traffic(args.precision, args.workload),
                 "kernel": "k_particles2d",
+                "algorithmic_bytes_per_launch": per_launch_bytes,
                 "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in timing.items()}}
 
     out = {
@@ -149,6 +194,8 @@ def main():
                    "occupancy_max_end": d["occupancy_max"], "relayouts": d["relayouts"]},
         "roofline": roof,
     }
+    if copy_cal:
+        out["copy_calibration"] = copy_cal
     if not args.no_cpu:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = _cpu_baseline(args.workload)

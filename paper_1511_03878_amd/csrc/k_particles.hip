@@ -271,7 +271,9 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
 #pragma unroll
                     for (int i = 0; i < 3; ++i) {
                         acc += DSx[i] * wy;
-                        atomicAdd(&Jxt[r0 + j * jw + i], ax * acc);
+                        // window entries off both supports are exactly zero;
+                        // masked lanes cost the LDS nothing
+                        if (acc != 0.0) atomicAdd(&Jxt[r0 + j * jw + i], ax * acc);
                     }
                 }
 #pragma unroll
@@ -281,7 +283,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
 #pragma unroll
                     for (int j = 0; j < 3; ++j) {
                         acc += DSy[j] * wx;
-                        atomicAdd(&Jyt[r0 + j * jw + i], ay * acc);
+                        if (acc != 0.0) atomicAdd(&Jyt[r0 + j * jw + i], ay * acc);
                     }
                 }
 #pragma unroll
@@ -290,7 +292,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
                     for (int i = 0; i < 4; ++i) {
                         const double wz = S0x[i] * S0y[j] + 0.5 * (DSx[i] * S0y[j] + S0x[i] * DSy[j]) +
                                           DSx[i] * DSy[j] * (1.0 / 3.0);
-                        atomicAdd(&Jzt[r0 + j * jw + i], az * wz);
+                        if (wz != 0.0 && az != 0.0) atomicAdd(&Jzt[r0 + j * jw + i], az * wz);
                     }
 
                 const int sx_ = x1 < T(0) ? -1 : (x1 >= (T)P0 ? 1 : 0);
