@@ -98,6 +98,60 @@ def _cpu_baseline(name, budget_s=25.0):
                       f"{dt:.1f} s on one host core"}
 
 
+def _scan_bench(count, steps, precision, seed=None):
+    """Batched parameter scan: `count` laser-wakefield simulations of uneven
+    size stepped together in one batch, against the same simulations run one
+    at a time.  Returns aggregate particle-steps/s of both."""
+    import torch
+    from paper_1511_03878_amd import workloads as W
+    from paper_1511_03878_amd.sim import Batch, Sim
+    params = W.scan_params(count)
+    wls = [W.scan_sim(p, steps, seed=W.DEFAULT_SEED + k) for k, p in enumerate(params)]
+    total = sum(int(w["w"].size) for w in wls) * steps
+    # one at a time
+    t_alone = 0.0
+    for wl in wls:
+        s = Sim.from_workload(wl, precision=precision)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps)
+        torch.cuda.synchronize()
+        t_alone += time.perf_counter() - t0
+        s.close()
+    # batched
+    sims = [Sim.from_workload(wl, precision=precision) for wl in wls]
+    b = Batch(precision)
+    for s in sims:
+        b.add(s, steps)
+    b.step(0)  # builds the batch tables outside the timed region
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < count:
+        done += b.step(steps)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    for s in sims:
+        s.close()
+    return {"sims": count, "steps_each": steps, "particle_steps": total,
+            "batched": total / t_batch, "one_at_a_time": total / t_alone,
+            "speedup": t_alone / t_batch, "unit": "particle-steps/s",
+            "grids": [list(p["n"]) for p in params][:8] + (["..."] if count > 8 else [])}
+
+
+def _serve_bench(count, rate, steps_range, budget_gb, precision):
+    """Served scan: Poisson arrivals admitted against an HBM budget and
+    stepped with continuous batching; time-to-result percentiles."""
+    from paper_1511_03878_amd import serve
+    reqs = serve.make_requests(count, rate, steps_range=steps_range)
+    srv = serve.Server(int(budget_gb * 2**30), precision=precision, slice_steps=25,
+                       result_fn=lambda sim: {"diag": sim.diag()})
+    rep = srv.run(reqs, realtime=True)
+    rep.update({"rate_per_s": rate, "steps_range": list(steps_range), "budget_GiB": budget_gb,
+                "unit": "particle-steps/s"})
+    return rep
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +161,13 @@ def main():
     ap.add_argument("--workload", default="lwfa")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--scan", type=int, default=16, metavar="N",
+                    help="also run a batched scan of N simulations vs one at a time (0: skip)")
+    ap.add_argument("--scan-steps", type=int, default=100)
+    ap.add_argument("--serve", type=int, default=24, metavar="N",
+                    help="also serve N Poisson-arriving requests and report p50/p99 (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=4.0)
+    ap.add_argument("--serve-steps", default="200,2000")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="before the run, time a plain device copy of MIB MiB (calibrates "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE against a known byte count)")
@@ -196,6 +257,16 @@ def main():
     }
     if copy_cal:
         out["copy_calibration"] = copy_cal
+    sim.close()
+    del sim
+    if args.scan > 0:
+        print(f"[bench] batched scan of {args.scan} simulations", file=sys.stderr, flush=True)
+        out["batched_scan"] = _scan_bench(args.scan, args.scan_steps, args.precision)
+    if args.serve > 0:
+        lo, hi = (int(v) for v in args.serve_steps.split(","))
+        print(f"[bench] serving {args.serve} requests", file=sys.stderr, flush=True)
+        out["served_scan"] = _serve_bench(args.serve, args.serve_rate, (lo, hi), 200.0,
+                                          args.precision)
     if not args.no_cpu:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = _cpu_baseline(args.workload)

@@ -219,6 +219,16 @@ int pic_batch_step(PicBatch *b, int64_t max_steps, int32_t *done);
 int pic_batch_finished(PicBatch *b, PicSim **out, int32_t cap, int32_t *n);
 int pic_batch_size(PicBatch *b, int32_t *n);
 
+/* ---- admission ---------------------------------------------------------------- */
+
+/* Device bytes a simulation of descriptor `d` holding `nparticles` particles
+ * (and a laser table of `laser_steps` rows) is expected to allocate under the
+ * default capacity policy: fields, two current buffers, particle slots with
+ * their staging copy, per-patch tables.  Host-only; used by admission
+ * control against an HBM budget. */
+int pic_estimate_bytes(const PicSimDesc *d, int64_t nparticles, int64_t laser_steps,
+                       int64_t *bytes);
+
 /* ---- errors ------------------------------------------------------------------ */
 
 const char *pic_strerror(int code);

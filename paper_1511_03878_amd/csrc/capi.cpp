@@ -1,6 +1,7 @@
 // C ABI of the patch-PIC library: argument validation, handle management and
 // translation of runtime errors into status codes.  No exception crosses
 // this boundary.
+#include <algorithm>
 #include <cstring>
 
 #include "runtime.h"
@@ -274,6 +275,34 @@ int pic_timing_get(PicSim *s, PicTiming *out)
             out->launches[k] = s->impl->timing.launches[k];
         }
     });
+}
+
+int pic_estimate_bytes(const PicSimDesc *d, int64_t nparticles, int64_t laser_steps,
+                       int64_t *bytes)
+{
+    if (!d || !bytes || nparticles < 0 || laser_steps < 0) return bad(PIC_EINVAL, "bad argument");
+    std::string why;
+    int rc = validate_desc(*d, why);
+    if (rc != PIC_OK) return bad(rc, why.c_str());
+    const int64_t s = d->precision == 32 ? 4 : 8;
+    const int64_t fx = d->periodic[0] ? d->n[0] : d->n[0] + 1;
+    const int64_t fy = d->periodic[1] ? d->n[1] : d->n[1] + 1;
+    const int64_t fsize = fx * fy;
+    const int64_t npatch = (int64_t)(d->n[0] / d->patch[0]) * (d->n[1] / d->patch[1]);
+    const double factor = d->capacity_factor > 0.0 ? d->capacity_factor : 2.0;
+    const int64_t mean = std::max<int64_t>(64, (nparticles + npatch - 1) / npatch);
+    const int64_t floor_cap = d->min_capacity ? d->min_capacity : mean;
+    // capacity policy: max(factor x count, floor) per patch, rounded up to 64
+    int64_t slots = std::max<int64_t>((int64_t)(factor * nparticles), floor_cap * npatch) + 64 * npatch;
+    const int64_t per_slot = 2 * (6 * s + 8) + 1 + 4;  // particles + staging, code, hole list
+    const int64_t max_tiles = ((fx + 15) / 16) * ((fy + 3) / 4);
+    int64_t b = 18 * fsize * s;                        // two E, B buffers, two J buffers
+    b += slots * per_slot;
+    b += npatch * (4 * 7 + 4 * 9 + 4 * 26 + 8 + 8 + 4);  // counts, keys, neighbour table, partials, offsets
+    b += max_tiles * 8 + 8 * 4 * 4096 + 4096;          // tile partials, history, state
+    b += laser_steps * d->n[1] * s * 2;
+    *bytes = b;
+    return PIC_OK;
 }
 
 // ---- batches --------------------------------------------------------------------

@@ -13,8 +13,11 @@
 //                                By = (2 Ez^n - (1 - r) B_1 - 4 Ez_i) / (1 + r)
 //   x = L, outflow:              Bz = (2 Ey^n - (1 - r) B_1) / (1 + r)
 //                                By = (-2 Ez^n - (1 - r) B_1) / (1 + r)
-// The kernel also accumulates the field energy of E^n, B^n over the tile's own
-// nodes and clears the tile of the J buffer the next step deposits into.
+// The kernel reads E^n, B^n from one field buffer and writes E^{n+1},
+// B^{n+1} to the other (tiles read halos of their neighbours, which must not
+// have been advanced yet).  It also accumulates the field energy of E^n, B^n
+// over the tile's own nodes and clears the tile of the J buffer the next step
+// deposits into.
 #include "kernels.h"
 
 namespace pic {
@@ -42,6 +45,8 @@ __global__ __launch_bounds__(256) void k_maxwell2d(const SimDev<T> *__restrict__
         const int64_t stepn = S.st->step;
         T *const *Jc = S.J[stepn & 1];
         T *const *Jn = S.J[(stepn + 1) & 1];
+        T *const *Fc = S.F[stepn & 1];
+        T *const *Fn = S.F[(stepn + 1) & 1];
 
         // ---- load nodes [X0-1, X0+TX+1] x [Y0-1, Y0+TY+1] -------------------
         // all loads of the tile are issued before the first LDS write, so each
@@ -66,12 +71,12 @@ __global__ __launch_bounds__(256) void k_maxwell2d(const SimDev<T> *__restrict__
             const int64_t kpd = (ip >= 0 && jd >= 0) ? ip + (int64_t)fn0 * jd : -1;
             const int64_t kpp = (ip >= 0 && jp >= 0) ? ip + (int64_t)fn0 * jp : -1;
             const int64_t kdd = (id >= 0 && jd >= 0) ? id + (int64_t)fn0 * jd : -1;
-            v[r][0] = kdp >= 0 ? S.F[0][kdp] : T(0);
-            v[r][1] = kpd >= 0 ? S.F[1][kpd] : T(0);
-            v[r][2] = kpp >= 0 ? S.F[2][kpp] : T(0);
-            v[r][3] = kpd >= 0 ? S.F[3][kpd] : T(0);
-            v[r][4] = kdp >= 0 ? S.F[4][kdp] : T(0);
-            v[r][5] = kdd >= 0 ? S.F[5][kdd] : T(0);
+            v[r][0] = kdp >= 0 ? Fc[0][kdp] : T(0);
+            v[r][1] = kpd >= 0 ? Fc[1][kpd] : T(0);
+            v[r][2] = kpp >= 0 ? Fc[2][kpp] : T(0);
+            v[r][3] = kpd >= 0 ? Fc[3][kpd] : T(0);
+            v[r][4] = kdp >= 0 ? Fc[4][kdp] : T(0);
+            v[r][5] = kdd >= 0 ? Fc[5][kdd] : T(0);
             v[r][6] = kdp >= 0 ? Jc[0][kdp] : T(0);
             v[r][7] = kpd >= 0 ? Jc[1][kpd] : T(0);
             v[r][8] = kpp >= 0 ? Jc[2][kpp] : T(0);
@@ -159,15 +164,15 @@ __global__ __launch_bounds__(256) void k_maxwell2d(const SimDev<T> *__restrict__
             // components stop one node short
             const bool dx_ok = per0 || gi <= n0 - 1;
             const int64_t k = gi + (int64_t)fn0 * gj;
-            S.F[1][k] = sE[1][c];
-            S.F[2][k] = sE[2][c];
-            S.F[3][k] = bx;
+            Fn[1][k] = sE[1][c];
+            Fn[2][k] = sE[2][c];
+            Fn[3][k] = bx;
             Jn[1][k] = T(0);
             Jn[2][k] = T(0);
             if (dx_ok) {
-                S.F[0][k] = sE[0][c];
-                S.F[4][k] = by;
-                S.F[5][k] = bz;
+                Fn[0][k] = sE[0][c];
+                Fn[4][k] = by;
+                Fn[5][k] = bz;
                 Jn[0][k] = T(0);
             }
         }

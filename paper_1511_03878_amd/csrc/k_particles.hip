@@ -50,7 +50,7 @@ __device__ __forceinline__ T gather9(const T *tile, int fw, int i0, int j0, cons
 // formed from the exact old offset and the displacement in FP64, so the
 // weight change keeps full relative accuracy even for FP32 storage.
 template <typename T>
-__device__ __forceinline__ void window4(T xl, double disp, int &m, double S0[4], double DS[4])
+__device__ __forceinline__ bool window4(T xl, double disp, int &m, double S0[4], double DS[4])
 {
     int i0 = (int)floor(xl + T(0.5));
     double d0 = (double)(xl - (T)i0);  // exact
@@ -71,7 +71,16 @@ __device__ __forceinline__ void window4(T xl, double disp, int &m, double S0[4],
         S0[k] = A0[k];
         DS[k] = A1[k] - A0[k];
     }
+    // window slot 3 carries weight only when the nearest node changed
+    return sg != 0;
 }
+
+// Reciprocal and reciprocal square root: hardware approximations (about one
+// ulp) for FP32, correctly rounded operations for FP64.
+__device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rsq_(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsq_(double x) { return 1.0 / sqrt(x); }
 
 template <typename T>
 __device__ __forceinline__ T below(T v);
@@ -87,13 +96,17 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-template <typename T, int BLOCK>
+// PC > 0: every simulation of the launch has PC x PC-cell patches, so tile
+// strides are compile-time constants and LDS offsets fold into instructions.
+template <typename T, int BLOCK, int PC>
 __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restrict__ sims,
                                                        const Item *__restrict__ items,
                                                        const int *__restrict__ nitems,
-                                                       int *__restrict__ head, int fstride,
-                                                       int jstride)
+                                                       int *__restrict__ head, int fstride_rt,
+                                                       int jstride_rt)
 {
+    const int fstride = PC ? (PC + 3) * (PC + 3) : fstride_rt;
+    const int jstride = PC ? (PC + 5) * (PC + 5) : jstride_rt;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     // current tile first (FP64 accumulation for either storage precision:
     // LDS float atomics are much slower here than FP64 ones), then fields
@@ -115,7 +128,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
         const int p = __builtin_amdgcn_readfirstlane(it.y);
         const int first = __builtin_amdgcn_readfirstlane(it.z);
         const int cnt = __builtin_amdgcn_readfirstlane(it.w);
-        const int P0 = S.P[0], P1 = S.P[1];
+        const int P0 = PC ? PC : S.P[0], P1 = PC ? PC : S.P[1];
         const int pxi = p % S.np[0], pyi = p / S.np[0];
         const int ox = pxi * P0, oy = pyi * P1;
         const int fw = P0 + 3, fh = P1 + 3, jw = P0 + 5, jh = P1 + 5;
@@ -123,6 +136,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
         const int per0 = S.periodic[0], per1 = S.periodic[1];
 
         // ---- stage E, B of nodes [ox-1, ox+P0+1] x [oy-1, oy+P1+1] --------
+        T *const *Fc = S.F[S.st->step & 1];
         // four nodes per thread per round, all loads issued before the stores
         for (int t0 = 0; t0 < fw * fh; t0 += 4 * BLOCK) {
             T v[4][6];
@@ -136,12 +150,12 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
                 const int jp = in ? axis_node(gj, n1, per1, 0) : -1;
                 const int jd = in ? axis_node(gj, n1, per1, 1) : -1;
                 // staggering: Ex (d,p) Ey (p,d) Ez (p,p) Bx (p,d) By (d,p) Bz (d,d)
-                v[r][0] = (id >= 0 && jp >= 0) ? S.F[0][id + fn0 * jp] : T(0);
-                v[r][1] = (ip >= 0 && jd >= 0) ? S.F[1][ip + fn0 * jd] : T(0);
-                v[r][2] = (ip >= 0 && jp >= 0) ? S.F[2][ip + fn0 * jp] : T(0);
-                v[r][3] = (ip >= 0 && jd >= 0) ? S.F[3][ip + fn0 * jd] : T(0);
-                v[r][4] = (id >= 0 && jp >= 0) ? S.F[4][id + fn0 * jp] : T(0);
-                v[r][5] = (id >= 0 && jd >= 0) ? S.F[5][id + fn0 * jd] : T(0);
+                v[r][0] = (id >= 0 && jp >= 0) ? Fc[0][id + fn0 * jp] : T(0);
+                v[r][1] = (ip >= 0 && jd >= 0) ? Fc[1][ip + fn0 * jd] : T(0);
+                v[r][2] = (ip >= 0 && jp >= 0) ? Fc[2][ip + fn0 * jp] : T(0);
+                v[r][3] = (ip >= 0 && jd >= 0) ? Fc[3][ip + fn0 * jd] : T(0);
+                v[r][4] = (id >= 0 && jp >= 0) ? Fc[4][id + fn0 * jp] : T(0);
+                v[r][5] = (id >= 0 && jd >= 0) ? Fc[5][id + fn0 * jd] : T(0);
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -158,8 +172,8 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
         const T dt = S.dt, q = S.q, m = S.m;
         const T eps = q * dt / (T(2) * m);
         const T rdx = dt / S.d[0], rdy = dt / S.d[1];
-        const double cx = -(double)q * (double)S.d[0] / (double)dt;
-        const double cy = -(double)q * (double)S.d[1] / (double)dt;
+        const double cx_ = -(double)q * (double)S.d[0] / (double)dt;
+        const double cy_ = -(double)q * (double)S.d[1] / (double)dt;
         const T Pmax0 = below((T)P0), Pmax1 = below((T)P1);
         const bool edge_lo = !per0 && pxi == 0, edge_hi = !per0 && pxi == S.np[0] - 1;
         double kin = 0.0;
@@ -222,12 +236,11 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
 
             // ---- Boris ------------------------------------------------------
             const T usq0 = ux * ux + uy * uy + uz * uz;
-            const T g0 = sqrt(T(1) + usq0);
             T umx = ux + eps * Ex, umy = uy + eps * Ey, umz = uz + eps * Ez;
-            const T gm = sqrt(T(1) + umx * umx + umy * umy + umz * umz);
-            const T tx = eps * Bx / gm, ty = eps * By / gm, tz = eps * Bz / gm;
+            const T igm = rsq_(T(1) + umx * umx + umy * umy + umz * umz);
+            const T tx = eps * igm * Bx, ty = eps * igm * By, tz = eps * igm * Bz;
             const T t2 = tx * tx + ty * ty + tz * tz;
-            const T s2 = T(2) / (T(1) + t2);
+            const T s2 = T(2) * rcp_(T(1) + t2);
             const T sx = s2 * tx, sy = s2 * ty, sz = s2 * tz;
             const T upx = umx + (umy * tz - umz * ty);
             const T upy = umy + (umz * tx - umx * tz);
@@ -239,10 +252,14 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
             uy = umy + eps * Ey;
             uz = umz + eps * Ez;
             const T usq1 = ux * ux + uy * uy + uz * uz;
-            const T g1 = sqrt(T(1) + usq1);
-            const T ig1 = T(1) / g1;
-            kin += (double)wgt * (double)m * 0.5 *
-                   ((double)usq0 / ((double)g0 + 1.0) + (double)usq1 / ((double)g1 + 1.0));
+            const T ig1 = rsq_(T(1) + usq1);
+            {
+                // w m ((gamma0 - 1) + (gamma1 - 1)) / 2 with gamma - 1 = u^2 / (gamma + 1)
+                const double g0p = sqrt(1.0 + (double)usq0) + 1.0;
+                const double g1p = (double)(T(1) + usq1) * (double)ig1 + 1.0;
+                kin += (double)wgt * (double)m * 0.5 *
+                       ((double)usq0 * g1p + (double)usq1 * g0p) / (g0p * g1p);
+            }
 
             // ---- move and classify -------------------------------------------
             const T dxl = rdx * ux * ig1, dyl = rdy * uy * ig1;
@@ -255,45 +272,80 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
                 y1 = yl;
             } else {
                 // ---- Esirkepov deposit on a 4x4 node window ------------------
+                // Only window slot 3 of an axis depends on whether the nearest
+                // node changed; its entries are exactly zero otherwise and their
+                // atomics are skipped (masked lanes cost the LDS nothing).
                 int mx, my;
                 double S0x[4], DSx[4], S0y[4], DSy[4];
-                window4(xl, (double)dxl, mx, S0x, DSx);
-                window4(yl, (double)dyl, my, S0y, DSy);
+                const bool cx = window4(xl, (double)dxl, mx, S0x, DSx);
+                const bool cy = window4(yl, (double)dyl, my, S0y, DSy);
                 const double qw = (double)wgt;
-                const double ax = cx * qw, ay = cy * qw;
                 const double az = (double)q * qw * (double)(uz * ig1);
                 double *Jxt = Jt, *Jyt = Jt + jstride, *Jzt = Jt + 2 * jstride;
                 const int r0 = (my + 2) * jw + (mx + 2);
+                // time-averaged transverse weights
+                double wx[4], wy[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const double wy = S0y[j] + 0.5 * DSy[j];
-                    double acc = 0.0;
-#pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-                        acc += DSx[i] * wy;
-                        // window entries off both supports are exactly zero;
-                        // masked lanes cost the LDS nothing
-                        if (acc != 0.0) atomicAdd(&Jxt[r0 + j * jw + i], ax * acc);
-                    }
+                for (int k = 0; k < 4; ++k) {
+                    wx[k] = S0x[k] + 0.5 * DSx[k];
+                    wy[k] = S0y[k] + 0.5 * DSy[k];
                 }
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const double wx = S0x[i] + 0.5 * DSx[i];
-                    double acc = 0.0;
+                if (dxl != T(0) || dyl != T(0)) {
+                    // Jx on dual x nodes: running sums of -q w (dx/dt) DSx, times wy
+                    double px[3], py[3];
+                    px[0] = cx_ * qw * DSx[0];
+                    px[1] = px[0] + cx_ * qw * DSx[1];
+                    px[2] = px[1] + cx_ * qw * DSx[2];
+                    py[0] = cy_ * qw * DSy[0];
+                    py[1] = py[0] + cy_ * qw * DSy[1];
+                    py[2] = py[1] + cy_ * qw * DSy[2];
 #pragma unroll
                     for (int j = 0; j < 3; ++j) {
-                        acc += DSy[j] * wx;
-                        if (acc != 0.0) atomicAdd(&Jyt[r0 + j * jw + i], ay * acc);
+                        atomicAdd(&Jxt[r0 + j * jw + 0], px[0] * wy[j]);
+                        atomicAdd(&Jxt[r0 + j * jw + 1], px[1] * wy[j]);
+                        if (cx) atomicAdd(&Jxt[r0 + j * jw + 2], px[2] * wy[j]);
+                    }
+                    if (cy) {
+                        atomicAdd(&Jxt[r0 + 3 * jw + 0], px[0] * wy[3]);
+                        atomicAdd(&Jxt[r0 + 3 * jw + 1], px[1] * wy[3]);
+                        if (cx) atomicAdd(&Jxt[r0 + 3 * jw + 2], px[2] * wy[3]);
+                    }
+                    // Jy on dual y nodes: running sums along y, times wx
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        atomicAdd(&Jyt[r0 + 0 * jw + i], py[0] * wx[i]);
+                        atomicAdd(&Jyt[r0 + 1 * jw + i], py[1] * wx[i]);
+                        if (cy) atomicAdd(&Jyt[r0 + 2 * jw + i], py[2] * wx[i]);
+                    }
+                    if (cx) {
+                        atomicAdd(&Jyt[r0 + 0 * jw + 3], py[0] * wx[3]);
+                        atomicAdd(&Jyt[r0 + 1 * jw + 3], py[1] * wx[3]);
+                        if (cy) atomicAdd(&Jyt[r0 + 2 * jw + 3], py[2] * wx[3]);
                     }
                 }
+                if (az != 0.0) {
+                    // Jz = q w vz (S0x S0y + DSx S0y / 2 + S0x DSy / 2 + DSx DSy / 3)
+                    //    = q w vz (wx S0y + bx DSy), bx = S0x / 2 + DSx / 3
+                    double ax_[4], bx_[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const double wz = S0x[i] * S0y[j] + 0.5 * (DSx[i] * S0y[j] + S0x[i] * DSy[j]) +
-                                          DSx[i] * DSy[j] * (1.0 / 3.0);
-                        if (wz != 0.0 && az != 0.0) atomicAdd(&Jzt[r0 + j * jw + i], az * wz);
+                    for (int k = 0; k < 4; ++k) {
+                        ax_[k] = az * wx[k];
+                        bx_[k] = az * (0.5 * S0x[k] + DSx[k] * (1.0 / 3.0));
                     }
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+#pragma unroll
+                        for (int i = 0; i < 3; ++i)
+                            atomicAdd(&Jzt[r0 + j * jw + i], ax_[i] * S0y[j] + bx_[i] * DSy[j]);
+                        if (cx) atomicAdd(&Jzt[r0 + j * jw + 3], ax_[3] * S0y[j] + bx_[3] * DSy[j]);
+                    }
+                    if (cy) {
+#pragma unroll
+                        for (int i = 0; i < 3; ++i)
+                            atomicAdd(&Jzt[r0 + 3 * jw + i], ax_[i] * S0y[3] + bx_[i] * DSy[3]);
+                        if (cx) atomicAdd(&Jzt[r0 + 3 * jw + 3], ax_[3] * S0y[3] + bx_[3] * DSy[3]);
+                    }
+                }
 
                 const int sx_ = x1 < T(0) ? -1 : (x1 >= (T)P0 ? 1 : 0);
                 const int sy_ = y1 < T(0) ? -1 : (y1 >= (T)P1 ? 1 : 0);
@@ -353,21 +405,30 @@ size_t lds_bytes(int maxP0, int maxP1, int &fstride, int &jstride)
 
 }  // namespace
 
+template <typename T, int BLOCK>
+static void launch_pc(int pc, const SimDev<T> *sims, const Item *items, const int *nitems, int *head,
+                      int grid, size_t lds, int fs, int js, hipStream_t st)
+{
+    if (pc == 32)
+        hipLaunchKernelGGL((k_particles2d<T, BLOCK, 32>), dim3(grid), dim3(BLOCK), lds, st, sims,
+                           items, nitems, head, fs, js);
+    else if (pc == 16)
+        hipLaunchKernelGGL((k_particles2d<T, BLOCK, 16>), dim3(grid), dim3(BLOCK), lds, st, sims,
+                           items, nitems, head, fs, js);
+    else
+        hipLaunchKernelGGL((k_particles2d<T, BLOCK, 0>), dim3(grid), dim3(BLOCK), lds, st, sims,
+                           items, nitems, head, fs, js);
+}
+
 template <typename T>
 void launch_particles(const SimDev<T> *sims, const Item *items, const int *nitems, int *head,
-                      int grid, int block, int maxP0, int maxP1, hipStream_t st)
+                      int grid, int block, int maxP0, int maxP1, int pc, hipStream_t st)
 {
     int fs, js;
     size_t lds = lds_bytes<T>(maxP0, maxP1, fs, js);
-    if (block == 1024)
-        hipLaunchKernelGGL((k_particles2d<T, 1024>), dim3(grid), dim3(1024), lds, st, sims, items,
-                           nitems, head, fs, js);
-    else if (block == 512)
-        hipLaunchKernelGGL((k_particles2d<T, 512>), dim3(grid), dim3(512), lds, st, sims, items,
-                           nitems, head, fs, js);
-    else
-        hipLaunchKernelGGL((k_particles2d<T, 256>), dim3(grid), dim3(256), lds, st, sims, items,
-                           nitems, head, fs, js);
+    if (block == 1024) launch_pc<T, 1024>(pc, sims, items, nitems, head, grid, lds, fs, js, st);
+    else if (block == 512) launch_pc<T, 512>(pc, sims, items, nitems, head, grid, lds, fs, js, st);
+    else launch_pc<T, 256>(pc, sims, items, nitems, head, grid, lds, fs, js, st);
 }
 
 template <typename T>
@@ -377,19 +438,19 @@ int particles_occupancy(int block, int maxP0, int maxP1)
     size_t lds = lds_bytes<T>(maxP0, maxP1, fs, js);
     hipError_t e;
     if (block == 1024)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particles2d<T, 1024>, 1024, lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particles2d<T, 1024, 0>, 1024, lds);
     else if (block == 512)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particles2d<T, 512>, 512, lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particles2d<T, 512, 0>, 512, lds);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particles2d<T, 256>, 256, lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particles2d<T, 256, 0>, 256, lds);
     if (e != hipSuccess) return 0;
     return nb;
 }
 
 template void launch_particles<float>(const SimDev<float> *, const Item *, const int *, int *, int,
-                                      int, int, int, hipStream_t);
+                                      int, int, int, int, hipStream_t);
 template void launch_particles<double>(const SimDev<double> *, const Item *, const int *, int *,
-                                       int, int, int, int, hipStream_t);
+                                       int, int, int, int, int, hipStream_t);
 template int particles_occupancy<float>(int, int, int);
 template int particles_occupancy<double>(int, int, int);
 

@@ -27,9 +27,11 @@ template <typename T>
 void launch_close_queue(const SimDev<T> *sims, const QueueArgs &q, hipStream_t st);
 
 // Persistent particle kernel: gather, Boris, move, classify, Esirkepov deposit.
+// pc: common square patch size of every simulation in the launch (16 or 32)
+// for the specialised kernel, 0 for the general one.
 template <typename T>
 void launch_particles(const SimDev<T> *sims, const Item *items, const int *nitems, int *head,
-                      int grid, int block, int maxP0, int maxP1, hipStream_t st);
+                      int grid, int block, int maxP0, int maxP1, int pc, hipStream_t st);
 template <typename T>
 int particles_occupancy(int block, int maxP0, int maxP1);
 

@@ -1,8 +1,8 @@
 // Device-side data layout and shared device helpers of the patch-PIC library.
 //
 // Layout in HBM (per simulation):
-//  - fields: one array per component (Ex Ey Ez Bx By Bz, and two J buffers of
-//    three components), row-major with x fastest, fn[a] nodes per axis;
+//  - fields: one array per component (two buffers of Ex Ey Ez Bx By Bz, and two
+//    J buffers of three components), row-major with x fastest, fn[a] nodes per axis;
 //  - particles: structure of arrays (local position per axis, u_x, u_y, u_z,
 //    weight, 64-bit id, 1-byte destination code) grouped by patch: patch p owns
 //    slots [off[p], off[p] + cap[p]) of every array and uses the first count[p];
@@ -54,8 +54,10 @@ struct SimDev {
     T dt;
     T q, m;
     double vcell;
-    // fields
-    T *F[6];
+    // fields: two buffers of E, B (the step's input is F[step & 1], the Yee
+    // update writes F[(step + 1) & 1], so no tile reads a halo another tile
+    // has already advanced) and two current buffers (deposit into J[step & 1])
+    T *F[2][6];
     T *J[2][3];
     // particles
     T *x[3], *u[3], *w;

@@ -117,7 +117,8 @@ SimImpl<T>::SimImpl(const PicSimDesc &d, const PicAllocator *a, hipStream_t s)
     fsize = (int64_t)fn[0] * fn[1];
     std::memset(&v, 0, sizeof(v));
     try {
-        for (int c = 0; c < 6; ++c) F[c] = (T *)alloc.get(sizeof(T) * fsize);
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < 6; ++c) F[b][c] = (T *)alloc.get(sizeof(T) * fsize);
         for (int b = 0; b < 2; ++b)
             for (int c = 0; c < 3; ++c) J[b][c] = (T *)alloc.get(sizeof(T) * fsize);
         st = (SimState *)alloc.get(sizeof(SimState));
@@ -137,7 +138,9 @@ SimImpl<T>::SimImpl(const PicSimDesc &d, const PicAllocator *a, hipStream_t s)
         kpart = (double *)alloc.get(sizeof(double) * npatch);
         hipcheck(hipMemsetAsync(upart, 0, sizeof(double) * max_tiles, stream), "memset upart");
         hipcheck(hipMemsetAsync(kpart, 0, sizeof(double) * npatch, stream), "memset kpart");
-        for (int c = 0; c < 6; ++c) hipcheck(hipMemsetAsync(F[c], 0, sizeof(T) * fsize, stream), "memset F");
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < 6; ++c)
+                hipcheck(hipMemsetAsync(F[b][c], 0, sizeof(T) * fsize, stream), "memset F");
         for (int b = 0; b < 2; ++b)
             for (int c = 0; c < 3; ++c)
                 hipcheck(hipMemsetAsync(J[b][c], 0, sizeof(T) * fsize, stream), "memset J");
@@ -252,7 +255,8 @@ template <typename T>
 void SimImpl<T>::release()
 {
     free_particles();
-    for (int c = 0; c < 6; ++c) alloc.put(F[c]);
+    for (int b = 0; b < 2; ++b)
+        for (int c = 0; c < 6; ++c) alloc.put(F[b][c]);
     for (int b = 0; b < 2; ++b)
         for (int c = 0; c < 3; ++c) alloc.put(J[b][c]);
     alloc.put(st);
@@ -364,7 +368,8 @@ void SimImpl<T>::refresh_view()
     V.q = (T)desc.q;
     V.m = (T)desc.m;
     V.vcell = desc.d[0] * desc.d[1];
-    for (int c = 0; c < 6; ++c) V.F[c] = F[c];
+    for (int b = 0; b < 2; ++b)
+        for (int c = 0; c < 6; ++c) V.F[b][c] = F[b][c];
     for (int b = 0; b < 2; ++b)
         for (int c = 0; c < 3; ++c) V.J[b][c] = J[b][c];
     V.x[0] = px[0]; V.x[1] = px[1]; V.x[2] = nullptr;
@@ -486,7 +491,8 @@ void SimImpl<T>::set_field(int comp, const double *h)
     if (comp < 0 || comp > 5) throw Error(PIC_EINVAL, "only E and B components can be set");
     std::vector<T> tmp(fsize);
     for (int64_t k = 0; k < fsize; ++k) tmp[k] = (T)h[k];
-    hipcheck(hipMemcpyAsync(F[comp], tmp.data(), sizeof(T) * fsize, hipMemcpyHostToDevice, stream), "field");
+    const SimState s = read_state();
+    hipcheck(hipMemcpyAsync(F[s.step & 1][comp], tmp.data(), sizeof(T) * fsize, hipMemcpyHostToDevice, stream), "field");
     hipcheck(hipStreamSynchronize(stream), "sync");
 }
 
@@ -507,7 +513,7 @@ void SimImpl<T>::get_field(int comp, double *h)
     }
     SimState s;
     hipcheck(hipMemcpy(&s, st, sizeof(s), hipMemcpyDeviceToHost), "state");
-    const T *src = comp < 6 ? F[comp] : J[(s.step + 1) & 1][comp - 6];
+    const T *src = comp < 6 ? F[s.step & 1][comp] : J[(s.step + 1) & 1][comp - 6];
     std::vector<T> tmp(fsize);
     hipcheck(hipMemcpyAsync(tmp.data(), src, sizeof(T) * fsize, hipMemcpyDeviceToHost, stream), "field");
     hipcheck(hipStreamSynchronize(stream), "sync");
@@ -814,6 +820,13 @@ void BatchImpl<T>::build_tables()
     }
     total_patches = pp[ns];
     total_tiles = tp[ns];
+    // a common square patch size of 16 or 32 selects the specialised kernel
+    patch_const = 0;
+    if (ns > 0 && (members[0]->P[0] == 16 || members[0]->P[0] == 32)) {
+        patch_const = members[0]->P[0];
+        for (auto *m : members)
+            if (m->P[0] != patch_const || m->P[1] != patch_const) patch_const = 0;
+    }
     // chunk: enough items to fill every CU several times over
     chunk = 0;
     for (auto *m : members) chunk = std::max(chunk, (int)m->desc.chunk);
@@ -914,7 +927,8 @@ void BatchImpl<T>::launch_one_step()
     const int ns = (int)members.size();
     Timing &tm = timing();
     tm.record(stream, 1, true);
-    launch_particles<T>(sims_d, items_d, nitems_d, head_d, grid_particles, block, maxP0, maxP1, stream);
+    launch_particles<T>(sims_d, items_d, nitems_d, head_d, grid_particles, block, maxP0, maxP1,
+                        patch_const, stream);
     tm.record(stream, 1, false);
     tm.record(stream, 2, true);
     launch_maxwell<T>(sims_d, ns, tile_prefix_d, total_tiles, grid_maxwell, tile_preset, stream);

@@ -82,7 +82,7 @@ struct SimImpl : SimBase {
     int n[3], P[3], np[3], fn[3], periodic[3];
     int npatch = 0;
     int64_t fsize = 0;
-    T *F[6] = {};
+    T *F[2][6] = {};
     T *J[2][3] = {};
     SimState *st = nullptr;
     double *hist = nullptr;
@@ -160,7 +160,7 @@ struct BatchImpl : BatchBase {
     int table_cap_items = 0;
     int total_patches = 0, total_tiles = 0;
     int maxP0 = 1, maxP1 = 1;
-    int chunk = 256, block = 256, tile_preset = 0;
+    int chunk = 256, block = 256, tile_preset = 0, patch_const = 0;
     int grid_particles = 1, grid_maxwell = 1, grid_rebin = 1;
     Timing own_timing;
 

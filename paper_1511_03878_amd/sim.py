@@ -69,6 +69,16 @@ def make_desc(grid: dict, precision: int, chunk: int = 0, block: int = 0,
                          int(field_tile), int(lane_stride))
 
 
+def estimate_bytes(grid: dict, precision: int, nparticles: int, laser_steps: int = 0,
+                   **tune) -> int:
+    """Device bytes a simulation is expected to allocate (host-only query)."""
+    out = C.c_int64()
+    desc = make_desc(grid, precision, **tune)
+    check(_capi.load().pic_estimate_bytes(C.byref(desc), int(nparticles), int(laser_steps),
+                                          C.byref(out)))
+    return out.value
+
+
 class Sim:
     """One simulation on the GPU (a handle of the C library)."""
 
