@@ -207,11 +207,11 @@ void maxwell_tile(int preset, int &tx, int &ty)
 
 template <typename T>
 void launch_maxwell(const SimDev<T> *sims, int nsims, const int *tile_prefix, int total_tiles,
-                    int grid, int preset, hipStream_t st)
+                    int grid, int preset, hipStream_t st, Ev2 ev)
 {
 #define PIC_MW(TX, TY)                                                                          \
-    hipLaunchKernelGGL((k_maxwell2d<T, TX, TY>), dim3(grid), dim3(256), 0, st, sims, nsims,    \
-                       tile_prefix, total_tiles)
+    hipExtLaunchKernelGGL((k_maxwell2d<T, TX, TY>), dim3(grid), dim3(256), 0, st, ev.start,    \
+                          ev.stop, 0, sims, nsims, tile_prefix, total_tiles)
     const int p = (preset >= 0 && preset < 6) ? preset : 0;
     if constexpr (sizeof(T) == 4) {
         switch (p) {
@@ -238,8 +238,8 @@ void launch_maxwell(const SimDev<T> *sims, int nsims, const int *tile_prefix, in
 template void maxwell_tile<float>(int, int &, int &);
 template void maxwell_tile<double>(int, int &, int &);
 template void launch_maxwell<float>(const SimDev<float> *, int, const int *, int, int, int,
-                                    hipStream_t);
+                                    hipStream_t, Ev2);
 template void launch_maxwell<double>(const SimDev<double> *, int, const int *, int, int, int,
-                                     hipStream_t);
+                                     hipStream_t, Ev2);
 
 }  // namespace pic

@@ -407,28 +407,28 @@ size_t lds_bytes(int maxP0, int maxP1, int &fstride, int &jstride)
 
 template <typename T, int BLOCK>
 static void launch_pc(int pc, const SimDev<T> *sims, const Item *items, const int *nitems, int *head,
-                      int grid, size_t lds, int fs, int js, hipStream_t st)
+                      int grid, size_t lds, int fs, int js, hipStream_t st, Ev2 ev)
 {
     if (pc == 32)
-        hipLaunchKernelGGL((k_particles2d<T, BLOCK, 32>), dim3(grid), dim3(BLOCK), lds, st, sims,
-                           items, nitems, head, fs, js);
+        hipExtLaunchKernelGGL((k_particles2d<T, BLOCK, 32>), dim3(grid), dim3(BLOCK), lds, st,
+                              ev.start, ev.stop, 0, sims, items, nitems, head, fs, js);
     else if (pc == 16)
-        hipLaunchKernelGGL((k_particles2d<T, BLOCK, 16>), dim3(grid), dim3(BLOCK), lds, st, sims,
-                           items, nitems, head, fs, js);
+        hipExtLaunchKernelGGL((k_particles2d<T, BLOCK, 16>), dim3(grid), dim3(BLOCK), lds, st,
+                              ev.start, ev.stop, 0, sims, items, nitems, head, fs, js);
     else
-        hipLaunchKernelGGL((k_particles2d<T, BLOCK, 0>), dim3(grid), dim3(BLOCK), lds, st, sims,
-                           items, nitems, head, fs, js);
+        hipExtLaunchKernelGGL((k_particles2d<T, BLOCK, 0>), dim3(grid), dim3(BLOCK), lds, st,
+                              ev.start, ev.stop, 0, sims, items, nitems, head, fs, js);
 }
 
 template <typename T>
 void launch_particles(const SimDev<T> *sims, const Item *items, const int *nitems, int *head,
-                      int grid, int block, int maxP0, int maxP1, int pc, hipStream_t st)
+                      int grid, int block, int maxP0, int maxP1, int pc, hipStream_t st, Ev2 ev)
 {
     int fs, js;
     size_t lds = lds_bytes<T>(maxP0, maxP1, fs, js);
-    if (block == 1024) launch_pc<T, 1024>(pc, sims, items, nitems, head, grid, lds, fs, js, st);
-    else if (block == 512) launch_pc<T, 512>(pc, sims, items, nitems, head, grid, lds, fs, js, st);
-    else launch_pc<T, 256>(pc, sims, items, nitems, head, grid, lds, fs, js, st);
+    if (block == 1024) launch_pc<T, 1024>(pc, sims, items, nitems, head, grid, lds, fs, js, st, ev);
+    else if (block == 512) launch_pc<T, 512>(pc, sims, items, nitems, head, grid, lds, fs, js, st, ev);
+    else launch_pc<T, 256>(pc, sims, items, nitems, head, grid, lds, fs, js, st, ev);
 }
 
 template <typename T>
@@ -448,9 +448,9 @@ int particles_occupancy(int block, int maxP0, int maxP1)
 }
 
 template void launch_particles<float>(const SimDev<float> *, const Item *, const int *, int *, int,
-                                      int, int, int, int, hipStream_t);
+                                      int, int, int, int, hipStream_t, Ev2);
 template void launch_particles<double>(const SimDev<double> *, const Item *, const int *, int *,
-                                       int, int, int, int, int, hipStream_t);
+                                       int, int, int, int, int, hipStream_t, Ev2);
 template int particles_occupancy<float>(int, int, int);
 template int particles_occupancy<double>(int, int, int);
 

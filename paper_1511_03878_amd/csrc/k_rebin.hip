@@ -69,15 +69,41 @@ __device__ __forceinline__ void copy_particle(const SimDev<T> &S, int64_t from, 
     ti[to] = fi[from];
 }
 
+// Count pass.  Each wave of the workgroup owns a contiguous range of the
+// patch's slots and loads the destination codes of up to kU x 64 of them at
+// once (one batch; a patch of at most kRCW x kU x 64 particles is one batch).
+// Leaver counts per key come from ballots, one per key present in a 64-slot
+// chunk, and are kept lane-indexed in a register (lane k: key k, lane kKeys:
+// all keys).  After one exchange of the per-wave counts through LDS every wave
+// knows where its leavers go: the vacated slots are listed in slot order and
+// the staged leavers are queued in a per-wave LDS ring, which is drained 64
+// entries at a time (one lane per particle, so the particle loads of 64
+// leavers are in flight together).
+constexpr int kRC = 512;  // threads of the count workgroup
+constexpr int kRCW = kRC / 64;
+constexpr int kU = 32;    // 64-slot chunks per batch of code loads
+constexpr int kRing = 128;
+
 template <typename T>
-__global__ __launch_bounds__(kRB) void k_rebin_count(const SimDev<T> *__restrict__ sims, int nsims,
+__device__ __forceinline__ void drain_ring(const SimDev<T> &S, int64_t base, const int2 *ring,
+                                           int &head, int tail, int lane)
+{
+    // copy up to 64 queued leavers (ring positions head .. min(tail, head + 64))
+    const int n = min(64, tail - head);
+    if (lane < n) {
+        const int2 e = ring[(head + lane) & (kRing - 1)];
+        copy_particle(S, base + e.x, base + e.y, false, true);
+    }
+    head += n;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRC) void k_rebin_count(const SimDev<T> *__restrict__ sims, int nsims,
                                                      const int *__restrict__ patch_prefix, int total)
 {
-    __shared__ int s_key[kNDir2];
-    __shared__ int s_cnt[kKeys];
-    __shared__ int s_koff[kKeys];
-    __shared__ int s_wc[kNW][kKeys + 1];
-    __shared__ int s_run[kKeys + 1];
+    __shared__ uint8_t s_kb[256];           // code -> key + 1 (0: the particle stays)
+    __shared__ int s_wc[kRCW][kKeys + 1];   // per wave: leavers of each key, then of all keys
+    __shared__ int2 s_ring[kRCW][kRing];    // per wave: (slot, staging slot) of queued leavers
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
@@ -88,57 +114,113 @@ __global__ __launch_bounds__(kRB) void k_rebin_count(const SimDev<T> *__restrict
         const int p = gp - patch_prefix[s];
         const int n = S.count[p];
         const int64_t base = S.off[p];
-        if (tid < kNDir2) s_key[tid] = nb_row(S.nbt, p)[tid];
-        if (tid < kKeys) s_cnt[tid] = 0;
-        if (tid <= kKeys) s_run[tid] = 0;
-        __syncthreads();
-        for (int k = tid; k < n; k += kRB) {
-            const int key = code_key(s_key, S.code[base + k]);
-            if (key >= 0) atomicAdd(&s_cnt[key], 1);
+        const uint8_t *code = S.code + base;
+        if (tid < 256) {
+            int kb = 0;
+            if (tid < kNDir2) kb = nb_row(S.nbt, p)[tid] + 1;
+            else if (tid == kRemoved) kb = kNDir2 + 1;
+            s_kb[tid] = (uint8_t)kb;
         }
         __syncthreads();
-        if (tid == 0) {
-            int acc = 0;
-            for (int k = 0; k < kKeys; ++k) { s_koff[k] = acc; acc += s_cnt[k]; }
-        }
-        __syncthreads();
-        int nleavers = 0;
-        for (int k = 0; k < kKeys; ++k) nleavers += s_cnt[k];
-        for (int c0 = 0; c0 < n && nleavers > 0; c0 += kRB) {
-            const int k = c0 + tid;
-            const int key = k < n ? code_key(s_key, S.code[base + k]) : -1;
-            const bool leaver = key >= 0;
-            // most chunks hold no leaver: skip the ranking entirely
-            if (!__syncthreads_or(leaver)) continue;
-            const uint64_t ball = __ballot(leaver);
-            int rank_key = 0;
+
+        const int per = ((n + kRC - 1) / kRC) * 64;
+        const int lo = min(n, wave * per), hi = min(n, lo + per);
+        const bool one = hi - lo <= 64 * kU;
+        // keys + 1 of the batch, four 64-slot chunks per register
+        uint32_t cw[kU / 4];
+        auto load = [&](int q0) {
+            const uint8_t *cp = code + q0 + lane;
+            const int left = hi - q0 - lane;  // chunk u holds a slot while 64 u < left
+            uint8_t t[kU];
 #pragma unroll
-            for (int kk = 0; kk < kKeys; ++kk) {
-                const uint64_t b = __ballot(key == kk);
-                if (key == kk) rank_key = __popcll(b & lt);
-                if (lane == 0) s_wc[wave][kk] = __popcll(b);
+            for (int u = 0; u < kU; ++u) t[u] = 64 * u < left ? cp[64 * u] : uint8_t(kStay2);
+#pragma unroll
+            for (int u = 0; u < kU; u += 4)
+                cw[u / 4] = (uint32_t)s_kb[t[u]] | ((uint32_t)s_kb[t[u + 1]] << 8) |
+                            ((uint32_t)s_kb[t[u + 2]] << 16) | ((uint32_t)s_kb[t[u + 3]] << 24);
+        };
+        auto key1 = [&](int u) { return (int)((cw[u / 4] >> (8 * (u % 4))) & 0xffu); };
+
+        // ---- walk 1: leavers per key in [lo, hi) ------------------------------
+        int cnt = 0;
+        for (int q0 = lo; q0 < hi; q0 += 64 * kU) {
+            load(q0);
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                if (q0 + 64 * u >= hi) break;
+                const int kc = key1(u);
+                uint64_t m = __ballot(kc != 0);
+                cnt += lane == kKeys ? __popcll(m) : 0;
+                while (m) {
+                    const int kk = __builtin_amdgcn_readlane(kc, __ffsll((long long)m) - 1);
+                    const uint64_t b = __ballot(kc == kk);
+                    cnt += lane == kk - 1 ? __popcll(b) : 0;
+                    m &= ~b;
+                }
             }
-            if (lane == 0) s_wc[wave][kKeys] = __popcll(ball);
-            __syncthreads();
-            if (leaver) {
-                int rk = s_run[key] + rank_key, ra = s_run[kKeys] + __popcll(ball & lt);
-                for (int w = 0; w < wave; ++w) { rk += s_wc[w][key]; ra += s_wc[w][kKeys]; }
-                S.holes[base + ra] = k;
-                if (key < kNDir2) copy_particle(S, base + k, base + s_koff[key] + rk, false, true);
-            }
-            __syncthreads();
-            if (tid <= kKeys) {
-                int add = 0;
-                for (int w = 0; w < kNW; ++w) add += s_wc[w][tid];
-                s_run[tid] += add;
-            }
-            __syncthreads();
         }
-        if (tid < kNDir2) S.kcnt[p * kNDir2 + tid] = s_cnt[tid];
-        if (tid == 0) {
-            int L = 0;
-            for (int k = 0; k < kKeys; ++k) L += s_cnt[k];
-            S.nleave[p] = L;
+        if (lane <= kKeys) s_wc[wave][lane] = cnt;
+        __syncthreads();
+
+        // ---- starting points: lane k of wave w holds the staging slot of the
+        // next key-k leaver of the wave (key offset + earlier waves), lane kKeys
+        // the next hole index ---------------------------------------------------
+        int run = 0;
+        if (lane <= kKeys) {
+            for (int w = 0; w < wave; ++w) run += s_wc[w][lane];
+            if (lane < kKeys)
+                for (int kk = 0; kk < lane; ++kk)
+                    for (int w = 0; w < kRCW; ++w) run += s_wc[w][kk];
+        }
+        if (wave == 0 && lane <= kKeys) {
+            int tot = 0;
+            for (int w = 0; w < kRCW; ++w) tot += s_wc[w][lane];
+            if (lane < kNDir2) S.kcnt[p * kNDir2 + lane] = tot;
+            if (lane == kKeys) S.nleave[p] = tot;
+        }
+
+        // ---- walk 2: list holes, queue and copy staged leavers -----------------
+        if (__builtin_amdgcn_readlane(cnt, kKeys) > 0) {
+            int2 *ring = s_ring[wave];
+            int head = 0, tail = 0;
+            for (int q0 = lo; q0 < hi; q0 += 64 * kU) {
+                if (!one) load(q0);
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    if (q0 + 64 * u >= hi) break;
+                    const int kc = key1(u);
+                    const int k = q0 + 64 * u + lane;
+                    uint64_t m = __ballot(kc != 0);
+                    if (!m) continue;
+                    const int h0 = __builtin_amdgcn_readlane(run, kKeys);
+                    if (kc) S.holes[base + h0 + __popcll(m & lt)] = k;
+                    run += lane == kKeys ? __popcll(m) : 0;
+                    const uint64_t st = m & ~__ballot(kc == kNDir2 + 1);
+                    int dest = 0;
+                    while (m) {
+                        const int kk = __builtin_amdgcn_readlane(kc, __ffsll((long long)m) - 1);
+                        const uint64_t b = __ballot(kc == kk);
+                        const int r0 = __builtin_amdgcn_readlane(run, kk - 1);
+                        if (kc == kk) dest = r0 + __popcll(b & lt);
+                        run += lane == kk - 1 ? __popcll(b) : 0;
+                        m &= ~b;
+                    }
+                    if (st) {
+                        if ((st >> lane) & 1)
+                            ring[(tail + __popcll(st & lt)) & (kRing - 1)] = make_int2(k, dest);
+                        tail += __popcll(st);
+                        __builtin_amdgcn_wave_barrier();
+                        if (tail - head >= 64) {
+                            drain_ring(S, base, ring, head, tail, lane);
+                            __builtin_amdgcn_wave_barrier();
+                        }
+                    }
+                }
+            }
+            while (head < tail) {
+                drain_ring(S, base, ring, head, tail, lane);
+                __builtin_amdgcn_wave_barrier();
+            }
         }
         __syncthreads();
     }
@@ -492,21 +574,23 @@ __global__ void k_scatter_codes(const uint8_t *__restrict__ packed,
 }  // namespace
 
 template <typename T>
-void launch_close_queue(const SimDev<T> *sims, const QueueArgs &q, hipStream_t st)
+void launch_close_queue(const SimDev<T> *sims, const QueueArgs &q, hipStream_t st, Ev2 ev)
 {
-    hipLaunchKernelGGL((k_close_queue<T>), dim3(1), dim3(kQB), 0, st, sims, q);
+    hipExtLaunchKernelGGL((k_close_queue<T>), dim3(1), dim3(kQB), 0, st, ev.start, ev.stop, 0, sims,
+                          q);
 }
 
 template <typename T>
 void launch_rebin(const SimDev<T> *sims, int nsims, const int *patch_prefix, int total_patches,
-                  int grid, hipStream_t st)
+                  int grid, hipStream_t st, Ev2 ev)
 {
-    hipLaunchKernelGGL((k_rebin_count<T>), dim3(grid), dim3(kRB), 0, st, sims, nsims, patch_prefix,
-                       total_patches);
+    // one count workgroup per patch (the hardware balances uneven patches)
+    hipExtLaunchKernelGGL((k_rebin_count<T>), dim3(std::min(total_patches, 1 << 20)), dim3(kRC), 0,
+                          st, ev.start, nullptr, 0, sims, nsims, patch_prefix, total_patches);
     hipLaunchKernelGGL((k_rebin_check<T>), dim3((total_patches + 255) / 256), dim3(256), 0, st, sims,
                        nsims, patch_prefix, total_patches);
-    hipLaunchKernelGGL((k_rebin_scatter<T>), dim3(grid), dim3(kRB), 0, st, sims, nsims,
-                       patch_prefix, total_patches);
+    hipExtLaunchKernelGGL((k_rebin_scatter<T>), dim3(grid), dim3(kRB), 0, st, nullptr, ev.stop, 0,
+                          sims, nsims, patch_prefix, total_patches);
 }
 
 template <typename T>
@@ -529,8 +613,9 @@ void launch_scatter_codes(const uint8_t *packed, const int64_t *packed_off, cons
 }
 
 #define PIC_INST(T)                                                                              \
-    template void launch_close_queue<T>(const SimDev<T> *, const QueueArgs &, hipStream_t);      \
-    template void launch_rebin<T>(const SimDev<T> *, int, const int *, int, int, hipStream_t);   \
+    template void launch_close_queue<T>(const SimDev<T> *, const QueueArgs &, hipStream_t, Ev2); \
+    template void launch_rebin<T>(const SimDev<T> *, int, const int *, int, int, hipStream_t,     \
+                                  Ev2);                                                          \
     template void launch_relayout<T>(const SimDev<T> *, const SimDev<T> *, int, hipStream_t);    \
     template void launch_rho<T>(const SimDev<T> *, int, double *, hipStream_t);
 PIC_INST(float)

@@ -1,11 +1,18 @@
 // Launch wrappers of the 2-D patch-PIC kernels (defined in the .hip files).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "pic_dev.h"
 
 namespace pic {
+
+// Optional start / stop events of a timed launch: recorded by the dispatch
+// itself (hipExtLaunchKernel), so timing adds no packets between kernels.
+struct Ev2 {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
 
 // Work item of the particle kernel: simulation slot, patch, first slot, count.
 using Item = int4;
@@ -24,14 +31,15 @@ struct QueueArgs {
 // Close the steps whose re-binning was applied (energy reduction, history,
 // step counter, budget) and build the work queue of the next step.
 template <typename T>
-void launch_close_queue(const SimDev<T> *sims, const QueueArgs &q, hipStream_t st);
+void launch_close_queue(const SimDev<T> *sims, const QueueArgs &q, hipStream_t st, Ev2 ev = {});
 
 // Persistent particle kernel: gather, Boris, move, classify, Esirkepov deposit.
 // pc: common square patch size of every simulation in the launch (16 or 32)
 // for the specialised kernel, 0 for the general one.
 template <typename T>
 void launch_particles(const SimDev<T> *sims, const Item *items, const int *nitems, int *head,
-                      int grid, int block, int maxP0, int maxP1, int pc, hipStream_t st);
+                      int grid, int block, int maxP0, int maxP1, int pc, hipStream_t st,
+                      Ev2 ev = {});
 template <typename T>
 int particles_occupancy(int block, int maxP0, int maxP1);
 
@@ -39,14 +47,14 @@ int particles_occupancy(int block, int maxP0, int maxP1);
 // other J buffer and accumulates the field energy of the incoming E, B.
 template <typename T>
 void launch_maxwell(const SimDev<T> *sims, int nsims, const int *tile_prefix, int total_tiles,
-                    int grid, int preset, hipStream_t st);
+                    int grid, int preset, hipStream_t st, Ev2 ev = {});
 template <typename T>
 void maxwell_tile(int preset, int &tx, int &ty);
 
 // Re-binning: count and stage leavers; check capacity; scatter.
 template <typename T>
 void launch_rebin(const SimDev<T> *sims, int nsims, const int *patch_prefix, int total_patches,
-                  int grid, hipStream_t st);
+                  int grid, hipStream_t st, Ev2 ev = {});
 
 // Copy particles into a new per-patch layout (capacity growth).
 template <typename T>

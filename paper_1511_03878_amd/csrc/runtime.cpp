@@ -698,27 +698,26 @@ void SimImpl<T>::check_free()
 // ---------------------------------------------------------------------------
 // timing
 
-void Timing::record(hipStream_t s, int k, bool begin)
+Ev2 Timing::pair(int k)
 {
-    if (!enabled) return;
-    if (begin) {
-        Ev e;
-        e.kind = k;
-        auto take = [&](hipEvent_t &ev) {
-            if (!pool.empty()) {
-                ev = pool.back();
-                pool.pop_back();
-            } else {
-                hipcheck(hipEventCreate(&ev), "event");
-            }
-        };
-        take(e.a);
-        take(e.b);
-        hipcheck(hipEventRecord(e.a, s), "event record");
-        events.push_back(e);
-    } else {
-        hipcheck(hipEventRecord(events.back().b, s), "event record");
-    }
+    Ev2 r;
+    if (!enabled) return r;
+    Ev e;
+    e.kind = k;
+    auto take = [&](hipEvent_t &ev) {
+        if (!pool.empty()) {
+            ev = pool.back();
+            pool.pop_back();
+        } else {
+            hipcheck(hipEventCreate(&ev), "event");
+        }
+    };
+    take(e.a);
+    take(e.b);
+    events.push_back(e);
+    r.start = e.a;
+    r.stop = e.b;
+    return r;
 }
 
 void Timing::collect()
@@ -913,10 +912,7 @@ QueueArgs BatchImpl<T>::queue_args() const
 template <typename T>
 void BatchImpl<T>::launch_close_queue_pass()
 {
-    Timing &tm = timing();
-    tm.record(stream, 0, true);
-    launch_close_queue<T>(sims_d, queue_args(), stream);
-    tm.record(stream, 0, false);
+    launch_close_queue<T>(sims_d, queue_args(), stream, timing().pair(0));
     hipcheck(hipGetLastError(), "queue launch");
 }
 
@@ -926,16 +922,11 @@ void BatchImpl<T>::launch_one_step()
 {
     const int ns = (int)members.size();
     Timing &tm = timing();
-    tm.record(stream, 1, true);
     launch_particles<T>(sims_d, items_d, nitems_d, head_d, grid_particles, block, maxP0, maxP1,
-                        patch_const, stream);
-    tm.record(stream, 1, false);
-    tm.record(stream, 2, true);
-    launch_maxwell<T>(sims_d, ns, tile_prefix_d, total_tiles, grid_maxwell, tile_preset, stream);
-    tm.record(stream, 2, false);
-    tm.record(stream, 3, true);
-    launch_rebin<T>(sims_d, ns, patch_prefix_d, total_patches, grid_rebin, stream);
-    tm.record(stream, 3, false);
+                        patch_const, stream, tm.pair(1));
+    launch_maxwell<T>(sims_d, ns, tile_prefix_d, total_tiles, grid_maxwell, tile_preset, stream,
+                      tm.pair(2));
+    launch_rebin<T>(sims_d, ns, patch_prefix_d, total_patches, grid_rebin, stream, tm.pair(3));
     launch_close_queue_pass();
 }
 

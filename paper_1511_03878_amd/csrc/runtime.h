@@ -44,7 +44,9 @@ struct Timing {
     std::vector<hipEvent_t> pool;
     double total_ms[kKinds] = {0, 0, 0, 0};
     int64_t launches[kKinds] = {0, 0, 0, 0};
-    void record(hipStream_t s, int kind, bool begin);
+    // events for one timed launch (or group of launches) of `kind`; both
+    // null when timing is off
+    Ev2 pair(int kind);
     void collect();
 };
 
