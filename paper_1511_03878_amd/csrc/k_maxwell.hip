@@ -36,13 +36,13 @@ __global__ __launch_bounds__(256) void k_maxwell2d(const SimDev<T> *__restrict__
     for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
         const int s = find_sim(tile_prefix, nsims, tile);
         const SimDev<T> &S = sims[s];
-        if (!S.st->active) continue;
+        if (!glb(S.st)->active) continue;
         const int lt = tile - tile_prefix[s];
         const int n0 = S.n[0], n1 = S.n[1], fn0 = S.fn[0], fn1 = S.fn[1];
         const int per0 = S.periodic[0], per1 = S.periodic[1];
         const int ntx = (fn0 + TX - 1) / TX;
         const int X0 = (lt % ntx) * TX, Y0 = (lt / ntx) * TY;
-        const int64_t stepn = S.st->step;
+        const int64_t stepn = glb(S.st)->step;
         T *const *Jc = S.J[stepn & 1];
         T *const *Jn = S.J[(stepn + 1) & 1];
         T *const *Fc = S.F[stepn & 1];
@@ -71,15 +71,15 @@ __global__ __launch_bounds__(256) void k_maxwell2d(const SimDev<T> *__restrict__
             const int64_t kpd = (ip >= 0 && jd >= 0) ? ip + (int64_t)fn0 * jd : -1;
             const int64_t kpp = (ip >= 0 && jp >= 0) ? ip + (int64_t)fn0 * jp : -1;
             const int64_t kdd = (id >= 0 && jd >= 0) ? id + (int64_t)fn0 * jd : -1;
-            v[r][0] = kdp >= 0 ? Fc[0][kdp] : T(0);
-            v[r][1] = kpd >= 0 ? Fc[1][kpd] : T(0);
-            v[r][2] = kpp >= 0 ? Fc[2][kpp] : T(0);
-            v[r][3] = kpd >= 0 ? Fc[3][kpd] : T(0);
-            v[r][4] = kdp >= 0 ? Fc[4][kdp] : T(0);
-            v[r][5] = kdd >= 0 ? Fc[5][kdd] : T(0);
-            v[r][6] = kdp >= 0 ? Jc[0][kdp] : T(0);
-            v[r][7] = kpd >= 0 ? Jc[1][kpd] : T(0);
-            v[r][8] = kpp >= 0 ? Jc[2][kpp] : T(0);
+            v[r][0] = kdp >= 0 ? glb(Fc[0])[kdp] : T(0);
+            v[r][1] = kpd >= 0 ? glb(Fc[1])[kpd] : T(0);
+            v[r][2] = kpp >= 0 ? glb(Fc[2])[kpp] : T(0);
+            v[r][3] = kpd >= 0 ? glb(Fc[3])[kpd] : T(0);
+            v[r][4] = kdp >= 0 ? glb(Fc[4])[kdp] : T(0);
+            v[r][5] = kdd >= 0 ? glb(Fc[5])[kdd] : T(0);
+            v[r][6] = kdp >= 0 ? glb(Jc[0])[kdp] : T(0);
+            v[r][7] = kpd >= 0 ? glb(Jc[1])[kpd] : T(0);
+            v[r][8] = kpp >= 0 ? glb(Jc[2])[kpp] : T(0);
         }
 #pragma unroll
         for (int r = 0; r < NIT; ++r) {
@@ -122,8 +122,8 @@ __global__ __launch_bounds__(256) void k_maxwell2d(const SimDev<T> *__restrict__
                     const int gj = wrap_idx(Y0 - 1 + b, n1);
                     T eyi = T(0), ezi = T(0);
                     if (ls < S.laser_steps) {
-                        if (S.laser_ey) eyi = S.laser_ey[ls * n1 + gj];
-                        if (S.laser_ez) ezi = S.laser_ez[ls * n1 + gj];
+                        if (S.laser_ey) eyi = glb(S.laser_ey)[ls * n1 + gj];
+                        if (S.laser_ez) ezi = glb(S.laser_ez)[ls * n1 + gj];
                     }
                     const int c = b * W;  // a = 0 is x-node -1 (dual -1/2 for By, Bz)
                     sB[2][c] = (T(4) * eyi - T(2) * sE[1][c + 1] - (T(1) - r) * sB[2][c + 1]) * ir;
@@ -164,16 +164,16 @@ __global__ __launch_bounds__(256) void k_maxwell2d(const SimDev<T> *__restrict__
             // components stop one node short
             const bool dx_ok = per0 || gi <= n0 - 1;
             const int64_t k = gi + (int64_t)fn0 * gj;
-            Fn[1][k] = sE[1][c];
-            Fn[2][k] = sE[2][c];
-            Fn[3][k] = bx;
-            Jn[1][k] = T(0);
-            Jn[2][k] = T(0);
+            glb(Fn[1])[k] = sE[1][c];
+            glb(Fn[2])[k] = sE[2][c];
+            glb(Fn[3])[k] = bx;
+            glb(Jn[1])[k] = T(0);
+            glb(Jn[2])[k] = T(0);
             if (dx_ok) {
-                Fn[0][k] = sE[0][c];
-                Fn[4][k] = by;
-                Fn[5][k] = bz;
-                Jn[0][k] = T(0);
+                glb(Fn[0])[k] = sE[0][c];
+                glb(Fn[4])[k] = by;
+                glb(Fn[5])[k] = bz;
+                glb(Jn[0])[k] = T(0);
             }
         }
 
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(256) void k_maxwell2d(const SimDev<T> *__restrict__
         if ((tid & 63) == 0) s_red[tid >> 6] = esum;
         __syncthreads();
         if (tid == 0)
-            S.upart[lt] = 0.5 * S.vcell * (s_red[0] + s_red[1] + s_red[2] + s_red[3]);
+            glb(S.upart)[lt] = 0.5 * S.vcell * (s_red[0] + s_red[1] + s_red[2] + s_red[3]);
         __syncthreads();
     }
 }

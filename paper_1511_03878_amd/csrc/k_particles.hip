@@ -136,7 +136,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
         const int per0 = S.periodic[0], per1 = S.periodic[1];
 
         // ---- stage E, B of nodes [ox-1, ox+P0+1] x [oy-1, oy+P1+1] --------
-        T *const *Fc = S.F[S.st->step & 1];
+        T *const *Fc = S.F[glb(S.st)->step & 1];
         // four nodes per thread per round, all loads issued before the stores
         for (int t0 = 0; t0 < fw * fh; t0 += 4 * BLOCK) {
             T v[4][6];
@@ -150,12 +150,12 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
                 const int jp = in ? axis_node(gj, n1, per1, 0) : -1;
                 const int jd = in ? axis_node(gj, n1, per1, 1) : -1;
                 // staggering: Ex (d,p) Ey (p,d) Ez (p,p) Bx (p,d) By (d,p) Bz (d,d)
-                v[r][0] = (id >= 0 && jp >= 0) ? Fc[0][id + fn0 * jp] : T(0);
-                v[r][1] = (ip >= 0 && jd >= 0) ? Fc[1][ip + fn0 * jd] : T(0);
-                v[r][2] = (ip >= 0 && jp >= 0) ? Fc[2][ip + fn0 * jp] : T(0);
-                v[r][3] = (ip >= 0 && jd >= 0) ? Fc[3][ip + fn0 * jd] : T(0);
-                v[r][4] = (id >= 0 && jp >= 0) ? Fc[4][id + fn0 * jp] : T(0);
-                v[r][5] = (id >= 0 && jd >= 0) ? Fc[5][id + fn0 * jd] : T(0);
+                v[r][0] = (id >= 0 && jp >= 0) ? glb(Fc[0])[id + fn0 * jp] : T(0);
+                v[r][1] = (ip >= 0 && jd >= 0) ? glb(Fc[1])[ip + fn0 * jd] : T(0);
+                v[r][2] = (ip >= 0 && jp >= 0) ? glb(Fc[2])[ip + fn0 * jp] : T(0);
+                v[r][3] = (ip >= 0 && jd >= 0) ? glb(Fc[3])[ip + fn0 * jd] : T(0);
+                v[r][4] = (id >= 0 && jp >= 0) ? glb(Fc[4])[id + fn0 * jp] : T(0);
+                v[r][5] = (id >= 0 && jd >= 0) ? glb(Fc[5])[id + fn0 * jd] : T(0);
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -196,8 +196,8 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
             const int kn = unit_particle(wv);
             if (kn < cnt) {
                 const int64_t g = base + kn;
-                nx_ = S.x[0][g]; ny_ = S.x[1][g];
-                nux = S.u[0][g]; nuy = S.u[1][g]; nuz = S.u[2][g]; nw_ = S.w[g];
+                nx_ = glb(S.x[0])[g]; ny_ = glb(S.x[1])[g];
+                nux = glb(S.u[0])[g]; nuy = glb(S.u[1])[g]; nuz = glb(S.u[2])[g]; nw_ = glb(S.w)[g];
             }
         }
         // units past the last full pass may map outside [0, cnt): skipped
@@ -211,8 +211,8 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
                 const int kn = unit_particle(u + NW);
                 if (kn < cnt) {
                     const int64_t gn = base + kn;
-                    nx_ = S.x[0][gn]; ny_ = S.x[1][gn];
-                    nux = S.u[0][gn]; nuy = S.u[1][gn]; nuz = S.u[2][gn]; nw_ = S.w[gn];
+                    nx_ = glb(S.x[0])[gn]; ny_ = glb(S.x[1])[gn];
+                    nux = glb(S.u[0])[gn]; nuy = glb(S.u[1])[gn]; nuz = glb(S.u[2])[gn]; nw_ = glb(S.w)[gn];
                 }
             }
             if (k >= cnt) continue;
@@ -356,27 +356,27 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
                 if (y1 > Pmax1) y1 = Pmax1;
                 code = gone ? kRemoved : (uint8_t)((sx_ + 1) + 3 * (sy_ + 1));
             }
-            S.x[0][g] = x1;
-            S.x[1][g] = y1;
-            S.u[0][g] = ux;
-            S.u[1][g] = uy;
-            S.u[2][g] = uz;
-            S.code[g] = code;
+            glb(S.x[0])[g] = x1;
+            glb(S.x[1])[g] = y1;
+            glb(S.u[0])[g] = ux;
+            glb(S.u[1])[g] = uy;
+            glb(S.u[2])[g] = uz;
+            glb(S.code)[g] = code;
         }
-        if (err) atomicOr(&S.st->flags, err);
+        if (err) __hip_atomic_fetch_or(&glb(S.st)->flags, err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
 
         // ---- flush the current tile -------------------------------------------
         {
-            T *const *Jg = S.J[S.st->step & 1];
+            T *const *Jg = S.J[glb(S.st)->step & 1];
             for (int t = tid; t < jw * jh; t += BLOCK) {
                 const int gi = ox - 2 + t % jw, gj = oy - 2 + t / jw;
                 const int ip = axis_node(gi, n0, per0, 0), id = axis_node(gi, n0, per0, 1);
                 const int jp = axis_node(gj, n1, per1, 0), jd = axis_node(gj, n1, per1, 1);
                 const T vx = (T)Jt[t], vy = (T)Jt[jstride + t], vz = (T)Jt[2 * jstride + t];
-                if (vx != T(0) && id >= 0 && jp >= 0) atomicAdd(&Jg[0][id + fn0 * jp], vx);
-                if (vy != T(0) && ip >= 0 && jd >= 0) atomicAdd(&Jg[1][ip + fn0 * jd], vy);
-                if (vz != T(0) && ip >= 0 && jp >= 0) atomicAdd(&Jg[2][ip + fn0 * jp], vz);
+                if (vx != T(0) && id >= 0 && jp >= 0) gadd(glb(Jg[0]) + (id + fn0 * jp), vx);
+                if (vy != T(0) && ip >= 0 && jd >= 0) gadd(glb(Jg[1]) + (ip + fn0 * jd), vy);
+                if (vz != T(0) && ip >= 0 && jp >= 0) gadd(glb(Jg[2]) + (ip + fn0 * jp), vz);
             }
         }
         // ---- kinetic energy and pushed count --------------------------------
@@ -389,7 +389,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
             // L2 address
             double tot = 0.0;
             for (int wv = 0; wv < BLOCK / kWave; ++wv) tot += s_red[wv];
-            atomicAdd(&S.kpart[p], tot * S.vcell);
+            gadd(glb(S.kpart) + p, tot * S.vcell);
         }
         __syncthreads();
     }

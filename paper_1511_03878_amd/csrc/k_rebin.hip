@@ -38,9 +38,9 @@ constexpr int kKeys = kNDir2 + 1;  // 9 direction keys + removed
 // patch itself, i.e. the particle stays; kNDir2 when it leaves an open face),
 // then the number of distinct source patches, the sources in ascending id and
 // the key under which each source stages the particles it sends here.
-__device__ __forceinline__ const int32_t *nb_row(const int32_t *nbt, int p)
+__device__ __forceinline__ gptr_t<const int32_t> nb_row(const int32_t *nbt, int p)
 {
-    return nbt + (int64_t)p * kNbStride;
+    return glb(nbt) + (int64_t)p * kNbStride;
 }
 
 __device__ __forceinline__ int code_key(const int *key, uint8_t c)
@@ -60,13 +60,13 @@ __device__ __forceinline__ void copy_particle(const SimDev<T> &S, int64_t from, 
     T *const *tu = to_stage ? S.su : S.u;
     T *tw = to_stage ? S.sw : S.w;
     int64_t *ti = to_stage ? S.sid : S.id;
-    tx[0][to] = fx[0][from];
-    tx[1][to] = fx[1][from];
-    tu[0][to] = fu[0][from];
-    tu[1][to] = fu[1][from];
-    tu[2][to] = fu[2][from];
-    tw[to] = fw[from];
-    ti[to] = fi[from];
+    glb(tx[0])[to] = glb(fx[0])[from];
+    glb(tx[1])[to] = glb(fx[1])[from];
+    glb(tu[0])[to] = glb(fu[0])[from];
+    glb(tu[1])[to] = glb(fu[1])[from];
+    glb(tu[2])[to] = glb(fu[2])[from];
+    glb(tw)[to] = glb(fw)[from];
+    glb(ti)[to] = glb(fi)[from];
 }
 
 // Count pass.  Each wave of the workgroup owns a contiguous range of the
@@ -110,11 +110,11 @@ __global__ __launch_bounds__(kRC) void k_rebin_count(const SimDev<T> *__restrict
     for (int gp = blockIdx.x; gp < total; gp += gridDim.x) {
         const int s = find_sim(patch_prefix, nsims, gp);
         const SimDev<T> &S = sims[s];
-        if (!S.st->active) continue;
+        if (!glb(S.st)->active) continue;
         const int p = gp - patch_prefix[s];
-        const int n = S.count[p];
-        const int64_t base = S.off[p];
-        const uint8_t *code = S.code + base;
+        const int n = glb(S.count)[p];
+        const int64_t base = glb(S.off)[p];
+        const gptr_t<const uint8_t> code = glb((const uint8_t *)S.code) + base;
         if (tid < 256) {
             int kb = 0;
             if (tid < kNDir2) kb = nb_row(S.nbt, p)[tid] + 1;
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(kRC) void k_rebin_count(const SimDev<T> *__restrict
         // keys + 1 of the batch, four 64-slot chunks per register
         uint32_t cw[kU / 4];
         auto load = [&](int q0) {
-            const uint8_t *cp = code + q0 + lane;
+            const gptr_t<const uint8_t> cp = code + q0 + lane;
             const int left = hi - q0 - lane;  // chunk u holds a slot while 64 u < left
             uint8_t t[kU];
 #pragma unroll
@@ -175,8 +175,8 @@ __global__ __launch_bounds__(kRC) void k_rebin_count(const SimDev<T> *__restrict
         if (wave == 0 && lane <= kKeys) {
             int tot = 0;
             for (int w = 0; w < kRCW; ++w) tot += s_wc[w][lane];
-            if (lane < kNDir2) S.kcnt[p * kNDir2 + lane] = tot;
-            if (lane == kKeys) S.nleave[p] = tot;
+            if (lane < kNDir2) glb(S.kcnt)[p * kNDir2 + lane] = tot;
+            if (lane == kKeys) glb(S.nleave)[p] = tot;
         }
 
         // ---- walk 2: list holes, queue and copy staged leavers -----------------
@@ -193,7 +193,7 @@ __global__ __launch_bounds__(kRC) void k_rebin_count(const SimDev<T> *__restrict
                     uint64_t m = __ballot(kc != 0);
                     if (!m) continue;
                     const int h0 = __builtin_amdgcn_readlane(run, kKeys);
-                    if (kc) S.holes[base + h0 + __popcll(m & lt)] = k;
+                    if (kc) glb(S.holes)[base + h0 + __popcll(m & lt)] = k;
                     run += lane == kKeys ? __popcll(m) : 0;
                     const uint64_t st = m & ~__ballot(kc == kNDir2 + 1);
                     int dest = 0;
@@ -234,25 +234,26 @@ __global__ __launch_bounds__(256) void k_rebin_check(const SimDev<T> *__restrict
     if (gp >= total) return;
     const int s = find_sim(patch_prefix, nsims, gp);
     const SimDev<T> &S = sims[s];
-    if (!S.st->active) return;
+    if (!glb(S.st)->active) return;
     const int q = gp - patch_prefix[s];
-    const int32_t *row = nb_row(S.nbt, q);
+    const gptr_t<const int32_t> row = nb_row(S.nbt, q);
     const int ns = row[kNDir2];
     int A = 0;
-    for (int i = 0; i < ns; ++i) A += S.kcnt[row[kNDir2 + 1 + i] * kNDir2 + row[kNDir2 + 9 + i]];
-    const int n = S.count[q], L = S.nleave[q];
+    for (int i = 0; i < ns; ++i) A += glb(S.kcnt)[row[kNDir2 + 1 + i] * kNDir2 + row[kNDir2 + 9 + i]];
+    const int n = glb(S.count)[q], L = glb(S.nleave)[q];
     const int np = n - L + A;
     // vacated slots below the new count (the list is ascending)
-    const int32_t *h = S.holes + S.off[q];
+    const gptr_t<const int32_t> h = glb((const int32_t *)S.holes) + glb(S.off)[q];
     int lo = 0, hi = L;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
         if (h[mid] < np) lo = mid + 1; else hi = mid;
     }
-    S.newcount[q] = np;
-    S.narrive[q] = A;
-    S.nhole[q] = lo;
-    if (np > S.cap[q]) atomicOr(&S.st->flags, kFlagPending);
+    glb(S.newcount)[q] = np;
+    glb(S.narrive)[q] = A;
+    glb(S.nhole)[q] = lo;
+    if (np > glb(S.cap)[q])
+        __hip_atomic_fetch_or(&glb(S.st)->flags, kFlagPending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <typename T>
@@ -272,27 +273,27 @@ __global__ __launch_bounds__(kRB) void k_rebin_scatter(const SimDev<T> *__restri
     for (int gp = blockIdx.x; gp < total; gp += gridDim.x) {
         const int s = find_sim(patch_prefix, nsims, gp);
         const SimDev<T> &S = sims[s];
-        if (!S.st->active || (S.st->flags & kFlagPending)) continue;
+        if (!glb(S.st)->active || (glb(S.st)->flags & kFlagPending)) continue;
         const int q = gp - patch_prefix[s];
-        const int n = S.count[q], np = S.newcount[q], nH = S.nhole[q], A = S.narrive[q];
-        const int64_t base = S.off[q];
-        const int32_t *row = nb_row(S.nbt, q);
+        const int n = glb(S.count)[q], np = glb(S.newcount)[q], nH = glb(S.nhole)[q], A = glb(S.narrive)[q];
+        const int64_t base = glb(S.off)[q];
+        const gptr_t<const int32_t> row = nb_row(S.nbt, q);
         if (tid < 8) {
             // one thread per source: its count and staging base for this patch
             const int ns = row[kNDir2];
             if (tid < ns) {
                 const int sp = row[kNDir2 + 1 + tid], k = row[kNDir2 + 9 + tid];
                 int koff = 0;
-                for (int e = 0; e < k; ++e) koff += S.kcnt[sp * kNDir2 + e];
+                for (int e = 0; e < k; ++e) koff += glb(S.kcnt)[sp * kNDir2 + e];
                 s_src[tid] = sp;
                 s_skey[tid] = k;
-                s_scnt[tid] = S.kcnt[sp * kNDir2 + k];
-                s_sbase[tid] = S.off[sp] + koff;
+                s_scnt[tid] = glb(S.kcnt)[sp * kNDir2 + k];
+                s_sbase[tid] = glb(S.off)[sp] + koff;
             }
             if (tid == 0) {
                 s_ns = ns;
                 s_run = 0;
-                if (q == 0) S.st->rebinned = 1u;
+                if (q == 0) glb(S.st)->rebinned = 1u;
             }
         } else if (tid < 8 + kNDir2) {
             s_key[tid - 8] = row[tid - 8];
@@ -304,7 +305,7 @@ __global__ __launch_bounds__(kRB) void k_rebin_scatter(const SimDev<T> *__restri
             const int c = s_scnt[i];
             for (int j = tid; j < c; j += kRB) {
                 const int a = abase + j;
-                const int target = a < nH ? S.holes[base + a] : n + (a - nH);
+                const int target = a < nH ? glb(S.holes)[base + a] : n + (a - nH);
                 copy_particle(S, s_sbase[i] + j, base + target, true, false);
             }
             abase += c;
@@ -315,7 +316,7 @@ __global__ __launch_bounds__(kRB) void k_rebin_scatter(const SimDev<T> *__restri
                 const int k = c0 + tid;
                 bool stay = false;
                 if (k < n) {
-                    const uint8_t c = S.code[base + k];
+                    const uint8_t c = glb(S.code)[base + k];
                     stay = c != kRemoved && s_key[c] < 0;
                 }
                 const uint64_t b = __ballot(stay);
@@ -324,7 +325,7 @@ __global__ __launch_bounds__(kRB) void k_rebin_scatter(const SimDev<T> *__restri
                 if (stay) {
                     int r = s_run + __popcll(b & lt);
                     for (int w = 0; w < wave; ++w) r += s_wc[w];
-                    copy_particle(S, base + k, base + S.holes[base + A + r], false, false);
+                    copy_particle(S, base + k, base + glb(S.holes)[base + A + r], false, false);
                 }
                 __syncthreads();
                 if (tid == 0) {
@@ -336,11 +337,13 @@ __global__ __launch_bounds__(kRB) void k_rebin_scatter(const SimDev<T> *__restri
             }
         }
         if (tid == 0) {
-            S.count[q] = np;
+            glb(S.count)[q] = np;
             int staged = 0;
-            for (int k = 0; k < kNDir2; ++k) staged += S.kcnt[q * kNDir2 + k];
-            const int removed = S.nleave[q] - staged;
-            if (removed) atomicAdd((unsigned long long *)&S.st->removed, (unsigned long long)removed);
+            for (int k = 0; k < kNDir2; ++k) staged += glb(S.kcnt)[q * kNDir2 + k];
+            const int removed = glb(S.nleave)[q] - staged;
+            if (removed)
+                __hip_atomic_fetch_add(&glb(S.st)->removed, (uint64_t)removed, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();
     }
@@ -361,6 +364,7 @@ __global__ __launch_bounds__(kRB) void k_rebin_scatter(const SimDev<T> *__restri
 constexpr int kQB = 1024;   // threads of the single queue workgroup
 constexpr int kQW = kQB / 64;
 constexpr int kBuckets = 1024;
+constexpr int kCntCache = 8192;
 
 template <typename T>
 __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict__ sims,
@@ -369,6 +373,8 @@ __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict
     __shared__ int s_hist[kBuckets];
     __shared__ uint8_t s_act[kMaxBatch];
     __shared__ int s_pushed[kMaxBatch];
+    __shared__ int s_pp[kMaxBatch + 1];  // patch prefix of the batch
+    __shared__ int s_cnt[kCntCache];     // particle counts of the first kCntCache patches
     __shared__ int s_wsum[kQW];
     __shared__ double s_red[kQW][2];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -389,17 +395,21 @@ __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict
         uint32_t flags = 0;
         if (s < nsims) {
             const SimDev<T> &S = sims[s];
-            SimState *st = S.st;
+            const gptr_t<SimState> st = glb(S.st);
             flags = st->flags;
             left = st->steps_left;
             closing = st->active && st->rebinned && !(flags & kFlagPending);
             double u = 0.0, k = 0.0;
             if (closing) {
                 const int nt = qa.tile_prefix[s + 1] - qa.tile_prefix[s];
-                for (int i = sub * 64 + lane; i < nt; i += G * 64) u += S.upart[i];
+                const gptr_t<const double> up = glb((const double *)S.upart);
+                const gptr_t<double> kp = glb(S.kpart);
+#pragma unroll 8
+                for (int i = sub * 64 + lane; i < nt; i += G * 64) u += up[i];
+#pragma unroll 8
                 for (int i = sub * 64 + lane; i < S.npatch; i += G * 64) {
-                    k += S.kpart[i];
-                    S.kpart[i] = 0.0;
+                    k += kp[i];
+                    kp[i] = 0.0;
                 }
 #pragma unroll
                 for (int o = 32; o > 0; o >>= 1) {
@@ -412,13 +422,13 @@ __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict
         __syncthreads();
         if (s < nsims && sub == 0 && lane == 0) {
             const SimDev<T> &S = sims[s];
-            SimState *st = S.st;
+            const gptr_t<SimState> st = glb(S.st);
             if (closing) {
                 double u = 0.0, k = 0.0;
                 for (int w = wave; w < wave + G; ++w) { u += s_red[w][0]; k += s_red[w][1]; }
                 if (left > 0) left -= 1;
                 const int64_t n = st->step;
-                double *h = S.hist + (n % kHistLen) * 4;
+                gptr_t<double> h = glb(S.hist) + (n % kHistLen) * 4;
                 h[0] = u;
                 h[1] = k;
                 h[2] = (double)st->pushed;
@@ -437,10 +447,36 @@ __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict
         __syncthreads();
     }
     for (int b = tid; b < kBuckets; b += kQB) s_hist[b] = 0;
+    for (int i = tid; i <= nsims; i += kQB) s_pp[i] = qa.patch_prefix[i];
     __syncthreads();
 
+    // ---- particle counts of the first kCntCache patches, loaded together ----------
+    const int total = s_pp[nsims];
+    const int ncache = min(total, kCntCache);
+    for (int g0 = 0; g0 < ncache; g0 += 8 * kQB) {
+        int v[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int gp = g0 + r * kQB + tid;
+            v[r] = 0;
+            if (gp < ncache) {
+                const int s = find_sim(s_pp, nsims, gp);
+                if (s_act[s]) v[r] = glb((const int32_t *)sims[s].count)[gp - s_pp[s]];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int gp = g0 + r * kQB + tid;
+            if (gp < ncache) s_cnt[gp] = v[r];
+        }
+    }
+    __syncthreads();
+    auto count_of = [&](int gp, int s) {
+        if (gp < kCntCache) return s_cnt[gp];
+        return s_act[s] ? glb((const int32_t *)sims[s].count)[gp - s_pp[s]] : 0;
+    };
+
     // ---- phase B: chunk histogram (bucket 0 = largest chunks) ------------------------
-    const int total = qa.patch_prefix[nsims];
     const int chunk = qa.chunk;
     auto bucket = [&](int c) { return kBuckets - 1 - (int)(((int64_t)(c - 1) * kBuckets) / chunk); };
     // lanes adding to one bucket are combined into a single LDS atomic
@@ -465,8 +501,8 @@ __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict
         const int gp = g0 + tid;
         int s = 0, n = 0;
         if (gp < total) {
-            s = find_sim(qa.patch_prefix, nsims, gp);
-            if (s_act[s]) n = sims[s].count[gp - qa.patch_prefix[s]];
+            s = find_sim(s_pp, nsims, gp);
+            n = count_of(gp, s);
             if (n) atomicAdd(&s_pushed[s], n);
         }
         for (int c0 = 0; __any(c0 < n); c0 += chunk) {
@@ -476,7 +512,7 @@ __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict
     }
     __syncthreads();
     for (int s = tid; s < nsims; s += kQB)
-        if (s_act[s]) sims[s].st->pushed = s_pushed[s];
+        if (s_act[s]) glb(sims[s].st)->pushed = s_pushed[s];
     // exclusive scan of the histogram (one bucket per thread)
     const int v = s_hist[tid];
     int incl = v;
@@ -499,20 +535,26 @@ __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict
         const int gp = g0 + tid;
         int s = 0, p = 0, n = 0;
         if (gp < total) {
-            s = find_sim(qa.patch_prefix, nsims, gp);
-            p = gp - qa.patch_prefix[s];
-            if (s_act[s]) n = sims[s].count[p];
+            s = find_sim(s_pp, nsims, gp);
+            p = gp - s_pp[s];
+            n = count_of(gp, s);
         }
         for (int c0 = 0; __any(c0 < n); c0 += chunk) {
             const bool has = c0 < n;
             const int c = has ? min(chunk, n - c0) : 0;
             const int pos = aggregated_add(has, has ? bucket(c) : 0, s_hist, true);
-            if (has && pos < qa.max_items) qa.items[pos] = make_int4(s, p, c0, c);
+            if (has && pos < qa.max_items) {
+                const gptr_t<int> it = glb(reinterpret_cast<int *>(qa.items)) + 4 * (int64_t)pos;
+                it[0] = s;
+                it[1] = p;
+                it[2] = c0;
+                it[3] = c;
+            }
         }
     }
     if (tid == 0) {
-        *qa.nitems = min(ntot, qa.max_items);
-        *qa.head = 0;
+        *glb(qa.nitems) = min(ntot, qa.max_items);
+        *glb(qa.head) = 0;
     }
 }
 

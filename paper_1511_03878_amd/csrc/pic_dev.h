@@ -121,6 +121,26 @@ __device__ __forceinline__ int neighbour2(const SimDev<T> &S, int p, int dir)
     return qx + S.np[0] * qy;
 }
 
+// Global-memory view of a device pointer read from a descriptor.  The
+// compiler cannot tell the address space of such a pointer and would emit
+// flat instructions, which also occupy the LDS counter (so a wait for an LDS
+// result waits for every flat load in flight) and need 64-bit lane addresses.
+template <typename T>
+using gptr_t = __attribute__((address_space(1))) T *;
+
+template <typename T>
+__device__ __forceinline__ gptr_t<T> glb(T *p)
+{
+    return (gptr_t<T>)p;
+}
+
+// Relaxed device-scope atomic add on global memory.
+template <typename T>
+__device__ __forceinline__ void gadd(gptr_t<T> p, T v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Locate the simulation of a global work index through an exclusive prefix
 // table of per-simulation work counts (nsims + 1 entries).
 __device__ __forceinline__ int find_sim(const int *prefix, int nsims, int g)
