@@ -168,7 +168,12 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
         for (int t = tid; t < 3 * jstride; t += BLOCK) Jt[t] = 0.0;
         __syncthreads();
 
-        const int64_t base = S.off[p] + first;
+        const int64_t base = glb(S.off)[p] + first;
+        // the item's particles through 32-bit offsets from per-item bases
+        const gptr_t<T> X0 = glb(S.x[0]) + base, X1 = glb(S.x[1]) + base;
+        const gptr_t<T> U0 = glb(S.u[0]) + base, U1 = glb(S.u[1]) + base, U2 = glb(S.u[2]) + base;
+        const gptr_t<const T> Wt = glb((const T *)S.w) + base;
+        const gptr_t<uint8_t> Cd = glb(S.code) + base;
         const T dt = S.dt, q = S.q, m = S.m;
         const T eps = q * dt / (T(2) * m);
         const T rdx = dt / S.d[0], rdy = dt / S.d[1];
@@ -189,15 +194,14 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
         // the current one is pushed.
         constexpr int NW = BLOCK / kWave;
         const int S_ = S.lane_stride;
-        const int wv = tid / kWave, ln = tid % kWave;
+        const int wv = __builtin_amdgcn_readfirstlane(tid / kWave), ln = tid % kWave;
         auto unit_particle = [&](int u) { return kWave * S_ * (u / S_) + ln * S_ + (u % S_); };
         T nx_ = T(0), ny_ = T(0), nux = T(0), nuy = T(0), nuz = T(0), nw_ = T(0);
         {
             const int kn = unit_particle(wv);
             if (kn < cnt) {
-                const int64_t g = base + kn;
-                nx_ = glb(S.x[0])[g]; ny_ = glb(S.x[1])[g];
-                nux = glb(S.u[0])[g]; nuy = glb(S.u[1])[g]; nuz = glb(S.u[2])[g]; nw_ = glb(S.w)[g];
+                nx_ = X0[kn]; ny_ = X1[kn];
+                nux = U0[kn]; nuy = U1[kn]; nuz = U2[kn]; nw_ = Wt[kn];
             }
         }
         // units past the last full pass may map outside [0, cnt): skipped
@@ -210,13 +214,11 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
             if (u + NW < uend) {
                 const int kn = unit_particle(u + NW);
                 if (kn < cnt) {
-                    const int64_t gn = base + kn;
-                    nx_ = glb(S.x[0])[gn]; ny_ = glb(S.x[1])[gn];
-                    nux = glb(S.u[0])[gn]; nuy = glb(S.u[1])[gn]; nuz = glb(S.u[2])[gn]; nw_ = glb(S.w)[gn];
+                    nx_ = X0[kn]; ny_ = X1[kn];
+                    nux = U0[kn]; nuy = U1[kn]; nuz = U2[kn]; nw_ = Wt[kn];
                 }
             }
             if (k >= cnt) continue;
-            const int64_t g = base + k;
 
             // ---- gather ---------------------------------------------------
             const int ipx = (int)floor(xl + T(0.5)), idx_ = (int)floor(xl);
@@ -253,8 +255,14 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
             uz = umz + eps * Ez;
             const T usq1 = ux * ux + uy * uy + uz * uz;
             const T ig1 = rsq_(T(1) + usq1);
-            {
-                // w m ((gamma0 - 1) + (gamma1 - 1)) / 2 with gamma - 1 = u^2 / (gamma + 1)
+            // w m ((gamma0 - 1) + (gamma1 - 1)) / 2 with gamma - 1 = u^2 / (gamma + 1)
+            // (no cancellation; FP32 storage keeps the diagnostic in FP32
+            // arithmetic, summed in FP64)
+            if constexpr (sizeof(T) == 4) {
+                const float a0 = 1.0f + usq0;
+                const float g0p = a0 * rsq_(a0) + 1.0f, g1p = (1.0f + usq1) * ig1 + 1.0f;
+                kin += (double)(wgt * m * 0.5f * (usq0 * rcp_(g0p) + usq1 * rcp_(g1p)));
+            } else {
                 const double g0p = sqrt(1.0 + (double)usq0) + 1.0;
                 const double g1p = (double)(T(1) + usq1) * (double)ig1 + 1.0;
                 kin += (double)wgt * (double)m * 0.5 *
@@ -356,12 +364,12 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
                 if (y1 > Pmax1) y1 = Pmax1;
                 code = gone ? kRemoved : (uint8_t)((sx_ + 1) + 3 * (sy_ + 1));
             }
-            glb(S.x[0])[g] = x1;
-            glb(S.x[1])[g] = y1;
-            glb(S.u[0])[g] = ux;
-            glb(S.u[1])[g] = uy;
-            glb(S.u[2])[g] = uz;
-            glb(S.code)[g] = code;
+            X0[k] = x1;
+            X1[k] = y1;
+            U0[k] = ux;
+            U1[k] = uy;
+            U2[k] = uz;
+            Cd[k] = code;
         }
         if (err) __hip_atomic_fetch_or(&glb(S.st)->flags, err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();

@@ -477,25 +477,20 @@ __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict
     };
 
     // ---- phase B: chunk histogram (bucket 0 = largest chunks) ------------------------
+    // A patch of n particles gives n / chunk full chunks (bucket 0) and one
+    // partial chunk.  Full chunks of a wave are counted with one LDS atomic
+    // (wave sum) and placed by a wave prefix sum; a partial chunk takes one
+    // LDS atomic on its own bucket.  Items of one bucket land in arbitrary
+    // order.
     const int chunk = qa.chunk;
     auto bucket = [&](int c) { return kBuckets - 1 - (int)(((int64_t)(c - 1) * kBuckets) / chunk); };
-    // lanes adding to one bucket are combined into a single LDS atomic
-    auto aggregated_add = [&](bool has, int b, int *counter_base, bool want_slot) {
-        uint64_t todo = __ballot(has);
-        int slot = -1;
-        while (todo) {
-            const int leader = __ffsll((unsigned long long)todo) - 1;
-            const int bl = __shfl(b, leader, 64);
-            const uint64_t same = __ballot(has && b == bl);
-            int base = 0;
-            if (lane == leader) base = atomicAdd(&counter_base[bl], __popcll(same));
-            if (want_slot) {
-                base = __shfl(base, leader, 64);
-                if (has && b == bl) slot = base + __popcll(same & lt);
-            }
-            todo &= ~same;
+    auto wave_incl_scan = [&](int v) {
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(v, o, 64);
+            if (lane >= o) v += y;
         }
-        return slot;
+        return v;
     };
     for (int g0 = 0; g0 < total; g0 += kQB) {
         const int gp = g0 + tid;
@@ -503,24 +498,29 @@ __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict
         if (gp < total) {
             s = find_sim(s_pp, nsims, gp);
             n = count_of(gp, s);
-            if (n) atomicAdd(&s_pushed[s], n);
         }
-        for (int c0 = 0; __any(c0 < n); c0 += chunk) {
-            const bool has = c0 < n;
-            aggregated_add(has, has ? bucket(min(chunk, n - c0)) : 0, s_hist, false);
+        // pushed particles per simulation: one LDS atomic per simulation per wave
+        uint64_t todo = __ballot(n > 0);
+        while (todo) {
+            const int sl = __shfl(s, __ffsll((unsigned long long)todo) - 1, 64);
+            const uint64_t same = __ballot(n > 0 && s == sl);
+            int v = (n > 0 && s == sl) ? n : 0;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (lane == 0) atomicAdd(&s_pushed[sl], v);
+            todo &= ~same;
         }
+        const int nfull = n / chunk, rem = n - nfull * chunk;
+        const int fsum = __shfl(wave_incl_scan(nfull), 63, 64);
+        if (lane == 0 && fsum) atomicAdd(&s_hist[0], fsum);
+        if (rem) atomicAdd(&s_hist[bucket(rem)], 1);
     }
     __syncthreads();
     for (int s = tid; s < nsims; s += kQB)
         if (s_act[s]) glb(sims[s].st)->pushed = s_pushed[s];
     // exclusive scan of the histogram (one bucket per thread)
     const int v = s_hist[tid];
-    int incl = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += y;
-    }
+    int incl = wave_incl_scan(v);
     if (lane == 63) s_wsum[wave] = incl;
     __syncthreads();
     int woff = 0;
@@ -531,6 +531,15 @@ __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict
     s_hist[tid] = woff + incl - v;
     __syncthreads();
     // ---- phase B: placement ------------------------------------------------------
+    const gptr_t<int> items = glb(reinterpret_cast<int *>(qa.items));
+    auto put = [&](int pos, int s, int p, int c0, int c) {
+        if (pos >= qa.max_items) return;
+        const gptr_t<int> it = items + 4 * (int64_t)pos;
+        it[0] = s;
+        it[1] = p;
+        it[2] = c0;
+        it[3] = c;
+    };
     for (int g0 = 0; g0 < total; g0 += kQB) {
         const int gp = g0 + tid;
         int s = 0, p = 0, n = 0;
@@ -539,18 +548,14 @@ __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict
             p = gp - s_pp[s];
             n = count_of(gp, s);
         }
-        for (int c0 = 0; __any(c0 < n); c0 += chunk) {
-            const bool has = c0 < n;
-            const int c = has ? min(chunk, n - c0) : 0;
-            const int pos = aggregated_add(has, has ? bucket(c) : 0, s_hist, true);
-            if (has && pos < qa.max_items) {
-                const gptr_t<int> it = glb(reinterpret_cast<int *>(qa.items)) + 4 * (int64_t)pos;
-                it[0] = s;
-                it[1] = p;
-                it[2] = c0;
-                it[3] = c;
-            }
-        }
+        const int nfull = n / chunk, rem = n - nfull * chunk;
+        const int incl_f = wave_incl_scan(nfull);
+        const int fsum = __shfl(incl_f, 63, 64);
+        int fbase = 0;
+        if (lane == 0 && fsum) fbase = atomicAdd(&s_hist[0], fsum);
+        fbase = __shfl(fbase, 0, 64) + incl_f - nfull;
+        for (int k = 0; k < nfull; ++k) put(fbase + k, s, p, k * chunk, chunk);
+        if (rem) put(atomicAdd(&s_hist[bucket(rem)], 1), s, p, nfull * chunk, rem);
     }
     if (tid == 0) {
         *glb(qa.nitems) = min(ntot, qa.max_items);
