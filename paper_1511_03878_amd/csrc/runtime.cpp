@@ -606,7 +606,13 @@ void SimImpl<T>::grow_capacity()
     hipcheck(hipMemcpyAsync(nxt.data(), newcount_d, sizeof(int32_t) * npatch, hipMemcpyDeviceToHost, stream), "newcount");
     hipcheck(hipStreamSynchronize(stream), "sync");
     std::vector<int32_t> need(npatch);
-    for (int p = 0; p < npatch; ++p) need[p] = std::max(cur[p], nxt[p]);
+    // a patch that overflowed is usually still filling (density compression
+    // moves with the driver): size it for twice its new count, so that it
+    // does not overflow again a few steps later
+    for (int p = 0; p < npatch; ++p) {
+        need[p] = std::max(cur[p], nxt[p]);
+        if (p < (int)cap_h.size() && nxt[p] > cap_h[p]) need[p] = (int32_t)std::min<int64_t>(2LL * nxt[p], INT32_MAX / 4);
+    }
     SimDev<T> oldv = v;
     SimDev<T> *oldv_d = (SimDev<T> *)alloc.get(sizeof(SimDev<T>));
     hipcheck(hipMemcpyAsync(oldv_d, &oldv, sizeof(oldv), hipMemcpyHostToDevice, stream), "old view");
