@@ -101,3 +101,69 @@ def esirkepov_quadrature_2d(x0, x1, w, q, vz, d, dt, n):
 def div_dual_2d(Jx, Jy, d):
     """Backward-difference divergence of dual-located currents onto primal nodes."""
     return (Jx - np.roll(Jx, 1, axis=1)) / d[0] + (Jy - np.roll(Jy, 1, axis=0)) / d[1]
+
+
+# ---------------------------------------------------------------------------
+# 3-D (periodic) references, arrays shaped (nz, ny, nx)
+
+STAG3 = [(1, 0, 0), (0, 1, 0), (0, 0, 1), (0, 1, 1), (1, 0, 1), (1, 1, 0)]
+
+
+def _outer3(sx, sy, sz):
+    return sz[:, None, None] * sy[None, :, None] * sx[None, None, :]
+
+
+def gather_3d(fields, xi, n):
+    """Brute-force gather on a periodic 3-D grid: sum over every node (and its
+    images) of F * S2 * S2 * S2 with each component's own staggering
+    (Ex, Ey, Ez half a cell up along their own axis; Bx, By, Bz half a cell
+    up along the two other axes)."""
+    out = []
+    for c in range(6):
+        s = [shape_on_axis(xi[a], n[a], STAG3[c][a]) for a in range(3)]
+        out.append(float(np.sum(fields[c] * _outer3(*s))))
+    return np.array(out)
+
+
+def rho_3d(xs, w, q, n):
+    """Charge density on primal nodes of a periodic 3-D grid."""
+    out = np.zeros((n[2], n[1], n[0]))
+    for k in range(len(w)):
+        s = [shape_on_axis(xs[a][k], n[a]) for a in range(3)]
+        out += q * w[k] * _outer3(*s)
+    return out
+
+
+def esirkepov_quadrature_3d(x0, x1, w, q, d, dt, n):
+    """Currents of one particle moving x0 -> x1 on a periodic 3-D grid: W_a is
+    the time integral of DS_a times the linearly interpolated transverse
+    shapes (two-point Gauss-Legendre, exact for the quadratic-in-t
+    integrand); J_a is the running sum of -q w (d_a/dt) W_a along axis a,
+    started far from the particle.  Returns [Jx, Jy, Jz], each (nz, ny, nx)."""
+    S0 = [shape_on_axis(x0[a], n[a]) for a in range(3)]
+    DS = [shape_on_axis(x1[a], n[a]) - S0[a] for a in range(3)]
+    out = []
+    for a in range(3):
+        Wa = np.zeros((n[2], n[1], n[0]))
+        for t, wt in GL2:
+            s = [S0[b] + t * DS[b] for b in range(3)]
+            s[a] = DS[a]
+            Wa += wt * _outer3(*s)
+        coef = -q * w * d[a] / dt
+        axis = 2 - a  # array axis of grid axis a
+        start = (int(math.floor(x0[a])) + n[a] // 2) % n[a]
+        Ja = np.zeros_like(Wa)
+        acc = np.zeros(np.delete(Wa.shape, axis))
+        for k in range(n[a]):
+            i = (start + k) % n[a]
+            acc = acc + coef * np.take(Wa, i, axis=axis)
+            idx = [slice(None)] * 3
+            idx[axis] = i
+            Ja[tuple(idx)] = acc
+        out.append(Ja)
+    return out
+
+
+def div_dual_3d(J, d):
+    """Backward-difference divergence of dual-located currents onto primal nodes."""
+    return sum((J[a] - np.roll(J[a], 1, axis=2 - a)) / d[a] for a in range(3))
