@@ -12,7 +12,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpic.so")
 
-SOURCES = ["k_particles.hip", "k_maxwell.hip", "k_rebin.hip", "runtime.cpp", "capi.cpp"]
+SOURCES = ["k_particles.hip", "k_particles3d.hip", "k_maxwell.hip", "k_maxwell3d.hip", "k_rebin.hip",
+           "runtime.cpp", "capi.cpp"]
 
 FLAGS = [
     "-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -115,9 +115,10 @@ int pic_particles_set(PicSim *s, int64_t n, const double *x, const double *y, co
     if (n < 0) return bad(PIC_EINVAL, "negative particle count");
     if (n > 0 && (!x || !y || !ux || !uy || !w)) return bad(PIC_EINVAL, "null particle array");
     if (n > (int64_t)1 << 34) return bad(PIC_EINVAL, "too many particles");
-    (void)z;
+    const bool three = s->impl->desc.ndim == 3;
+    if (n > 0 && three && !z) return bad(PIC_EINVAL, "null z positions in a 3-D box");
     return guarded([&] {
-        const double *xs[3] = {x, y, nullptr};
+        const double *xs[3] = {x, y, three ? z : nullptr};
         const double *us[3] = {ux, uy, uz};
         s->impl->set_particles(n, xs, us, w);
     });
@@ -127,6 +128,7 @@ int pic_laser_set(PicSim *s, int64_t nsteps, const double *ey, const double *ez)
 {
     if (!s) return bad(PIC_EINVAL, "null handle");
     if (nsteps < 0) return bad(PIC_EINVAL, "negative table length");
+    if (s->impl->desc.ndim != 2) return bad(PIC_ENOTSUP, "laser injection is 2-D only");
     if (s->impl->desc.periodic[0]) return bad(PIC_ESTATE, "the driven face needs an open x axis");
     return guarded([&] { s->impl->set_laser(nsteps, ey, ez); });
 }
@@ -136,7 +138,8 @@ static size_t field_count(PicSim *s)
     const PicSimDesc &d = s->impl->desc;
     size_t fx = d.periodic[0] ? d.n[0] : d.n[0] + 1;
     size_t fy = d.periodic[1] ? d.n[1] : d.n[1] + 1;
-    return fx * fy;
+    size_t fz = d.ndim == 3 ? (size_t)d.n[2] : 1;
+    return fx * fy * fz;
 }
 
 int pic_fields_set(PicSim *s, int comp, const double *host, size_t count)
@@ -285,20 +288,26 @@ int pic_estimate_bytes(const PicSimDesc *d, int64_t nparticles, int64_t laser_st
     int rc = validate_desc(*d, why);
     if (rc != PIC_OK) return bad(rc, why.c_str());
     const int64_t s = d->precision == 32 ? 4 : 8;
+    const bool three = d->ndim == 3;
     const int64_t fx = d->periodic[0] ? d->n[0] : d->n[0] + 1;
     const int64_t fy = d->periodic[1] ? d->n[1] : d->n[1] + 1;
-    const int64_t fsize = fx * fy;
-    const int64_t npatch = (int64_t)(d->n[0] / d->patch[0]) * (d->n[1] / d->patch[1]);
+    const int64_t fz = three ? d->n[2] : 1;
+    const int64_t fsize = fx * fy * fz;
+    const int64_t npatch = (int64_t)(d->n[0] / d->patch[0]) * (d->n[1] / d->patch[1]) *
+                           (three ? d->n[2] / d->patch[2] : 1);
+    const int64_t ndir = three ? 27 : 9;
     const double factor = d->capacity_factor > 0.0 ? d->capacity_factor : 2.0;
     const int64_t mean = std::max<int64_t>(64, (nparticles + npatch - 1) / npatch);
     const int64_t floor_cap = d->min_capacity ? d->min_capacity : mean;
     // capacity policy: max(factor x count, floor) per patch, rounded up to 64
     int64_t slots = std::max<int64_t>((int64_t)(factor * nparticles), floor_cap * npatch) + 64 * npatch;
-    const int64_t per_slot = 2 * (6 * s + 8) + 1 + 4;  // particles + staging, code, hole list
-    const int64_t max_tiles = ((fx + 15) / 16) * ((fy + 3) / 4);
+    // particles + staging, code, hole list
+    const int64_t per_slot = 2 * ((three ? 7 : 6) * s + 8) + 1 + 4;
+    const int64_t max_tiles = three ? (fsize + 255) / 256 : ((fx + 15) / 16) * ((fy + 3) / 4);
     int64_t b = 18 * fsize * s;                        // two E, B buffers, two J buffers
     b += slots * per_slot;
-    b += npatch * (4 * 7 + 4 * 9 + 4 * 26 + 8 + 8 + 4);  // counts, keys, neighbour table, partials, offsets
+    // counts, keys, neighbour table, partials, offsets
+    b += npatch * (4 * 7 + 4 * ndir + 4 * (3 * ndir - 1) + 8 + 8 + 4);
     b += max_tiles * 8 + 8 * 4 * 4096 + 4096;          // tile partials, history, state
     b += laser_steps * d->n[1] * s * 2;
     *bytes = b;
@@ -311,14 +320,21 @@ int pic_batch_create(int32_t ndim, int32_t precision, void *hip_stream, PicBatch
 {
     if (!out) return bad(PIC_EINVAL, "null output");
     *out = nullptr;
-    if (ndim != 2) return bad(PIC_ENOTSUP, "ndim must be 2");
+    if (ndim != 2 && ndim != 3) return bad(PIC_ENOTSUP, "ndim must be 2 or 3");
     if (precision != 32 && precision != 64) return bad(PIC_EINVAL, "precision must be 32 or 64");
     return guarded([&] {
         PicBatch *b = new PicBatch;
         b->ndim = ndim;
         b->precision = precision;
-        if (precision == 32) b->impl = new BatchImpl<float>((hipStream_t)hip_stream);
-        else b->impl = new BatchImpl<double>((hipStream_t)hip_stream);
+        if (precision == 32) {
+            auto *bi = new BatchImpl<float>((hipStream_t)hip_stream);
+            bi->nd = ndim;
+            b->impl = bi;
+        } else {
+            auto *bi = new BatchImpl<double>((hipStream_t)hip_stream);
+            bi->nd = ndim;
+            b->impl = bi;
+        }
         b->impl->precision = precision;
         b->impl->stream = (hipStream_t)hip_stream;
         *out = b;

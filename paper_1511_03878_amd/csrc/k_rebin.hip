@@ -30,22 +30,18 @@ namespace {
 
 constexpr int kRB = 256;  // threads per re-binning workgroup
 constexpr int kNW = kRB / 64;
-constexpr int kKeys = kNDir2 + 1;  // 9 direction keys + removed
 
 // The neighbour table of a simulation (built once on the host from the patch
-// grid) holds per patch: the canonical key of each of the 9 directions (the
+// grid) holds per patch: the canonical key of each of the ND directions (the
 // smallest direction reaching the same neighbour; -1 when the neighbour is the
-// patch itself, i.e. the particle stays; kNDir2 when it leaves an open face),
+// patch itself, i.e. the particle stays; ND when it leaves an open face),
 // then the number of distinct source patches, the sources in ascending id and
-// the key under which each source stages the particles it sends here.
+// the key under which each source stages the particles it sends here.  Key ND
+// also stands for a removed particle.
+template <int ND>
 __device__ __forceinline__ gptr_t<const int32_t> nb_row(const int32_t *nbt, int p)
 {
-    return glb(nbt) + (int64_t)p * kNbStride;
-}
-
-__device__ __forceinline__ int code_key(const int *key, uint8_t c)
-{
-    return c == kRemoved ? kNDir2 : key[c];
+    return glb(nbt) + (int64_t)p * nb_stride(ND);
 }
 
 template <typename T>
@@ -62,6 +58,7 @@ __device__ __forceinline__ void copy_particle(const SimDev<T> &S, int64_t from, 
     int64_t *ti = to_stage ? S.sid : S.id;
     glb(tx[0])[to] = glb(fx[0])[from];
     glb(tx[1])[to] = glb(fx[1])[from];
+    if (S.ndim == 3) glb(tx[2])[to] = glb(fx[2])[from];
     glb(tu[0])[to] = glb(fu[0])[from];
     glb(tu[1])[to] = glb(fu[1])[from];
     glb(tu[2])[to] = glb(fu[2])[from];
@@ -97,10 +94,11 @@ __device__ __forceinline__ void drain_ring(const SimDev<T> &S, int64_t base, con
     head += n;
 }
 
-template <typename T>
+template <typename T, int ND>
 __global__ __launch_bounds__(kRC) void k_rebin_count(const SimDev<T> *__restrict__ sims, int nsims,
                                                      const int *__restrict__ patch_prefix, int total)
 {
+    constexpr int kKeys = ND + 1;           // ND direction keys + removed
     __shared__ uint8_t s_kb[256];           // code -> key + 1 (0: the particle stays)
     __shared__ int s_wc[kRCW][kKeys + 1];   // per wave: leavers of each key, then of all keys
     __shared__ int2 s_ring[kRCW][kRing];    // per wave: (slot, staging slot) of queued leavers
@@ -117,8 +115,8 @@ __global__ __launch_bounds__(kRC) void k_rebin_count(const SimDev<T> *__restrict
         const gptr_t<const uint8_t> code = glb((const uint8_t *)S.code) + base;
         if (tid < 256) {
             int kb = 0;
-            if (tid < kNDir2) kb = nb_row(S.nbt, p)[tid] + 1;
-            else if (tid == kRemoved) kb = kNDir2 + 1;
+            if (tid < ND) kb = nb_row<ND>(S.nbt, p)[tid] + 1;
+            else if (tid == kRemoved) kb = ND + 1;
             s_kb[tid] = (uint8_t)kb;
         }
         __syncthreads();
@@ -133,7 +131,7 @@ __global__ __launch_bounds__(kRC) void k_rebin_count(const SimDev<T> *__restrict
             const int left = hi - q0 - lane;  // chunk u holds a slot while 64 u < left
             uint8_t t[kU];
 #pragma unroll
-            for (int u = 0; u < kU; ++u) t[u] = 64 * u < left ? cp[64 * u] : uint8_t(kStay2);
+            for (int u = 0; u < kU; ++u) t[u] = 64 * u < left ? cp[64 * u] : uint8_t(ND / 2);
 #pragma unroll
             for (int u = 0; u < kU; u += 4)
                 cw[u / 4] = (uint32_t)s_kb[t[u]] | ((uint32_t)s_kb[t[u + 1]] << 8) |
@@ -175,7 +173,7 @@ __global__ __launch_bounds__(kRC) void k_rebin_count(const SimDev<T> *__restrict
         if (wave == 0 && lane <= kKeys) {
             int tot = 0;
             for (int w = 0; w < kRCW; ++w) tot += s_wc[w][lane];
-            if (lane < kNDir2) glb(S.kcnt)[p * kNDir2 + lane] = tot;
+            if (lane < ND) glb(S.kcnt)[p * ND + lane] = tot;
             if (lane == kKeys) glb(S.nleave)[p] = tot;
         }
 
@@ -195,7 +193,7 @@ __global__ __launch_bounds__(kRC) void k_rebin_count(const SimDev<T> *__restrict
                     const int h0 = __builtin_amdgcn_readlane(run, kKeys);
                     if (kc) glb(S.holes)[base + h0 + __popcll(m & lt)] = k;
                     run += lane == kKeys ? __popcll(m) : 0;
-                    const uint64_t st = m & ~__ballot(kc == kNDir2 + 1);
+                    const uint64_t st = m & ~__ballot(kc == ND + 1);
                     int dest = 0;
                     while (m) {
                         const int kk = __builtin_amdgcn_readlane(kc, __ffsll((long long)m) - 1);
@@ -226,7 +224,7 @@ __global__ __launch_bounds__(kRC) void k_rebin_count(const SimDev<T> *__restrict
     }
 }
 
-template <typename T>
+template <typename T, int ND>
 __global__ __launch_bounds__(256) void k_rebin_check(const SimDev<T> *__restrict__ sims, int nsims,
                                                      const int *__restrict__ patch_prefix, int total)
 {
@@ -236,10 +234,10 @@ __global__ __launch_bounds__(256) void k_rebin_check(const SimDev<T> *__restrict
     const SimDev<T> &S = sims[s];
     if (!glb(S.st)->active) return;
     const int q = gp - patch_prefix[s];
-    const gptr_t<const int32_t> row = nb_row(S.nbt, q);
-    const int ns = row[kNDir2];
+    const gptr_t<const int32_t> row = nb_row<ND>(S.nbt, q);
+    const int ns = row[ND];
     int A = 0;
-    for (int i = 0; i < ns; ++i) A += glb(S.kcnt)[row[kNDir2 + 1 + i] * kNDir2 + row[kNDir2 + 9 + i]];
+    for (int i = 0; i < ns; ++i) A += glb(S.kcnt)[row[ND + 1 + i] * ND + row[2 * ND + i]];
     const int n = glb(S.count)[q], L = glb(S.nleave)[q];
     const int np = n - L + A;
     // vacated slots below the new count (the list is ascending)
@@ -256,15 +254,16 @@ __global__ __launch_bounds__(256) void k_rebin_check(const SimDev<T> *__restrict
         __hip_atomic_fetch_or(&glb(S.st)->flags, kFlagPending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <typename T>
+template <typename T, int ND>
 __global__ __launch_bounds__(kRB) void k_rebin_scatter(const SimDev<T> *__restrict__ sims, int nsims,
                                                        const int *__restrict__ patch_prefix,
                                                        int total)
 {
-    __shared__ int s_src[8], s_skey[8], s_scnt[8];
-    __shared__ int64_t s_sbase[8];
+    constexpr int NS = ND - 1;  // at most this many distinct source patches
+    __shared__ int s_src[NS], s_skey[NS], s_scnt[NS];
+    __shared__ int64_t s_sbase[NS];
     __shared__ int s_ns;
-    __shared__ int s_key[kNDir2];
+    __shared__ int s_key[ND];
     __shared__ int s_wc[kNW];
     __shared__ int s_run;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -277,17 +276,17 @@ __global__ __launch_bounds__(kRB) void k_rebin_scatter(const SimDev<T> *__restri
         const int q = gp - patch_prefix[s];
         const int n = glb(S.count)[q], np = glb(S.newcount)[q], nH = glb(S.nhole)[q], A = glb(S.narrive)[q];
         const int64_t base = glb(S.off)[q];
-        const gptr_t<const int32_t> row = nb_row(S.nbt, q);
-        if (tid < 8) {
+        const gptr_t<const int32_t> row = nb_row<ND>(S.nbt, q);
+        if (tid < NS) {
             // one thread per source: its count and staging base for this patch
-            const int ns = row[kNDir2];
+            const int ns = row[ND];
             if (tid < ns) {
-                const int sp = row[kNDir2 + 1 + tid], k = row[kNDir2 + 9 + tid];
+                const int sp = row[ND + 1 + tid], k = row[2 * ND + tid];
                 int koff = 0;
-                for (int e = 0; e < k; ++e) koff += glb(S.kcnt)[sp * kNDir2 + e];
+                for (int e = 0; e < k; ++e) koff += glb(S.kcnt)[sp * ND + e];
                 s_src[tid] = sp;
                 s_skey[tid] = k;
-                s_scnt[tid] = glb(S.kcnt)[sp * kNDir2 + k];
+                s_scnt[tid] = glb(S.kcnt)[sp * ND + k];
                 s_sbase[tid] = glb(S.off)[sp] + koff;
             }
             if (tid == 0) {
@@ -295,8 +294,8 @@ __global__ __launch_bounds__(kRB) void k_rebin_scatter(const SimDev<T> *__restri
                 s_run = 0;
                 if (q == 0) glb(S.st)->rebinned = 1u;
             }
-        } else if (tid < 8 + kNDir2) {
-            s_key[tid - 8] = row[tid - 8];
+        } else if (tid >= 64 && tid < 64 + ND) {
+            s_key[tid - 64] = row[tid - 64];
         }
         __syncthreads();
         // arrivals: holes first, then appended from slot n
@@ -339,7 +338,7 @@ __global__ __launch_bounds__(kRB) void k_rebin_scatter(const SimDev<T> *__restri
         if (tid == 0) {
             glb(S.count)[q] = np;
             int staged = 0;
-            for (int k = 0; k < kNDir2; ++k) staged += glb(S.kcnt)[q * kNDir2 + k];
+            for (int k = 0; k < ND; ++k) staged += glb(S.kcnt)[q * ND + k];
             const int removed = glb(S.nleave)[q] - staged;
             if (removed)
                 __hip_atomic_fetch_add(&glb(S.st)->removed, (uint64_t)removed, __ATOMIC_RELAXED,
@@ -574,6 +573,7 @@ __global__ void k_relayout(const SimDev<T> *__restrict__ src, const SimDev<T> *_
     for (int k = threadIdx.x; k < n; k += blockDim.x) {
         dst->x[0][b + k] = src->x[0][a + k];
         dst->x[1][b + k] = src->x[1][a + k];
+        if (src->ndim == 3) dst->x[2][b + k] = src->x[2][a + k];
         dst->u[0][b + k] = src->u[0][a + k];
         dst->u[1][b + k] = src->u[1][a + k];
         dst->u[2][b + k] = src->u[2][a + k];
@@ -627,17 +627,27 @@ void launch_close_queue(const SimDev<T> *sims, const QueueArgs &q, hipStream_t s
                           q);
 }
 
-template <typename T>
-void launch_rebin(const SimDev<T> *sims, int nsims, const int *patch_prefix, int total_patches,
-                  int grid, hipStream_t st, Ev2 ev)
+template <typename T, int ND>
+static void launch_rebin_nd(const SimDev<T> *sims, int nsims, const int *patch_prefix,
+                            int total_patches, int grid, hipStream_t st, Ev2 ev)
 {
     // one count workgroup per patch (the hardware balances uneven patches)
-    hipExtLaunchKernelGGL((k_rebin_count<T>), dim3(std::min(total_patches, 1 << 20)), dim3(kRC), 0,
-                          st, ev.start, nullptr, 0, sims, nsims, patch_prefix, total_patches);
-    hipLaunchKernelGGL((k_rebin_check<T>), dim3((total_patches + 255) / 256), dim3(256), 0, st, sims,
-                       nsims, patch_prefix, total_patches);
-    hipExtLaunchKernelGGL((k_rebin_scatter<T>), dim3(grid), dim3(kRB), 0, st, nullptr, ev.stop, 0,
+    hipExtLaunchKernelGGL((k_rebin_count<T, ND>), dim3(std::min(total_patches, 1 << 20)), dim3(kRC),
+                          0, st, ev.start, nullptr, 0, sims, nsims, patch_prefix, total_patches);
+    hipLaunchKernelGGL((k_rebin_check<T, ND>), dim3((total_patches + 255) / 256), dim3(256), 0, st,
+                       sims, nsims, patch_prefix, total_patches);
+    hipExtLaunchKernelGGL((k_rebin_scatter<T, ND>), dim3(grid), dim3(kRB), 0, st, nullptr, ev.stop, 0,
                           sims, nsims, patch_prefix, total_patches);
+}
+
+template <typename T>
+void launch_rebin(const SimDev<T> *sims, int nsims, const int *patch_prefix, int total_patches,
+                  int grid, int ndim, hipStream_t st, Ev2 ev)
+{
+    if (ndim == 3)
+        launch_rebin_nd<T, kNDir3>(sims, nsims, patch_prefix, total_patches, grid, st, ev);
+    else
+        launch_rebin_nd<T, kNDir2>(sims, nsims, patch_prefix, total_patches, grid, st, ev);
 }
 
 template <typename T>
@@ -661,8 +671,8 @@ void launch_scatter_codes(const uint8_t *packed, const int64_t *packed_off, cons
 
 #define PIC_INST(T)                                                                              \
     template void launch_close_queue<T>(const SimDev<T> *, const QueueArgs &, hipStream_t, Ev2); \
-    template void launch_rebin<T>(const SimDev<T> *, int, const int *, int, int, hipStream_t,     \
-                                  Ev2);                                                          \
+    template void launch_rebin<T>(const SimDev<T> *, int, const int *, int, int, int,            \
+                                  hipStream_t, Ev2);                                             \
     template void launch_relayout<T>(const SimDev<T> *, const SimDev<T> *, int, hipStream_t);    \
     template void launch_rho<T>(const SimDev<T> *, int, double *, hipStream_t);
 PIC_INST(float)

@@ -43,6 +43,24 @@ void launch_particles(const SimDev<T> *sims, const Item *items, const int *nitem
 template <typename T>
 int particles_occupancy(int block, int maxP0, int maxP1);
 
+// 3-D particle kernel (periodic boxes): 27-node gather, Boris, move, 26-way
+// classification, Esirkepov deposit on a 4x4x4 window.  LDS per workgroup:
+// particles3d_lds_bytes(precision, largest patch edges).
+template <typename T>
+void launch_particles3d(const SimDev<T> *sims, const Item *items, const int *nitems, int *head,
+                        int grid, int block, int maxP0, int maxP1, int maxP2, hipStream_t st,
+                        Ev2 ev = {});
+template <typename T>
+int particles3d_occupancy(int block, int maxP0, int maxP1, int maxP2);
+size_t particles3d_lds_bytes(int precision, int P0, int P1, int P2);
+
+// 3-D Yee update on a periodic box (three passes; tiles are blocks of 256
+// nodes), with the field energy of the incoming E, B per tile.
+template <typename T>
+void launch_maxwell3d(const SimDev<T> *sims, int nsims, const int *tile_prefix, int total_tiles,
+                      int grid, hipStream_t st, Ev2 ev = {});
+constexpr int kMaxwell3dTile = 256;
+
 // Fused Yee update (half B, E, half B) with face conditions; clears the
 // other J buffer and accumulates the field energy of the incoming E, B.
 template <typename T>
@@ -51,10 +69,11 @@ void launch_maxwell(const SimDev<T> *sims, int nsims, const int *tile_prefix, in
 template <typename T>
 void maxwell_tile(int preset, int &tx, int &ty);
 
-// Re-binning: count and stage leavers; check capacity; scatter.
+// Re-binning: count and stage leavers; check capacity; scatter (ndim 2 or 3:
+// 9 or 27 neighbour directions).
 template <typename T>
 void launch_rebin(const SimDev<T> *sims, int nsims, const int *patch_prefix, int total_patches,
-                  int grid, hipStream_t st, Ev2 ev = {});
+                  int grid, int ndim, hipStream_t st, Ev2 ev = {});
 
 // Copy particles into a new per-patch layout (capacity growth).
 template <typename T>

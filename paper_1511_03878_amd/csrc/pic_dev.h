@@ -23,7 +23,12 @@ constexpr int kHistLen = 4096;     // energy-history ring length
 constexpr int kMaxBatch = 2048;    // simulations per batch
 constexpr int kNDir2 = 9;          // neighbour directions in 2-D (4 = stay)
 constexpr int kStay2 = 4;
-constexpr int kNbStride = 26;      // neighbour-table entries per patch (9 keys, count, 8 sources, 8 keys)
+constexpr int kNDir3 = 27;         // neighbour directions in 3-D (13 = stay)
+constexpr int kStay3 = 13;
+// neighbour-table entries per patch: nd keys, the number of distinct source
+// patches, up to nd - 1 sources and the key each of them stages under
+constexpr int nb_stride(int nd) { return nd + 1 + 2 * (nd - 1); }
+constexpr int kNbStride = nb_stride(kNDir2);
 constexpr uint8_t kRemoved = 255;
 
 // sticky state flags
@@ -49,7 +54,7 @@ struct SimDev {
     int n[3], P[3], np[3], fn[3], periodic[3];
     int npatch;
     int ndim;
-    int lane_stride;   // particles between consecutive lanes of a wave (power of 2)
+    int lane_stride;   // particles between consecutive lanes of a wave
     T d[3];
     T dt;
     T q, m;

@@ -73,7 +73,7 @@ static int cu_count()
 
 int validate_desc(const PicSimDesc &d, std::string &why)
 {
-    if (d.ndim != 2) { why = "ndim must be 2"; return PIC_ENOTSUP; }
+    if (d.ndim != 2 && d.ndim != 3) { why = "ndim must be 2 or 3"; return PIC_ENOTSUP; }
     if (d.precision != 32 && d.precision != 64) { why = "precision must be 32 or 64"; return PIC_EINVAL; }
     double inv2 = 0.0;
     for (int a = 0; a < d.ndim; ++a) {
@@ -84,7 +84,17 @@ int validate_desc(const PicSimDesc &d, std::string &why)
         if (a > 0 && !d.periodic[a]) { why = "only the x axis may be open"; return PIC_EINVAL; }
         inv2 += 1.0 / (d.d[a] * d.d[a]);
     }
-    if ((int64_t)d.n[0] * d.n[1] > (int64_t)1 << 30) { why = "grid too large"; return PIC_EINVAL; }
+    if (d.ndim == 3) {
+        for (int a = 0; a < 3; ++a)
+            if (!d.periodic[a]) { why = "3-D boxes must be periodic on every axis"; return PIC_ENOTSUP; }
+        // the particle kernel holds the patch's field and current tiles in LDS
+        if (particles3d_lds_bytes(d.precision, d.patch[0], d.patch[1], d.patch[2]) > 150 * 1024) {
+            why = "3-D patch too large for the LDS tiles (8 x 8 x 8 cells fit)";
+            return PIC_ENOTSUP;
+        }
+    }
+    const int64_t cells = (int64_t)d.n[0] * d.n[1] * (d.ndim == 3 ? d.n[2] : 1);
+    if (cells > (int64_t)1 << 30) { why = "grid too large"; return PIC_EINVAL; }
     if (!(d.dt > 0.0) || d.dt >= 1.0 / std::sqrt(inv2)) { why = "dt must be positive and below the Yee limit"; return PIC_EINVAL; }
     if (!(d.m > 0.0) || !std::isfinite(d.q)) { why = "species mass must be positive"; return PIC_EINVAL; }
     if (d.capacity_factor != 0.0 && !(d.capacity_factor >= 1.0)) { why = "capacity_factor must be >= 1"; return PIC_EINVAL; }
@@ -106,15 +116,17 @@ SimImpl<T>::SimImpl(const PicSimDesc &d, const PicAllocator *a, hipStream_t s)
     precision = d.precision;
     stream = s;
     if (a) alloc.hook = *a;
+    nd = d.ndim;
+    ndir = nd == 3 ? kNDir3 : kNDir2;
     for (int ax = 0; ax < 3; ++ax) {
-        n[ax] = ax < 2 ? d.n[ax] : 1;
-        P[ax] = ax < 2 ? d.patch[ax] : 1;
-        periodic[ax] = ax < 2 ? (d.periodic[ax] ? 1 : 0) : 1;
+        n[ax] = ax < nd ? d.n[ax] : 1;
+        P[ax] = ax < nd ? d.patch[ax] : 1;
+        periodic[ax] = ax < nd ? (d.periodic[ax] ? 1 : 0) : 1;
         np[ax] = n[ax] / P[ax];
-        fn[ax] = (ax < 2 && !periodic[ax]) ? n[ax] + 1 : n[ax];
+        fn[ax] = (ax < nd && !periodic[ax]) ? n[ax] + 1 : n[ax];
     }
-    npatch = np[0] * np[1];
-    fsize = (int64_t)fn[0] * fn[1];
+    npatch = np[0] * np[1] * np[2];
+    fsize = (int64_t)fn[0] * fn[1] * fn[2];
     std::memset(&v, 0, sizeof(v));
     try {
         for (int b = 0; b < 2; ++b)
@@ -125,7 +137,7 @@ SimImpl<T>::SimImpl(const PicSimDesc &d, const PicAllocator *a, hipStream_t s)
         hist = (double *)alloc.get(sizeof(double) * kHistLen * 4);
         counts_d = (int32_t *)alloc.get(sizeof(int32_t) * npatch);
         newcount_d = (int32_t *)alloc.get(sizeof(int32_t) * npatch);
-        kcnt_d = (int32_t *)alloc.get(sizeof(int32_t) * npatch * kNDir2);
+        kcnt_d = (int32_t *)alloc.get(sizeof(int32_t) * npatch * ndir);
         nleave_d = (int32_t *)alloc.get(sizeof(int32_t) * npatch);
         narrive_d = (int32_t *)alloc.get(sizeof(int32_t) * npatch);
         nhole_d = (int32_t *)alloc.get(sizeof(int32_t) * npatch);
@@ -133,7 +145,9 @@ SimImpl<T>::SimImpl(const PicSimDesc &d, const PicAllocator *a, hipStream_t s)
         tprefix_d = (int *)alloc.get(sizeof(int) * 2);
         view_d = (SimDev<T> *)alloc.get(sizeof(SimDev<T>));
         // per-tile energy partials, sized for the smallest Yee tile preset (16 x 4)
-        max_tiles = (int64_t)((fn[0] + 15) / 16) * ((fn[1] + 3) / 4);
+        // in 2-D and for blocks of nodes in 3-D
+        max_tiles = nd == 3 ? (fsize + kMaxwell3dTile - 1) / kMaxwell3dTile
+                            : (int64_t)((fn[0] + 15) / 16) * ((fn[1] + 3) / 4);
         upart = (double *)alloc.get(sizeof(double) * max_tiles);
         kpart = (double *)alloc.get(sizeof(double) * npatch);
         hipcheck(hipMemsetAsync(upart, 0, sizeof(double) * max_tiles, stream), "memset upart");
@@ -183,6 +197,7 @@ void SimImpl<T>::step(int64_t nsteps)
     if (!solo) {
         solo = new BatchImpl<T>(stream);
         solo->solo_mode = true;
+        solo->nd = nd;
         solo->members.push_back(this);
         solo->dirty = true;
     }
@@ -200,43 +215,45 @@ void SimImpl<T>::step(int64_t nsteps)
 template <typename T>
 void SimImpl<T>::build_neighbour_table()
 {
+    // direction d = (dx + 1) + 3 (dy + 1) [+ 9 (dz + 1)]
+    const int stay = ndir / 2, stride = nb_stride(ndir);
     auto nbr = [&](int p, int d) {
-        int qx = p % np[0] + d % 3 - 1, qy = p / np[0] + d / 3 - 1;
-        if (qx < 0 || qx >= np[0]) {
-            if (!periodic[0]) return -1;
-            qx = (qx + np[0]) % np[0];
+        int q[3] = {p % np[0], (p / np[0]) % np[1], p / (np[0] * np[1])};
+        const int dd[3] = {d % 3 - 1, (d / 3) % 3 - 1, d / 9 - 1};
+        for (int a = 0; a < nd; ++a) {
+            q[a] += dd[a];
+            if (q[a] < 0 || q[a] >= np[a]) {
+                if (!periodic[a]) return -1;
+                q[a] = (q[a] + np[a]) % np[a];
+            }
         }
-        if (qy < 0 || qy >= np[1]) {
-            if (!periodic[1]) return -1;
-            qy = (qy + np[1]) % np[1];
-        }
-        return qx + np[0] * qy;
+        return q[0] + np[0] * (q[1] + np[1] * q[2]);
     };
     auto key_of = [&](int p, int target) {
-        for (int d = 0; d < kNDir2; ++d)
-            if (d != kStay2 && nbr(p, d) == target) return d;
+        for (int d = 0; d < ndir; ++d)
+            if (d != stay && nbr(p, d) == target) return d;
         return -1;
     };
-    std::vector<int32_t> t((size_t)npatch * kNbStride, -1);
+    std::vector<int32_t> t((size_t)npatch * stride, -1);
+    std::vector<int> nb(ndir);
     for (int p = 0; p < npatch; ++p) {
-        int32_t *row = &t[(size_t)p * kNbStride];
-        int nb[kNDir2];
-        for (int d = 0; d < kNDir2; ++d) nb[d] = nbr(p, d);
-        for (int d = 0; d < kNDir2; ++d) {
-            if (d == kStay2 || nb[d] == p) row[d] = -1;
-            else if (nb[d] < 0) row[d] = kNDir2;
+        int32_t *row = &t[(size_t)p * stride];
+        for (int d = 0; d < ndir; ++d) nb[d] = nbr(p, d);
+        for (int d = 0; d < ndir; ++d) {
+            if (d == stay || nb[d] == p) row[d] = -1;
+            else if (nb[d] < 0) row[d] = ndir;
             else row[d] = key_of(p, nb[d]);
         }
         std::vector<int> src;
-        for (int d = 0; d < kNDir2; ++d)
-            if (d != kStay2 && nb[d] >= 0 && nb[d] != p &&
+        for (int d = 0; d < ndir; ++d)
+            if (d != stay && nb[d] >= 0 && nb[d] != p &&
                 std::find(src.begin(), src.end(), nb[d]) == src.end())
                 src.push_back(nb[d]);
         std::sort(src.begin(), src.end());
-        row[kNDir2] = (int32_t)src.size();
+        row[ndir] = (int32_t)src.size();
         for (size_t i = 0; i < src.size(); ++i) {
-            row[kNDir2 + 1 + i] = src[i];
-            row[kNDir2 + 9 + i] = key_of(src[i], p);
+            row[ndir + 1 + i] = src[i];
+            row[2 * ndir + i] = key_of(src[i], p);
         }
     }
     nbt_d = (int32_t *)alloc.get(sizeof(int32_t) * t.size());
@@ -318,7 +335,7 @@ std::vector<void *> SimImpl<T>::layout_particles(const std::vector<int32_t> &nee
             part_bufs.push_back(p);
             return p;
         };
-        for (int a = 0; a < 2; ++a) {
+        for (int a = 0; a < nd; ++a) {
             px[a] = (T *)get(sizeof(T) * total);
             sx[a] = (T *)get(sizeof(T) * total);
         }
@@ -359,21 +376,21 @@ void SimImpl<T>::refresh_view()
         V.np[a] = np[a];
         V.fn[a] = fn[a];
         V.periodic[a] = periodic[a];
-        V.d[a] = (T)(a < 2 ? desc.d[a] : 1.0);
+        V.d[a] = (T)(a < nd ? desc.d[a] : 1.0);
     }
     V.npatch = npatch;
-    V.ndim = 2;
+    V.ndim = nd;
     V.lane_stride = lane_stride;
     V.dt = (T)desc.dt;
     V.q = (T)desc.q;
     V.m = (T)desc.m;
-    V.vcell = desc.d[0] * desc.d[1];
+    V.vcell = desc.d[0] * desc.d[1] * (nd == 3 ? desc.d[2] : 1.0);
     for (int b = 0; b < 2; ++b)
         for (int c = 0; c < 6; ++c) V.F[b][c] = F[b][c];
     for (int b = 0; b < 2; ++b)
         for (int c = 0; c < 3; ++c) V.J[b][c] = J[b][c];
-    V.x[0] = px[0]; V.x[1] = px[1]; V.x[2] = nullptr;
-    V.sx[0] = sx[0]; V.sx[1] = sx[1]; V.sx[2] = nullptr;
+    V.x[0] = px[0]; V.x[1] = px[1]; V.x[2] = nd == 3 ? px[2] : nullptr;
+    V.sx[0] = sx[0]; V.sx[1] = sx[1]; V.sx[2] = nd == 3 ? sx[2] : nullptr;
     for (int a = 0; a < 3; ++a) { V.u[a] = pu[a]; V.su[a] = su[a]; }
     V.w = pw; V.sw = sw; V.id = pid; V.sid = sid; V.code = code; V.holes = holes;
     V.cap = cap_d; V.off = off_d; V.count = counts_d; V.newcount = newcount_d;
@@ -390,28 +407,25 @@ void SimImpl<T>::set_particles(int64_t cnt, const double *const xs[3], const dou
 {
     check_free();
     for (int64_t k = 0; k < cnt; ++k)
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < nd; ++a)
             if (!(xs[a][k] >= 0.0 && xs[a][k] < (double)n[a]))
                 throw Error(PIC_EINVAL, "particle " + std::to_string(k) + " outside the domain");
-    // patch of each particle and counts
+    // cell and patch of each particle, and counts
+    auto cell_of = [&](int64_t k, int a) { return a < nd ? std::min((int)std::floor(xs[a][k]), n[a] - 1) : 0; };
     std::vector<int32_t> pp(cnt), counts(npatch, 0);
     for (int64_t k = 0; k < cnt; ++k) {
-        int cx = std::min((int)std::floor(xs[0][k]), n[0] - 1) / P[0];
-        int cy = std::min((int)std::floor(xs[1][k]), n[1] - 1) / P[1];
-        pp[k] = cx + np[0] * cy;
+        pp[k] = cell_of(k, 0) / P[0] + np[0] * (cell_of(k, 1) / P[1] + np[1] * (cell_of(k, 2) / P[2]));
         counts[pp[k]]++;
     }
     {
-        // lane stride of the particle kernel: particles per occupied cell,
-        // rounded down to a power of two (cells hold their particles in a run)
-        std::vector<uint8_t> occupied((size_t)n[0] * n[1], 0);
+        // lane stride of the particle kernel: about two cells' worth of
+        // particles between lanes (cells hold their particles in a run)
+        std::vector<uint8_t> occupied((size_t)n[0] * n[1] * n[2], 0);
         for (int64_t k = 0; k < cnt; ++k)
-            occupied[(size_t)std::min((int)xs[0][k], n[0] - 1) +
-                     (size_t)n[0] * std::min((int)xs[1][k], n[1] - 1)] = 1;
+            occupied[(size_t)cell_of(k, 0) + (size_t)n[0] * ((size_t)cell_of(k, 1) + (size_t)n[1] * cell_of(k, 2))] = 1;
         int64_t cells = 0;
         for (uint8_t o : occupied) cells += o;
         const double ppc = cells ? (double)cnt / cells : 1.0;
-        // about two cells' worth of particles between lanes
         lane_stride = desc.lane_stride ? desc.lane_stride
                                        : (int)std::max(1.0, std::min(64.0, std::round(2.0 * ppc)));
     }
@@ -421,17 +435,18 @@ void SimImpl<T>::set_particles(int64_t cnt, const double *const xs[3], const dou
     // canonical initial order: id order inside each patch
     std::vector<int64_t> pos(off_h.begin(), off_h.end() - 1);
     const int64_t tot = total_cap;
-    std::vector<T> hx[2], hu[3];
-    for (auto &a : hx) a.assign(tot, T(0));
+    std::vector<T> hx[3], hu[3];
+    for (int a = 0; a < nd; ++a) hx[a].assign(tot, T(0));
     for (auto &a : hu) a.assign(tot, T(0));
     std::vector<T> hw(tot, T(0));
     std::vector<int64_t> hid(tot, -1);
-    const T pmax[2] = {std::nextafter((T)P[0], (T)0), std::nextafter((T)P[1], (T)0)};
+    const T pmax[3] = {std::nextafter((T)P[0], (T)0), std::nextafter((T)P[1], (T)0),
+                       std::nextafter((T)P[2], (T)0)};
     for (int64_t k = 0; k < cnt; ++k) {
         const int p = pp[k];
         const int64_t t = pos[p]++;
-        const int o[2] = {(p % np[0]) * P[0], (p / np[0]) * P[1]};
-        for (int a = 0; a < 2; ++a) {
+        const int o[3] = {(p % np[0]) * P[0], ((p / np[0]) % np[1]) * P[1], (p / (np[0] * np[1])) * P[2]};
+        for (int a = 0; a < nd; ++a) {
             T loc = (T)(xs[a][k] - (double)o[a]);
             if (loc > pmax[a]) loc = pmax[a];
             if (loc < T(0)) loc = T(0);
@@ -441,13 +456,13 @@ void SimImpl<T>::set_particles(int64_t cnt, const double *const xs[3], const dou
         hw[t] = (T)w[k];
         hid[t] = k;
     }
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < nd; ++a)
         hipcheck(hipMemcpyAsync(px[a], hx[a].data(), sizeof(T) * tot, hipMemcpyHostToDevice, stream), "x");
     for (int a = 0; a < 3; ++a)
         hipcheck(hipMemcpyAsync(pu[a], hu[a].data(), sizeof(T) * tot, hipMemcpyHostToDevice, stream), "u");
     hipcheck(hipMemcpyAsync(pw, hw.data(), sizeof(T) * tot, hipMemcpyHostToDevice, stream), "w");
     hipcheck(hipMemcpyAsync(pid, hid.data(), sizeof(int64_t) * tot, hipMemcpyHostToDevice, stream), "id");
-    hipcheck(hipMemsetAsync(code, kStay2, tot, stream), "code");
+    hipcheck(hipMemsetAsync(code, ndir / 2, tot, stream), "code");
     hipcheck(hipMemcpyAsync(counts_d, counts.data(), sizeof(int32_t) * npatch, hipMemcpyHostToDevice, stream), "counts");
     SimState s0;
     std::memset(&s0, 0, sizeof(s0));
@@ -461,6 +476,7 @@ template <typename T>
 void SimImpl<T>::set_laser(int64_t nsteps, const double *ey, const double *ez)
 {
     check_free();
+    if (nd != 2) throw Error(PIC_ENOTSUP, "laser injection needs an open x face (2-D boxes)");
     hipcheck(hipStreamSynchronize(stream), "sync");
     alloc.put(laser_ey);
     alloc.put(laser_ez);
@@ -502,6 +518,7 @@ void SimImpl<T>::get_field(int comp, double *h)
     if (comp < 0 || comp > 9) throw Error(PIC_EINVAL, "bad component");
     hipcheck(hipStreamSynchronize(stream), "sync");
     if (comp == PIC_RHO) {
+        if (nd != 2) throw Error(PIC_ENOTSUP, "charge density diagnostic is 2-D only");
         double *tmp = (double *)alloc.get(sizeof(double) * fsize);
         hipcheck(hipMemsetAsync(tmp, 0, sizeof(double) * fsize, stream), "memset rho");
         launch_rho<T>(view_d, npatch, tmp, stream);
@@ -560,12 +577,13 @@ void SimImpl<T>::get_particles(double *xo[3], double *uo[3], double *wo, int64_t
         int64_t o = 0;
         for (int p = 0; p < npatch; ++p) {
             const double org = axis == 0 ? (double)((p % np[0]) * P[0])
-                             : axis == 1 ? (double)((p / np[0]) * P[1]) : 0.0;
+                             : axis == 1 ? (double)(((p / np[0]) % np[1]) * P[1])
+                             : axis == 2 ? (double)((p / (np[0] * np[1])) * P[2]) : 0.0;
             for (int k = 0; k < c[p]; ++k) dst[o++] = org + (double)tmp[off_h[p] + k];
         }
     };
-    for (int a = 0; a < 2; ++a) if (xo[a]) fetch(px[a], xo[a], a);
-    if (xo[2]) std::fill(xo[2], xo[2] + live, 0.0);
+    for (int a = 0; a < nd; ++a) if (xo[a]) fetch(px[a], xo[a], a);
+    if (nd == 2 && xo[2]) std::fill(xo[2], xo[2] + live, 0.0);
     for (int a = 0; a < 3; ++a) if (uo[a]) fetch(pu[a], uo[a], 3);
     if (wo) fetch(pw, wo, 3);
     if (ido) {
@@ -643,7 +661,7 @@ void SimImpl<T>::recover_pending()
         s.flags &= ~kFlagPending;
         s.active = 1;
         hipcheck(hipMemcpyAsync(&st->flags, &s.flags, sizeof(uint32_t) * 2, hipMemcpyHostToDevice, stream), "flags");
-        launch_rebin<T>(view_d, 1, prefix_d, npatch, std::min(npatch, 4 * cu_count()), stream);
+        launch_rebin<T>(view_d, 1, prefix_d, npatch, std::min(npatch, 4 * cu_count()), nd, stream);
         hipcheck(hipGetLastError(), "rebin launch");
         s = read_state();
         if (!(s.flags & kFlagPending)) return;
@@ -659,7 +677,7 @@ void SimImpl<T>::rebin_codes(const uint8_t *codes_h, size_t cnt)
     const int64_t live = std::accumulate(c.begin(), c.end(), int64_t(0));
     if ((int64_t)cnt != live) throw Error(PIC_EINVAL, "code count must equal the live particle count");
     for (size_t k = 0; k < cnt; ++k)
-        if (codes_h[k] >= kNDir2 && codes_h[k] != kRemoved) throw Error(PIC_EINVAL, "bad direction code");
+        if (codes_h[k] >= ndir && codes_h[k] != kRemoved) throw Error(PIC_EINVAL, "bad direction code");
     std::vector<int64_t> poff(npatch + 1, 0);
     for (int p = 0; p < npatch; ++p) poff[p + 1] = poff[p] + c[p];
     uint8_t *pk = (uint8_t *)alloc.get(std::max<size_t>(cnt, 1));
@@ -671,7 +689,7 @@ void SimImpl<T>::rebin_codes(const uint8_t *codes_h, size_t cnt)
     SimState s = read_state();
     s.active = 1;
     hipcheck(hipMemcpyAsync(&st->active, &s.active, sizeof(uint32_t), hipMemcpyHostToDevice, stream), "active");
-    launch_rebin<T>(view_d, 1, prefix_d, npatch, std::min(npatch, 4 * cu_count()), stream);
+    launch_rebin<T>(view_d, 1, prefix_d, npatch, std::min(npatch, 4 * cu_count()), nd, stream);
     hipcheck(hipGetLastError(), "rebin launch");
     s = read_state();
     alloc.put(pk);
@@ -775,12 +793,14 @@ void BatchImpl<T>::add(SimImpl<T> *s, int64_t nsteps)
 {
     if (s->batch) throw Error(PIC_ESTATE, "simulation already in a batch");
     if (s->stream != stream) throw Error(PIC_EINVAL, "simulation and batch must share a stream");
+    if (nd && s->nd != nd) throw Error(PIC_EINVAL, "simulation and batch differ in dimensions");
     SimState st = s->read_state();
     st.steps_left = nsteps;
     hipcheck(hipMemcpyAsync(&s->st->steps_left, &st.steps_left, sizeof(int64_t), hipMemcpyHostToDevice, stream), "budget");
     hipcheck(hipStreamSynchronize(stream), "sync");
     s->batch = this;
     members.push_back(s);
+    nd = s->nd;
     dirty = true;
 }
 
@@ -808,26 +828,29 @@ void BatchImpl<T>::build_tables()
     for (auto *m : members) if (m->desc.field_tile) tile_preset = m->desc.field_tile;
     int tx, ty;
     maxwell_tile<T>(tile_preset, tx, ty);
-    maxP0 = maxP1 = 1;
+    maxP0 = maxP1 = maxP2 = 1;
     int64_t items = 0;
     int64_t particles = 0;
     if (ns > kMaxBatch) throw Error(PIC_EINVAL, "too many simulations in one batch");
     for (int i = 0; i < ns; ++i) {
         SimImpl<T> *m = members[i];
         pp[i + 1] = pp[i] + m->npatch;
-        const int ntx = (m->fn[0] + tx - 1) / tx, nty = (m->fn[1] + ty - 1) / ty;
-        tp[i + 1] = tp[i] + ntx * nty;
-        const int own[2] = {0, ntx * nty};
+        // Yee tiles: TX x TY node tiles in 2-D, blocks of nodes in 3-D
+        const int ntiles = nd == 3 ? (int)((m->fsize + kMaxwell3dTile - 1) / kMaxwell3dTile)
+                                   : ((m->fn[0] + tx - 1) / tx) * ((m->fn[1] + ty - 1) / ty);
+        tp[i + 1] = tp[i] + ntiles;
+        const int own[2] = {0, ntiles};
         hipcheck(hipMemcpyAsync(m->tprefix_d, own, sizeof(own), hipMemcpyHostToDevice, stream), "tile count");
         maxP0 = std::max(maxP0, m->P[0]);
         maxP1 = std::max(maxP1, m->P[1]);
+        maxP2 = std::max(maxP2, m->P[2]);
         particles += m->num_particles();
     }
     total_patches = pp[ns];
     total_tiles = tp[ns];
     // a common square patch size of 16 or 32 selects the specialised kernel
     patch_const = 0;
-    if (ns > 0 && (members[0]->P[0] == 16 || members[0]->P[0] == 32)) {
+    if (nd == 2 && ns > 0 && (members[0]->P[0] == 16 || members[0]->P[0] == 32)) {
         patch_const = members[0]->P[0];
         for (auto *m : members)
             if (m->P[0] != patch_const || m->P[1] != patch_const) patch_const = 0;
@@ -844,11 +867,12 @@ void BatchImpl<T>::build_tables()
     }
     for (auto *m : members) items += m->max_items(chunk);
     items = std::max<int64_t>(items, 1);
-    block = sizeof(T) == 8 ? 1024 : 512;
+    block = (sizeof(T) == 8 && nd == 2) ? 1024 : 512;
     for (auto *m : members) if (m->desc.block) block = m->desc.block;
-    const int occ = std::max(1, particles_occupancy<T>(block, maxP0, maxP1));
+    const int occ = std::max(1, nd == 3 ? particles3d_occupancy<T>(block, maxP0, maxP1, maxP2)
+                                        : particles_occupancy<T>(block, maxP0, maxP1));
     grid_particles = cu_count() * occ;
-    grid_maxwell = std::max(1, std::min(total_tiles, cu_count() * 8));
+    grid_maxwell = std::max(1, std::min(total_tiles, cu_count() * (nd == 3 ? 32 : 8)));
     grid_rebin = std::max(1, std::min(total_patches, cu_count() * 8));
 
     // device tables (hipMalloc directly: small, batch-owned)
@@ -928,11 +952,17 @@ void BatchImpl<T>::launch_one_step()
 {
     const int ns = (int)members.size();
     Timing &tm = timing();
-    launch_particles<T>(sims_d, items_d, nitems_d, head_d, grid_particles, block, maxP0, maxP1,
-                        patch_const, stream, tm.pair(1));
-    launch_maxwell<T>(sims_d, ns, tile_prefix_d, total_tiles, grid_maxwell, tile_preset, stream,
-                      tm.pair(2));
-    launch_rebin<T>(sims_d, ns, patch_prefix_d, total_patches, grid_rebin, stream, tm.pair(3));
+    if (nd == 3) {
+        launch_particles3d<T>(sims_d, items_d, nitems_d, head_d, grid_particles, block, maxP0, maxP1,
+                              maxP2, stream, tm.pair(1));
+        launch_maxwell3d<T>(sims_d, ns, tile_prefix_d, total_tiles, grid_maxwell, stream, tm.pair(2));
+    } else {
+        launch_particles<T>(sims_d, items_d, nitems_d, head_d, grid_particles, block, maxP0, maxP1,
+                            patch_const, stream, tm.pair(1));
+        launch_maxwell<T>(sims_d, ns, tile_prefix_d, total_tiles, grid_maxwell, tile_preset, stream,
+                          tm.pair(2));
+    }
+    launch_rebin<T>(sims_d, ns, patch_prefix_d, total_patches, grid_rebin, nd, stream, tm.pair(3));
     launch_close_queue_pass();
 }
 

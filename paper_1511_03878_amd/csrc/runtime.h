@@ -81,6 +81,8 @@ struct BatchImpl;
 template <typename T>
 struct SimImpl : SimBase {
     Allocator alloc;
+    int nd = 2;     // dimensions
+    int ndir = 9;   // neighbour directions (9 in 2-D, 27 in 3-D)
     int n[3], P[3], np[3], fn[3], periodic[3];
     int npatch = 0;
     int64_t fsize = 0;
@@ -98,7 +100,7 @@ struct SimImpl : SimBase {
     int64_t laser_steps = 0;
     // particle layout
     std::vector<void *> part_bufs;
-    T *px[2] = {}, *sx[2] = {}, *pu[3] = {}, *su[3] = {}, *pw = nullptr, *sw = nullptr;
+    T *px[3] = {}, *sx[3] = {}, *pu[3] = {}, *su[3] = {}, *pw = nullptr, *sw = nullptr;
     int64_t *pid = nullptr, *sid = nullptr;
     uint8_t *code = nullptr;
     int32_t *holes = nullptr, *cap_d = nullptr;
@@ -161,7 +163,8 @@ struct BatchImpl : BatchBase {
     int *nitems_d = nullptr, *head_d = nullptr;
     int table_cap_items = 0;
     int total_patches = 0, total_tiles = 0;
-    int maxP0 = 1, maxP1 = 1;
+    int nd = 0;  // dimensions of the members (set by the first one)
+    int maxP0 = 1, maxP1 = 1, maxP2 = 1;
     int chunk = 256, block = 256, tile_preset = 0, patch_const = 0;
     int grid_particles = 1, grid_maxwell = 1, grid_rebin = 1;
     Timing own_timing;

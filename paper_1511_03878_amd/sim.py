@@ -94,10 +94,11 @@ class Sim:
         check(lib.pic_sim_create(C.byref(desc), C.byref(self._alloc.struct) if self._alloc else None,
                                  C.c_void_p(self.stream), C.byref(h)))
         self._h = h
+        self.ndim = int(grid["ndim"])
         n = list(grid["n"])
-        per = list(grid.get("periodic", [1, 1]))
-        self.fn = [n[a] if per[a] else n[a] + 1 for a in range(2)]
-        self.npatch = (n[0] // grid["patch"][0]) * (n[1] // grid["patch"][1])
+        per = list(grid.get("periodic", [1] * self.ndim))
+        self.fn = [n[a] if per[a] else n[a] + 1 for a in range(self.ndim)] + [1] * (3 - self.ndim)
+        self.npatch = int(np.prod([n[a] // grid["patch"][a] for a in range(self.ndim)]))
 
     @property
     def handle(self):
@@ -121,7 +122,8 @@ class Sim:
         u = [_f64(a) for a in u]
         w = _f64(w)
         n = w.size
-        check(_capi.load().pic_particles_set(self._h, n, _dp(x[0]), _dp(x[1]), None,
+        check(_capi.load().pic_particles_set(self._h, n, _dp(x[0]), _dp(x[1]),
+                                             _dp(x[2]) if self.ndim == 3 else None,
                                              _dp(u[0]), _dp(u[1]), _dp(u[2]), _dp(w)))
 
     def set_laser(self, ey=None, ez=None):
@@ -152,8 +154,10 @@ class Sim:
     # -- state out -------------------------------------------------------------
     def field(self, comp) -> np.ndarray:
         c = _capi.COMPONENTS.index(comp) if isinstance(comp, str) else int(comp)
-        out = np.zeros(self.fn[0] * self.fn[1])
+        out = np.zeros(self.fn[0] * self.fn[1] * self.fn[2])
         check(_capi.load().pic_fields_get(self._h, c, _dp(out), out.size))
+        if self.ndim == 3:
+            return out.reshape(self.fn[2], self.fn[1], self.fn[0])
         return out.reshape(self.fn[1], self.fn[0])
 
     def num_particles(self) -> int:
@@ -162,14 +166,15 @@ class Sim:
         return n.value
 
     def particles(self):
-        """(x[2], u[3], w, id) in canonical (patch, slot) order, positions global."""
+        """(x[ndim], u[3], w, id) in canonical (patch, slot) order, positions global."""
         n = self.num_particles()
-        x = [np.zeros(n) for _ in range(2)]
+        x = [np.zeros(n) for _ in range(self.ndim)]
         u = [np.zeros(n) for _ in range(3)]
         w = np.zeros(n)
         ids = np.zeros(n, dtype=np.int64)
         check(_capi.load().pic_particles_get(
-            self._h, _dp(x[0]), _dp(x[1]), None, _dp(u[0]), _dp(u[1]), _dp(u[2]), _dp(w),
+            self._h, _dp(x[0]), _dp(x[1]), _dp(x[2]) if self.ndim == 3 else None,
+            _dp(u[0]), _dp(u[1]), _dp(u[2]), _dp(w),
             ids.ctypes.data_as(C.POINTER(C.c_int64)), n))
         return x, u, w, ids
 
@@ -208,11 +213,11 @@ class Sim:
 class Batch:
     """Simulations of one precision stepped together (one queue, one launch per kernel)."""
 
-    def __init__(self, precision: int = 32, stream: int | None = None):
+    def __init__(self, precision: int = 32, stream: int | None = None, ndim: int = 2):
         lib = _capi.load()
         self.stream = current_stream_handle() if stream is None else int(stream)
         h = C.c_void_p()
-        check(lib.pic_batch_create(2, int(precision), C.c_void_p(self.stream), C.byref(h)))
+        check(lib.pic_batch_create(int(ndim), int(precision), C.c_void_p(self.stream), C.byref(h)))
         self._h = h
         self.members = {}
 

@@ -30,10 +30,12 @@ def gpu_sim(wl, precision, **kw):
 
 
 def fields_of(sim, comps, oracle_layout=False):
+    """Field components; the oracle's (fn_z, fn_y, fn_x) arrays of a 2-D box are
+    reduced to (fn_y, fn_x) like the GPU's."""
     out = []
     for c in comps:
         f = sim.field(c)
-        out.append(f[0] if oracle_layout else f)
+        out.append(f[0] if oracle_layout and f.shape[0] == 1 else f)
     return out
 
 
@@ -57,3 +59,12 @@ def neighbour_patch(p, code, np_, periodic):
             return -1
         qy %= np_[1]
     return qx + np_[0] * qy
+
+
+def neighbour_patch3(p, code, np_):
+    """Destination patch of direction code (dx+1) + 3 (dy+1) + 9 (dz+1) from
+    patch p of a periodic 3-D patch grid."""
+    q = [p % np_[0], (p // np_[0]) % np_[1], p // (np_[0] * np_[1])]
+    dd = [code % 3 - 1, (code // 3) % 3 - 1, code // 9 - 1]
+    q = [(q[a] + dd[a]) % np_[a] for a in range(3)]
+    return q[0] + np_[0] * (q[1] + np_[1] * q[2])
