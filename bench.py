@@ -27,8 +27,9 @@ if ROOT not in sys.path:
 METRIC = "particle-steps/sec (gather+push+deposit+Maxwell) & % HBM peak; batched p50/p99"
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per particle-step of the fused particle kernel: read the
-# position (2 components), momentum (3) and weight, write position and momentum
-BYTES_PER_PARTICLE_STEP = {32: 44, 64: 88}
+# position (2 or 3 components), momentum (3) and weight, write position and
+# momentum
+BYTES_PER_PARTICLE_STEP = {(2, 32): 44, (2, 64): 88, (3, 32): 52, (3, 64): 104}
 
 
 def _workload(name, steps):
@@ -41,6 +42,12 @@ def _workload(name, steps):
     elif name == "lwfa_small":
         wl = W.lwfa_2d_small(nsteps=max(steps, 1))
         desc = "lwfa_2d_small: 512x128 cells, 32x32-cell patches, 4 ppc"
+    elif name == "blob3d":
+        wl = W.blob_3d(patch=(8, 8, 8))
+        desc = ("blob_3d: 512x256x256 cells (dx=0.1 c/w_p), periodic, 8x8x8-cell patches "
+                "(each 16^3 patch of the configuration as 8 GPU patches), ppc=round(8 n/n0) with "
+                f"n = n0 (1 + 0.9 cos kx) and a 4 n0 sphere of radius 20 cells, 10 keV "
+                f"({wl['w'].size / 1e6:.1f}M particles)")
     elif name == "uniform":
         wl = W.uniform_2d()
         desc = "uniform_2d: 128x128 cells, 16x16-cell patches, 16 ppc, 1 keV, periodic"
@@ -77,7 +84,12 @@ def _cpu_baseline(name, budget_s=25.0):
     """Time the FP64 oracle (single-threaded C, as it stands) on one step of
     the same workload on this host."""
     import oracle
-    wl, _ = _workload(name, 1)
+    if name == "blob3d":
+        # one eighth of the box (256 x 128 x 128 cells, same density profile)
+        from paper_1511_03878_amd import workloads as W
+        wl = W.blob_3d(n=(256, 128, 128), patch=(8, 8, 8))
+    else:
+        wl, _ = _workload(name, 1)
     if not os.path.exists(os.path.join(ROOT, "oracle", "liborc.so")):
         oracle.build(force=False)
     o = oracle.Sim(wl["grid"])
@@ -94,7 +106,8 @@ def _cpu_baseline(name, budget_s=25.0):
             break
     dt = time.perf_counter() - t0
     return {"value": n * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} step(s) of the full workload ({n} particles), FP64 oracle, "
+            "sample": f"{steps} step(s) of {'one eighth of ' if name == 'blob3d' else ''}"
+                      f"the workload ({n} particles), FP64 oracle, "
                       f"{dt:.1f} s on one host core"}
 
 
@@ -203,13 +216,18 @@ def main():
     wl, desc = _workload(args.workload, args.steps)
     print(f"[bench] workload ready: {desc}", file=sys.stderr, flush=True)
 
-    if args.warmup > 0:
+    if args.warmup > 0 and wl["grid"]["ndim"] == 2:
         w = Sim.from_workload(wl, precision=args.precision)
         w.step(args.warmup)
         w.sync()
         w.close()
         del w
     sim = Sim.from_workload(wl, precision=args.precision)
+    if args.warmup > 0 and wl["grid"]["ndim"] == 3:
+        # the 3-D box is statistically stationary: warm up on the timed instance
+        sim.step(args.warmup)
+        sim.sync()
+    step0 = sim.diag()["step"]
     if not args.no_kernel_timing:
         sim.timing_enable(True)
     torch.cuda.synchronize()
@@ -220,7 +238,7 @@ def main():
     t1 = time.perf_counter()
     sim.sync()
     wall = t1 - t0
-    _, _, pushed = sim.history(0, args.steps)
+    _, _, pushed = sim.history(step0, args.steps)
     total = int(pushed.sum())
     value = total / wall
     timing = sim.timing() if not args.no_kernel_timing else {}
@@ -230,12 +248,13 @@ def main():
     if timing:
         ms, launches = timing["particles"]
         avg_s = ms / 1e3 / max(launches, 1)
-        per_launch_bytes = BYTES_PER_PARTICLE_STEP[args.precision] * total / max(launches, 1)
+        ndim = wl["grid"]["ndim"]
+        per_launch_bytes = BYTES_PER_PARTICLE_STEP[(ndim, args.precision)] * total / max(launches, 1)
         achieved = per_launch_bytes / avg_s / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": _measured_traffic(args.precision, args.workload),
-                "kernel": "k_particles2d",
+                "kernel": "k_particles2d" if wl["grid"]["ndim"] == 2 else "k_particles3d",
                 "algorithmic_bytes_per_launch": per_launch_bytes,
                 "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in timing.items()}}
 

@@ -140,3 +140,62 @@ def test_blob3d_batch_matches_alone():
     assert done == 2
     for s, ref in zip(sims, alone):
         assert rel_l2([s.field(c) for c in ("Ex", "Ey", "Ez", "Bx", "By", "Bz")], ref) < 1e-12
+
+
+def test_full_blob3d_sampled_push_and_slab_continuity():
+    """The 512 x 256 x 256 box (2.8e8 particles, 8^3-cell patches) in the
+    configuration bench.py times (FP32).  After one step (fields nonzero),
+    the second step of 2000 sampled particles matches the oracle's gather,
+    Boris push and move evaluated one by one on the GPU's own fields and
+    state; charge continuity holds on a slab of node planes; no particle is
+    lost."""
+    _announce("3-D blob 512x256x256 fp32 (2.8e8 particles): sampled push and slab continuity")
+    wl = W.to_float32_state(W.blob_3d(patch=(8, 8, 8)))
+    grid = wl["grid"]
+    N = wl["w"].size
+    assert np.all(wl["w"] == wl["w"][0])  # constant weight (ppc follows the density)
+    g = gpu_sim(wl, 32)
+    del wl
+    _announce("  loaded; stepping")
+    g.step(1)
+    x0, u0, _, id0 = g.particles()
+    F = [g.field(c) for c in ("Ex", "Ey", "Ez", "Bx", "By", "Bz")]
+    g.step(1)
+    x1, u1, w1, id1 = g.particles()
+    assert id1.size == N and g.diag()["removed"] == 0
+    pos1 = np.empty(N, dtype=np.int64)
+    pos1[id1] = np.arange(N)
+
+    _announce("  two steps done; sampled push against the oracle")
+    # sampled push against the oracle's per-particle operations
+    o = oracle.Sim(grid)
+    for c in range(6):
+        o.set_field(c, F[c])
+    del F
+    rng = np.random.default_rng(11)
+    n, d, dt, q, m = grid["n"], grid["d"], grid["dt"], grid["q"], grid["m"]
+    for k in rng.choice(N, 2000, replace=False):
+        xi = [x0[a][k] for a in range(3)]
+        EB = o.gather(xi)
+        u = oracle.boris([u0[a][k] for a in range(3)], EB[:3], EB[3:], q, m, dt)
+        gam = np.sqrt(1.0 + np.dot(u, u))
+        j = pos1[id0[k]]
+        for a in range(3):
+            assert abs(u1[a][j] - u[a]) <= 2e-6 * max(1.0, np.abs(u).max()), (k, a, u1[a][j], u[a])
+            xn = (xi[a] + dt * u[a] / (gam * d[a])) % n[a]
+            dx = (x1[a][j] - xn + n[a] / 2) % n[a] - n[a] / 2
+            assert abs(dx) < 2e-5, (k, a, x1[a][j], xn)
+    del o, u0, u1
+
+    _announce("  continuity on a slab")
+    # continuity on node planes x = 103, 104 from the particles of x0 in [100, 108)
+    J = [g.field(c) for c in ("Jx", "Jy", "Jz")]
+    sel = (x0[0] >= 100.0) & (x0[0] < 108.0)
+    ids = id0[sel]
+    xa = [x0[a][sel] for a in range(3)]
+    xb = [x1[a][pos1[ids]] for a in range(3)]
+    r0 = _rho3(xa, np.full(ids.size, w1[0]), -1.0, n)
+    r1 = _rho3(xb, np.full(ids.size, w1[0]), -1.0, n)
+    div = sum((J[a] - np.roll(J[a], 1, axis=2 - a)) / d[a] for a in range(3))
+    res = (r1 - r0 + dt * div)[:, :, 103:105]
+    assert np.abs(res).max() / np.abs(r0[:, :, 103:105]).max() < 1e-6
