@@ -186,6 +186,20 @@ int pic_history_get(PicSim *s, int64_t first, int64_t n, double *U, double *K, i
 
 /* ---- re-binning as a function (test hook) ---------------------------------- */
 
+/* Checkpoint / resume.  pic_state_save writes the whole simulation state
+ * (E and B of the current time level, the last deposit J, the particles in
+ * canonical (patch, slot) order with their ids, patch counts, step and
+ * removed counters, energy history) into a host buffer: with blob == NULL it
+ * only stores the bytes needed in *size; otherwise *size must be at least
+ * that and receives the bytes written.  Fails with PIC_ESTATE while a
+ * capacity-overflow recovery is pending.  pic_state_load restores such a
+ * blob into a handle created with the same grid, patch layout and precision
+ * (PIC_EINVAL otherwise; the handle is unchanged when the header is
+ * rejected), after which stepping continues bit for bit as from the saved
+ * handle.  Both synchronise the handle's stream; the blob is borrowed. */
+int pic_state_save(PicSim *s, void *blob, size_t *size);
+int pic_state_load(PicSim *s, const void *blob, size_t size);
+
 /* Apply only the re-binning to the current particles, with the destination
  * of each particle given in (patch, slot) order as a direction code:
  * (dx+1) + 3 (dy+1) for a move to the neighbour patch (dx, dy) in

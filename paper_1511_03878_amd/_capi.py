@@ -25,7 +25,8 @@ EXPORTS = (
     "pic_patch_counts_get", "pic_diag_get", "pic_history_get", "pic_rebin_codes",
     "pic_timing_enable", "pic_timing_get", "pic_batch_create", "pic_batch_destroy",
     "pic_batch_add", "pic_batch_remove", "pic_batch_step", "pic_batch_finished",
-    "pic_batch_size", "pic_estimate_bytes", "pic_strerror", "pic_last_error",
+    "pic_batch_size", "pic_estimate_bytes", "pic_state_save", "pic_state_load", "pic_strerror",
+    "pic_last_error",
 )
 
 
@@ -113,6 +114,8 @@ def load() -> C.CDLL:
         "pic_batch_finished": (C.c_int, [_vp, C.POINTER(_vp), C.c_int32, _I32]),
         "pic_batch_size": (C.c_int, [_vp, _I32]),
         "pic_estimate_bytes": (C.c_int, [C.POINTER(SimDesc), C.c_int64, C.c_int64, _I64]),
+        "pic_state_save": (C.c_int, [_vp, _vp, C.POINTER(C.c_size_t)]),
+        "pic_state_load": (C.c_int, [_vp, _vp, C.c_size_t]),
         "pic_strerror": (C.c_char_p, [C.c_int]),
         "pic_last_error": (C.c_char_p, []),
     }

@@ -244,6 +244,27 @@ int pic_history_get(PicSim *s, int64_t first, int64_t n, double *U, double *K, i
     return guarded([&] { s->impl->history(first, n, U, K, pushed); });
 }
 
+int pic_state_save(PicSim *s, void *blob, size_t *size)
+{
+    if (!s || !size) return bad(PIC_EINVAL, "null argument");
+    return guarded([&] {
+        const size_t need = s->impl->state_bytes();
+        if (!blob) {
+            *size = need;
+            return;
+        }
+        if (*size < need) throw Error(PIC_EINVAL, "checkpoint buffer too small");
+        s->impl->state_save(blob);
+        *size = need;
+    });
+}
+
+int pic_state_load(PicSim *s, const void *blob, size_t size)
+{
+    if (!s || !blob) return bad(PIC_EINVAL, "null argument");
+    return guarded([&] { s->impl->state_load(blob, size); });
+}
+
 int pic_rebin_codes(PicSim *s, const uint8_t *codes, size_t count)
 {
     if (!s || (count && !codes)) return bad(PIC_EINVAL, "null argument");

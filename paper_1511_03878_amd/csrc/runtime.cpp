@@ -613,6 +613,166 @@ void SimImpl<T>::history(int64_t first, int64_t cnt, double *U, double *K, int64
     }
 }
 
+// ---------------------------------------------------------------------------
+// checkpoint
+//
+// Blob layout (host byte order): a header, the patch counts, E and B of the
+// current time level and the last deposit (3 + 3 + 3 arrays of fsize values
+// of the simulation's precision), the particles in canonical (patch, slot)
+// order (patch-local positions per axis, three momenta, weight, 64-bit id),
+// and the energy-history ring.
+
+namespace {
+struct CkptHeader {
+    char magic[8];
+    int32_t version, ndim, precision, npatch;
+    int32_t n[3], patch[3], periodic[3];
+    int64_t live, step, removed, fsize;
+    double U, K;
+};
+constexpr char kCkptMagic[8] = {'P', 'I', 'C', 'S', 'T', 'A', 'T', 'E'};
+}  // namespace
+
+template <typename T>
+size_t SimImpl<T>::state_bytes()
+{
+    const int64_t live = num_particles();
+    return sizeof(CkptHeader) + sizeof(int32_t) * npatch + sizeof(T) * 9 * fsize +
+           (size_t)live * (sizeof(T) * (nd + 4) + sizeof(int64_t)) + sizeof(double) * kHistLen * 4;
+}
+
+template <typename T>
+void SimImpl<T>::state_save(void *blob)
+{
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    const SimState s = read_state();
+    if (s.flags & kFlagPending) throw Error(PIC_ESTATE, "a re-binning is pending");
+    const std::vector<int32_t> c = read_counts();
+    const int64_t live = std::accumulate(c.begin(), c.end(), int64_t(0));
+    CkptHeader h;
+    std::memset(&h, 0, sizeof(h));
+    std::memcpy(h.magic, kCkptMagic, 8);
+    h.version = 1;
+    h.ndim = nd;
+    h.precision = precision;
+    h.npatch = npatch;
+    for (int a = 0; a < 3; ++a) { h.n[a] = n[a]; h.patch[a] = P[a]; h.periodic[a] = periodic[a]; }
+    h.live = live;
+    h.step = s.step;
+    h.removed = s.removed;
+    h.fsize = fsize;
+    h.U = s.U;
+    h.K = s.K;
+    char *o = static_cast<char *>(blob);
+    std::memcpy(o, &h, sizeof(h));
+    o += sizeof(h);
+    std::memcpy(o, c.data(), sizeof(int32_t) * npatch);
+    o += sizeof(int32_t) * npatch;
+    auto d2h = [&](const void *src, size_t bytes) {
+        hipcheck(hipMemcpyAsync(o, src, bytes, hipMemcpyDeviceToHost, stream), "checkpoint");
+        o += bytes;
+    };
+    for (int k = 0; k < 6; ++k) d2h(F[s.step & 1][k], sizeof(T) * fsize);
+    for (int k = 0; k < 3; ++k) d2h(J[(s.step + 1) & 1][k], sizeof(T) * fsize);
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    // particles: compact each array patch by patch
+    const int64_t tot = total_cap;
+    std::vector<T> tmp(tot);
+    auto pack = [&](const T *src) {
+        hipcheck(hipMemcpyAsync(tmp.data(), src, sizeof(T) * tot, hipMemcpyDeviceToHost, stream), "checkpoint");
+        hipcheck(hipStreamSynchronize(stream), "sync");
+        for (int p = 0; p < npatch; ++p) {
+            std::memcpy(o, tmp.data() + off_h[p], sizeof(T) * c[p]);
+            o += sizeof(T) * c[p];
+        }
+    };
+    for (int a = 0; a < nd; ++a) pack(px[a]);
+    for (int a = 0; a < 3; ++a) pack(pu[a]);
+    pack(pw);
+    std::vector<int64_t> itmp(tot);
+    hipcheck(hipMemcpyAsync(itmp.data(), pid, sizeof(int64_t) * tot, hipMemcpyDeviceToHost, stream), "checkpoint");
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    for (int p = 0; p < npatch; ++p) {
+        std::memcpy(o, itmp.data() + off_h[p], sizeof(int64_t) * c[p]);
+        o += sizeof(int64_t) * c[p];
+    }
+    d2h(hist, sizeof(double) * kHistLen * 4);
+    hipcheck(hipStreamSynchronize(stream), "sync");
+}
+
+template <typename T>
+void SimImpl<T>::state_load(const void *blob, size_t size)
+{
+    check_free();
+    if (size < sizeof(CkptHeader)) throw Error(PIC_EINVAL, "checkpoint too small");
+    CkptHeader h;
+    std::memcpy(&h, blob, sizeof(h));
+    if (std::memcmp(h.magic, kCkptMagic, 8) || h.version != 1) throw Error(PIC_EINVAL, "not a checkpoint");
+    bool same = h.ndim == nd && h.precision == precision && h.npatch == npatch && h.fsize == fsize;
+    for (int a = 0; a < 3; ++a)
+        same = same && h.n[a] == n[a] && h.patch[a] == P[a] && h.periodic[a] == periodic[a];
+    if (!same) throw Error(PIC_EINVAL, "checkpoint of a different grid, patch layout or precision");
+    const char *i = static_cast<const char *>(blob) + sizeof(h);
+    std::vector<int32_t> c(npatch);
+    std::memcpy(c.data(), i, sizeof(int32_t) * npatch);
+    i += sizeof(int32_t) * npatch;
+    int64_t live = 0;
+    for (int32_t v : c) {
+        if (v < 0) throw Error(PIC_EINVAL, "corrupt checkpoint");
+        live += v;
+    }
+    if (live != h.live) throw Error(PIC_EINVAL, "corrupt checkpoint");
+    const size_t need = sizeof(CkptHeader) + sizeof(int32_t) * npatch + sizeof(T) * 9 * fsize +
+                        (size_t)live * (sizeof(T) * (nd + 4) + sizeof(int64_t)) + sizeof(double) * kHistLen * 4;
+    if (size < need) throw Error(PIC_EINVAL, "checkpoint truncated");
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    // fields: the current level into F[step & 1], the last deposit into J[(step + 1) & 1]
+    auto h2d = [&](void *dst, size_t bytes) {
+        hipcheck(hipMemcpyAsync(dst, i, bytes, hipMemcpyHostToDevice, stream), "restore");
+        i += bytes;
+    };
+    for (int k = 0; k < 6; ++k) h2d(F[h.step & 1][k], sizeof(T) * fsize);
+    for (int k = 0; k < 3; ++k) h2d(J[(h.step + 1) & 1][k], sizeof(T) * fsize);
+    for (int k = 0; k < 3; ++k) hipcheck(hipMemsetAsync(J[h.step & 1][k], 0, sizeof(T) * fsize, stream), "restore");
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    // particles into a fresh layout
+    std::vector<void *> old = layout_particles(c);
+    for (void *p : old) alloc.put(p);
+    const int64_t tot = total_cap;
+    std::vector<T> tmp(tot);
+    auto unpack = [&](T *dst) {
+        std::fill(tmp.begin(), tmp.end(), T(0));
+        for (int p = 0; p < npatch; ++p) {
+            std::memcpy(tmp.data() + off_h[p], i, sizeof(T) * c[p]);
+            i += sizeof(T) * c[p];
+        }
+        hipcheck(hipMemcpyAsync(dst, tmp.data(), sizeof(T) * tot, hipMemcpyHostToDevice, stream), "restore");
+        hipcheck(hipStreamSynchronize(stream), "sync");
+    };
+    for (int a = 0; a < nd; ++a) unpack(px[a]);
+    for (int a = 0; a < 3; ++a) unpack(pu[a]);
+    unpack(pw);
+    std::vector<int64_t> itmp(tot, -1);
+    for (int p = 0; p < npatch; ++p) {
+        std::memcpy(itmp.data() + off_h[p], i, sizeof(int64_t) * c[p]);
+        i += sizeof(int64_t) * c[p];
+    }
+    hipcheck(hipMemcpyAsync(pid, itmp.data(), sizeof(int64_t) * tot, hipMemcpyHostToDevice, stream), "restore");
+    hipcheck(hipMemsetAsync(code, ndir / 2, tot, stream), "restore");
+    hipcheck(hipMemcpyAsync(counts_d, c.data(), sizeof(int32_t) * npatch, hipMemcpyHostToDevice, stream), "restore");
+    h2d(hist, sizeof(double) * kHistLen * 4);
+    SimState s0;
+    std::memset(&s0, 0, sizeof(s0));
+    s0.step = h.step;
+    s0.removed = h.removed;
+    s0.U = h.U;
+    s0.K = h.K;
+    hipcheck(hipMemcpyAsync(st, &s0, sizeof(s0), hipMemcpyHostToDevice, stream), "restore");
+    hipcheck(hipMemsetAsync(kpart, 0, sizeof(double) * npatch, stream), "restore");
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    if (solo) solo->dirty = true;
+}
+
 // Grow patch capacities (only ever grows) so that every patch holds both its
 // current particles and the count the pending re-binning needs, and copy the
 // particles into the new layout.

@@ -197,6 +197,21 @@ class Sim:
                                            P.ctypes.data_as(C.POINTER(C.c_int64))))
         return U, K, P
 
+    def save_state(self) -> bytes:
+        """Checkpoint of the whole simulation state (host bytes)."""
+        lib = _capi.load()
+        n = C.c_size_t()
+        check(lib.pic_state_save(self._h, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        check(lib.pic_state_save(self._h, C.cast(buf, C.c_void_p), C.byref(n)))
+        return buf.raw[:n.value]
+
+    def load_state(self, blob: bytes):
+        """Restore a checkpoint written by save_state of a simulation with the
+        same grid, patches and precision."""
+        buf = C.create_string_buffer(bytes(blob), len(blob))
+        check(_capi.load().pic_state_load(self._h, C.cast(buf, C.c_void_p), len(blob)))
+
     def rebin_codes(self, codes):
         c = np.ascontiguousarray(codes, dtype=np.uint8)
         check(_capi.load().pic_rebin_codes(self._h, c.ctypes.data_as(C.POINTER(C.c_uint8)), c.size))

@@ -155,3 +155,44 @@ def test_empty_simulation_steps():
     g.set_particles([np.zeros(0), np.zeros(0)], [np.zeros(0)] * 3, np.zeros(0))
     g.step(3)
     assert g.diag()["step"] == 3 and g.num_particles() == 0
+
+
+@pytest.mark.parametrize("case", ["uniform_fp64", "lwfa_fp32", "blob3d_fp64"])
+def test_checkpoint_round_trip_and_resume(case):
+    """Save after k steps and restore into a fresh handle: saving again gives
+    the same bytes; stepping on matches the uninterrupted run (float atomics
+    reorder sums, so FP64 within 1e-12 with exact counts and ids, FP32 within
+    1e-5)."""
+    _announce(f"checkpoint / resume: {case}")
+    if case == "uniform_fp64":
+        wl, prec, k, m = W.uniform_2d(n=(64, 64), patch=(16, 16), ppc=4, T_keV=50.0), 64, 7, 6
+    elif case == "lwfa_fp32":
+        wl, prec, k, m = W.to_float32_state(W.lwfa_2d_small(nsteps=40)), 32, 20, 15
+    else:
+        wl, prec, k, m = W.blob_3d(n=(32, 16, 16), d=(0.1, 0.1, 0.1), patch=(8, 8, 4), ppc0=2,
+                                   blob_radius=4.0, T_keV=30.0), 64, 4, 5
+    ref = gpu_sim(wl, prec)
+    ref.step(k + m)
+    a = gpu_sim(wl, prec)
+    a.step(k)
+    blob = a.save_state()
+    a.close()
+    from paper_1511_03878_amd.sim import Sim
+    b = Sim(wl["grid"], prec)
+    b.load_state(blob)
+    assert b.save_state() == blob
+    if wl.get("laser"):
+        b.set_laser(wl["laser"].get("ey"), wl["laser"].get("ez"))
+    b.step(m)
+    tol = 1e-12 if prec == 64 else 1e-5
+    comps = ("Ex", "Ey", "Ez", "Bx", "By", "Bz")
+    assert rel_l2([b.field(c) for c in comps], [ref.field(c) for c in comps]) < tol
+    assert b.diag()["step"] == ref.diag()["step"] == k + m
+    Ub, Kb, _ = b.history(k, m)
+    Ur, Kr, _ = ref.history(k, m)
+    assert np.allclose(Ub, Ur, rtol=100 * tol, atol=0) and np.allclose(Kb, Kr, rtol=100 * tol, atol=0)
+    if prec == 64:
+        assert np.array_equal(b.counts(), ref.counts())
+        assert np.array_equal(b.particles()[3], ref.particles()[3])
+    else:
+        assert b.counts().sum() == ref.counts().sum()
