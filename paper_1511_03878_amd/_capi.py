@@ -43,6 +43,7 @@ class SimDesc(C.Structure):
         ("periodic", C.c_int32 * 3), ("q", C.c_double), ("m", C.c_double),
         ("capacity_factor", C.c_double), ("min_capacity", C.c_int32), ("chunk", C.c_int32),
         ("block", C.c_int32), ("field_tile", C.c_int32), ("lane_stride", C.c_int32),
+        ("graph", C.c_int32),
     ]
 
 

@@ -102,6 +102,7 @@ int validate_desc(const PicSimDesc &d, std::string &why)
     if (d.field_tile < 0 || d.field_tile > 5) { why = "field_tile must be 0..5"; return PIC_EINVAL; }
     if (d.lane_stride < 0 || d.lane_stride > 64) { why = "lane_stride must be 0..64"; return PIC_EINVAL; }
     if (d.block != 0 && d.block != 256 && d.block != 512 && d.block != 1024) { why = "block must be 0, 256, 512 or 1024"; return PIC_EINVAL; }
+    if (d.graph != 0 && d.graph != 1) { why = "graph must be 0 or 1"; return PIC_EINVAL; }
     return PIC_OK;
 }
 
@@ -929,14 +930,62 @@ BatchImpl<T>::BatchImpl(hipStream_t s) { stream = s; precision = sizeof(T) == 4 
 template <typename T>
 BatchImpl<T>::~BatchImpl()
 {
+    free_graph();
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
     if (!solo_mode)
         for (auto *m : members) m->batch = nullptr;
     free_tables();
 }
 
 template <typename T>
+void BatchImpl<T>::free_graph()
+{
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    graph_exec = nullptr;
+}
+
+// Capture kGraphSteps step passes into a graph on a private stream (a null
+// stream cannot be captured); the graph is replayed on the batch's stream.
+// Kernel arguments are the batch tables, so the graph lives until they are
+// rebuilt.  On any capture failure graphs are switched off for the batch.
+template <typename T>
+bool BatchImpl<T>::capture_graph()
+{
+    if (graph_failed) return false;
+    if (!capture_stream) {
+        if (hipStreamCreateWithFlags(&capture_stream, hipStreamNonBlocking) != hipSuccess) {
+            capture_stream = nullptr;
+            graph_failed = true;
+            return false;
+        }
+    }
+    hipStream_t user = stream;
+    stream = capture_stream;
+    hipGraph_t g = nullptr;
+    bool ok = hipStreamBeginCapture(capture_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+        try {
+            for (int k = 0; k < kGraphSteps; ++k) launch_one_step();
+        } catch (...) {
+            ok = false;
+        }
+        ok = (hipStreamEndCapture(capture_stream, &g) == hipSuccess) && ok && g;
+    }
+    stream = user;
+    if (ok) ok = hipGraphInstantiate(&graph_exec, g, nullptr, nullptr, 0) == hipSuccess;
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    if (!ok) {
+        graph_exec = nullptr;
+        graph_failed = true;
+    }
+    return ok;
+}
+
+template <typename T>
 void BatchImpl<T>::free_tables()
 {
+    free_graph();
     for (void *p : table_bufs) {
         if (p) (void)hipFree(p);
     }
@@ -1027,6 +1076,8 @@ void BatchImpl<T>::build_tables()
     }
     for (auto *m : members) items += m->max_items(chunk);
     items = std::max<int64_t>(items, 1);
+    use_graph = false;
+    for (auto *m : members) use_graph = use_graph || m->desc.graph;
     block = (sizeof(T) == 8 && nd == 2) ? 1024 : 512;
     for (auto *m : members) if (m->desc.block) block = m->desc.block;
     const int occ = std::max(1, nd == 3 ? particles3d_occupancy<T>(block, maxP0, maxP1, maxP2)
@@ -1148,7 +1199,7 @@ int BatchImpl<T>::run(int64_t max_steps, bool until_done)
         if (!(s.flags & kFlagErrMask)) budget = std::max(budget, s.steps_left);
     }
     int64_t launched = 0;
-    const int64_t K = 32;
+    const int64_t K = kGraphSteps;
     int finished = 0;
     launch_close_queue_pass();  // queue of the first step
     for (;;) {
@@ -1156,7 +1207,15 @@ int BatchImpl<T>::run(int64_t max_steps, bool until_done)
         int64_t todo = std::min<int64_t>(K, budget);
         if (!until_done) todo = std::min<int64_t>(todo, max_steps - launched);
         if (todo <= 0) break;
-        for (int64_t k = 0; k < todo; ++k) launch_one_step();
+        bool replayed = false;
+        if (todo == kGraphSteps && use_graph && !timing().enabled) {
+            if (graph_exec || capture_graph()) {
+                hipcheck(hipGraphLaunch(graph_exec, stream), "graph launch");
+                replayed = true;
+            }
+        }
+        if (!replayed)
+            for (int64_t k = 0; k < todo; ++k) launch_one_step();
         launched += todo;
         // poll member states
         bool any_left = false;

@@ -175,6 +175,13 @@ struct BatchImpl : BatchBase {
     int chunk = 256, block = 256, tile_preset = 0, patch_const = 0;
     int grid_particles = 1, grid_maxwell = 1, grid_rebin = 1;
     Timing own_timing;
+    // step batches replayed from a captured graph
+    static constexpr int kGraphSteps = 32;
+    bool use_graph = false, graph_failed = false;
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t capture_stream = nullptr;
+    void free_graph();
+    bool capture_graph();
 
     explicit BatchImpl(hipStream_t s);
     ~BatchImpl() override;
