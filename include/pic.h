@@ -188,6 +188,24 @@ int pic_history_get(PicSim *s, int64_t first, int64_t n, double *U, double *K, i
 
 /* ---- re-binning as a function (test hook) ---------------------------------- */
 
+/* Launch-setting tuner.  Tries, by coordinate descent, the workgroup size of
+ * the particle kernel, the Yee tile shape (2-D), the lane stride and the
+ * chunk size; each candidate runs `steps` steps (0 = 10) from the same saved
+ * state, and the simulation's state is restored afterwards (tuning does not
+ * advance it).  The fastest settings are applied to the handle.  With a
+ * non-NULL `cache` path the result is stored in that text file under a key
+ * of dimensions, precision, grid, patch shape and particle count (to a
+ * factor of two); a later call with the same key applies the stored
+ * settings without running.  `out` (may be NULL) receives the settings in
+ * effect.  Not for members of a batch (PIC_ESTATE). */
+typedef struct {
+    int32_t block, field_tile, lane_stride, chunk;
+    double ms_per_step;    /* of the chosen settings (0 on a cache hit) */
+    int32_t trials;        /* candidates timed */
+    int32_t from_cache;    /* 1 when the settings came from the cache */
+} PicTuneResult;
+int pic_autotune(PicSim *s, int32_t steps, const char *cache, PicTuneResult *out);
+
 /* Checkpoint / resume.  pic_state_save writes the whole simulation state
  * (E and B of the current time level, the last deposit J, the particles in
  * canonical (patch, slot) order with their ids, patch counts, step and

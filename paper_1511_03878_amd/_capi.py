@@ -25,7 +25,8 @@ EXPORTS = (
     "pic_patch_counts_get", "pic_diag_get", "pic_history_get", "pic_rebin_codes",
     "pic_timing_enable", "pic_timing_get", "pic_batch_create", "pic_batch_destroy",
     "pic_batch_add", "pic_batch_remove", "pic_batch_step", "pic_batch_finished",
-    "pic_batch_size", "pic_estimate_bytes", "pic_state_save", "pic_state_load", "pic_strerror",
+    "pic_batch_size", "pic_estimate_bytes", "pic_autotune", "pic_state_save", "pic_state_load",
+    "pic_strerror",
     "pic_last_error",
 )
 
@@ -44,6 +45,14 @@ class SimDesc(C.Structure):
         ("capacity_factor", C.c_double), ("min_capacity", C.c_int32), ("chunk", C.c_int32),
         ("block", C.c_int32), ("field_tile", C.c_int32), ("lane_stride", C.c_int32),
         ("graph", C.c_int32),
+    ]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [
+        ("block", C.c_int32), ("field_tile", C.c_int32), ("lane_stride", C.c_int32),
+        ("chunk", C.c_int32), ("ms_per_step", C.c_double), ("trials", C.c_int32),
+        ("from_cache", C.c_int32),
     ]
 
 
@@ -115,6 +124,7 @@ def load() -> C.CDLL:
         "pic_batch_finished": (C.c_int, [_vp, C.POINTER(_vp), C.c_int32, _I32]),
         "pic_batch_size": (C.c_int, [_vp, _I32]),
         "pic_estimate_bytes": (C.c_int, [C.POINTER(SimDesc), C.c_int64, C.c_int64, _I64]),
+        "pic_autotune": (C.c_int, [_vp, C.c_int32, C.c_char_p, C.POINTER(TuneResult)]),
         "pic_state_save": (C.c_int, [_vp, _vp, C.POINTER(C.c_size_t)]),
         "pic_state_load": (C.c_int, [_vp, _vp, C.c_size_t]),
         "pic_strerror": (C.c_char_p, [C.c_int]),

@@ -244,6 +244,13 @@ int pic_history_get(PicSim *s, int64_t first, int64_t n, double *U, double *K, i
     return guarded([&] { s->impl->history(first, n, U, K, pushed); });
 }
 
+int pic_autotune(PicSim *s, int32_t steps, const char *cache, PicTuneResult *out)
+{
+    if (!s) return bad(PIC_EINVAL, "null handle");
+    if (steps < 0) return bad(PIC_EINVAL, "negative step count");
+    return guarded([&] { s->impl->autotune(steps, cache, out); });
+}
+
 int pic_state_save(PicSim *s, void *blob, size_t *size)
 {
     if (!s || !size) return bad(PIC_EINVAL, "null argument");

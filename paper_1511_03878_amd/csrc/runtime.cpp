@@ -4,6 +4,10 @@
 // capi.cpp.
 #include "runtime.h"
 
+#include <chrono>
+#include <cstdio>
+#include <fstream>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -772,6 +776,97 @@ void SimImpl<T>::state_load(const void *blob, size_t size)
     hipcheck(hipMemsetAsync(kpart, 0, sizeof(double) * npatch, stream), "restore");
     hipcheck(hipStreamSynchronize(stream), "sync");
     if (solo) solo->dirty = true;
+}
+
+// ---------------------------------------------------------------------------
+// launch-setting tuner
+
+template <typename T>
+void SimImpl<T>::autotune(int steps, const char *cache, PicTuneResult *out)
+{
+    check_free();
+    if (steps <= 0) steps = 10;
+    const int64_t live = num_particles();
+    int bucket = 0;
+    while (((int64_t)1 << bucket) < std::max<int64_t>(live, 1)) ++bucket;
+    char key[160];
+    std::snprintf(key, sizeof(key), "pic-tune nd=%d prec=%d n=%d,%d,%d patch=%d,%d,%d np2=%d", nd, precision,
+                  n[0], n[1], n[2], P[0], P[1], P[2], bucket);
+    struct Cfg {
+        int block, field_tile, lane_stride, chunk;
+    };
+    auto apply = [&](const Cfg &c) {
+        desc.block = c.block;
+        desc.field_tile = c.field_tile;
+        desc.chunk = c.chunk;
+        lane_stride = c.lane_stride;
+        refresh_view();
+        if (solo) solo->dirty = true;
+    };
+    PicTuneResult res;
+    std::memset(&res, 0, sizeof(res));
+    // cache lookup: "<key> block field_tile lane_stride chunk"
+    if (cache) {
+        std::ifstream f(cache);
+        std::string line;
+        const std::string k(key);
+        while (std::getline(f, line)) {
+            if (line.compare(0, k.size(), k) != 0 || line.size() <= k.size() || line[k.size()] != ' ') continue;
+            Cfg c;
+            if (std::sscanf(line.c_str() + k.size(), "%d %d %d %d", &c.block, &c.field_tile, &c.lane_stride,
+                            &c.chunk) == 4) {
+                apply(c);
+                res = {c.block, c.field_tile, c.lane_stride, c.chunk, 0.0, 0, 1};
+                if (out) *out = res;
+                return;
+            }
+        }
+    }
+    std::vector<char> blob(state_bytes());
+    state_save(blob.data());
+    const int ls0 = lane_stride;
+    auto timed = [&](const Cfg &c) {
+        apply(c);
+        state_load(blob.data(), blob.size());
+        hipcheck(hipStreamSynchronize(stream), "sync");
+        const auto t0 = std::chrono::steady_clock::now();
+        step(steps);
+        hipcheck(hipStreamSynchronize(stream), "sync");
+        const auto t1 = std::chrono::steady_clock::now();
+        ++res.trials;
+        return std::chrono::duration<double, std::milli>(t1 - t0).count() / steps;
+    };
+    Cfg best{desc.block, desc.field_tile, ls0, desc.chunk};
+    double best_ms = timed(best);
+    auto try_knob = [&](int Cfg::*field, std::initializer_list<int> values) {
+        for (int v : values) {
+            if (v == best.*field) continue;
+            Cfg c = best;
+            c.*field = v;
+            const double ms = timed(c);
+            if (ms < 0.99 * best_ms) {
+                best = c;
+                best_ms = ms;
+            }
+        }
+    };
+    try_knob(&Cfg::block, {256, 512, 1024});
+    if (nd == 2) try_knob(&Cfg::field_tile, {1, 2, 3, 4, 5});
+    try_knob(&Cfg::lane_stride, {std::max(1, ls0 / 2), std::min(64, ls0 * 2), 1});
+    try_knob(&Cfg::chunk, {1024, 2048, 4096, 8192});
+    apply(best);
+    state_load(blob.data(), blob.size());
+    res.block = best.block;
+    res.field_tile = best.field_tile;
+    res.lane_stride = best.lane_stride;
+    res.chunk = best.chunk;
+    res.ms_per_step = best_ms;
+    if (cache) {
+        std::ofstream f(cache, std::ios::app);
+        f << key << ' ' << best.block << ' ' << best.field_tile << ' ' << best.lane_stride << ' ' << best.chunk
+          << '\n';
+    }
+    if (out) *out = res;
 }
 
 // Grow patch capacities (only ever grows) so that every patch holds both its

@@ -73,6 +73,7 @@ struct SimBase {
     virtual void step(int64_t nsteps) = 0;
     virtual bool in_batch() const = 0;
     virtual size_t device_bytes() const = 0;
+    virtual void autotune(int steps, const char *cache, PicTuneResult *out) = 0;
     // checkpoint: bytes of the blob, write it, restore from it
     virtual size_t state_bytes() = 0;
     virtual void state_save(void *blob) = 0;
@@ -146,6 +147,7 @@ struct SimImpl : SimBase {
     void step(int64_t nsteps) override;
     bool in_batch() const override { return batch != nullptr; }
     size_t device_bytes() const override { return alloc.live_bytes; }
+    void autotune(int steps, const char *cache, PicTuneResult *out) override;
     size_t state_bytes() override;
     void state_save(void *blob) override;
     void state_load(const void *blob, size_t size) override;

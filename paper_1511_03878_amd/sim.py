@@ -197,6 +197,14 @@ class Sim:
                                            P.ctypes.data_as(C.POINTER(C.c_int64))))
         return U, K, P
 
+    def autotune(self, steps: int = 10, cache: str | None = None) -> dict:
+        """Pick the fastest launch settings for this simulation (its state is
+        restored afterwards); with a cache file, reuse a stored choice."""
+        r = _capi.TuneResult()
+        check(_capi.load().pic_autotune(self._h, int(steps),
+                                        cache.encode() if cache else None, C.byref(r)))
+        return {k: getattr(r, k) for k, _ in _capi.TuneResult._fields_}
+
     def save_state(self) -> bytes:
         """Checkpoint of the whole simulation state (host bytes)."""
         lib = _capi.load()

@@ -225,3 +225,26 @@ def test_graph_replays_match_plain_launches():
     assert np.array_equal(g.counts(), o.counts())
     assert np.array_equal(g.particles()[3], o.particles()[3])
     assert g.diag()["relayouts"] >= 1
+
+
+def test_autotune_restores_state_and_caches(tmp_path):
+    _announce("autotune: state restored, settings cached")
+    wl = W.lwfa_2d_small(nsteps=200)
+    g = gpu_sim(wl, 32)
+    g.step(30)
+    before = [g.field(c) for c in ("Ex", "Ey", "Bz")] + [g.particles()[3], g.counts()]
+    cache = str(tmp_path / "tune.txt")
+    r = g.autotune(steps=4, cache=cache)
+    assert r["from_cache"] == 0 and r["trials"] >= 8
+    assert r["block"] in (256, 512, 1024) and 0 <= r["field_tile"] <= 5 and 1 <= r["lane_stride"] <= 64
+    after = [g.field(c) for c in ("Ex", "Ey", "Bz")] + [g.particles()[3], g.counts()]
+    for a, b in zip(before, after):
+        assert np.array_equal(a, b)
+    assert g.diag()["step"] == 30
+    g.step(10)  # the tuned settings run
+    assert g.diag()["step"] == 40
+    h = gpu_sim(wl, 32)
+    r2 = h.autotune(steps=4, cache=cache)
+    assert r2["from_cache"] == 1 and r2["trials"] == 0
+    assert (r2["block"], r2["field_tile"], r2["lane_stride"], r2["chunk"]) == \
+        (r["block"], r["field_tile"], r["lane_stride"], r["chunk"])
