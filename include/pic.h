@@ -103,7 +103,7 @@ typedef struct {
     int32_t block;         /* threads per particle workgroup: 256, 512 or 1024; 0 = 512 (FP32) / 1024 (FP64) */
     int32_t field_tile;    /* Yee tile shape preset 0..5 (0 = default for the precision) */
     int32_t lane_stride;   /* particles between adjacent lanes of the particle kernel, 1..64;
-                              0 = about two cells' worth (from the loaded particles) */
+                              0 = 2 */
     int32_t graph;         /* 1: step in batches of 32 replayed from a captured HIP graph
                               (when kernel timing is off); 0: plain launches */
 } PicSimDesc;

@@ -120,14 +120,13 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
         double kin = 0.0;
         uint32_t err = 0;
 
-        // Lane mapping.  Particles of one cell sit next to each other in a
-        // patch, and LDS atomics of lanes that hit one address (or bank)
-        // serialise.  The chunk is cut into units of 64 lanes: unit u takes
-        // particles 64 S (u / S) + l S + (u % S) for lanes l = 0..63, so with
-        // S about two cells' worth of particles the lanes of one wave sit two
-        // cells apart and their shape windows start at distinct nodes.  Waves
-        // take units round-robin; the next unit's particle is loaded before
-        // the current one is pushed.
+        // Lane mapping.  The chunk is cut into units of 64 lanes: unit u
+        // takes particles 64 S (u / S) + l S + (u % S) for lanes l = 0..63
+        // (S = lane_stride).  A larger S spreads the lanes of a wave over
+        // more cells (fewer LDS atomics on one address) but makes every
+        // particle load and store touch more cache lines; S = 2 is the
+        // measured balance.  Waves take units round-robin; the next unit's
+        // particle is loaded before the current one is pushed.
         constexpr int NW = BLOCK / kWave;
         const int S_ = S.lane_stride;
         const int wv = __builtin_amdgcn_readfirstlane(tid / kWave), ln = tid % kWave;

@@ -114,7 +114,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles3d(const SimDev<T> *__restri
         double kin = 0.0;
         uint32_t err = 0;
 
-        // lanes take particles lane_stride apart (about two cells), as in 2-D
+        // lanes take particles lane_stride apart, as in 2-D
         constexpr int NW = BLOCK / kWave;
         const int S_ = S.lane_stride;
         const int wv = __builtin_amdgcn_readfirstlane(tid / kWave), ln = tid % kWave;

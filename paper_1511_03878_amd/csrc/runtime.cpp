@@ -422,18 +422,12 @@ void SimImpl<T>::set_particles(int64_t cnt, const double *const xs[3], const dou
         pp[k] = cell_of(k, 0) / P[0] + np[0] * (cell_of(k, 1) / P[1] + np[1] * (cell_of(k, 2) / P[2]));
         counts[pp[k]]++;
     }
-    {
-        // lane stride of the particle kernel: about two cells' worth of
-        // particles between lanes (cells hold their particles in a run)
-        std::vector<uint8_t> occupied((size_t)n[0] * n[1] * n[2], 0);
-        for (int64_t k = 0; k < cnt; ++k)
-            occupied[(size_t)cell_of(k, 0) + (size_t)n[0] * ((size_t)cell_of(k, 1) + (size_t)n[1] * cell_of(k, 2))] = 1;
-        int64_t cells = 0;
-        for (uint8_t o : occupied) cells += o;
-        const double ppc = cells ? (double)cnt / cells : 1.0;
-        lane_stride = desc.lane_stride ? desc.lane_stride
-                                       : (int)std::max(1.0, std::min(64.0, std::round(2.0 * ppc)));
-    }
+    // lane stride of the particle kernel: neighbouring lanes take particles
+    // two slots apart.  Wider strides (lanes in different cells, fewer LDS
+    // atomics on one address) cost more in uncoalesced particle loads than
+    // they save: measured on the laser box, stride 8 (two cells) is 1.5x
+    // slower than stride 2.
+    lane_stride = desc.lane_stride ? desc.lane_stride : 2;
     hipcheck(hipStreamSynchronize(stream), "sync");
     std::vector<void *> old = layout_particles(counts);
     for (void *p : old) alloc.put(p);
