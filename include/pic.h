@@ -229,7 +229,12 @@ int pic_rebin_codes(PicSim *s, const uint8_t *codes, size_t count);
 
 /* ---- timing ------------------------------------------------------------------ */
 
-int pic_timing_enable(PicSim *s, int on);
+/* Per-kernel timing from start/stop events recorded by the dispatches.
+ * mode 0: off; 1: every kernel group (queue, particles, Yee, re-binning);
+ * 2: the particle kernel only (one event pair per step, the least
+ * perturbation).  Enabling resets the totals; timing also turns graph
+ * replay off while on. */
+int pic_timing_enable(PicSim *s, int mode);
 int pic_timing_get(PicSim *s, PicTiming *out); /* synchronises */
 
 /* ---- batches of simulations stepped together ------------------------------- */

@@ -281,9 +281,11 @@ int pic_rebin_codes(PicSim *s, const uint8_t *codes, size_t count)
 int pic_timing_enable(PicSim *s, int on)
 {
     if (!s) return bad(PIC_EINVAL, "null handle");
+    if (on < 0 || on > 2) return bad(PIC_EINVAL, "timing mode must be 0, 1 or 2");
     return guarded([&] {
         s->impl->timing.collect();
         s->impl->timing.enabled = on != 0;
+        s->impl->timing.only = on == 2 ? 1 : -1;
         if (on) {
             for (int k = 0; k < Timing::kKinds; ++k) {
                 s->impl->timing.total_ms[k] = 0;

@@ -1,0 +1,202 @@
+// Re-binning helpers: neighbour-table rows, particle copies and the
+// per-patch leaver count of the re-binning kernels.
+#pragma once
+
+#include "pic_dev.h"
+
+namespace pic {
+
+// The neighbour table of a simulation (built once on the host from the patch
+// grid) holds per patch: the canonical key of each of the ND directions (the
+// smallest direction reaching the same neighbour; -1 when the neighbour is the
+// patch itself, i.e. the particle stays; ND when it leaves an open face),
+// then the number of distinct source patches, the sources in ascending id and
+// the key under which each source stages the particles it sends here.  Key ND
+// also stands for a removed particle.
+template <int ND>
+__device__ __forceinline__ gptr_t<const int32_t> nb_row(const int32_t *nbt, int p)
+{
+    return glb(nbt) + (int64_t)p * nb_stride(ND);
+}
+
+template <typename T>
+__device__ __forceinline__ void copy_particle(const SimDev<T> &S, int64_t from, int64_t to,
+                                              bool from_stage, bool to_stage)
+{
+    T *const *fx = from_stage ? S.sx : S.x;
+    T *const *fu = from_stage ? S.su : S.u;
+    const T *fw = from_stage ? S.sw : S.w;
+    const int64_t *fi = from_stage ? S.sid : S.id;
+    T *const *tx = to_stage ? S.sx : S.x;
+    T *const *tu = to_stage ? S.su : S.u;
+    T *tw = to_stage ? S.sw : S.w;
+    int64_t *ti = to_stage ? S.sid : S.id;
+    glb(tx[0])[to] = glb(fx[0])[from];
+    glb(tx[1])[to] = glb(fx[1])[from];
+    if (S.ndim == 3) glb(tx[2])[to] = glb(fx[2])[from];
+    glb(tu[0])[to] = glb(fu[0])[from];
+    glb(tu[1])[to] = glb(fu[1])[from];
+    glb(tu[2])[to] = glb(fu[2])[from];
+    glb(tw)[to] = glb(fw)[from];
+    glb(ti)[to] = glb(fi)[from];
+}
+
+// Count pass.  Each wave of the workgroup owns a contiguous range of the
+// patch's slots and loads the destination codes of up to kU x 64 of them at
+// once (one batch; a patch of at most waves x kU x 64 particles is one batch).
+// Leaver counts per key come from ballots, one per key present in a 64-slot
+// chunk, and are kept lane-indexed in a register (lane k: key k, lane kKeys:
+// all keys).  After one exchange of the per-wave counts through LDS every wave
+// knows where its leavers go: the vacated slots are listed in slot order and
+// the staged leavers are queued in a per-wave LDS ring, which is drained 64
+// entries at a time (one lane per particle, so the particle loads of 64
+// leavers are in flight together).
+constexpr int kRC = 512;  // threads of the count workgroup of the re-binning kernel
+constexpr int kU = 32;    // 64-slot chunks per batch of code loads
+constexpr int kRing = 128;
+
+template <typename T>
+__device__ __forceinline__ void drain_ring(const SimDev<T> &S, int64_t base, const int2 *ring,
+                                           int &head, int tail, int lane)
+{
+    // copy up to 64 queued leavers (ring positions head .. min(tail, head + 64))
+    const int n = min(64, tail - head);
+    if (lane < n) {
+        const int2 e = ring[(head + lane) & (kRing - 1)];
+        copy_particle(S, base + e.x, base + e.y, false, true);
+    }
+    head += n;
+}
+
+template <int ND, int NWV>
+struct CountSmem {
+    uint8_t kb[256];             // code -> key + 1 (0: the particle stays)
+    int wc[NWV][ND + 3];         // per wave: leavers of each key, then of all keys
+    int2 ring[NWV][kRing];       // per wave: (slot, staging slot) of queued leavers
+};
+
+// Leavers of patch p: per-key counts (kcnt, nleave), the vacated slots in
+// ascending order (holes) and the staged copies of the leavers, grouped by
+// destination key in slot order.  Called by every thread of a workgroup of
+// NWV waves (contains barriers).
+template <typename T, int ND, int NWV>
+__device__ __forceinline__ void count_patch(const SimDev<T> &S, int p, CountSmem<ND, NWV> &sm)
+{
+    constexpr int kKeys = ND + 1;  // ND direction keys + removed
+    constexpr int kThreads = NWV * 64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int n = glb(S.count)[p];
+    const int64_t base = glb(S.off)[p];
+    const gptr_t<const uint8_t> code = glb((const uint8_t *)S.code) + base;
+    if (tid < 256) {
+        int kb = 0;
+        if (tid < ND) kb = nb_row<ND>(S.nbt, p)[tid] + 1;
+        else if (tid == kRemoved) kb = ND + 1;
+        sm.kb[tid] = (uint8_t)kb;
+    }
+    __syncthreads();
+
+    const int per = ((n + kThreads - 1) / kThreads) * 64;
+    const int lo = min(n, wave * per), hi = min(n, lo + per);
+    const bool one = hi - lo <= 64 * kU;
+    // keys + 1 of the batch, four 64-slot chunks per register
+    uint32_t cw[kU / 4];
+    auto load = [&](int q0) {
+        const gptr_t<const uint8_t> cp = code + q0 + lane;
+        const int left = hi - q0 - lane;  // chunk u holds a slot while 64 u < left
+        uint8_t t[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) t[u] = 64 * u < left ? cp[64 * u] : uint8_t(ND / 2);
+#pragma unroll
+        for (int u = 0; u < kU; u += 4)
+            cw[u / 4] = (uint32_t)sm.kb[t[u]] | ((uint32_t)sm.kb[t[u + 1]] << 8) |
+                        ((uint32_t)sm.kb[t[u + 2]] << 16) | ((uint32_t)sm.kb[t[u + 3]] << 24);
+    };
+    auto key1 = [&](int u) { return (int)((cw[u / 4] >> (8 * (u % 4))) & 0xffu); };
+
+    // ---- walk 1: leavers per key in [lo, hi) ------------------------------
+    int cnt = 0;
+    for (int q0 = lo; q0 < hi; q0 += 64 * kU) {
+        load(q0);
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            if (q0 + 64 * u >= hi) break;
+            const int kc = key1(u);
+            uint64_t m = __ballot(kc != 0);
+            cnt += lane == kKeys ? __popcll(m) : 0;
+            while (m) {
+                const int kk = __builtin_amdgcn_readlane(kc, __ffsll((long long)m) - 1);
+                const uint64_t b = __ballot(kc == kk);
+                cnt += lane == kk - 1 ? __popcll(b) : 0;
+                m &= ~b;
+            }
+        }
+    }
+    if (lane <= kKeys) sm.wc[wave][lane] = cnt;
+    __syncthreads();
+
+    // ---- starting points: lane k of wave w holds the staging slot of the
+    // next key-k leaver of the wave (key offset + earlier waves), lane kKeys
+    // the next hole index ---------------------------------------------------
+    int run = 0;
+    if (lane <= kKeys) {
+        for (int w = 0; w < wave; ++w) run += sm.wc[w][lane];
+        if (lane < kKeys)
+            for (int kk = 0; kk < lane; ++kk)
+                for (int w = 0; w < NWV; ++w) run += sm.wc[w][kk];
+    }
+    if (wave == 0 && lane <= kKeys) {
+        int tot = 0;
+        for (int w = 0; w < NWV; ++w) tot += sm.wc[w][lane];
+        if (lane < ND) glb(S.kcnt)[p * ND + lane] = tot;
+        if (lane == kKeys) glb(S.nleave)[p] = tot;
+    }
+
+    // ---- walk 2: list holes, queue and copy staged leavers -----------------
+    if (__builtin_amdgcn_readlane(cnt, kKeys) > 0) {
+        int2 *ring = sm.ring[wave];
+        int head = 0, tail = 0;
+        for (int q0 = lo; q0 < hi; q0 += 64 * kU) {
+            if (!one) load(q0);
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                if (q0 + 64 * u >= hi) break;
+                const int kc = key1(u);
+                const int k = q0 + 64 * u + lane;
+                uint64_t m = __ballot(kc != 0);
+                if (!m) continue;
+                const int h0 = __builtin_amdgcn_readlane(run, kKeys);
+                if (kc) glb(S.holes)[base + h0 + __popcll(m & lt)] = k;
+                run += lane == kKeys ? __popcll(m) : 0;
+                const uint64_t st = m & ~__ballot(kc == ND + 1);
+                int dest = 0;
+                while (m) {
+                    const int kk = __builtin_amdgcn_readlane(kc, __ffsll((long long)m) - 1);
+                    const uint64_t b = __ballot(kc == kk);
+                    const int r0 = __builtin_amdgcn_readlane(run, kk - 1);
+                    if (kc == kk) dest = r0 + __popcll(b & lt);
+                    run += lane == kk - 1 ? __popcll(b) : 0;
+                    m &= ~b;
+                }
+                if (st) {
+                    if ((st >> lane) & 1)
+                        ring[(tail + __popcll(st & lt)) & (kRing - 1)] = make_int2(k, dest);
+                    tail += __popcll(st);
+                    __builtin_amdgcn_wave_barrier();
+                    if (tail - head >= 64) {
+                        drain_ring(S, base, ring, head, tail, lane);
+                        __builtin_amdgcn_wave_barrier();
+                    }
+                }
+            }
+        }
+        while (head < tail) {
+            drain_ring(S, base, ring, head, tail, lane);
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    __syncthreads();
+}
+
+}  // namespace pic

@@ -975,7 +975,7 @@ void SimImpl<T>::check_free()
 Ev2 Timing::pair(int k)
 {
     Ev2 r;
-    if (!enabled) return r;
+    if (!enabled || (only >= 0 && k != only)) return r;
     Ev e;
     e.kind = k;
     auto take = [&](hipEvent_t &ev) {

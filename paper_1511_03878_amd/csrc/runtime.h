@@ -40,6 +40,7 @@ struct Timing {
         hipEvent_t a, b;
     };
     bool enabled = false;
+    int only = -1;  // time only this kind (-1: all)
     std::vector<Ev> events;
     std::vector<hipEvent_t> pool;
     double total_ms[kKinds] = {0, 0, 0, 0};

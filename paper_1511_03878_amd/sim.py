@@ -224,8 +224,11 @@ class Sim:
         c = np.ascontiguousarray(codes, dtype=np.uint8)
         check(_capi.load().pic_rebin_codes(self._h, c.ctypes.data_as(C.POINTER(C.c_uint8)), c.size))
 
-    def timing_enable(self, on: bool = True):
-        check(_capi.load().pic_timing_enable(self._h, 1 if on else 0))
+    def timing_enable(self, on=True):
+        """True / 1: time every kernel group; 2 or "particles": the particle
+        kernel only; False / 0: off."""
+        mode = 2 if on == "particles" else int(on)
+        check(_capi.load().pic_timing_enable(self._h, mode))
 
     def timing(self) -> dict:
         t = _capi.Timing()
