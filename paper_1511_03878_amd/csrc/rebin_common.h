@@ -51,7 +51,7 @@ __device__ __forceinline__ void copy_particle(const SimDev<T> &S, int64_t from, 
 // the staged leavers are queued in a per-wave LDS ring, which is drained 64
 // entries at a time (one lane per particle, so the particle loads of 64
 // leavers are in flight together).
-constexpr int kRC = 512;  // threads of the count workgroup of the re-binning kernel
+constexpr int kRC = 256;  // threads of the count workgroup of the re-binning kernel
 constexpr int kU = 32;    // 64-slot chunks per batch of code loads
 constexpr int kRing = 128;
 
