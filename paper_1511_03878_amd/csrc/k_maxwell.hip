@@ -194,7 +194,7 @@ __global__ __launch_bounds__(256) void k_maxwell2d(const SimDev<T> *__restrict__
 // FP32 tiles hold 9 x (TX+3)(TY+3) floats of LDS, FP64 tiles doubles.
 namespace {
 constexpr int kTiles32[6][2] = {{64, 16}, {64, 8}, {128, 8}, {32, 16}, {32, 32}, {128, 4}};
-constexpr int kTiles64[6][2] = {{32, 16}, {64, 8}, {32, 8}, {16, 16}, {64, 4}, {128, 4}};
+constexpr int kTiles64[6][2] = {{64, 8}, {32, 16}, {32, 8}, {16, 16}, {64, 4}, {128, 4}};
 }  // namespace
 
 template <typename T>
@@ -224,12 +224,12 @@ void launch_maxwell(const SimDev<T> *sims, int nsims, const int *tile_prefix, in
         }
     } else {
         switch (p) {
-        case 1: PIC_MW(64, 8); break;
+        case 1: PIC_MW(32, 16); break;
         case 2: PIC_MW(32, 8); break;
         case 3: PIC_MW(16, 16); break;
         case 4: PIC_MW(64, 4); break;
         case 5: PIC_MW(128, 4); break;
-        default: PIC_MW(32, 16); break;
+        default: PIC_MW(64, 8); break;
         }
     }
 #undef PIC_MW
