@@ -71,39 +71,9 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
         const int n0 = S.n[0], n1 = S.n[1], fn0 = S.fn[0];
         const int per0 = S.periodic[0], per1 = S.periodic[1];
 
-        // ---- stage E, B of nodes [ox-1, ox+P0+1] x [oy-1, oy+P1+1] --------
-        T *const *Fc = S.F[glb(S.st)->step & 1];
-        // four nodes per thread per round, all loads issued before the stores
-        for (int t0 = 0; t0 < fw * fh; t0 += 4 * BLOCK) {
-            T v[4][6];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int t = t0 + r * BLOCK + tid;
-                const int gi = ox - 1 + t % fw, gj = oy - 1 + t / fw;
-                const bool in = t < fw * fh;
-                const int ip = in ? axis_node(gi, n0, per0, 0) : -1;
-                const int id = in ? axis_node(gi, n0, per0, 1) : -1;
-                const int jp = in ? axis_node(gj, n1, per1, 0) : -1;
-                const int jd = in ? axis_node(gj, n1, per1, 1) : -1;
-                // staggering: Ex (d,p) Ey (p,d) Ez (p,p) Bx (p,d) By (d,p) Bz (d,d)
-                v[r][0] = (id >= 0 && jp >= 0) ? glb(Fc[0])[id + fn0 * jp] : T(0);
-                v[r][1] = (ip >= 0 && jd >= 0) ? glb(Fc[1])[ip + fn0 * jd] : T(0);
-                v[r][2] = (ip >= 0 && jp >= 0) ? glb(Fc[2])[ip + fn0 * jp] : T(0);
-                v[r][3] = (ip >= 0 && jd >= 0) ? glb(Fc[3])[ip + fn0 * jd] : T(0);
-                v[r][4] = (id >= 0 && jp >= 0) ? glb(Fc[4])[id + fn0 * jp] : T(0);
-                v[r][5] = (id >= 0 && jd >= 0) ? glb(Fc[5])[id + fn0 * jd] : T(0);
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int t = t0 + r * BLOCK + tid;
-                if (t < fw * fh)
-#pragma unroll
-                    for (int c = 0; c < 6; ++c) Ft[c * fstride + t] = v[r][c];
-            }
-        }
-        for (int t = tid; t < 3 * jstride; t += BLOCK) Jt[t] = 0.0;
-        __syncthreads();
-
+        // field level of this step and the item's particle range (two loads in flight)
+        const int par = __builtin_amdgcn_readfirstlane((int)(glb(S.st)->step & 1));
+        T *const *Fc = S.F[par];
         const int64_t base = glb(S.off)[p] + first;
         // the item's particles through 32-bit offsets from per-item bases
         const gptr_t<T> X0 = glb(S.x[0]) + base, X1 = glb(S.x[1]) + base;
@@ -120,40 +90,80 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
         double kin = 0.0;
         uint32_t err = 0;
 
-        // Lane mapping.  The chunk is cut into units of 64 lanes: unit u
-        // takes particles 64 S (u / S) + l S + (u % S) for lanes l = 0..63
-        // (S = lane_stride).  A larger S spreads the lanes of a wave over
-        // more cells (fewer LDS atomics on one address) but makes every
-        // particle load and store touch more cache lines; S = 2 is the
-        // measured balance.  Waves take units round-robin; the next unit's
-        // particle is loaded before the current one is pushed.
+        // Lane mapping.  The item's particles are cut into units of 64
+        // lanes.  Full passes of 64 S particles (S = lane_stride) give S units,
+        // unit u taking particles 64 S (u / S) + l S + (u % S) for lanes
+        // l = 0..63: a larger S spreads the lanes of a wave over more cells
+        // (fewer LDS atomics on one address) but makes every particle load and
+        // store touch more cache lines; S = 2 is the measured balance.  The
+        // rest after the last full pass is cut into units of 64 consecutive
+        // particles, so every unit holds at least one particle, and the lanes
+        // past the item's end repeat its last particle with zero weight: they
+        // compute and store the same values in the same instruction, and no
+        // lane branches around a memory access (the compiler would otherwise
+        // wait for the stores of one unit before starting the next).  Waves
+        // take units round-robin; the next unit's particle is loaded before
+        // the current one is pushed, and the first unit's before the field
+        // tile is staged (the two latencies overlap).
         constexpr int NW = BLOCK / kWave;
         const int S_ = S.lane_stride;
         const int wv = __builtin_amdgcn_readfirstlane(tid / kWave), ln = tid % kWave;
-        auto unit_particle = [&](int u) { return kWave * S_ * (u / S_) + ln * S_ + (u % S_); };
-        T nx_ = T(0), ny_ = T(0), nux = T(0), nuy = T(0), nuz = T(0), nw_ = T(0);
-        {
-            const int kn = unit_particle(wv);
-            if (kn < cnt) {
-                nx_ = X0[kn]; ny_ = X1[kn];
-                nux = U0[kn]; nuy = U1[kn]; nuz = U2[kn]; nw_ = Wt[kn];
-            }
-        }
-        // units past the last full pass may map outside [0, cnt): skipped
-        const int uend = ((cnt + kWave * S_ - 1) / (kWave * S_)) * S_;
-        for (int u = wv; u < uend; u += NW) {
-            const int k = unit_particle(u);
-            const T xl = nx_, yl = ny_;
-            T ux = nux, uy = nuy, uz = nuz;
-            const T wgt = nw_;
-            if (u + NW < uend) {
-                const int kn = unit_particle(u + NW);
-                if (kn < cnt) {
-                    nx_ = X0[kn]; ny_ = X1[kn];
-                    nux = U0[kn]; nuy = U1[kn]; nuz = U2[kn]; nw_ = Wt[kn];
+        const int npass = cnt / (kWave * S_), ufull = npass * S_;
+        const int uend = ufull + (cnt - npass * kWave * S_ + kWave - 1) / kWave;
+        auto unit_particle = [&](int u) {
+            return u < ufull ? kWave * S_ * (u / S_) + ln * S_ + (u % S_)
+                             : kWave * S_ * npass + kWave * (u - ufull) + ln;
+        };
+        // an item holds at least one particle, so index cnt - 1 is valid
+        T nx_, ny_, nux, nuy, nuz, nw_;
+        auto load_unit = [&](int u) {
+            const int kn = min(unit_particle(u), cnt - 1);
+            nx_ = X0[kn]; ny_ = X1[kn];
+            nux = U0[kn]; nuy = U1[kn]; nuz = U2[kn]; nw_ = Wt[kn];
+        };
+        load_unit(wv);
+        // ---- stage E, B of nodes [ox-1, ox+P0+1] x [oy-1, oy+P1+1] --------
+        // four nodes per thread per round, all loads issued before the stores
+        for (int t0 = 0; t0 < fw * fh; t0 += 4 * BLOCK) {
+            // Every load is unconditional, from node 0 where the tile node is
+            // outside the grid or past the tile, and zeroed afterwards: a
+            // load under a condition becomes a branch, and the compiler then
+            // waits for each load before issuing the next.
+            T v[4][6];
+            bool ok[4][6];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int t = t0 + r * BLOCK + tid;
+                const bool in = t < fw * fh;
+                const int tt = in ? t : 0;
+                const int gi = ox - 1 + tt % fw, gj = oy - 1 + tt / fw;
+                const int ip = axis_node(gi, n0, per0, 0), id = axis_node(gi, n0, per0, 1);
+                const int jp = axis_node(gj, n1, per1, 0), jd = axis_node(gj, n1, per1, 1);
+                // staggering: Ex (d,p) Ey (p,d) Ez (p,p) Bx (p,d) By (d,p) Bz (d,d)
+                const int ix[6] = {id, ip, ip, ip, id, id}, jy[6] = {jp, jd, jp, jd, jp, jd};
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    ok[r][c] = in && ix[c] >= 0 && jy[c] >= 0;
+                    v[r][c] = glb(Fc[c])[ok[r][c] ? ix[c] + fn0 * jy[c] : 0];
                 }
             }
-            if (k >= cnt) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int t = t0 + r * BLOCK + tid;
+                if (t < fw * fh)
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) Ft[c * fstride + t] = ok[r][c] ? v[r][c] : T(0);
+            }
+        }
+        for (int t = tid; t < 3 * jstride; t += BLOCK) Jt[t] = 0.0;
+        __syncthreads();
+
+        for (int u = wv; u < uend; u += NW) {
+            const int kr = unit_particle(u), k = min(kr, cnt - 1);
+            const T xl = nx_, yl = ny_;
+            T ux = nux, uy = nuy, uz = nuz;
+            const T wgt = kr < cnt ? nw_ : T(0);
+            load_unit(u + NW);
 
             // ---- gather ---------------------------------------------------
             const int ipx = (int)floor(xl + T(0.5)), idx_ = (int)floor(xl);
@@ -311,15 +321,15 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
 
         // ---- flush the current tile -------------------------------------------
         {
-            T *const *Jg = S.J[glb(S.st)->step & 1];
+            const gptr_t<T> Jgx = glb(S.J[par][0]), Jgy = glb(S.J[par][1]), Jgz = glb(S.J[par][2]);
             for (int t = tid; t < jw * jh; t += BLOCK) {
                 const int gi = ox - 2 + t % jw, gj = oy - 2 + t / jw;
                 const int ip = axis_node(gi, n0, per0, 0), id = axis_node(gi, n0, per0, 1);
                 const int jp = axis_node(gj, n1, per1, 0), jd = axis_node(gj, n1, per1, 1);
                 const T vx = (T)Jt[t], vy = (T)Jt[jstride + t], vz = (T)Jt[2 * jstride + t];
-                if (vx != T(0) && id >= 0 && jp >= 0) gadd(glb(Jg[0]) + (id + fn0 * jp), vx);
-                if (vy != T(0) && ip >= 0 && jd >= 0) gadd(glb(Jg[1]) + (ip + fn0 * jd), vy);
-                if (vz != T(0) && ip >= 0 && jp >= 0) gadd(glb(Jg[2]) + (ip + fn0 * jp), vz);
+                if (vx != T(0) && id >= 0 && jp >= 0) gadd(Jgx + (id + fn0 * jp), vx);
+                if (vy != T(0) && ip >= 0 && jd >= 0) gadd(Jgy + (ip + fn0 * jd), vy);
+                if (vz != T(0) && ip >= 0 && jp >= 0) gadd(Jgz + (ip + fn0 * jp), vz);
             }
         }
         // ---- kinetic energy and pushed count --------------------------------

@@ -7,7 +7,9 @@ stream.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import weakref
 
 import numpy as np
 
@@ -23,6 +25,30 @@ def _dp(a):
 
 def _f64(a):
     return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+# Handles still open at interpreter exit are closed by an exit hook: their
+# device memory goes back through torch's allocator, which must still be
+# there (module teardown would otherwise run the frees after torch is gone).
+# The hook is registered after torch is loaded, so it runs before torch's own.
+_LIVE_BATCHES: "weakref.WeakSet" = weakref.WeakSet()
+_LIVE_SIMS: "weakref.WeakSet" = weakref.WeakSet()
+_exit_hook = False
+
+
+def _close_all():
+    for b in list(_LIVE_BATCHES):
+        b.close()
+    for s in list(_LIVE_SIMS):
+        s.close()
+
+
+def _track(registry, obj):
+    global _exit_hook
+    if not _exit_hook:
+        atexit.register(_close_all)
+        _exit_hook = True
+    registry.add(obj)
 
 
 class _TorchAllocator:
@@ -94,6 +120,7 @@ class Sim:
         check(lib.pic_sim_create(C.byref(desc), C.byref(self._alloc.struct) if self._alloc else None,
                                  C.c_void_p(self.stream), C.byref(h)))
         self._h = h
+        _track(_LIVE_SIMS, self)
         self.ndim = int(grid["ndim"])
         n = list(grid["n"])
         per = list(grid.get("periodic", [1] * self.ndim))
@@ -245,6 +272,7 @@ class Batch:
         h = C.c_void_p()
         check(lib.pic_batch_create(int(ndim), int(precision), C.c_void_p(self.stream), C.byref(h)))
         self._h = h
+        _track(_LIVE_BATCHES, self)
         self.members = {}
 
     def add(self, sim: Sim, nsteps: int):
