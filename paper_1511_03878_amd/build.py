@@ -24,9 +24,18 @@ FLAGS = [
 ]
 
 
+# The particle kernels claim their next work item early and use the index
+# only much later; the atomic optimizer would rewrite that claim into a wave
+# reduction that waits for the result at once.
+EXTRA = {
+    "k_particles.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"],
+    "k_particles3d.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"],
+}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = ["hipcc", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = ["hipcc", *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr[-6000:]}")

@@ -48,21 +48,36 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
     // LDS float atomics are much slower here than FP64 ones), then fields
     double *Jt = reinterpret_cast<double *>(smem_raw);
     T *Ft = reinterpret_cast<T *>(Jt + 3 * jstride);
-    __shared__ int s_item;
-    __shared__ double s_red[BLOCK / kWave];
+    __shared__ int s_item[2];
 
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, ln = tid % kWave;
     const int total = *nitems;
-    for (;;) {
-        if (tid == 0) s_item = atomicAdd(head, 1);
-        __syncthreads();
-        const int idx = __builtin_amdgcn_readfirstlane(s_item);
-        __syncthreads();
-        if (idx >= total) break;
+    // Items are claimed one ahead: the next index is requested while the
+    // current item runs and published through the other of two LDS slots.
+    if (tid == 0) s_item[0] = atomicAdd(head, 1);
+    __syncthreads();
+    int idx = __builtin_amdgcn_readfirstlane(s_item[0]);
+    int slot = 1;
+    // Kinetic energy: a running sum per lane, reduced over the wave and
+    // added to the simulation's per-patch partials when the wave moves on to
+    // another simulation and at the end (partials of different waves land
+    // on different patches, so they rarely collide).
+    double kin = 0.0;
+    int kin_sim = -1, kin_p = 0;
+    auto flush_kin = [&]() {
+        const double t = wave_sum(kin);
+        if (kin_sim >= 0 && ln == 0) gadd(glb(sims[kin_sim].kpart) + kin_p, t * sims[kin_sim].vcell);
+        kin = 0.0;
+    };
+    while (idx < total) {
+        int next = 0;
+        if (tid == 0) next = atomicAdd(head, 1);
         const Item it = items[idx];
-        const SimDev<T> &S = sims[__builtin_amdgcn_readfirstlane(it.x)];
+        const int si = __builtin_amdgcn_readfirstlane(it.x & kItemSimMask);
+        const int par = __builtin_amdgcn_readfirstlane(it.x >> 30);  // field level of this step
+        const SimDev<T> &S = sims[si];
         const int p = __builtin_amdgcn_readfirstlane(it.y);
-        const int first = __builtin_amdgcn_readfirstlane(it.z);
+        const int64_t base = __builtin_amdgcn_readfirstlane(it.z);
         const int cnt = __builtin_amdgcn_readfirstlane(it.w);
         const int P0 = PC ? PC : S.P[0], P1 = PC ? PC : S.P[1];
         const int pxi = p % S.np[0], pyi = p / S.np[0];
@@ -71,10 +86,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
         const int n0 = S.n[0], n1 = S.n[1], fn0 = S.fn[0];
         const int per0 = S.periodic[0], per1 = S.periodic[1];
 
-        // field level of this step and the item's particle range (two loads in flight)
-        const int par = __builtin_amdgcn_readfirstlane((int)(glb(S.st)->step & 1));
         T *const *Fc = S.F[par];
-        const int64_t base = glb(S.off)[p] + first;
         // the item's particles through 32-bit offsets from per-item bases
         const gptr_t<T> X0 = glb(S.x[0]) + base, X1 = glb(S.x[1]) + base;
         const gptr_t<T> U0 = glb(S.u[0]) + base, U1 = glb(S.u[1]) + base, U2 = glb(S.u[2]) + base;
@@ -87,7 +99,11 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
         const double cy_ = -(double)q * (double)S.d[1] / (double)dt;
         const T Pmax0 = below((T)P0), Pmax1 = below((T)P1);
         const bool edge_lo = !per0 && pxi == 0, edge_hi = !per0 && pxi == S.np[0] - 1;
-        double kin = 0.0;
+        if (si != kin_sim) {
+            flush_kin();
+            kin_sim = si;
+        }
+        kin_p = p;
         uint32_t err = 0;
 
         // Lane mapping.  The item's particles are cut into units of 64
@@ -107,7 +123,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
         // tile is staged (the two latencies overlap).
         constexpr int NW = BLOCK / kWave;
         const int S_ = S.lane_stride;
-        const int wv = __builtin_amdgcn_readfirstlane(tid / kWave), ln = tid % kWave;
+        const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
         const int npass = cnt / (kWave * S_), ufull = npass * S_;
         const int uend = ufull + (cnt - npass * kWave * S_ + kWave - 1) / kWave;
         auto unit_particle = [&](int u) {
@@ -157,6 +173,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
         }
         for (int t = tid; t < 3 * jstride; t += BLOCK) Jt[t] = 0.0;
         __syncthreads();
+        if (tid == 0) s_item[slot] = next;  // read after the item's last barrier
 
         for (int u = wv; u < uend; u += NW) {
             const int kr = unit_particle(u), k = min(kr, cnt - 1);
@@ -332,20 +349,11 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
                 if (vz != T(0) && ip >= 0 && jp >= 0) gadd(Jgz + (ip + fn0 * jp), vz);
             }
         }
-        // ---- kinetic energy and pushed count --------------------------------
-        kin = wave_sum(kin);
-        if ((tid & (kWave - 1)) == 0) s_red[tid / kWave] = kin;
         __syncthreads();
-        if (tid == 0) {
-            // per-patch partial (chunks of one patch rarely collide); a single
-            // per-simulation accumulator would serialise every item on one
-            // L2 address
-            double tot = 0.0;
-            for (int wv = 0; wv < BLOCK / kWave; ++wv) tot += s_red[wv];
-            gadd(glb(S.kpart) + p, tot * S.vcell);
-        }
-        __syncthreads();
+        idx = __builtin_amdgcn_readfirstlane(s_item[slot]);
+        slot ^= 1;
     }
+    flush_kin();
 }
 
 template <typename T>

@@ -44,21 +44,31 @@ __global__ __launch_bounds__(BLOCK) void k_particles3d(const SimDev<T> *__restri
                                                        int *__restrict__ head)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ int s_item;
-    __shared__ double s_red[BLOCK / kWave];
+    __shared__ int s_item[2];
 
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, ln = tid % kWave;
     const int total = *glb(nitems);
-    for (;;) {
-        if (tid == 0) s_item = atomicAdd(head, 1);
-        __syncthreads();
-        const int idx = __builtin_amdgcn_readfirstlane(s_item);
-        __syncthreads();
-        if (idx >= total) break;
+    // items claimed one ahead, kinetic energy kept per wave (as in 2-D)
+    if (tid == 0) s_item[0] = atomicAdd(head, 1);
+    __syncthreads();
+    int idx = __builtin_amdgcn_readfirstlane(s_item[0]);
+    int slot = 1;
+    double kin = 0.0;
+    int kin_sim = -1, kin_p = 0;
+    auto flush_kin = [&]() {
+        const double t = wave_sum(kin);
+        if (kin_sim >= 0 && ln == 0) gadd(glb(sims[kin_sim].kpart) + kin_p, t * sims[kin_sim].vcell);
+        kin = 0.0;
+    };
+    while (idx < total) {
+        int next = 0;
+        if (tid == 0) next = atomicAdd(head, 1);
         const Item it = items[idx];
-        const SimDev<T> &S = sims[__builtin_amdgcn_readfirstlane(it.x)];
+        const int si = __builtin_amdgcn_readfirstlane(it.x & kItemSimMask);
+        const int par = __builtin_amdgcn_readfirstlane(it.x >> 30);
+        const SimDev<T> &S = sims[si];
         const int p = __builtin_amdgcn_readfirstlane(it.y);
-        const int first = __builtin_amdgcn_readfirstlane(it.z);
+        const int64_t base = __builtin_amdgcn_readfirstlane(it.z);
         const int cnt = __builtin_amdgcn_readfirstlane(it.w);
         const int P0 = S.P[0], P1 = S.P[1], P2 = S.P[2];
         const int pxi = p % S.np[0], pyi = (p / S.np[0]) % S.np[1], pzi = p / (S.np[0] * S.np[1]);
@@ -70,23 +80,53 @@ __global__ __launch_bounds__(BLOCK) void k_particles3d(const SimDev<T> *__restri
         T *Ft = reinterpret_cast<T *>(Jt + 3 * jstride);
         const int n0 = S.n[0], n1 = S.n[1], n2 = S.n[2];
         const int fn0 = S.fn[0], fn1 = S.fn[1];
+        if (si != kin_sim) {
+            flush_kin();
+            kin_sim = si;
+        }
+        kin_p = p;
+
+        const gptr_t<T> X0 = glb(S.x[0]) + base, X1 = glb(S.x[1]) + base, X2 = glb(S.x[2]) + base;
+        const gptr_t<T> U0 = glb(S.u[0]) + base, U1 = glb(S.u[1]) + base, U2 = glb(S.u[2]) + base;
+        const gptr_t<const T> Wt = glb((const T *)S.w) + base;
+        const gptr_t<uint8_t> Cd = glb(S.code) + base;
+
+        // lane mapping, remainder units and prefetch as in 2-D: no lane
+        // branches around a memory access, lanes past the end repeat the
+        // item's last particle with zero weight
+        constexpr int NW = BLOCK / kWave;
+        const int S_ = S.lane_stride;
+        const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
+        const int npass = cnt / (kWave * S_), ufull = npass * S_;
+        const int uend = ufull + (cnt - npass * kWave * S_ + kWave - 1) / kWave;
+        auto unit_particle = [&](int u) {
+            return u < ufull ? kWave * S_ * (u / S_) + ln * S_ + (u % S_)
+                             : kWave * S_ * npass + kWave * (u - ufull) + ln;
+        };
+        T nx_, ny_, nz_, nux, nuy, nuz, nw_;
+        auto load_unit = [&](int u) {
+            const int kn = min(unit_particle(u), cnt - 1);
+            nx_ = X0[kn]; ny_ = X1[kn]; nz_ = X2[kn];
+            nux = U0[kn]; nuy = U1[kn]; nuz = U2[kn]; nw_ = Wt[kn];
+        };
+        load_unit(wv);
 
         // ---- stage E, B of nodes [o-1, o+P+1] on every axis (periodic) -----
-        T *const *Fc = S.F[glb(S.st)->step & 1];
+        // (unconditional loads from an in-range node; only tile nodes are stored)
+        T *const *Fc = S.F[par];
         for (int t0 = 0; t0 < fstride; t0 += 4 * BLOCK) {
             T v[4][6];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int t = t0 + r * BLOCK + tid;
-                const bool in = t < fstride;
-                const int tt = in ? t : 0;  // keeps every computed index inside the grid
+                const int tt = t < fstride ? t : 0;
                 const int a = tt % fw, b = (tt / fw) % fh, c = tt / fwh;
                 const int gi = axis_node(ox - 1 + a, n0, 1, 0);
                 const int gj = axis_node(oy - 1 + b, n1, 1, 0);
                 const int gk = axis_node(oz - 1 + c, n2, 1, 0);
                 const int64_t k = gi + (int64_t)fn0 * (gj + (int64_t)fn1 * gk);
 #pragma unroll
-                for (int cc = 0; cc < 6; ++cc) v[r][cc] = in ? glb(Fc[cc])[k] : T(0);
+                for (int cc = 0; cc < 6; ++cc) v[r][cc] = glb(Fc[cc])[k];
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -98,12 +138,8 @@ __global__ __launch_bounds__(BLOCK) void k_particles3d(const SimDev<T> *__restri
         }
         for (int t = tid; t < 3 * jstride; t += BLOCK) Jt[t] = 0.0;
         __syncthreads();
+        if (tid == 0) s_item[slot] = next;  // read after the item's last barrier
 
-        const int64_t base = glb(S.off)[p] + first;
-        const gptr_t<T> X0 = glb(S.x[0]) + base, X1 = glb(S.x[1]) + base, X2 = glb(S.x[2]) + base;
-        const gptr_t<T> U0 = glb(S.u[0]) + base, U1 = glb(S.u[1]) + base, U2 = glb(S.u[2]) + base;
-        const gptr_t<const T> Wt = glb((const T *)S.w) + base;
-        const gptr_t<uint8_t> Cd = glb(S.code) + base;
         const T dt = S.dt, q = S.q, m = S.m;
         const T eps = q * dt / (T(2) * m);
         const T rdx = dt / S.d[0], rdy = dt / S.d[1], rdz = dt / S.d[2];
@@ -111,23 +147,16 @@ __global__ __launch_bounds__(BLOCK) void k_particles3d(const SimDev<T> *__restri
         const double cy_ = -(double)q * (double)S.d[1] / (double)dt;
         const double cz_ = -(double)q * (double)S.d[2] / (double)dt;
         const T Pmax0 = below((T)P0), Pmax1 = below((T)P1), Pmax2 = below((T)P2);
-        double kin = 0.0;
         uint32_t err = 0;
 
-        // lanes take particles lane_stride apart, as in 2-D
-        constexpr int NW = BLOCK / kWave;
-        const int S_ = S.lane_stride;
-        const int wv = __builtin_amdgcn_readfirstlane(tid / kWave), ln = tid % kWave;
-        auto unit_particle = [&](int u) { return kWave * S_ * (u / S_) + ln * S_ + (u % S_); };
-        const int uend = ((cnt + kWave * S_ - 1) / (kWave * S_)) * S_;
         for (int u = wv; u < uend; u += NW) {
-            const int k = unit_particle(u);
-            if (k >= cnt) continue;
-            const T xl = X0[k], yl = X1[k], zl = X2[k];
-            T ux = U0[k], uy = U1[k], uz = U2[k];
-            const T wgt = Wt[k];
+            const int kr = unit_particle(u), k = min(kr, cnt - 1);
+            const T xl = nx_, yl = ny_, zl = nz_;
+            T ux = nux, uy = nuy, uz = nuz;
+            const T wgt = kr < cnt ? nw_ : T(0);
+            load_unit(u + NW);
 
-            // ---- gather -----------------------------------------------------
+            // ---- gather -------------------------------------------------
             int ip[3], id[3];
             T wp[3][3], wd[3][3];
             const T xs[3] = {xl, yl, zl};
@@ -293,7 +322,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles3d(const SimDev<T> *__restri
 
         // ---- flush the current tile (nodes [o-2, o+P+2] on every axis) ------
         {
-            T *const *Jg = S.J[glb(S.st)->step & 1];
+            const gptr_t<T> Jgx = glb(S.J[par][0]), Jgy = glb(S.J[par][1]), Jgz = glb(S.J[par][2]);
             for (int t = tid; t < jstride; t += BLOCK) {
                 const int a = t % jw, b = (t / jw) % jh, c = t / jwh;
                 const int gi = axis_node(ox - 2 + a, n0, 1, 0);
@@ -301,22 +330,16 @@ __global__ __launch_bounds__(BLOCK) void k_particles3d(const SimDev<T> *__restri
                 const int gk = axis_node(oz - 2 + c, n2, 1, 0);
                 const int64_t k = gi + (int64_t)fn0 * (gj + (int64_t)fn1 * gk);
                 const T vx = (T)Jt[t], vy = (T)Jt[jstride + t], vz = (T)Jt[2 * jstride + t];
-                if (vx != T(0)) gadd(glb(Jg[0]) + k, vx);
-                if (vy != T(0)) gadd(glb(Jg[1]) + k, vy);
-                if (vz != T(0)) gadd(glb(Jg[2]) + k, vz);
+                if (vx != T(0)) gadd(Jgx + k, vx);
+                if (vy != T(0)) gadd(Jgy + k, vy);
+                if (vz != T(0)) gadd(Jgz + k, vz);
             }
         }
-        // ---- kinetic energy ---------------------------------------------------
-        kin = wave_sum(kin);
-        if ((tid & (kWave - 1)) == 0) s_red[tid / kWave] = kin;
         __syncthreads();
-        if (tid == 0) {
-            double tot = 0.0;
-            for (int w = 0; w < BLOCK / kWave; ++w) tot += s_red[w];
-            gadd(glb(S.kpart) + p, tot * S.vcell);
-        }
-        __syncthreads();
+        idx = __builtin_amdgcn_readfirstlane(s_item[slot]);
+        slot ^= 1;
     }
+    flush_kin();
 }
 
 }  // namespace

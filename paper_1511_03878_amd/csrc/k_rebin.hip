@@ -192,6 +192,7 @@ __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict
 {
     __shared__ int s_hist[kBuckets];
     __shared__ uint8_t s_act[kMaxBatch];
+    __shared__ uint8_t s_par[kMaxBatch];   // parity of the step the queue is for
     __shared__ int s_pushed[kMaxBatch];
     __shared__ int s_pp[kMaxBatch + 1];  // patch prefix of the batch
     __shared__ int s_cnt[kCntCache];     // particle counts of the first kCntCache patches
@@ -262,6 +263,7 @@ __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict
             const uint32_t act = left > 0 && !(flags & (kFlagPending | kFlagErrMask));
             st->active = act;
             s_act[s] = (uint8_t)act;
+            s_par[s] = (uint8_t)(st->step & 1);
             s_pushed[s] = 0;
         }
         __syncthreads();
@@ -352,12 +354,14 @@ __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict
     __syncthreads();
     // ---- phase B: placement ------------------------------------------------------
     const gptr_t<int> items = glb(reinterpret_cast<int *>(qa.items));
-    auto put = [&](int pos, int s, int p, int c0, int c) {
+    // item = {simulation | step parity << 30, patch, first slot, count}: the
+    // particle kernel starts on it without reading the simulation's state
+    auto put = [&](int pos, int s, int p, int64_t slot, int c) {
         if (pos >= qa.max_items) return;
         const gptr_t<int> it = items + 4 * (int64_t)pos;
-        it[0] = s;
+        it[0] = s | ((int)s_par[s] << 30);
         it[1] = p;
-        it[2] = c0;
+        it[2] = (int)slot;
         it[3] = c;
     };
     for (int g0 = 0; g0 < total; g0 += kQB) {
@@ -374,8 +378,9 @@ __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict
         int fbase = 0;
         if (lane == 0 && fsum) fbase = atomicAdd(&s_hist[0], fsum);
         fbase = __shfl(fbase, 0, 64) + incl_f - nfull;
-        for (int k = 0; k < nfull; ++k) put(fbase + k, s, p, k * chunk, chunk);
-        if (rem) put(atomicAdd(&s_hist[bucket(rem)], 1), s, p, nfull * chunk, rem);
+        const int64_t o = n > 0 ? glb((const int64_t *)sims[s].off)[p] : 0;
+        for (int k = 0; k < nfull; ++k) put(fbase + k, s, p, o + (int64_t)k * chunk, chunk);
+        if (rem) put(atomicAdd(&s_hist[bucket(rem)], 1), s, p, o + (int64_t)nfull * chunk, rem);
     }
     if (tid == 0) {
         *glb(qa.nitems) = min(ntot, qa.max_items);

@@ -14,8 +14,11 @@ struct Ev2 {
     hipEvent_t start = nullptr, stop = nullptr;
 };
 
-// Work item of the particle kernel: simulation slot, patch, first slot, count.
+// Work item of the particle kernel: {simulation slot | parity of the step
+// << 30, patch, slot of the item's first particle in the simulation's
+// particle arrays, count}.
 using Item = int4;
+constexpr int kItemSimMask = (1 << 30) - 1;
 
 struct QueueArgs {
     int nsims;

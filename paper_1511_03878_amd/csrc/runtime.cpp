@@ -332,6 +332,8 @@ std::vector<void *> SimImpl<T>::layout_particles(const std::vector<int32_t> &nee
         off[p + 1] = off[p] + c;
     }
     const int64_t total = off[npatch];
+    // work items address particle slots with 32-bit offsets
+    if (total > INT32_MAX) throw Error(PIC_EOVERFLOW, "more than 2^31 - 1 particle slots in one simulation");
     std::vector<void *> old;
     old.swap(part_bufs);
     try {
