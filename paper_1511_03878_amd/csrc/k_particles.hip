@@ -105,6 +105,8 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
         }
         kin_p = p;
         uint32_t err = 0;
+        bool left = false;  // a particle of this lane changed patch or was removed
+        float kin32 = 0.0f;
 
         // Lane mapping.  The item's particles are cut into units of 64
         // lanes.  Full passes of 64 S particles (S = lane_stride) give S units,
@@ -133,9 +135,9 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
         // an item holds at least one particle, so index cnt - 1 is valid
         T nx_, ny_, nux, nuy, nuz, nw_;
         auto load_unit = [&](int u) {
-            const int kn = min(unit_particle(u), cnt - 1);
-            nx_ = X0[kn]; ny_ = X1[kn];
-            nux = U0[kn]; nuy = U1[kn]; nuz = U2[kn]; nw_ = Wt[kn];
+            const uint32_t kn = min(unit_particle(u), cnt - 1);  // unsigned: base + 32-bit offset addressing
+            nx_ = *at(X0, kn); ny_ = *at(X1, kn);
+            nux = *at(U0, kn); nuy = *at(U1, kn); nuz = *at(U2, kn); nw_ = *at(Wt, kn);
         };
         load_unit(wv);
         // ---- stage E, B of nodes [ox-1, ox+P0+1] x [oy-1, oy+P1+1] --------
@@ -176,7 +178,8 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
         if (tid == 0) s_item[slot] = next;  // read after the item's last barrier
 
         for (int u = wv; u < uend; u += NW) {
-            const int kr = unit_particle(u), k = min(kr, cnt - 1);
+            const int kr = unit_particle(u);
+            const uint32_t k = min(kr, cnt - 1);
             const T xl = nx_, yl = ny_;
             T ux = nux, uy = nuy, uz = nuz;
             const T wgt = kr < cnt ? nw_ : T(0);
@@ -219,11 +222,12 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
             const T ig1 = rsq_(T(1) + usq1);
             // w m ((gamma0 - 1) + (gamma1 - 1)) / 2 with gamma - 1 = u^2 / (gamma + 1)
             // (no cancellation; FP32 storage keeps the diagnostic in FP32
-            // arithmetic, summed in FP64)
+            // arithmetic: a per-lane FP32 sum over the item, without the
+            // factor m / 2, added to the FP64 running sum once per item)
             if constexpr (sizeof(T) == 4) {
                 const float a0 = 1.0f + usq0;
                 const float g0p = a0 * rsq_(a0) + 1.0f, g1p = (1.0f + usq1) * ig1 + 1.0f;
-                kin += (double)(wgt * m * 0.5f * (usq0 * rcp_(g0p) + usq1 * rcp_(g1p)));
+                kin32 += wgt * (usq0 * g1p + usq1 * g0p) * rcp_(g0p * g1p);
             } else {
                 const double g0p = sqrt(1.0 + (double)usq0) + 1.0;
                 const double g1p = (double)(T(1) + usq1) * (double)ig1 + 1.0;
@@ -326,13 +330,17 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
                 if (y1 > Pmax1) y1 = Pmax1;
                 code = gone ? kRemoved : (uint8_t)((sx_ + 1) + 3 * (sy_ + 1));
             }
-            X0[k] = x1;
-            X1[k] = y1;
-            U0[k] = ux;
-            U1[k] = uy;
-            U2[k] = uz;
-            Cd[k] = code;
+            *at(X0, k) = x1;
+            *at(X1, k) = y1;
+            *at(U0, k) = ux;
+            *at(U1, k) = uy;
+            *at(U2, k) = uz;
+            *at(Cd, k) = code;
+            left |= code != kStay2;
         }
+        kin += 0.5 * (double)m * (double)kin32;
+        // the re-binning scans only patches that may have leavers
+        if (__ballot(left) && ln == 0) *glb(S.moved + p) = 1;
         if (err) __hip_atomic_fetch_or(&glb(S.st)->flags, err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
 

@@ -148,6 +148,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles3d(const SimDev<T> *__restri
         const double cz_ = -(double)q * (double)S.d[2] / (double)dt;
         const T Pmax0 = below((T)P0), Pmax1 = below((T)P1), Pmax2 = below((T)P2);
         uint32_t err = 0;
+        bool left = false;
 
         for (int u = wv; u < uend; u += NW) {
             const int kr = unit_particle(u), k = min(kr, cnt - 1);
@@ -315,7 +316,9 @@ __global__ __launch_bounds__(BLOCK) void k_particles3d(const SimDev<T> *__restri
             U1[k] = uy;
             U2[k] = uz;
             Cd[k] = code;
+            left |= code != kStay3;
         }
+        if (__ballot(left) && ln == 0) *glb(S.moved + p) = 1;
         if (err)
             __hip_atomic_fetch_or(&glb(S.st)->flags, err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();

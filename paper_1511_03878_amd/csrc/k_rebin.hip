@@ -41,7 +41,14 @@ __global__ __launch_bounds__(kRC) void k_rebin_count(const SimDev<T> *__restrict
         const int s = find_sim(patch_prefix, nsims, gp);
         const SimDev<T> &S = sims[s];
         if (!glb(S.st)->active) continue;
-        count_patch<T, ND, kRC / 64>(S, gp - patch_prefix[s], sm);
+        const int p = gp - patch_prefix[s];
+        if (!*glb(S.moved + p)) {
+            // no particle of the patch changed patch or was removed: no leavers
+            if (threadIdx.x < ND) glb(S.kcnt)[p * ND + threadIdx.x] = 0;
+            if (threadIdx.x == 0) glb(S.nleave)[p] = 0;
+            continue;
+        }
+        count_patch<T, ND, kRC / 64>(S, p, sm);
     }
 }
 
@@ -96,6 +103,14 @@ __global__ __launch_bounds__(kRB) void k_rebin_scatter(const SimDev<T> *__restri
         if (!glb(S.st)->active || (glb(S.st)->flags & kFlagPending)) continue;
         const int q = gp - patch_prefix[s];
         const int n = glb(S.count)[q], np = glb(S.newcount)[q], nH = glb(S.nhole)[q], A = glb(S.narrive)[q];
+        if (A == 0 && np == n && glb(S.nleave)[q] == 0) {
+            // nothing arrives and nothing leaves
+            if (tid == 0) {
+                if (q == 0) glb(S.st)->rebinned = 1u;
+                *glb(S.moved + q) = 0;
+            }
+            continue;
+        }
         const int64_t base = glb(S.off)[q];
         const gptr_t<const int32_t> row = nb_row<ND>(S.nbt, q);
         if (tid < NS) {
@@ -115,20 +130,19 @@ __global__ __launch_bounds__(kRB) void k_rebin_scatter(const SimDev<T> *__restri
                 s_run = 0;
                 if (q == 0) glb(S.st)->rebinned = 1u;
             }
+
         } else if (tid >= 64 && tid < 64 + ND) {
             s_key[tid - 64] = row[tid - 64];
         }
         __syncthreads();
-        // arrivals: holes first, then appended from slot n
-        int abase = 0;
-        for (int i = 0; i < s_ns; ++i) {
-            const int c = s_scnt[i];
-            for (int j = tid; j < c; j += kRB) {
-                const int a = abase + j;
-                const int target = a < nH ? glb(S.holes)[base + a] : n + (a - nH);
-                copy_particle(S, s_sbase[i] + j, base + target, true, false);
-            }
-            abase += c;
+        // arrivals (sources in ascending id, each in its slot order): holes
+        // first, then appended from slot n; one thread per arrival, so the
+        // copies of all sources are in flight together
+        for (int a = tid; a < A; a += kRB) {
+            int i = 0, a0 = 0;
+            while (i + 1 < s_ns && a >= a0 + s_scnt[i]) a0 += s_scnt[i++];
+            const int target = a < nH ? glb(S.holes)[base + a] : n + (a - nH);
+            copy_particle(S, s_sbase[i] + (a - a0), base + target, true, false);
         }
         // stayers in [n', n) fill the remaining holes
         if (np < n) {
@@ -158,6 +172,7 @@ __global__ __launch_bounds__(kRB) void k_rebin_scatter(const SimDev<T> *__restri
         }
         if (tid == 0) {
             glb(S.count)[q] = np;
+            *glb(S.moved + q) = 0;
             int staged = 0;
             for (int k = 0; k < ND; ++k) staged += glb(S.kcnt)[q * ND + k];
             const int removed = glb(S.nleave)[q] - staged;

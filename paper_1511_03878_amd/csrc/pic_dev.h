@@ -80,6 +80,7 @@ struct SimDev {
     int32_t *nleave;   // per patch: all leavers (incl. removed)
     int32_t *narrive;  // per patch: arrivals (set by the capacity check)
     int32_t *nhole;    // per patch: vacated slots below the new count
+    int32_t *moved;    // per patch: nonzero when a particle may have left since the last re-binning
     const T *laser_ey, *laser_ez;
     int64_t laser_steps;
     SimState *st;
@@ -140,6 +141,17 @@ __device__ __forceinline__ gptr_t<T> glb(T *p)
 }
 
 // Relaxed device-scope atomic add on global memory.
+// Element i of a global array through a 32-bit byte offset from a uniform
+// base: the load or store then takes the base from scalar registers and only
+// the offset from a vector register (no 64-bit address arithmetic per lane).
+// The caller keeps i * sizeof(T) below 2^32.
+template <typename T>
+__device__ __forceinline__ gptr_t<T> at(gptr_t<T> base, uint32_t i)
+{
+    typedef __attribute__((address_space(1))) char gchar;
+    return (gptr_t<T>)((gchar *)base + i * (uint32_t)sizeof(T));
+}
+
 template <typename T>
 __device__ __forceinline__ void gadd(gptr_t<T> p, T v)
 {

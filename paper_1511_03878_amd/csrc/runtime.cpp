@@ -146,6 +146,9 @@ SimImpl<T>::SimImpl(const PicSimDesc &d, const PicAllocator *a, hipStream_t s)
         nleave_d = (int32_t *)alloc.get(sizeof(int32_t) * npatch);
         narrive_d = (int32_t *)alloc.get(sizeof(int32_t) * npatch);
         nhole_d = (int32_t *)alloc.get(sizeof(int32_t) * npatch);
+        moved_d = (int32_t *)alloc.get(sizeof(int32_t) * npatch);
+        // every patch is scanned by the first re-binning
+        hipcheck(hipMemsetAsync(moved_d, 1, sizeof(int32_t) * npatch, stream), "memset moved");
         prefix_d = (int *)alloc.get(sizeof(int) * 2);
         tprefix_d = (int *)alloc.get(sizeof(int) * 2);
         view_d = (SimDev<T> *)alloc.get(sizeof(SimDev<T>));
@@ -289,6 +292,7 @@ void SimImpl<T>::release()
     alloc.put(nleave_d);
     alloc.put(narrive_d);
     alloc.put(nhole_d);
+    alloc.put(moved_d);
     alloc.put(prefix_d);
     alloc.put(tprefix_d);
     alloc.put(nbt_d);
@@ -402,6 +406,7 @@ void SimImpl<T>::refresh_view()
     V.w = pw; V.sw = sw; V.id = pid; V.sid = sid; V.code = code; V.holes = holes;
     V.cap = cap_d; V.off = off_d; V.count = counts_d; V.newcount = newcount_d;
     V.kcnt = kcnt_d; V.nleave = nleave_d; V.narrive = narrive_d; V.nhole = nhole_d;
+    V.moved = moved_d;
     V.laser_ey = laser_ey; V.laser_ez = laser_ez; V.laser_steps = laser_steps;
     V.st = st; V.hist = hist; V.upart = upart; V.kpart = kpart; V.nbt = nbt_d;
     hipcheck(hipMemcpyAsync(view_d, &v, sizeof(v), hipMemcpyHostToDevice, stream), "view upload");
@@ -938,6 +943,7 @@ void SimImpl<T>::rebin_codes(const uint8_t *codes_h, size_t cnt)
     hipcheck(hipMemcpyAsync(po, poff.data(), sizeof(int64_t) * (npatch + 1), hipMemcpyHostToDevice, stream), "codes off");
     launch_scatter_codes(pk, po, off_d, counts_d, code, npatch, stream);
     hipcheck(hipGetLastError(), "codes launch");
+    hipcheck(hipMemsetAsync(moved_d, 1, sizeof(int32_t) * npatch, stream), "moved");
     SimState s = read_state();
     s.active = 1;
     hipcheck(hipMemcpyAsync(&st->active, &s.active, sizeof(uint32_t), hipMemcpyHostToDevice, stream), "active");
