@@ -211,6 +211,7 @@ __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict
     __shared__ int s_pushed[kMaxBatch];
     __shared__ int s_pp[kMaxBatch + 1];  // patch prefix of the batch
     __shared__ int s_cnt[kCntCache];     // particle counts of the first kCntCache patches
+    __shared__ int s_off[kCntCache];     // and their first particle slots
     __shared__ int s_wsum[kQW];
     __shared__ double s_red[kQW][2];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -291,20 +292,27 @@ __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict
     const int total = s_pp[nsims];
     const int ncache = min(total, kCntCache);
     for (int g0 = 0; g0 < ncache; g0 += 8 * kQB) {
-        int v[8];
+        int v[8], o[8];
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             const int gp = g0 + r * kQB + tid;
             v[r] = 0;
+            o[r] = 0;
             if (gp < ncache) {
                 const int s = find_sim(s_pp, nsims, gp);
-                if (s_act[s]) v[r] = glb((const int32_t *)sims[s].count)[gp - s_pp[s]];
+                if (s_act[s]) {
+                    v[r] = glb((const int32_t *)sims[s].count)[gp - s_pp[s]];
+                    o[r] = (int)glb((const int64_t *)sims[s].off)[gp - s_pp[s]];
+                }
             }
         }
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             const int gp = g0 + r * kQB + tid;
-            if (gp < ncache) s_cnt[gp] = v[r];
+            if (gp < ncache) {
+                s_cnt[gp] = v[r];
+                s_off[gp] = o[r];
+            }
         }
     }
     __syncthreads();
@@ -393,7 +401,7 @@ __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict
         int fbase = 0;
         if (lane == 0 && fsum) fbase = atomicAdd(&s_hist[0], fsum);
         fbase = __shfl(fbase, 0, 64) + incl_f - nfull;
-        const int64_t o = n > 0 ? glb((const int64_t *)sims[s].off)[p] : 0;
+        const int64_t o = n == 0 ? 0 : gp < kCntCache ? s_off[gp] : glb((const int64_t *)sims[s].off)[p];
         for (int k = 0; k < nfull; ++k) put(fbase + k, s, p, o + (int64_t)k * chunk, chunk);
         if (rem) put(atomicAdd(&s_hist[bucket(rem)], 1), s, p, o + (int64_t)nfull * chunk, rem);
     }

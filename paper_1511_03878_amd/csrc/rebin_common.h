@@ -51,7 +51,7 @@ __device__ __forceinline__ void copy_particle(const SimDev<T> &S, int64_t from, 
 // the staged leavers are queued in a per-wave LDS ring, which is drained 64
 // entries at a time (one lane per particle, so the particle loads of 64
 // leavers are in flight together).
-constexpr int kRC = 256;  // threads of the count workgroup of the re-binning kernel
+constexpr int kRC = 512;  // threads of the count workgroup of the re-binning kernel (measured: 256 and 1024 slower)
 constexpr int kU = 32;    // 64-slot chunks per batch of code loads
 constexpr int kRing = 128;
 
@@ -84,18 +84,25 @@ __device__ __forceinline__ void count_patch(const SimDev<T> &S, int p, CountSmem
 {
     constexpr int kKeys = ND + 1;  // ND direction keys + removed
     constexpr int kThreads = NWV * 64;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // (NWV == 1 would give one wave per patch, synchronised by wave barriers
+    // only; a whole workgroup per patch measured faster)
+    const int tid = NWV == 1 ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = NWV == 1 ? 0 : (int)(threadIdx.x >> 6);
+    auto group_sync = [&]() {
+        if constexpr (NWV == 1) __builtin_amdgcn_wave_barrier();
+        else __syncthreads();
+    };
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int n = glb(S.count)[p];
     const int64_t base = glb(S.off)[p];
     const gptr_t<const uint8_t> code = glb((const uint8_t *)S.code) + base;
-    if (tid < 256) {
+    for (int e = tid; e < 256; e += kThreads) {
         int kb = 0;
-        if (tid < ND) kb = nb_row<ND>(S.nbt, p)[tid] + 1;
-        else if (tid == kRemoved) kb = ND + 1;
-        sm.kb[tid] = (uint8_t)kb;
+        if (e < ND) kb = nb_row<ND>(S.nbt, p)[e] + 1;
+        else if (e == kRemoved) kb = ND + 1;
+        sm.kb[e] = (uint8_t)kb;
     }
-    __syncthreads();
+    group_sync();
 
     const int per = ((n + kThreads - 1) / kThreads) * 64;
     const int lo = min(n, wave * per), hi = min(n, lo + per);
@@ -134,7 +141,7 @@ __device__ __forceinline__ void count_patch(const SimDev<T> &S, int p, CountSmem
         }
     }
     if (lane <= kKeys) sm.wc[wave][lane] = cnt;
-    __syncthreads();
+    group_sync();
 
     // ---- starting points: lane k of wave w holds the staging slot of the
     // next key-k leaver of the wave (key offset + earlier waves), lane kKeys
@@ -196,7 +203,7 @@ __device__ __forceinline__ void count_patch(const SimDev<T> &S, int p, CountSmem
             __builtin_amdgcn_wave_barrier();
         }
     }
-    __syncthreads();
+    group_sync();
 }
 
 }  // namespace pic
