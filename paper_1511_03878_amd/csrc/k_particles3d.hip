@@ -9,6 +9,8 @@
 // along the two other axes.  The LDS holds the field tile of (P+3)^3 nodes
 // and the current tile of (P+5)^3 nodes, so the patch edge is limited (8
 // cells per axis fits twice over in one CU's LDS for FP32).
+#include <type_traits>
+
 #include "kernels.h"
 #include "particle_common.h"
 
@@ -43,6 +45,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles3d(const SimDev<T> *__restri
                                                        const int *__restrict__ nitems,
                                                        int *__restrict__ head)
 {
+    using W = typename std::conditional<sizeof(T) == 4, float, double>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int s_item[2];
 
@@ -225,28 +228,31 @@ __global__ __launch_bounds__(BLOCK) void k_particles3d(const SimDev<T> *__restri
                     // axis carries weight only when its nearest node changed;
                     // its (exactly zero) entries skip their atomics.
                     int mx, my, mz;
-                    double S0x[4], DSx[4], S0y[4], DSy[4], S0z[4], DSz[4];
+                    // weights and products in W (FP32 for FP32 storage: fewer live
+                    // registers, so more waves fit); sums in the FP64 tile
+                    W S0x[4], DSx[4], S0y[4], DSy[4], S0z[4], DSz[4];
                     const bool cx = window4(xl, (double)dxl, mx, S0x, DSx);
                     const bool cy = window4(yl, (double)dyl, my, S0y, DSy);
                     const bool cz = window4(zl, (double)dzl, mz, S0z, DSz);
-                    const double qw = (double)wgt;
-                    double Ax[4], Bx_[4], Ay[4], By_[4];
+                    const W qw = (W)wgt;
+                    W Ax[4], Bx_[4], Ay[4], By_[4];
 #pragma unroll
                     for (int k2 = 0; k2 < 4; ++k2) {
-                        Ax[k2] = S0x[k2] + 0.5 * DSx[k2];
-                        Bx_[k2] = 0.5 * S0x[k2] + DSx[k2] * (1.0 / 3.0);
-                        Ay[k2] = S0y[k2] + 0.5 * DSy[k2];
-                        By_[k2] = 0.5 * S0y[k2] + DSy[k2] * (1.0 / 3.0);
+                        Ax[k2] = S0x[k2] + W(0.5) * DSx[k2];
+                        Bx_[k2] = W(0.5) * S0x[k2] + DSx[k2] * W(1.0 / 3.0);
+                        Ay[k2] = S0y[k2] + W(0.5) * DSy[k2];
+                        By_[k2] = W(0.5) * S0y[k2] + DSy[k2] * W(1.0 / 3.0);
                     }
-                    double px[3], py[3], pz[3];
-                    px[0] = cx_ * qw * DSx[0];
-                    py[0] = cy_ * qw * DSy[0];
-                    pz[0] = cz_ * qw * DSz[0];
+                    const W cq = (W)cx_ * qw, dq = (W)cy_ * qw, eq = (W)cz_ * qw;
+                    W px[3], py[3], pz[3];
+                    px[0] = cq * DSx[0];
+                    py[0] = dq * DSy[0];
+                    pz[0] = eq * DSz[0];
 #pragma unroll
                     for (int k2 = 1; k2 < 3; ++k2) {
-                        px[k2] = px[k2 - 1] + cx_ * qw * DSx[k2];
-                        py[k2] = py[k2 - 1] + cy_ * qw * DSy[k2];
-                        pz[k2] = pz[k2 - 1] + cz_ * qw * DSz[k2];
+                        px[k2] = px[k2 - 1] + cq * DSx[k2];
+                        py[k2] = py[k2 - 1] + dq * DSy[k2];
+                        pz[k2] = pz[k2 - 1] + eq * DSz[k2];
                     }
                     double *Jxt = Jt, *Jyt = Jt + jstride, *Jzt = Jt + 2 * jstride;
                     const int r0 = (mz + 2) * jwh + (my + 2) * jw + (mx + 2);
@@ -259,11 +265,11 @@ __global__ __launch_bounds__(BLOCK) void k_particles3d(const SimDev<T> *__restri
 #pragma unroll
                         for (int j = 0; j < 4; ++j) {
                             if (j >= mj) break;
-                            const double tr = Ay[j] * S0z[kk] + By_[j] * DSz[kk];
+                            const W tr = Ay[j] * S0z[kk] + By_[j] * DSz[kk];
 #pragma unroll
                             for (int i = 0; i < 3; ++i) {
                                 if (i >= ni) break;
-                                atomicAdd(&Jxt[r0 + kk * jwh + j * jw + i], px[i] * tr);
+                                atomicAdd(&Jxt[r0 + kk * jwh + j * jw + i], (double)(px[i] * tr));
                             }
                         }
                     }
@@ -274,11 +280,11 @@ __global__ __launch_bounds__(BLOCK) void k_particles3d(const SimDev<T> *__restri
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
                             if (i >= mi) break;
-                            const double tr = Ax[i] * S0z[kk] + Bx_[i] * DSz[kk];
+                            const W tr = Ax[i] * S0z[kk] + Bx_[i] * DSz[kk];
 #pragma unroll
                             for (int j = 0; j < 3; ++j) {
                                 if (j >= nj) break;
-                                atomicAdd(&Jyt[r0 + kk * jwh + j * jw + i], py[j] * tr);
+                                atomicAdd(&Jyt[r0 + kk * jwh + j * jw + i], (double)(py[j] * tr));
                             }
                         }
                     }
@@ -289,11 +295,11 @@ __global__ __launch_bounds__(BLOCK) void k_particles3d(const SimDev<T> *__restri
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
                             if (i >= mi) break;
-                            const double tr = Ax[i] * S0y[j] + Bx_[i] * DSy[j];
+                            const W tr = Ax[i] * S0y[j] + Bx_[i] * DSy[j];
 #pragma unroll
                             for (int kk = 0; kk < 3; ++kk) {
                                 if (kk >= nk) break;
-                                atomicAdd(&Jzt[r0 + kk * jwh + j * jw + i], pz[kk] * tr);
+                                atomicAdd(&Jzt[r0 + kk * jwh + j * jw + i], (double)(pz[kk] * tr));
                             }
                         }
                     }

@@ -24,11 +24,12 @@ __device__ __forceinline__ void qweights(A dl, A &wm, A &w0, A &wp)
 
 // Window of four nodes per axis that holds both the old and the new
 // quadratic supports of a move shorter than one cell.  On return S0/DS are
-// the old weights and the weight change at nodes m..m+3.  The new offset is
-// formed from the exact old offset and the displacement in FP64, so the
-// weight change keeps full relative accuracy even for FP32 storage.
-template <typename T>
-__device__ __forceinline__ bool window4(T xl, double disp, int &m, double S0[4], double DS[4])
+// the old weights and the weight change at nodes m..m+3, computed in FP64 and
+// rounded once to W.  The new offset is formed from the exact old offset and
+// the displacement in FP64, so the weight change keeps full relative accuracy
+// (to W's rounding) even for FP32 storage.
+template <typename T, typename W>
+__device__ __forceinline__ bool window4(T xl, double disp, int &m, W S0[4], W DS[4])
 {
     int i0 = (int)floor(xl + T(0.5));
     double d0 = (double)(xl - (T)i0);  // exact
@@ -46,8 +47,8 @@ __device__ __forceinline__ bool window4(T xl, double disp, int &m, double S0[4],
     double A1[4] = {s1 ? 0.0 : o1m, s1 ? o1m : o10, s1 ? o10 : o1p, s1 ? o1p : 0.0};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        S0[k] = A0[k];
-        DS[k] = A1[k] - A0[k];
+        S0[k] = (W)A0[k];
+        DS[k] = (W)(A1[k] - A0[k]);
     }
     // window slot 3 carries weight only when the nearest node changed
     return sg != 0;
