@@ -106,6 +106,8 @@ typedef struct {
                               0 = 2 */
     int32_t graph;         /* 1: step in batches of 32 replayed from a captured HIP graph
                               (when kernel timing is off); 0: plain launches */
+    int32_t patch_order;   /* order of equal-size work items: 0 = patch id; 1 = the Hilbert
+                              curve of pic_patch_order (power-of-two patch grids only) */
 } PicSimDesc;
 
 /* Diagnostics of a simulation (pic_diag_get synchronises the stream). */
@@ -267,6 +269,29 @@ int pic_batch_size(PicBatch *b, int32_t *n);
  * control against an HBM budget. */
 int pic_estimate_bytes(const PicSimDesc *d, int64_t nparticles, int64_t laser_steps,
                        int64_t *bytes);
+
+/* ---- patch order and segments (section 3.1, Fig. 2) ------------------------------ */
+
+/* Patch ids (x + np[0] (y + np[1] z), row-major) in the order of the Hilbert
+ * space-filling curve along which the paper arranges its patches (section
+ * 3.1; Fig. 2: on a 32 x 32 grid the curve visits every patch once, from
+ * patch (0, 0) to patch (31, 0)).  ndim 2 or 3; np[a] patches per axis, each a
+ * power of two; in 3-D two axes equal and the third at least as long.  Longer
+ * grids are cut into squares (cubes) of the shortest side along the longest
+ * axis, traversed in turn; consecutive patches of the order are always face
+ * neighbours.  `order` (caller-owned, n = product of np entries) receives the
+ * ids.  Host-only.  PIC_EINVAL for bad arguments or n not matching np,
+ * PIC_ENOTSUP for other grid shapes. */
+int pic_patch_order(int32_t ndim, const int32_t np[3], int32_t *order, int64_t n);
+
+/* Cut a sequence of n non-negative costs (patch loads in curve order) into k
+ * contiguous segments, one per process in the paper's decomposition: segment
+ * j is [bounds[j], bounds[j + 1]), where bounds[j] is the first position whose
+ * preceding costs sum to at least j / k of the total, so every segment costs at
+ * most total / k plus the largest single cost.  `bounds` (caller-owned) has
+ * k + 1 entries.  Host-only.  PIC_EINVAL for a null pointer, n < 0, k < 1 or a
+ * negative cost. */
+int pic_curve_segments(const int64_t *cost, int64_t n, int32_t k, int64_t *bounds);
 
 /* ---- errors ------------------------------------------------------------------ */
 

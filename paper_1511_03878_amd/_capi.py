@@ -26,7 +26,7 @@ EXPORTS = (
     "pic_timing_enable", "pic_timing_get", "pic_batch_create", "pic_batch_destroy",
     "pic_batch_add", "pic_batch_remove", "pic_batch_step", "pic_batch_finished",
     "pic_batch_size", "pic_estimate_bytes", "pic_autotune", "pic_state_save", "pic_state_load",
-    "pic_strerror",
+    "pic_patch_order", "pic_curve_segments", "pic_strerror",
     "pic_last_error",
 )
 
@@ -44,7 +44,7 @@ class SimDesc(C.Structure):
         ("periodic", C.c_int32 * 3), ("q", C.c_double), ("m", C.c_double),
         ("capacity_factor", C.c_double), ("min_capacity", C.c_int32), ("chunk", C.c_int32),
         ("block", C.c_int32), ("field_tile", C.c_int32), ("lane_stride", C.c_int32),
-        ("graph", C.c_int32),
+        ("graph", C.c_int32), ("patch_order", C.c_int32),
     ]
 
 
@@ -127,6 +127,8 @@ def load() -> C.CDLL:
         "pic_autotune": (C.c_int, [_vp, C.c_int32, C.c_char_p, C.POINTER(TuneResult)]),
         "pic_state_save": (C.c_int, [_vp, _vp, C.POINTER(C.c_size_t)]),
         "pic_state_load": (C.c_int, [_vp, _vp, C.c_size_t]),
+        "pic_patch_order": (C.c_int, [C.c_int32, _I32, _I32, C.c_int64]),
+        "pic_curve_segments": (C.c_int, [_I64, C.c_int64, C.c_int32, _I64]),
         "pic_strerror": (C.c_char_p, [C.c_int]),
         "pic_last_error": (C.c_char_p, []),
     }

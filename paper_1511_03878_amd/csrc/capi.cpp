@@ -310,6 +310,35 @@ int pic_timing_get(PicSim *s, PicTiming *out)
     });
 }
 
+int pic_patch_order(int32_t ndim, const int32_t np[3], int32_t *order, int64_t n)
+{
+    if (!np || !order || (ndim != 2 && ndim != 3)) return bad(PIC_EINVAL, "bad argument");
+    int64_t total = 1;
+    int p[3] = {1, 1, 1};
+    for (int a = 0; a < ndim; ++a) {
+        if (np[a] < 1 || np[a] > (1 << 20)) return bad(PIC_EINVAL, "patch counts must be in [1, 2^20]");
+        p[a] = np[a];
+        total *= np[a];
+    }
+    if (total != n) return bad(PIC_EINVAL, "n must equal the number of patches");
+    return guarded([&] {
+        std::vector<int32_t> out;
+        std::string why;
+        const int rc = hilbert_patch_order(ndim, p, out, why);
+        if (rc != PIC_OK) throw Error(rc, why);
+        std::memcpy(order, out.data(), sizeof(int32_t) * (size_t)n);
+    });
+}
+
+int pic_curve_segments(const int64_t *cost, int64_t n, int32_t k, int64_t *bounds)
+{
+    if ((!cost && n > 0) || !bounds || n < 0 || k < 1) return bad(PIC_EINVAL, "bad argument");
+    for (int64_t i = 0; i < n; ++i)
+        if (cost[i] < 0) return bad(PIC_EINVAL, "negative cost");
+    curve_segments(cost, n, k, bounds);
+    return PIC_OK;
+}
+
 int pic_estimate_bytes(const PicSimDesc *d, int64_t nparticles, int64_t laser_steps,
                        int64_t *bytes)
 {

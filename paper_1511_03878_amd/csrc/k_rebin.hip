@@ -210,7 +210,7 @@ __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict
     __shared__ uint8_t s_par[kMaxBatch];   // parity of the step the queue is for
     __shared__ int s_pushed[kMaxBatch];
     __shared__ int s_pp[kMaxBatch + 1];  // patch prefix of the batch
-    __shared__ int s_cnt[kCntCache];     // particle counts of the first kCntCache patches
+    __shared__ int s_cnt[kCntCache];     // particle counts at the first kCntCache queue positions
     __shared__ int s_off[kCntCache];     // and their first particle slots
     __shared__ int s_wsum[kQW];
     __shared__ double s_red[kQW][2];
@@ -288,6 +288,13 @@ __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict
     for (int i = tid; i <= nsims; i += kQB) s_pp[i] = qa.patch_prefix[i];
     __syncthreads();
 
+    // queue position gp of simulation s -> its patch (curve order when the
+    // simulation asks for it, else patch id order)
+    auto patch_at = [&](int gp, int s) {
+        const int lp = gp - s_pp[s];
+        const int32_t *po = sims[s].porder;
+        return po ? (int)glb(po)[lp] : lp;
+    };
     // ---- particle counts of the first kCntCache patches, loaded together ----------
     const int total = s_pp[nsims];
     const int ncache = min(total, kCntCache);
@@ -301,8 +308,9 @@ __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict
             if (gp < ncache) {
                 const int s = find_sim(s_pp, nsims, gp);
                 if (s_act[s]) {
-                    v[r] = glb((const int32_t *)sims[s].count)[gp - s_pp[s]];
-                    o[r] = (int)glb((const int64_t *)sims[s].off)[gp - s_pp[s]];
+                    const int p = patch_at(gp, s);
+                    v[r] = glb((const int32_t *)sims[s].count)[p];
+                    o[r] = (int)glb((const int64_t *)sims[s].off)[p];
                 }
             }
         }
@@ -318,7 +326,7 @@ __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict
     __syncthreads();
     auto count_of = [&](int gp, int s) {
         if (gp < kCntCache) return s_cnt[gp];
-        return s_act[s] ? glb((const int32_t *)sims[s].count)[gp - s_pp[s]] : 0;
+        return s_act[s] ? glb((const int32_t *)sims[s].count)[patch_at(gp, s)] : 0;
     };
 
     // ---- phase B: chunk histogram (bucket 0 = largest chunks) ------------------------
@@ -392,7 +400,7 @@ __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict
         int s = 0, p = 0, n = 0;
         if (gp < total) {
             s = find_sim(s_pp, nsims, gp);
-            p = gp - s_pp[s];
+            p = patch_at(gp, s);
             n = count_of(gp, s);
         }
         const int nfull = n / chunk, rem = n - nfull * chunk;

@@ -81,6 +81,7 @@ struct SimDev {
     int32_t *narrive;  // per patch: arrivals (set by the capacity check)
     int32_t *nhole;    // per patch: vacated slots below the new count
     int32_t *moved;    // per patch: nonzero when a particle may have left since the last re-binning
+    const int32_t *porder;  // queue order of the patches (position -> patch id), or null: id order
     const T *laser_ey, *laser_ez;
     int64_t laser_steps;
     SimState *st;

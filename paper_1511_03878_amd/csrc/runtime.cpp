@@ -107,6 +107,7 @@ int validate_desc(const PicSimDesc &d, std::string &why)
     if (d.lane_stride < 0 || d.lane_stride > 64) { why = "lane_stride must be 0..64"; return PIC_EINVAL; }
     if (d.block != 0 && d.block != 256 && d.block != 512 && d.block != 1024) { why = "block must be 0, 256, 512 or 1024"; return PIC_EINVAL; }
     if (d.graph != 0 && d.graph != 1) { why = "graph must be 0 or 1"; return PIC_EINVAL; }
+    if (d.patch_order != 0 && d.patch_order != 1) { why = "patch_order must be 0 or 1"; return PIC_EINVAL; }
     return PIC_OK;
 }
 
@@ -149,6 +150,16 @@ SimImpl<T>::SimImpl(const PicSimDesc &d, const PicAllocator *a, hipStream_t s)
         moved_d = (int32_t *)alloc.get(sizeof(int32_t) * npatch);
         // every patch is scanned by the first re-binning
         hipcheck(hipMemsetAsync(moved_d, 1, sizeof(int32_t) * npatch, stream), "memset moved");
+        if (desc.patch_order == 1) {
+            const int npc[3] = {np[0], np[1], nd == 3 ? np[2] : 1};
+            std::vector<int32_t> ord;
+            std::string why;
+            const int rc = hilbert_patch_order(nd, npc, ord, why);
+            if (rc != PIC_OK) throw Error(PIC_EINVAL, "patch_order 1: " + why);
+            porder_d = (int32_t *)alloc.get(sizeof(int32_t) * npatch);
+            hipcheck(hipMemcpyAsync(porder_d, ord.data(), sizeof(int32_t) * npatch, hipMemcpyHostToDevice, stream), "order");
+            hipcheck(hipStreamSynchronize(stream), "sync");
+        }
         prefix_d = (int *)alloc.get(sizeof(int) * 2);
         tprefix_d = (int *)alloc.get(sizeof(int) * 2);
         view_d = (SimDev<T> *)alloc.get(sizeof(SimDev<T>));
@@ -293,6 +304,7 @@ void SimImpl<T>::release()
     alloc.put(narrive_d);
     alloc.put(nhole_d);
     alloc.put(moved_d);
+    if (porder_d) alloc.put(porder_d);
     alloc.put(prefix_d);
     alloc.put(tprefix_d);
     alloc.put(nbt_d);
@@ -407,6 +419,7 @@ void SimImpl<T>::refresh_view()
     V.cap = cap_d; V.off = off_d; V.count = counts_d; V.newcount = newcount_d;
     V.kcnt = kcnt_d; V.nleave = nleave_d; V.narrive = narrive_d; V.nhole = nhole_d;
     V.moved = moved_d;
+    V.porder = porder_d;
     V.laser_ey = laser_ey; V.laser_ez = laser_ez; V.laser_steps = laser_steps;
     V.st = st; V.hist = hist; V.upart = upart; V.kpart = kpart; V.nbt = nbt_d;
     hipcheck(hipMemcpyAsync(view_d, &v, sizeof(v), hipMemcpyHostToDevice, stream), "view upload");

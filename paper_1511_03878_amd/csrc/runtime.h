@@ -23,6 +23,9 @@ void set_error(const std::string &m);
 extern thread_local std::string g_last_error;
 void hipcheck(hipError_t e, const char *what);
 int validate_desc(const PicSimDesc &d, std::string &why);
+// patch ids in Hilbert-curve order (order.cpp); PIC_ENOTSUP for unsupported grids
+int hilbert_patch_order(int nd, const int np[3], std::vector<int32_t> &out, std::string &why);
+void curve_segments(const int64_t *cost, int64_t n, int k, int64_t *bounds);
 
 struct Allocator {
     PicAllocator hook{nullptr, nullptr, nullptr};
@@ -97,7 +100,7 @@ struct SimImpl : SimBase {
     SimState *st = nullptr;
     double *hist = nullptr;
     int32_t *counts_d = nullptr, *newcount_d = nullptr, *kcnt_d = nullptr, *nleave_d = nullptr;
-    int32_t *narrive_d = nullptr, *nhole_d = nullptr, *moved_d = nullptr;
+    int32_t *narrive_d = nullptr, *nhole_d = nullptr, *moved_d = nullptr, *porder_d = nullptr;
     int *prefix_d = nullptr, *tprefix_d = nullptr;
     int32_t *nbt_d = nullptr;
     double *upart = nullptr, *kpart = nullptr;

@@ -81,7 +81,8 @@ def current_stream_handle() -> int:
 
 def make_desc(grid: dict, precision: int, chunk: int = 0, block: int = 0,
               capacity_factor: float = 0.0, min_capacity: int = 0,
-              field_tile: int = 0, lane_stride: int = 0, graph: int = 0) -> _capi.SimDesc:
+              field_tile: int = 0, lane_stride: int = 0, graph: int = 0,
+              patch_order: int = 0) -> _capi.SimDesc:
     nd = int(grid["ndim"])
     n = list(grid["n"]) + [1] * (3 - len(grid["n"]))
     d = list(grid["d"]) + [1.0] * (3 - len(grid["d"]))
@@ -92,7 +93,7 @@ def make_desc(grid: dict, precision: int, chunk: int = 0, block: int = 0,
                          (C.c_int32 * 3)(*[int(p) for p in per[:3]]),
                          float(grid.get("q", -1.0)), float(grid.get("m", 1.0)),
                          float(capacity_factor), int(min_capacity), int(chunk), int(block),
-                         int(field_tile), int(lane_stride), int(graph))
+                         int(field_tile), int(lane_stride), int(graph), int(patch_order))
 
 
 def estimate_bytes(grid: dict, precision: int, nparticles: int, laser_steps: int = 0,
@@ -103,6 +104,27 @@ def estimate_bytes(grid: dict, precision: int, nparticles: int, laser_steps: int
     check(_capi.load().pic_estimate_bytes(C.byref(desc), int(nparticles), int(laser_steps),
                                           C.byref(out)))
     return out.value
+
+
+def patch_order(np_) -> np.ndarray:
+    """Patch ids in Hilbert-curve order for a grid of np_ patches per axis
+    (pic_patch_order)."""
+    nd = len(np_)
+    p = (C.c_int32 * 3)(*(list(int(v) for v in np_) + [1] * (3 - nd)))
+    n = int(np.prod(np_))
+    out = np.empty(n, dtype=np.int32)
+    check(_capi.load().pic_patch_order(nd, p, out.ctypes.data_as(C.POINTER(C.c_int32)), n))
+    return out
+
+
+def curve_segments(costs, k: int) -> np.ndarray:
+    """Segment boundaries (k + 1 entries) of a cost sequence in curve order
+    (pic_curve_segments)."""
+    c = np.ascontiguousarray(costs, dtype=np.int64)
+    out = np.empty(int(k) + 1, dtype=np.int64)
+    check(_capi.load().pic_curve_segments(c.ctypes.data_as(C.POINTER(C.c_int64)), c.size, int(k),
+                                          out.ctypes.data_as(C.POINTER(C.c_int64))))
+    return out
 
 
 class Sim:
