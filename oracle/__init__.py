@@ -78,6 +78,7 @@ def _load():
         "orc_field_energy": (C.c_double, [vp]),
         "orc_rho": (None, [vp, _D]),
         "orc_maxwell": (None, [vp]),
+        "orc_set_maxwell_order": (C.c_int, [vp, C.c_int]),
         "orc_deposit": (None, [vp, _D, _D, C.c_double, C.c_double]),
         "orc_gather": (None, [vp, _D, _D]),
         "orc_boris": (None, [_D, _D, _D, C.c_double, C.c_double, C.c_double]),
@@ -242,6 +243,11 @@ class Sim:
         """Three-sweep Yee update with the current J and laser row."""
         _load().orc_maxwell(self._p)
 
+    def set_maxwell_order(self, order: int):
+        """Field solver of spatial order 2 (Yee, the default) or 6 (staggered
+        sixth-order differences; every axis periodic)."""
+        if _load().orc_set_maxwell_order(self._p, int(order)) != 0:
+            raise ValueError("oracle: unsupported field solver order for this grid")
     def deposit(self, xa, xb, w, vz):
         a = _f64(list(xa) + [0.0] * (3 - len(xa)))
         b = _f64(list(xb) + [0.0] * (3 - len(xb)))

@@ -67,6 +67,7 @@ typedef struct {
     int64_t step;
     double U_last, K_last;
     int64_t removed;
+    int morder;       /* spatial order of the field solver: 2 (Yee) or 6 */
 } orc_sim;
 
 /* Staggering of Ex Ey Ez Bx By Bz (J shares E's): 1 = half a cell up. */
@@ -288,6 +289,97 @@ void orc_deposit(orc_sim *s, const double xa[3], const double xb[3], double w, d
  *   By_ghost(L) = (-2 Ez^n - (1 - r) By_1) / (1 + r)
  * (transverse derivative terms are left out of the condition). */
 
+/* Sixth-order staggered first difference (the high-order field solver the
+ * paper mentions for one of its comparison codes, section 2; it gives no
+ * coefficients).  The derivative at the midpoint of nodes i and i + 1 is
+ * sum_m c_m (f(i + m) - f(i + 1 - m)) / h, m = 1..3; matching the Taylor
+ * series of f at the midpoint, c1 + 3 c2 + 5 c3 = 1 and c1 + 3^3 c2 + 5^3 c3 =
+ * c1 + 3^5 c2 + 5^5 c3 = 0, whose solution is below. */
+static const double C6[3] = {75.0 / 64.0, -25.0 / 384.0, 3.0 / 640.0};
+
+/* Difference of component c along axis a at the half point after node
+ * (i, j, k) (fwd = 1: between the node and the next one) or before it
+ * (fwd = 0: between the previous node and this one), not yet divided by the
+ * cell size.  Order 2: the two neighbours; order 6: the three pairs above. */
+static double dstag(const orc_sim *s, int c, int a, int64_t i, int64_t j, int64_t k, int fwd)
+{
+    int64_t p[3] = {i, j, k};
+    if (!fwd) p[a] -= 1;            /* midpoint between p and p + 1 along a */
+    if (s->morder == 2) {
+        int64_t q[3] = {p[0], p[1], p[2]};
+        q[a] += 1;
+        return fget(s, c, q[0], q[1], q[2]) - fget(s, c, p[0], p[1], p[2]);
+    }
+    double acc = 0.0;
+    for (int m = 1; m <= 3; ++m) {
+        int64_t hi[3] = {p[0], p[1], p[2]}, lo[3] = {p[0], p[1], p[2]};
+        hi[a] += m;
+        lo[a] += 1 - m;
+        acc += C6[m - 1] * (fget(s, c, hi[0], hi[1], hi[2]) - fget(s, c, lo[0], lo[1], lo[2]));
+    }
+    return acc;
+}
+
+/* Field solver of order 6 (periodic axes only; the Yee update below covers
+ * order 2 with its open faces): the same three sweeps with dstag. */
+static void b_half_hi(orc_sim *s)
+{
+    const double h = 0.5 * s->g.dt;
+    const double ix = 1.0 / s->g.d[0], iy = 1.0 / s->g.d[1];
+    const double iz = s->g.ndim == 3 ? 1.0 / s->g.d[2] : 0.0;
+    for (int64_t k = 0; k < s->fn[2]; ++k)
+        for (int64_t j = 0; j < s->fn[1]; ++j)
+            for (int64_t i = 0; i < s->fn[0]; ++i) {
+                const int64_t f = flat3(s, 3, i, j, k);
+                double bx = dstag(s, 2, 1, i, j, k, 1) * iy, by = -dstag(s, 2, 0, i, j, k, 1) * ix;
+                double bz = dstag(s, 1, 0, i, j, k, 1) * ix - dstag(s, 0, 1, i, j, k, 1) * iy;
+                if (s->g.ndim == 3) {
+                    bx -= dstag(s, 1, 2, i, j, k, 1) * iz;
+                    by += dstag(s, 0, 2, i, j, k, 1) * iz;
+                }
+                s->F[3][f] -= h * bx;
+                s->F[4][f] -= h * by;
+                s->F[5][f] -= h * bz;
+            }
+}
+
+static void maxwell_hi(orc_sim *s)
+{
+    const double dt = s->g.dt;
+    const double ix = 1.0 / s->g.d[0], iy = 1.0 / s->g.d[1];
+    const double iz = s->g.ndim == 3 ? 1.0 / s->g.d[2] : 0.0;
+    b_half_hi(s);
+    for (int64_t k = 0; k < s->fn[2]; ++k)
+        for (int64_t j = 0; j < s->fn[1]; ++j)
+            for (int64_t i = 0; i < s->fn[0]; ++i) {
+                const int64_t f = flat3(s, 0, i, j, k);
+                /* Ex += dt (dBz/dy - dBy/dz - Jx), Ey += dt (dBx/dz - dBz/dx - Jy),
+                   Ez += dt (dBy/dx - dBx/dy - Jz); backward differences */
+                double ex = dstag(s, 5, 1, i, j, k, 0) * iy, ey = -dstag(s, 5, 0, i, j, k, 0) * ix;
+                double ez = dstag(s, 4, 0, i, j, k, 0) * ix - dstag(s, 3, 1, i, j, k, 0) * iy;
+                if (s->g.ndim == 3) {
+                    ex -= dstag(s, 4, 2, i, j, k, 0) * iz;
+                    ey += dstag(s, 3, 2, i, j, k, 0) * iz;
+                }
+                s->F[0][f] += dt * (ex - s->F[6][f]);
+                s->F[1][f] += dt * (ey - s->F[7][f]);
+                s->F[2][f] += dt * (ez - s->F[8][f]);
+            }
+    b_half_hi(s);
+}
+
+/* Choose the field solver order: 2 (Yee, default) or 6 (all axes periodic).
+ * Returns 0, or -1 for an unsupported request. */
+int orc_set_maxwell_order(orc_sim *s, int order)
+{
+    if (order == 2) { s->morder = 2; return 0; }
+    if (order != 6) return -1;
+    for (int a = 0; a < s->g.ndim; ++a)
+        if (!s->g.periodic[a]) return -1;
+    s->morder = 6;
+    return 0;
+}
+
 static void b_half(orc_sim *s)
 {
     const double h = 0.5 * s->g.dt;
@@ -321,6 +413,10 @@ static double laser_row(const orc_sim *s, const double *tab, int64_t j, int64_t 
 
 void orc_maxwell(orc_sim *s)
 {
+    if (s->morder == 6) {
+        maxwell_hi(s);
+        return;
+    }
     const double dt = s->g.dt;
     const double ix = 1.0 / s->g.d[0], iy = 1.0 / s->g.d[1];
     const double iz = s->g.ndim == 3 ? 1.0 / s->g.d[2] : 0.0;
@@ -462,6 +558,7 @@ orc_sim *orc_create(const orc_desc *d)
     if (d->ndim != 2 && d->ndim != 3) return NULL;
     orc_sim *s = calloc(1, sizeof(orc_sim));
     s->g = *d;
+    s->morder = 2;
     if (s->g.ndim == 2) { s->g.n[2] = 1; s->g.patch[2] = 1; s->g.periodic[2] = 1; s->g.d[2] = 1.0; }
     for (int a = 0; a < 3; ++a) {
         if (s->g.n[a] <= 0 || s->g.patch[a] <= 0 || s->g.n[a] % s->g.patch[a]) { free(s); return NULL; }
