@@ -36,7 +36,7 @@ __global__ __launch_bounds__(256) void k_maxwell2d(const SimDev<T> *__restrict__
     for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
         const int s = find_sim(tile_prefix, nsims, tile);
         const SimDev<T> &S = sims[s];
-        if (!glb(S.st)->active) continue;
+        if (!glb(S.st)->active || S.morder == 6) continue;
         const int lt = tile - tile_prefix[s];
         const int n0 = S.n[0], n1 = S.n[1], fn0 = S.fn[0], fn1 = S.fn[1];
         const int per0 = S.periodic[0], per1 = S.periodic[1];
@@ -188,6 +188,104 @@ __global__ __launch_bounds__(256) void k_maxwell2d(const SimDev<T> *__restrict__
     }
 }
 
+// Sixth-order staggered field solver (2-D, periodic axes): the same three
+// sweeps as three passes over the tiles of the Yee decomposition (so the
+// per-tile energy partials line up), one node per thread iteration, the
+// neighbours read from global memory (L2 hits).  The derivative at a half
+// point comes from the three node pairs around it with the weights that cancel
+// the h^2 and h^4 terms of the Taylor series: 75/64, -25/384, 3/640.
+// PASS 0: B^{n+1/2} from E^n into the other buffer, energy of E^n, B^n;
+// PASS 1: E^{n+1} from B^{n+1/2} and J, clears the other J buffer;
+// PASS 2: B^{n+1} from E^{n+1}, in place (it reads E only).
+template <typename T, int PASS>
+__global__ __launch_bounds__(256) void k_maxwell2d_hi(const SimDev<T> *__restrict__ sims, int nsims,
+                                                      const int *__restrict__ tile_prefix, int total,
+                                                      int TX, int TY)
+{
+    __shared__ double s_red[4];
+    const int tid = threadIdx.x;
+    constexpr T c1 = T(75.0 / 64.0), c2 = T(-25.0 / 384.0), c3 = T(3.0 / 640.0);
+    for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+        const int s = find_sim(tile_prefix, nsims, tile);
+        const SimDev<T> &S = sims[s];
+        if (!glb(S.st)->active || S.morder != 6) continue;
+        const int lt = tile - tile_prefix[s];
+        const int n0 = S.n[0], n1 = S.n[1];
+        const int ntx = (n0 + TX - 1) / TX;
+        const int X0 = (lt % ntx) * TX, Y0 = (lt / ntx) * TY;
+        const int64_t stepn = glb(S.st)->step;
+        T *const *Fc = S.F[stepn & 1];
+        T *const *Fn = S.F[(stepn + 1) & 1];
+        const T dt = S.dt, h = T(0.5) * S.dt;
+        const T ix = T(1) / S.d[0], iy = T(1) / S.d[1];
+        double esum = 0.0;
+        for (int t = tid; t < TX * TY; t += 256) {
+            const int gi = X0 + t % TX, gj = Y0 + t / TX;
+            if (gi >= n0 || gj >= n1) continue;
+            const int64_t k = gi + (int64_t)n0 * gj;
+            // value of array f at node (gi + di, gj + dj), periodic (|d| <= 3 <= n)
+            auto node = [&](const T *f, int di, int dj) {
+                int a = gi + di, b = gj + dj;
+                a += a < 0 ? n0 : 0;
+                a -= a >= n0 ? n0 : 0;
+                b += b < 0 ? n1 : 0;
+                b -= b >= n1 ? n1 : 0;
+                return glb(f)[a + (int64_t)n0 * b];
+            };
+            // forward difference (half point after the node) and backward
+            // (half point before it) along x (ax = 0) or y (ax = 1)
+            auto dfw = [&](const T *f, int ax) {
+                const int u = ax == 0, v = ax == 1;
+                return c1 * (node(f, u, v) - node(f, 0, 0)) + c2 * (node(f, 2 * u, 2 * v) - node(f, -u, -v)) +
+                       c3 * (node(f, 3 * u, 3 * v) - node(f, -2 * u, -2 * v));
+            };
+            auto dbw = [&](const T *f, int ax) {
+                const int u = ax == 0, v = ax == 1;
+                return c1 * (node(f, 0, 0) - node(f, -u, -v)) + c2 * (node(f, u, v) - node(f, -2 * u, -2 * v)) +
+                       c3 * (node(f, 2 * u, 2 * v) - node(f, -3 * u, -3 * v));
+            };
+            if constexpr (PASS == 0 || PASS == 2) {
+                T *const *E = PASS == 0 ? Fc : Fn;
+                const T bx0 = glb(PASS == 0 ? Fc[3] : Fn[3])[k];
+                const T by0 = glb(PASS == 0 ? Fc[4] : Fn[4])[k];
+                const T bz0 = glb(PASS == 0 ? Fc[5] : Fn[5])[k];
+                const T bx = bx0 - h * dfw(E[2], 1) * iy;
+                const T by = by0 + h * dfw(E[2], 0) * ix;
+                const T bz = bz0 - h * (dfw(E[1], 0) * ix - dfw(E[0], 1) * iy);
+                if constexpr (PASS == 0) {
+                    const T ex = glb(Fc[0])[k], ey = glb(Fc[1])[k], ez = glb(Fc[2])[k];
+                    esum += (double)ex * ex + (double)ey * ey + (double)ez * ez + (double)bx0 * bx0 +
+                            (double)by0 * by0 + (double)bz0 * bz0;
+                }
+                glb(Fn[3])[k] = bx;
+                glb(Fn[4])[k] = by;
+                glb(Fn[5])[k] = bz;
+            } else {
+                T *const *Jc = S.J[stepn & 1];
+                T *const *Jn = S.J[(stepn + 1) & 1];
+                const T ex = glb(Fc[0])[k] + dt * (dbw(Fn[5], 1) * iy - glb(Jc[0])[k]);
+                const T ey = glb(Fc[1])[k] + dt * (-dbw(Fn[5], 0) * ix - glb(Jc[1])[k]);
+                const T ez = glb(Fc[2])[k] + dt * (dbw(Fn[4], 0) * ix - dbw(Fn[3], 1) * iy - glb(Jc[2])[k]);
+                glb(Fn[0])[k] = ex;
+                glb(Fn[1])[k] = ey;
+                glb(Fn[2])[k] = ez;
+                glb(Jn[0])[k] = T(0);
+                glb(Jn[1])[k] = T(0);
+                glb(Jn[2])[k] = T(0);
+            }
+        }
+        if constexpr (PASS == 0) {
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) esum += __shfl_xor(esum, o, 64);
+            if ((tid & 63) == 0) s_red[tid >> 6] = esum;
+            __syncthreads();
+            if (tid == 0)
+                glb(S.upart)[lt] = 0.5 * S.vcell * (s_red[0] + s_red[1] + s_red[2] + s_red[3]);
+            __syncthreads();
+        }
+    }
+}
+
 }  // namespace
 
 // Tile shapes (TX x TY nodes per workgroup) the tuner can choose from.
@@ -207,11 +305,12 @@ void maxwell_tile(int preset, int &tx, int &ty)
 
 template <typename T>
 void launch_maxwell(const SimDev<T> *sims, int nsims, const int *tile_prefix, int total_tiles,
-                    int grid, int preset, hipStream_t st, Ev2 ev)
+                    int grid, int preset, bool hi_order, hipStream_t st, Ev2 ev)
 {
+    hipEvent_t stop1 = hi_order ? nullptr : ev.stop;
 #define PIC_MW(TX, TY)                                                                          \
     hipExtLaunchKernelGGL((k_maxwell2d<T, TX, TY>), dim3(grid), dim3(256), 0, st, ev.start,    \
-                          ev.stop, 0, sims, nsims, tile_prefix, total_tiles)
+                          stop1, 0, sims, nsims, tile_prefix, total_tiles)
     const int p = (preset >= 0 && preset < 6) ? preset : 0;
     if constexpr (sizeof(T) == 4) {
         switch (p) {
@@ -233,13 +332,24 @@ void launch_maxwell(const SimDev<T> *sims, int nsims, const int *tile_prefix, in
         }
     }
 #undef PIC_MW
+    if (hi_order) {
+        // the sixth-order simulations of the batch (the Yee kernel skipped their tiles)
+        int tx, ty;
+        maxwell_tile<T>(preset, tx, ty);
+        hipLaunchKernelGGL((k_maxwell2d_hi<T, 0>), dim3(grid), dim3(256), 0, st, sims, nsims, tile_prefix,
+                           total_tiles, tx, ty);
+        hipLaunchKernelGGL((k_maxwell2d_hi<T, 1>), dim3(grid), dim3(256), 0, st, sims, nsims, tile_prefix,
+                           total_tiles, tx, ty);
+        hipExtLaunchKernelGGL((k_maxwell2d_hi<T, 2>), dim3(grid), dim3(256), 0, st, nullptr, ev.stop, 0,
+                              sims, nsims, tile_prefix, total_tiles, tx, ty);
+    }
 }
 
 template void maxwell_tile<float>(int, int &, int &);
 template void maxwell_tile<double>(int, int &, int &);
-template void launch_maxwell<float>(const SimDev<float> *, int, const int *, int, int, int,
+template void launch_maxwell<float>(const SimDev<float> *, int, const int *, int, int, int, bool,
                                     hipStream_t, Ev2);
-template void launch_maxwell<double>(const SimDev<double> *, int, const int *, int, int, int,
+template void launch_maxwell<double>(const SimDev<double> *, int, const int *, int, int, int, bool,
                                      hipStream_t, Ev2);
 
 }  // namespace pic

@@ -55,6 +55,7 @@ struct SimDev {
     int npatch;
     int ndim;
     int lane_stride;   // particles between consecutive lanes of a wave
+    int morder;        // field solver order: 2 (Yee) or 6
     T d[3];
     T dt;
     T q, m;

@@ -108,6 +108,18 @@ int validate_desc(const PicSimDesc &d, std::string &why)
     if (d.block != 0 && d.block != 256 && d.block != 512 && d.block != 1024) { why = "block must be 0, 256, 512 or 1024"; return PIC_EINVAL; }
     if (d.graph != 0 && d.graph != 1) { why = "graph must be 0 or 1"; return PIC_EINVAL; }
     if (d.patch_order != 0 && d.patch_order != 1) { why = "patch_order must be 0 or 1"; return PIC_EINVAL; }
+    if (d.maxwell_order != 0 && d.maxwell_order != 2 && d.maxwell_order != 6) {
+        why = "maxwell_order must be 0, 2 or 6";
+        return PIC_EINVAL;
+    }
+    if (d.maxwell_order == 6) {
+        if (d.ndim != 2) { why = "the sixth-order field solver is built for 2-D boxes only"; return PIC_ENOTSUP; }
+        for (int a = 0; a < d.ndim; ++a)
+            if (!d.periodic[a]) { why = "the sixth-order field solver needs every axis periodic"; return PIC_EINVAL; }
+        // its largest modified wave number per axis is (2 / d) (75/64 + 25/384 + 3/640)
+        const double S6 = 75.0 / 64.0 + 25.0 / 384.0 + 3.0 / 640.0;
+        if (d.dt >= 1.0 / (S6 * std::sqrt(inv2))) { why = "dt above the sixth-order solver's stability limit"; return PIC_EINVAL; }
+    }
     return PIC_OK;
 }
 
@@ -404,6 +416,7 @@ void SimImpl<T>::refresh_view()
     V.npatch = npatch;
     V.ndim = nd;
     V.lane_stride = lane_stride;
+    V.morder = desc.maxwell_order == 6 ? 6 : 2;
     V.dt = (T)desc.dt;
     V.q = (T)desc.q;
     V.m = (T)desc.m;
@@ -1145,6 +1158,8 @@ void BatchImpl<T>::build_tables()
     std::vector<int> pp(ns + 1, 0), tp(ns + 1, 0);
     tile_preset = 0;
     for (auto *m : members) if (m->desc.field_tile) tile_preset = m->desc.field_tile;
+    hi_order = false;
+    for (auto *m : members) hi_order = hi_order || m->desc.maxwell_order == 6;
     int tx, ty;
     maxwell_tile<T>(tile_preset, tx, ty);
     maxP0 = maxP1 = maxP2 = 1;
@@ -1280,8 +1295,8 @@ void BatchImpl<T>::launch_one_step()
     } else {
         launch_particles<T>(sims_d, items_d, nitems_d, head_d, grid_particles, block, maxP0, maxP1,
                             patch_const, stream, tm.pair(1));
-        launch_maxwell<T>(sims_d, ns, tile_prefix_d, total_tiles, grid_maxwell, tile_preset, stream,
-                          tm.pair(2));
+        launch_maxwell<T>(sims_d, ns, tile_prefix_d, total_tiles, grid_maxwell, tile_preset, hi_order,
+                          stream, tm.pair(2));
     }
     launch_rebin<T>(sims_d, ns, patch_prefix_d, total_patches, grid_rebin, nd, stream, tm.pair(3));
     launch_close_queue_pass();

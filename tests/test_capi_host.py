@@ -52,6 +52,7 @@ def _desc(**kw):
     s.capacity_factor, s.min_capacity, s.chunk, s.block, s.field_tile, s.lane_stride = (
         d["capacity_factor"], d["min_capacity"], d["chunk"], d["block"], d["field_tile"],
         d["lane_stride"])
+    s.maxwell_order = d.get("maxwell_order", 0)
     return s
 
 
@@ -68,6 +69,11 @@ def _desc(**kw):
     (dict(field_tile=9), -1),
     (dict(lane_stride=65), -1),
     (dict(n=(2, 64, 1), patch=(2, 16, 1)), -1),  # fewer than 4 cells
+    (dict(maxwell_order=4), -1),
+    (dict(maxwell_order=6, periodic=(0, 1, 1)), -1),  # sixth order needs periodic axes
+    (dict(maxwell_order=6, dt=0.06), -1),    # within the Yee limit, above the sixth-order one
+    (dict(maxwell_order=6, ndim=3, n=(16, 16, 16), patch=(8, 8, 8), d=(0.1, 0.1, 0.1),
+          dt=0.04), -9),                     # built for 2-D only
 ])
 def test_bad_descriptors_fail_before_device_work(lib, bad, code):
     h = C.c_void_p()

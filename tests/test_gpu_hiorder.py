@@ -1,0 +1,153 @@
+"""Parity of the sixth-order field solver of the HIP path with the FP64 oracle.
+
+The solver replaces the Yee differences by sixth-order staggered ones on the
+same grid (periodic axes, 2-D).  Bars as for the Yee path: FP64 fields within
+1e-11 relative L2 after 10 steps of the full PIC step, FP32 within 1e-5 after
+one step, occupancy and particle ids bit-exact; vacuum fields within 1e-12
+after 20 steps, also with Yee and sixth-order simulations in one batch.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1511_03878_amd import workloads as W
+from tests.helpers import compare_fields, gpu_sim
+
+pytestmark = pytest.mark.gpu
+
+# the sixth-order stability limit is 1 / (sum_m |c_m|) of the Yee one
+S6 = 75 / 64 + 25 / 384 + 3 / 640
+
+
+def _announce(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+def _oracle6(wl, nsteps):
+    s = oracle.Sim(wl["grid"])
+    s.set_maxwell_order(6)
+    s.set_particles(wl["x"], wl["u"], wl["w"])
+    s.step(nsteps)
+    return s
+
+
+def _vacuum(n, d, seed, order, precision=64):
+    from paper_1511_03878_amd.sim import Sim
+    grid = dict(ndim=2, n=list(n), d=list(d), dt=W.cfl_dt(d, 0.9 / S6), patch=[16, 16],
+                periodic=[1, 1], q=-1.0, m=1.0)
+    g = Sim(grid, precision, maxwell_order=order)
+    g.set_particles([np.zeros(0), np.zeros(0)], [np.zeros(0)] * 3, np.zeros(0))
+    o = oracle.Sim(grid)
+    if order == 6:
+        o.set_maxwell_order(6)
+    rng = np.random.default_rng(seed)
+    for c in ("Ex", "Ey", "Ez", "Bx", "By", "Bz"):
+        f = rng.standard_normal((n[1], n[0]))
+        g.set_field(c, f)
+        o.set_field(c, f)
+    return g, o
+
+
+def test_sixth_order_vacuum_fields_fp64():
+    _announce("sixth-order vacuum fields 96x64 fp64, 20 steps")
+    g, o = _vacuum((96, 64), (0.1, 0.13), 21, 6)
+    g.step(20)
+    o.step(20)
+    e, b = compare_fields(g, o)
+    assert e < 1e-12 and b < 1e-12, (e, b)
+
+
+def test_sixth_order_ragged_tiles_fp64():
+    # 80 x 48 cells: neither axis a multiple of the 64 x 8 / 64 x 16 Yee tiles
+    _announce("sixth-order vacuum fields 80x48 fp64, 7 steps")
+    from paper_1511_03878_amd.sim import Sim
+    g, o = _vacuum((80, 48), (0.1, 0.1), 5, 6)
+    g.step(7)
+    o.step(7)
+    e, b = compare_fields(g, o)
+    assert e < 1e-12 and b < 1e-12, (e, b)
+
+
+def test_sixth_order_pic_fp64_ten_steps():
+    _announce("uniform 64x64 16ppc fp64 sixth order, 10 steps")
+    wl = W.uniform_2d(n=(64, 64), cfl=0.95 / S6)
+    g = gpu_sim(wl, 64, maxwell_order=6)
+    g.step(10)
+    o = _oracle6(wl, 10)
+    e, b = compare_fields(g, o)
+    assert e < 1e-11 and b < 1e-11, (e, b)
+    assert np.array_equal(g.counts(), o.counts())
+    gx, gu, gw, gid = g.particles()
+    ox, ou, ow, oid = o.particles()
+    assert np.array_equal(gid, oid)
+    for a in range(2):
+        assert np.abs(gx[a] - ox[a]).max() < 1e-11
+    U, K, pushed = g.history(9, 1)
+    Uo, Ko = o.energy()
+    assert abs(U[0] - Uo) <= 1e-10 * abs(Uo) and abs(K[0] - Ko) <= 1e-12 * abs(Ko)
+    # the sixth-order run differs from a Yee run of the same input
+    y = gpu_sim(wl, 64)
+    y.step(10)
+    assert np.abs(y.field("Ez") - g.field("Ez")).max() > 1e-6
+
+
+def test_sixth_order_pic_fp32_one_step():
+    _announce("uniform 64x64 16ppc fp32 sixth order, 1 step")
+    wl = W.to_float32_state(W.uniform_2d(n=(64, 64), cfl=0.95 / S6))
+    g = gpu_sim(wl, 32, maxwell_order=6)
+    g.step(1)
+    o = _oracle6(wl, 1)
+    e, b = compare_fields(g, o)
+    assert e < 1e-5 and b < 1e-5, (e, b)
+    assert np.array_equal(g.counts(), o.counts())
+
+
+def test_mixed_orders_in_one_batch():
+    """A Yee and a sixth-order simulation stepped in one batch each match their oracle."""
+    _announce("batch of a Yee and a sixth-order vacuum box, fp64, 9 steps")
+    from paper_1511_03878_amd.sim import Batch
+    g2, o2 = _vacuum((64, 48), (0.1, 0.1), 3, 2)
+    g6, o6 = _vacuum((96, 64), (0.1, 0.12), 4, 6)
+    b = Batch(64)
+    b.add(g2, 9)
+    b.add(g6, 9)
+    while len(b.finished()) < 2:
+        b.step(16)
+    o2.step(9)
+    o6.step(9)
+    for g, o in ((g2, o2), (g6, o6)):
+        e, bb = compare_fields(g, o)
+        assert e < 1e-12 and bb < 1e-12, (e, bb)
+    b.close()
+
+
+def test_sixth_order_dispersion_beats_yee():
+    """A plane wave of 8 cells per wavelength along the grid diagonal keeps its
+    phase far better under the sixth-order solver (measured on the GPU state
+    against the exact solution of the continuous equations)."""
+    _announce("plane wave 128x128 fp64, Yee vs sixth order, 400 steps")
+    from paper_1511_03878_amd.sim import Sim
+    n, d = 128, 0.1
+    dt = W.cfl_dt((d, d), 0.1 / S6)  # small enough that the time error stays below both
+    kx = ky = 2 * math.pi * 16 / (n * d)
+    k = math.hypot(kx, ky)
+    i = np.arange(n)[None, :]
+    j = np.arange(n)[:, None]
+    err = {}
+    for order in (2, 6):
+        grid = dict(ndim=2, n=[n, n], d=[d, d], dt=dt, patch=[16, 16], periodic=[1, 1], q=-1.0, m=1.0)
+        g = Sim(grid, 64, maxwell_order=order)
+        g.set_particles([np.zeros(0), np.zeros(0)], [np.zeros(0)] * 3, np.zeros(0))
+        # a wave along (1, 1): E = z^ cos(k.r - w t), B = k^ x E, B taken at t = dt / 2
+        ph = lambda x, y, t: np.cos(kx * x + ky * y - k * t)
+        g.set_field("Ez", ph(i * d, j * d, 0.0))
+        g.set_field("Bx", (ky / k) * ph(i * d, (j + 0.5) * d, 0.5 * dt))
+        g.set_field("By", -(kx / k) * ph((i + 0.5) * d, j * d, 0.5 * dt))
+        nst = 400
+        g.step(nst)
+        err[order] = np.abs(g.field("Ez") - ph(i * d, j * d, nst * dt)).max()
+    assert err[6] < 0.05 * err[2], err
