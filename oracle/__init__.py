@@ -79,6 +79,9 @@ def _load():
         "orc_rho": (None, [vp, _D]),
         "orc_maxwell": (None, [vp]),
         "orc_set_maxwell_order": (C.c_int, [vp, C.c_int]),
+        "orc_set_window": (C.c_int, [vp, C.c_int64, C.c_double, C.c_int, C.c_int, _D, C.c_int64]),
+        "orc_window_shift": (C.c_int64, [vp]),
+        "orc_next_id": (C.c_int64, [vp]),
         "orc_deposit": (None, [vp, _D, _D, C.c_double, C.c_double]),
         "orc_gather": (None, [vp, _D, _D]),
         "orc_boris": (None, [_D, _D, _D, C.c_double, C.c_double, C.c_double]),
@@ -248,6 +251,25 @@ class Sim:
         sixth-order differences; every axis periodic)."""
         if _load().orc_set_maxwell_order(self._p, int(order)) != 0:
             raise ValueError("oracle: unsupported field solver order for this grid")
+
+    def set_window(self, start: int, velocity: float, ppc, density):
+        """Moving window along x (2-D, open x faces): it jumps one patch column
+        whenever v c (n - start) dt reaches the next multiple of the patch width;
+        the new column is filled with ppc = (ppc_x, ppc_y) cold particles per cell
+        of the given per-column density (the last entry continues)."""
+        dens = _f64(density)
+        if _load().orc_set_window(self._p, int(start), float(velocity), int(ppc[0]), int(ppc[1]),
+                                  _dp(dens), dens.size) != 0:
+            raise ValueError("oracle: unsupported moving window for this grid")
+        self._win_dens = dens
+
+    @property
+    def window_shift(self) -> int:
+        return int(_load().orc_window_shift(self._p))
+
+    @property
+    def next_id(self) -> int:
+        return int(_load().orc_next_id(self._p))
     def deposit(self, xa, xb, w, vz):
         a = _f64(list(xa) + [0.0] * (3 - len(xa)))
         b = _f64(list(xb) + [0.0] * (3 - len(xb)))

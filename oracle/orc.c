@@ -68,6 +68,15 @@ typedef struct {
     double U_last, K_last;
     int64_t removed;
     int morder;       /* spatial order of the field solver: 2 (Yee) or 6 */
+    /* moving window along x (see orc_set_window) */
+    int win;          /* 1: the window moves */
+    int64_t win_start;/* completed steps before the window starts to move */
+    double win_v;     /* window speed in units of c */
+    int win_ppc[2];   /* injected particles per cell along x and y */
+    double *win_dens; /* plasma density of global cell column c (the last entry beyond) */
+    int64_t win_ncols;
+    int64_t win_shift;/* shifts done so far (the window has moved win_shift * patch[0] cells) */
+    int64_t next_id;  /* id of the next injected particle */
 } orc_sim;
 
 /* Staggering of Ex Ey Ez Bx By Bz (J shares E's): 1 = half a cell up. */
@@ -588,6 +597,7 @@ void orc_destroy(orc_sim *s)
     free_particles(s);
     free(s->count);
     free(s->laser_ey); free(s->laser_ez);
+    free(s->win_dens);
     free(s);
 }
 
@@ -651,6 +661,7 @@ int orc_set_particles(orc_sim *s, int64_t n, const double *const xs[3],
     }
     free(pos);
     free(pid);
+    s->next_id = n;
     return 0;
 }
 
@@ -743,6 +754,136 @@ void orc_rho(const orc_sim *s, double *out)
     }
 }
 
+/* ---- moving window -----------------------------------------------------
+ *
+ * The LWFA runs of the paper follow the pulse over more than a millimetre of
+ * plasma (sections 2.1 and 2.3), which a box of fixed size covers only if it
+ * moves with the pulse.  The patch structure makes the move a relabelling: the window
+ * jumps by one patch column (patch[0] cells) whenever the distance it should
+ * have travelled, v c (n - start) dt after n completed steps, reaches the next
+ * multiple of the patch width.  At a jump the fields and currents move left by
+ * patch[0] cells with zeros entering at the right, the particles of the first
+ * patch column leave the box (counted as removed), every other patch becomes
+ * its left neighbour with its particles in the same slots (positions lose
+ * patch[0] cells), and the new last column is filled with a cold plasma:
+ * ppc_x x ppc_y particles per cell on a regular lattice at offsets
+ * ((a + 1/2) / ppc_x, (b + 1/2) / ppc_y), weight density / (ppc_x ppc_y),
+ * zero momentum, in the order (patch row, cell row, cell column, b, a), ids
+ * continuing from the largest one handed out. */
+
+/* Shifts due after `done` completed steps. */
+static int64_t win_due(const orc_sim *s, int64_t done)
+{
+    const int64_t N = done - s->win_start;
+    if (N <= 0) return 0;
+    return (int64_t)floor(s->win_v * (double)N * s->g.dt / ((double)s->g.patch[0] * s->g.d[0]));
+}
+
+static double win_density(const orc_sim *s, int64_t col)
+{
+    return s->win_dens[col < s->win_ncols ? col : s->win_ncols - 1];
+}
+
+static void window_shift(orc_sim *s)
+{
+    const int S = s->g.patch[0], P1 = s->g.patch[1];
+    const int npx = s->np[0], npy = s->np[1];
+    const int64_t fn0 = s->fn[0], fn1 = s->fn[1];
+    /* fields and currents */
+    for (int c = 0; c < ORC_NCOMP; ++c)
+        for (int64_t j = 0; j < fn1; ++j) {
+            double *row = s->F[c] + j * fn0;
+            for (int64_t i = 0; i < fn0; ++i) row[i] = i + S < fn0 ? row[i + S] : 0.0;
+        }
+    /* injected particles per new patch (density depends on the column only) */
+    const int ppc = s->win_ppc[0] * s->win_ppc[1];
+    const int64_t col0 = (s->win_shift + 1) * S + (int64_t)(npx - 1) * S;  /* global column of the new column's first cell */
+    int64_t per_patch = 0;
+    for (int il = 0; il < S; ++il)
+        if (win_density(s, col0 + il) > 0.0) per_patch += (int64_t)P1 * ppc;
+    /* particles: old patch starts */
+    int64_t *start = malloc(sizeof(int64_t) * (s->npatch + 1));
+    start[0] = 0;
+    for (int p = 0; p < s->npatch; ++p) start[p + 1] = start[p] + s->count[p];
+    int64_t gone = 0;
+    for (int py = 0; py < npy; ++py) gone += s->count[npx * py];
+    const int64_t nnew = s->npart - gone + per_patch * npy;
+    double *nx[3], *nu[3], *nw = malloc(sizeof(double) * (nnew + 1));
+    int64_t *nid = malloc(sizeof(int64_t) * (nnew + 1));
+    for (int a = 0; a < 3; ++a) {
+        nx[a] = malloc(sizeof(double) * (nnew + 1));
+        nu[a] = malloc(sizeof(double) * (nnew + 1));
+    }
+    int32_t *ncount = malloc(sizeof(int32_t) * s->npatch);
+    int64_t t = 0;
+    for (int py = 0; py < npy; ++py)
+        for (int px = 0; px < npx; ++px) {
+            const int p = px + npx * py;
+            if (px + 1 < npx) {
+                const int q = p + 1;  /* the patch that becomes p */
+                for (int64_t k = start[q]; k < start[q + 1]; ++k, ++t) {
+                    for (int a = 0; a < 3; ++a) { nx[a][t] = s->x[a][k]; nu[a][t] = s->u[a][k]; }
+                    nx[0][t] -= (double)S;
+                    nw[t] = s->w[k];
+                    nid[t] = s->id[k];
+                }
+                ncount[p] = s->count[q];
+            } else {
+                const double X0 = (double)(px * S), Y0 = (double)(py * P1);
+                for (int jl = 0; jl < P1; ++jl)
+                    for (int il = 0; il < S; ++il) {
+                        const double dens = win_density(s, col0 + il);
+                        if (!(dens > 0.0)) continue;
+                        for (int b = 0; b < s->win_ppc[1]; ++b)
+                            for (int a = 0; a < s->win_ppc[0]; ++a, ++t) {
+                                nx[0][t] = X0 + il + (a + 0.5) / s->win_ppc[0];
+                                nx[1][t] = Y0 + jl + (b + 0.5) / s->win_ppc[1];
+                                nx[2][t] = 0.0;
+                                nu[0][t] = nu[1][t] = nu[2][t] = 0.0;
+                                nw[t] = dens / ppc;
+                                nid[t] = s->next_id++;
+                            }
+                    }
+                ncount[p] = (int32_t)per_patch;
+            }
+        }
+    s->removed += gone;
+    free_particles(s);
+    for (int a = 0; a < 3; ++a) { s->x[a] = nx[a]; s->u[a] = nu[a]; }
+    s->w = nw;
+    s->id = nid;
+    s->npart = nnew;
+    memcpy(s->count, ncount, sizeof(int32_t) * s->npatch);
+    free(ncount);
+    free(start);
+    s->win_shift += 1;
+}
+
+/* Start a moving window: 2-D boxes with open x faces; 0 < v <= 1; density
+ * per global cell column (ncols >= 1 entries, non-negative).  Returns 0, or -1
+ * for an unsupported request. */
+int orc_set_window(orc_sim *s, int64_t start, double v, int ppc_x, int ppc_y,
+                   const double *dens, int64_t ncols)
+{
+    if (s->g.ndim != 2 || s->g.periodic[0]) return -1;
+    if (!(v > 0.0 && v <= 1.0) || start < 0 || ppc_x < 1 || ppc_y < 1 || ncols < 1 || !dens) return -1;
+    for (int64_t c = 0; c < ncols; ++c)
+        if (!(dens[c] >= 0.0) || !isfinite(dens[c])) return -1;
+    free(s->win_dens);
+    s->win_dens = malloc(sizeof(double) * ncols);
+    memcpy(s->win_dens, dens, sizeof(double) * ncols);
+    s->win_ncols = ncols;
+    s->win = 1;
+    s->win_start = start;
+    s->win_v = v;
+    s->win_ppc[0] = ppc_x;
+    s->win_ppc[1] = ppc_y;
+    return 0;
+}
+
+int64_t orc_window_shift(const orc_sim *s) { return s->win_shift; }
+int64_t orc_next_id(const orc_sim *s) { return s->next_id; }
+
 /* One full step n -> n+1 (state x^n, u^{n-1/2}, E^n, B^n on entry). */
 static void one_step(orc_sim *s)
 {
@@ -812,6 +953,7 @@ static void one_step(orc_sim *s)
     free(newcount);
     free(src);
     free(dest);
+    if (s->win && win_due(s, s->step + 1) > s->win_shift) window_shift(s);
     s->step += 1;
 }
 
