@@ -125,6 +125,7 @@ typedef struct {
     double occupancy_mean;
     int32_t flags;         /* sticky device error bits (see pic_sync) */
     int32_t relayouts;     /* capacity re-layouts performed so far */
+    int64_t window_cells;  /* cells the moving window has travelled (0 without one) */
 } PicDiag;
 
 /* Per-kernel timing accumulated while timing is enabled (HIP events on the
@@ -160,6 +161,30 @@ int pic_particles_set(PicSim *s, int64_t n, const double *x, const double *y, co
  * (t + 1/2) dt, n[1] values per row.  ey or ez may be NULL (zero).  Steps
  * beyond the table see no incident field. */
 int pic_laser_set(PicSim *s, int64_t nsteps, const double *ey, const double *ez);
+
+/* Moving window along x (2-D boxes with open x faces).  The LWFA runs follow
+ * the pulse over more than a millimetre of plasma (Sec. 2.1, 2.3); the box
+ * follows it by jumps of one patch column (patch[0] cells, Sec. 3.1): after
+ * step n completes, a jump is made when floor(velocity * (n + 1 - start_step)
+ * * dt / (patch[0] * d[0])), evaluated in FP64, exceeds the jumps made so far.
+ * A jump moves E, B and the last deposit left by patch[0] nodes (zeros enter
+ * at the right), removes the particles of the first patch column (counted in
+ * PicDiag.removed), gives every other patch the particles of its right
+ * neighbour in the same slots, and fills the new last column with a cold
+ * plasma: ppc_x * ppc_y particles per cell at offsets ((a + 1/2) / ppc_x,
+ * (b + 1/2) / ppc_y), weight density / (ppc_x * ppc_y), zero momentum, ids
+ * continuing from the largest handed out, in (patch row, cell row, cell
+ * column, b, a) order.  density[c] (host, FP64, ncols >= 1 values, copied) is
+ * the plasma density of global cell column c, counted from the box's initial
+ * x = 0; columns beyond the table take density[ncols - 1].  velocity in (0, 1]
+ * (units of c), start_step >= 0, ppc_x * ppc_y <= 4096, at most 4096 patch
+ * columns.  Patch capacities are raised to hold one column's injection
+ * (grows device memory).  The window's configuration is not part of a
+ * checkpoint (its progress is); set it again after pic_state_load.  Errors:
+ * PIC_ENOTSUP in 3-D or beyond 4096 patch columns, PIC_EINVAL for a periodic
+ * x axis or bad arguments, PIC_ESTATE while the simulation is in a batch. */
+int pic_window_set(PicSim *s, int64_t start_step, double velocity, int32_t ppc_x, int32_t ppc_y,
+                   const double *density, int64_t ncols);
 
 /* Overwrite one field component (E or B) from a host FP64 array of
  * count = fn[0]*fn[1]*fn[2] values. */

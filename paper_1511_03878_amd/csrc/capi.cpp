@@ -124,6 +124,13 @@ int pic_particles_set(PicSim *s, int64_t n, const double *x, const double *y, co
     });
 }
 
+int pic_window_set(PicSim *s, int64_t start_step, double velocity, int32_t ppc_x, int32_t ppc_y,
+                   const double *density, int64_t ncols)
+{
+    if (!s || !density) return bad(PIC_EINVAL, "null argument");
+    return guarded([&] { s->impl->set_window(start_step, velocity, ppc_x, ppc_y, density, ncols); });
+}
+
 int pic_laser_set(PicSim *s, int64_t nsteps, const double *ey, const double *ez)
 {
     if (!s) return bad(PIC_EINVAL, "null handle");
@@ -173,6 +180,7 @@ int pic_sync(PicSim *s)
         SimState st = s->impl->read_state();
         if (st.flags & kFlagNaN) rc = PIC_ENAN;
         else if (st.flags & kFlagCFL) rc = PIC_ECFL;
+        else if (st.flags & kFlagWin) rc = PIC_EOVERFLOW;
     });
     if (g != PIC_OK) return g;
     if (rc != PIC_OK) set_error("a particle error stopped the simulation");
@@ -228,6 +236,7 @@ int pic_diag_get(PicSim *s, PicDiag *out)
         out->occupancy_mean = c.empty() ? 0.0 : (double)tot / c.size();
         out->flags = (int32_t)st.flags;
         out->relayouts = s->impl->relayouts;
+        out->window_cells = st.wshift * s->impl->desc.patch[0];
         if (st.step > 0) {
             double U = 0, K = 0;
             int64_t pushed = 0;

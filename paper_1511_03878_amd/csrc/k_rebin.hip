@@ -272,6 +272,13 @@ __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict
                 h[3] = (double)st->removed;
                 st->U = u;
                 st->K = k;
+                if (st->wpend) {
+                    // the window jumped at the end of this step
+                    st->next_id += st->wadd;
+                    st->wshift += 1;
+                    st->wadd = 0;
+                    st->wpend = 0u;
+                }
                 st->step = n + 1;
                 st->steps_left = left;
                 st->rebinned = 0u;

@@ -64,6 +64,12 @@ void launch_maxwell3d(const SimDev<T> *sims, int nsims, const int *tile_prefix, 
                       int grid, hipStream_t st, Ev2 ev = {});
 constexpr int kMaxwell3dTile = 256;
 
+// Moving-window jump of one simulation (2-D): a no-op unless the step in
+// flight ends with a jump.  fn1 = field rows, npy = patch rows.
+template <typename T>
+void launch_window(const SimDev<T> *sim, int fn1, int npy, hipStream_t st);
+constexpr int kWindowMaxPatchColumns = 4096;
+
 // Fused Yee update (half B, E, half B) with face conditions; clears the
 // other J buffer and accumulates the field energy of the incoming E, B.
 // hi_order: the batch holds simulations with the sixth-order solver, which

@@ -35,7 +35,8 @@ constexpr uint8_t kRemoved = 255;
 constexpr uint32_t kFlagPending = 1u;  // a patch overflowed: re-binning of the last step not applied
 constexpr uint32_t kFlagNaN = 2u;      // non-finite momentum
 constexpr uint32_t kFlagCFL = 4u;      // a particle moved a cell or more
-constexpr uint32_t kFlagErrMask = kFlagNaN | kFlagCFL;
+constexpr uint32_t kFlagWin = 8u;      // a window jump found a patch too small for its injected particles
+constexpr uint32_t kFlagErrMask = kFlagNaN | kFlagCFL | kFlagWin;
 
 struct SimState {
     int64_t step;        // completed steps
@@ -47,6 +48,12 @@ struct SimState {
     double U, K;         // energies of the last completed step
     uint32_t rebinned;   // the step in flight has applied its re-binning
     uint32_t pad;
+    // moving window
+    int64_t next_id;     // id of the next injected particle
+    int64_t wshift;      // window jumps done (each one patch column)
+    int64_t wadd;        // particles injected by the jump of the step in flight
+    uint32_t wpend;      // the step in flight jumped (applied when the step closes)
+    uint32_t pad2;
 };
 
 template <typename T>
@@ -56,6 +63,13 @@ struct SimDev {
     int ndim;
     int lane_stride;   // particles between consecutive lanes of a wave
     int morder;        // field solver order: 2 (Yee) or 6
+    // moving window (2-D, open x): jumps of P[0] cells, cold lattice injection
+    int win;           // 1: the window moves
+    int wppc[2];       // injected particles per cell along x, y
+    int64_t wstart;    // completed steps before the window starts
+    double wvel, wdt, wdx;  // speed (units of c), time step and cell size along x, in FP64
+    const double *wdens;    // density per global cell column (the last entry continues)
+    int64_t wncols;
     T d[3];
     T dt;
     T q, m;

@@ -224,6 +224,7 @@ void SimImpl<T>::step(int64_t nsteps)
     if (nsteps < 0) throw Error(PIC_EINVAL, "negative step count");
     if (nsteps == 0) return;
     SimState s = read_state();
+    if (s.flags & kFlagWin) throw Error(PIC_EOVERFLOW, "a window jump found a patch too small");
     if (s.flags & kFlagErrMask) throw Error((s.flags & kFlagNaN) ? PIC_ENAN : PIC_ECFL, "simulation stopped by a particle error");
     if (!solo) {
         solo = new BatchImpl<T>(stream);
@@ -310,6 +311,8 @@ void SimImpl<T>::release()
     alloc.put(st);
     alloc.put(hist);
     alloc.put(counts_d);
+    alloc.put(wdens_d);
+    wdens_d = nullptr;
     alloc.put(newcount_d);
     alloc.put(kcnt_d);
     alloc.put(nleave_d);
@@ -340,6 +343,7 @@ void SimImpl<T>::release()
 template <typename T>
 std::vector<void *> SimImpl<T>::layout_particles(const std::vector<int32_t> &need)
 {
+    sync_layout();
     std::vector<int32_t> cap(npatch);
     std::vector<int64_t> off(npatch + 1, 0);
     // floor of every patch: the given minimum, or else the mean occupancy
@@ -355,6 +359,7 @@ std::vector<void *> SimImpl<T>::layout_particles(const std::vector<int32_t> &nee
         c = std::max<int64_t>(c, need[p]);
         c = (c + 63) & ~int64_t(63);
         if (p < (int)cap_h.size()) c = std::max<int64_t>(c, cap_h[p]);  // never shrink
+        c = std::max<int64_t>(c, cap_floor);
         if (c > INT32_MAX / 2) throw Error(PIC_EOVERFLOW, "patch capacity overflow");
         cap[p] = (int32_t)c;
         off[p + 1] = off[p] + c;
@@ -417,6 +422,15 @@ void SimImpl<T>::refresh_view()
     V.ndim = nd;
     V.lane_stride = lane_stride;
     V.morder = desc.maxwell_order == 6 ? 6 : 2;
+    V.win = win_on ? 1 : 0;
+    V.wppc[0] = win_ppc[0];
+    V.wppc[1] = win_ppc[1];
+    V.wstart = win_start;
+    V.wvel = win_v;
+    V.wdt = desc.dt;
+    V.wdx = desc.d[0];
+    V.wdens = wdens_d;
+    V.wncols = win_ncols;
     V.dt = (T)desc.dt;
     V.q = (T)desc.q;
     V.m = (T)desc.m;
@@ -498,6 +512,7 @@ void SimImpl<T>::set_particles(int64_t cnt, const double *const xs[3], const dou
     hipcheck(hipMemcpyAsync(counts_d, counts.data(), sizeof(int32_t) * npatch, hipMemcpyHostToDevice, stream), "counts");
     SimState s0;
     std::memset(&s0, 0, sizeof(s0));
+    s0.next_id = cnt;
     hipcheck(hipMemcpyAsync(st, &s0, sizeof(s0), hipMemcpyHostToDevice, stream), "state");
     hipcheck(hipStreamSynchronize(stream), "sync");
     relayouts = 0;
@@ -529,6 +544,56 @@ void SimImpl<T>::set_laser(int64_t nsteps, const double *ey, const double *ez)
         hipcheck(hipStreamSynchronize(stream), "sync");
     }
     refresh_view();
+    hipcheck(hipStreamSynchronize(stream), "sync");
+}
+
+// Moving window (2-D, open x): jumps of one patch column; every patch must
+// be able to hold the particles one jump injects into it.
+template <typename T>
+void SimImpl<T>::set_window(int64_t start, double vel, int ppcx, int ppcy, const double *dens,
+                            int64_t ncols)
+{
+    check_free();
+    if (nd != 2) throw Error(PIC_ENOTSUP, "the moving window is built for 2-D boxes");
+    if (periodic[0]) throw Error(PIC_EINVAL, "the moving window needs an open x axis");
+    if (!(vel > 0.0 && vel <= 1.0)) throw Error(PIC_EINVAL, "window speed must be in (0, 1]");
+    if (start < 0) throw Error(PIC_EINVAL, "negative window start");
+    if (ppcx < 1 || ppcy < 1 || (int64_t)ppcx * ppcy > 4096) throw Error(PIC_EINVAL, "particles per cell must be 1..4096");
+    if (ncols < 1 || !dens) throw Error(PIC_EINVAL, "empty density table");
+    for (int64_t c = 0; c < ncols; ++c)
+        if (!(dens[c] >= 0.0) || !std::isfinite(dens[c])) throw Error(PIC_EINVAL, "density must be finite and non-negative");
+    if (np[0] > kWindowMaxPatchColumns) throw Error(PIC_ENOTSUP, "more than 4096 patch columns");
+    const int64_t need = (int64_t)P[0] * P[1] * ppcx * ppcy;
+    if (need > INT32_MAX / 4) throw Error(PIC_EINVAL, "too many injected particles per patch");
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    double *d = (double *)alloc.get(sizeof(double) * ncols);
+    hipcheck(hipMemcpyAsync(d, dens, sizeof(double) * ncols, hipMemcpyHostToDevice, stream), "window");
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    alloc.put(wdens_d);
+    wdens_d = d;
+    win_on = true;
+    win_start = start;
+    win_v = vel;
+    win_ppc[0] = ppcx;
+    win_ppc[1] = ppcy;
+    win_ncols = ncols;
+    cap_floor = (int32_t)need;
+    sync_layout();
+    bool small = false;
+    for (int32_t c : cap_h) small = small || c < cap_floor;
+    if (small) relayout(read_counts());
+    refresh_view();
+    hipcheck(hipStreamSynchronize(stream), "sync");
+}
+
+// Re-read the capacities and segment offsets that window jumps rotate.
+template <typename T>
+void SimImpl<T>::sync_layout()
+{
+    if (!win_on || cap_h.empty() || !cap_d) return;
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    hipcheck(hipMemcpyAsync(cap_h.data(), cap_d, sizeof(int32_t) * npatch, hipMemcpyDeviceToHost, stream), "cap");
+    hipcheck(hipMemcpyAsync(off_h.data(), off_d, sizeof(int64_t) * (npatch + 1), hipMemcpyDeviceToHost, stream), "off");
     hipcheck(hipStreamSynchronize(stream), "sync");
 }
 
@@ -597,6 +662,7 @@ int64_t SimImpl<T>::num_particles()
 template <typename T>
 void SimImpl<T>::get_particles(double *xo[3], double *uo[3], double *wo, int64_t *ido, size_t cnt)
 {
+    sync_layout();
     auto c = read_counts();
     const int64_t live = std::accumulate(c.begin(), c.end(), int64_t(0));
     if ((int64_t)cnt < live) throw Error(PIC_EINVAL, "output arrays too small");
@@ -661,6 +727,7 @@ struct CkptHeader {
     int32_t n[3], patch[3], periodic[3];
     int64_t live, step, removed, fsize;
     double U, K;
+    int64_t wshift, next_id;  // moving window: jumps done, next injected id
 };
 constexpr char kCkptMagic[8] = {'P', 'I', 'C', 'S', 'T', 'A', 'T', 'E'};
 }  // namespace
@@ -677,6 +744,7 @@ template <typename T>
 void SimImpl<T>::state_save(void *blob)
 {
     hipcheck(hipStreamSynchronize(stream), "sync");
+    sync_layout();
     const SimState s = read_state();
     if (s.flags & kFlagPending) throw Error(PIC_ESTATE, "a re-binning is pending");
     const std::vector<int32_t> c = read_counts();
@@ -684,7 +752,7 @@ void SimImpl<T>::state_save(void *blob)
     CkptHeader h;
     std::memset(&h, 0, sizeof(h));
     std::memcpy(h.magic, kCkptMagic, 8);
-    h.version = 1;
+    h.version = 2;
     h.ndim = nd;
     h.precision = precision;
     h.npatch = npatch;
@@ -695,6 +763,8 @@ void SimImpl<T>::state_save(void *blob)
     h.fsize = fsize;
     h.U = s.U;
     h.K = s.K;
+    h.wshift = s.wshift;
+    h.next_id = s.next_id;
     char *o = static_cast<char *>(blob);
     std::memcpy(o, &h, sizeof(h));
     o += sizeof(h);
@@ -739,7 +809,7 @@ void SimImpl<T>::state_load(const void *blob, size_t size)
     if (size < sizeof(CkptHeader)) throw Error(PIC_EINVAL, "checkpoint too small");
     CkptHeader h;
     std::memcpy(&h, blob, sizeof(h));
-    if (std::memcmp(h.magic, kCkptMagic, 8) || h.version != 1) throw Error(PIC_EINVAL, "not a checkpoint");
+    if (std::memcmp(h.magic, kCkptMagic, 8) || h.version != 2) throw Error(PIC_EINVAL, "not a checkpoint");
     bool same = h.ndim == nd && h.precision == precision && h.npatch == npatch && h.fsize == fsize;
     for (int a = 0; a < 3; ++a)
         same = same && h.n[a] == n[a] && h.patch[a] == P[a] && h.periodic[a] == periodic[a];
@@ -799,6 +869,8 @@ void SimImpl<T>::state_load(const void *blob, size_t size)
     s0.removed = h.removed;
     s0.U = h.U;
     s0.K = h.K;
+    s0.wshift = h.wshift;
+    s0.next_id = h.next_id;
     hipcheck(hipMemcpyAsync(st, &s0, sizeof(s0), hipMemcpyHostToDevice, stream), "restore");
     hipcheck(hipMemsetAsync(kpart, 0, sizeof(double) * npatch, stream), "restore");
     hipcheck(hipStreamSynchronize(stream), "sync");
@@ -903,6 +975,7 @@ template <typename T>
 void SimImpl<T>::grow_capacity()
 {
     hipcheck(hipStreamSynchronize(stream), "sync");
+    sync_layout();
     std::vector<int32_t> cur = read_counts(), nxt(npatch);
     hipcheck(hipMemcpyAsync(nxt.data(), newcount_d, sizeof(int32_t) * npatch, hipMemcpyDeviceToHost, stream), "newcount");
     hipcheck(hipStreamSynchronize(stream), "sync");
@@ -914,6 +987,13 @@ void SimImpl<T>::grow_capacity()
         need[p] = std::max(cur[p], nxt[p]);
         if (p < (int)cap_h.size() && nxt[p] > cap_h[p]) need[p] = (int32_t)std::min<int64_t>(2LL * nxt[p], INT32_MAX / 4);
     }
+    relayout(need);
+}
+
+// New layout for the given per-patch needs; the live particles are copied.
+template <typename T>
+void SimImpl<T>::relayout(const std::vector<int32_t> &need)
+{
     SimDev<T> oldv = v;
     SimDev<T> *oldv_d = (SimDev<T> *)alloc.get(sizeof(SimDev<T>));
     hipcheck(hipMemcpyAsync(oldv_d, &oldv, sizeof(oldv), hipMemcpyHostToDevice, stream), "old view");
@@ -1278,6 +1358,9 @@ QueueArgs BatchImpl<T>::queue_args() const
 template <typename T>
 void BatchImpl<T>::launch_close_queue_pass()
 {
+    // window jumps of the steps that close in this pass
+    for (size_t i = 0; i < members.size(); ++i)
+        if (members[i]->win_on) launch_window<T>(sims_d + i, members[i]->fn[1], members[i]->np[1], stream);
     launch_close_queue<T>(sims_d, queue_args(), stream, timing().pair(0));
     hipcheck(hipGetLastError(), "queue launch");
 }

@@ -66,6 +66,8 @@ struct SimBase {
     virtual void set_particles(int64_t n, const double *const xs[3], const double *const us[3],
                                const double *w) = 0;
     virtual void set_laser(int64_t nsteps, const double *ey, const double *ez) = 0;
+    virtual void set_window(int64_t start, double vel, int ppcx, int ppcy, const double *dens,
+                            int64_t ncols) = 0;
     virtual void set_field(int comp, const double *h) = 0;
     virtual void get_field(int comp, double *h) = 0;
     virtual SimState read_state() = 0;
@@ -116,6 +118,14 @@ struct SimImpl : SimBase {
     int64_t *off_d = nullptr;
     std::vector<int32_t> cap_h;
     std::vector<int64_t> off_h;
+    // moving window: jumps rotate count/cap/off on the device, so cap_h and
+    // off_h are re-read (sync_layout) before the host uses them
+    bool win_on = false;
+    int64_t win_start = 0, win_ncols = 0;
+    double win_v = 0.0;
+    int win_ppc[2] = {1, 1};
+    double *wdens_d = nullptr;
+    int32_t cap_floor = 0;  // smallest patch capacity (the particles one jump injects)
     int64_t total_cap = 0;
     int max_items_cache = -1, chunk_cache = -1;
     int64_t layout_version = 0;
@@ -132,6 +142,8 @@ struct SimImpl : SimBase {
     std::vector<void *> layout_particles(const std::vector<int32_t> &need);
     void refresh_view();
     void grow_capacity();
+    void relayout(const std::vector<int32_t> &need);
+    void sync_layout();
     void recover_pending();
     void build_neighbour_table();
     int max_items(int chunk);
@@ -140,6 +152,8 @@ struct SimImpl : SimBase {
     void set_particles(int64_t n, const double *const xs[3], const double *const us[3],
                        const double *w) override;
     void set_laser(int64_t nsteps, const double *ey, const double *ez) override;
+    void set_window(int64_t start, double vel, int ppcx, int ppcy, const double *dens,
+                    int64_t ncols) override;
     void set_field(int comp, const double *h) override;
     void get_field(int comp, double *h) override;
     SimState read_state() override;

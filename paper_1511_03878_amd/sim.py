@@ -186,6 +186,13 @@ class Sim:
         v = _f64(np.asarray(values).reshape(-1))
         check(_capi.load().pic_fields_set(self._h, c, _dp(v), v.size))
 
+    def set_window(self, start: int, velocity: float, ppc, density):
+        """Moving window along x (pic_window_set): jumps of one patch column,
+        cold plasma of density[global column] injected at ppc = (ppc_x, ppc_y)."""
+        d = _f64(np.atleast_1d(density))
+        check(_capi.load().pic_window_set(self._h, int(start), float(velocity), int(ppc[0]),
+                                          int(ppc[1]), _dp(d), d.size))
+
     @classmethod
     def from_workload(cls, wl: dict, precision: int = 64, **kw) -> "Sim":
         s = cls(wl["grid"], precision, **kw)

@@ -146,8 +146,12 @@ def lwfa_2d(n=(4096, 1024), lam=2.0 * math.pi, cells_per_lam=(32, 8), patch=(32,
                                 y_center=Ly / 2 if y_center is None else y_center)
     grid = dict(ndim=2, n=list(n), d=list(d), dt=dt, patch=list(patch),
                 periodic=[0, 1], q=-1.0, m=1.0)
+    # density of every cell column at its centre, for a moving window's
+    # injection (the plateau continues beyond the table)
+    cc = np.arange(int(math.ceil(x1)) + 2) + 0.5
+    col_dens = np.where(cc < x0, 0.0, np.where(cc >= x1, n_plateau, n_plateau * (cc - x0) / (x1 - x0)))
     return dict(name="lwfa_2d", grid=grid, x=pos, u=mom, w=w,
-                laser=dict(ey=laser_ey, ez=None))
+                laser=dict(ey=laser_ey, ez=None), column_density=col_dens, ppc=ppc)
 
 
 def lwfa_2d_small(nsteps=200, seed=DEFAULT_SEED, n=(512, 128), patch=(32, 32), **kw):
