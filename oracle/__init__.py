@@ -81,6 +81,9 @@ def _load():
         "orc_set_maxwell_order": (C.c_int, [vp, C.c_int]),
         "orc_set_window": (C.c_int, [vp, C.c_int64, C.c_double, C.c_int, C.c_int, _D, C.c_int64]),
         "orc_window_shift": (C.c_int64, [vp]),
+        "orc_merge": (C.c_int64, [vp, C.c_int, C.c_int]),
+        "orc_set_merge": (C.c_int, [vp, C.c_int, C.c_int, C.c_int]),
+        "orc_merged": (C.c_int64, [vp]),
         "orc_next_id": (C.c_int64, [vp]),
         "orc_deposit": (None, [vp, _D, _D, C.c_double, C.c_double]),
         "orc_gather": (None, [vp, _D, _D]),
@@ -262,6 +265,23 @@ class Sim:
                                   _dp(dens), dens.size) != 0:
             raise ValueError("oracle: unsupported moving window for this grid")
         self._win_dens = dens
+
+    def merge(self, cmax: int, iters: int) -> int:
+        """One merge pass now (2-D): cells holding more than cmax particles are
+        clustered in momentum into cmax / 2 groups; groups of three or more
+        become conserving pairs.  Returns the particles taken out."""
+        if self.ndim != 2 or not (4 <= cmax <= 32) or not (1 <= iters <= 64):
+            raise ValueError("oracle: unsupported merge request")
+        return int(_load().orc_merge(self._p, int(cmax), int(iters)))
+
+    def set_merge(self, every: int, cmax: int = 16, iters: int = 8):
+        """Merge after every `every`-th step (0: never)."""
+        if _load().orc_set_merge(self._p, int(every), int(cmax), int(iters)) != 0:
+            raise ValueError("oracle: unsupported merge request")
+
+    @property
+    def merged(self) -> int:
+        return int(_load().orc_merged(self._p))
 
     @property
     def window_shift(self) -> int:

@@ -77,6 +77,10 @@ typedef struct {
     int64_t win_ncols;
     int64_t win_shift;/* shifts done so far (the window has moved win_shift * patch[0] cells) */
     int64_t next_id;  /* id of the next injected particle */
+    /* particle merging (see orc_merge) */
+    int merge_every;  /* merge after every merge_every-th step (0: never) */
+    int merge_cmax, merge_iters;
+    int64_t merged;   /* particles taken out by merging so far */
 } orc_sim;
 
 /* Staggering of Ex Ey Ez Bx By Bz (J shares E's): 1 = half a cell up. */
@@ -884,6 +888,218 @@ int orc_set_window(orc_sim *s, int64_t start, double v, int ppc_x, int ppc_y,
 int64_t orc_window_shift(const orc_sim *s) { return s->win_shift; }
 int64_t orc_next_id(const orc_sim *s) { return s->next_id; }
 
+/* ---- particle merging ----------------------------------------------------
+ *
+ * Dynamic load limiting (section 3.2): where a cell holds too many
+ * super-particles they are merged, by a k-means clustering, in a way that
+ * keeps the conserved quantities.  The paper leaves the scheme to its
+ * reference; this is the reading built here.  In a 2-D cell holding more than
+ * cmax particles (taken in slot order), the momenta u = p / (m c) are grouped
+ * into k = cmax / 2 clusters by weighted Lloyd iterations: the centroids
+ * start at the momenta of members floor(j n / k), then `iters` rounds assign
+ * every member to its nearest centroid (squared distance, lowest index on
+ * ties) and move every non-empty centroid to its cluster's weighted mean.  A
+ * final cluster of three or more members becomes two particles of half its
+ * weight W each, at its weighted mean position, with momenta
+ * |u_t| (cos t e1 +- sin t e2): gamma_t = E / W is the cluster's mean Lorentz
+ * factor, |u_t| = sqrt(gamma_t^2 - 1), e1 the direction of its momentum P
+ * (x if P = 0), cos t = |P| / (W |u_t|) (at most 1 by the convexity of gamma),
+ * e2 the unit vector along the axis least aligned with e1 made orthogonal to
+ * it.  Weight, momentum and kinetic energy of the cell stay as they were
+ * (each cell's charge too); the pair carries the two smallest ids of the
+ * cluster.  Clusters of one or two members stay as they are.  The patch then
+ * holds its untouched particles in their slot order, followed by the pairs in
+ * (cell, cluster) order. */
+
+#define ORC_MERGE_KMAX 16
+
+/* k-means and pair for one cell: mem[0..n) particle indices (slot order).
+ * Writes kept[] flags for the members and appends pairs to the out arrays;
+ * returns the number of pairs. */
+static int merge_cell(const orc_sim *s, const int64_t *mem, int n, int cmax, int iters, char *kept,
+                      double *ox[3], double *ou[3], double *ow, int64_t *oid, int64_t base)
+{
+    const int k = cmax / 2;
+    double c[ORC_MERGE_KMAX][3];
+    int *asg = malloc(sizeof(int) * n);
+    for (int j = 0; j < k; ++j)
+        for (int a = 0; a < 3; ++a) c[j][a] = s->u[a][mem[(int64_t)j * n / k]];
+    for (int it = 0; it < iters; ++it) {
+        for (int i = 0; i < n; ++i) {
+            const int64_t q = mem[i];
+            int best = 0;
+            double bd = 0.0;
+            for (int j = 0; j < k; ++j) {
+                const double dx = s->u[0][q] - c[j][0], dy = s->u[1][q] - c[j][1], dz = s->u[2][q] - c[j][2];
+                const double d2 = dx * dx + dy * dy + dz * dz;
+                if (j == 0 || d2 < bd) { bd = d2; best = j; }
+            }
+            asg[i] = best;
+        }
+        for (int j = 0; j < k; ++j) {
+            double sw = 0.0, su[3] = {0.0, 0.0, 0.0};
+            for (int i = 0; i < n; ++i)
+                if (asg[i] == j) {
+                    const int64_t q = mem[i];
+                    sw += s->w[q];
+                    for (int a = 0; a < 3; ++a) su[a] += s->w[q] * s->u[a][q];
+                }
+            if (sw > 0.0)
+                for (int a = 0; a < 3; ++a) c[j][a] = su[a] / sw;
+        }
+    }
+    int pairs = 0;
+    for (int j = 0; j < k; ++j) {
+        int cnt = 0;
+        for (int i = 0; i < n; ++i) cnt += asg[i] == j;
+        if (cnt < 3) {
+            for (int i = 0; i < n; ++i)
+                if (asg[i] == j) kept[i] = 1;
+            continue;
+        }
+        double W = 0.0, E = 0.0, P[3] = {0.0, 0.0, 0.0}, X[2] = {0.0, 0.0};
+        int64_t id0 = INT64_MAX, id1 = INT64_MAX;
+        for (int i = 0; i < n; ++i) {
+            if (asg[i] != j) continue;
+            const int64_t q = mem[i];
+            const double w = s->w[q];
+            const double g = sqrt(1.0 + s->u[0][q] * s->u[0][q] + s->u[1][q] * s->u[1][q] + s->u[2][q] * s->u[2][q]);
+            W += w;
+            E += w * g;
+            for (int a = 0; a < 3; ++a) P[a] += w * s->u[a][q];
+            X[0] += w * s->x[0][q];
+            X[1] += w * s->x[1][q];
+            const int64_t id = s->id[q];
+            if (id < id0) { id1 = id0; id0 = id; }
+            else if (id < id1) id1 = id;
+        }
+        const double gt = E / W;
+        const double ut = gt > 1.0 ? sqrt(gt * gt - 1.0) : 0.0;
+        const double pn = sqrt(P[0] * P[0] + P[1] * P[1] + P[2] * P[2]);
+        double e1[3] = {1.0, 0.0, 0.0};
+        if (pn > 0.0)
+            for (int a = 0; a < 3; ++a) e1[a] = P[a] / pn;
+        int ax = 0;
+        for (int a = 1; a < 3; ++a)
+            if (fabs(e1[a]) < fabs(e1[ax])) ax = a;
+        double e2[3] = {0.0, 0.0, 0.0};
+        e2[ax] = 1.0;
+        const double dp = e1[ax];
+        for (int a = 0; a < 3; ++a) e2[a] -= dp * e1[a];
+        const double en = sqrt(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]);
+        for (int a = 0; a < 3; ++a) e2[a] /= en;
+        double ct = ut > 0.0 ? pn / (W * ut) : 0.0;
+        if (ct > 1.0) ct = 1.0;
+        const double st = sqrt(1.0 - ct * ct);
+        for (int h = 0; h < 2; ++h) {
+            const int64_t t = base + 2 * pairs + h;
+            const double sg = h == 0 ? 1.0 : -1.0;
+            for (int a = 0; a < 3; ++a) ou[a][t] = ut * (ct * e1[a] + sg * st * e2[a]);
+            ox[0][t] = X[0] / W;
+            ox[1][t] = X[1] / W;
+            ox[2][t] = 0.0;
+            ow[t] = 0.5 * W;
+            oid[t] = h == 0 ? id0 : id1;
+        }
+        ++pairs;
+    }
+    free(asg);
+    return pairs;
+}
+
+/* One merge pass over every patch (2-D).  Returns the particles taken out. */
+int64_t orc_merge(orc_sim *s, int cmax, int iters)
+{
+    const int P0 = s->g.patch[0], P1 = s->g.patch[1], ncell = P0 * P1;
+    int64_t *start = malloc(sizeof(int64_t) * (s->npatch + 1));
+    start[0] = 0;
+    for (int p = 0; p < s->npatch; ++p) start[p + 1] = start[p] + s->count[p];
+    /* at most as many particles as before */
+    const int64_t cap = s->npart + 1;
+    double *nx[3], *nu[3], *nw = malloc(sizeof(double) * cap);
+    int64_t *nid = malloc(sizeof(int64_t) * cap);
+    for (int a = 0; a < 3; ++a) {
+        nx[a] = malloc(sizeof(double) * cap);
+        nu[a] = malloc(sizeof(double) * cap);
+    }
+    /* pairs of a patch before they are appended */
+    double *px_[3], *pu_[3], *pw_ = malloc(sizeof(double) * cap);
+    int64_t *pid_ = malloc(sizeof(int64_t) * cap);
+    for (int a = 0; a < 3; ++a) {
+        px_[a] = malloc(sizeof(double) * cap);
+        pu_[a] = malloc(sizeof(double) * cap);
+    }
+    int *cellof = malloc(sizeof(int) * cap);
+    char *keep = malloc(cap);
+    int64_t *mem = malloc(sizeof(int64_t) * cap);
+    char *mkept = malloc(cap);
+    int *ccount = malloc(sizeof(int) * ncell);
+    int64_t t = 0, taken = 0;
+    for (int p = 0; p < s->npatch; ++p) {
+        const int px = p % s->np[0], py = p / s->np[0];
+        const int64_t a0 = start[p], a1 = start[p + 1];
+        memset(ccount, 0, sizeof(int) * ncell);
+        for (int64_t q = a0; q < a1; ++q) {
+            int cx = (int)floor(s->x[0][q]) - px * P0, cy = (int)floor(s->x[1][q]) - py * P1;
+            if (cx < 0) cx = 0;
+            if (cx > P0 - 1) cx = P0 - 1;
+            if (cy < 0) cy = 0;
+            if (cy > P1 - 1) cy = P1 - 1;
+            cellof[q - a0] = cx + P0 * cy;
+            ccount[cx + P0 * cy]++;
+            keep[q - a0] = 1;
+        }
+        int64_t npair = 0;
+        for (int cidx = 0; cidx < ncell; ++cidx) {
+            if (ccount[cidx] <= cmax) continue;
+            int n = 0;
+            for (int64_t q = a0; q < a1; ++q)
+                if (cellof[q - a0] == cidx) mem[n++] = q;
+            memset(mkept, 0, n);
+            npair += merge_cell(s, mem, n, cmax, iters, mkept, px_, pu_, pw_, pid_, 2 * npair);
+            for (int i = 0; i < n; ++i) keep[mem[i] - a0] = mkept[i];
+        }
+        int32_t c = 0;
+        for (int64_t q = a0; q < a1; ++q) {
+            if (!keep[q - a0]) continue;
+            for (int a = 0; a < 3; ++a) { nx[a][t] = s->x[a][q]; nu[a][t] = s->u[a][q]; }
+            nw[t] = s->w[q];
+            nid[t] = s->id[q];
+            ++t;
+            ++c;
+        }
+        for (int64_t i = 0; i < 2 * npair; ++i, ++t, ++c) {
+            for (int a = 0; a < 3; ++a) { nx[a][t] = px_[a][i]; nu[a][t] = pu_[a][i]; }
+            nw[t] = pw_[i];
+            nid[t] = pid_[i];
+        }
+        taken += s->count[p] - c;
+        s->count[p] = c;
+    }
+    free_particles(s);
+    for (int a = 0; a < 3; ++a) { s->x[a] = nx[a]; s->u[a] = nu[a]; free(px_[a]); free(pu_[a]); }
+    s->w = nw;
+    s->id = nid;
+    s->npart = t;
+    s->merged += taken;
+    free(pw_); free(pid_); free(cellof); free(keep); free(mem); free(mkept); free(ccount); free(start);
+    return taken;
+}
+
+/* Merge after every `every`-th step (0: never); 2-D only, 4 <= cmax <= 32,
+ * 1 <= iters <= 64.  Returns 0, or -1 for an unsupported request. */
+int orc_set_merge(orc_sim *s, int every, int cmax, int iters)
+{
+    if (every < 0) return -1;
+    if (every > 0 && (s->g.ndim != 2 || cmax < 4 || cmax > 2 * ORC_MERGE_KMAX || iters < 1 || iters > 64)) return -1;
+    s->merge_every = every;
+    s->merge_cmax = cmax;
+    s->merge_iters = iters;
+    return 0;
+}
+
+int64_t orc_merged(const orc_sim *s) { return s->merged; }
+
 /* One full step n -> n+1 (state x^n, u^{n-1/2}, E^n, B^n on entry). */
 static void one_step(orc_sim *s)
 {
@@ -953,6 +1169,8 @@ static void one_step(orc_sim *s)
     free(newcount);
     free(src);
     free(dest);
+    if (s->merge_every > 0 && (s->step + 1) % s->merge_every == 0)
+        orc_merge(s, s->merge_cmax, s->merge_iters);
     if (s->win && win_due(s, s->step + 1) > s->win_shift) window_shift(s);
     s->step += 1;
 }
