@@ -126,6 +126,7 @@ typedef struct {
     int32_t flags;         /* sticky device error bits (see pic_sync) */
     int32_t relayouts;     /* capacity re-layouts performed so far */
     int64_t window_cells;  /* cells the moving window has travelled (0 without one) */
+    int64_t merged;        /* particles taken out by merging so far */
 } PicDiag;
 
 /* Per-kernel timing accumulated while timing is enabled (HIP events on the
@@ -185,6 +186,30 @@ int pic_laser_set(PicSim *s, int64_t nsteps, const double *ey, const double *ez)
  * x axis or bad arguments, PIC_ESTATE while the simulation is in a batch. */
 int pic_window_set(PicSim *s, int64_t start_step, double velocity, int32_t ppc_x, int32_t ppc_y,
                    const double *density, int64_t ncols);
+
+/* Particle merging, the dynamic load limiting of Sec. 3.2 (2-D): in every
+ * cell holding more than cell_max particles (4..32), the momenta u = p/(mc),
+ * taken in slot order, are grouped by weighted k-means into k = cell_max / 2
+ * clusters (centroids start at the momenta of members floor(j n / k); each
+ * of `iterations` rounds (1..64) assigns every member to its nearest centroid,
+ * lowest index on ties, then moves every non-empty centroid to its cluster's
+ * weighted mean).  A cluster of three or more becomes two particles of half
+ * its weight W at its weighted mean position, with momenta
+ * |u_t| (cos t e1 +- sin t e2), gamma_t = (sum w gamma) / W,
+ * |u_t| = sqrt(gamma_t^2 - 1), e1 along the cluster momentum P (x if P = 0),
+ * cos t = |P| / (W |u_t|), e2 the axis least aligned with e1 made orthogonal
+ * to it; the pair takes the cluster's two smallest ids.  Each cell keeps its
+ * weight (charge), momentum, kinetic energy and charge centre; afterwards no
+ * cell holds more than cell_max particles.  A patch then holds its untouched
+ * particles in slot order followed by the pairs in (cell, cluster) order.
+ * The clustering runs in FP64 (FP32 particles are widened).
+ * pic_merge_set: merge after every `every`-th step (0: never; the pass runs
+ * after the re-binning, before a window jump).  pic_merge: one pass now;
+ * *taken (may be NULL) receives the particles taken out.  Errors: PIC_ENOTSUP
+ * in 3-D, PIC_EINVAL for out-of-range arguments, PIC_ESTATE in a batch or
+ * while a re-binning is pending. */
+int pic_merge_set(PicSim *s, int32_t every, int32_t cell_max, int32_t iterations);
+int pic_merge(PicSim *s, int32_t cell_max, int32_t iterations, int64_t *taken);
 
 /* Overwrite one field component (E or B) from a host FP64 array of
  * count = fn[0]*fn[1]*fn[2] values. */

@@ -26,7 +26,8 @@ EXPORTS = (
     "pic_timing_enable", "pic_timing_get", "pic_batch_create", "pic_batch_destroy",
     "pic_batch_add", "pic_batch_remove", "pic_batch_step", "pic_batch_finished",
     "pic_batch_size", "pic_estimate_bytes", "pic_autotune", "pic_state_save", "pic_state_load",
-    "pic_patch_order", "pic_curve_segments", "pic_window_set", "pic_strerror",
+    "pic_patch_order", "pic_curve_segments", "pic_window_set", "pic_merge_set", "pic_merge",
+    "pic_strerror",
     "pic_last_error",
 )
 
@@ -71,7 +72,7 @@ class Diag(C.Structure):
         ("field_energy", C.c_double), ("kinetic_energy", C.c_double),
         ("occupancy_min", C.c_int32), ("occupancy_max", C.c_int32),
         ("occupancy_mean", C.c_double), ("flags", C.c_int32), ("relayouts", C.c_int32),
-        ("window_cells", C.c_int64),
+        ("window_cells", C.c_int64), ("merged", C.c_int64),
     ]
 
 
@@ -107,6 +108,8 @@ def load() -> C.CDLL:
         "pic_particles_set": (C.c_int, [_vp, C.c_int64, _D, _D, _D, _D, _D, _D, _D]),
         "pic_laser_set": (C.c_int, [_vp, C.c_int64, _D, _D]),
         "pic_window_set": (C.c_int, [_vp, C.c_int64, C.c_double, C.c_int32, C.c_int32, _D, C.c_int64]),
+        "pic_merge_set": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32]),
+        "pic_merge": (C.c_int, [_vp, C.c_int32, C.c_int32, C.POINTER(C.c_int64)]),
         "pic_fields_set": (C.c_int, [_vp, C.c_int, _D, C.c_size_t]),
         "pic_fields_get": (C.c_int, [_vp, C.c_int, _D, C.c_size_t]),
         "pic_step": (C.c_int, [_vp, C.c_int64]),

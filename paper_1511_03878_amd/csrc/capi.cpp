@@ -131,6 +131,21 @@ int pic_window_set(PicSim *s, int64_t start_step, double velocity, int32_t ppc_x
     return guarded([&] { s->impl->set_window(start_step, velocity, ppc_x, ppc_y, density, ncols); });
 }
 
+int pic_merge_set(PicSim *s, int32_t every, int32_t cell_max, int32_t iterations)
+{
+    if (!s) return bad(PIC_EINVAL, "null handle");
+    return guarded([&] { s->impl->set_merge(every, cell_max, iterations); });
+}
+
+int pic_merge(PicSim *s, int32_t cell_max, int32_t iterations, int64_t *taken)
+{
+    if (!s) return bad(PIC_EINVAL, "null handle");
+    return guarded([&] {
+        const int64_t t = s->impl->merge_now(cell_max, iterations);
+        if (taken) *taken = t;
+    });
+}
+
 int pic_laser_set(PicSim *s, int64_t nsteps, const double *ey, const double *ez)
 {
     if (!s) return bad(PIC_EINVAL, "null handle");
@@ -237,6 +252,7 @@ int pic_diag_get(PicSim *s, PicDiag *out)
         out->flags = (int32_t)st.flags;
         out->relayouts = s->impl->relayouts;
         out->window_cells = st.wshift * s->impl->desc.patch[0];
+        out->merged = st.merged;
         if (st.step > 0) {
             double U = 0, K = 0;
             int64_t pushed = 0;

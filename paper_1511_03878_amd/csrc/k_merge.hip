@@ -1,0 +1,355 @@
+// Particle merging (dynamic load limiting, section 3.2), 2-D.
+//
+// Where a cell holds more than cmax particles, their momenta u = p / (m c)
+// are grouped by weighted Lloyd iterations into k = cmax / 2 clusters
+// (centroids start at the momenta of members floor(j n / k) in slot order;
+// each round assigns every member to its nearest centroid, lowest index on
+// ties, and moves every non-empty centroid to its cluster's weighted mean).
+// A final cluster of three or more members becomes two particles of half its
+// weight W each, at its weighted mean position, with momenta
+// |u_t| (cos t e1 +- sin t e2): gamma_t = E / W, |u_t| = sqrt(gamma_t^2 - 1),
+// e1 along the cluster momentum P (x if P = 0), cos t = |P| / (W |u_t|), e2 the
+// axis least aligned with e1 made orthogonal to it.  Weight, momentum, kinetic
+// energy and the first moment of the charge of every cell are kept; the pair
+// takes the two smallest ids of its cluster.  A patch then holds its untouched
+// particles in slot order followed by the pairs in (cell, cluster) order.
+//
+// One workgroup per patch.  The cells' member lists are built in slot order
+// in the patch's vacated-slot list (free outside the re-binning), the
+// clustering of a cell runs on one thread in FP64 in the same order of
+// operations as a plain sequential loop (no contraction into fused
+// multiply-adds), the new patch contents are assembled in the staging arrays
+// and copied back.  The pass runs between the re-binning and the step close,
+// before a window jump.
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+#include "pic_dev.h"
+
+namespace pic {
+namespace {
+
+constexpr int kMB = 256;          // threads per workgroup
+constexpr int kMaxCells = 4096;   // cells per patch (64 x 64)
+constexpr int kKMax = 16;         // clusters per cell (cmax <= 32)
+constexpr uint8_t kKeep = 0xFF;   // a particle that stays as it is
+
+// Exclusive prefix sum of a[0..n) in place (n <= kMaxCells); returns the total.
+__device__ int block_scan(int *a, int n, int *s_w)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int per = (n + kMB - 1) / kMB;
+    int loc = 0;
+    for (int r = 0; r < per; ++r) {
+        const int i = tid * per + r;
+        if (i < n) loc += a[i];
+    }
+    int inc = loc;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += v;
+    }
+    if (lane == 63) s_w[wave] = inc;
+    __syncthreads();
+    int before = inc - loc;
+    for (int w = 0; w < wave; ++w) before += s_w[w];
+    const int total = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+    for (int r = 0; r < per; ++r) {
+        const int i = tid * per + r;
+        if (i < n) {
+            const int v = a[i];
+            a[i] = before;
+            before += v;
+        }
+    }
+    __syncthreads();
+    return total;
+}
+
+// Weighted Lloyd clustering of one cell's members (slot indices mem[0..n)
+// relative to the patch segment); writes the final cluster of every member
+// into code[].  Each round assigns a member and adds it to its cluster's sums
+// in one pass (the sums of a cluster still grow in member order), with the
+// centroids and sums held in registers (k <= kKMax).
+template <typename T>
+__device__ void cluster_cell(const SimDev<T> &S, int64_t base, const int32_t *mem, int n, int k,
+                             int iters)
+{
+#pragma clang fp contract(off)
+    double cx[kKMax], cy[kKMax], cz[kKMax];
+#pragma unroll
+    for (int j = 0; j < kKMax; ++j) {
+        cx[j] = cy[j] = cz[j] = 0.0;
+        if (j < k) {
+            const int64_t q = base + mem[(int64_t)j * n / k];
+            cx[j] = (double)glb(S.u[0])[q];
+            cy[j] = (double)glb(S.u[1])[q];
+            cz[j] = (double)glb(S.u[2])[q];
+        }
+    }
+    for (int it = 0; it < iters; ++it) {
+        double sw[kKMax], sx[kKMax], sy[kKMax], sz[kKMax];
+#pragma unroll
+        for (int j = 0; j < kKMax; ++j) sw[j] = sx[j] = sy[j] = sz[j] = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const int64_t q = base + mem[i];
+            const double ux = glb(S.u[0])[q], uy = glb(S.u[1])[q], uz = glb(S.u[2])[q];
+            const double w = glb(S.w)[q];
+            int best = 0;
+            double bd = 0.0;
+#pragma unroll
+            for (int j = 0; j < kKMax; ++j) {
+                if (j < k) {
+                    const double dx = ux - cx[j], dy = uy - cy[j], dz = uz - cz[j];
+                    const double d2 = dx * dx + dy * dy + dz * dz;
+                    if (j == 0 || d2 < bd) {
+                        bd = d2;
+                        best = j;
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kKMax; ++j)
+                if (j == best) {
+                    sw[j] += w;
+                    sx[j] += w * ux;
+                    sy[j] += w * uy;
+                    sz[j] += w * uz;
+                }
+            if (it == iters - 1) glb(S.code)[q] = (uint8_t)best;
+        }
+#pragma unroll
+        for (int j = 0; j < kKMax; ++j)
+            if (j < k && sw[j] > 0.0) {
+                cx[j] = sx[j] / sw[j];
+                cy[j] = sy[j] / sw[j];
+                cz[j] = sz[j] / sw[j];
+            }
+    }
+}
+
+// The conserving pair of cluster j (members whose code is j); writes it to
+// the staging arrays at slot `dst` and dst + 1.
+template <typename T>
+__device__ void write_pair(const SimDev<T> &S, int64_t base, const int32_t *mem, int n, int j, int64_t dst)
+{
+#pragma clang fp contract(off)
+    double W = 0.0, E = 0.0, P0 = 0.0, P1 = 0.0, P2 = 0.0, X0 = 0.0, X1 = 0.0;
+    int64_t id0 = INT64_MAX, id1 = INT64_MAX;
+    for (int i = 0; i < n; ++i) {
+        const int64_t q = base + mem[i];
+        if (glb(S.code)[q] != j) continue;
+        const double w = glb(S.w)[q];
+        const double ux = glb(S.u[0])[q], uy = glb(S.u[1])[q], uz = glb(S.u[2])[q];
+        const double g = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
+        W += w;
+        E += w * g;
+        P0 += w * ux;
+        P1 += w * uy;
+        P2 += w * uz;
+        X0 += w * (double)glb(S.x[0])[q];
+        X1 += w * (double)glb(S.x[1])[q];
+        const int64_t id = glb(S.id)[q];
+        if (id < id0) {
+            id1 = id0;
+            id0 = id;
+        } else if (id < id1) {
+            id1 = id;
+        }
+    }
+    const double gt = E / W;
+    const double ut = gt > 1.0 ? sqrt(gt * gt - 1.0) : 0.0;
+    const double pn = sqrt(P0 * P0 + P1 * P1 + P2 * P2);
+    double e1[3] = {1.0, 0.0, 0.0};
+    if (pn > 0.0) {
+        e1[0] = P0 / pn;
+        e1[1] = P1 / pn;
+        e1[2] = P2 / pn;
+    }
+    int ax = 0;
+    for (int a = 1; a < 3; ++a)
+        if (fabs(e1[a]) < fabs(e1[ax])) ax = a;
+    double e2[3] = {0.0, 0.0, 0.0};
+    e2[ax] = 1.0;
+    const double dp = e1[ax];
+    for (int a = 0; a < 3; ++a) e2[a] -= dp * e1[a];
+    const double en = sqrt(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]);
+    for (int a = 0; a < 3; ++a) e2[a] /= en;
+    double ct = ut > 0.0 ? pn / (W * ut) : 0.0;
+    if (ct > 1.0) ct = 1.0;
+    const double st = sqrt(1.0 - ct * ct);
+    for (int h = 0; h < 2; ++h) {
+        const int64_t t = dst + h;
+        const double sg = h == 0 ? 1.0 : -1.0;
+        for (int a = 0; a < 3; ++a) glb(S.su[a])[t] = (T)(ut * (ct * e1[a] + sg * st * e2[a]));
+        glb(S.sx[0])[t] = (T)(X0 / W);
+        glb(S.sx[1])[t] = (T)(X1 / W);
+        glb(S.sw)[t] = (T)(0.5 * W);
+        glb(S.sid)[t] = h == 0 ? id0 : id1;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kMB) void k_merge2d(const SimDev<T> *__restrict__ sp, int cmax, int iters,
+                                                 int forced)
+{
+    __shared__ int s_cnt[kMaxCells];   // particles per cell
+    __shared__ int s_pos[kMaxCells];   // start of the cell's member list (its end while it is built)
+    __shared__ int s_out[kMaxCells];   // first pair output of the cell
+    __shared__ int s_chunk[kMB];
+    __shared__ int s_w[4];
+    __shared__ int s_run;
+    const SimDev<T> &S = *sp;
+    const gptr_t<SimState> st = glb(S.st);
+    if (!forced) {
+        if (S.mevery <= 0) return;
+        if (!st->active || !st->rebinned || (st->flags & kFlagPending)) return;
+        if ((st->step + 1) % S.mevery != 0) return;
+        cmax = S.mcmax;
+        iters = S.miters;
+    }
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int P0 = S.P[0], P1 = S.P[1], ncell = P0 * P1;
+    const int k = cmax / 2;
+    int64_t taken = 0;
+    for (int p = blockIdx.x; p < S.npatch; p += gridDim.x) {
+        const int n = glb(S.count)[p];
+        if (n <= cmax) continue;
+        const int64_t base = glb(S.off)[p];
+        auto cell_of = [&](int i) {
+            int cx = (int)floor(glb(S.x[0])[base + i]), cy = (int)floor(glb(S.x[1])[base + i]);
+            cx = min(max(cx, 0), P0 - 1);
+            cy = min(max(cy, 0), P1 - 1);
+            return cx + P0 * cy;
+        };
+        // ---- cell counts; every particle starts as kept ----
+        for (int c = tid; c < ncell; c += kMB) s_cnt[c] = 0;
+        __syncthreads();
+        for (int i = tid; i < n; i += kMB) {
+            atomicAdd(&s_cnt[cell_of(i)], 1);
+            glb(S.code)[base + i] = kKeep;
+        }
+        __syncthreads();
+        // member lists of the cells above the threshold, one after another
+        for (int c = tid; c < ncell; c += kMB) s_pos[c] = s_cnt[c] > cmax ? s_cnt[c] : 0;
+        __syncthreads();
+        const int heavy = block_scan(s_pos, ncell, s_w);
+        if (heavy == 0) continue;
+        // ---- member lists in slot order (chunks of kMB particles) ----
+        const gptr_t<int32_t> mem = glb(S.holes) + base;
+        for (int i0 = 0; i0 < n; i0 += kMB) {
+            const int i = i0 + tid;
+            const int c = i < n ? cell_of(i) : -1;
+            s_chunk[tid] = c;
+            __syncthreads();
+            const bool hv = c >= 0 && s_cnt[c] > cmax;
+            int rank = 0, same = 0;
+            if (hv) {
+                for (int t = 0; t < kMB; ++t) {
+                    const int o = s_chunk[t];
+                    rank += (o == c && t < tid) ? 1 : 0;
+                    same += (o == c) ? 1 : 0;
+                }
+                mem[s_pos[c] + rank] = i;
+            }
+            __syncthreads();
+            if (hv && rank == 0) s_pos[c] += same;
+            __syncthreads();
+        }
+        // ---- clustering, one thread per crowded cell ----
+        for (int c = tid; c < ncell; c += kMB) {
+            const int nc = s_cnt[c];
+            int outs = 0;
+            if (nc > cmax) {
+                s_pos[c] -= nc;  // back to the list's start
+                const int32_t *m = (const int32_t *)&mem[s_pos[c]];
+                cluster_cell(S, base, m, nc, k, iters);
+                int size[kKMax];
+                for (int j = 0; j < k; ++j) size[j] = 0;
+                for (int i = 0; i < nc; ++i) size[glb(S.code)[base + m[i]]]++;
+                for (int j = 0; j < k; ++j) outs += size[j] >= 3 ? 2 : 0;
+                // members of clusters of one or two stay as they are
+                for (int i = 0; i < nc; ++i) {
+                    const int64_t q = base + m[i];
+                    if (size[glb(S.code)[q]] < 3) glb(S.code)[q] = kKeep;
+                }
+            }
+            s_out[c] = outs;
+        }
+        __syncthreads();
+        const int nout = block_scan(s_out, ncell, s_w);
+        // ---- kept particles, in slot order, to the front of the staging copy ----
+        if (tid == 0) s_run = 0;
+        __syncthreads();
+        for (int i0 = 0; i0 < n; i0 += kMB) {
+            const int i = i0 + tid;
+            const bool kp = i < n && glb(S.code)[base + i] == kKeep;
+            const uint64_t b = __ballot(kp);
+            if (lane == 0) s_w[wave] = __popcll(b);
+            __syncthreads();
+            if (kp) {
+                int r = s_run + __popcll(b & lt);
+                for (int w = 0; w < wave; ++w) r += s_w[w];
+                const int64_t src = base + i, dst = base + r;
+                glb(S.sx[0])[dst] = glb(S.x[0])[src];
+                glb(S.sx[1])[dst] = glb(S.x[1])[src];
+                for (int a = 0; a < 3; ++a) glb(S.su[a])[dst] = glb(S.u[a])[src];
+                glb(S.sw)[dst] = glb(S.w)[src];
+                glb(S.sid)[dst] = glb(S.id)[src];
+            }
+            __syncthreads();
+            if (tid == 0) s_run += s_w[0] + s_w[1] + s_w[2] + s_w[3];
+            __syncthreads();
+        }
+        const int nkeep = s_run;
+        // ---- the pairs after them, in (cell, cluster) order ----
+        for (int c = tid; c < ncell; c += kMB) {
+            const int nc = s_cnt[c];
+            if (nc <= cmax) continue;
+            const int32_t *m = (const int32_t *)&mem[s_pos[c]];
+            int64_t dst = base + nkeep + s_out[c];
+            for (int j = 0; j < k; ++j) {
+                bool any = false;
+                for (int i = 0; i < nc && !any; ++i) any = glb(S.code)[base + m[i]] == j;
+                if (!any) continue;
+                write_pair(S, base, m, nc, j, dst);
+                dst += 2;
+            }
+        }
+        __syncthreads();
+        // ---- back into the patch's slots ----
+        const int nn = nkeep + nout;
+        for (int i = tid; i < nn; i += kMB) {
+            const int64_t q = base + i;
+            glb(S.x[0])[q] = glb(S.sx[0])[q];
+            glb(S.x[1])[q] = glb(S.sx[1])[q];
+            for (int a = 0; a < 3; ++a) glb(S.u[a])[q] = glb(S.su[a])[q];
+            glb(S.w)[q] = glb(S.sw)[q];
+            glb(S.id)[q] = glb(S.sid)[q];
+            glb(S.code)[q] = (uint8_t)kStay2;
+        }
+        if (tid == 0) {
+            glb(S.count)[p] = nn;
+            taken += n - nn;
+        }
+        __syncthreads();
+    }
+    if (tid == 0 && taken)
+        __hip_atomic_fetch_add(&st->merged, taken, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace
+
+template <typename T>
+void launch_merge(const SimDev<T> *sim, int npatch, int cmax, int iters, int forced, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_merge2d<T>), dim3(std::min(npatch, 2048)), dim3(kMB), 0, st, sim, cmax, iters, forced);
+}
+
+template void launch_merge<float>(const SimDev<float> *, int, int, int, int, hipStream_t);
+template void launch_merge<double>(const SimDev<double> *, int, int, int, int, hipStream_t);
+
+}  // namespace pic

@@ -70,6 +70,12 @@ template <typename T>
 void launch_window(const SimDev<T> *sim, int fn1, int npy, hipStream_t st);
 constexpr int kWindowMaxPatchColumns = 4096;
 
+// Particle merging of one simulation (2-D).  forced = 0: a no-op unless the
+// step in flight is a merge step (cmax, iters then come from the simulation);
+// forced = 1: merge now with the given cmax (4..32) and iters.
+template <typename T>
+void launch_merge(const SimDev<T> *sim, int npatch, int cmax, int iters, int forced, hipStream_t st);
+
 // Fused Yee update (half B, E, half B) with face conditions; clears the
 // other J buffer and accumulates the field energy of the incoming E, B.
 // hi_order: the batch holds simulations with the sixth-order solver, which

@@ -54,6 +54,7 @@ struct SimState {
     int64_t wadd;        // particles injected by the jump of the step in flight
     uint32_t wpend;      // the step in flight jumped (applied when the step closes)
     uint32_t pad2;
+    int64_t merged;      // particles taken out by merging so far
 };
 
 template <typename T>
@@ -70,6 +71,8 @@ struct SimDev {
     double wvel, wdt, wdx;  // speed (units of c), time step and cell size along x, in FP64
     const double *wdens;    // density per global cell column (the last entry continues)
     int64_t wncols;
+    // particle merging (2-D): after every mevery-th step (0: never)
+    int mevery, mcmax, miters;
     T d[3];
     T dt;
     T q, m;

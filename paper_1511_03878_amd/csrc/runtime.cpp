@@ -431,6 +431,9 @@ void SimImpl<T>::refresh_view()
     V.wdx = desc.d[0];
     V.wdens = wdens_d;
     V.wncols = win_ncols;
+    V.mevery = merge_every;
+    V.mcmax = merge_cmax;
+    V.miters = merge_iters;
     V.dt = (T)desc.dt;
     V.q = (T)desc.q;
     V.m = (T)desc.m;
@@ -584,6 +587,41 @@ void SimImpl<T>::set_window(int64_t start, double vel, int ppcx, int ppcy, const
     if (small) relayout(read_counts());
     refresh_view();
     hipcheck(hipStreamSynchronize(stream), "sync");
+}
+
+// Particle merging (2-D): after every `every`-th step (0: never), or now.
+template <typename T>
+void SimImpl<T>::set_merge(int every, int cmax, int iters)
+{
+    check_free();
+    if (every < 0) throw Error(PIC_EINVAL, "negative merge interval");
+    if (every > 0) {
+        if (nd != 2) throw Error(PIC_ENOTSUP, "particle merging is built for 2-D boxes");
+        if (cmax < 4 || cmax > 32) throw Error(PIC_EINVAL, "cell_max must be 4..32");
+        if (iters < 1 || iters > 64) throw Error(PIC_EINVAL, "iterations must be 1..64");
+    }
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    merge_every = every;
+    merge_cmax = cmax;
+    merge_iters = iters;
+    refresh_view();
+    hipcheck(hipStreamSynchronize(stream), "sync");
+}
+
+template <typename T>
+int64_t SimImpl<T>::merge_now(int cmax, int iters)
+{
+    check_free();
+    if (nd != 2) throw Error(PIC_ENOTSUP, "particle merging is built for 2-D boxes");
+    if (cmax < 4 || cmax > 32) throw Error(PIC_EINVAL, "cell_max must be 4..32");
+    if (iters < 1 || iters > 64) throw Error(PIC_EINVAL, "iterations must be 1..64");
+    const SimState s0 = read_state();
+    if (s0.flags & kFlagPending) throw Error(PIC_ESTATE, "a re-binning is pending");
+    if (!cap_d) return 0;
+    launch_merge<T>(view_d, npatch, cmax, iters, 1, stream);
+    hipcheck(hipGetLastError(), "merge launch");
+    const SimState s1 = read_state();
+    return s1.merged - s0.merged;
 }
 
 // Re-read the capacities and segment offsets that window jumps rotate.
@@ -1358,9 +1396,13 @@ QueueArgs BatchImpl<T>::queue_args() const
 template <typename T>
 void BatchImpl<T>::launch_close_queue_pass()
 {
-    // window jumps of the steps that close in this pass
+    // merges, then window jumps, of the steps that close in this pass
     for (size_t i = 0; i < members.size(); ++i)
-        if (members[i]->win_on) launch_window<T>(sims_d + i, members[i]->fn[1], members[i]->np[1], stream);
+        if (members[i]->merge_every > 0 && members[i]->cap_d)
+            launch_merge<T>(sims_d + i, members[i]->npatch, 0, 0, 0, stream);
+    for (size_t i = 0; i < members.size(); ++i)
+        if (members[i]->win_on && members[i]->cap_d)
+            launch_window<T>(sims_d + i, members[i]->fn[1], members[i]->np[1], stream);
     launch_close_queue<T>(sims_d, queue_args(), stream, timing().pair(0));
     hipcheck(hipGetLastError(), "queue launch");
 }

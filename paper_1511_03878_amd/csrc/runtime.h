@@ -68,6 +68,8 @@ struct SimBase {
     virtual void set_laser(int64_t nsteps, const double *ey, const double *ez) = 0;
     virtual void set_window(int64_t start, double vel, int ppcx, int ppcy, const double *dens,
                             int64_t ncols) = 0;
+    virtual void set_merge(int every, int cmax, int iters) = 0;
+    virtual int64_t merge_now(int cmax, int iters) = 0;
     virtual void set_field(int comp, const double *h) = 0;
     virtual void get_field(int comp, double *h) = 0;
     virtual SimState read_state() = 0;
@@ -126,6 +128,7 @@ struct SimImpl : SimBase {
     int win_ppc[2] = {1, 1};
     double *wdens_d = nullptr;
     int32_t cap_floor = 0;  // smallest patch capacity (the particles one jump injects)
+    int merge_every = 0, merge_cmax = 16, merge_iters = 8;
     int64_t total_cap = 0;
     int max_items_cache = -1, chunk_cache = -1;
     int64_t layout_version = 0;
@@ -154,6 +157,8 @@ struct SimImpl : SimBase {
     void set_laser(int64_t nsteps, const double *ey, const double *ez) override;
     void set_window(int64_t start, double vel, int ppcx, int ppcy, const double *dens,
                     int64_t ncols) override;
+    void set_merge(int every, int cmax, int iters) override;
+    int64_t merge_now(int cmax, int iters) override;
     void set_field(int comp, const double *h) override;
     void get_field(int comp, double *h) override;
     SimState read_state() override;

@@ -186,6 +186,16 @@ class Sim:
         v = _f64(np.asarray(values).reshape(-1))
         check(_capi.load().pic_fields_set(self._h, c, _dp(v), v.size))
 
+    def set_merge(self, every: int, cell_max: int = 16, iterations: int = 8):
+        """Merge crowded cells after every `every`-th step (0: never); pic_merge_set."""
+        check(_capi.load().pic_merge_set(self._h, int(every), int(cell_max), int(iterations)))
+
+    def merge(self, cell_max: int = 16, iterations: int = 8) -> int:
+        """One merge pass now (pic_merge); returns the particles taken out."""
+        t = C.c_int64()
+        check(_capi.load().pic_merge(self._h, int(cell_max), int(iterations), C.byref(t)))
+        return t.value
+
     def set_window(self, start: int, velocity: float, ppc, density):
         """Moving window along x (pic_window_set): jumps of one patch column,
         cold plasma of density[global column] injected at ppc = (ppc_x, ppc_y)."""
