@@ -109,9 +109,9 @@ typedef struct {
     int32_t patch_order;   /* order of equal-size work items: 0 = patch id; 1 = the Hilbert
                               curve of pic_patch_order (power-of-two patch grids only) */
     int32_t maxwell_order; /* field solver: 0 or 2 = Yee (second order, Sec. 2.1); 6 = staggered
-                              differences of sixth order on the same grid (2-D, every axis
-                              periodic, dt < (sum_m |c_m|)^(-1) (sum 1/d^2)^(-1/2) with
-                              c = 75/64, -25/384, 3/640; PIC_ENOTSUP in 3-D) */
+                              differences of sixth order on the same grid (every axis periodic,
+                              dt < (sum_m |c_m|)^(-1) (sum 1/d^2)^(-1/2) with
+                              c = 75/64, -25/384, 3/640) */
 } PicSimDesc;
 
 /* Diagnostics of a simulation (pic_diag_get synchronises the stream). */

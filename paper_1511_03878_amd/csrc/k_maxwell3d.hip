@@ -8,7 +8,9 @@
 //      own B and neighbouring E).
 // B updates take forward differences of E, E updates backward differences of B;
 // staggering as in the particle kernel.  A "tile" here is a block of 256
-// consecutive nodes (x fastest) of one simulation.
+// consecutive nodes (x fastest) of one simulation.  A simulation with the
+// sixth-order solver takes the same passes with the three-pair staggered
+// differences (weights 75/64, -25/384, 3/640) in place of the two-point ones.
 #include "kernels.h"
 
 namespace pic {
@@ -36,6 +38,23 @@ __device__ __forceinline__ Node3 node3(int64_t k, int fn0, int fn1, int fn2)
     r.kp = k + (l + 1 < fn2 ? sz : -(int64_t)(fn2 - 1) * sz);
     r.km = k + (l > 0 ? -sz : (int64_t)(fn2 - 1) * sz);
     return r;
+}
+
+// Sixth-order staggered difference of f along the axis with node index i of
+// n (stride between neighbours `stride`), periodic: forward (the half point
+// after node k) or backward (the half point before it).
+template <typename T>
+__device__ __forceinline__ T d6(const gptr_t<const T> f, int64_t k, int64_t stride, int i, int n, bool fwd)
+{
+    auto at = [&](int o) {
+        int ii = i + o;
+        ii += ii < 0 ? n : 0;
+        ii -= ii >= n ? n : 0;
+        return f[k + (int64_t)(ii - i) * stride];
+    };
+    const T c1 = T(75.0 / 64.0), c2 = T(-25.0 / 384.0), c3 = T(3.0 / 640.0);
+    return fwd ? c1 * (at(1) - at(0)) + c2 * (at(2) - at(-1)) + c3 * (at(3) - at(-2))
+               : c1 * (at(0) - at(-1)) + c2 * (at(1) - at(-2)) + c3 * (at(2) - at(-3));
 }
 
 // pass 1 (PASS = 0) and pass 3 (PASS = 2): B -= h curl E
@@ -72,9 +91,20 @@ __global__ __launch_bounds__(kMB) void k_maxwell3d_b(const SimDev<T> *__restrict
                 esum = (double)ex * ex + (double)ey * ey + (double)ez * ez + (double)bx * bx +
                        (double)by * by + (double)bz * bz;
             }
-            glb(Fn[3])[k] = bx - h * ((Ez[nd.jp] - ez) * iy - (Ey[nd.kp] - ey) * iz);
-            glb(Fn[4])[k] = by - h * ((Ex[nd.kp] - ex) * iz - (Ez[nd.ip] - ez) * ix);
-            glb(Fn[5])[k] = bz - h * ((Ey[nd.ip] - ey) * ix - (Ex[nd.jp] - ex) * iy);
+            if (S.morder == 6) {
+                const int i = (int)(k % fn0), j = (int)((k / fn0) % fn1), l = (int)(k / ((int64_t)fn0 * fn1));
+                const int64_t sy = fn0, sz = (int64_t)fn0 * fn1;
+                auto dx = [&](gptr_t<const T> f) { return d6<T>(f, k, 1, i, fn0, true); };
+                auto dy = [&](gptr_t<const T> f) { return d6<T>(f, k, sy, j, fn1, true); };
+                auto dz = [&](gptr_t<const T> f) { return d6<T>(f, k, sz, l, fn2, true); };
+                glb(Fn[3])[k] = bx - h * (dy(Ez) * iy - dz(Ey) * iz);
+                glb(Fn[4])[k] = by - h * (dz(Ex) * iz - dx(Ez) * ix);
+                glb(Fn[5])[k] = bz - h * (dx(Ey) * ix - dy(Ex) * iy);
+            } else {
+                glb(Fn[3])[k] = bx - h * ((Ez[nd.jp] - ez) * iy - (Ey[nd.kp] - ey) * iz);
+                glb(Fn[4])[k] = by - h * ((Ex[nd.kp] - ex) * iz - (Ez[nd.ip] - ez) * ix);
+                glb(Fn[5])[k] = bz - h * ((Ey[nd.ip] - ey) * ix - (Ex[nd.jp] - ex) * iy);
+            }
         }
         if (PASS == 0) {
 #pragma unroll
@@ -116,6 +146,20 @@ __global__ __launch_bounds__(kMB) void k_maxwell3d_e(const SimDev<T> *__restrict
         const gptr_t<const T> Bx = glb((const T *)Fn[3]), By = glb((const T *)Fn[4]),
                               Bz = glb((const T *)Fn[5]);
         const T bx = Bx[k], by = By[k], bz = Bz[k];
+        if (S.morder == 6) {
+            const int i = (int)(k % fn0), j = (int)((k / fn0) % fn1), l = (int)(k / ((int64_t)fn0 * fn1));
+            const int64_t sy = fn0, sz = (int64_t)fn0 * fn1;
+            auto dx = [&](gptr_t<const T> f) { return d6<T>(f, k, 1, i, fn0, false); };
+            auto dy = [&](gptr_t<const T> f) { return d6<T>(f, k, sy, j, fn1, false); };
+            auto dz = [&](gptr_t<const T> f) { return d6<T>(f, k, sz, l, fn2, false); };
+            glb(Fn[0])[k] = glb((const T *)Fc[0])[k] + dt * (dy(Bz) * iy - dz(By) * iz - glb((const T *)Jc[0])[k]);
+            glb(Fn[1])[k] = glb((const T *)Fc[1])[k] + dt * (dz(Bx) * iz - dx(Bz) * ix - glb((const T *)Jc[1])[k]);
+            glb(Fn[2])[k] = glb((const T *)Fc[2])[k] + dt * (dx(By) * ix - dy(Bx) * iy - glb((const T *)Jc[2])[k]);
+            glb(Jn[0])[k] = T(0);
+            glb(Jn[1])[k] = T(0);
+            glb(Jn[2])[k] = T(0);
+            continue;
+        }
         glb(Fn[0])[k] = glb((const T *)Fc[0])[k] +
                         dt * ((bz - Bz[nd.jm]) * iy - (by - By[nd.km]) * iz - glb((const T *)Jc[0])[k]);
         glb(Fn[1])[k] = glb((const T *)Fc[1])[k] +

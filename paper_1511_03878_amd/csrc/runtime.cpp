@@ -113,7 +113,6 @@ int validate_desc(const PicSimDesc &d, std::string &why)
         return PIC_EINVAL;
     }
     if (d.maxwell_order == 6) {
-        if (d.ndim != 2) { why = "the sixth-order field solver is built for 2-D boxes only"; return PIC_ENOTSUP; }
         for (int a = 0; a < d.ndim; ++a)
             if (!d.periodic[a]) { why = "the sixth-order field solver needs every axis periodic"; return PIC_EINVAL; }
         // its largest modified wave number per axis is (2 / d) (75/64 + 25/384 + 3/640)

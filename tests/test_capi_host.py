@@ -73,7 +73,7 @@ def _desc(**kw):
     (dict(maxwell_order=6, periodic=(0, 1, 1)), -1),  # sixth order needs periodic axes
     (dict(maxwell_order=6, dt=0.06), -1),    # within the Yee limit, above the sixth-order one
     (dict(maxwell_order=6, ndim=3, n=(16, 16, 16), patch=(8, 8, 8), d=(0.1, 0.1, 0.1),
-          dt=0.04), -9),                     # built for 2-D only
+          dt=0.05), -1),                     # 3-D: within the Yee limit, above the sixth-order one
 ])
 def test_bad_descriptors_fail_before_device_work(lib, bad, code):
     h = C.c_void_p()

@@ -151,3 +151,44 @@ def test_sixth_order_dispersion_beats_yee():
         g.step(nst)
         err[order] = np.abs(g.field("Ez") - ph(i * d, j * d, nst * dt)).max()
     assert err[6] < 0.05 * err[2], err
+
+
+def test_sixth_order_3d_vacuum_fields_fp64():
+    _announce("sixth-order vacuum fields 3-D 32x16x16 fp64, 12 steps")
+    from paper_1511_03878_amd.sim import Sim
+    n, d = (32, 16, 16), (0.1, 0.12, 0.11)
+    grid = dict(ndim=3, n=list(n), d=list(d), dt=W.cfl_dt(d, 0.9 / S6), patch=[8, 8, 8],
+                periodic=[1, 1, 1], q=-1.0, m=1.0)
+    g = Sim(grid, 64, maxwell_order=6)
+    g.set_particles([np.zeros(0)] * 3, [np.zeros(0)] * 3, np.zeros(0))
+    o = oracle.Sim(grid)
+    o.set_maxwell_order(6)
+    rng = np.random.default_rng(31)
+    for c in ("Ex", "Ey", "Ez", "Bx", "By", "Bz"):
+        f = rng.standard_normal((n[2], n[1], n[0]))
+        g.set_field(c, f)
+        o.set_field(c, f)
+    g.step(12)
+    o.step(12)
+    e, b = compare_fields(g, o)
+    assert e < 1e-12 and b < 1e-12, (e, b)
+
+
+def test_sixth_order_3d_pic_fp64_and_fp32():
+    _announce("sixth-order 3-D blob 32x16x16 fp64 6 steps, fp32 1 step")
+    wl = W.blob_3d(n=(32, 16, 16), d=(0.1, 0.1, 0.1), patch=(8, 8, 8), ppc0=2, blob_radius=4.0,
+                   T_keV=20.0, cfl=0.9 / S6)
+    g = gpu_sim(wl, 64, maxwell_order=6)
+    g.step(6)
+    o = _oracle6(wl, 6)
+    e, b = compare_fields(g, o)
+    assert e < 1e-11 and b < 1e-11, (e, b)
+    assert np.array_equal(g.counts(), o.counts())
+    assert np.array_equal(g.particles()[3], o.particles()[3])
+    w32 = W.to_float32_state(wl)
+    g = gpu_sim(w32, 32, maxwell_order=6)
+    g.step(1)
+    o = _oracle6(w32, 1)
+    e, b = compare_fields(g, o)
+    assert e < 1e-5 and b < 1e-5, (e, b)
+    assert np.array_equal(g.counts(), o.counts())
