@@ -24,16 +24,27 @@ namespace pic {
 
 namespace {
 
+// Workgroups are dispatched to the 8 XCDs in turn (workgroup b to XCD b % 8),
+// and each XCD has its own L2.  Renumbering the workgroups XCD-major gives
+// every XCD a contiguous band of tiles, so the halo rows and columns a tile
+// shares with its neighbours are mostly fetched into the same L2.
+__device__ __forceinline__ int xcd_block()
+{
+    const int g = (int)gridDim.x, b = (int)blockIdx.x;
+    return (g & 7) ? b : (b & 7) * (g >> 3) + (b >> 3);
+}
+
 template <typename T, int TX, int TY>
 __global__ __launch_bounds__(256) void k_maxwell2d(const SimDev<T> *__restrict__ sims, int nsims,
                                                    const int *__restrict__ tile_prefix, int total)
 {
     constexpr int W = TX + 3, H = TY + 3, NB = W * H;
-    __shared__ T sE[3][NB], sB[3][NB], sJ[3][NB];
+    constexpr int NE = (TX + 1) * (TY + 1);  // nodes of sweep 2
+    __shared__ T sE[3][NB], sB[3][NB];
     __shared__ double s_red[4];
     const int tid = threadIdx.x;
 
-    for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    for (int tile = xcd_block(); tile < total; tile += gridDim.x) {
         const int s = find_sim(tile_prefix, nsims, tile);
         const SimDev<T> &S = sims[s];
         if (!glb(S.st)->active || S.morder == 6) continue;
@@ -49,37 +60,58 @@ __global__ __launch_bounds__(256) void k_maxwell2d(const SimDev<T> *__restrict__
         T *const *Fn = S.F[(stepn + 1) & 1];
 
         // ---- load nodes [X0-1, X0+TX+1] x [Y0-1, Y0+TY+1] -------------------
-        // all loads of the tile are issued before the first LDS write, so each
-        // thread keeps NIT x 9 requests in flight
-        constexpr int NIT = (NB + 255) / 256;
-        T v[NIT][9];
-        double esum = 0.0;
-#pragma unroll
-        for (int r = 0; r < NIT; ++r) {
-            const int t = tid + 256 * r;
-            const int a = t % W, b = t / W;
+        // All loads of the tile are issued before the first LDS write, from an
+        // index that is always in range (a node that does not exist reads node
+        // 0 and the value is dropped afterwards), so no load sits behind a
+        // branch and each thread keeps all its requests in flight.  J is read
+        // straight into the registers of the thread that uses it in sweep 2.
+        // staggering: Ex (d,p) Ey (p,d) Ez (p,p) Bx (p,d) By (d,p) Bz (d,d)
+        struct Idx {
+            int64_t dp, pd, pp, dd;
+        };
+        auto node_idx = [&](int a, int b) {
             const int gi = X0 - 1 + a, gj = Y0 - 1 + b;
             // nodes more than one past the last stored node feed no update
             // (tiles may be wider than the grid); they stay zero
-            const bool need = t < NB && gi <= fn0 + 1 && gj <= fn1 + 1;
+            const bool need = gi <= fn0 + 1 && gj <= fn1 + 1;
             const int ip = need ? axis_node(gi, n0, per0, 0) : -1;
             const int id = need ? axis_node(gi, n0, per0, 1) : -1;
             const int jp = need ? axis_node(gj, n1, per1, 0) : -1;
             const int jd = need ? axis_node(gj, n1, per1, 1) : -1;
-            // staggering: Ex (d,p) Ey (p,d) Ez (p,p) Bx (p,d) By (d,p) Bz (d,d)
-            const int64_t kdp = (id >= 0 && jp >= 0) ? id + (int64_t)fn0 * jp : -1;
-            const int64_t kpd = (ip >= 0 && jd >= 0) ? ip + (int64_t)fn0 * jd : -1;
-            const int64_t kpp = (ip >= 0 && jp >= 0) ? ip + (int64_t)fn0 * jp : -1;
-            const int64_t kdd = (id >= 0 && jd >= 0) ? id + (int64_t)fn0 * jd : -1;
-            v[r][0] = kdp >= 0 ? glb(Fc[0])[kdp] : T(0);
-            v[r][1] = kpd >= 0 ? glb(Fc[1])[kpd] : T(0);
-            v[r][2] = kpp >= 0 ? glb(Fc[2])[kpp] : T(0);
-            v[r][3] = kpd >= 0 ? glb(Fc[3])[kpd] : T(0);
-            v[r][4] = kdp >= 0 ? glb(Fc[4])[kdp] : T(0);
-            v[r][5] = kdd >= 0 ? glb(Fc[5])[kdd] : T(0);
-            v[r][6] = kdp >= 0 ? glb(Jc[0])[kdp] : T(0);
-            v[r][7] = kpd >= 0 ? glb(Jc[1])[kpd] : T(0);
-            v[r][8] = kpp >= 0 ? glb(Jc[2])[kpp] : T(0);
+            Idx r;
+            r.dp = (id >= 0 && jp >= 0) ? id + (int64_t)fn0 * jp : -1;
+            r.pd = (ip >= 0 && jd >= 0) ? ip + (int64_t)fn0 * jd : -1;
+            r.pp = (ip >= 0 && jp >= 0) ? ip + (int64_t)fn0 * jp : -1;
+            r.dd = (id >= 0 && jd >= 0) ? id + (int64_t)fn0 * jd : -1;
+            return r;
+        };
+        auto ld = [&](T *f, int64_t k) {
+            const T x = glb(f)[k >= 0 ? k : 0];
+            return k >= 0 ? x : T(0);
+        };
+        constexpr int NIT = (NB + 255) / 256;
+        constexpr int NJT = (NE + 255) / 256;
+        T v[NIT][6];
+        T jv[NJT][3];
+        double esum = 0.0;
+#pragma unroll
+        for (int r = 0; r < NIT; ++r) {
+            const int t = min(tid + 256 * r, NB - 1);
+            const Idx q = node_idx(t % W, t / W);
+            v[r][0] = ld(Fc[0], q.dp);
+            v[r][1] = ld(Fc[1], q.pd);
+            v[r][2] = ld(Fc[2], q.pp);
+            v[r][3] = ld(Fc[3], q.pd);
+            v[r][4] = ld(Fc[4], q.dp);
+            v[r][5] = ld(Fc[5], q.dd);
+        }
+#pragma unroll
+        for (int r = 0; r < NJT; ++r) {
+            const int t = min(tid + 256 * r, NE - 1);
+            const Idx q = node_idx(1 + t % (TX + 1), 1 + t / (TX + 1));
+            jv[r][0] = ld(Jc[0], q.dp);
+            jv[r][1] = ld(Jc[1], q.pd);
+            jv[r][2] = ld(Jc[2], q.pp);
         }
 #pragma unroll
         for (int r = 0; r < NIT; ++r) {
@@ -90,7 +122,6 @@ __global__ __launch_bounds__(256) void k_maxwell2d(const SimDev<T> *__restrict__
             const bool own = a >= 1 && a <= TX && b >= 1 && b <= TY && gi < fn0 && gj < fn1;
             sE[0][t] = v[r][0]; sE[1][t] = v[r][1]; sE[2][t] = v[r][2];
             sB[0][t] = v[r][3]; sB[1][t] = v[r][4]; sB[2][t] = v[r][5];
-            sJ[0][t] = v[r][6]; sJ[1][t] = v[r][7]; sJ[2][t] = v[r][8];
             if (own) {
                 // invalid (outside) nodes were loaded as zero, so they add nothing
 #pragma unroll
@@ -142,12 +173,15 @@ __global__ __launch_bounds__(256) void k_maxwell2d(const SimDev<T> *__restrict__
         }
 
         // ---- sweep 2: E^{n+1} on a in [1, TX+1], b in [1, TY+1] -------------
-        for (int t = tid; t < (TX + 1) * (TY + 1); t += 256) {
+#pragma unroll
+        for (int r = 0; r < NJT; ++r) {
+            const int t = tid + 256 * r;
+            if (t >= NE) break;
             const int a = 1 + t % (TX + 1), b = 1 + t / (TX + 1);
             const int c = b * W + a;
-            sE[0][c] += dt * ((sB[2][c] - sB[2][c - W]) * iy - sJ[0][c]);
-            sE[1][c] += dt * (-(sB[2][c] - sB[2][c - 1]) * ix - sJ[1][c]);
-            sE[2][c] += dt * ((sB[1][c] - sB[1][c - 1]) * ix - (sB[0][c] - sB[0][c - W]) * iy - sJ[2][c]);
+            sE[0][c] += dt * ((sB[2][c] - sB[2][c - W]) * iy - jv[r][0]);
+            sE[1][c] += dt * (-(sB[2][c] - sB[2][c - 1]) * ix - jv[r][1]);
+            sE[2][c] += dt * ((sB[1][c] - sB[1][c - 1]) * ix - (sB[0][c] - sB[0][c - W]) * iy - jv[r][2]);
         }
         __syncthreads();
 
@@ -205,7 +239,7 @@ __global__ __launch_bounds__(256) void k_maxwell2d_hi(const SimDev<T> *__restric
     __shared__ double s_red[4];
     const int tid = threadIdx.x;
     constexpr T c1 = T(75.0 / 64.0), c2 = T(-25.0 / 384.0), c3 = T(3.0 / 640.0);
-    for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    for (int tile = xcd_block(); tile < total; tile += gridDim.x) {
         const int s = find_sim(tile_prefix, nsims, tile);
         const SimDev<T> &S = sims[s];
         if (!glb(S.st)->active || S.morder != 6) continue;
