@@ -1172,9 +1172,33 @@ BatchImpl<T>::~BatchImpl()
 {
     free_graph();
     if (capture_stream) (void)hipStreamDestroy(capture_stream);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side_stream) (void)hipStreamDestroy(side_stream);
     if (!solo_mode)
         for (auto *m : members) m->batch = nullptr;
     free_tables();
+}
+
+// The second stream (default priority) and the two events that order it.
+template <typename T>
+bool BatchImpl<T>::ensure_side()
+{
+    if (side_stream) return true;
+    if (side_failed) return false;
+    if (hipStreamCreateWithFlags(&side_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ev_join, hipEventDisableTiming) != hipSuccess) {
+        if (side_stream) (void)hipStreamDestroy(side_stream);
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+        side_stream = nullptr;
+        ev_fork = ev_join = nullptr;
+        side_failed = true;
+        (void)hipGetLastError();
+        return false;
+    }
+    return true;
 }
 
 template <typename T>
@@ -1412,17 +1436,29 @@ void BatchImpl<T>::launch_one_step()
 {
     const int ns = (int)members.size();
     Timing &tm = timing();
-    if (nd == 3) {
+    if (nd == 3)
         launch_particles3d<T>(sims_d, items_d, nitems_d, head_d, grid_particles, block, maxP0, maxP1,
                               maxP2, stream, tm.pair(1));
-        launch_maxwell3d<T>(sims_d, ns, tile_prefix_d, total_tiles, grid_maxwell, stream, tm.pair(2));
-    } else {
+    else
         launch_particles<T>(sims_d, items_d, nitems_d, head_d, grid_particles, block, maxP0, maxP1,
                             patch_const, stream, tm.pair(1));
-        launch_maxwell<T>(sims_d, ns, tile_prefix_d, total_tiles, grid_maxwell, tile_preset, hi_order,
-                          stream, tm.pair(2));
+    // the field update (fields, currents, tile energies) and the re-binning
+    // (particles, counts) touch disjoint data: run them side by side
+    const bool fork = ensure_side();
+    hipStream_t fs = stream;
+    if (fork) {
+        hipcheck(hipEventRecord(ev_fork, stream), "fork");
+        hipcheck(hipStreamWaitEvent(side_stream, ev_fork, 0), "fork");
+        fs = side_stream;
     }
+    if (nd == 3)
+        launch_maxwell3d<T>(sims_d, ns, tile_prefix_d, total_tiles, grid_maxwell, fs, tm.pair(2));
+    else
+        launch_maxwell<T>(sims_d, ns, tile_prefix_d, total_tiles, grid_maxwell, tile_preset, hi_order, fs,
+                          tm.pair(2));
+    if (fork) hipcheck(hipEventRecord(ev_join, side_stream), "join");
     launch_rebin<T>(sims_d, ns, patch_prefix_d, total_patches, grid_rebin, nd, stream, tm.pair(3));
+    if (fork) hipcheck(hipStreamWaitEvent(stream, ev_join, 0), "join");
     launch_close_queue_pass();
 }
 

@@ -206,6 +206,12 @@ struct BatchImpl : BatchBase {
     bool use_graph = false, graph_failed = false;
     hipGraphExec_t graph_exec = nullptr;
     hipStream_t capture_stream = nullptr;
+    // the field update runs on a second stream beside the re-binning (they
+    // share no data); forked after the particle kernel, joined before the close
+    hipStream_t side_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    bool side_failed = false;
+    bool ensure_side();
     void free_graph();
     bool capture_graph();
 
