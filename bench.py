@@ -32,9 +32,40 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_PARTICLE_STEP = {(2, 32): 44, (2, 64): 88, (3, 32): 52, (3, 64): 104}
 
 
+# per-workload options applied to the simulation (and to the oracle for the
+# CPU baseline): descriptor settings, moving window, merging
+S6 = 75 / 64 + 25 / 384 + 3 / 640   # the sixth-order solver's stability factor
+
+
+def _options(name, wl):
+    if name == "lwfa_window":
+        return {"window": (300, 1.0, (wl["ppc"], 1), wl["column_density"]), "merge": (100, 8, 8)}
+    if name == "periodic_hi":
+        return {"tune": {"maxwell_order": 6}}
+    return {}
+
+
+def _apply(sim, opts, oracle_side=False):
+    if "window" in opts:
+        sim.set_window(*opts["window"])
+    if "merge" in opts:
+        sim.set_merge(*opts["merge"])
+    if oracle_side and opts.get("tune", {}).get("maxwell_order") == 6:
+        sim.set_maxwell_order(6)
+
+
 def _workload(name, steps):
     from paper_1511_03878_amd import workloads as W
-    if name == "lwfa":
+    if name == "lwfa_window":
+        wl = W.lwfa_2d(nsteps=max(steps, 1))
+        desc = ("lwfa_2d with a moving window from step 300 (v = c, jumps of one 32-cell patch column, "
+                "4 ppc cold plasma of the profile injected) and particle merging every 100 steps "
+                "(cells above 8 particles, 8 k-means rounds): 4096x1024 cells, 16.5M particles")
+    elif name == "periodic_hi":
+        wl = W.uniform_2d(n=(4096, 1024), patch=(32, 32), ppc=4, T_keV=1.0, cfl=0.9 / S6)
+        desc = ("uniform_2d with the sixth-order field solver: 4096x1024 cells (dx=0.1 c/w_p), "
+                "32x32-cell patches, 4 ppc, 1 keV, periodic (16.8M particles)")
+    elif name == "lwfa":
         wl = W.lwfa_2d(nsteps=max(steps, 1))
         desc = ("lwfa_2d: 4096x1024 cells (dx=lambda/32, dy=lambda/8), 32x32-cell patches, "
                 "4 ppc electrons behind a 2->12 lambda ramp to 0.003 n_c (16.5M particles), "
@@ -54,6 +85,14 @@ def _workload(name, steps):
     else:
         raise SystemExit(f"unknown workload {name}")
     return wl, desc
+
+
+def _sim_for(wl, name, precision):
+    from paper_1511_03878_amd.sim import Sim
+    opts = _options(name, wl)
+    sim = Sim.from_workload(wl, precision=precision, **opts.get("tune", {}))
+    _apply(sim, opts)
+    return sim
 
 
 def _kernel_source_sha():
@@ -96,6 +135,7 @@ def _cpu_baseline(name, budget_s=25.0):
     o.set_particles(wl["x"], wl["u"], wl["w"])
     if wl.get("laser"):
         o.set_laser(ey=wl["laser"]["ey"], ez=wl["laser"].get("ez"))
+    _apply(o, _options(name, wl), oracle_side=True)
     n = wl["w"].size
     t0 = time.perf_counter()
     steps = 0
@@ -217,12 +257,12 @@ def main():
     print(f"[bench] workload ready: {desc}", file=sys.stderr, flush=True)
 
     if args.warmup > 0 and wl["grid"]["ndim"] == 2:
-        w = Sim.from_workload(wl, precision=args.precision)
+        w = _sim_for(wl, args.workload, args.precision)
         w.step(args.warmup)
         w.sync()
         w.close()
         del w
-    sim = Sim.from_workload(wl, precision=args.precision)
+    sim = _sim_for(wl, args.workload, args.precision)
     if args.warmup > 0 and wl["grid"]["ndim"] == 3:
         # the 3-D box is statistically stationary: warm up on the timed instance
         sim.step(args.warmup)
