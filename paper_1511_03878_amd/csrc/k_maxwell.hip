@@ -339,14 +339,16 @@ void maxwell_tile(int preset, int &tx, int &ty)
 
 template <typename T>
 void launch_maxwell(const SimDev<T> *sims, int nsims, const int *tile_prefix, int total_tiles,
-                    int grid, int preset, bool hi_order, hipStream_t st, Ev2 ev)
+                    int grid, int preset, bool yee, bool hi_order, hipStream_t st, Ev2 ev)
 {
     hipEvent_t stop1 = hi_order ? nullptr : ev.stop;
 #define PIC_MW(TX, TY)                                                                          \
     hipExtLaunchKernelGGL((k_maxwell2d<T, TX, TY>), dim3(grid), dim3(256), 0, st, ev.start,    \
                           stop1, 0, sims, nsims, tile_prefix, total_tiles)
     const int p = (preset >= 0 && preset < 6) ? preset : 0;
-    if constexpr (sizeof(T) == 4) {
+    if (!yee) {
+        // every simulation of the batch uses the sixth-order solver
+    } else if constexpr (sizeof(T) == 4) {
         switch (p) {
         case 1: PIC_MW(64, 8); break;
         case 2: PIC_MW(128, 8); break;
@@ -370,8 +372,8 @@ void launch_maxwell(const SimDev<T> *sims, int nsims, const int *tile_prefix, in
         // the sixth-order simulations of the batch (the Yee kernel skipped their tiles)
         int tx, ty;
         maxwell_tile<T>(preset, tx, ty);
-        hipLaunchKernelGGL((k_maxwell2d_hi<T, 0>), dim3(grid), dim3(256), 0, st, sims, nsims, tile_prefix,
-                           total_tiles, tx, ty);
+        hipExtLaunchKernelGGL((k_maxwell2d_hi<T, 0>), dim3(grid), dim3(256), 0, st, yee ? nullptr : ev.start,
+                              nullptr, 0, sims, nsims, tile_prefix, total_tiles, tx, ty);
         hipLaunchKernelGGL((k_maxwell2d_hi<T, 1>), dim3(grid), dim3(256), 0, st, sims, nsims, tile_prefix,
                            total_tiles, tx, ty);
         hipExtLaunchKernelGGL((k_maxwell2d_hi<T, 2>), dim3(grid), dim3(256), 0, st, nullptr, ev.stop, 0,
@@ -381,9 +383,9 @@ void launch_maxwell(const SimDev<T> *sims, int nsims, const int *tile_prefix, in
 
 template void maxwell_tile<float>(int, int &, int &);
 template void maxwell_tile<double>(int, int &, int &);
-template void launch_maxwell<float>(const SimDev<float> *, int, const int *, int, int, int, bool,
+template void launch_maxwell<float>(const SimDev<float> *, int, const int *, int, int, int, bool, bool,
                                     hipStream_t, Ev2);
-template void launch_maxwell<double>(const SimDev<double> *, int, const int *, int, int, int, bool,
+template void launch_maxwell<double>(const SimDev<double> *, int, const int *, int, int, int, bool, bool,
                                      hipStream_t, Ev2);
 
 }  // namespace pic

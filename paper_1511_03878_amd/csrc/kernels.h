@@ -78,11 +78,11 @@ void launch_merge(const SimDev<T> *sim, int npatch, int cmax, int iters, int for
 
 // Fused Yee update (half B, E, half B) with face conditions; clears the
 // other J buffer and accumulates the field energy of the incoming E, B.
-// hi_order: the batch holds simulations with the sixth-order solver, which
-// take three further passes.
+// yee: the batch holds simulations with the Yee solver; hi_order: it holds
+// simulations with the sixth-order solver, which take three further passes.
 template <typename T>
 void launch_maxwell(const SimDev<T> *sims, int nsims, const int *tile_prefix, int total_tiles,
-                    int grid, int preset, bool hi_order, hipStream_t st, Ev2 ev = {});
+                    int grid, int preset, bool yee, bool hi_order, hipStream_t st, Ev2 ev = {});
 template <typename T>
 void maxwell_tile(int preset, int &tx, int &ty);
 

@@ -1299,8 +1299,11 @@ void BatchImpl<T>::build_tables()
     std::vector<int> pp(ns + 1, 0), tp(ns + 1, 0);
     tile_preset = 0;
     for (auto *m : members) if (m->desc.field_tile) tile_preset = m->desc.field_tile;
-    hi_order = false;
-    for (auto *m : members) hi_order = hi_order || m->desc.maxwell_order == 6;
+    hi_order = yee_any = false;
+    for (auto *m : members) {
+        hi_order = hi_order || m->desc.maxwell_order == 6;
+        yee_any = yee_any || m->desc.maxwell_order != 6;
+    }
     int tx, ty;
     maxwell_tile<T>(tile_preset, tx, ty);
     maxP0 = maxP1 = maxP2 = 1;
@@ -1454,8 +1457,8 @@ void BatchImpl<T>::launch_one_step()
     if (nd == 3)
         launch_maxwell3d<T>(sims_d, ns, tile_prefix_d, total_tiles, grid_maxwell, fs, tm.pair(2));
     else
-        launch_maxwell<T>(sims_d, ns, tile_prefix_d, total_tiles, grid_maxwell, tile_preset, hi_order, fs,
-                          tm.pair(2));
+        launch_maxwell<T>(sims_d, ns, tile_prefix_d, total_tiles, grid_maxwell, tile_preset, yee_any, hi_order,
+                          fs, tm.pair(2));
     if (fork) hipcheck(hipEventRecord(ev_join, side_stream), "join");
     launch_rebin<T>(sims_d, ns, patch_prefix_d, total_patches, grid_rebin, nd, stream, tm.pair(3));
     if (fork) hipcheck(hipStreamWaitEvent(stream, ev_join, 0), "join");

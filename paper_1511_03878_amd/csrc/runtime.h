@@ -199,6 +199,7 @@ struct BatchImpl : BatchBase {
     int maxP0 = 1, maxP1 = 1, maxP2 = 1;
     int chunk = 256, block = 256, tile_preset = 0, patch_const = 0;
     bool hi_order = false;  // some member uses the sixth-order field solver
+    bool yee_any = true;    // some member uses the Yee solver
     int grid_particles = 1, grid_maxwell = 1, grid_rebin = 1;
     Timing own_timing;
     // step batches replayed from a captured graph
