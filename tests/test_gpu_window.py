@@ -174,3 +174,19 @@ def test_window_full_size_lwfa_conserves_particles():
     assert d["particles"] == n0 - d["removed"] + injected
     assert injected > 0 and d["flags"] == 0
     assert np.unique(ids).size == ids.size
+
+
+def test_window_with_merging_and_curve_order_fp64():
+    """Merging every 10 steps (before each jump) and the Hilbert-ordered work
+    queue together with the window, small laser box, against the oracle."""
+    _announce("window + merge every 10 + curve order: lwfa 512x128 fp64, 70 steps")
+    wl = W.lwfa_2d_small(nsteps=70, ppc=8)
+    win = (5, 1.0, (2, 2), wl["column_density"])
+    g, o = _pair(wl, 64, win, patch_order=1)
+    g.set_merge(10, 6, 4)
+    o.set_merge(10, 6, 4)
+    g.step(70)
+    o.step(70)
+    assert o.window_shift >= 1 and o.merged > 0
+    _check_fp64(g, o)
+    assert g.diag()["merged"] == o.merged
