@@ -14,13 +14,14 @@
 // takes the two smallest ids of its cluster.  A patch then holds its untouched
 // particles in slot order followed by the pairs in (cell, cluster) order.
 //
-// One workgroup per patch.  The cells' member lists are built in slot order
-// in the patch's vacated-slot list (free outside the re-binning), the
-// clustering of a cell runs on one thread in FP64 in the same order of
-// operations as a plain sequential loop (no contraction into fused
-// multiply-adds), the new patch contents are assembled in the staging arrays
-// and copied back.  The pass runs between the re-binning and the step close,
-// before a window jump.
+// One workgroup per patch.  The members of every crowded cell are copied,
+// in slot order, into a contiguous run of the staging arrays (free outside
+// the re-binning), with their slots listed in the vacated-slot list; the
+// clustering of a cell runs on one thread in FP64 over that contiguous run in
+// the same order of operations as a plain sequential loop (no contraction into
+// fused multiply-adds); the untouched particles are then compacted in place
+// (in slot order) and the pairs written after them.  The pass runs between the
+// re-binning and the step close, before a window jump.
 
 #include <hip/hip_runtime.h>
 
@@ -34,6 +35,7 @@ constexpr int kMB = 256;          // threads per workgroup
 constexpr int kMaxCells = 4096;   // cells per patch (64 x 64)
 constexpr int kKMax = 16;         // clusters per cell (cmax <= 32)
 constexpr uint8_t kKeep = 0xFF;   // a particle that stays as it is
+constexpr int kAsgLDS = 32768;    // members whose clusters are also kept in LDS (per patch)
 
 // Exclusive prefix sum of a[0..n) in place (n <= kMaxCells); returns the total.
 __device__ int block_scan(int *a, int n, int *s_w)
@@ -68,25 +70,28 @@ __device__ int block_scan(int *a, int n, int *s_w)
     return total;
 }
 
-// Weighted Lloyd clustering of one cell's members (slot indices mem[0..n)
-// relative to the patch segment); writes the final cluster of every member
-// into code[].  Each round assigns a member and adds it to its cluster's sums
-// in one pass (the sums of a cluster still grow in member order), with the
-// centroids and sums held in registers (k <= kKMax).
+// Weighted Lloyd clustering of one cell's members: their data at staging
+// slots lst .. lst + n (member order), their own slots in mem[0..n) (relative
+// to the patch segment).  Each round assigns a member and adds it to its
+// cluster's sums in one pass (the sums of a cluster still grow in member
+// order), centroids and sums in registers (k <= kKMax); the final round's
+// cluster of every member goes to code[] at its own slot.
 template <typename T>
-__device__ void cluster_cell(const SimDev<T> &S, int64_t base, const int32_t *mem, int n, int k,
-                             int iters)
+__device__ void cluster_cell(const SimDev<T> &S, int64_t base, int64_t lst, const int32_t *mem, int n,
+                             int k, int iters, uint8_t *asg)
 {
 #pragma clang fp contract(off)
+    const gptr_t<const T> U0 = glb((const T *)S.su[0]) + lst, U1 = glb((const T *)S.su[1]) + lst,
+                          U2 = glb((const T *)S.su[2]) + lst, Wt = glb((const T *)S.sw) + lst;
     double cx[kKMax], cy[kKMax], cz[kKMax];
 #pragma unroll
     for (int j = 0; j < kKMax; ++j) {
         cx[j] = cy[j] = cz[j] = 0.0;
         if (j < k) {
-            const int64_t q = base + mem[(int64_t)j * n / k];
-            cx[j] = (double)glb(S.u[0])[q];
-            cy[j] = (double)glb(S.u[1])[q];
-            cz[j] = (double)glb(S.u[2])[q];
+            const int64_t q = (int64_t)j * n / k;
+            cx[j] = (double)U0[q];
+            cy[j] = (double)U1[q];
+            cz[j] = (double)U2[q];
         }
     }
     for (int it = 0; it < iters; ++it) {
@@ -94,9 +99,8 @@ __device__ void cluster_cell(const SimDev<T> &S, int64_t base, const int32_t *me
 #pragma unroll
         for (int j = 0; j < kKMax; ++j) sw[j] = sx[j] = sy[j] = sz[j] = 0.0;
         for (int i = 0; i < n; ++i) {
-            const int64_t q = base + mem[i];
-            const double ux = glb(S.u[0])[q], uy = glb(S.u[1])[q], uz = glb(S.u[2])[q];
-            const double w = glb(S.w)[q];
+            const double ux = U0[i], uy = U1[i], uz = U2[i];
+            const double w = Wt[i];
             int best = 0;
             double bd = 0.0;
 #pragma unroll
@@ -118,7 +122,10 @@ __device__ void cluster_cell(const SimDev<T> &S, int64_t base, const int32_t *me
                     sy[j] += w * uy;
                     sz[j] += w * uz;
                 }
-            if (it == iters - 1) glb(S.code)[q] = (uint8_t)best;
+            if (it == iters - 1) {
+                glb(S.code)[base + mem[i]] = (uint8_t)best;
+                if (asg) asg[i] = (uint8_t)best;
+            }
         }
 #pragma unroll
         for (int j = 0; j < kKMax; ++j)
@@ -130,28 +137,38 @@ __device__ void cluster_cell(const SimDev<T> &S, int64_t base, const int32_t *me
     }
 }
 
-// The conserving pair of cluster j (members whose code is j); writes it to
-// the staging arrays at slot `dst` and dst + 1.
+// Cluster of member i: from LDS when the patch's members fit there, else from
+// code[] at the member's slot.
 template <typename T>
-__device__ void write_pair(const SimDev<T> &S, int64_t base, const int32_t *mem, int n, int j, int64_t dst)
+__device__ __forceinline__ int member_cluster(const SimDev<T> &S, int64_t base, const int32_t *mem,
+                                              const uint8_t *asg, int i)
+{
+    return asg ? asg[i] : glb(S.code)[base + mem[i]];
+}
+
+// The conserving pair of cluster j, members' data at staging slots
+// lst .. lst + n; written to the particle arrays at slots dst, dst + 1.
+template <typename T>
+__device__ void write_pair(const SimDev<T> &S, int64_t base, int64_t lst, const int32_t *mem,
+                           const uint8_t *asg, int n, int j, int64_t dst)
 {
 #pragma clang fp contract(off)
     double W = 0.0, E = 0.0, P0 = 0.0, P1 = 0.0, P2 = 0.0, X0 = 0.0, X1 = 0.0;
     int64_t id0 = INT64_MAX, id1 = INT64_MAX;
     for (int i = 0; i < n; ++i) {
-        const int64_t q = base + mem[i];
-        if (glb(S.code)[q] != j) continue;
-        const double w = glb(S.w)[q];
-        const double ux = glb(S.u[0])[q], uy = glb(S.u[1])[q], uz = glb(S.u[2])[q];
+        if (member_cluster(S, base, mem, asg, i) != j) continue;
+        const int64_t q = lst + i;
+        const double w = glb(S.sw)[q];
+        const double ux = glb(S.su[0])[q], uy = glb(S.su[1])[q], uz = glb(S.su[2])[q];
         const double g = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
         W += w;
         E += w * g;
         P0 += w * ux;
         P1 += w * uy;
         P2 += w * uz;
-        X0 += w * (double)glb(S.x[0])[q];
-        X1 += w * (double)glb(S.x[1])[q];
-        const int64_t id = glb(S.id)[q];
+        X0 += w * (double)glb(S.sx[0])[q];
+        X1 += w * (double)glb(S.sx[1])[q];
+        const int64_t id = glb(S.sid)[q];
         if (id < id0) {
             id1 = id0;
             id0 = id;
@@ -183,11 +200,11 @@ __device__ void write_pair(const SimDev<T> &S, int64_t base, const int32_t *mem,
     for (int h = 0; h < 2; ++h) {
         const int64_t t = dst + h;
         const double sg = h == 0 ? 1.0 : -1.0;
-        for (int a = 0; a < 3; ++a) glb(S.su[a])[t] = (T)(ut * (ct * e1[a] + sg * st * e2[a]));
-        glb(S.sx[0])[t] = (T)(X0 / W);
-        glb(S.sx[1])[t] = (T)(X1 / W);
-        glb(S.sw)[t] = (T)(0.5 * W);
-        glb(S.sid)[t] = h == 0 ? id0 : id1;
+        for (int a = 0; a < 3; ++a) glb(S.u[a])[t] = (T)(ut * (ct * e1[a] + sg * st * e2[a]));
+        glb(S.x[0])[t] = (T)(X0 / W);
+        glb(S.x[1])[t] = (T)(X1 / W);
+        glb(S.w)[t] = (T)(0.5 * W);
+        glb(S.id)[t] = h == 0 ? id0 : id1;
     }
 }
 
@@ -196,8 +213,9 @@ __global__ __launch_bounds__(kMB) void k_merge2d(const SimDev<T> *__restrict__ s
                                                  int forced)
 {
     __shared__ int s_cnt[kMaxCells];   // particles per cell
-    __shared__ int s_pos[kMaxCells];   // start of the cell's member list (its end while it is built)
+    __shared__ int s_pos[kMaxCells];   // start of the cell's member run (its end while it is built)
     __shared__ int s_out[kMaxCells];   // first pair output of the cell
+    __shared__ uint8_t s_asg[kAsgLDS]; // final cluster of every member, in run order
     __shared__ int s_chunk[kMB];
     __shared__ int s_w[4];
     __shared__ int s_run;
@@ -233,12 +251,14 @@ __global__ __launch_bounds__(kMB) void k_merge2d(const SimDev<T> *__restrict__ s
             glb(S.code)[base + i] = kKeep;
         }
         __syncthreads();
-        // member lists of the cells above the threshold, one after another
+        // member runs of the cells above the threshold, one after another
         for (int c = tid; c < ncell; c += kMB) s_pos[c] = s_cnt[c] > cmax ? s_cnt[c] : 0;
         __syncthreads();
         const int heavy = block_scan(s_pos, ncell, s_w);
         if (heavy == 0) continue;
-        // ---- member lists in slot order (chunks of kMB particles) ----
+        const bool in_lds = heavy <= kAsgLDS;
+        // ---- member runs in slot order (chunks of kMB particles): slot list
+        // and a copy of the member's data in the staging arrays ----
         const gptr_t<int32_t> mem = glb(S.holes) + base;
         for (int i0 = 0; i0 < n; i0 += kMB) {
             const int i = i0 + tid;
@@ -253,7 +273,14 @@ __global__ __launch_bounds__(kMB) void k_merge2d(const SimDev<T> *__restrict__ s
                     rank += (o == c && t < tid) ? 1 : 0;
                     same += (o == c) ? 1 : 0;
                 }
-                mem[s_pos[c] + rank] = i;
+                const int at_ = s_pos[c] + rank;
+                mem[at_] = i;
+                const int64_t src = base + i, dst = base + at_;
+                glb(S.sx[0])[dst] = glb(S.x[0])[src];
+                glb(S.sx[1])[dst] = glb(S.x[1])[src];
+                for (int a = 0; a < 3; ++a) glb(S.su[a])[dst] = glb(S.u[a])[src];
+                glb(S.sw)[dst] = glb(S.w)[src];
+                glb(S.sid)[dst] = glb(S.id)[src];
             }
             __syncthreads();
             if (hv && rank == 0) s_pos[c] += same;
@@ -264,24 +291,30 @@ __global__ __launch_bounds__(kMB) void k_merge2d(const SimDev<T> *__restrict__ s
             const int nc = s_cnt[c];
             int outs = 0;
             if (nc > cmax) {
-                s_pos[c] -= nc;  // back to the list's start
+                s_pos[c] -= nc;  // back to the run's start
                 const int32_t *m = (const int32_t *)&mem[s_pos[c]];
-                cluster_cell(S, base, m, nc, k, iters);
+                uint8_t *asg = in_lds ? &s_asg[s_pos[c]] : nullptr;
+                cluster_cell(S, base, base + s_pos[c], m, nc, k, iters, asg);
                 int size[kKMax];
                 for (int j = 0; j < k; ++j) size[j] = 0;
-                for (int i = 0; i < nc; ++i) size[glb(S.code)[base + m[i]]]++;
+                for (int i = 0; i < nc; ++i) {
+                    const int cj = member_cluster(S, base, m, asg, i);
+                    if (cj < k) size[cj]++;
+                }
                 for (int j = 0; j < k; ++j) outs += size[j] >= 3 ? 2 : 0;
                 // members of clusters of one or two stay as they are
                 for (int i = 0; i < nc; ++i) {
-                    const int64_t q = base + m[i];
-                    if (size[glb(S.code)[q]] < 3) glb(S.code)[q] = kKeep;
+                    const int cj = member_cluster(S, base, m, asg, i);
+                    if (cj < k && size[cj] < 3) glb(S.code)[base + m[i]] = kKeep;
                 }
             }
             s_out[c] = outs;
         }
         __syncthreads();
         const int nout = block_scan(s_out, ncell, s_w);
-        // ---- kept particles, in slot order, to the front of the staging copy ----
+        // ---- kept particles, in slot order, compacted in place: a chunk reads
+        // its particles before any of them is written, and writes only below
+        // the next chunk's first slot ----
         if (tid == 0) s_run = 0;
         __syncthreads();
         for (int i0 = 0; i0 < n; i0 += kMB) {
@@ -289,48 +322,61 @@ __global__ __launch_bounds__(kMB) void k_merge2d(const SimDev<T> *__restrict__ s
             const bool kp = i < n && glb(S.code)[base + i] == kKeep;
             const uint64_t b = __ballot(kp);
             if (lane == 0) s_w[wave] = __popcll(b);
+            T vx0 = T(0), vx1 = T(0), vu0 = T(0), vu1 = T(0), vu2 = T(0), vw = T(0);
+            int64_t vid = 0;
+            if (kp) {
+                const int64_t src = base + i;
+                vx0 = glb(S.x[0])[src];
+                vx1 = glb(S.x[1])[src];
+                vu0 = glb(S.u[0])[src];
+                vu1 = glb(S.u[1])[src];
+                vu2 = glb(S.u[2])[src];
+                vw = glb(S.w)[src];
+                vid = glb(S.id)[src];
+            }
             __syncthreads();
             if (kp) {
                 int r = s_run + __popcll(b & lt);
                 for (int w = 0; w < wave; ++w) r += s_w[w];
-                const int64_t src = base + i, dst = base + r;
-                glb(S.sx[0])[dst] = glb(S.x[0])[src];
-                glb(S.sx[1])[dst] = glb(S.x[1])[src];
-                for (int a = 0; a < 3; ++a) glb(S.su[a])[dst] = glb(S.u[a])[src];
-                glb(S.sw)[dst] = glb(S.w)[src];
-                glb(S.sid)[dst] = glb(S.id)[src];
+                const int64_t dst = base + r;
+                glb(S.x[0])[dst] = vx0;
+                glb(S.x[1])[dst] = vx1;
+                glb(S.u[0])[dst] = vu0;
+                glb(S.u[1])[dst] = vu1;
+                glb(S.u[2])[dst] = vu2;
+                glb(S.w)[dst] = vw;
+                glb(S.id)[dst] = vid;
             }
             __syncthreads();
             if (tid == 0) s_run += s_w[0] + s_w[1] + s_w[2] + s_w[3];
             __syncthreads();
         }
         const int nkeep = s_run;
-        // ---- the pairs after them, in (cell, cluster) order ----
+        // ---- the pairs after them, in (cell, cluster) order (the members'
+        // clusters stay in code[] at their old slots until every pair is out) ----
         for (int c = tid; c < ncell; c += kMB) {
             const int nc = s_cnt[c];
             if (nc <= cmax) continue;
             const int32_t *m = (const int32_t *)&mem[s_pos[c]];
+            const uint8_t *asg = in_lds ? &s_asg[s_pos[c]] : nullptr;
+            // (without the LDS copy, members of clusters of one or two read as
+            // kKeep and are not counted: those clusters make no pair either way)
+            int size[kKMax];
+            for (int j = 0; j < k; ++j) size[j] = 0;
+            for (int i = 0; i < nc; ++i) {
+                const int cj = member_cluster(S, base, m, asg, i);
+                if (cj < k) size[cj]++;
+            }
             int64_t dst = base + nkeep + s_out[c];
             for (int j = 0; j < k; ++j) {
-                bool any = false;
-                for (int i = 0; i < nc && !any; ++i) any = glb(S.code)[base + m[i]] == j;
-                if (!any) continue;
-                write_pair(S, base, m, nc, j, dst);
+                if (size[j] < 3) continue;
+                write_pair(S, base, base + s_pos[c], m, asg, nc, j, dst);
                 dst += 2;
             }
         }
         __syncthreads();
-        // ---- back into the patch's slots ----
         const int nn = nkeep + nout;
-        for (int i = tid; i < nn; i += kMB) {
-            const int64_t q = base + i;
-            glb(S.x[0])[q] = glb(S.sx[0])[q];
-            glb(S.x[1])[q] = glb(S.sx[1])[q];
-            for (int a = 0; a < 3; ++a) glb(S.u[a])[q] = glb(S.su[a])[q];
-            glb(S.w)[q] = glb(S.sw)[q];
-            glb(S.id)[q] = glb(S.sid)[q];
-            glb(S.code)[q] = (uint8_t)kStay2;
-        }
+        for (int i = tid; i < nn; i += kMB) glb(S.code)[base + i] = (uint8_t)kStay2;
         if (tid == 0) {
             glb(S.count)[p] = nn;
             taken += n - nn;

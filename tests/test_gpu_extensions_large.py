@@ -81,3 +81,21 @@ def test_merge_pass_over_4096_patches_fp64():
     for a in range(3):
         np.testing.assert_allclose(gu[a], ou[a], rtol=1e-13, atol=1e-13)
     np.testing.assert_allclose(gw, ow, rtol=1e-14)
+
+
+def test_merge_pass_with_more_members_than_the_lds_copy_fp64():
+    """Patches of 64 x 64 cells at 9 per cell: more crowded-cell members per
+    patch (36864) than the kernel keeps in LDS, so the clusters are read back
+    from the particle codes; same result as the oracle."""
+    _announce("merge pass fp64, 128x128 cells, 64x64 patches, 9 ppc, cmax 4")
+    wl = W.uniform_2d(n=(128, 128), patch=(64, 64), ppc=9, T_keV=10.0, seed=78)
+    g = gpu_sim(wl, 64)
+    o = oracle.Sim(wl["grid"])
+    o.set_particles(wl["x"], wl["u"], wl["w"])
+    assert g.merge(4, 3) == o.merge(4, 3) > 0
+    assert np.array_equal(g.counts(), o.counts())
+    gx, gu, gw, gid = g.particles()
+    ox, ou, ow, oid = o.particles()
+    assert np.array_equal(gid, oid)
+    for a in range(3):
+        np.testing.assert_allclose(gu[a], ou[a], rtol=1e-13, atol=1e-13)
