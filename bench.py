@@ -99,7 +99,7 @@ def _kernel_source_sha():
     """Hash of the sources the particle kernel is built from."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("k_particles.hip", "pic_dev.h", "kernels.h"):
+    for f in ("k_particles.hip", "particle_common.h", "pic_dev.h", "kernels.h"):
         with open(os.path.join(ROOT, "paper_1511_03878_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

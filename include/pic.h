@@ -97,7 +97,7 @@ typedef struct {
     int32_t periodic[3];   /* 1 periodic; 0 open: Silver-Mueller fields, absorbing
                               particles (x axis only) */
     double q, m;           /* species charge and mass */
-    double capacity_factor;/* slots per patch = max(min_capacity, factor * count); 0 = 2 */
+    double capacity_factor;/* slots per patch = max(min_capacity, factor * count); 0 = 3 */
     int32_t min_capacity;  /* 0 = the mean patch occupancy (at least 64) */
     int32_t chunk;         /* max particles per work item; 0 = chosen from the load */
     int32_t block;         /* threads per particle workgroup: 256, 512 or 1024; 0 = 512 (FP32) / 1024 (FP64) */

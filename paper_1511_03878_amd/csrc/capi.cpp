@@ -380,7 +380,7 @@ int pic_estimate_bytes(const PicSimDesc *d, int64_t nparticles, int64_t laser_st
     const int64_t npatch = (int64_t)(d->n[0] / d->patch[0]) * (d->n[1] / d->patch[1]) *
                            (three ? d->n[2] / d->patch[2] : 1);
     const int64_t ndir = three ? 27 : 9;
-    const double factor = d->capacity_factor > 0.0 ? d->capacity_factor : 2.0;
+    const double factor = d->capacity_factor > 0.0 ? d->capacity_factor : 3.0;
     const int64_t mean = std::max<int64_t>(64, (nparticles + npatch - 1) / npatch);
     const int64_t floor_cap = d->min_capacity ? d->min_capacity : mean;
     // capacity policy: max(factor x count, floor) per patch, rounded up to 64

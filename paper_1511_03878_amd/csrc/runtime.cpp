@@ -129,7 +129,7 @@ template <typename T>
 SimImpl<T>::SimImpl(const PicSimDesc &d, const PicAllocator *a, hipStream_t s)
 {
     desc = d;
-    if (desc.capacity_factor == 0.0) desc.capacity_factor = 2.0;
+    if (desc.capacity_factor == 0.0) desc.capacity_factor = 3.0;
     precision = d.precision;
     stream = s;
     if (a) alloc.hook = *a;
