@@ -216,7 +216,6 @@ __global__ __launch_bounds__(kMB) void k_merge2d(const SimDev<T> *__restrict__ s
     __shared__ int s_pos[kMaxCells];   // start of the cell's member run (its end while it is built)
     __shared__ int s_out[kMaxCells];   // first pair output of the cell
     __shared__ uint8_t s_asg[kAsgLDS]; // final cluster of every member, in run order
-    __shared__ int s_chunk[kMB];
     __shared__ int s_w[4];
     __shared__ int s_run;
     const SimDev<T> &S = *sp;
@@ -257,34 +256,39 @@ __global__ __launch_bounds__(kMB) void k_merge2d(const SimDev<T> *__restrict__ s
         const int heavy = block_scan(s_pos, ncell, s_w);
         if (heavy == 0) continue;
         const bool in_lds = heavy <= kAsgLDS;
-        // ---- member runs in slot order (chunks of kMB particles): slot list
-        // and a copy of the member's data in the staging arrays ----
+        // ---- member runs in slot order, one wave of 64 consecutive slots at a
+        // time: lanes of one cell find each other with ballots, and the waves of
+        // a chunk take their places in wave order ----
         const gptr_t<int32_t> mem = glb(S.holes) + base;
         for (int i0 = 0; i0 < n; i0 += kMB) {
             const int i = i0 + tid;
             const int c = i < n ? cell_of(i) : -1;
-            s_chunk[tid] = c;
-            __syncthreads();
             const bool hv = c >= 0 && s_cnt[c] > cmax;
-            int rank = 0, same = 0;
-            if (hv) {
-                for (int t = 0; t < kMB; ++t) {
-                    const int o = s_chunk[t];
-                    rank += (o == c && t < tid) ? 1 : 0;
-                    same += (o == c) ? 1 : 0;
-                }
-                const int at_ = s_pos[c] + rank;
-                mem[at_] = i;
-                const int64_t src = base + i, dst = base + at_;
-                glb(S.sx[0])[dst] = glb(S.x[0])[src];
-                glb(S.sx[1])[dst] = glb(S.x[1])[src];
-                for (int a = 0; a < 3; ++a) glb(S.su[a])[dst] = glb(S.u[a])[src];
-                glb(S.sw)[dst] = glb(S.w)[src];
-                glb(S.sid)[dst] = glb(S.id)[src];
+            // lanes of this wave in the same crowded cell
+            uint64_t match = 0, todo = __ballot(hv);
+            while (todo) {
+                const int lead = __ffsll((unsigned long long)todo) - 1;
+                const int cl = __shfl(c, lead, 64);
+                const uint64_t m = __ballot(hv && c == cl);
+                if (hv && c == cl) match = m;
+                todo &= ~m;
             }
-            __syncthreads();
-            if (hv && rank == 0) s_pos[c] += same;
-            __syncthreads();
+            const int rank = __popcll(match & lt), same = __popcll(match);
+            for (int w = 0; w < kMB / 64; ++w) {
+                if (wave == w && hv) {
+                    const int at_ = s_pos[c] + rank;
+                    mem[at_] = i;
+                    const int64_t src = base + i, dst = base + at_;
+                    glb(S.sx[0])[dst] = glb(S.x[0])[src];
+                    glb(S.sx[1])[dst] = glb(S.x[1])[src];
+                    for (int a = 0; a < 3; ++a) glb(S.su[a])[dst] = glb(S.u[a])[src];
+                    glb(S.sw)[dst] = glb(S.w)[src];
+                    glb(S.sid)[dst] = glb(S.id)[src];
+                }
+                __syncthreads();
+                if (wave == w && hv && rank == 0) s_pos[c] += same;
+                __syncthreads();
+            }
         }
         // ---- clustering, one thread per crowded cell ----
         for (int c = tid; c < ncell; c += kMB) {
