@@ -31,7 +31,9 @@
  * kept in cell units xi = x / dx, global, in FP64.
  *
  * Functions follow the step order: gather, Boris, move, deposit, boundary,
- * Maxwell, re-bin.  Everything is plain loops in FP64.
+ * Maxwell, re-bin; then the options of the step's end: particle merging
+ * (section 3.2) and the moving window (sections 2.1, 2.3), and the
+ * sixth-order field solver (section 2.1).  Everything is plain loops in FP64.
  */
 #include <math.h>
 #include <stdint.h>
