@@ -81,3 +81,29 @@ def test_3d_batch_with_yee_and_sixth_order_fp64():
         o.step(8)
         e, bb = compare_fields(g, o)
         assert e < 1e-12 and bb < 1e-12, (e, bb)
+
+
+def test_autotune_with_window_and_merging_restores_state(tmp_path):
+    """The tuner's trial steps jump the window and merge; the state it
+    restores afterwards is the one it started from, and the run then
+    continues to agree with the oracle (FP64)."""
+    _announce("autotune with window + merging, lwfa 512x128 fp64")
+    wl = W.lwfa_2d_small(nsteps=200, ppc=8)
+    win = (0, 1.0, (2, 2), wl["column_density"])
+    g = gpu_sim(wl, 64)
+    g.set_window(*win)
+    g.set_merge(5, 6, 4)
+    o = oracle.Sim(wl["grid"])
+    o.set_particles(wl["x"], wl["u"], wl["w"])
+    o.set_laser(ey=wl["laser"]["ey"])
+    o.set_window(*win)
+    o.set_merge(5, 6, 4)
+    g.step(30)
+    before = g.save_state()
+    g.autotune(steps=40, cache=str(tmp_path / "tune.txt"))
+    assert g.save_state() == before
+    g.step(20)
+    o.step(50)
+    assert o.window_shift >= 1 and o.merged > 0
+    _check(g, o)
+    assert g.diag()["removed"] == o.removed
