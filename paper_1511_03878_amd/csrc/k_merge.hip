@@ -290,12 +290,21 @@ __global__ __launch_bounds__(kMB) void k_merge2d(const SimDev<T> *__restrict__ s
                 __syncthreads();
             }
         }
-        // ---- clustering, one thread per crowded cell ----
+        // ---- clustering, one thread per crowded cell; the threads take the
+        // cells one at a time from a counter, so that a few very crowded cells
+        // do not leave one thread with all the work ----
         for (int c = tid; c < ncell; c += kMB) {
+            if (s_cnt[c] > cmax) s_pos[c] -= s_cnt[c];  // back to the run's start
+            s_out[c] = 0;
+        }
+        if (tid == 0) s_run = 0;
+        __syncthreads();
+        for (;;) {
+            const int c = atomicAdd(&s_run, 1);
+            if (c >= ncell) break;
             const int nc = s_cnt[c];
             int outs = 0;
             if (nc > cmax) {
-                s_pos[c] -= nc;  // back to the run's start
                 const int32_t *m = (const int32_t *)&mem[s_pos[c]];
                 uint8_t *asg = in_lds ? &s_asg[s_pos[c]] : nullptr;
                 cluster_cell(S, base, base + s_pos[c], m, nc, k, iters, asg);
@@ -311,8 +320,8 @@ __global__ __launch_bounds__(kMB) void k_merge2d(const SimDev<T> *__restrict__ s
                     const int cj = member_cluster(S, base, m, asg, i);
                     if (cj < k && size[cj] < 3) glb(S.code)[base + m[i]] = kKeep;
                 }
+                s_out[c] = outs;
             }
-            s_out[c] = outs;
         }
         __syncthreads();
         const int nout = block_scan(s_out, ncell, s_w);
