@@ -70,7 +70,8 @@ enum {
     PIC_EX = 0, PIC_EY = 1, PIC_EZ = 2,
     PIC_BX = 3, PIC_BY = 4, PIC_BZ = 5,
     PIC_JX = 6, PIC_JY = 7, PIC_JZ = 8,
-    PIC_RHO = 9 /* charge density of the particles on primal nodes (get only) */
+    PIC_RHO = 9 /* charge density q sum_p w_p prod_a S2(xi_p,a - node_a) of the particles on
+                   primal nodes, FP64, 2-D and 3-D (get only) */
 };
 
 typedef struct PicSim PicSim;
@@ -88,7 +89,7 @@ typedef struct {
 /* Simulation descriptor.  One electron-like species per simulation
  * (immobile neutralising ions enter only diagnostics). */
 typedef struct {
-    int32_t ndim;          /* 2 */
+    int32_t ndim;          /* 2 or 3 (3-D boxes are periodic on every axis) */
     int32_t precision;     /* 32 or 64: storage and arithmetic of fields and particles */
     int32_t n[3];          /* cells per axis, at least 4 (n[2] ignored in 2-D) */
     double d[3];           /* cell size per axis */
@@ -128,6 +129,29 @@ typedef struct {
     int64_t window_cells;  /* cells the moving window has travelled (0 without one) */
     int64_t merged;        /* particles taken out by merging so far */
 } PicDiag;
+
+/* Residuals of the discrete conservation laws (pic_residuals).  The paper
+ * states none; they check the charge-conserving deposition and the Yee
+ * update on the device's own state, in FP64, at primal nodes (div E and
+ * div J are backward differences of the staggered E and J):
+ *   gauss      = max |div E^k - (rho^k - rho^0)| / max |rho^0|, where rho^0 is
+ *                the particles' charge density when they were loaded (the
+ *                immobile neutralising ions carry -rho^0); NaN after a
+ *                checkpoint load (the load-time charge is not saved);
+ *   continuity = max |rho^k - rho^{k-1} + dt div J^{k-1/2}| / max |rho^k|,
+ *                defined only when the previous pic_residuals call on this
+ *                handle was made one step earlier (else NaN).
+ * Each ratio falls back to the plain maximum when its denominator is 0.
+ * Nodes within three cells of an open x face are left out (an absorbed
+ * particle takes its charge with it after depositing its whole move).  Merging changes the node charge of the cells it touches,
+ * so the Gauss residual is meaningful only before the first merge. */
+typedef struct {
+    int64_t step;          /* k: completed steps of the state examined */
+    double gauss;
+    double continuity;
+    double rho_max;        /* max |rho^k| */
+    double rho0_max;       /* max |rho^0| (NaN when unknown) */
+} PicResiduals;
 
 /* Per-kernel timing accumulated while timing is enabled (HIP events on the
  * handle's stream around every launch). */
@@ -238,6 +262,11 @@ int pic_particles_get(PicSim *s, double *x, double *y, double *z, double *ux, do
                       double *uz, double *w, int64_t *id, size_t count);
 int pic_patch_counts_get(PicSim *s, int32_t *counts, size_t count);
 int pic_diag_get(PicSim *s, PicDiag *out);
+/* Gauss and continuity residuals of the current state (see PicResiduals);
+ * synchronises the stream.  Each call records rho^k for the continuity
+ * residual of a call one step later.  PIC_ENOTSUP with a moving window,
+ * PIC_ESTATE while a capacity-overflow recovery is pending. */
+int pic_residuals(PicSim *s, PicResiduals *out);
 /* Energy history of completed steps first..first+n-1 (the last 4096 steps
  * are kept): U^k and K^k of step k and the particles it pushed. */
 int pic_history_get(PicSim *s, int64_t first, int64_t n, double *U, double *K, int64_t *pushed);

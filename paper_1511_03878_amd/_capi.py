@@ -22,7 +22,7 @@ COMPONENTS = ("Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz", "rho")
 EXPORTS = (
     "pic_sim_create", "pic_sim_destroy", "pic_particles_set", "pic_laser_set", "pic_fields_set",
     "pic_step", "pic_sync", "pic_fields_get", "pic_num_particles", "pic_particles_get",
-    "pic_patch_counts_get", "pic_diag_get", "pic_history_get", "pic_rebin_codes",
+    "pic_patch_counts_get", "pic_diag_get", "pic_residuals", "pic_history_get", "pic_rebin_codes",
     "pic_timing_enable", "pic_timing_get", "pic_batch_create", "pic_batch_destroy",
     "pic_batch_add", "pic_batch_remove", "pic_batch_step", "pic_batch_finished",
     "pic_batch_size", "pic_estimate_bytes", "pic_autotune", "pic_state_save", "pic_state_load",
@@ -76,6 +76,11 @@ class Diag(C.Structure):
     ]
 
 
+class Residuals(C.Structure):
+    _fields_ = [("step", C.c_int64), ("gauss", C.c_double), ("continuity", C.c_double),
+                ("rho_max", C.c_double), ("rho0_max", C.c_double)]
+
+
 class Timing(C.Structure):
     _fields_ = [("nkernels", C.c_int32), ("name", C.c_char_p * 8), ("total_ms", C.c_double * 8),
                 ("launches", C.c_int64 * 8)]
@@ -118,6 +123,7 @@ def load() -> C.CDLL:
         "pic_particles_get": (C.c_int, [_vp, _D, _D, _D, _D, _D, _D, _D, _I64, C.c_size_t]),
         "pic_patch_counts_get": (C.c_int, [_vp, _I32, C.c_size_t]),
         "pic_diag_get": (C.c_int, [_vp, C.POINTER(Diag)]),
+        "pic_residuals": (C.c_int, [_vp, C.POINTER(Residuals)]),
         "pic_history_get": (C.c_int, [_vp, C.c_int64, C.c_int64, _D, _D, _I64]),
         "pic_rebin_codes": (C.c_int, [_vp, C.POINTER(C.c_uint8), C.c_size_t]),
         "pic_timing_enable": (C.c_int, [_vp, C.c_int]),

@@ -229,6 +229,12 @@ int pic_patch_counts_get(PicSim *s, int32_t *counts, size_t count)
     });
 }
 
+int pic_residuals(PicSim *s, PicResiduals *out)
+{
+    if (!s || !out) return bad(PIC_EINVAL, "null argument");
+    return guarded([&] { s->impl->residuals(out); });
+}
+
 int pic_diag_get(PicSim *s, PicDiag *out)
 {
     if (!s || !out) return bad(PIC_EINVAL, "null argument");

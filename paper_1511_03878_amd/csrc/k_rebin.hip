@@ -449,29 +449,6 @@ __global__ void k_relayout(const SimDev<T> *__restrict__ src, const SimDev<T> *_
 
 // ---- diagnostics ------------------------------------------------------------------
 
-template <typename T>
-__global__ void k_rho(const SimDev<T> *__restrict__ S, double *__restrict__ out)
-{
-    const int p = blockIdx.x;
-    const int n = S->count[p];
-    const int64_t base = S->off[p];
-    const int ox = (p % S->np[0]) * S->P[0], oy = (p / S->np[0]) * S->P[1];
-    for (int k = threadIdx.x; k < n; k += blockDim.x) {
-        const double x = (double)S->x[0][base + k], y = (double)S->x[1][base + k];
-        const double qw = (double)S->q * (double)S->w[base + k];
-        const int ix = (int)floor(x + 0.5), iy = (int)floor(y + 0.5);
-        const double dx = x - ix, dy = y - iy;
-        const double wx[3] = {0.5 * (0.5 - dx) * (0.5 - dx), 0.75 - dx * dx, 0.5 * (0.5 + dx) * (0.5 + dx)};
-        const double wy[3] = {0.5 * (0.5 - dy) * (0.5 - dy), 0.75 - dy * dy, 0.5 * (0.5 + dy) * (0.5 + dy)};
-        for (int b = 0; b < 3; ++b)
-            for (int a = 0; a < 3; ++a) {
-                const int gi = axis_node(ox + ix + a - 1, S->n[0], S->periodic[0], 0);
-                const int gj = axis_node(oy + iy + b - 1, S->n[1], S->periodic[1], 0);
-                if (gi >= 0 && gj >= 0) atomicAdd(&out[gi + (int64_t)S->fn[0] * gj], qw * wx[a] * wy[b]);
-            }
-    }
-}
-
 __global__ void k_scatter_codes(const uint8_t *__restrict__ packed,
                                 const int64_t *__restrict__ packed_off,
                                 const int64_t *__restrict__ off, const int32_t *__restrict__ count,
@@ -520,12 +497,6 @@ void launch_relayout(const SimDev<T> *src, const SimDev<T> *dst, int npatch, hip
     hipLaunchKernelGGL((k_relayout<T>), dim3(npatch), dim3(256), 0, st, src, dst);
 }
 
-template <typename T>
-void launch_rho(const SimDev<T> *sim, int npatch, double *out, hipStream_t st)
-{
-    hipLaunchKernelGGL((k_rho<T>), dim3(npatch), dim3(256), 0, st, sim, out);
-}
-
 void launch_scatter_codes(const uint8_t *packed, const int64_t *packed_off, const int64_t *off,
                           const int32_t *count, uint8_t *code, int npatch, hipStream_t st)
 {
@@ -537,8 +508,7 @@ void launch_scatter_codes(const uint8_t *packed, const int64_t *packed_off, cons
     template void launch_close_queue<T>(const SimDev<T> *, const QueueArgs &, hipStream_t, Ev2); \
     template void launch_rebin<T>(const SimDev<T> *, int, const int *, int, int, int,            \
                                   hipStream_t, Ev2);                                             \
-    template void launch_relayout<T>(const SimDev<T> *, const SimDev<T> *, int, hipStream_t);    \
-    template void launch_rho<T>(const SimDev<T> *, int, double *, hipStream_t);
+    template void launch_relayout<T>(const SimDev<T> *, const SimDev<T> *, int, hipStream_t);
 PIC_INST(float)
 PIC_INST(double)
 #undef PIC_INST

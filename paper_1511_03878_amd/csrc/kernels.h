@@ -96,9 +96,21 @@ void launch_rebin(const SimDev<T> *sims, int nsims, const int *patch_prefix, int
 template <typename T>
 void launch_relayout(const SimDev<T> *src, const SimDev<T> *dst, int npatch, hipStream_t st);
 
-// Charge density on primal nodes (diagnostic).
+// Diagnostics (k_diag.hip).  fill_doubles clears with a kernel (safe under
+// graph capture).  launch_rho adds the particles' charge density on primal
+// nodes (2-D or 3-D) into `out` (fn[0] fn[1] fn[2] doubles, cleared by the
+// caller).  launch_residuals reduces, over nodes, the Gauss residual
+// div E - (rho - rho0), the continuity residual rho - rho_prev + dt div J, and
+// the largest |rho| and |rho0|, into out[0..3] (rho0 / rho_prev may be null:
+// that entry is then 0); `partials` holds residual_partials() doubles.
+void fill_doubles(double *p, int64_t n, double v, hipStream_t st);
 template <typename T>
-void launch_rho(const SimDev<T> *sim, int npatch, double *out, hipStream_t st);
+void launch_rho(const SimDev<T> *sim, int npatch, int ndim, double *out, hipStream_t st);
+template <typename T>
+void launch_residuals(const SimDev<T> *sim, int ndim, int64_t fsize, int fpar, int jpar,
+                      const double *rho, const double *rho0, const double *rho_prev,
+                      double *partials, double *out, hipStream_t st);
+int residual_partials();
 
 // Set the destination codes of all live particles from a packed host-supplied
 // array in (patch, slot) order.

@@ -9,6 +9,7 @@
 #include <fstream>
 
 #include <algorithm>
+#include <limits>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -324,6 +325,9 @@ void SimImpl<T>::release()
     alloc.put(nbt_d);
     alloc.put(upart);
     alloc.put(kpart);
+    alloc.put(rho0_d);
+    alloc.put(rhoprev_d);
+    rho0_d = rhoprev_d = nullptr;
     alloc.put(view_d);
     alloc.put(laser_ey);
     alloc.put(laser_ez);
@@ -519,6 +523,60 @@ void SimImpl<T>::set_particles(int64_t cnt, const double *const xs[3], const dou
     hipcheck(hipStreamSynchronize(stream), "sync");
     relayouts = 0;
     if (solo) solo->dirty = true;
+    record_rho0();
+}
+
+// Charge density of the particles as loaded: the reference of the Gauss
+// residual (the immobile neutralising ions carry its negative).
+template <typename T>
+void SimImpl<T>::record_rho0()
+{
+    if (!rho0_d) rho0_d = (double *)alloc.get(sizeof(double) * fsize);
+    fill_doubles(rho0_d, fsize, 0.0, stream);
+    launch_rho<T>(view_d, npatch, nd, rho0_d, stream);
+    hipcheck(hipGetLastError(), "rho launch");
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    rho0_valid = true;
+    alloc.put(rhoprev_d);
+    rhoprev_d = nullptr;
+    rhoprev_step = -1;
+}
+
+// Gauss and continuity residuals of the current state (see k_diag.hip).
+template <typename T>
+void SimImpl<T>::residuals(PicResiduals *out)
+{
+    if (win_on) throw Error(PIC_ENOTSUP, "residuals are not defined for a moving window");
+    const SimState s = read_state();
+    if (s.flags & kFlagPending) throw Error(PIC_ESTATE, "a re-binning is pending");
+    double *rho = (double *)alloc.get(sizeof(double) * fsize);
+    double *part = nullptr;
+    try {
+        part = (double *)alloc.get(sizeof(double) * (residual_partials() + 4));
+    } catch (...) {
+        alloc.put(rho);
+        throw;
+    }
+    fill_doubles(rho, fsize, 0.0, stream);
+    launch_rho<T>(view_d, npatch, nd, rho, stream);
+    const bool cont = rhoprev_d && rhoprev_step == s.step - 1;
+    launch_residuals<T>(view_d, nd, fsize, (int)(s.step & 1), (int)((s.step + 1) & 1), rho,
+                        rho0_valid ? rho0_d : nullptr, cont ? rhoprev_d : nullptr, part,
+                        part + residual_partials(), stream);
+    hipcheck(hipGetLastError(), "residual launch");
+    double m[4];
+    hipcheck(hipMemcpyAsync(m, part + residual_partials(), sizeof(m), hipMemcpyDeviceToHost, stream), "residuals");
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    alloc.put(part);
+    alloc.put(rhoprev_d);
+    rhoprev_d = rho;
+    rhoprev_step = s.step;
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    out->step = s.step;
+    out->gauss = rho0_valid ? (m[3] > 0.0 ? m[0] / m[3] : m[0]) : nan;
+    out->continuity = cont ? (m[2] > 0.0 ? m[1] / m[2] : m[1]) : nan;
+    out->rho_max = m[2];
+    out->rho0_max = rho0_valid ? m[3] : nan;
 }
 
 template <typename T>
@@ -652,10 +710,9 @@ void SimImpl<T>::get_field(int comp, double *h)
     if (comp < 0 || comp > 9) throw Error(PIC_EINVAL, "bad component");
     hipcheck(hipStreamSynchronize(stream), "sync");
     if (comp == PIC_RHO) {
-        if (nd != 2) throw Error(PIC_ENOTSUP, "charge density diagnostic is 2-D only");
         double *tmp = (double *)alloc.get(sizeof(double) * fsize);
-        hipcheck(hipMemsetAsync(tmp, 0, sizeof(double) * fsize, stream), "memset rho");
-        launch_rho<T>(view_d, npatch, tmp, stream);
+        fill_doubles(tmp, fsize, 0.0, stream);
+        launch_rho<T>(view_d, npatch, nd, tmp, stream);
         hipcheck(hipGetLastError(), "rho launch");
         hipcheck(hipMemcpyAsync(h, tmp, sizeof(double) * fsize, hipMemcpyDeviceToHost, stream), "rho");
         hipcheck(hipStreamSynchronize(stream), "sync");
@@ -912,6 +969,9 @@ void SimImpl<T>::state_load(const void *blob, size_t size)
     hipcheck(hipMemsetAsync(kpart, 0, sizeof(double) * npatch, stream), "restore");
     hipcheck(hipStreamSynchronize(stream), "sync");
     if (solo) solo->dirty = true;
+    // the charge at load is not part of a checkpoint
+    rho0_valid = false;
+    rhoprev_step = -1;
 }
 
 // ---------------------------------------------------------------------------
@@ -1016,14 +1076,10 @@ void SimImpl<T>::grow_capacity()
     std::vector<int32_t> cur = read_counts(), nxt(npatch);
     hipcheck(hipMemcpyAsync(nxt.data(), newcount_d, sizeof(int32_t) * npatch, hipMemcpyDeviceToHost, stream), "newcount");
     hipcheck(hipStreamSynchronize(stream), "sync");
+    // every patch is sized again by the descriptor's rule (capacity_factor
+    // times the larger of its current and its new count, never shrinking)
     std::vector<int32_t> need(npatch);
-    // a patch that overflowed is usually still filling (density compression
-    // moves with the driver): size it for twice its new count, so that it
-    // does not overflow again a few steps later
-    for (int p = 0; p < npatch; ++p) {
-        need[p] = std::max(cur[p], nxt[p]);
-        if (p < (int)cap_h.size() && nxt[p] > cap_h[p]) need[p] = (int32_t)std::min<int64_t>(2LL * nxt[p], INT32_MAX / 4);
-    }
+    for (int p = 0; p < npatch; ++p) need[p] = std::max(cur[p], nxt[p]);
     relayout(need);
 }
 

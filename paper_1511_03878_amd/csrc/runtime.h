@@ -78,6 +78,7 @@ struct SimBase {
     virtual void get_particles(double *xo[3], double *uo[3], double *wo, int64_t *ido, size_t n) = 0;
     virtual void history(int64_t first, int64_t n, double *U, double *K, int64_t *pushed) = 0;
     virtual void rebin_codes(const uint8_t *codes, size_t n) = 0;
+    virtual void residuals(PicResiduals *out) = 0;
     virtual void step(int64_t nsteps) = 0;
     virtual bool in_batch() const = 0;
     virtual size_t device_bytes() const = 0;
@@ -109,6 +110,11 @@ struct SimImpl : SimBase {
     int32_t *nbt_d = nullptr;
     double *upart = nullptr, *kpart = nullptr;
     int64_t max_tiles = 0;
+    // diagnostics: the particles' charge density at load (the immobile ions
+    // carry its negative) and at the last residual call
+    double *rho0_d = nullptr, *rhoprev_d = nullptr;
+    bool rho0_valid = false;
+    int64_t rhoprev_step = -1;
     T *laser_ey = nullptr, *laser_ez = nullptr;
     int64_t laser_steps = 0;
     // particle layout
@@ -167,6 +173,8 @@ struct SimImpl : SimBase {
     void get_particles(double *xo[3], double *uo[3], double *wo, int64_t *ido, size_t n) override;
     void history(int64_t first, int64_t n, double *U, double *K, int64_t *pushed) override;
     void rebin_codes(const uint8_t *codes, size_t n) override;
+    void residuals(PicResiduals *out) override;
+    void record_rho0();
     void step(int64_t nsteps) override;
     bool in_batch() const override { return batch != nullptr; }
     size_t device_bytes() const override { return alloc.live_bytes; }

@@ -256,6 +256,13 @@ class Sim:
         check(_capi.load().pic_diag_get(self._h, C.byref(d)))
         return {k: getattr(d, k) for k, _ in _capi.Diag._fields_}
 
+    def residuals(self) -> dict:
+        """Gauss and continuity residuals of the current state (pic_residuals);
+        the continuity entry is NaN unless the previous call was one step earlier."""
+        r = _capi.Residuals()
+        check(_capi.load().pic_residuals(self._h, C.byref(r)))
+        return {k: getattr(r, k) for k, _ in _capi.Residuals._fields_}
+
     def history(self, first: int, n: int):
         U = np.zeros(n)
         K = np.zeros(n)

@@ -167,3 +167,62 @@ def esirkepov_quadrature_3d(x0, x1, w, q, d, dt, n):
 def div_dual_3d(J, d):
     """Backward-difference divergence of dual-located currents onto primal nodes."""
     return sum((J[a] - np.roll(J[a], 1, axis=2 - a)) / d[a] for a in range(3))
+
+
+# ---------------------------------------------------------------------------
+# particle merging: weighted Lloyd k-means in momentum, one crowded cell
+
+def lloyd_cell(u, w, k, iters):
+    """Weighted Lloyd iterations on momenta u (n x 3) with weights w, k
+    centroids started at members floor(j n / k).  Every round assigns each
+    member to its nearest centroid (squared distance, lowest index on ties)
+    and moves every non-empty centroid to the weighted mean of its members,
+    summed in member order.  Returns (assignment, centroids after each
+    round)."""
+    u = np.asarray(u, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    n = len(w)
+    cen = np.array([u[(j * n) // k] for j in range(k)])
+    history = []
+    asg = np.zeros(n, dtype=np.int64)
+    for _ in range(iters):
+        d2 = ((u[:, None, :] - cen[None, :, :]) ** 2).sum(axis=2)
+        asg = np.argmin(d2, axis=1)  # first minimum: lowest index on ties
+        new = cen.copy()
+        for j in range(k):
+            sw, su = 0.0, np.zeros(3)
+            for i in range(n):
+                if asg[i] == j:
+                    sw += w[i]
+                    su = su + w[i] * u[i]
+            if sw > 0.0:
+                new[j] = su / sw
+        cen = new
+        history.append(cen.copy())
+    return asg, history
+
+
+def merge_pair(u, w, x, ids):
+    """The two particles that replace a cluster: half its weight each, at its
+    weighted mean position, with the cluster's mean Lorentz factor and total
+    momentum, split symmetrically about the momentum direction."""
+    u = np.asarray(u, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    W = w.sum()
+    g = np.sqrt(1.0 + (u * u).sum(axis=1))
+    gt = (w * g).sum() / W
+    ut = np.sqrt(max(gt * gt - 1.0, 0.0))
+    P = (w[:, None] * u).sum(axis=0)
+    pn = np.linalg.norm(P)
+    e1 = P / pn if pn > 0 else np.array([1.0, 0.0, 0.0])
+    ax = int(np.argmin(np.abs(e1)))
+    e2 = np.zeros(3)
+    e2[ax] = 1.0
+    e2 -= e2 @ e1 * e1
+    e2 /= np.linalg.norm(e2)
+    ct = min(pn / (W * ut), 1.0) if ut > 0 else 0.0
+    st = np.sqrt(1.0 - ct * ct)
+    X = (w[:, None] * np.asarray(x, dtype=np.float64)).sum(axis=0) / W
+    lo = sorted(ids)[:2]
+    return [(X, ut * (ct * e1 + st * e2), 0.5 * W, lo[0]),
+            (X, ut * (ct * e1 - st * e2), 0.5 * W, lo[1])]

@@ -38,3 +38,43 @@ def test_order_errors():
     assert e.value.code == -1
     with pytest.raises(PicError):
         sim.curve_segments([1, 2], 0)
+
+
+def _blocks_contiguous(pts, nd, b):
+    """Every aligned block of side b holds consecutive curve positions."""
+    seen = {}
+    for i, p in enumerate(pts):
+        key = tuple(v // b for v in p)
+        seen.setdefault(key, []).append(i)
+    return all(v[-1] - v[0] + 1 == len(v) for v in seen.values())
+
+
+@pytest.mark.parametrize("np_", [(2, 2, 2), (4, 4, 4), (8, 8, 8), (16, 16, 16), (16, 8, 8), (8, 32, 8),
+                                 (32, 16, 16)])
+def test_patch_order_3d_is_a_hilbert_order(np_):
+    """The product's 3-D order pinned by the defining properties of a
+    Hilbert-type curve, independently of the oracle (3-D Hilbert curves are
+    not unique; both sides use the published transpose routine): every patch
+    once, face-neighbour steps, each aligned cube of side 2^m visited as one
+    contiguous run at every level m, start at the origin, and each cube of
+    the shortest side (a square's side in the paper's 2-D figure) left at its
+    far corner along the longest axis."""
+    order = sim.patch_order(np_)
+    nx, ny = np_[0], np_[1]
+    pts = [(int(p) % nx, (int(p) // nx) % ny, int(p) // (nx * ny)) for p in order]
+    assert sorted(order.tolist()) == list(range(int(np.prod(np_))))
+    assert all(sum(abs(a[i] - b[i]) for i in range(3)) == 1 for a, b in zip(pts, pts[1:]))
+    side = min(np_)
+    m = 1
+    while (1 << m) <= side:
+        assert _blocks_contiguous(pts, 3, 1 << m), (np_, 1 << m)
+        m += 1
+    assert pts[0] == (0, 0, 0)
+    long_ax = int(np.argmax(np_))
+    cubes = int(np.prod(np_)) // side ** 3
+    if cubes == 1:
+        end = [0, 0, 0]
+        end[0] = side - 1
+        assert pts[-1] == tuple(end)
+    else:
+        assert pts[-1][long_ax] == np_[long_ax] - 1
