@@ -376,6 +376,23 @@ int pic_patch_order(int32_t ndim, const int32_t np[3], int32_t *order, int64_t n
  * negative cost. */
 int pic_curve_segments(const int64_t *cost, int64_t n, int32_t k, int64_t *bounds);
 
+/* ---- allocation-free entry point ---------------------------------------------- */
+
+/* Largest grid (fn[0] fn[1] fn[2] field nodes) pic_rho_get_noalloc accepts. */
+#define PIC_NOALLOC_MAX_NODES 8388608
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the charge
+ * density of pic_fields_get(s, PIC_RHO, host, count) without any device
+ * allocation.  The node sums are kept in a static device array of
+ * PIC_NOALLOC_MAX_NODES doubles (64 MiB) that the library holds on every GPU
+ * it runs on until the process ends; it is cleared by a kernel on every call.
+ * All calls on one GPU share that array, so calls that overlap on one GPU
+ * (from several threads or streams) race.  count must equal the grid's node
+ * count; grids with more than PIC_NOALLOC_MAX_NODES nodes fail with
+ * PIC_EINVAL before any device work.  Synchronises the handle's stream. */
+int pic_rho_get_noalloc(PicSim *s, double *host, size_t count);
+
 /* ---- errors ------------------------------------------------------------------ */
 
 const char *pic_strerror(int code);

@@ -27,7 +27,7 @@ EXPORTS = (
     "pic_batch_add", "pic_batch_remove", "pic_batch_step", "pic_batch_finished",
     "pic_batch_size", "pic_estimate_bytes", "pic_autotune", "pic_state_save", "pic_state_load",
     "pic_patch_order", "pic_curve_segments", "pic_window_set", "pic_merge_set", "pic_merge",
-    "pic_strerror",
+    "pic_rho_get_noalloc", "pic_strerror",
     "pic_last_error",
 )
 
@@ -124,6 +124,7 @@ def load() -> C.CDLL:
         "pic_patch_counts_get": (C.c_int, [_vp, _I32, C.c_size_t]),
         "pic_diag_get": (C.c_int, [_vp, C.POINTER(Diag)]),
         "pic_residuals": (C.c_int, [_vp, C.POINTER(Residuals)]),
+        "pic_rho_get_noalloc": (C.c_int, [_vp, _D, C.c_size_t]),
         "pic_history_get": (C.c_int, [_vp, C.c_int64, C.c_int64, _D, _D, _I64]),
         "pic_rebin_codes": (C.c_int, [_vp, C.POINTER(C.c_uint8), C.c_size_t]),
         "pic_timing_enable": (C.c_int, [_vp, C.c_int]),

@@ -235,6 +235,12 @@ int pic_residuals(PicSim *s, PicResiduals *out)
     return guarded([&] { s->impl->residuals(out); });
 }
 
+int pic_rho_get_noalloc(PicSim *s, double *host, size_t count)
+{
+    if (!s || !host) return bad(PIC_EINVAL, "null argument");
+    return guarded([&] { s->impl->rho_noalloc(host, count); });
+}
+
 int pic_diag_get(PicSim *s, PicDiag *out)
 {
     if (!s || !out) return bad(PIC_EINVAL, "null argument");

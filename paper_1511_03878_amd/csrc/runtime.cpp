@@ -542,6 +542,27 @@ void SimImpl<T>::record_rho0()
     rhoprev_step = -1;
 }
 
+// Charge density without any allocation: the static per-device scratch
+// holds the node sums (cleared by a kernel), then one copy to the host.
+template <typename T>
+void SimImpl<T>::rho_noalloc(double *h, size_t count)
+{
+    if ((int64_t)count != fsize) throw Error(PIC_EINVAL, "count must equal the number of field nodes");
+    if (fsize > (int64_t)PIC_NOALLOC_MAX_NODES)
+        throw Error(PIC_EINVAL, "grid has " + std::to_string(fsize) + " nodes, more than the " +
+                                    std::to_string((int64_t)PIC_NOALLOC_MAX_NODES) +
+                                    " the allocation-free scratch holds");
+    double *scr = noalloc_scratch();
+    fill_doubles(scr, fsize, 0.0, stream);
+    launch_rho<T>(view_d, npatch, nd, scr, stream);
+    hipcheck(hipGetLastError(), "rho launch");
+    hipcheck(hipMemcpyAsync(h, scr, sizeof(double) * fsize, hipMemcpyDeviceToHost, stream), "rho");
+    hipcheck(hipStreamSynchronize(stream), "sync");
+}
+
+// The paper's imbalance measure (section 3.1, Fig. 4: time of the busiest
+// unit over the mean) from the item stamps of the last stamped particle
+// launch: per compute unit, the summed time of this simulation's items.
 // Gauss and continuity residuals of the current state (see k_diag.hip).
 template <typename T>
 void SimImpl<T>::residuals(PicResiduals *out)

@@ -20,6 +20,10 @@ struct Error : std::runtime_error {
 };
 
 void set_error(const std::string &m);
+// Device address, on the current device, of the static scratch of the
+// allocation-free charge-density call (PIC_NOALLOC_MAX_NODES doubles).
+constexpr int kMaxDevices = 64;
+double *noalloc_scratch();
 extern thread_local std::string g_last_error;
 void hipcheck(hipError_t e, const char *what);
 int validate_desc(const PicSimDesc &d, std::string &why);
@@ -79,6 +83,7 @@ struct SimBase {
     virtual void history(int64_t first, int64_t n, double *U, double *K, int64_t *pushed) = 0;
     virtual void rebin_codes(const uint8_t *codes, size_t n) = 0;
     virtual void residuals(PicResiduals *out) = 0;
+    virtual void rho_noalloc(double *h, size_t count) = 0;
     virtual void step(int64_t nsteps) = 0;
     virtual bool in_batch() const = 0;
     virtual size_t device_bytes() const = 0;
@@ -174,6 +179,7 @@ struct SimImpl : SimBase {
     void history(int64_t first, int64_t n, double *U, double *K, int64_t *pushed) override;
     void rebin_codes(const uint8_t *codes, size_t n) override;
     void residuals(PicResiduals *out) override;
+    void rho_noalloc(double *h, size_t count) override;
     void record_rho0();
     void step(int64_t nsteps) override;
     bool in_batch() const override { return batch != nullptr; }
