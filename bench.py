@@ -1,22 +1,41 @@
-"""Benchmark: particle-steps/s of the full 2-D patch-PIC step on one MI355X.
+"""Benchmark: particle-steps/s of the patch-PIC step on one MI355X.
 
 A step is one pass of the whole hot path over the resident state: work-queue
-build, fused gather / Boris / move / Esirkepov deposit, fused Yee update with
-the laser-driven and outflow faces, and the per-patch re-binning.  The
-workload is the laser-wakefield box (4096 x 1024 cells, 32 x 32-cell patches,
-4 electrons per plasma cell behind a linear density ramp, a0 = 4 Gaussian
-laser driven through x = 0), all inputs seeded and synthetic.
+build, fused gather / Boris / move / Esirkepov deposit, Yee update with its
+face conditions, and the per-patch re-binning.  All inputs are seeded and
+synthetic and are loaded on the device from their descriptions.
 
-Prints one JSON line.  The timed region covers exactly --steps steps of a
-freshly loaded simulation (inputs already in HBM), bracketed by device
-synchronisations; --warmup steps run first on a separate instance.
+The headline workload is the largest single-GPU configuration, the 3-D box
+(512 x 256 x 256 cells, density n0 (1 + 0.9 cos kx) plus a 4 n0 sphere of
+radius 20 cells, round(8 n / n0) electrons per cell, 10 keV, periodic, FP32;
+2.7e8 particles).  The timed region covers exactly --steps steps of the
+instance that ran the --warmup steps (inputs already in HBM), bracketed by
+device synchronisations.
+
+Further measurements on the same JSON line (each on its own instance, after
+the headline):
+  lwfa_late     -- the 4096 x 1024 laser-wakefield box (FP32), timed over the
+                   steps after step 1000, once the pulse has formed a wake
+                   and patch occupancy is uneven;
+  batched_scan  -- 64 laser-wakefield simulations of uneven size, 500 steps
+                   each, stepped in one batch against the same simulations
+                   run one at a time;
+  served_scan   -- Poisson arrivals (4/s) of such simulations with 200..2000
+                   steps each, admitted against a 200 GiB HBM budget and
+                   stepped with continuous batching: 20 warm-up requests, then
+                   400 measured (p50 / p99 time-to-result), plus the same
+                   requests served in compressed time with continuous batching
+                   and one at a time;
+  cpu_baseline  -- the FP64 oracle (OpenMP timing build) on a sample of the
+                   headline workload on this host, at 1 thread and all threads.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
+import subprocess
 import sys
 import time
 
@@ -30,11 +49,41 @@ HBM_PEAK_GBS = 8000.0
 # position (2 or 3 components), momentum (3) and weight, write position and
 # momentum
 BYTES_PER_PARTICLE_STEP = {(2, 32): 44, (2, 64): 88, (3, 32): 52, (3, 64): 104}
-
-
-# per-workload options applied to the simulation (and to the oracle for the
-# CPU baseline): descriptor settings, moving window, merging
 S6 = 75 / 64 + 25 / 384 + 3 / 640   # the sixth-order solver's stability factor
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# workloads
+
+def _workload(name):
+    from paper_1511_03878_amd import workloads as W
+    if name == "blob3d":
+        wl = W.blob_3d(patch=(8, 8, 8))
+        desc = ("blob_3d: 512x256x256 cells (dx=0.1 c/w_p), periodic, n = n0 (1 + 0.9 cos kx) plus a "
+                "4 n0 sphere of radius 20 cells, round(8 n/n0) electrons per cell (2.7e8), 10 keV, "
+                "FP32; each 16^3-cell patch of the configuration run as eight 8^3 GPU patches")
+    elif name == "lwfa":
+        wl = W.lwfa_2d()
+        desc = ("lwfa_2d: 4096x1024 cells (dx=lambda/32, dy=lambda/8), 32x32-cell patches, 4 ppc "
+                "electrons behind a 2->12 lambda ramp to 0.003 n_c (16.5M), a0=4 w0=12 lambda "
+                "Gaussian laser through x=0, open x / periodic y")
+    elif name == "lwfa_window":
+        wl = W.lwfa_2d()
+        desc = ("lwfa_2d with a moving window from step 300 and particle merging every 100 steps "
+                "(cells above 8 particles, 8 k-means rounds)")
+    elif name == "periodic_hi":
+        wl = W.uniform_2d(n=(4096, 1024), patch=(32, 32), ppc=4, T_keV=1.0, cfl=0.9 / S6)
+        desc = "uniform_2d 4096x1024, 4 ppc, 1 keV, sixth-order field solver"
+    elif name == "uniform":
+        wl = W.uniform_2d()
+        desc = "uniform_2d: 128x128 cells, 16x16-cell patches, 16 ppc, 1 keV, periodic"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return wl, desc
 
 
 def _options(name, wl):
@@ -45,134 +94,160 @@ def _options(name, wl):
     return {}
 
 
-def _apply(sim, opts, oracle_side=False):
-    if "window" in opts:
-        sim.set_window(*opts["window"])
-    if "merge" in opts:
-        sim.set_merge(*opts["merge"])
-    if oracle_side and opts.get("tune", {}).get("maxwell_order") == 6:
-        sim.set_maxwell_order(6)
-
-
-def _workload(name, steps):
-    from paper_1511_03878_amd import workloads as W
-    if name == "lwfa_window":
-        wl = W.lwfa_2d(nsteps=max(steps, 1))
-        desc = ("lwfa_2d with a moving window from step 300 (v = c, jumps of one 32-cell patch column, "
-                "4 ppc cold plasma of the profile injected) and particle merging every 100 steps "
-                "(cells above 8 particles, 8 k-means rounds): 4096x1024 cells, 16.5M particles")
-    elif name == "periodic_hi":
-        wl = W.uniform_2d(n=(4096, 1024), patch=(32, 32), ppc=4, T_keV=1.0, cfl=0.9 / S6)
-        desc = ("uniform_2d with the sixth-order field solver: 4096x1024 cells (dx=0.1 c/w_p), "
-                "32x32-cell patches, 4 ppc, 1 keV, periodic (16.8M particles)")
-    elif name == "lwfa":
-        wl = W.lwfa_2d(nsteps=max(steps, 1))
-        desc = ("lwfa_2d: 4096x1024 cells (dx=lambda/32, dy=lambda/8), 32x32-cell patches, "
-                "4 ppc electrons behind a 2->12 lambda ramp to 0.003 n_c (16.5M particles), "
-                "a0=4 w0=12 lambda Gaussian laser through x=0, open x / periodic y")
-    elif name == "lwfa_small":
-        wl = W.lwfa_2d_small(nsteps=max(steps, 1))
-        desc = "lwfa_2d_small: 512x128 cells, 32x32-cell patches, 4 ppc"
-    elif name == "blob3d":
-        wl = W.blob_3d(patch=(8, 8, 8))
-        desc = ("blob_3d: 512x256x256 cells (dx=0.1 c/w_p), periodic, 8x8x8-cell patches "
-                "(each 16^3 patch of the configuration as 8 GPU patches), ppc=round(8 n/n0) with "
-                f"n = n0 (1 + 0.9 cos kx) and a 4 n0 sphere of radius 20 cells, 10 keV "
-                f"({wl['w'].size / 1e6:.1f}M particles)")
-    elif name == "uniform":
-        wl = W.uniform_2d()
-        desc = "uniform_2d: 128x128 cells, 16x16-cell patches, 16 ppc, 1 keV, periodic"
-    else:
-        raise SystemExit(f"unknown workload {name}")
-    return wl, desc
-
-
 def _sim_for(wl, name, precision):
     from paper_1511_03878_amd.sim import Sim
     opts = _options(name, wl)
     sim = Sim.from_workload(wl, precision=precision, **opts.get("tune", {}))
-    _apply(sim, opts)
+    if "window" in opts:
+        sim.set_window(*opts["window"])
+    if "merge" in opts:
+        sim.set_merge(*opts["merge"])
     return sim
 
 
-def _kernel_source_sha():
-    """Hash of the sources the particle kernel is built from."""
-    import hashlib
+# ---------------------------------------------------------------------------
+# roofline pieces
+
+def _kernel_source_sha(ndim):
     h = hashlib.sha256()
-    for f in ("k_particles.hip", "particle_common.h", "pic_dev.h", "kernels.h"):
+    files = ("k_particles3d.hip",) if ndim == 3 else ("k_particles.hip",)
+    for f in files + ("particle_common.h", "pic_dev.h", "kernels.h"):
         with open(os.path.join(ROOT, "paper_1511_03878_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def _measured_traffic(precision, workload):
+def _measured_traffic(kernel, workload, precision, ndim):
     """HBM bytes per launch of the particle kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE measurement, if it was taken on the current
-    kernel source (else None)."""
+    kernel source in the same window (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
-        rec = json.load(f).get(f"k_particles2d/{workload}/f{precision}")
-    if not rec or rec.get("source_sha") != _kernel_source_sha():
+        rec = json.load(f).get(f"{kernel}/{workload}/f{precision}")
+    if not rec or rec.get("source_sha") != _kernel_source_sha(ndim):
         return None
     return rec.get("traffic_bytes_per_launch")
 
 
-def _cpu_baseline(name, budget_s=25.0):
-    """Time the FP64 oracle (single-threaded C, as it stands) on one step of
-    the same workload on this host."""
-    import oracle
-    if name == "blob3d":
-        # one eighth of the box (256 x 128 x 128 cells, same density profile)
-        from paper_1511_03878_amd import workloads as W
-        wl = W.blob_3d(n=(256, 128, 128), patch=(8, 8, 8))
-    else:
-        wl, _ = _workload(name, 1)
-    if not os.path.exists(os.path.join(ROOT, "oracle", "liborc.so")):
-        oracle.build(force=False)
-    o = oracle.Sim(wl["grid"])
-    o.set_particles(wl["x"], wl["u"], wl["w"])
-    if wl.get("laser"):
-        o.set_laser(ey=wl["laser"]["ey"], ez=wl["laser"].get("ez"))
-    _apply(o, _options(name, wl), oracle_side=True)
-    n = wl["w"].size
+def _roofline(timing, total, ndim, precision, workload, breakdown):
+    ms, launches = timing["particles"]
+    avg_s = ms / 1e3 / max(launches, 1)
+    per_launch = BYTES_PER_PARTICLE_STEP[(ndim, precision)] * total / max(launches, 1)
+    achieved = per_launch / avg_s / 1e9
+    kernel = "k_particles2d" if ndim == 2 else "k_particles3d"
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": _measured_traffic(kernel, workload, precision, ndim),
+            "kernel": kernel, "algorithmic_bytes_per_launch": per_launch,
+            "kernel_ms_per_launch": round(avg_s * 1e3, 4), "launches": launches,
+            "kernel_ms_per_launch_after_timed_region": breakdown}
+
+
+def _timed_window(sim, steps, ndim, precision, workload, kernel_timing=True):
+    """Time `steps` steps of `sim` (particle kernel timed by its own dispatch
+    events); returns (particle-steps/s, ms/step, pushed, roofline)."""
+    import torch
+    step0 = sim.diag()["step"]
+    if kernel_timing:
+        sim.timing_enable("particles")
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    steps = 0
-    while True:
-        o.step(1)
-        steps += 1
-        if time.perf_counter() - t0 > budget_s / 2 or steps >= 3:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": n * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} step(s) of {'one eighth of ' if name == 'blob3d' else ''}"
-                      f"the workload ({n} particles), FP64 oracle, "
-                      f"{dt:.1f} s on one host core"}
+    sim.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sim.sync()
+    _, _, pushed = sim.history(step0, steps)
+    total = int(pushed.sum())
+    roof = None
+    if kernel_timing:
+        timing = sim.timing()
+        sim.timing_enable(True)
+        sim.step(min(16, max(1, steps // 4)))
+        breakdown = {k: round(v[0] / max(v[1], 1), 4) for k, v in sim.timing().items()}
+        sim.timing_enable(False)
+        roof = _roofline(timing, total, ndim, precision, workload, breakdown)
+    return total / wall, wall * 1e3 / steps, total, roof
 
 
-def _scan_bench(count, steps, precision, seed=None):
+def _imbalance(sim):
+    """The paper's imbalance measure (section 3.1, Fig. 4) on one more step
+    with per-item stamps: max / mean busy time of the compute units with the
+    work queue, and with the same item times dealt out as fixed domains."""
+    sim.timing_enable("stamps")
+    sim.step(1)
+    r = sim.imbalance()
+    sim.timing_enable(False)
+    keep = ("imbalance", "static_imbalance", "segment_imbalance", "units", "items", "span_us",
+            "busy_max_us", "busy_mean_us", "patch_max_us", "patch_mean_us")
+    return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items() if k in keep}
+
+
+# ---------------------------------------------------------------------------
+# extra measurements
+
+def _lwfa_late(precision, pre_steps=1000, steps=200):
+    """The laser box timed after its first `pre_steps` steps (wake formed,
+    uneven patch occupancy)."""
+    wl, desc = _workload("lwfa")
+    sim = _sim_for(wl, "lwfa", precision)
+    sim.step(pre_steps)
+    sim.sync()
+    d0 = sim.diag()
+    val, ms, total, roof = _timed_window(sim, steps, 2, precision, "lwfa_late")
+    d = sim.diag()
+    out = {"workload": desc, "steps_before": pre_steps, "steps_timed": steps, "value": val,
+           "unit": "particle-steps/s", "ms_per_step": ms, "particles": d["particles"],
+           "occupancy": {"min": d0["occupancy_min"], "mean": round(d0["occupancy_mean"], 1),
+                         "max": d0["occupancy_max"]},
+           "relayouts": d["relayouts"], "roofline": roof, "imbalance": _imbalance(sim)}
+    sim.close()
+    return out
+
+
+TUNE_CACHE = os.path.join(ROOT, "_build", "patch_tune.txt")
+
+
+def _tuned_scan_patch(params, precision):
+    """Patch edge and particle-kernel workgroup size of the scan, picked by the
+    library's patch tuner on the median-sized draw (the choice applies to
+    every member, so one batch shares one kernel specialisation)."""
+    from paper_1511_03878_amd import workloads as W
+    from paper_1511_03878_amd.sim import autotune_patch
+    sizes = [p["n"][0] * p["n"][1] * p["ppc"] for p in params]
+    rep = params[sorted(range(len(params)), key=lambda k: sizes[k])[len(params) // 2]]
+    os.makedirs(os.path.dirname(TUNE_CACHE), exist_ok=True)
+    grid, tune, res = autotune_patch(W.scan_sim(rep), precision, candidates=(16, 32), warm=20, steps=20,
+                                     cache=TUNE_CACHE)
+    patch = tuple(grid["patch"][:2])
+    return patch, tune, {"patch": list(patch), "block": tune["block"], "trials": res["trials"],
+                         "from_cache": res["from_cache"], "ms_per_step": res["ms_per_step"],
+                         "tuned_on": list(rep["n"])}
+
+
+def _scan_bench(count, steps, precision):
     """Batched parameter scan: `count` laser-wakefield simulations of uneven
-    size stepped together in one batch, against the same simulations run one
-    at a time.  Returns aggregate particle-steps/s of both."""
+    size stepped together in one batch (one work queue, one persistent
+    particle launch per step) against the same simulations run one at a
+    time.  Returns aggregate particle-steps/s of both."""
     import torch
     from paper_1511_03878_amd import workloads as W
     from paper_1511_03878_amd.sim import Batch, Sim
     params = W.scan_params(count)
-    wls = [W.scan_sim(p, steps, seed=W.DEFAULT_SEED + k) for k, p in enumerate(params)]
-    total = sum(int(w["w"].size) for w in wls) * steps
-    # one at a time
-    t_alone = 0.0
+    patch, tune, tuned = _tuned_scan_patch(params, precision)
+    wls = [W.scan_sim(p, seed=W.DEFAULT_SEED + k, patch=patch) for k, p in enumerate(params)]
+    t_alone, total = 0.0, 0
     for wl in wls:
-        s = Sim.from_workload(wl, precision=precision)
+        s = Sim.from_workload(wl, precision=precision, **tune)
+        total += s.num_particles() * steps
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s.step(steps)
         torch.cuda.synchronize()
         t_alone += time.perf_counter() - t0
         s.close()
-    # batched
-    sims = [Sim.from_workload(wl, precision=precision) for wl in wls]
+    sims = [Sim.from_workload(wl, precision=precision, **tune) for wl in wls]
     b = Batch(precision)
     for s in sims:
         b.add(s, steps)
@@ -186,43 +261,115 @@ def _scan_bench(count, steps, precision, seed=None):
     t_batch = time.perf_counter() - t0
     for s in sims:
         s.close()
+    b.close()
     return {"sims": count, "steps_each": steps, "particle_steps": total,
             "batched": total / t_batch, "one_at_a_time": total / t_alone,
-            "speedup": t_alone / t_batch, "unit": "particle-steps/s",
+            "speedup": t_alone / t_batch, "unit": "particle-steps/s", "launch": "one batch, one "
+            "persistent particle launch per step over every member's patches", "autotuned": tuned,
             "grids": [list(p["n"]) for p in params][:8] + (["..."] if count > 8 else [])}
 
 
-def _serve_bench(count, rate, steps_range, budget_gb, precision):
+def _serve_bench(count, warm, rate, steps_range, budget_gb, precision, compare):
     """Served scan: Poisson arrivals admitted against an HBM budget and
-    stepped with continuous batching; time-to-result percentiles."""
+    stepped with continuous batching (real time; the first `warm` requests
+    are warm-up); then the first `compare` requests again in compressed time
+    (idle gaps skipped), with continuous batching and one at a time."""
     from paper_1511_03878_amd import serve
-    reqs = serve.make_requests(count, rate, steps_range=steps_range)
-    srv = serve.Server(int(budget_gb * 2**30), precision=precision, slice_steps=25,
-                       result_fn=lambda sim: {"diag": sim.diag()})
-    rep = srv.run(reqs, realtime=True)
+    from paper_1511_03878_amd import workloads as W
+    reqs = serve.make_requests(count + warm, rate, steps_range=steps_range)
+    patch, tune, tuned = _tuned_scan_patch(W.scan_params(64), precision)
+    budget = int(budget_gb * 2**30)
+    srv = serve.Server(budget, precision=precision, slice_steps=25, result_fn=lambda sim: {},
+                       patch=patch, tune=tune)
+    rep = srv.run(reqs, realtime=True, warmup=warm)
     rep.update({"rate_per_s": rate, "steps_range": list(steps_range), "budget_GiB": budget_gb,
-                "unit": "particle-steps/s"})
+                "warmup_requests": warm, "unit": "particle-steps/s", "autotuned": tuned})
+    if compare > 0:
+        cmp = {}
+        for label, members in (("continuous_batching", 256), ("one_at_a_time", 1)):
+            rq = serve.make_requests(compare, rate, steps_range=steps_range)
+            s2 = serve.Server(budget, precision=precision, slice_steps=25, result_fn=lambda sim: {},
+                              max_members=members, patch=patch, tune=tune)
+            r = s2.run(rq, realtime=False)
+            cmp[label] = {"throughput": r["throughput"], "ttr_p50_s": r["ttr_p50_s"],
+                          "ttr_p99_s": r["ttr_p99_s"], "wall_s": r["wall_s"]}
+        cmp["speedup"] = cmp["continuous_batching"]["throughput"] / cmp["one_at_a_time"]["throughput"]
+        cmp["requests"] = compare
+        cmp["note"] = "compressed time: idle gaps before an arrival are skipped"
+        rep["compressed_comparison"] = cmp
     return rep
 
+
+def _cpu_model():
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return "unknown"
+
+
+def _cpu_baseline(budget_s=25.0):
+    """The FP64 oracle (timing build: -O3 -march=native, OpenMP particle loop
+    with per-thread current arrays) on a 128 x 64 x 64 box with the headline's
+    density profile and cell size, at 1 thread and at every host thread."""
+    import oracle
+    from paper_1511_03878_amd import workloads as W
+    oracle.use_timing_build()
+    wl = W.blob_3d(n=(128, 64, 64), patch=(8, 8, 8), blob_radius=20.0)
+    res = {}
+    nproc = os.cpu_count() or 1
+    for th in (1, nproc):
+        got = oracle.set_threads(th)
+        o = oracle.Sim(wl["grid"])
+        o.particles_init(wl["species"])
+        n = o.particles()[2].size
+        steps, t0 = 0, time.perf_counter()
+        while True:
+            o.step(1)
+            steps += 1
+            if time.perf_counter() - t0 > budget_s / 4 or steps >= 3:
+                break
+        dt = time.perf_counter() - t0
+        res[th] = (n * steps / dt, got, steps, n, dt)
+        del o
+    best = res[nproc]
+    return {"value": best[0], "unit": "particle-steps/s", "cores": best[1], "kind": "oracle",
+            "cpu_model": _cpu_model(), "value_1_thread": res[1][0],
+            "sample": (f"{best[2]} step(s) of a 128x64x64 box with the headline's profile "
+                       f"({best[3]} particles), FP64 oracle timing build (-O3 -march=native, OpenMP), "
+                       f"{best[4]:.1f} s at {best[1]} threads; {res[1][2]} step(s) at 1 thread "
+                       f"{res[1][4]:.1f} s")}
+
+
+# ---------------------------------------------------------------------------
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", type=int, default=32, choices=(32, 64))
-    ap.add_argument("--workload", default="lwfa")
+    ap.add_argument("--workload", default="blob3d")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-kernel-timing", action="store_true")
-    ap.add_argument("--scan", type=int, default=16, metavar="N",
-                    help="also run a batched scan of N simulations vs one at a time (0: skip)")
-    ap.add_argument("--scan-steps", type=int, default=100)
-    ap.add_argument("--serve", type=int, default=24, metavar="N",
-                    help="also serve N Poisson-arriving requests and report p50/p99 (0: skip)")
+    ap.add_argument("--no-late", action="store_true")
+    ap.add_argument("--scan", type=int, default=64, metavar="N",
+                    help="batched scan of N simulations vs one at a time (0: skip)")
+    ap.add_argument("--scan-steps", type=int, default=500)
+    ap.add_argument("--serve", type=int, default=400, metavar="N",
+                    help="serve N Poisson-arriving requests after the warm-up ones (0: skip)")
+    ap.add_argument("--serve-warmup", type=int, default=20)
+    ap.add_argument("--serve-compare", type=int, default=100)
     ap.add_argument("--serve-rate", type=float, default=4.0)
     ap.add_argument("--serve-steps", default="200,2000")
+    ap.add_argument("--pre-steps", type=int, default=0,
+                    help="untimed steps of the headline instance before its warm-up (e.g. the laser "
+                         "box after step 1000)")
+    ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
-                    help="before the run, time a plain device copy of MIB MiB (calibrates "
+                    help="first time an elementwise kernel that reads and writes MIB MiB (calibrates "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE against a known byte count)")
     args = ap.parse_args()
 
@@ -232,8 +379,6 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1511_03878_amd.sim import Sim
-
     torch.cuda.set_device(0)
     copy_cal = None
     if args.copy_calibration > 0:
@@ -253,61 +398,22 @@ def main():
         copy_cal = {"kernel": "elementwise mul", "bytes_read": 4 * n, "bytes_written": 4 * n, "ms": ms,
                     "GBps": 8 * n / ms / 1e6}
         del a, b
-    wl, desc = _workload(args.workload, args.steps)
-    print(f"[bench] workload ready: {desc}", file=sys.stderr, flush=True)
-
-    if args.warmup > 0 and wl["grid"]["ndim"] == 2:
-        w = _sim_for(wl, args.workload, args.precision)
-        w.step(args.warmup)
-        w.sync()
-        w.close()
-        del w
+    wl, desc = _workload(args.workload)
+    ndim = wl["grid"]["ndim"]
+    t_setup = time.perf_counter()
     sim = _sim_for(wl, args.workload, args.precision)
-    if args.warmup > 0 and wl["grid"]["ndim"] == 3:
-        # the 3-D box is statistically stationary: warm up on the timed instance
+    sim.sync()
+    _log(f"workload loaded on the device in {time.perf_counter() - t_setup:.1f} s: {desc}")
+    if args.pre_steps > 0:
+        sim.step(args.pre_steps)
+        sim.sync()
+    if args.warmup > 0:
         sim.step(args.warmup)
         sim.sync()
-    step0 = sim.diag()["step"]
-    if not args.no_kernel_timing:
-        # the particle kernel (the roofline's kernel) is timed inside the timed
-        # region; the other kernels only afterwards (each timed kernel adds a
-        # few microseconds between launches)
-        sim.timing_enable("particles")
-    torch.cuda.synchronize()
-    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    sim.step(args.steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    sim.sync()
-    wall = t1 - t0
-    _, _, pushed = sim.history(step0, args.steps)
-    total = int(pushed.sum())
-    value = total / wall
-    timing = sim.timing() if not args.no_kernel_timing else {}
+    _log(f"timing {args.steps} steps")
+    value, ms_step, total, roof = _timed_window(sim, args.steps, ndim, args.precision, args.workload,
+                                                kernel_timing=not args.no_kernel_timing)
     d = sim.diag()
-    breakdown = {}
-    if not args.no_kernel_timing:
-        # per-kernel breakdown over a short window after the timed region
-        sim.timing_enable(True)
-        sim.step(min(64, max(1, args.steps // 4)))
-        breakdown = {k: round(v[0] / max(v[1], 1), 4) for k, v in sim.timing().items()}
-
-    roof = None
-    if timing:
-        ms, launches = timing["particles"]
-        avg_s = ms / 1e3 / max(launches, 1)
-        ndim = wl["grid"]["ndim"]
-        per_launch_bytes = BYTES_PER_PARTICLE_STEP[(ndim, args.precision)] * total / max(launches, 1)
-        achieved = per_launch_bytes / avg_s / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": _measured_traffic(args.precision, args.workload),
-                "kernel": "k_particles2d" if wl["grid"]["ndim"] == 2 else "k_particles3d",
-                "algorithmic_bytes_per_launch": per_launch_bytes,
-                "particle_kernel_ms_per_launch": round(avg_s * 1e3, 4),
-                "kernel_ms_per_launch_after_timed_region": breakdown}
-
     out = {
         "metric": METRIC,
         "value": value,
@@ -315,32 +421,40 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
+        "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32" if args.precision == 32 else "f64",
         "data": "synthetic",
-        "config": {"workload": desc, "steps_timed": args.steps,
-                   "particles_start": int(wl["w"].size), "particles_end": int(d["particles"]),
-                   "occupancy_max_end": d["occupancy_max"], "relayouts": d["relayouts"]},
+        "config": {"workload": desc, "steps_timed": args.steps, "particles": int(d["particles"]),
+                   "occupancy": {"min": d["occupancy_min"], "mean": round(d["occupancy_mean"], 1),
+                                 "max": d["occupancy_max"]},
+                   "relayouts": d["relayouts"]},
         "roofline": roof,
+        "imbalance": _imbalance(sim),
     }
+    if args.pre_steps:
+        out["config"]["steps_before_warmup"] = args.pre_steps
     if copy_cal:
         out["copy_calibration"] = copy_cal
     sim.close()
     del sim
+    torch.cuda.empty_cache()
+    if not args.no_late:
+        _log("laser box after step 1000")
+        out["lwfa_late"] = _lwfa_late(args.precision)
     if args.scan > 0:
-        print(f"[bench] batched scan of {args.scan} simulations", file=sys.stderr, flush=True)
+        _log(f"batched scan of {args.scan} simulations x {args.scan_steps} steps")
         out["batched_scan"] = _scan_bench(args.scan, args.scan_steps, args.precision)
     if args.serve > 0:
         lo, hi = (int(v) for v in args.serve_steps.split(","))
-        print(f"[bench] serving {args.serve} requests", file=sys.stderr, flush=True)
-        out["served_scan"] = _serve_bench(args.serve, args.serve_rate, (lo, hi), 200.0,
-                                          args.precision)
+        _log(f"serving {args.serve_warmup} + {args.serve} requests")
+        out["served_scan"] = _serve_bench(args.serve, args.serve_warmup, args.serve_rate, (lo, hi),
+                                          200.0, args.precision, args.serve_compare)
     if not args.no_cpu:
-        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = _cpu_baseline(args.workload)
+        _log("timing the CPU oracle")
+        out["cpu_baseline"] = _cpu_baseline()
     print(json.dumps(out), flush=True)
 
 

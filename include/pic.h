@@ -128,6 +128,7 @@ typedef struct {
     int32_t relayouts;     /* capacity re-layouts performed so far */
     int64_t window_cells;  /* cells the moving window has travelled (0 without one) */
     int64_t merged;        /* particles taken out by merging so far */
+    int64_t device_bytes;  /* device memory the handle holds now (grows with patch capacity) */
 } PicDiag;
 
 /* Residuals of the discrete conservation laws (pic_residuals).  The paper
@@ -180,6 +181,91 @@ void pic_sim_destroy(PicSim *s);
  * precision; positions are stored as offsets from their patch origin. */
 int pic_particles_set(PicSim *s, int64_t n, const double *x, const double *y, const double *z,
                       const double *ux, const double *uy, const double *uz, const double *w);
+
+/* ---- species and lasers -------------------------------------------------- */
+
+/* The paper sets up its runs by laser and plasma parameters (section 2.2: a
+ * Gaussian pulse of given a0, waist and duration focused at the foot of a
+ * density ramp; section 3: a plasma whose super-particle density follows the
+ * density).  These calls load the species and drive the laser from such
+ * descriptions, on the device.
+ *
+ * Density profiles (lengths in c/omega_r, densities in n_r):
+ *   PIC_PROFILE_UNIFORM     n0 everywhere;
+ *   PIC_PROFILE_RAMP        0 below x0 = param[0], rising linearly to n0 at
+ *                           x1 = param[1], n0 beyond (cells whose lower x face
+ *                           is at or beyond x0 hold plasma);
+ *   PIC_PROFILE_COS_SPHERE  n0 (1 + param[0] cos(2 pi x / L_x)), and
+ *                           param[5] n0 inside the sphere of centre
+ *                           (param[1], param[2], param[3]) and radius param[4]
+ *                           (evaluated at cell centres).
+ * Loading rules: PIC_LOAD_WEIGHT puts ppc particles in every plasma cell with
+ * weight n / ppc (n at the particle for the ramp, at the cell centre
+ * otherwise); PIC_LOAD_COUNT puts round(ppc n / n0) particles in a cell with
+ * weight n0 / ppc (super-particle count follows the density, as in the
+ * paper's 3-D runs, section 3).
+ * Particles are generated cell by cell in row-major order (x fastest), k =
+ * 0 .. count - 1 in a cell; that order is the id order.  Random numbers come
+ * from SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) in counter form: draw
+ * d of particle g in stream r is output r 2^44 + 8 g + d of the generator
+ * seeded with `seed`, and a uniform double is its top 53 bits times 2^-53.
+ * Stream 0: position on axis a = cell index + draw a (kept below the cell's
+ * upper face).  Stream 1: momenta, every component Gaussian with
+ * sigma = sqrt(temperature) by Box-Muller (radius from 1 - draw 0 and 1 -
+ * draw 2, angles 2 pi draw 1 and 2 pi draw 3; u_x, u_y from the first pair,
+ * u_z the cosine of the second); temperature 0 is a cold species. */
+enum { PIC_PROFILE_UNIFORM = 0, PIC_PROFILE_RAMP = 1, PIC_PROFILE_COS_SPHERE = 2 };
+enum { PIC_LOAD_WEIGHT = 0, PIC_LOAD_COUNT = 1 };
+typedef struct {
+    double q, m;           /* must equal the simulation descriptor's */
+    int32_t profile;       /* PIC_PROFILE_* */
+    int32_t loading;       /* PIC_LOAD_* */
+    int32_t ppc;           /* 1..4096 */
+    int32_t reserved;      /* 0 */
+    double n0;             /* reference density (> 0) */
+    double param[6];       /* profile parameters (see above) */
+    double temperature;    /* kT / (m c^2) >= 0 */
+    uint64_t seed;
+} PicSpeciesDesc;
+
+/* Describe the simulation's species (one per simulation; the immobile
+ * neutralising ions are implicit and carry minus its charge at load).  *sid
+ * (may be NULL) receives 0.  Host-only.  PIC_EINVAL for bad values,
+ * PIC_ENOTSUP for a second species, PIC_ESTATE in a batch. */
+int pic_species_add(PicSim *s, const PicSpeciesDesc *d, int32_t *sid);
+/* Generate species sid's particles on the device as described above; replaces
+ * any previous particles and resets the step counter to 0, like
+ * pic_particles_set.  PIC_ESTATE without a species or in a batch. */
+int pic_particles_init(PicSim *s, int32_t sid);
+
+/* A Gaussian laser pulse driving the open x = 0 face of a 2-D box (the LWFA
+ * driver of section 2.2), evaluated in FP64 by the field update every step
+ * at time (n + 1/2) dt on the face's Ey (y = (j + 1/2) d_y) or Ez (y = j d_y)
+ * positions: a 2-D paraxial Gaussian beam of waist w0 (1/e field radius) in
+ * the plane x = x_focus, Rayleigh length omega0 w0^2 / 2; at the face, a
+ * distance s = -x_focus from the waist, spot w = w0 sqrt(1 + (s / x_R)^2),
+ * curvature s / (s^2 + x_R^2), Gouy shift atan(s / x_R) / 2, amplitude
+ * a0 omega0 sqrt(w0 / w); field
+ *   E = a0 omega0 sqrt(w0 / w) exp(-2 ln 2 (t - t0)^2 / tau^2) exp(-(y - yc)^2 / w^2)
+ *       sin(omega0 (t - t0) - omega0 (y - yc)^2 curv / 2 + Gouy + phase),
+ * tau the FWHM of the intensity.  Lasers add to each other and to a table
+ * set with pic_laser_set.  Not part of a checkpoint (add them again after
+ * pic_state_load).  PIC_ENOTSUP in 3-D, for another face or beyond four
+ * lasers; PIC_EINVAL for a periodic x axis or bad values; PIC_ESTATE in a
+ * batch. */
+typedef struct {
+    double a0;             /* peak field a0 omega0, in m_e c omega_r / e */
+    double omega0;         /* carrier frequency (units of omega_r) */
+    double w0;             /* waist */
+    double tau;            /* FWHM duration of the intensity */
+    double t0;             /* time of the envelope peak at the face */
+    double x_focus;        /* position of the waist along x */
+    double y_center;       /* beam axis */
+    double phase;          /* carrier phase */
+    int32_t polarisation;  /* 1: Ey (in the plane), 2: Ez */
+    int32_t face;          /* 0: x = 0 (the only face supported) */
+} PicLaserDesc;
+int pic_laser_add(PicSim *s, const PicLaserDesc *d);
 
 /* Incident field driving the open x = 0 face: row t (t = 0..nsteps-1) holds
  * the incident Ey (at y = (j + 1/2) d_y) and Ez (at y = j d_y) at time
@@ -235,6 +321,13 @@ int pic_window_set(PicSim *s, int64_t start_step, double velocity, int32_t ppc_x
 int pic_merge_set(PicSim *s, int32_t every, int32_t cell_max, int32_t iterations);
 int pic_merge(PicSim *s, int32_t cell_max, int32_t iterations, int64_t *taken);
 
+/* Set the completed-step counter of a state loaded from elsewhere
+ * (particles and fields at time step * dt): a laser's time and the field
+ * buffer that pic_fields_set writes follow it, so call it before
+ * pic_fields_set.  The energy history restarts at that step.  PIC_ESTATE in
+ * a batch or while a capacity-overflow recovery is pending. */
+int pic_step_set(PicSim *s, int64_t step);
+
 /* Overwrite one field component (E or B) from a host FP64 array of
  * count = fn[0]*fn[1]*fn[2] values. */
 int pic_fields_set(PicSim *s, int comp, const double *host, size_t count);
@@ -261,7 +354,14 @@ int pic_num_particles(PicSim *s, int64_t *n);
 int pic_particles_get(PicSim *s, double *x, double *y, double *z, double *ux, double *uy,
                       double *uz, double *w, int64_t *id, size_t count);
 int pic_patch_counts_get(PicSim *s, int32_t *counts, size_t count);
+/* The particle permutation: ids[k] is the id of the particle in canonical
+ * (patch, slot) position k (count >= live particles). */
+int pic_perm_get(PicSim *s, int64_t *ids, size_t count);
 int pic_diag_get(PicSim *s, PicDiag *out);
+/* Device memory the handle holds now (host-only, no synchronisation): what
+ * admission control charges a resident simulation; it grows when patch
+ * capacities grow. */
+int pic_device_bytes(PicSim *s, int64_t *bytes);
 /* Gauss and continuity residuals of the current state (see PicResiduals);
  * synchronises the stream.  Each call records rho^k for the continuity
  * residual of a call one step later.  PIC_ENOTSUP with a moving window,
@@ -288,8 +388,27 @@ typedef struct {
     double ms_per_step;    /* of the chosen settings (0 on a cache hit) */
     int32_t trials;        /* candidates timed */
     int32_t from_cache;    /* 1 when the settings came from the cache */
+    int32_t patch[3];      /* patch shape (pic_autotune_patch; else the handle's) */
 } PicTuneResult;
 int pic_autotune(PicSim *s, int32_t steps, const char *cache, PicTuneResult *out);
+
+/* Patch-size tuner.  The patch is the paper's unit of load balance (section
+ * 3.1) and is fixed when a handle is created, so this tunes a descriptor:
+ * for each candidate edge c (patches of c cells on every axis; candidates
+ * that do not divide the grid or that the descriptor rules refuse are
+ * skipped) it builds a temporary simulation of *d with that patch, loads
+ * species sp on the device (and laser l, may be NULL), runs `warm` steps and
+ * then times `steps` steps (0 = 20), and writes the fastest candidate's
+ * shape into d->patch.  The fastest workgroup size of the particle kernel is
+ * chosen along with it (written into d->block).  With a non-NULL `cache` path
+ * the choice is stored under a key of dimensions, precision, grid, density
+ * profile, loading and ppc, and a later call with the same key applies it
+ * without running.  Device memory comes from `a` (NULL: hipMalloc / hipFree)
+ * and work runs on hip_stream.  PIC_EINVAL when no candidate fits. */
+int pic_autotune_patch(PicSimDesc *d, const PicSpeciesDesc *sp, const PicLaserDesc *l,
+                       const int32_t *candidates, int32_t ncand, int32_t warm, int32_t steps,
+                       const PicAllocator *a, void *hip_stream, const char *cache,
+                       PicTuneResult *out);
 
 /* Checkpoint / resume.  pic_state_save writes the whole simulation state
  * (E and B of the current time level, the last deposit J, the particles in
@@ -317,10 +436,38 @@ int pic_rebin_codes(PicSim *s, const uint8_t *codes, size_t count);
 /* Per-kernel timing from start/stop events recorded by the dispatches.
  * mode 0: off; 1: every kernel group (queue, particles, Yee, re-binning);
  * 2: the particle kernel only (one event pair per step, the least
- * perturbation).  Enabling resets the totals; timing also turns graph
+ * perturbation); 3: as 2, and every work item of the particle launch also
+ * records when it started and ended and on which compute unit it ran (for
+ * pic_imbalance).  Enabling resets the totals; timing also turns graph
  * replay off while on. */
 int pic_timing_enable(PicSim *s, int mode);
 int pic_timing_get(PicSim *s, PicTiming *out); /* synchronises */
+
+/* Load imbalance of the last particle launch made while timing mode 3 was on
+ * (the paper's measure, section 3.1 and Fig. 4: the time of the busiest
+ * processing unit over the mean).  The work of one step is this
+ * simulation's work items; a compute unit's busy time is the summed
+ * duration (start to end on the device clock) of the items it ran.  For
+ * comparison the same item times are also dealt out as fixed domains, one
+ * per compute unit: equal runs of patch ids (a static decomposition without
+ * balancing) and contiguous segments of the Hilbert-curve patch order cut
+ * by particle count (pic_curve_segments; patch id order on grids the curve
+ * does not cover).  Synchronises.  PIC_ESTATE when no stamped launch ran
+ * this simulation's items. */
+typedef struct {
+    int64_t step;             /* completed steps (the stamps describe the last stamped step) */
+    int32_t items;            /* this simulation's work items in that launch */
+    int32_t units;            /* compute units that ran at least one of them */
+    int32_t device_units;     /* compute units of the device */
+    double span_us;           /* first item start to last item end */
+    double busy_max_us;       /* busiest compute unit */
+    double busy_mean_us;      /* mean over every compute unit of the device */
+    double imbalance;         /* busy_max / busy_mean with the work queue */
+    double static_imbalance;  /* max / mean with equal runs of patch ids per unit */
+    double segment_imbalance; /* max / mean with count-balanced curve segments per unit */
+    double patch_max_us, patch_mean_us; /* summed item time per patch */
+} PicImbalance;
+int pic_imbalance(PicSim *s, PicImbalance *out);
 
 /* ---- batches of simulations stepped together ------------------------------- */
 

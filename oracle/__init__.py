@@ -23,6 +23,9 @@ _LIB = os.path.join(_HERE, "liborc.so")
 COMPONENTS = ("Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz")
 
 
+_LIB_OMP = os.path.join(_HERE, "liborc_omp.so")
+
+
 def build(force: bool = True) -> str:
     """Compile orc.c into liborc.so next to it and return the path."""
     if force or not os.path.exists(_LIB):
@@ -31,6 +34,34 @@ def build(force: bool = True) -> str:
             ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
+
+
+def build_timing(force: bool = True) -> str:
+    """Compile the timing build of the same source (-O3 -march=native for this
+    host, OpenMP over the particle loop with per-thread current arrays) into
+    liborc_omp.so; only the CPU baseline of the benchmark loads it."""
+    if force or not os.path.exists(_LIB_OMP):
+        tmp = _LIB_OMP + ".tmp"
+        subprocess.check_call(["gcc", "-O3", "-march=native", "-fopenmp", "-std=c11", "-fPIC", "-shared",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_OMP)
+    return _LIB_OMP
+
+
+def use_timing_build():
+    """Load the timing build in place of the plain one (CPU baseline only)."""
+    global _lib, _LIB
+    build_timing(force=True)
+    _LIB = _LIB_OMP
+    _lib = None
+    return _load()
+
+
+def set_threads(n: int) -> int:
+    """Host threads of the particle loop (timing build); returns the count in effect."""
+    lib = _load()
+    lib.orc_set_threads(int(n))
+    return int(lib.orc_threads())
 
 
 class _Desc(C.Structure):
@@ -73,6 +104,14 @@ def _load():
         "orc_get_field": (None, [vp, C.c_int, _D]),
         "orc_set_field": (None, [vp, C.c_int, _D]),
         "orc_set_laser": (None, [vp, C.c_int64, _D, _D]),
+        "orc_add_laser": (C.c_int, [vp] + [C.c_double] * 8 + [C.c_int]),
+        "orc_gauss_beam": (C.c_double, [C.c_double] * 10),
+        "orc_splitmix64": (C.c_uint64, [C.c_uint64, C.c_uint64]),
+        "orc_particles_init": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, C.c_double, _D, C.c_double,
+                                         C.c_uint64]),
+        "orc_round_storage": (None, [vp]),
+        "orc_set_threads": (None, [C.c_int]),
+        "orc_threads": (C.c_int, []),
         "orc_step": (None, [vp, C.c_int64]),
         "orc_energy": (None, [vp, _D, _D]),
         "orc_field_energy": (C.c_double, [vp]),
@@ -133,6 +172,23 @@ def boris(u, E, B, q: float, m: float, dt: float) -> np.ndarray:
     BB = _f64(B)
     _load().orc_boris(_dp(uu), _dp(EE), _dp(BB), float(q), float(m), float(dt))
     return uu
+
+
+def splitmix64(seed: int, n: int) -> int:
+    """Output n of the SplitMix64 generator seeded with `seed`."""
+    return int(_load().orc_splitmix64(int(seed) & (2 ** 64 - 1), int(n)))
+
+
+def gauss_beam(laser: dict, t: float, y: float) -> float:
+    """Incident field of a Gaussian laser description at the x = 0 face."""
+    L = laser
+    return float(_load().orc_gauss_beam(L["a0"], L.get("omega0", 1.0), L["w0"], L["tau"], L["t0"],
+                                        L["x_focus"], L["y_center"], L.get("phase", 0.0), float(t),
+                                        float(y)))
+
+
+PROFILES = {"uniform": 0, "ramp": 1, "cos_sphere": 2}
+LOADINGS = {"weight": 0, "count": 1}
 
 
 def rebin(counts, dest):
@@ -235,6 +291,33 @@ class Sim:
         nsteps = next(a.shape[0] for a in arrs if a is not None)
         ptrs = [None if a is None else _dp(a) for a in arrs]
         _load().orc_set_laser(self._p, nsteps, ptrs[0], ptrs[1])
+
+    def particles_init(self, sp: dict):
+        """Load a species description (profile, loading, ppc, n0, param,
+        temperature, seed) with the oracle's own SplitMix64 loader."""
+        p = _f64(list(sp.get("param", [])) + [0.0] * 6)[:6].copy()
+        rc = _load().orc_particles_init(self._p, PROFILES[sp["profile"]], LOADINGS[sp.get("loading", "weight")],
+                                        int(sp["ppc"]), float(sp.get("n0", 1.0)), _dp(p),
+                                        float(sp.get("temperature", 0.0)),
+                                        int(sp.get("seed", 0)) & (2 ** 64 - 1))
+        if rc != 0:
+            raise ValueError("oracle: unsupported species description")
+
+    def round_storage(self):
+        """Round the particle state to what FP32 storage holds (positions as
+        FP32 offsets from their patch origin, rounded to nearest and kept
+        below the patch's upper face; momenta and weights in FP32), back in
+        FP64: the state an FP32 run starts from after loading these particles."""
+        _load().orc_round_storage(self._p)
+
+    def add_laser(self, laser: dict):
+        """A Gaussian laser through the x = 0 face (2-D, open x)."""
+        L = laser
+        rc = _load().orc_add_laser(self._p, L["a0"], L.get("omega0", 1.0), L["w0"], L["tau"], L["t0"],
+                                   L["x_focus"], L["y_center"], L.get("phase", 0.0),
+                                   int(L.get("polarisation", 1)))
+        if rc != 0:
+            raise ValueError("oracle: unsupported laser")
 
     def rho(self) -> np.ndarray:
         out = np.zeros(self.fsize)

@@ -35,8 +35,12 @@
  * (section 3.2) and the moving window (sections 2.1, 2.3), and the
  * sixth-order field solver (section 2.1).  Everything is plain loops in FP64.
  */
+#define _DEFAULT_SOURCE
 #include <math.h>
 #include <stdint.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -66,6 +70,11 @@ typedef struct {
     int64_t laser_steps;
     int laser_n1;     /* transverse nodes per table row (n[1] * n[2]) */
     double *laser_ey, *laser_ez;
+    /* Gaussian lasers through x = 0 (see orc_add_laser): a0, omega0, w0, tau,
+     * t0, x_focus, y_center, phase; polarisation 1 (Ey) or 2 (Ez) */
+    int nlaser;
+    double las[4][8];
+    int las_pol[4];
     int64_t step;
     double U_last, K_last;
     int64_t removed;
@@ -80,6 +89,9 @@ typedef struct {
     int64_t win_shift;/* shifts done so far (the window has moved win_shift * patch[0] cells) */
     int64_t next_id;  /* id of the next injected particle */
     /* particle merging (see orc_merge) */
+    double **jbuf;    /* OpenMP build only: per-thread current arrays (3 per thread) */
+    double **jpriv;   /* jbuf while the particle loop runs, else NULL */
+    int jthreads;
     int merge_every;  /* merge after every merge_every-th step (0: never) */
     int merge_cmax, merge_iters;
     int64_t merged;   /* particles taken out by merging so far */
@@ -229,7 +241,33 @@ static void window_weights(double x0, double x1, int64_t *i0, double S0[5], doub
 static void jadd(orc_sim *s, int comp, int64_t i, int64_t j, int64_t k, double v)
 {
     int64_t f = flat3(s, comp, i, j, k);
-    if (f >= 0) s->F[comp][f] += v;
+    if (f < 0) return;
+#ifdef _OPENMP
+    if (s->jpriv) {
+        s->jpriv[3 * omp_get_thread_num() + comp - 6][f] += v;
+        return;
+    }
+#endif
+    s->F[comp][f] += v;
+}
+
+/* Host threads of the particle loop (OpenMP build; 1 otherwise). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 void orc_deposit(orc_sim *s, const double xa[3], const double xb[3], double w, double vz)
@@ -426,6 +464,66 @@ static double laser_row(const orc_sim *s, const double *tab, int64_t j, int64_t 
     return tab[s->step * s->laser_n1 + j + (int64_t)s->g.n[1] * k];
 }
 
+/* Incident field of a y- or z-polarised 2-D paraxial Gaussian beam at the
+ * x = 0 face, time t, transverse position y (the laser of the LWFA runs,
+ * section 2.2: a focused Gaussian pulse of amplitude a0).  Waist w0 (1/e
+ * radius of the field) in the plane x = x_focus, Rayleigh length
+ * x_R = omega0 w0^2 / 2 (c = 1).  At distance xi = 0 - x_focus from the
+ * focus the beam has radius w = w0 sqrt(1 + (xi / x_R)^2), wavefront
+ * curvature 1/R = xi / (xi^2 + x_R^2) and Gouy phase atan(xi / x_R) / 2 (half
+ * the 3-D value: one transverse dimension), and its amplitude falls as
+ * sqrt(w0 / w) (power per unit length kept).  Temporal envelope
+ * exp(-2 ln 2 (t - t0)^2 / tau^2): tau is the FWHM of the intensity.  Peak
+ * field a0 omega0 (units m_e c omega_r / e). */
+static double gauss_beam(const double *L, double t, double y)
+{
+    const double a0 = L[0], om = L[1], w0 = L[2], tau = L[3], t0 = L[4], xf = L[5], yc = L[6], ph = L[7];
+    const double xr = 0.5 * om * w0 * w0;
+    const double xi = 0.0 - xf;
+    const double w = w0 * sqrt(1.0 + (xi / xr) * (xi / xr));
+    const double inv_r = xi / (xi * xi + xr * xr);
+    const double gouy = 0.5 * atan2(xi, xr);
+    const double dy = y - yc;
+    const double amp = a0 * om * sqrt(w0 / w);
+    const double env = exp(-2.0 * log(2.0) * ((t - t0) / tau) * ((t - t0) / tau));
+    const double tr = exp(-(dy / w) * (dy / w));
+    return amp * env * tr * sin(om * (t - t0) - 0.5 * om * dy * dy * inv_r + gouy + ph);
+}
+
+/* Incident Ey (comp 1, on dual y positions (j + 1/2) dy) or Ez (comp 2, on
+ * primal y positions j dy) at the x = 0 face during the step in flight
+ * (time (step + 1/2) dt): the table row plus every Gaussian laser. */
+static double incident(const orc_sim *s, int comp, int64_t j, int64_t k)
+{
+    double v = laser_row(s, comp == 1 ? s->laser_ey : s->laser_ez, j, k);
+    const double t = ((double)s->step + 0.5) * s->g.dt;
+    const double y = ((double)j + (comp == 1 ? 0.5 : 0.0)) * s->g.d[1];
+    for (int l = 0; l < s->nlaser; ++l)
+        if (s->las_pol[l] == comp) v += gauss_beam(s->las[l], t, y);
+    return v;
+}
+
+/* Add a Gaussian laser driving the open x = 0 face (2-D): parameters as in
+ * gauss_beam, pol 1 (Ey) or 2 (Ez).  Returns 0, or -1 for an unsupported
+ * request (3-D, periodic x, more than four lasers, bad values). */
+int orc_add_laser(orc_sim *s, double a0, double omega0, double w0, double tau, double t0,
+                  double x_focus, double y_center, double phase, int pol)
+{
+    if (s->g.ndim != 2 || s->g.periodic[0] || s->nlaser >= 4) return -1;
+    if (!(omega0 > 0.0 && w0 > 0.0 && tau > 0.0 && a0 >= 0.0) || (pol != 1 && pol != 2)) return -1;
+    double *L = s->las[s->nlaser];
+    L[0] = a0; L[1] = omega0; L[2] = w0; L[3] = tau; L[4] = t0; L[5] = x_focus; L[6] = y_center; L[7] = phase;
+    s->las_pol[s->nlaser++] = pol;
+    return 0;
+}
+
+double orc_gauss_beam(double a0, double omega0, double w0, double tau, double t0, double x_focus,
+                      double y_center, double phase, double t, double y)
+{
+    const double L[8] = {a0, omega0, w0, tau, t0, x_focus, y_center, phase};
+    return gauss_beam(L, t, y);
+}
+
 void orc_maxwell(orc_sim *s)
 {
     if (s->morder == 6) {
@@ -449,8 +547,8 @@ void orc_maxwell(orc_sim *s)
         for (int64_t k = 0; k < nz; ++k)
             for (int64_t j = 0; j < s->fn[1]; ++j) {
                 int64_t t = j + s->fn[1] * k;
-                double eyi = laser_row(s, s->laser_ey, j, k);
-                double ezi = laser_row(s, s->laser_ez, j, k);
+                double eyi = incident(s, 1, j, k);
+                double ezi = incident(s, 2, j, k);
                 gbz0[t] = (4.0 * eyi - 2.0 * fget(s, 1, 0, j, k) - (1.0 - r) * fget(s, 5, 0, j, k)) / (1.0 + r);
                 gby0[t] = (2.0 * fget(s, 2, 0, j, k) - (1.0 - r) * fget(s, 4, 0, j, k) - 4.0 * ezi) / (1.0 + r);
                 gbz1[t] = (2.0 * fget(s, 1, nx, j, k) - (1.0 - r) * fget(s, 5, nx - 1, j, k)) / (1.0 + r);
@@ -604,6 +702,9 @@ void orc_destroy(orc_sim *s)
     free(s->count);
     free(s->laser_ey); free(s->laser_ez);
     free(s->win_dens);
+    if (s->jbuf)
+        for (int t = 0; t < 3 * s->jthreads; ++t) free(s->jbuf[t]);
+    free(s->jbuf);
     free(s);
 }
 
@@ -669,6 +770,166 @@ int orc_set_particles(orc_sim *s, int64_t n, const double *const xs[3],
     free(pid);
     s->next_id = n;
     return 0;
+}
+
+/* ---- particle loading from a species description ---------------------
+ *
+ * Random numbers: SplitMix64 (Steele, Lea and Flood, "Fast splittable
+ * pseudorandom number generators", OOPSLA 2014).  The generator adds the
+ * odd constant gamma = 0x9E3779B97F4A7C15 to its state and returns the state
+ * through two xor-shift-multiply rounds and a final xor-shift, so output n of
+ * the generator seeded with s depends only on s + (n + 1) gamma: any draw is
+ * reached directly from its counter.  Draw d (< 8) of particle g (the
+ * particle's index in generation order, < 2^41) in stream r uses counter
+ * r 2^44 + 8 g + d; a uniform double is the top 53 bits times 2^-53.
+ * Stream 0: positions, stream 1: momenta. */
+uint64_t orc_splitmix64(uint64_t seed, uint64_t n)
+{
+    uint64_t z = seed + (n + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+static double draw01(uint64_t seed, uint64_t stream, int64_t g, int d)
+{
+    const uint64_t c = (stream << 44) + ((uint64_t)g << 3) + (uint64_t)d;
+    return (double)(orc_splitmix64(seed, c) >> 11) * 0x1.0p-53;
+}
+
+/* Species description: profile 0 uniform n0; 1 vacuum below x0 = p[0], a
+ * linear ramp from 0 at x0 to n0 at x1 = p[1], then n0 (x0 on a cell face);
+ * 2 n0 (1 + p[0] cos(2 pi x / L_x)) with a sphere of centre (p[1], p[2],
+ * p[3]) and radius p[4] at p[5] n0 (evaluated at cell centres).  loading 0:
+ * ppc particles in every cell where the density is positive (profile 1:
+ * cells at or beyond x0), weight n(x) / ppc at the particle's position
+ * (profile 1) or the cell centre; loading 1: round(ppc n / n0) particles in a
+ * cell, weight n0 / ppc.  Lengths in c/omega_r.  temperature = kT / (m c^2):
+ * every momentum component Gaussian with sigma = sqrt(temperature) (Box-
+ * Muller on draws 0, 1 and 2, 3 of stream 1); 0 gives a cold species.
+ * Particles are made cell by cell in row-major order (x fastest), k = 0 ..
+ * count - 1 in a cell; that order is the id order.  A position is the cell
+ * index plus a uniform draw (draw a of stream 0 on axis a), kept below the
+ * cell's upper face. */
+typedef struct {
+    int profile, loading, ppc;
+    double n0, p[6], temperature;
+    uint64_t seed;
+} orc_species;
+
+static double density_at(const orc_sim *s, const orc_species *sp, const double xc[3])
+{
+    if (sp->profile == 1) {
+        const double X0 = sp->p[0] / s->g.d[0], X1 = sp->p[1] / s->g.d[0];
+        if (xc[0] < X0) return 0.0;
+        if (X1 <= X0 || xc[0] >= X1) return sp->n0;
+        return sp->n0 * ((xc[0] - X0) / (X1 - X0));
+    }
+    if (sp->profile == 2) {
+        double r2 = 0.0;
+        for (int a = 0; a < s->g.ndim; ++a) {
+            const double dd = xc[a] * s->g.d[a] - sp->p[1 + a];
+            r2 += dd * dd;
+        }
+        if (r2 <= sp->p[4] * sp->p[4]) return sp->p[5] * sp->n0;
+        return sp->n0 * (1.0 + sp->p[0] * cos(2.0 * M_PI * xc[0] / (double)s->g.n[0]));
+    }
+    return sp->n0;
+}
+
+static int cell_count(const orc_sim *s, const orc_species *sp, const int64_t c[3])
+{
+    double xc[3] = {(double)c[0] + 0.5, (double)c[1] + 0.5, (double)c[2] + 0.5};
+    if (sp->profile == 1) {
+        /* every cell at or beyond the ramp start holds plasma */
+        return (double)c[0] >= sp->p[0] / s->g.d[0] ? sp->ppc : 0;
+    }
+    const double n = density_at(s, sp, xc);
+    if (sp->loading == 1) return (int)rint((double)sp->ppc * n / sp->n0);
+    return n > 0.0 ? sp->ppc : 0;
+}
+
+int orc_particles_init(orc_sim *s, int profile, int loading, int ppc, double n0, const double *p,
+                       double temperature, uint64_t seed)
+{
+    orc_species sp;
+    memset(&sp, 0, sizeof(sp));
+    sp.profile = profile; sp.loading = loading; sp.ppc = ppc; sp.n0 = n0;
+    for (int i = 0; i < 6; ++i) sp.p[i] = p ? p[i] : 0.0;
+    sp.temperature = temperature; sp.seed = seed;
+    if (profile < 0 || profile > 2 || loading < 0 || loading > 1 || ppc < 1 || !(n0 > 0.0)) return -1;
+    const int nd = s->g.ndim;
+    const int64_t nc[3] = {s->g.n[0], s->g.n[1], nd == 3 ? s->g.n[2] : 1};
+    int64_t total = 0;
+    for (int64_t k = 0; k < nc[2]; ++k)
+        for (int64_t j = 0; j < nc[1]; ++j)
+            for (int64_t i = 0; i < nc[0]; ++i) {
+                const int64_t c[3] = {i, j, k};
+                total += cell_count(s, &sp, c);
+            }
+    double *xs[3], *us[3], *w = malloc(sizeof(double) * (total + 1));
+    for (int a = 0; a < 3; ++a) {
+        xs[a] = calloc(total + 1, sizeof(double));
+        us[a] = calloc(total + 1, sizeof(double));
+    }
+    const double sig = sqrt(temperature);
+    int64_t g = 0;
+    for (int64_t k = 0; k < nc[2]; ++k)
+        for (int64_t j = 0; j < nc[1]; ++j)
+            for (int64_t i = 0; i < nc[0]; ++i) {
+                const int64_t c[3] = {i, j, k};
+                const int cnt = cell_count(s, &sp, c);
+                for (int q = 0; q < cnt; ++q, ++g) {
+                    double x[3] = {0.0, 0.0, 0.0};
+                    for (int a = 0; a < nd; ++a) {
+                        x[a] = (double)c[a] + draw01(seed, 0, g, a);
+                        if (x[a] >= (double)(c[a] + 1)) x[a] = nextafter((double)(c[a] + 1), 0.0);
+                        xs[a][g] = x[a];
+                    }
+                    if (profile == 1) {
+                        w[g] = density_at(s, &sp, x) / ppc;
+                    } else {
+                        const double xc[3] = {(double)i + 0.5, (double)j + 0.5, (double)k + 0.5};
+                        w[g] = loading == 1 ? n0 / ppc : density_at(s, &sp, xc) / ppc;
+                    }
+                    if (temperature > 0.0) {
+                        const double r1 = sqrt(-2.0 * log(1.0 - draw01(seed, 1, g, 0)));
+                        const double r2 = sqrt(-2.0 * log(1.0 - draw01(seed, 1, g, 2)));
+                        const double f1 = 2.0 * M_PI * draw01(seed, 1, g, 1);
+                        const double f2 = 2.0 * M_PI * draw01(seed, 1, g, 3);
+                        us[0][g] = sig * r1 * cos(f1);
+                        us[1][g] = sig * r1 * sin(f1);
+                        us[2][g] = sig * r2 * cos(f2);
+                    }
+                }
+            }
+    const int rc = orc_set_particles(s, total, (const double *const *)xs, (const double *const *)us, w);
+    for (int a = 0; a < 3; ++a) { free(xs[a]); free(us[a]); }
+    free(w);
+    return rc;
+}
+
+/* Round the particle state to FP32 storage and back: positions become
+ * patch origin + (float)(x - origin), kept below the patch's upper face (the
+ * offset a patch-local FP32 position holds); momenta and weights become their
+ * nearest floats. */
+void orc_round_storage(orc_sim *s)
+{
+    for (int64_t q = 0; q < s->npart; ++q) {
+        double xi[3] = {s->x[0][q], s->x[1][q], s->x[2][q]};
+        const int p = patch_of(s, xi);
+        const int pc[3] = {p % s->np[0], (p / s->np[0]) % s->np[1], p / (s->np[0] * s->np[1])};
+        for (int a = 0; a < s->g.ndim; ++a) {
+            const double o = (double)(pc[a] * s->g.patch[a]);
+            float loc = (float)(s->x[a][q] - o);
+            const float top = nextafterf((float)s->g.patch[a], 0.0f);
+            if (loc > top) loc = top;
+            if (loc < 0.0f) loc = 0.0f;
+            s->x[a][q] = o + (double)loc;
+        }
+        for (int a = 0; a < 3; ++a) s->u[a][q] = (double)(float)s->u[a][q];
+        s->w[q] = (double)(float)s->w[q];
+    }
 }
 
 void orc_get_particles(const orc_sim *s, double *xo[3], double *uo[3], double *wo, int64_t *ido)
@@ -1111,9 +1372,26 @@ static void one_step(orc_sim *s)
     for (int c = 6; c < 9; ++c) memset(s->F[c], 0, sizeof(double) * s->fsize);
     int32_t *dest = malloc(sizeof(int32_t) * (s->npart + 1));
     double K = 0.0;
-    int64_t k = 0;
-    for (int p = 0; p < s->npatch; ++p)
-        for (int32_t sl = 0; sl < s->count[p]; ++sl, ++k) {
+#ifdef _OPENMP
+    /* timing build: threads push disjoint particle ranges and deposit into
+     * private current arrays, summed below in thread order */
+    const int nth = omp_get_max_threads();
+    if (nth > 1 && s->jthreads != nth) {
+        if (s->jbuf)
+            for (int t = 0; t < 3 * s->jthreads; ++t) free(s->jbuf[t]);
+        free(s->jbuf);
+        s->jbuf = malloc(sizeof(double *) * 3 * nth);
+        for (int t = 0; t < 3 * nth; ++t) s->jbuf[t] = malloc(sizeof(double) * s->fsize);
+        s->jthreads = nth;
+    }
+    if (nth > 1)
+        for (int t = 0; t < 3 * nth; ++t) memset(s->jbuf[t], 0, sizeof(double) * s->fsize);
+    double **jp = nth > 1 ? s->jbuf : NULL;
+    s->jpriv = jp;
+#pragma omp parallel for reduction(+ : K) schedule(static)
+#endif
+    for (int64_t k = 0; k < s->npart; ++k) {
+        {
             double x0[3] = {s->x[0][k], s->x[1][k], s->x[2][k]};
             double u[3] = {s->u[0][k], s->u[1][k], s->u[2][k]};
             double EB[6];
@@ -1139,6 +1417,14 @@ static void one_step(orc_sim *s)
             for (int a = 0; a < 3; ++a) { s->x[a][k] = x1[a]; s->u[a][k] = u[a]; }
             dest[k] = removed ? -1 : patch_of(s, x1);
         }
+    }
+#ifdef _OPENMP
+    if (jp)
+        for (int t = 0; t < nth; ++t)
+            for (int c = 0; c < 3; ++c)
+                for (int64_t f = 0; f < s->fsize; ++f) s->F[6 + c][f] += jp[3 * t + c][f];
+    s->jpriv = NULL;
+#endif
     s->K_last = K;
 
     orc_maxwell(s);

@@ -27,7 +27,9 @@ EXPORTS = (
     "pic_batch_add", "pic_batch_remove", "pic_batch_step", "pic_batch_finished",
     "pic_batch_size", "pic_estimate_bytes", "pic_autotune", "pic_state_save", "pic_state_load",
     "pic_patch_order", "pic_curve_segments", "pic_window_set", "pic_merge_set", "pic_merge",
-    "pic_rho_get_noalloc", "pic_strerror",
+    "pic_rho_get_noalloc", "pic_species_add", "pic_particles_init", "pic_laser_add",
+    "pic_perm_get", "pic_device_bytes", "pic_imbalance", "pic_step_set", "pic_autotune_patch",
+    "pic_strerror",
     "pic_last_error",
 )
 
@@ -50,11 +52,27 @@ class SimDesc(C.Structure):
     ]
 
 
+class SpeciesDesc(C.Structure):
+    _fields_ = [
+        ("q", C.c_double), ("m", C.c_double), ("profile", C.c_int32), ("loading", C.c_int32),
+        ("ppc", C.c_int32), ("reserved", C.c_int32), ("n0", C.c_double), ("param", C.c_double * 6),
+        ("temperature", C.c_double), ("seed", C.c_uint64),
+    ]
+
+
+class LaserDesc(C.Structure):
+    _fields_ = [
+        ("a0", C.c_double), ("omega0", C.c_double), ("w0", C.c_double), ("tau", C.c_double),
+        ("t0", C.c_double), ("x_focus", C.c_double), ("y_center", C.c_double), ("phase", C.c_double),
+        ("polarisation", C.c_int32), ("face", C.c_int32),
+    ]
+
+
 class TuneResult(C.Structure):
     _fields_ = [
         ("block", C.c_int32), ("field_tile", C.c_int32), ("lane_stride", C.c_int32),
         ("chunk", C.c_int32), ("ms_per_step", C.c_double), ("trials", C.c_int32),
-        ("from_cache", C.c_int32),
+        ("from_cache", C.c_int32), ("patch", C.c_int32 * 3),
     ]
 
 
@@ -72,13 +90,21 @@ class Diag(C.Structure):
         ("field_energy", C.c_double), ("kinetic_energy", C.c_double),
         ("occupancy_min", C.c_int32), ("occupancy_max", C.c_int32),
         ("occupancy_mean", C.c_double), ("flags", C.c_int32), ("relayouts", C.c_int32),
-        ("window_cells", C.c_int64), ("merged", C.c_int64),
+        ("window_cells", C.c_int64), ("merged", C.c_int64), ("device_bytes", C.c_int64),
     ]
 
 
 class Residuals(C.Structure):
     _fields_ = [("step", C.c_int64), ("gauss", C.c_double), ("continuity", C.c_double),
                 ("rho_max", C.c_double), ("rho0_max", C.c_double)]
+
+
+class Imbalance(C.Structure):
+    _fields_ = [("step", C.c_int64), ("items", C.c_int32), ("units", C.c_int32),
+                ("device_units", C.c_int32), ("span_us", C.c_double), ("busy_max_us", C.c_double),
+                ("busy_mean_us", C.c_double), ("imbalance", C.c_double),
+                ("static_imbalance", C.c_double), ("segment_imbalance", C.c_double),
+                ("patch_max_us", C.c_double), ("patch_mean_us", C.c_double)]
 
 
 class Timing(C.Structure):
@@ -125,6 +151,16 @@ def load() -> C.CDLL:
         "pic_diag_get": (C.c_int, [_vp, C.POINTER(Diag)]),
         "pic_residuals": (C.c_int, [_vp, C.POINTER(Residuals)]),
         "pic_rho_get_noalloc": (C.c_int, [_vp, _D, C.c_size_t]),
+        "pic_species_add": (C.c_int, [_vp, C.POINTER(SpeciesDesc), _I32]),
+        "pic_particles_init": (C.c_int, [_vp, C.c_int32]),
+        "pic_laser_add": (C.c_int, [_vp, C.POINTER(LaserDesc)]),
+        "pic_perm_get": (C.c_int, [_vp, _I64, C.c_size_t]),
+        "pic_device_bytes": (C.c_int, [_vp, _I64]),
+        "pic_imbalance": (C.c_int, [_vp, C.POINTER(Imbalance)]),
+        "pic_step_set": (C.c_int, [_vp, C.c_int64]),
+        "pic_autotune_patch": (C.c_int, [C.POINTER(SimDesc), C.POINTER(SpeciesDesc), C.POINTER(LaserDesc),
+                                         _I32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(Allocator), _vp,
+                                         C.c_char_p, C.POINTER(TuneResult)]),
         "pic_history_get": (C.c_int, [_vp, C.c_int64, C.c_int64, _D, _D, _I64]),
         "pic_rebin_codes": (C.c_int, [_vp, C.POINTER(C.c_uint8), C.c_size_t]),
         "pic_timing_enable": (C.c_int, [_vp, C.c_int]),

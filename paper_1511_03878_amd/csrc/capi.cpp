@@ -124,6 +124,43 @@ int pic_particles_set(PicSim *s, int64_t n, const double *x, const double *y, co
     });
 }
 
+int pic_species_add(PicSim *s, const PicSpeciesDesc *d, int32_t *sid)
+{
+    if (!s || !d) return bad(PIC_EINVAL, "null argument");
+    return guarded([&] {
+        s->impl->add_species(*d);
+        if (sid) *sid = 0;
+    });
+}
+
+int pic_particles_init(PicSim *s, int32_t sid)
+{
+    if (!s) return bad(PIC_EINVAL, "null handle");
+    if (sid != 0) return bad(PIC_EINVAL, "unknown species id");
+    return guarded([&] { s->impl->particles_init(); });
+}
+
+int pic_laser_add(PicSim *s, const PicLaserDesc *d)
+{
+    if (!s || !d) return bad(PIC_EINVAL, "null argument");
+    return guarded([&] { s->impl->add_laser(*d); });
+}
+
+int pic_perm_get(PicSim *s, int64_t *ids, size_t count)
+{
+    if (!s || !ids) return bad(PIC_EINVAL, "null argument");
+    return guarded([&] {
+        double *xo[3] = {nullptr, nullptr, nullptr}, *uo[3] = {nullptr, nullptr, nullptr};
+        s->impl->get_particles(xo, uo, nullptr, ids, count);
+    });
+}
+
+int pic_step_set(PicSim *s, int64_t step)
+{
+    if (!s) return bad(PIC_EINVAL, "null handle");
+    return guarded([&] { s->impl->set_step(step); });
+}
+
 int pic_window_set(PicSim *s, int64_t start_step, double velocity, int32_t ppc_x, int32_t ppc_y,
                    const double *density, int64_t ncols)
 {
@@ -241,6 +278,19 @@ int pic_rho_get_noalloc(PicSim *s, double *host, size_t count)
     return guarded([&] { s->impl->rho_noalloc(host, count); });
 }
 
+int pic_device_bytes(PicSim *s, int64_t *bytes)
+{
+    if (!s || !bytes) return bad(PIC_EINVAL, "null argument");
+    *bytes = (int64_t)s->impl->device_bytes();
+    return PIC_OK;
+}
+
+int pic_imbalance(PicSim *s, PicImbalance *out)
+{
+    if (!s || !out) return bad(PIC_EINVAL, "null argument");
+    return guarded([&] { s->impl->imbalance(out); });
+}
+
 int pic_diag_get(PicSim *s, PicDiag *out)
 {
     if (!s || !out) return bad(PIC_EINVAL, "null argument");
@@ -265,6 +315,7 @@ int pic_diag_get(PicSim *s, PicDiag *out)
         out->relayouts = s->impl->relayouts;
         out->window_cells = st.wshift * s->impl->desc.patch[0];
         out->merged = st.merged;
+        out->device_bytes = (int64_t)s->impl->device_bytes();
         if (st.step > 0) {
             double U = 0, K = 0;
             int64_t pushed = 0;
@@ -286,6 +337,22 @@ int pic_autotune(PicSim *s, int32_t steps, const char *cache, PicTuneResult *out
     if (!s) return bad(PIC_EINVAL, "null handle");
     if (steps < 0) return bad(PIC_EINVAL, "negative step count");
     return guarded([&] { s->impl->autotune(steps, cache, out); });
+}
+
+int pic_autotune_patch(PicSimDesc *d, const PicSpeciesDesc *sp, const PicLaserDesc *l,
+                       const int32_t *candidates, int32_t ncand, int32_t warm, int32_t steps,
+                       const PicAllocator *a, void *hip_stream, const char *cache,
+                       PicTuneResult *out)
+{
+    if (!d || !sp || !candidates) return bad(PIC_EINVAL, "null argument");
+    if (ncand <= 0 || warm < 0 || steps < 0) return bad(PIC_EINVAL, "bad candidate count or step counts");
+    std::string why;
+    int rc = validate_desc(*d, why);
+    if (rc != PIC_OK) return bad(rc, why.c_str());
+    if (a && (!a->alloc || !a->free)) return bad(PIC_EINVAL, "allocator needs both alloc and free");
+    return guarded([&] {
+        autotune_patch(*d, *sp, l, candidates, ncand, warm, steps, a, (hipStream_t)hip_stream, cache, out);
+    });
 }
 
 int pic_state_save(PicSim *s, void *blob, size_t *size)
@@ -318,11 +385,12 @@ int pic_rebin_codes(PicSim *s, const uint8_t *codes, size_t count)
 int pic_timing_enable(PicSim *s, int on)
 {
     if (!s) return bad(PIC_EINVAL, "null handle");
-    if (on < 0 || on > 2) return bad(PIC_EINVAL, "timing mode must be 0, 1 or 2");
+    if (on < 0 || on > 3) return bad(PIC_EINVAL, "timing mode must be 0, 1, 2 or 3");
     return guarded([&] {
         s->impl->timing.collect();
         s->impl->timing.enabled = on != 0;
-        s->impl->timing.only = on == 2 ? 1 : -1;
+        s->impl->timing.only = on >= 2 ? 1 : -1;
+        s->impl->timing.stamp = on == 3;
         if (on) {
             for (int k = 0; k < Timing::kKinds; ++k) {
                 s->impl->timing.total_ms[k] = 0;
@@ -405,6 +473,7 @@ int pic_estimate_bytes(const PicSimDesc *d, int64_t nparticles, int64_t laser_st
     // counts, keys, neighbour table, partials, offsets
     b += npatch * (4 * 7 + 4 * ndir + 4 * (3 * ndir - 1) + 8 + 8 + 4);
     b += max_tiles * 8 + 8 * 4 * 4096 + 4096;          // tile partials, history, state
+    b += 8 * fsize;                                    // charge density at load (diagnostics)
     b += laser_steps * d->n[1] * s * 2;
     *bytes = b;
     return PIC_OK;

@@ -159,7 +159,17 @@ __global__ void k_residual_final(const double *__restrict__ partials, int nblock
                                                  fmax(red[threadIdx.x][2], red[threadIdx.x][3]));
 }
 
+__global__ void k_copy_int(const int *__restrict__ src, int *__restrict__ dst)
+{
+    if (threadIdx.x == 0) *dst = *src;
+}
+
 }  // namespace
+
+void launch_copy_int(const int *src, int *dst, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_copy_int, dim3(1), dim3(64), 0, st, src, dst);
+}
 
 void fill_doubles(double *p, int64_t n, double v, hipStream_t st)
 {

@@ -24,6 +24,29 @@ namespace pic {
 
 namespace {
 
+// Field of a 2-D Gaussian beam at the x = 0 face at time t and transverse
+// position y.  L = {a0, omega0, w0, tau, t0, x_focus, y_center, phase}.
+// Paraxial beam in one transverse dimension: waist w0 at x_focus, Rayleigh
+// length z_R = omega0 w0^2 / 2; at the face (distance s = -x_focus from the
+// waist) the spot is w0 sqrt(1 + (s / z_R)^2), the wavefront curvature
+// s / (s^2 + z_R^2), the Gouy shift atan(s / z_R) / 2, and the amplitude
+// a0 omega0 sqrt(w0 / spot).  Envelope exp(-2 ln2 ((t - t0) / tau)^2), tau the
+// intensity FWHM; carrier sin(omega0 (t - t0) - omega0 y'^2 curv / 2 +
+// Gouy + phase), y' = y - y_center.  Evaluated in FP64.
+__device__ double beam_field(const double L[8], double t, double y)
+{
+    const double om = L[1], w0 = L[2], s = -L[5];
+    const double zr = 0.5 * om * w0 * w0;
+    const double spot = w0 * sqrt(1.0 + (s / zr) * (s / zr));
+    const double curv = s / (s * s + zr * zr);
+    const double gouy = 0.5 * atan2(s, zr);
+    const double yr = y - L[6], tr = (t - L[4]) / L[3];
+    const double env = exp(-2.0 * M_LN2 * tr * tr);
+    const double prof = exp(-(yr / spot) * (yr / spot));
+    const double ph = om * (t - L[4]) - 0.5 * om * yr * yr * curv + gouy + L[7];
+    return L[0] * om * sqrt(w0 / spot) * env * prof * sin(ph);
+}
+
 // Workgroups are dispatched to the 8 XCDs in turn (workgroup b to XCD b % 8),
 // and each XCD has its own L2.  Renumbering the workgroups XCD-major gives
 // every XCD a contiguous band of tiles, so the halo rows and columns a tile
@@ -155,6 +178,16 @@ __global__ __launch_bounds__(256) void k_maxwell2d(const SimDev<T> *__restrict__
                     if (ls < S.laser_steps) {
                         if (S.laser_ey) eyi = glb(S.laser_ey)[ls * n1 + gj];
                         if (S.laser_ez) ezi = glb(S.laser_ez)[ls * n1 + gj];
+                    }
+                    if (S.nlaser) {
+                        const double t = ((double)ls + 0.5) * S.wdt;
+                        double ey = 0.0, ez = 0.0;
+                        for (int l = 0; l < S.nlaser; ++l) {
+                            if (S.las_pol[l] == 1) ey += beam_field(S.las[l], t, ((double)gj + 0.5) * S.dd[1]);
+                            else ez += beam_field(S.las[l], t, (double)gj * S.dd[1]);
+                        }
+                        eyi += (T)ey;
+                        ezi += (T)ez;
                     }
                     const int c = b * W;  // a = 0 is x-node -1 (dual -1/2 for By, Bz)
                     sB[2][c] = (T(4) * eyi - T(2) * sE[1][c + 1] - (T(1) - r) * sB[2][c + 1]) * ir;

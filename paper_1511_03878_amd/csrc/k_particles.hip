@@ -10,6 +10,8 @@
 // single-GPU form of exchanging patches to even out load).
 #include <math.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 #include "particle_common.h"
 
@@ -39,7 +41,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
                                                        const Item *__restrict__ items,
                                                        const int *__restrict__ nitems,
                                                        int *__restrict__ head, int fstride_rt,
-                                                       int jstride_rt)
+                                                       int jstride_rt, ItemStamp *__restrict__ stamps)
 {
     const int fstride = PC ? (PC + 3) * (PC + 3) : fstride_rt;
     const int jstride = PC ? (PC + 5) * (PC + 5) : jstride_rt;
@@ -73,6 +75,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
         int next = 0;
         if (tid == 0) next = atomicAdd(head, 1);
         const Item it = items[idx];
+        const long long t_item = (stamps && tid == 0) ? wall_clock64() : 0;
         const int si = __builtin_amdgcn_readfirstlane(it.x & kItemSimMask);
         const int par = __builtin_amdgcn_readfirstlane(it.x >> 30);  // field level of this step
         const SimDev<T> &S = sims[si];
@@ -358,6 +361,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
             }
         }
         __syncthreads();
+        if (stamps && tid == 0) record_item(stamps + idx, t_item, si, p, it.w);
         idx = __builtin_amdgcn_readfirstlane(s_item[slot]);
         slot ^= 1;
     }
@@ -376,28 +380,29 @@ size_t lds_bytes(int maxP0, int maxP1, int &fstride, int &jstride)
 
 template <typename T, int BLOCK>
 static void launch_pc(int pc, const SimDev<T> *sims, const Item *items, const int *nitems, int *head,
-                      int grid, size_t lds, int fs, int js, hipStream_t st, Ev2 ev)
+                      int grid, size_t lds, int fs, int js, ItemStamp *stamps, hipStream_t st, Ev2 ev)
 {
     if (pc == 32)
         hipExtLaunchKernelGGL((k_particles2d<T, BLOCK, 32>), dim3(grid), dim3(BLOCK), lds, st,
-                              ev.start, ev.stop, 0, sims, items, nitems, head, fs, js);
+                              ev.start, ev.stop, 0, sims, items, nitems, head, fs, js, stamps);
     else if (pc == 16)
         hipExtLaunchKernelGGL((k_particles2d<T, BLOCK, 16>), dim3(grid), dim3(BLOCK), lds, st,
-                              ev.start, ev.stop, 0, sims, items, nitems, head, fs, js);
+                              ev.start, ev.stop, 0, sims, items, nitems, head, fs, js, stamps);
     else
         hipExtLaunchKernelGGL((k_particles2d<T, BLOCK, 0>), dim3(grid), dim3(BLOCK), lds, st,
-                              ev.start, ev.stop, 0, sims, items, nitems, head, fs, js);
+                              ev.start, ev.stop, 0, sims, items, nitems, head, fs, js, stamps);
 }
 
 template <typename T>
 void launch_particles(const SimDev<T> *sims, const Item *items, const int *nitems, int *head,
-                      int grid, int block, int maxP0, int maxP1, int pc, hipStream_t st, Ev2 ev)
+                      int grid, int block, int maxP0, int maxP1, int pc, ItemStamp *stamps,
+                      hipStream_t st, Ev2 ev)
 {
     int fs, js;
     size_t lds = lds_bytes<T>(maxP0, maxP1, fs, js);
-    if (block == 1024) launch_pc<T, 1024>(pc, sims, items, nitems, head, grid, lds, fs, js, st, ev);
-    else if (block == 512) launch_pc<T, 512>(pc, sims, items, nitems, head, grid, lds, fs, js, st, ev);
-    else launch_pc<T, 256>(pc, sims, items, nitems, head, grid, lds, fs, js, st, ev);
+    if (block == 1024) launch_pc<T, 1024>(pc, sims, items, nitems, head, grid, lds, fs, js, stamps, st, ev);
+    else if (block == 512) launch_pc<T, 512>(pc, sims, items, nitems, head, grid, lds, fs, js, stamps, st, ev);
+    else launch_pc<T, 256>(pc, sims, items, nitems, head, grid, lds, fs, js, stamps, st, ev);
 }
 
 template <typename T>
@@ -406,20 +411,25 @@ int particles_occupancy(int block, int maxP0, int maxP1)
     int fs, js, nb = 0;
     size_t lds = lds_bytes<T>(maxP0, maxP1, fs, js);
     hipError_t e;
-    if (block == 1024)
+    const void *f;
+    if (block == 1024) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particles2d<T, 1024, 0>, 1024, lds);
-    else if (block == 512)
+        f = (const void *)k_particles2d<T, 1024, 0>;
+    } else if (block == 512) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particles2d<T, 512, 0>, 512, lds);
-    else
+        f = (const void *)k_particles2d<T, 512, 0>;
+    } else {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particles2d<T, 256, 0>, 256, lds);
-    if (e != hipSuccess) return 0;
-    return nb;
+        f = (const void *)k_particles2d<T, 256, 0>;
+    }
+    const int own = resident_workgroups(f, block, lds);
+    return std::max(e == hipSuccess ? nb : 0, own);
 }
 
 template void launch_particles<float>(const SimDev<float> *, const Item *, const int *, int *, int,
-                                      int, int, int, int, hipStream_t, Ev2);
+                                      int, int, int, int, ItemStamp *, hipStream_t, Ev2);
 template void launch_particles<double>(const SimDev<double> *, const Item *, const int *, int *,
-                                       int, int, int, int, int, hipStream_t, Ev2);
+                                       int, int, int, int, int, ItemStamp *, hipStream_t, Ev2);
 template int particles_occupancy<float>(int, int, int);
 template int particles_occupancy<double>(int, int, int);
 

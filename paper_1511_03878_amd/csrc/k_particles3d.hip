@@ -6,9 +6,16 @@
 // FP64 LDS tile that is flushed to the global current once per item.
 //
 // Staggering (half a cell up): Ex, Ey, Ez along their own axis; Bx, By, Bz
-// along the two other axes.  The LDS holds the field tile of (P+3)^3 nodes
-// and the current tile of (P+5)^3 nodes, so the patch edge is limited (8
-// cells per axis fits twice over in one CU's LDS for FP32).
+// along the two other axes.  Each component's tile holds just the nodes its
+// stencil can reach from a particle of the patch: on an axis where the
+// component sits on primal nodes the gather reads nodes -1 .. P+1 (P + 3),
+// where it sits half a cell up -1 .. P (P + 2); the current J_a spans dual
+// nodes -2 .. P+1 along a (P + 4) and primal nodes -2 .. P+2 across (P + 5).
+// For 8^3-cell patches the two tiles take 76 KB (FP32 fields, FP64
+// currents), so two workgroups share a CU.  Patch shapes 8 x 8 x 8 and
+// 8 x 8 x 4 are compiled with constant tile pitches (LDS offsets become
+// instruction immediates); other shapes take the general kernel.
+#include <algorithm>
 #include <type_traits>
 
 #include "kernels.h"
@@ -39,11 +46,20 @@ __device__ __forceinline__ T gather27(const T *tile, int fw, int fwh, int i0, in
     return acc;
 }
 
-template <typename T, int BLOCK>
+// Per-component tile geometry: entries of component c along axis a.
+__host__ __device__ constexpr int fext(int P, int c, int a)
+{
+    // E_c is half a cell up along c; B_c along the two other axes
+    return P + 3 - (c < 3 ? (a == c ? 1 : 0) : (a == c - 3 ? 0 : 1));
+}
+__host__ __device__ constexpr int jext(int P, int c, int a) { return P + 5 - (a == c ? 1 : 0); }
+
+template <typename T, int BLOCK, int PX, int PY, int PZ>
 __global__ __launch_bounds__(BLOCK) void k_particles3d(const SimDev<T> *__restrict__ sims,
                                                        const Item *__restrict__ items,
                                                        const int *__restrict__ nitems,
-                                                       int *__restrict__ head)
+                                                       int *__restrict__ head,
+                                                       ItemStamp *__restrict__ stamps)
 {
     using W = typename std::conditional<sizeof(T) == 4, float, double>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -67,20 +83,42 @@ __global__ __launch_bounds__(BLOCK) void k_particles3d(const SimDev<T> *__restri
         int next = 0;
         if (tid == 0) next = atomicAdd(head, 1);
         const Item it = items[idx];
+        const long long t_item = (stamps && tid == 0) ? wall_clock64() : 0;
         const int si = __builtin_amdgcn_readfirstlane(it.x & kItemSimMask);
         const int par = __builtin_amdgcn_readfirstlane(it.x >> 30);
         const SimDev<T> &S = sims[si];
         const int p = __builtin_amdgcn_readfirstlane(it.y);
         const int64_t base = __builtin_amdgcn_readfirstlane(it.z);
         const int cnt = __builtin_amdgcn_readfirstlane(it.w);
-        const int P0 = S.P[0], P1 = S.P[1], P2 = S.P[2];
+        const int P0 = PX ? PX : S.P[0], P1 = PY ? PY : S.P[1], P2 = PZ ? PZ : S.P[2];
         const int pxi = p % S.np[0], pyi = (p / S.np[0]) % S.np[1], pzi = p / (S.np[0] * S.np[1]);
         const int ox = pxi * P0, oy = pyi * P1, oz = pzi * P2;
-        const int fw = P0 + 3, fh = P1 + 3, fd = P2 + 3, fwh = fw * fh;
-        const int jw = P0 + 5, jh = P1 + 5, jd = P2 + 5, jwh = jw * jh;
-        const int fstride = fwh * fd, jstride = jwh * jd;
+        // staging box (every component's tile fits in it) and current box
+        const int fw = P0 + 3, fh = P1 + 3, fwh = fw * fh, fstride = fwh * (P2 + 3);
+        const int jw = P0 + 5, jh = P1 + 5, jwh = jw * jh, jstride = jwh * (P2 + 5);
+        // component tiles: row pitch, plane pitch and start of each
+        int frow[6], fpl[6], fofs[6], jrow[3], jpl[3], jofs[3];
+        {
+            int o = 0;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                frow[c] = fext(P0, c, 0);
+                fpl[c] = frow[c] * fext(P1, c, 1);
+                fofs[c] = o;
+                o += fpl[c] * fext(P2, c, 2);
+            }
+            o = 0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                jrow[c] = jext(P0, c, 0);
+                jpl[c] = jrow[c] * jext(P1, c, 1);
+                jofs[c] = o;
+                o += jpl[c] * jext(P2, c, 2);
+            }
+        }
+        const int jtot = jofs[2] + jpl[2] * jext(P2, 2, 2);
         double *Jt = reinterpret_cast<double *>(smem_raw);
-        T *Ft = reinterpret_cast<T *>(Jt + 3 * jstride);
+        T *Ft = reinterpret_cast<T *>(Jt + jtot);
         const int n0 = S.n[0], n1 = S.n[1], n2 = S.n[2];
         const int fn0 = S.fn[0], fn1 = S.fn[1];
         if (si != kin_sim) {
@@ -134,12 +172,16 @@ __global__ __launch_bounds__(BLOCK) void k_particles3d(const SimDev<T> *__restri
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int t = t0 + r * BLOCK + tid;
-                if (t < fstride)
+                if (t < fstride) {
+                    const int a = t % fw, b = (t / fw) % fh, c = t / fwh;
 #pragma unroll
-                    for (int cc = 0; cc < 6; ++cc) Ft[cc * fstride + t] = v[r][cc];
+                    for (int cc = 0; cc < 6; ++cc)
+                        if (a < fext(P0, cc, 0) && b < fext(P1, cc, 1) && c < fext(P2, cc, 2))
+                            Ft[fofs[cc] + c * fpl[cc] + b * frow[cc] + a] = v[r][cc];
+                }
             }
         }
-        for (int t = tid; t < 3 * jstride; t += BLOCK) Jt[t] = 0.0;
+        for (int t = tid; t < jtot; t += BLOCK) Jt[t] = 0.0;
         __syncthreads();
         if (tid == 0) s_item[slot] = next;  // read after the item's last barrier
 
@@ -171,12 +213,12 @@ __global__ __launch_bounds__(BLOCK) void k_particles3d(const SimDev<T> *__restri
                 qweights(xs[a] - (T)ip[a], wp[a][0], wp[a][1], wp[a][2]);
                 qweights(xs[a] - (T)id[a] - T(0.5), wd[a][0], wd[a][1], wd[a][2]);
             }
-            const T Ex = gather27(Ft + 0 * fstride, fw, fwh, id[0], ip[1], ip[2], wd[0], wp[1], wp[2]);
-            const T Ey = gather27(Ft + 1 * fstride, fw, fwh, ip[0], id[1], ip[2], wp[0], wd[1], wp[2]);
-            const T Ez = gather27(Ft + 2 * fstride, fw, fwh, ip[0], ip[1], id[2], wp[0], wp[1], wd[2]);
-            const T Bx = gather27(Ft + 3 * fstride, fw, fwh, ip[0], id[1], id[2], wp[0], wd[1], wd[2]);
-            const T By = gather27(Ft + 4 * fstride, fw, fwh, id[0], ip[1], id[2], wd[0], wp[1], wd[2]);
-            const T Bz = gather27(Ft + 5 * fstride, fw, fwh, id[0], id[1], ip[2], wd[0], wd[1], wp[2]);
+            const T Ex = gather27(Ft + fofs[0], frow[0], fpl[0], id[0], ip[1], ip[2], wd[0], wp[1], wp[2]);
+            const T Ey = gather27(Ft + fofs[1], frow[1], fpl[1], ip[0], id[1], ip[2], wp[0], wd[1], wp[2]);
+            const T Ez = gather27(Ft + fofs[2], frow[2], fpl[2], ip[0], ip[1], id[2], wp[0], wp[1], wd[2]);
+            const T Bx = gather27(Ft + fofs[3], frow[3], fpl[3], ip[0], id[1], id[2], wp[0], wd[1], wd[2]);
+            const T By = gather27(Ft + fofs[4], frow[4], fpl[4], id[0], ip[1], id[2], wd[0], wp[1], wd[2]);
+            const T Bz = gather27(Ft + fofs[5], frow[5], fpl[5], id[0], id[1], ip[2], wd[0], wd[1], wp[2]);
 
             // ---- Boris --------------------------------------------------------
             const T usq0 = ux * ux + uy * uy + uz * uz;
@@ -254,8 +296,10 @@ __global__ __launch_bounds__(BLOCK) void k_particles3d(const SimDev<T> *__restri
                         py[k2] = py[k2 - 1] + dq * DSy[k2];
                         pz[k2] = pz[k2 - 1] + eq * DSz[k2];
                     }
-                    double *Jxt = Jt, *Jyt = Jt + jstride, *Jzt = Jt + 2 * jstride;
-                    const int r0 = (mz + 2) * jwh + (my + 2) * jw + (mx + 2);
+                    double *Jxt = Jt + jofs[0], *Jyt = Jt + jofs[1], *Jzt = Jt + jofs[2];
+                    const int rx = (mz + 2) * jpl[0] + (my + 2) * jrow[0] + (mx + 2);
+                    const int ry = (mz + 2) * jpl[1] + (my + 2) * jrow[1] + (mx + 2);
+                    const int rz = (mz + 2) * jpl[2] + (my + 2) * jrow[2] + (mx + 2);
                     const int ni = cx ? 3 : 2, nj = cy ? 3 : 2, nk = cz ? 3 : 2;
                     const int mi = cx ? 4 : 3, mj = cy ? 4 : 3, mk = cz ? 4 : 3;
                     // Jx: dual x (prefix index i), transverse (j, k)
@@ -269,7 +313,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles3d(const SimDev<T> *__restri
 #pragma unroll
                             for (int i = 0; i < 3; ++i) {
                                 if (i >= ni) break;
-                                atomicAdd(&Jxt[r0 + kk * jwh + j * jw + i], (double)(px[i] * tr));
+                                atomicAdd(&Jxt[rx + kk * jpl[0] + j * jrow[0] + i], (double)(px[i] * tr));
                             }
                         }
                     }
@@ -284,7 +328,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles3d(const SimDev<T> *__restri
 #pragma unroll
                             for (int j = 0; j < 3; ++j) {
                                 if (j >= nj) break;
-                                atomicAdd(&Jyt[r0 + kk * jwh + j * jw + i], (double)(py[j] * tr));
+                                atomicAdd(&Jyt[ry + kk * jpl[1] + j * jrow[1] + i], (double)(py[j] * tr));
                             }
                         }
                     }
@@ -299,7 +343,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles3d(const SimDev<T> *__restri
 #pragma unroll
                             for (int kk = 0; kk < 3; ++kk) {
                                 if (kk >= nk) break;
-                                atomicAdd(&Jzt[r0 + kk * jwh + j * jw + i], (double)(pz[kk] * tr));
+                                atomicAdd(&Jzt[rz + kk * jpl[2] + j * jrow[2] + i], (double)(pz[kk] * tr));
                             }
                         }
                     }
@@ -338,13 +382,17 @@ __global__ __launch_bounds__(BLOCK) void k_particles3d(const SimDev<T> *__restri
                 const int gj = axis_node(oy - 2 + b, n1, 1, 0);
                 const int gk = axis_node(oz - 2 + c, n2, 1, 0);
                 const int64_t k = gi + (int64_t)fn0 * (gj + (int64_t)fn1 * gk);
-                const T vx = (T)Jt[t], vy = (T)Jt[jstride + t], vz = (T)Jt[2 * jstride + t];
+                // entries outside a component's tile hold no current
+                const T vx = a < jrow[0] ? (T)Jt[jofs[0] + c * jpl[0] + b * jrow[0] + a] : T(0);
+                const T vy = b < jext(P1, 1, 1) ? (T)Jt[jofs[1] + c * jpl[1] + b * jrow[1] + a] : T(0);
+                const T vz = c < jext(P2, 2, 2) ? (T)Jt[jofs[2] + c * jpl[2] + b * jrow[2] + a] : T(0);
                 if (vx != T(0)) gadd(Jgx + k, vx);
                 if (vy != T(0)) gadd(Jgy + k, vy);
                 if (vz != T(0)) gadd(Jgz + k, vz);
             }
         }
         __syncthreads();
+        if (stamps && tid == 0) record_item(stamps + idx, t_item, si, p, it.w);
         idx = __builtin_amdgcn_readfirstlane(s_item[slot]);
         slot ^= 1;
     }
@@ -355,48 +403,68 @@ __global__ __launch_bounds__(BLOCK) void k_particles3d(const SimDev<T> *__restri
 
 size_t particles3d_lds_bytes(int precision, int P0, int P1, int P2)
 {
-    const size_t fs = (size_t)(P0 + 3) * (P1 + 3) * (P2 + 3);
-    const size_t js = (size_t)(P0 + 5) * (P1 + 5) * (P2 + 5);
-    return sizeof(double) * 3 * js + (size_t)(precision / 8) * 6 * fs;
+    size_t js = 0, fs = 0;
+    for (int c = 0; c < 3; ++c) js += (size_t)jext(P0, c, 0) * jext(P1, c, 1) * jext(P2, c, 2);
+    for (int c = 0; c < 6; ++c) fs += (size_t)fext(P0, c, 0) * fext(P1, c, 1) * fext(P2, c, 2);
+    return sizeof(double) * js + (size_t)(precision / 8) * fs;
+}
+
+namespace {
+
+// The kernel for a launch: shape 1 = every patch 8 x 8 x 8, 2 = 8 x 8 x 4,
+// 0 = general.
+template <typename T, int BLOCK>
+auto kernel_for(int shape) -> decltype(&k_particles3d<T, BLOCK, 0, 0, 0>)
+{
+    if (shape == 1) return &k_particles3d<T, BLOCK, 8, 8, 8>;
+    if (shape == 2) return &k_particles3d<T, BLOCK, 8, 8, 4>;
+    return &k_particles3d<T, BLOCK, 0, 0, 0>;
+}
+
+template <typename T>
+auto kernel_for(int block, int shape) -> decltype(&k_particles3d<T, 512, 0, 0, 0>)
+{
+    if (block == 1024) return kernel_for<T, 1024>(shape);
+    if (block == 256) return kernel_for<T, 256>(shape);
+    return kernel_for<T, 512>(shape);
+}
+
+}  // namespace
+
+int particles3d_shape(int P0, int P1, int P2)
+{
+    if (P0 == 8 && P1 == 8 && P2 == 8) return 1;
+    if (P0 == 8 && P1 == 8 && P2 == 4) return 2;
+    return 0;
 }
 
 template <typename T>
 void launch_particles3d(const SimDev<T> *sims, const Item *items, const int *nitems, int *head,
-                        int grid, int block, int maxP0, int maxP1, int maxP2, hipStream_t st,
-                        Ev2 ev)
+                        int grid, int block, int maxP0, int maxP1, int maxP2, int shape,
+                        ItemStamp *stamps, hipStream_t st, Ev2 ev)
 {
     const size_t lds = particles3d_lds_bytes(sizeof(T) * 8, maxP0, maxP1, maxP2);
-    if (block == 1024)
-        hipExtLaunchKernelGGL((k_particles3d<T, 1024>), dim3(grid), dim3(1024), lds, st, ev.start,
-                              ev.stop, 0, sims, items, nitems, head);
-    else if (block == 256)
-        hipExtLaunchKernelGGL((k_particles3d<T, 256>), dim3(grid), dim3(256), lds, st, ev.start,
-                              ev.stop, 0, sims, items, nitems, head);
-    else
-        hipExtLaunchKernelGGL((k_particles3d<T, 512>), dim3(grid), dim3(512), lds, st, ev.start,
-                              ev.stop, 0, sims, items, nitems, head);
+    const int b = block == 1024 || block == 256 ? block : 512;
+    hipExtLaunchKernelGGL(kernel_for<T>(b, shape), dim3(grid), dim3(b), lds, st, ev.start, ev.stop, 0, sims,
+                          items, nitems, head, stamps);
 }
 
 template <typename T>
-int particles3d_occupancy(int block, int maxP0, int maxP1, int maxP2)
+int particles3d_occupancy(int block, int maxP0, int maxP1, int maxP2, int shape)
 {
     const size_t lds = particles3d_lds_bytes(sizeof(T) * 8, maxP0, maxP1, maxP2);
+    const int b = block == 1024 || block == 256 ? block : 512;
     int nb = 0;
-    hipError_t e;
-    if (block == 1024)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particles3d<T, 1024>, 1024, lds);
-    else if (block == 256)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particles3d<T, 256>, 256, lds);
-    else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particles3d<T, 512>, 512, lds);
-    return e == hipSuccess ? nb : 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel_for<T>(b, shape), b, lds);
+    const int own = resident_workgroups((const void *)kernel_for<T>(b, shape), b, lds);
+    return std::max(e == hipSuccess ? nb : 0, own);
 }
 
 template void launch_particles3d<float>(const SimDev<float> *, const Item *, const int *, int *, int,
-                                        int, int, int, int, hipStream_t, Ev2);
+                                        int, int, int, int, int, ItemStamp *, hipStream_t, Ev2);
 template void launch_particles3d<double>(const SimDev<double> *, const Item *, const int *, int *,
-                                         int, int, int, int, int, hipStream_t, Ev2);
-template int particles3d_occupancy<float>(int, int, int, int);
-template int particles3d_occupancy<double>(int, int, int, int);
+                                         int, int, int, int, int, int, ItemStamp *, hipStream_t, Ev2);
+template int particles3d_occupancy<float>(int, int, int, int, int);
+template int particles3d_occupancy<double>(int, int, int, int, int);
 
 }  // namespace pic

@@ -14,11 +14,56 @@ struct Ev2 {
     hipEvent_t start = nullptr, stop = nullptr;
 };
 
+// Workgroups of `func` (block threads, dyn_lds bytes of dynamic LDS) that fit
+// on one CU together, from the kernel's own register and LDS use: 512 VGPRs
+// per SIMD lane (allocated in granules of 8), 8 wave slots per SIMD, and the
+// device's LDS per CU (160 KB on gfx950).  The runtime's occupancy query
+// caps LDS lower, so the larger of the two answers sizes persistent grids
+// (a workgroup that cannot be resident at once just starts later).
+inline int resident_workgroups(const void *func, int block, size_t dyn_lds)
+{
+    hipFuncAttributes a;
+    if (hipFuncGetAttributes(&a, func) != hipSuccess) return 0;
+    int dev = 0, lds_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess)
+        return 0;
+    const int waves = (block + 63) / 64, per_simd = (waves + 3) / 4;
+    const int regs = ((a.numRegs > 0 ? a.numRegs : 1) + 7) / 8 * 8;
+    const int by_regs = (512 / regs) / per_simd;
+    const size_t lds = dyn_lds + a.sharedSizeBytes;
+    const int by_lds = lds ? (int)((size_t)lds_cu / lds) : 64;
+    const int by_slots = 32 / waves;
+    int n = by_regs < by_lds ? by_regs : by_lds;
+    return n < by_slots ? n : by_slots;
+}
+
 // Work item of the particle kernel: {simulation slot | parity of the step
 // << 30, patch, slot of the item's first particle in the simulation's
 // particle arrays, count}.
 using Item = int4;
 constexpr int kItemSimMask = (1 << 30) - 1;
+
+// Optional per-item record of a particle launch (diagnostics): start and end
+// of the item on the device's constant-rate clock, the compute unit that ran
+// it (__smid: XCD, shader engine and CU ids), its simulation slot, patch and
+// particle count.  Written by thread 0 of the workgroup with vector stores.
+struct ItemStamp {
+    long long t0, t1;
+    int hw, sim, patch, count;
+};
+
+__device__ __forceinline__ void record_item(ItemStamp *r, long long t0, int sim, int patch, int count)
+{
+    ItemStamp v;
+    v.t0 = t0;
+    v.t1 = wall_clock64();
+    v.hw = (int)__smid();
+    v.sim = sim;
+    v.patch = patch;
+    v.count = count;
+    *r = v;
+}
 
 struct QueueArgs {
     int nsims;
@@ -41,21 +86,25 @@ void launch_close_queue(const SimDev<T> *sims, const QueueArgs &q, hipStream_t s
 // for the specialised kernel, 0 for the general one.
 template <typename T>
 void launch_particles(const SimDev<T> *sims, const Item *items, const int *nitems, int *head,
-                      int grid, int block, int maxP0, int maxP1, int pc, hipStream_t st,
-                      Ev2 ev = {});
+                      int grid, int block, int maxP0, int maxP1, int pc, ItemStamp *stamps,
+                      hipStream_t st, Ev2 ev = {});
 template <typename T>
 int particles_occupancy(int block, int maxP0, int maxP1);
 
 // 3-D particle kernel (periodic boxes): 27-node gather, Boris, move, 26-way
 // classification, Esirkepov deposit on a 4x4x4 window.  LDS per workgroup:
 // particles3d_lds_bytes(precision, largest patch edges).
+// shape: particles3d_shape() of the common patch shape of every simulation
+// in the launch (1: 8 x 8 x 8, 2: 8 x 8 x 4, compiled with constant tile
+// pitches), 0 for the general kernel.
 template <typename T>
 void launch_particles3d(const SimDev<T> *sims, const Item *items, const int *nitems, int *head,
-                        int grid, int block, int maxP0, int maxP1, int maxP2, hipStream_t st,
-                        Ev2 ev = {});
+                        int grid, int block, int maxP0, int maxP1, int maxP2, int shape,
+                        ItemStamp *stamps, hipStream_t st, Ev2 ev = {});
 template <typename T>
-int particles3d_occupancy(int block, int maxP0, int maxP1, int maxP2);
+int particles3d_occupancy(int block, int maxP0, int maxP1, int maxP2, int shape);
 size_t particles3d_lds_bytes(int precision, int P0, int P1, int P2);
+int particles3d_shape(int P0, int P1, int P2);
 
 // 3-D Yee update on a periodic box (three passes; tiles are blocks of 256
 // nodes), with the field energy of the incoming E, B per tile.
@@ -111,6 +160,25 @@ void launch_residuals(const SimDev<T> *sim, int ndim, int64_t fsize, int fpar, i
                       const double *rho, const double *rho0, const double *rho_prev,
                       double *partials, double *out, hipStream_t st);
 int residual_partials();
+// copy *src to *dst on the stream (one thread)
+void launch_copy_int(const int *src, int *dst, hipStream_t st);
+
+// Particle loading from a species description (k_init.hip): count the
+// particles of every row segment (one grid row inside one patch column,
+// nseg = rows x patch columns), then write them into their patch slots
+// given each segment's first id and first slot inside its patch.
+constexpr int kProfileUniform = 0, kProfileRamp = 1, kProfileCosSphere = 2;
+constexpr int kLoadWeight = 0, kLoadCount = 1;
+struct InitSpec {
+    int profile, loading, ppc, nd;
+    int n[3], P[3], np[3];
+    double n0, p[6], sigma, d[3];
+    uint64_t seed;
+};
+void launch_init_count(const InitSpec &sp, int64_t nseg, int64_t *seg, hipStream_t st);
+template <typename T>
+void launch_init_fill(const InitSpec &sp, int64_t nseg, const int64_t *first, const int32_t *slot0,
+                      const SimDev<T> *sim, hipStream_t st);
 
 // Set the destination codes of all live particles from a packed host-supplied
 // array in (patch, slot) order.

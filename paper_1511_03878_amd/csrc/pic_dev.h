@@ -21,6 +21,7 @@ namespace pic {
 constexpr int kMaxPatch = 64;      // cells per patch per axis
 constexpr int kHistLen = 4096;     // energy-history ring length
 constexpr int kMaxBatch = 2048;    // simulations per batch
+constexpr int kMaxLasers = 4;      // Gaussian lasers per simulation
 constexpr int kNDir2 = 9;          // neighbour directions in 2-D (4 = stay)
 constexpr int kStay2 = 4;
 constexpr int kNDir3 = 27;         // neighbour directions in 3-D (13 = stay)
@@ -102,6 +103,12 @@ struct SimDev {
     const int32_t *porder;  // queue order of the patches (position -> patch id), or null: id order
     const T *laser_ey, *laser_ez;
     int64_t laser_steps;
+    // Gaussian lasers through x = 0, evaluated in FP64 every step: a0, omega0,
+    // w0, tau, t0, x_focus, y_center, phase; polarisation 1 (Ey) or 2 (Ez)
+    int nlaser;
+    int las_pol[kMaxLasers];
+    double las[kMaxLasers][8];
+    double dd[3];      // cell sizes in FP64
     SimState *st;
     double *hist;      // [kHistLen][4]: U, K, pushed, removed
     const int32_t *nbt; // neighbour table, kNbStride entries per patch

@@ -9,6 +9,8 @@
 #include <fstream>
 
 #include <algorithm>
+#include <memory>
+#include <climits>
 #include <limits>
 #include <cmath>
 #include <cstring>
@@ -454,6 +456,14 @@ void SimImpl<T>::refresh_view()
     V.moved = moved_d;
     V.porder = porder_d;
     V.laser_ey = laser_ey; V.laser_ez = laser_ez; V.laser_steps = laser_steps;
+    V.nlaser = (int)lasers.size();
+    for (int l = 0; l < V.nlaser; ++l) {
+        const PicLaserDesc &L = lasers[l];
+        const double vals[8] = {L.a0, L.omega0, L.w0, L.tau, L.t0, L.x_focus, L.y_center, L.phase};
+        for (int c = 0; c < 8; ++c) V.las[l][c] = vals[c];
+        V.las_pol[l] = L.polarisation;
+    }
+    for (int a = 0; a < 3; ++a) V.dd[a] = a < nd ? desc.d[a] : 1.0;
     V.st = st; V.hist = hist; V.upart = upart; V.kpart = kpart; V.nbt = nbt_d;
     hipcheck(hipMemcpyAsync(view_d, &v, sizeof(v), hipMemcpyHostToDevice, stream), "view upload");
     ++layout_version;
@@ -515,15 +525,144 @@ void SimImpl<T>::set_particles(int64_t cnt, const double *const xs[3], const dou
     hipcheck(hipMemcpyAsync(pw, hw.data(), sizeof(T) * tot, hipMemcpyHostToDevice, stream), "w");
     hipcheck(hipMemcpyAsync(pid, hid.data(), sizeof(int64_t) * tot, hipMemcpyHostToDevice, stream), "id");
     hipcheck(hipMemsetAsync(code, ndir / 2, tot, stream), "code");
+    finish_load(counts, cnt);
+}
+
+// Common end of a particle load: counts, a fresh state block (step 0), the
+// load-time charge density.
+template <typename T>
+void SimImpl<T>::finish_load(const std::vector<int32_t> &counts, int64_t total)
+{
     hipcheck(hipMemcpyAsync(counts_d, counts.data(), sizeof(int32_t) * npatch, hipMemcpyHostToDevice, stream), "counts");
+    hipcheck(hipMemsetAsync(moved_d, 1, sizeof(int32_t) * npatch, stream), "moved");
     SimState s0;
     std::memset(&s0, 0, sizeof(s0));
-    s0.next_id = cnt;
+    s0.next_id = total;
     hipcheck(hipMemcpyAsync(st, &s0, sizeof(s0), hipMemcpyHostToDevice, stream), "state");
     hipcheck(hipStreamSynchronize(stream), "sync");
     relayouts = 0;
     if (solo) solo->dirty = true;
     record_rho0();
+}
+
+// Species description (one species per simulation; the immobile neutralising
+// ions are implicit: their charge is minus the species' charge at load).
+template <typename T>
+void SimImpl<T>::add_species(const PicSpeciesDesc &sp)
+{
+    check_free();
+    if (has_species) throw Error(PIC_ENOTSUP, "one species per simulation");
+    if (sp.q != desc.q || sp.m != desc.m) throw Error(PIC_EINVAL, "species charge and mass must equal the descriptor's");
+    if (sp.profile < 0 || sp.profile > 2) throw Error(PIC_EINVAL, "unknown density profile");
+    if (sp.loading < 0 || sp.loading > 1) throw Error(PIC_EINVAL, "unknown loading rule");
+    if (sp.ppc < 1 || sp.ppc > 4096) throw Error(PIC_EINVAL, "ppc must be 1..4096");
+    if (!(sp.n0 > 0.0) || !(sp.temperature >= 0.0) || !std::isfinite(sp.temperature))
+        throw Error(PIC_EINVAL, "n0 must be positive and the temperature finite and non-negative");
+    for (double v : sp.param)
+        if (!std::isfinite(v)) throw Error(PIC_EINVAL, "profile parameters must be finite");
+    if (sp.profile == PIC_PROFILE_COS_SPHERE && (sp.param[4] < 0.0 || sp.param[5] < 0.0 || std::fabs(sp.param[0]) > 1.0))
+        throw Error(PIC_EINVAL, "cosine modulation above 1 or negative sphere radius / factor");
+    species = sp;
+    has_species = true;
+}
+
+// Generate the species' particles on the device (see k_init.hip).
+template <typename T>
+void SimImpl<T>::particles_init()
+{
+    check_free();
+    if (!has_species) throw Error(PIC_ESTATE, "no species added");
+    InitSpec sp;
+    std::memset(&sp, 0, sizeof(sp));
+    sp.profile = species.profile;
+    sp.loading = species.loading;
+    sp.ppc = species.ppc;
+    sp.nd = nd;
+    sp.n0 = species.n0;
+    for (int i = 0; i < 6; ++i) sp.p[i] = species.param[i];
+    sp.sigma = std::sqrt(species.temperature);
+    sp.seed = species.seed;
+    for (int a = 0; a < 3; ++a) {
+        sp.n[a] = n[a];
+        sp.P[a] = P[a];
+        sp.np[a] = np[a];
+        sp.d[a] = a < nd ? desc.d[a] : 1.0;
+    }
+    const int64_t nseg = (int64_t)n[1] * n[2] * np[0];
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    int64_t *seg_d = (int64_t *)alloc.get(sizeof(int64_t) * nseg);
+    std::vector<int64_t> seg(nseg);
+    launch_init_count(sp, nseg, seg_d, stream);
+    hipcheck(hipGetLastError(), "init count launch");
+    hipcheck(hipMemcpyAsync(seg.data(), seg_d, sizeof(int64_t) * nseg, hipMemcpyDeviceToHost, stream), "segments");
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    alloc.put(seg_d);
+    // first id of every segment (row-major order) and its first slot in its
+    // patch (segments of a patch come in the patch's own row-major order)
+    std::vector<int64_t> first(nseg);
+    std::vector<int32_t> slot0(nseg), counts(npatch, 0);
+    std::vector<int64_t> pcount(npatch, 0);
+    int64_t total = 0;
+    for (int64_t s_ = 0; s_ < nseg; ++s_) {
+        first[s_] = total;
+        total += seg[s_];
+        const int px = (int)(s_ % np[0]);
+        const int64_t r = s_ / np[0];
+        const int j = (int)(r % n[1]), k = (int)(r / n[1]);
+        const int p = px + np[0] * (j / P[1] + np[1] * (k / P[2]));
+        slot0[s_] = (int32_t)pcount[p];
+        pcount[p] += seg[s_];
+        if (pcount[p] > INT32_MAX / 4) throw Error(PIC_EOVERFLOW, "too many particles in one patch");
+    }
+    if (total >= ((int64_t)1 << 41)) throw Error(PIC_EINVAL, "too many particles");
+    for (int p = 0; p < npatch; ++p) counts[p] = (int32_t)pcount[p];
+    lane_stride = desc.lane_stride ? desc.lane_stride : 2;
+    std::vector<void *> old = layout_particles(counts);
+    for (void *p : old) alloc.put(p);
+    const int64_t tot = total_cap;
+    for (int a = 0; a < nd; ++a) hipcheck(hipMemsetAsync(px[a], 0, sizeof(T) * tot, stream), "clear x");
+    for (int a = 0; a < 3; ++a) hipcheck(hipMemsetAsync(pu[a], 0, sizeof(T) * tot, stream), "clear u");
+    hipcheck(hipMemsetAsync(pw, 0, sizeof(T) * tot, stream), "clear w");
+    hipcheck(hipMemsetAsync(pid, 0xff, sizeof(int64_t) * tot, stream), "clear id");
+    hipcheck(hipMemsetAsync(code, ndir / 2, tot, stream), "code");
+    int64_t *first_d = (int64_t *)alloc.get(sizeof(int64_t) * nseg);
+    int32_t *slot_d = nullptr;
+    try {
+        slot_d = (int32_t *)alloc.get(sizeof(int32_t) * nseg);
+    } catch (...) {
+        alloc.put(first_d);
+        throw;
+    }
+    hipcheck(hipMemcpyAsync(first_d, first.data(), sizeof(int64_t) * nseg, hipMemcpyHostToDevice, stream), "first ids");
+    hipcheck(hipMemcpyAsync(slot_d, slot0.data(), sizeof(int32_t) * nseg, hipMemcpyHostToDevice, stream), "first slots");
+    launch_init_fill<T>(sp, nseg, first_d, slot_d, view_d, stream);
+    hipcheck(hipGetLastError(), "init fill launch");
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    alloc.put(first_d);
+    alloc.put(slot_d);
+    finish_load(counts, total);
+}
+
+// Gaussian laser through the open x = 0 face (2-D), evaluated by the Yee
+// kernel every step.
+template <typename T>
+void SimImpl<T>::add_laser(const PicLaserDesc &l)
+{
+    check_free();
+    if (nd != 2) throw Error(PIC_ENOTSUP, "laser injection needs an open x face (2-D boxes)");
+    if (periodic[0]) throw Error(PIC_EINVAL, "laser injection needs an open x axis");
+    if (l.face != 0) throw Error(PIC_ENOTSUP, "only the x = 0 face takes a laser");
+    if ((int)lasers.size() >= kMaxLasers) throw Error(PIC_ENOTSUP, "at most four lasers");
+    if (l.polarisation != 1 && l.polarisation != 2) throw Error(PIC_EINVAL, "polarisation must be 1 (Ey) or 2 (Ez)");
+    const double v[8] = {l.a0, l.omega0, l.w0, l.tau, l.t0, l.x_focus, l.y_center, l.phase};
+    for (double x : v)
+        if (!std::isfinite(x)) throw Error(PIC_EINVAL, "laser parameters must be finite");
+    if (!(l.a0 >= 0.0 && l.omega0 > 0.0 && l.w0 > 0.0 && l.tau > 0.0))
+        throw Error(PIC_EINVAL, "a0 >= 0, omega0 > 0, w0 > 0 and tau > 0 are required");
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    lasers.push_back(l);
+    refresh_view();
+    hipcheck(hipStreamSynchronize(stream), "sync");
 }
 
 // Charge density of the particles as loaded: the reference of the Gauss
@@ -563,6 +702,84 @@ void SimImpl<T>::rho_noalloc(double *h, size_t count)
 // The paper's imbalance measure (section 3.1, Fig. 4: time of the busiest
 // unit over the mean) from the item stamps of the last stamped particle
 // launch: per compute unit, the summed time of this simulation's items.
+template <typename T>
+void SimImpl<T>::imbalance(PicImbalance *out)
+{
+    BatchImpl<T> *b = batch ? batch : solo;
+    if (!b || !b->stamps_d || b->dirty) throw Error(PIC_ESTATE, "no particle launch has been stamped");
+    int slot = -1;
+    for (size_t i = 0; i < b->members.size(); ++i)
+        if (b->members[i] == this) slot = (int)i;
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    int n = 0;
+    hipcheck(hipMemcpy(&n, b->stamp_n_d, sizeof(int), hipMemcpyDeviceToHost), "stamp count");
+    n = std::max(0, std::min(n, b->table_cap_items));
+    std::vector<ItemStamp> rec(n);
+    if (n) hipcheck(hipMemcpy(rec.data(), b->stamps_d, sizeof(ItemStamp) * n, hipMemcpyDeviceToHost), "stamps");
+    int dev = 0, khz = 0;
+    hipcheck(hipGetDevice(&dev), "device");
+    hipcheck(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev), "clock rate");
+    if (khz <= 0) throw Error(PIC_EHIP, "no device clock rate");
+    const double us = 1000.0 / khz;
+    std::map<int, double> busy;
+    std::vector<double> pcost(npatch, 0.0);
+    long long t_lo = LLONG_MAX, t_hi = LLONG_MIN;
+    int items = 0;
+    for (const ItemStamp &r : rec) {
+        if (r.sim != slot || r.t1 < r.t0 || r.patch < 0 || r.patch >= npatch) continue;
+        const double d = (double)(r.t1 - r.t0) * us;
+        busy[r.hw] += d;
+        pcost[r.patch] += d;
+        t_lo = std::min(t_lo, r.t0);
+        t_hi = std::max(t_hi, r.t1);
+        ++items;
+    }
+    if (!items) throw Error(PIC_ESTATE, "the stamped launch ran no item of this simulation");
+    const int ncu = cu_count();
+    double tot = 0.0, mx = 0.0;
+    for (auto &kv : busy) {
+        tot += kv.second;
+        mx = std::max(mx, kv.second);
+    }
+    // the same item times dealt to the CUs as fixed domains: equal runs of
+    // patch ids, or curve segments cut by particle count (section 3.1)
+    auto worst = [&](const std::vector<int64_t> &bounds, const std::vector<int32_t> &order) {
+        double w = 0.0;
+        for (int r = 0; r < ncu; ++r) {
+            double c = 0.0;
+            for (int64_t q = bounds[r]; q < bounds[r + 1]; ++q) c += pcost[order[q]];
+            w = std::max(w, c);
+        }
+        return w;
+    };
+    std::vector<int32_t> ids(npatch);
+    std::iota(ids.begin(), ids.end(), 0);
+    std::vector<int64_t> eq(ncu + 1);
+    for (int r = 0; r <= ncu; ++r) eq[r] = (int64_t)r * npatch / ncu;
+    std::vector<int32_t> curve;
+    std::string why;
+    const int npc[3] = {np[0], np[1], nd == 3 ? np[2] : 1};
+    if (hilbert_patch_order(nd, npc, curve, why) != PIC_OK) curve = ids;
+    std::vector<int32_t> cnt = read_counts();
+    std::vector<int64_t> cost(npatch), seg(ncu + 1);
+    for (int q = 0; q < npatch; ++q) cost[q] = cnt[curve[q]];
+    curve_segments(cost.data(), npatch, ncu, seg.data());
+    const double mean = tot / ncu;
+    const SimState s = read_state();
+    out->step = s.step;
+    out->items = items;
+    out->units = (int32_t)busy.size();
+    out->device_units = ncu;
+    out->span_us = (double)(t_hi - t_lo) * us;
+    out->busy_max_us = mx;
+    out->busy_mean_us = mean;
+    out->imbalance = mean > 0 ? mx / mean : 0.0;
+    out->static_imbalance = mean > 0 ? worst(eq, ids) / mean : 0.0;
+    out->segment_imbalance = mean > 0 ? worst(seg, curve) / mean : 0.0;
+    out->patch_max_us = *std::max_element(pcost.begin(), pcost.end());
+    out->patch_mean_us = tot / npatch;
+}
+
 // Gauss and continuity residuals of the current state (see k_diag.hip).
 template <typename T>
 void SimImpl<T>::residuals(PicResiduals *out)
@@ -711,6 +928,23 @@ void SimImpl<T>::sync_layout()
     hipcheck(hipMemcpyAsync(cap_h.data(), cap_d, sizeof(int32_t) * npatch, hipMemcpyDeviceToHost, stream), "cap");
     hipcheck(hipMemcpyAsync(off_h.data(), off_d, sizeof(int64_t) * (npatch + 1), hipMemcpyDeviceToHost, stream), "off");
     hipcheck(hipStreamSynchronize(stream), "sync");
+}
+
+template <typename T>
+void SimImpl<T>::set_step(int64_t step)
+{
+    check_free();
+    if (step < 0) throw Error(PIC_EINVAL, "negative step");
+    SimState s = read_state();
+    if (s.flags & kFlagPending) throw Error(PIC_ESTATE, "a re-binning is pending");
+    // the current E, B move to the buffer of the new step's parity
+    if ((s.step & 1) != (step & 1))
+        for (int c = 0; c < 6; ++c)
+            hipcheck(hipMemcpyAsync(F[step & 1][c], F[s.step & 1][c], sizeof(T) * fsize, hipMemcpyDeviceToDevice, stream), "fields");
+    s.step = step;
+    hipcheck(hipMemcpyAsync(&st->step, &s.step, sizeof(int64_t), hipMemcpyHostToDevice, stream), "step");
+    hipcheck(hipStreamSynchronize(stream), "sync");
+    rhoprev_step = -1;
 }
 
 template <typename T>
@@ -1078,10 +1312,89 @@ void SimImpl<T>::autotune(int steps, const char *cache, PicTuneResult *out)
     res.lane_stride = best.lane_stride;
     res.chunk = best.chunk;
     res.ms_per_step = best_ms;
+    for (int i = 0; i < 3; ++i) res.patch[i] = P[i];
     if (cache) {
         std::ofstream f(cache, std::ios::app);
         f << key << ' ' << best.block << ' ' << best.field_tile << ' ' << best.lane_stride << ' ' << best.chunk
           << '\n';
+    }
+    if (out) *out = res;
+}
+
+// Patch-size tuner: temporary simulations of the descriptor at every
+// candidate patch edge, loaded from the species description on the device.
+void autotune_patch(PicSimDesc &d, const PicSpeciesDesc &sp, const PicLaserDesc *l, const int32_t *cand,
+                    int ncand, int warm, int steps, const PicAllocator *a, hipStream_t stream,
+                    const char *cache, PicTuneResult *out)
+{
+    if (steps <= 0) steps = 20;
+    if (warm < 0) throw Error(PIC_EINVAL, "negative warm-up");
+    if (!cand || ncand <= 0) throw Error(PIC_EINVAL, "no candidates");
+    const int nd = d.ndim;
+    char key[200];
+    std::snprintf(key, sizeof(key), "pic-patch nd=%d prec=%d n=%d,%d,%d profile=%d load=%d ppc=%d", nd,
+                  d.precision, d.n[0], d.n[1], nd == 3 ? d.n[2] : 1, sp.profile, sp.loading, sp.ppc);
+    PicTuneResult res;
+    std::memset(&res, 0, sizeof(res));
+    if (cache) {
+        std::ifstream f(cache);
+        std::string line;
+        const std::string k(key);
+        while (std::getline(f, line)) {
+            if (line.compare(0, k.size(), k) != 0 || line.size() <= k.size() || line[k.size()] != ' ') continue;
+            int p0, p1, p2, blk;
+            if (std::sscanf(line.c_str() + k.size(), "%d %d %d %d", &p0, &p1, &p2, &blk) == 4) {
+                PicSimDesc t = d;
+                t.patch[0] = p0; t.patch[1] = p1; t.patch[2] = p2;
+                t.block = blk;
+                std::string why;
+                if (validate_desc(t, why) != PIC_OK) break;  // stale entry: tune again
+                d = t;
+                res.from_cache = 1;
+                res.block = blk;
+                for (int i = 0; i < 3; ++i) res.patch[i] = d.patch[i];
+                if (out) *out = res;
+                return;
+            }
+        }
+    }
+    double best_ms = -1.0;
+    PicSimDesc best = d;
+    const int blocks[3] = {256, 512, 1024};
+    for (int ci = 0; ci < ncand; ++ci) {
+        for (int bi = 0; bi < 3; ++bi) {
+            PicSimDesc t = d;
+            for (int ax = 0; ax < 3; ++ax) t.patch[ax] = ax < nd ? cand[ci] : 1;
+            t.block = blocks[bi];
+            std::string why;
+            if (validate_desc(t, why) != PIC_OK) break;
+            std::unique_ptr<SimBase> sim;
+            if (t.precision == 32) sim.reset(new SimImpl<float>(t, a, stream));
+            else sim.reset(new SimImpl<double>(t, a, stream));
+            sim->add_species(sp);
+            sim->particles_init();
+            if (l) sim->add_laser(*l);
+            if (warm) sim->step(warm);
+            hipcheck(hipStreamSynchronize(stream), "sync");
+            const auto t0 = std::chrono::steady_clock::now();
+            sim->step(steps);
+            hipcheck(hipStreamSynchronize(stream), "sync");
+            const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / steps;
+            ++res.trials;
+            if (best_ms < 0 || ms < best_ms) {
+                best_ms = ms;
+                best = t;
+            }
+        }
+    }
+    if (best_ms < 0) throw Error(PIC_EINVAL, "no candidate patch size fits the grid");
+    d = best;
+    res.block = d.block;
+    res.ms_per_step = best_ms;
+    for (int i = 0; i < 3; ++i) res.patch[i] = d.patch[i];
+    if (cache) {
+        std::ofstream f(cache, std::ios::app);
+        f << key << ' ' << d.patch[0] << ' ' << d.patch[1] << ' ' << d.patch[2] << ' ' << d.block << '\n';
     }
     if (out) *out = res;
 }
@@ -1334,7 +1647,8 @@ void BatchImpl<T>::free_tables()
     sims_d = nullptr;
     patch_prefix_d = tile_prefix_d = nullptr;
     items_d = nullptr;
-    nitems_d = head_d = nullptr;
+    stamps_d = nullptr;
+    nitems_d = head_d = stamp_n_d = nullptr;
     table_cap_items = 0;
 }
 
@@ -1403,12 +1717,20 @@ void BatchImpl<T>::build_tables()
     }
     total_patches = pp[ns];
     total_tiles = tp[ns];
-    // a common square patch size of 16 or 32 selects the specialised kernel
+    // a common patch size selects a kernel compiled for it: square 16 or 32
+    // in 2-D, 8 x 8 x 8 or 8 x 8 x 4 in 3-D
     patch_const = 0;
     if (nd == 2 && ns > 0 && (members[0]->P[0] == 16 || members[0]->P[0] == 32)) {
         patch_const = members[0]->P[0];
         for (auto *m : members)
             if (m->P[0] != patch_const || m->P[1] != patch_const) patch_const = 0;
+    }
+    if (nd == 3 && ns > 0) {
+        patch_const = particles3d_shape(members[0]->P[0], members[0]->P[1], members[0]->P[2]);
+        for (auto *m : members)
+            if (particles3d_shape(m->P[0], m->P[1], m->P[2]) != patch_const ||
+                m->P[0] != members[0]->P[0] || m->P[1] != members[0]->P[1] || m->P[2] != members[0]->P[2])
+                patch_const = 0;
     }
     // chunk: enough items to fill every CU several times over
     chunk = 0;
@@ -1426,7 +1748,7 @@ void BatchImpl<T>::build_tables()
     for (auto *m : members) use_graph = use_graph || m->desc.graph;
     block = (sizeof(T) == 8 && nd == 2) ? 1024 : 512;
     for (auto *m : members) if (m->desc.block) block = m->desc.block;
-    const int occ = std::max(1, nd == 3 ? particles3d_occupancy<T>(block, maxP0, maxP1, maxP2)
+    const int occ = std::max(1, nd == 3 ? particles3d_occupancy<T>(block, maxP0, maxP1, maxP2, patch_const)
                                         : particles_occupancy<T>(block, maxP0, maxP1));
     grid_particles = cu_count() * occ;
     grid_maxwell = std::max(1, std::min(total_tiles, cu_count() * (nd == 3 ? 32 : 8)));
@@ -1444,8 +1766,10 @@ void BatchImpl<T>::build_tables()
     patch_prefix_d = (int *)get(sizeof(int) * (ns + 1));
     tile_prefix_d = (int *)get(sizeof(int) * (ns + 1));
     items_d = (Item *)get(sizeof(Item) * items);
-    nitems_d = (int *)get(sizeof(int) * 2);
+    stamps_d = (ItemStamp *)get(sizeof(ItemStamp) * items);
+    nitems_d = (int *)get(sizeof(int) * 4);
     head_d = nitems_d + 1;
+    stamp_n_d = nitems_d + 2;
     table_cap_items = (int)items;
     std::vector<SimDev<T>> views(ns);
     for (int i = 0; i < ns; ++i) {
@@ -1456,7 +1780,7 @@ void BatchImpl<T>::build_tables()
     if (ns) hipcheck(hipMemcpyAsync(sims_d, views.data(), sizeof(SimDev<T>) * ns, hipMemcpyHostToDevice, stream), "views");
     hipcheck(hipMemcpyAsync(patch_prefix_d, pp.data(), sizeof(int) * (ns + 1), hipMemcpyHostToDevice, stream), "prefix");
     hipcheck(hipMemcpyAsync(tile_prefix_d, tp.data(), sizeof(int) * (ns + 1), hipMemcpyHostToDevice, stream), "prefix");
-    hipcheck(hipMemsetAsync(nitems_d, 0, sizeof(int) * 2, stream), "nitems");
+    hipcheck(hipMemsetAsync(nitems_d, 0, sizeof(int) * 4, stream), "nitems");
     hipcheck(hipStreamSynchronize(stream), "sync");
     dirty = false;
 }
@@ -1516,12 +1840,14 @@ void BatchImpl<T>::launch_one_step()
 {
     const int ns = (int)members.size();
     Timing &tm = timing();
+    ItemStamp *stamps = tm.stamp ? stamps_d : nullptr;
+    if (stamps) launch_copy_int(nitems_d, stamp_n_d, stream);
     if (nd == 3)
         launch_particles3d<T>(sims_d, items_d, nitems_d, head_d, grid_particles, block, maxP0, maxP1,
-                              maxP2, stream, tm.pair(1));
+                              maxP2, patch_const, stamps, stream, tm.pair(1));
     else
         launch_particles<T>(sims_d, items_d, nitems_d, head_d, grid_particles, block, maxP0, maxP1,
-                            patch_const, stream, tm.pair(1));
+                            patch_const, stamps, stream, tm.pair(1));
     // the field update (fields, currents, tile energies) and the re-binning
     // (particles, counts) touch disjoint data: run them side by side
     const bool fork = ensure_side();

@@ -30,6 +30,9 @@ int validate_desc(const PicSimDesc &d, std::string &why);
 // patch ids in Hilbert-curve order (order.cpp); PIC_ENOTSUP for unsupported grids
 int hilbert_patch_order(int nd, const int np[3], std::vector<int32_t> &out, std::string &why);
 void curve_segments(const int64_t *cost, int64_t n, int k, int64_t *bounds);
+void autotune_patch(PicSimDesc &d, const PicSpeciesDesc &sp, const PicLaserDesc *l, const int32_t *cand,
+                    int ncand, int warm, int steps, const PicAllocator *a, hipStream_t stream,
+                    const char *cache, PicTuneResult *out);
 
 struct Allocator {
     PicAllocator hook{nullptr, nullptr, nullptr};
@@ -47,6 +50,7 @@ struct Timing {
         hipEvent_t a, b;
     };
     bool enabled = false;
+    bool stamp = false;  // record per-item stamps in the particle launch
     int only = -1;  // time only this kind (-1: all)
     std::vector<Ev> events;
     std::vector<hipEvent_t> pool;
@@ -70,11 +74,15 @@ struct SimBase {
     virtual void set_particles(int64_t n, const double *const xs[3], const double *const us[3],
                                const double *w) = 0;
     virtual void set_laser(int64_t nsteps, const double *ey, const double *ez) = 0;
+    virtual void add_laser(const PicLaserDesc &l) = 0;
+    virtual void add_species(const PicSpeciesDesc &sp) = 0;
+    virtual void particles_init() = 0;
     virtual void set_window(int64_t start, double vel, int ppcx, int ppcy, const double *dens,
                             int64_t ncols) = 0;
     virtual void set_merge(int every, int cmax, int iters) = 0;
     virtual int64_t merge_now(int cmax, int iters) = 0;
     virtual void set_field(int comp, const double *h) = 0;
+    virtual void set_step(int64_t step) = 0;
     virtual void get_field(int comp, double *h) = 0;
     virtual SimState read_state() = 0;
     virtual std::vector<int32_t> read_counts() = 0;
@@ -83,6 +91,7 @@ struct SimBase {
     virtual void history(int64_t first, int64_t n, double *U, double *K, int64_t *pushed) = 0;
     virtual void rebin_codes(const uint8_t *codes, size_t n) = 0;
     virtual void residuals(PicResiduals *out) = 0;
+    virtual void imbalance(PicImbalance *out) = 0;
     virtual void rho_noalloc(double *h, size_t count) = 0;
     virtual void step(int64_t nsteps) = 0;
     virtual bool in_batch() const = 0;
@@ -122,6 +131,9 @@ struct SimImpl : SimBase {
     int64_t rhoprev_step = -1;
     T *laser_ey = nullptr, *laser_ez = nullptr;
     int64_t laser_steps = 0;
+    std::vector<PicLaserDesc> lasers;
+    bool has_species = false;
+    PicSpeciesDesc species{};
     // particle layout
     std::vector<void *> part_bufs;
     T *px[3] = {}, *sx[3] = {}, *pu[3] = {}, *su[3] = {}, *pw = nullptr, *sw = nullptr;
@@ -166,11 +178,16 @@ struct SimImpl : SimBase {
     void set_particles(int64_t n, const double *const xs[3], const double *const us[3],
                        const double *w) override;
     void set_laser(int64_t nsteps, const double *ey, const double *ez) override;
+    void add_laser(const PicLaserDesc &l) override;
+    void add_species(const PicSpeciesDesc &sp) override;
+    void particles_init() override;
+    void finish_load(const std::vector<int32_t> &counts, int64_t total);
     void set_window(int64_t start, double vel, int ppcx, int ppcy, const double *dens,
                     int64_t ncols) override;
     void set_merge(int every, int cmax, int iters) override;
     int64_t merge_now(int cmax, int iters) override;
     void set_field(int comp, const double *h) override;
+    void set_step(int64_t step) override;
     void get_field(int comp, double *h) override;
     SimState read_state() override;
     std::vector<int32_t> read_counts() override;
@@ -179,6 +196,7 @@ struct SimImpl : SimBase {
     void history(int64_t first, int64_t n, double *U, double *K, int64_t *pushed) override;
     void rebin_codes(const uint8_t *codes, size_t n) override;
     void residuals(PicResiduals *out) override;
+    void imbalance(PicImbalance *out) override;
     void rho_noalloc(double *h, size_t count) override;
     void record_rho0();
     void step(int64_t nsteps) override;
@@ -207,6 +225,8 @@ struct BatchImpl : BatchBase {
     int *patch_prefix_d = nullptr, *tile_prefix_d = nullptr;
     Item *items_d = nullptr;
     int *nitems_d = nullptr, *head_d = nullptr;
+    ItemStamp *stamps_d = nullptr;  // per-item records of the last stamped particle launch
+    int *stamp_n_d = nullptr;       // its item count
     int table_cap_items = 0;
     int total_patches = 0, total_tiles = 0;
     int nd = 0;  // dimensions of the members (set by the first one)

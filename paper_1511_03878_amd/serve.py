@@ -43,8 +43,25 @@ class Request:
         return self.done - self.arrival
 
 
-def make_workload(req: Request, seed: int = W.DEFAULT_SEED):
-    return W.scan_sim(req.params, req.nsteps, seed=seed + req.rid)
+def make_workload(req: Request, seed: int = W.DEFAULT_SEED, patch=(32, 32)):
+    return W.scan_sim(req.params, seed=seed + req.rid, patch=tuple(patch))
+
+
+def particle_count(wl: dict) -> int:
+    """Particles a workload loads (for admission before the simulation
+    exists): explicit arrays, or a uniform or ramp species description (ppc in
+    every cell at or beyond the ramp start)."""
+    if "x" in wl:
+        return int(np.asarray(wl["w"]).size)
+    sp, g = wl["species"], wl["grid"]
+    cells = int(np.prod(g["n"]))
+    if sp["profile"] == "uniform":
+        return sp["ppc"] * cells
+    if sp["profile"] == "ramp":
+        X0 = sp["param"][0] / g["d"][0]
+        cols = int(np.count_nonzero(np.arange(g["n"][0]) >= X0))
+        return sp["ppc"] * cols * (cells // g["n"][0])
+    raise ValueError("admission estimate needs explicit arrays or a uniform / ramp species")
 
 
 def default_result(sim: Sim) -> dict:
@@ -60,38 +77,51 @@ class Server:
 
     def __init__(self, budget_bytes: int, precision: int = 32, slice_steps: int = 25,
                  result_fn: Callable[[Sim], dict] = default_result, clock=time.perf_counter,
-                 max_members: int = 256):
+                 max_members: int = 256, patch=(32, 32), tune: Optional[dict] = None):
         self.budget = int(budget_bytes)
         self.precision = precision
         self.slice_steps = slice_steps
         self.result_fn = result_fn
         self.clock = clock
         self.max_members = max_members
+        self.patch = tuple(patch)       # patch edge of every request (e.g. from the patch tuner)
+        self.tune = dict(tune or {})    # descriptor settings of every request
         self.batch = Batch(precision)
         self.in_use = 0
+        self.peak_in_use = 0
+        self.charges = []          # (resident count, bytes charged, bytes the residents hold)
         self.resident: dict = {}   # sim handle -> (Request, Sim)
         self._t0 = clock()
         self._skew = 0.0
 
     def _admit(self, req: Request, now: float) -> bool:
         if req.workload is None:
-            req.workload = make_workload(req)
+            req.workload = make_workload(req, patch=self.patch)
             wl = req.workload
-            req.nparticles = int(wl["w"].size)
-            laser_steps = wl["laser"]["ey"].shape[0] if wl.get("laser") else 0
-            req.bytes = estimate_bytes(wl["grid"], self.precision, req.nparticles, laser_steps)
+            req.nparticles = particle_count(wl)
+            req.bytes = estimate_bytes(wl["grid"], self.precision, req.nparticles, **self.tune)
         wl = req.workload
         if req.bytes > self.budget:
             raise ValueError(f"request {req.rid} needs {req.bytes} B, above the whole budget")
         if self.in_use + req.bytes > self.budget or len(self.resident) >= self.max_members:
             return False
-        sim = Sim.from_workload(wl, precision=self.precision)
+        sim = Sim.from_workload(wl, precision=self.precision, **self.tune)
+        req.nparticles = sim.num_particles()
         req.workload = None  # the state lives on the GPU now
         self.batch.add(sim, req.nsteps)
-        self.in_use += req.bytes
         self.resident[sim.handle.value] = (req, sim)
+        self._charge()
         req.admitted = now
         return True
+
+    def _charge(self):
+        """Charge every resident simulation the device memory it holds now
+        (capacity growth after an overflowing patch raises it), but at least
+        its admission estimate."""
+        held = [sim.device_bytes() for _, sim in self.resident.values()]
+        self.in_use = sum(max(req.bytes, h) for (req, _), h in zip(self.resident.values(), held))
+        self.peak_in_use = max(self.peak_in_use, self.in_use)
+        self.charges.append((len(held), self.in_use, sum(held)))
 
     def _retire(self, now: float):
         for sim in self.batch.finished():
@@ -100,15 +130,17 @@ class Server:
             req.done = self._now()
             self.batch.remove(sim)
             sim.close()
-            self.in_use -= req.bytes
+        self._charge()
 
     def _now(self) -> float:
         return self.clock() - self._t0 + self._skew
 
-    def run(self, requests, realtime: bool = True) -> dict:
+    def run(self, requests, realtime: bool = True, warmup: int = 0) -> dict:
         """Serve `requests` (arrival times in seconds from now).  With
         realtime=False, idle gaps before the next arrival are skipped (the
-        clock jumps ahead) instead of slept through."""
+        clock jumps ahead) instead of slept through.  The first `warmup`
+        requests (by arrival) are served but left out of the time-to-result
+        percentiles."""
         reqs = sorted(requests, key=lambda r: r.arrival)
         waiting = collections.deque()
         i = 0
@@ -137,12 +169,13 @@ class Server:
             slices += 1
             self._retire(now)
         wall = self._now()
-        ttr = np.array([r.time_to_result for r in reqs])
+        meas = reqs[warmup:] if warmup < len(reqs) else reqs
+        ttr = np.array([r.time_to_result for r in meas])
         psteps = sum(r.nparticles * r.nsteps for r in reqs)
-        return {"requests": len(reqs), "wall_s": wall, "particle_steps": psteps,
+        return {"requests": len(meas), "wall_s": wall, "particle_steps": psteps,
                 "throughput": psteps / wall if wall > 0 else 0.0,
                 "ttr_p50_s": float(np.percentile(ttr, 50)), "ttr_p99_s": float(np.percentile(ttr, 99)),
-                "ttr_max_s": float(ttr.max()), "slices": slices}
+                "ttr_max_s": float(ttr.max()), "slices": slices, "peak_in_use_bytes": self.peak_in_use}
 
 
 def make_requests(count: int, rate: float, steps_range=(200, 2000), seed: int = W.DEFAULT_SEED,

@@ -107,6 +107,48 @@ def estimate_bytes(grid: dict, precision: int, nparticles: int, laser_steps: int
     return out.value
 
 
+def species_desc(sp: dict) -> _capi.SpeciesDesc:
+    from .workloads import LOADINGS, PROFILES
+    return _capi.SpeciesDesc(float(sp.get("q", -1.0)), float(sp.get("m", 1.0)),
+                             PROFILES[sp["profile"]], LOADINGS[sp.get("loading", "weight")],
+                             int(sp["ppc"]), 0, float(sp.get("n0", 1.0)),
+                             (C.c_double * 6)(*(list(sp.get("param", [])) + [0.0] * 6)[:6]),
+                             float(sp.get("temperature", 0.0)), int(sp.get("seed", 0)) & (2 ** 64 - 1))
+
+
+def laser_desc(laser: dict) -> _capi.LaserDesc:
+    return _capi.LaserDesc(float(laser["a0"]), float(laser.get("omega0", 1.0)), float(laser["w0"]),
+                           float(laser["tau"]), float(laser["t0"]), float(laser["x_focus"]),
+                           float(laser["y_center"]), float(laser.get("phase", 0.0)),
+                           int(laser.get("polarisation", 1)), 0)
+
+
+def _tune_dict(r) -> dict:
+    return {k: (list(getattr(r, k)) if k == "patch" else getattr(r, k)) for k, _ in _capi.TuneResult._fields_}
+
+
+def autotune_patch(wl: dict, precision: int, candidates=(16, 32), warm: int = 20, steps: int = 20,
+                   cache: str | None = None, **tune):
+    """Pick the patch edge (and particle-kernel workgroup size) for a workload
+    described by a species (pic_autotune_patch): temporary simulations at each
+    candidate are loaded on the device and timed.  Returns (grid with the
+    chosen patch, tune settings to pass to Sim, the tuner's result)."""
+    desc = make_desc(wl["grid"], precision, **tune)
+    sp = species_desc(wl["species"])
+    las = laser_desc(wl["laser"]) if wl.get("laser") and "a0" in wl["laser"] else None
+    cand = (C.c_int32 * len(candidates))(*[int(c) for c in candidates])
+    stream = current_stream_handle()
+    alloc = _TorchAllocator(stream)
+    r = _capi.TuneResult()
+    check(_capi.load().pic_autotune_patch(C.byref(desc), C.byref(sp), C.byref(las) if las else None, cand,
+                                          len(candidates), int(warm), int(steps), C.byref(alloc.struct),
+                                          C.c_void_p(stream), cache.encode() if cache else None,
+                                          C.byref(r)))
+    grid = dict(wl["grid"])
+    grid["patch"] = list(desc.patch)[:int(wl["grid"]["ndim"])]
+    return grid, {"block": int(desc.block)}, _tune_dict(r)
+
+
 def patch_order(np_) -> np.ndarray:
     """Patch ids in Hilbert-curve order for a grid of np_ patches per axis
     (pic_patch_order)."""
@@ -176,10 +218,30 @@ class Sim:
                                              _dp(x[2]) if self.ndim == 3 else None,
                                              _dp(u[0]), _dp(u[1]), _dp(u[2]), _dp(w)))
 
+    def add_species(self, sp: dict) -> int:
+        """Describe the species (pic_species_add); see workloads.species."""
+        d = species_desc(sp)
+        sid = C.c_int32()
+        check(_capi.load().pic_species_add(self._h, C.byref(d), C.byref(sid)))
+        return sid.value
+
+    def particles_init(self, sid: int = 0):
+        """Generate the species' particles on the device (pic_particles_init)."""
+        check(_capi.load().pic_particles_init(self._h, int(sid)))
+
+    def add_laser(self, laser: dict):
+        """Gaussian laser through x = 0 (pic_laser_add); see workloads.gaussian_laser."""
+        d = laser_desc(laser)
+        check(_capi.load().pic_laser_add(self._h, C.byref(d)))
+
     def set_laser(self, ey=None, ez=None):
         ey, ez = _f64(ey), _f64(ez)
         nsteps = (ey if ey is not None else ez).shape[0]
         check(_capi.load().pic_laser_set(self._h, nsteps, _dp(ey), _dp(ez)))
+
+    def set_step(self, step: int):
+        """Completed-step counter of a state loaded from elsewhere (pic_step_set)."""
+        check(_capi.load().pic_step_set(self._h, int(step)))
 
     def set_field(self, comp, values):
         c = _capi.COMPONENTS.index(comp) if isinstance(comp, str) else int(comp)
@@ -205,10 +267,21 @@ class Sim:
 
     @classmethod
     def from_workload(cls, wl: dict, precision: int = 64, **kw) -> "Sim":
+        """A simulation of a workload: explicit particle arrays (x, u, w) when
+        the workload holds them, else the species description loaded on the
+        device; a laser description is added, an incident-field table set."""
         s = cls(wl["grid"], precision, **kw)
-        s.set_particles(wl["x"], wl["u"], wl["w"])
-        if wl.get("laser"):
-            s.set_laser(wl["laser"].get("ey"), wl["laser"].get("ez"))
+        if "x" in wl:
+            s.set_particles(wl["x"], wl["u"], wl["w"])
+        else:
+            s.add_species(wl["species"])
+            s.particles_init()
+        laser = wl.get("laser")
+        if laser:
+            if "a0" in laser:
+                s.add_laser(laser)
+            else:
+                s.set_laser(laser.get("ey"), laser.get("ez"))
         return s
 
     # -- stepping ------------------------------------------------------------
@@ -245,6 +318,19 @@ class Sim:
             ids.ctypes.data_as(C.POINTER(C.c_int64)), n))
         return x, u, w, ids
 
+    def device_bytes(self) -> int:
+        """Device memory the handle holds now (pic_device_bytes, no sync)."""
+        b = C.c_int64()
+        check(_capi.load().pic_device_bytes(self._h, C.byref(b)))
+        return b.value
+
+    def perm(self) -> np.ndarray:
+        """Particle ids in canonical (patch, slot) order (pic_perm_get)."""
+        n = self.num_particles()
+        ids = np.zeros(n, dtype=np.int64)
+        check(_capi.load().pic_perm_get(self._h, ids.ctypes.data_as(C.POINTER(C.c_int64)), n))
+        return ids
+
     def counts(self) -> np.ndarray:
         c = np.zeros(self.npatch, dtype=np.int32)
         check(_capi.load().pic_patch_counts_get(self._h, c.ctypes.data_as(C.POINTER(C.c_int32)),
@@ -277,7 +363,7 @@ class Sim:
         r = _capi.TuneResult()
         check(_capi.load().pic_autotune(self._h, int(steps),
                                         cache.encode() if cache else None, C.byref(r)))
-        return {k: getattr(r, k) for k, _ in _capi.TuneResult._fields_}
+        return _tune_dict(r)
 
     def save_state(self) -> bytes:
         """Checkpoint of the whole simulation state (host bytes)."""
@@ -300,9 +386,16 @@ class Sim:
 
     def timing_enable(self, on=True):
         """True / 1: time every kernel group; 2 or "particles": the particle
-        kernel only; False / 0: off."""
-        mode = 2 if on == "particles" else int(on)
+        kernel only; 3 or "stamps": the particle kernel and per-item stamps
+        (for imbalance()); False / 0: off."""
+        mode = {"particles": 2, "stamps": 3}.get(on, on) if isinstance(on, str) else int(on)
         check(_capi.load().pic_timing_enable(self._h, mode))
+
+    def imbalance(self) -> dict:
+        """Load imbalance of the last stamped particle launch (pic_imbalance)."""
+        r = _capi.Imbalance()
+        check(_capi.load().pic_imbalance(self._h, C.byref(r)))
+        return {k: getattr(r, k) for k, _ in _capi.Imbalance._fields_}
 
     def timing(self) -> dict:
         t = _capi.Timing()

@@ -14,12 +14,29 @@ def rel_l2(a_list, b_list):
     return np.sqrt(num / den) if den > 0 else np.sqrt(num)
 
 
-def oracle_run(wl, nsteps, laser=True):
+def oracle_sim(wl, laser=True, storage=64):
+    """The oracle loaded with a workload: its explicit arrays, or its species
+    description through the oracle's own loader (rounded to FP32 storage when
+    storage == 32); its laser description or incident-field table."""
     import oracle
     s = oracle.Sim(wl["grid"])
-    s.set_particles(wl["x"], wl["u"], wl["w"])
-    if laser and wl.get("laser"):
-        s.set_laser(ey=wl["laser"].get("ey"), ez=wl["laser"].get("ez"))
+    if "x" in wl:
+        s.set_particles(wl["x"], wl["u"], wl["w"])
+    else:
+        s.particles_init(wl["species"])
+        if storage == 32:
+            s.round_storage()
+    L = wl.get("laser")
+    if laser and L:
+        if "a0" in L:
+            s.add_laser(L)
+        else:
+            s.set_laser(ey=L.get("ey"), ez=L.get("ez"))
+    return s
+
+
+def oracle_run(wl, nsteps, laser=True, storage=64):
+    s = oracle_sim(wl, laser=laser, storage=storage)
     s.step(nsteps)
     return s
 

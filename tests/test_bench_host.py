@@ -27,35 +27,33 @@ def test_bytes_per_particle_step_from_the_particle_layout(nd, prec):
     assert bench.BYTES_PER_PARTICLE_STEP[(nd, prec)] == t * ((nd + 3 + 1) + (nd + 3))
 
 
-class _Rec:
-    def __init__(self):
-        self.calls = []
-
-    def __getattr__(self, name):
-        return lambda *a: self.calls.append((name, a))
-
-
-def test_workload_options_reach_both_sides():
+def test_workload_options():
     wl = {"ppc": 4, "column_density": [0.0, 1.0]}
-    g, o = _Rec(), _Rec()
     opts = bench._options("lwfa_window", wl)
-    bench._apply(g, opts)
-    bench._apply(o, opts, oracle_side=True)
-    assert [c[0] for c in g.calls] == ["set_window", "set_merge"] == [c[0] for c in o.calls]
-    hi = bench._options("periodic_hi", {})
-    assert hi["tune"] == {"maxwell_order": 6}
-    o = _Rec()
-    bench._apply(o, hi, oracle_side=True)
-    assert o.calls == [("set_maxwell_order", (6,))]
-    assert bench._options("lwfa", {}) == {}
+    assert opts["window"][0] == 300 and opts["merge"] == (100, 8, 8)
+    assert bench._options("periodic_hi", {})["tune"] == {"maxwell_order": 6}
+    assert bench._options("lwfa", {}) == {} and bench._options("blob3d", {}) == {}
+
+
+def test_headline_is_the_largest_configuration():
+    """The default workload is the 3-D box of 512 x 256 x 256 cells (the
+    largest single-GPU configuration), loaded from its description."""
+    wl, desc = bench._workload("blob3d")
+    assert wl["grid"]["n"] == [512, 256, 256] and wl["grid"]["ndim"] == 3
+    assert wl["species"]["loading"] == "count" and "x" not in wl
+    assert desc.startswith("blob_3d: 512x256x256")
 
 
 def test_traffic_is_reported_only_for_the_measured_source():
-    with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
-        rec = json.load(f)["k_particles2d/lwfa/f32"]
-    got = bench._measured_traffic(32, "lwfa")
-    if rec["source_sha"] == bench._kernel_source_sha():
-        assert got == rec["traffic_bytes_per_launch"]
-    else:
-        assert got is None
-    assert bench._measured_traffic(32, "no_such_workload") is None
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    with open(path) as f:
+        recs = json.load(f)
+    for key, rec in recs.items():
+        kernel, workload, prec = key.split("/")
+        nd = 3 if kernel == "k_particles3d" else 2
+        got = bench._measured_traffic(kernel, workload, int(prec[1:]), nd)
+        if rec["source_sha"] == bench._kernel_source_sha(nd):
+            assert got == rec["traffic_bytes_per_launch"]
+        else:
+            assert got is None
+    assert bench._measured_traffic("k_particles2d", "no_such_workload", 32, 2) is None

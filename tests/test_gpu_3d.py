@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_1511_03878_amd import workloads as W
+from tests import fixtures as W
 from tests.helpers import compare_fields, gpu_sim, neighbour_patch3, oracle_run, rel_l2
 
 pytestmark = pytest.mark.gpu

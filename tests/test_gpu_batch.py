@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 from paper_1511_03878_amd import serve
-from paper_1511_03878_amd import workloads as W
+from tests import fixtures as W
 from paper_1511_03878_amd.sim import Batch, Sim
 from tests.helpers import B_COMPS, E_COMPS, rel_l2
 
@@ -106,7 +106,7 @@ def test_serving_admits_under_budget_and_results_match_alone():
     for r in reqs:
         wl = serve.make_workload(r)
         from paper_1511_03878_amd.sim import estimate_bytes
-        sizes.append(estimate_bytes(wl["grid"], 32, wl["w"].size, wl["laser"]["ey"].shape[0]))
+        sizes.append(estimate_bytes(wl["grid"], 32, serve.particle_count(wl)))
     budget = int(max(sizes) * 1.6)  # at most one or two residents at a time
     srv = serve.Server(budget, precision=32, slice_steps=10)
     report = srv.run(reqs, realtime=False)
@@ -124,3 +124,46 @@ def test_serving_admits_under_budget_and_results_match_alone():
         assert rel_l2([s.field("Ey"), s.field("Bz")], [r.result["Ey"], r.result["Bz"]]) < 1e-4
         U, K, _ = s.history(0, r.nsteps)
         assert np.allclose(U, r.result["U"], rtol=1e-4, atol=1e-9 * max(1.0, abs(U).max()))
+
+
+def test_served_results_match_the_oracle_and_growth_is_charged():
+    """Requests served together (continuous batching, FP32, loaded on the
+    device from their descriptions) against the oracle run from the same
+    descriptions rounded to FP32 storage: one-step requests' fields within
+    1e-5, 120-step requests' energy histories within 1e-3.  Patches are
+    sized without slack, so capacities grow while the requests are resident,
+    and the server charges each resident what it really holds."""
+    _announce("served vs oracle: 4 requests fp32, capacity growth charged")
+    from tests.helpers import oracle_sim
+    reqs = serve.make_requests(4, rate=100.0, steps_range=(1, 1), scan_patch=32)
+    for k, r in enumerate(reqs):
+        r.params = dict(r.params, n=(min(r.params["n"][0], 320), min(r.params["n"][1], 128)), a0=6.0)
+        r.nsteps = 1 if k % 2 == 0 else 120
+    tune = {"capacity_factor": 1.0, "min_capacity": 64}
+
+    def result(sim):
+        d = sim.diag()
+        U, K, _ = sim.history(0, d["step"])
+        return {"diag": d, "U": U, "K": K, "held": sim.device_bytes(),
+                "fields": [sim.field(c) for c in ("Ex", "Ey", "Bz")]}
+
+    srv = serve.Server(int(64 * 2**30), precision=32, slice_steps=5, result_fn=result, tune=tune)
+    srv.run(reqs, realtime=False)
+    assert srv.in_use == 0
+    # every charge covered what the residents held, estimate or more
+    assert all(charged >= held for _, charged, held in srv.charges)
+    assert max(n for n, _, _ in srv.charges) >= 2  # requests shared the GPU
+    grew = [r for r in reqs if r.result["diag"]["relayouts"] > 0]
+    assert grew and all(r.result["held"] > r.bytes for r in grew)
+    for r in reqs:
+        wl = serve.make_workload(r)
+        o = oracle_sim(wl, storage=32)
+        Wo = []
+        for _ in range(r.nsteps):
+            o.step(1)
+            Wo.append(sum(o.energy()))
+        if r.nsteps == 1:
+            ref = [o.field(c)[0] for c in ("Ex", "Ey", "Bz")]
+            assert rel_l2(r.result["fields"], ref) < 1e-5
+        Wg = r.result["U"] + r.result["K"]
+        assert np.abs(Wg - np.array(Wo)).max() <= 1e-3 * max(np.abs(Wo).max(), 1e-300)

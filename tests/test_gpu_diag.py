@@ -9,7 +9,7 @@ import math
 import numpy as np
 import pytest
 
-from paper_1511_03878_amd import workloads as W
+from tests import fixtures as W
 from tests.brute import div_dual_2d, rho_2d, rho_3d
 from tests.helpers import gpu_sim
 
@@ -127,3 +127,28 @@ def test_residuals_open_box_and_checkpoint():
     r2 = h.residuals()
     assert math.isnan(r2["gauss"]) and math.isnan(r2["continuity"])
     assert r2["rho_max"] == pytest.approx(r["rho_max"], rel=1e-14)
+
+
+def test_imbalance_from_item_stamps():
+    """pic_imbalance on the small laser box once the pulse is in the plasma:
+    every item is stamped, the work queue spreads the item time more evenly
+    over the compute units than fixed domains of equal patch-id runs would,
+    and the accounting adds up."""
+    _announce("imbalance from item stamps, small laser box fp32")
+    from paper_1511_03878_amd._capi import PicError
+    wl = W.lwfa_2d_small()
+    g = gpu_sim(wl, 32)
+    g.step(60)
+    with pytest.raises(PicError) as e:
+        g.imbalance()
+    assert e.value.code == -8
+    g.timing_enable("stamps")
+    g.step(1)
+    r = g.imbalance()
+    g.timing_enable(False)
+    assert r["step"] == 61 and r["items"] >= 1 and 1 <= r["units"] <= r["device_units"]
+    assert r["imbalance"] >= 1.0 and r["static_imbalance"] >= r["imbalance"]
+    assert r["segment_imbalance"] >= 1.0
+    total = r["busy_mean_us"] * r["device_units"]
+    assert total == pytest.approx(r["patch_mean_us"] * g.npatch, rel=1e-9)
+    assert r["span_us"] > 0 and r["busy_max_us"] <= r["span_us"] * 64

@@ -9,7 +9,7 @@ import os
 import numpy as np
 import pytest
 
-from paper_1511_03878_amd import workloads as W
+from tests import fixtures as W
 from tests.brute import div_dual_2d
 from tests.helpers import compare_fields, gpu_sim, oracle_run
 

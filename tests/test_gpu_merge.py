@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_1511_03878_amd import workloads as W
+from tests import fixtures as W
 from tests.helpers import compare_fields, gpu_sim
 
 pytestmark = pytest.mark.gpu

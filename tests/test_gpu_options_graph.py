@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_1511_03878_amd import workloads as W
+from tests import fixtures as W
 from tests.helpers import compare_fields, gpu_sim
 
 pytestmark = pytest.mark.gpu
@@ -95,7 +95,7 @@ def test_autotune_with_window_and_merging_restores_state(tmp_path):
     g.set_merge(5, 6, 4)
     o = oracle.Sim(wl["grid"])
     o.set_particles(wl["x"], wl["u"], wl["w"])
-    o.set_laser(ey=wl["laser"]["ey"])
+    o.add_laser(wl["laser"])
     o.set_window(*win)
     o.set_merge(5, 6, 4)
     g.step(30)

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_1511_03878_amd import workloads as W
+from tests import fixtures as W
 from tests.helpers import compare_fields, gpu_sim, neighbour_patch, oracle_run, rel_l2
 
 pytestmark = pytest.mark.gpu
@@ -182,7 +182,7 @@ def test_checkpoint_round_trip_and_resume(case):
     b.load_state(blob)
     assert b.save_state() == blob
     if wl.get("laser"):
-        b.set_laser(wl["laser"].get("ey"), wl["laser"].get("ez"))
+        b.add_laser(wl["laser"])
     b.step(m)
     tol = 1e-12 if prec == 64 else 1e-5
     comps = ("Ex", "Ey", "Ez", "Bx", "By", "Bz")

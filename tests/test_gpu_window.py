@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_1511_03878_amd import workloads as W
+from tests import fixtures as W
 from tests.helpers import compare_fields, gpu_sim
 
 pytestmark = pytest.mark.gpu
@@ -40,7 +40,7 @@ def _pair(wl, precision, window, **kw):
     o = oracle.Sim(wl["grid"])
     o.set_particles(wl["x"], wl["u"], wl["w"])
     if wl.get("laser"):
-        o.set_laser(ey=wl["laser"].get("ey"), ez=wl["laser"].get("ez"))
+        o.add_laser(wl["laser"])
     o.set_window(*window)
     return g, o
 

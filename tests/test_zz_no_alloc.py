@@ -8,7 +8,8 @@ import ctypes as C
 import numpy as np
 import pytest
 
-from paper_1511_03878_amd import _capi, workloads as W
+from paper_1511_03878_amd import _capi
+from tests import fixtures as W
 from paper_1511_03878_amd.sim import Sim
 from tests.helpers import gpu_sim
 
