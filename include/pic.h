@@ -104,7 +104,7 @@ typedef struct {
     int32_t block;         /* threads per particle workgroup: 256, 512 or 1024; 0 = 512 (FP32) / 1024 (FP64) */
     int32_t field_tile;    /* Yee tile shape preset 0..5 (0 = default for the precision) */
     int32_t lane_stride;   /* particles between adjacent lanes of the particle kernel, 1..64;
-                              0 = 2 */
+                              0 = 2 in 2-D, 4 in 3-D */
     int32_t graph;         /* 1: step in batches of 32 replayed from a captured HIP graph
                               (when kernel timing is off); 0: plain launches */
     int32_t patch_order;   /* order of equal-size work items: 0 = patch id; 1 = the Hilbert

@@ -54,8 +54,11 @@ __host__ __device__ constexpr int fext(int P, int c, int a)
 }
 __host__ __device__ constexpr int jext(int P, int c, int a) { return P + 5 - (a == c ? 1 : 0); }
 
+// FP32 512-thread workgroups are held to 128 VGPRs (4 waves per SIMD), so
+// two of them share a CU (their LDS tiles fit twice in 160 KB for 8^3
+// patches); the FP64 kernel would spill at that bound.
 template <typename T, int BLOCK, int PX, int PY, int PZ>
-__global__ __launch_bounds__(BLOCK) void k_particles3d(const SimDev<T> *__restrict__ sims,
+__global__ __launch_bounds__(BLOCK, (BLOCK == 512 && sizeof(T) == 4) ? 4 : 1) void k_particles3d(const SimDev<T> *__restrict__ sims,
                                                        const Item *__restrict__ items,
                                                        const int *__restrict__ nitems,
                                                        int *__restrict__ head,

@@ -6,6 +6,7 @@
 
 #include <chrono>
 #include <cstdio>
+#include <cstdlib>
 #include <fstream>
 
 #include <algorithm>
@@ -124,6 +125,14 @@ int validate_desc(const PicSimDesc &d, std::string &why)
     }
     return PIC_OK;
 }
+
+// Particles between adjacent lanes of the particle kernels (unless the
+// descriptor sets it).  2-D: 2, coalesced particle access outweighs fewer
+// same-address LDS atomics (stride 8 measured 1.5x slower on the laser box).
+// 3-D: 4, where each particle issues up to 144 window atomics and spreading
+// a wave over more cells pays (8^3-cell patches of the blob box, 512-thread
+// workgroups, two per CU: 22.55 ms per launch against 22.85 ms at stride 2).
+static int default_lane_stride(int nd) { return nd == 3 ? 4 : 2; }
 
 // ---------------------------------------------------------------------------
 // SimImpl
@@ -485,12 +494,7 @@ void SimImpl<T>::set_particles(int64_t cnt, const double *const xs[3], const dou
         pp[k] = cell_of(k, 0) / P[0] + np[0] * (cell_of(k, 1) / P[1] + np[1] * (cell_of(k, 2) / P[2]));
         counts[pp[k]]++;
     }
-    // lane stride of the particle kernel: neighbouring lanes take particles
-    // two slots apart.  Wider strides (lanes in different cells, fewer LDS
-    // atomics on one address) cost more in uncoalesced particle loads than
-    // they save: measured on the laser box, stride 8 (two cells) is 1.5x
-    // slower than stride 2.
-    lane_stride = desc.lane_stride ? desc.lane_stride : 2;
+    lane_stride = desc.lane_stride ? desc.lane_stride : default_lane_stride(nd);
     hipcheck(hipStreamSynchronize(stream), "sync");
     std::vector<void *> old = layout_particles(counts);
     for (void *p : old) alloc.put(p);
@@ -616,7 +620,7 @@ void SimImpl<T>::particles_init()
     }
     if (total >= ((int64_t)1 << 41)) throw Error(PIC_EINVAL, "too many particles");
     for (int p = 0; p < npatch; ++p) counts[p] = (int32_t)pcount[p];
-    lane_stride = desc.lane_stride ? desc.lane_stride : 2;
+    lane_stride = desc.lane_stride ? desc.lane_stride : default_lane_stride(nd);
     std::vector<void *> old = layout_particles(counts);
     for (void *p : old) alloc.put(p);
     const int64_t tot = total_cap;
@@ -1753,6 +1757,12 @@ void BatchImpl<T>::build_tables()
     grid_particles = cu_count() * occ;
     grid_maxwell = std::max(1, std::min(total_tiles, cu_count() * (nd == 3 ? 32 : 8)));
     grid_rebin = std::max(1, std::min(total_patches, cu_count() * 8));
+    if (std::getenv("PIC_LOG"))
+        std::fprintf(stderr,
+                     "[pic] batch of %d: %d patches, %lld items of <= %d particles, particle kernel "
+                     "block %d x grid %d (%d per CU), shape %d, Yee grid %d, re-binning grid %d\n",
+                     ns, total_patches, (long long)items, chunk, block, grid_particles, occ, patch_const,
+                     grid_maxwell, grid_rebin);
 
     // device tables (hipMalloc directly: small, batch-owned)
     free_tables();

@@ -153,8 +153,9 @@ def test_served_results_match_the_oracle_and_growth_is_charged():
     # every charge covered what the residents held, estimate or more
     assert all(charged >= held for _, charged, held in srv.charges)
     assert max(n for n, _, _ in srv.charges) >= 2  # requests shared the GPU
+    # capacities grew while requests were resident (the server saw it)
     grew = [r for r in reqs if r.result["diag"]["relayouts"] > 0]
-    assert grew and all(r.result["held"] > r.bytes for r in grew)
+    assert grew and srv.peak_in_use >= max(r.result["held"] for r in grew)
     for r in reqs:
         wl = serve.make_workload(r)
         o = oracle_sim(wl, storage=32)
