@@ -269,11 +269,14 @@ def _scan_bench(count, steps, precision):
             "grids": [list(p["n"]) for p in params][:8] + (["..."] if count > 8 else [])}
 
 
-def _serve_bench(count, warm, rate, steps_range, budget_gb, precision, compare):
+def _serve_bench(count, warm, rate, steps_range, budget_gb, precision, compare, compare_rate):
     """Served scan: Poisson arrivals admitted against an HBM budget and
     stepped with continuous batching (real time; the first `warm` requests
-    are warm-up); then the first `compare` requests again in compressed time
-    (idle gaps skipped), with continuous batching and one at a time."""
+    are warm-up); then `compare` requests arriving at `compare_rate` per
+    second (faster than one request at a time can be served, so that the
+    comparison measures service capacity rather than the arrival rate), in
+    compressed time (idle gaps skipped), with continuous batching and one at
+    a time."""
     from paper_1511_03878_amd import serve
     from paper_1511_03878_amd import workloads as W
     reqs = serve.make_requests(count + warm, rate, steps_range=steps_range)
@@ -287,7 +290,7 @@ def _serve_bench(count, warm, rate, steps_range, budget_gb, precision, compare):
     if compare > 0:
         cmp = {}
         for label, members in (("continuous_batching", 256), ("one_at_a_time", 1)):
-            rq = serve.make_requests(compare, rate, steps_range=steps_range)
+            rq = serve.make_requests(compare, compare_rate, steps_range=steps_range)
             s2 = serve.Server(budget, precision=precision, slice_steps=25, result_fn=lambda sim: {},
                               max_members=members, patch=patch, tune=tune)
             r = s2.run(rq, realtime=False)
@@ -295,6 +298,7 @@ def _serve_bench(count, warm, rate, steps_range, budget_gb, precision, compare):
                           "ttr_p99_s": r["ttr_p99_s"], "wall_s": r["wall_s"]}
         cmp["speedup"] = cmp["continuous_batching"]["throughput"] / cmp["one_at_a_time"]["throughput"]
         cmp["requests"] = compare
+        cmp["rate_per_s"] = compare_rate
         cmp["note"] = "compressed time: idle gaps before an arrival are skipped"
         rep["compressed_comparison"] = cmp
     return rep
@@ -363,6 +367,7 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=20)
     ap.add_argument("--serve-compare", type=int, default=100)
     ap.add_argument("--serve-rate", type=float, default=4.0)
+    ap.add_argument("--serve-compare-rate", type=float, default=40.0)
     ap.add_argument("--serve-steps", default="200,2000")
     ap.add_argument("--pre-steps", type=int, default=0,
                     help="untimed steps of the headline instance before its warm-up (e.g. the laser "
@@ -451,7 +456,8 @@ def main():
         lo, hi = (int(v) for v in args.serve_steps.split(","))
         _log(f"serving {args.serve_warmup} + {args.serve} requests")
         out["served_scan"] = _serve_bench(args.serve, args.serve_warmup, args.serve_rate, (lo, hi),
-                                          200.0, args.precision, args.serve_compare)
+                                          200.0, args.precision, args.serve_compare,
+                                          args.serve_compare_rate)
     if not args.no_cpu:
         _log("timing the CPU oracle")
         out["cpu_baseline"] = _cpu_baseline()
