@@ -2,8 +2,19 @@
 // item (a chunk of one patch) stage the patch's E and B into LDS, then per
 // particle gather with quadratic shapes on 27 nodes, relativistic Boris push,
 // move, classify the destination among the 26 neighbours, and deposit the
-// charge-conserving (Esirkepov) current on a 4 x 4 x 4 node window into an
-// FP64 LDS tile that is flushed to the global current once per item.
+// charge-conserving (Esirkepov) current into an FP64 LDS tile that is
+// flushed to the global current once per item.
+//
+// Deposit in two classes.  A particle whose nearest node changes on no axis
+// has a fixed window (2 x 3 x 3 entries per current component, 54 LDS
+// atomics); one whose nearest node changes on some axis (about one in six in
+// a 10 keV plasma at the Courant limit) needs up to 4 x 4 x 3 per component
+// (144).  A masked LDS atomic costs a wave as much as a full one, so mixing
+// the two in one wave would issue the full window for nearly every wave.
+// The second class is deferred instead: its momentum is stored, its old
+// position left in memory, and its slot listed in LDS; the list is deposited
+// 64 particles at a time, and what remains at the end of an item is pooled
+// over the workgroup's waves.
 //
 // Staggering (half a cell up): Ex, Ey, Ez along their own axis; Bx, By, Bz
 // along the two other axes.  Each component's tile holds just the nodes its
@@ -46,6 +57,92 @@ __device__ __forceinline__ T gather27(const T *tile, int fw, int fwh, int i0, in
     return acc;
 }
 
+// Esirkepov deposit of one particle into the FP64 current tiles:
+// W_a = DS_a (S0_b S0_c + DS_b S0_c / 2 + S0_b DS_c / 2 + DS_b DS_c / 3)
+//     = DS_a (A_b S0_c + B_b DS_c) with A = S0 + DS / 2, B = S0 / 2 + DS / 3,
+// and J_a is the running sum of -q w (d_a / dt) W_a along a (cq, dq, eq hold
+// -q w d_a / dt).  Window slot 3 of an axis carries weight only when the
+// particle's nearest node on that axis changed (c_a).  FULL = false is the
+// fixed window of a particle whose nearest node changed on no axis (2 x 3 x 3
+// entries per component); FULL = true takes each lane's own extents.
+template <bool FULL, typename W>
+__device__ __forceinline__ void deposit_window(double *Jxt, double *Jyt, double *Jzt, const int jpl[3],
+                                               const int jrow[3], int mx, int my, int mz, bool cx, bool cy,
+                                               bool cz, const W S0x[4], const W DSx[4], const W S0y[4],
+                                               const W DSy[4], const W S0z[4], const W DSz[4], W cq, W dq,
+                                               W eq)
+{
+    W Ax[4], Bx[4], Ay[4], By[4];
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) {
+        Ax[k2] = S0x[k2] + W(0.5) * DSx[k2];
+        Bx[k2] = W(0.5) * S0x[k2] + DSx[k2] * W(1.0 / 3.0);
+        Ay[k2] = S0y[k2] + W(0.5) * DSy[k2];
+        By[k2] = W(0.5) * S0y[k2] + DSy[k2] * W(1.0 / 3.0);
+    }
+    W px[3], py[3], pz[3];
+    px[0] = cq * DSx[0];
+    py[0] = dq * DSy[0];
+    pz[0] = eq * DSz[0];
+#pragma unroll
+    for (int k2 = 1; k2 < 3; ++k2) {
+        px[k2] = px[k2 - 1] + cq * DSx[k2];
+        py[k2] = py[k2 - 1] + dq * DSy[k2];
+        pz[k2] = pz[k2 - 1] + eq * DSz[k2];
+    }
+    const int rx = (mz + 2) * jpl[0] + (my + 2) * jrow[0] + (mx + 2);
+    const int ry = (mz + 2) * jpl[1] + (my + 2) * jrow[1] + (mx + 2);
+    const int rz = (mz + 2) * jpl[2] + (my + 2) * jrow[2] + (mx + 2);
+    // prefix entries (the last one is the particle's net zero) and transverse extents
+    const int ni = FULL && cx ? 3 : 2, nj = FULL && cy ? 3 : 2, nk = FULL && cz ? 3 : 2;
+    const int mi = FULL && cx ? 4 : 3, mj = FULL && cy ? 4 : 3, mk = FULL && cz ? 4 : 3;
+    // Jx: dual x (prefix index i), transverse (j, k)
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+        if (kk >= mk) break;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (j >= mj) break;
+            const W tr = Ay[j] * S0z[kk] + By[j] * DSz[kk];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                if (i >= ni) break;
+                atomicAdd(&Jxt[rx + kk * jpl[0] + j * jrow[0] + i], (double)(px[i] * tr));
+            }
+        }
+    }
+    // Jy: dual y (prefix index j), transverse (i, k)
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+        if (kk >= mk) break;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (i >= mi) break;
+            const W tr = Ax[i] * S0z[kk] + Bx[i] * DSz[kk];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                if (j >= nj) break;
+                atomicAdd(&Jyt[ry + kk * jpl[1] + j * jrow[1] + i], (double)(py[j] * tr));
+            }
+        }
+    }
+    // Jz: dual z (prefix index k), transverse (i, j)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (j >= mj) break;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (i >= mi) break;
+            const W tr = Ax[i] * S0y[j] + Bx[i] * DSy[j];
+#pragma unroll
+            for (int kk = 0; kk < 3; ++kk) {
+                if (kk >= nk) break;
+                atomicAdd(&Jzt[rz + kk * jpl[2] + j * jrow[2] + i], (double)(pz[kk] * tr));
+            }
+        }
+    }
+}
+
 // Per-component tile geometry: entries of component c along axis a.
 __host__ __device__ constexpr int fext(int P, int c, int a)
 {
@@ -67,6 +164,8 @@ __global__ __launch_bounds__(BLOCK, (BLOCK == 512 && sizeof(T) == 4) ? 4 : 1) vo
     using W = typename std::conditional<sizeof(T) == 4, float, double>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int s_item[2];
+    __shared__ int s_q[BLOCK / kWave][kWave];  // per wave: slots of deferred particles
+    __shared__ int s_qn[BLOCK / kWave];
 
     const int tid = threadIdx.x, ln = tid % kWave;
     const int total = *glb(nitems);
@@ -197,6 +296,51 @@ __global__ __launch_bounds__(BLOCK, (BLOCK == 512 && sizeof(T) == 4) ? 4 : 1) vo
         const T Pmax0 = below((T)P0), Pmax1 = below((T)P1), Pmax2 = below((T)P2);
         uint32_t err = 0;
         bool left = false;
+        double *Jxt = Jt + jofs[0], *Jyt = Jt + jofs[1], *Jzt = Jt + jofs[2];
+
+        // new position inside the patch (wrapped by one patch edge, kept
+        // below P in storage precision) and the destination code
+        auto place = [&](T &x1, T &y1, T &z1) -> uint8_t {
+            const int sx_ = x1 < T(0) ? -1 : (x1 >= (T)P0 ? 1 : 0);
+            const int sy_ = y1 < T(0) ? -1 : (y1 >= (T)P1 ? 1 : 0);
+            const int sz_ = z1 < T(0) ? -1 : (z1 >= (T)P2 ? 1 : 0);
+            x1 -= (T)(sx_ * P0);
+            y1 -= (T)(sy_ * P1);
+            z1 -= (T)(sz_ * P2);
+            if (x1 > Pmax0) x1 = Pmax0;
+            if (y1 > Pmax1) y1 = Pmax1;
+            if (z1 > Pmax2) z1 = Pmax2;
+            return (uint8_t)((sx_ + 1) + 3 * (sy_ + 1) + 9 * (sz_ + 1));
+        };
+        // Deferred particles (nearest node changed on some axis): their
+        // momentum is already stored and their old position is still in
+        // memory; deposit on the full window, then store position and code.
+        auto push_deferred = [&](bool valid, int kq) {
+            const int k = valid ? kq : 0;
+            const T xl = X0[k], yl = X1[k], zl = X2[k];
+            const T ux = U0[k], uy = U1[k], uz = U2[k];
+            const W qw = valid ? (W)Wt[k] : W(0);
+            const T ig1 = rsq_(T(1) + (ux * ux + uy * uy + uz * uz));
+            const T dxl = rdx * ux * ig1, dyl = rdy * uy * ig1, dzl = rdz * uz * ig1;
+            int mx, my, mz;
+            W S0x[4], DSx[4], S0y[4], DSy[4], S0z[4], DSz[4];
+            const bool cx = window4(xl, (double)dxl, mx, S0x, DSx);
+            const bool cy = window4(yl, (double)dyl, my, S0y, DSy);
+            const bool cz = window4(zl, (double)dzl, mz, S0z, DSz);
+            if (valid)
+                deposit_window<true>(Jxt, Jyt, Jzt, jpl, jrow, mx, my, mz, cx, cy, cz, S0x, DSx, S0y, DSy,
+                                     S0z, DSz, (W)cx_ * qw, (W)cy_ * qw, (W)cz_ * qw);
+            T x1 = xl + dxl, y1 = yl + dyl, z1 = zl + dzl;
+            const uint8_t code = place(x1, y1, z1);
+            if (valid) {
+                X0[k] = x1;
+                X1[k] = y1;
+                X2[k] = z1;
+                Cd[k] = code;
+                left |= code != kStay3;
+            }
+        };
+        int qn = 0;  // entries in this wave's deferred list (wave-uniform)
 
         for (int u = wv; u < uend; u += NW) {
             const int kr = unit_particle(u), k = min(kr, cnt - 1);
@@ -253,9 +397,10 @@ __global__ __launch_bounds__(BLOCK, (BLOCK == 512 && sizeof(T) == 4) ? 4 : 1) vo
                        ((double)usq0 * g1p + (double)usq1 * g0p) / (g0p * g1p);
             }
 
-            // ---- move and classify --------------------------------------------
+            // ---- move, deposit, classify ---------------------------------------
             const T dxl = rdx * ux * ig1, dyl = rdy * uy * ig1, dzl = rdz * uz * ig1;
             uint8_t code;
+            bool defer = false;
             T x1 = xl + dxl, y1 = yl + dyl, z1 = zl + dzl;
             if (!(fabs(dxl) < T(1) && fabs(dyl) < T(1) && fabs(dzl) < T(1))) {
                 err |= (isfinite(ux) && isfinite(uy) && isfinite(uz)) ? kFlagCFL : kFlagNaN;
@@ -265,111 +410,73 @@ __global__ __launch_bounds__(BLOCK, (BLOCK == 512 && sizeof(T) == 4) ? 4 : 1) vo
                 z1 = zl;
             } else {
                 if (dxl != T(0) || dyl != T(0) || dzl != T(0)) {
-                    // ---- Esirkepov deposit on a 4x4x4 node window -------------
-                    // W_a = DS_a (S0_b S0_c + DS_b S0_c / 2 + S0_b DS_c / 2 +
-                    // DS_b DS_c / 3) = DS_a (A_b S0_c + B_b DS_c) with
-                    // A = S0 + DS / 2, B = S0 / 2 + DS / 3; J_a is the running
-                    // sum of -q w (d_a / dt) W_a along a.  Window slot 3 of an
-                    // axis carries weight only when its nearest node changed;
-                    // its (exactly zero) entries skip their atomics.
-                    int mx, my, mz;
                     // weights and products in W (FP32 for FP32 storage: fewer live
                     // registers, so more waves fit); sums in the FP64 tile
+                    int mx, my, mz;
                     W S0x[4], DSx[4], S0y[4], DSy[4], S0z[4], DSz[4];
                     const bool cx = window4(xl, (double)dxl, mx, S0x, DSx);
                     const bool cy = window4(yl, (double)dyl, my, S0y, DSy);
                     const bool cz = window4(zl, (double)dzl, mz, S0z, DSz);
-                    const W qw = (W)wgt;
-                    W Ax[4], Bx_[4], Ay[4], By_[4];
-#pragma unroll
-                    for (int k2 = 0; k2 < 4; ++k2) {
-                        Ax[k2] = S0x[k2] + W(0.5) * DSx[k2];
-                        Bx_[k2] = W(0.5) * S0x[k2] + DSx[k2] * W(1.0 / 3.0);
-                        Ay[k2] = S0y[k2] + W(0.5) * DSy[k2];
-                        By_[k2] = W(0.5) * S0y[k2] + DSy[k2] * W(1.0 / 3.0);
-                    }
-                    const W cq = (W)cx_ * qw, dq = (W)cy_ * qw, eq = (W)cz_ * qw;
-                    W px[3], py[3], pz[3];
-                    px[0] = cq * DSx[0];
-                    py[0] = dq * DSy[0];
-                    pz[0] = eq * DSz[0];
-#pragma unroll
-                    for (int k2 = 1; k2 < 3; ++k2) {
-                        px[k2] = px[k2 - 1] + cq * DSx[k2];
-                        py[k2] = py[k2 - 1] + dq * DSy[k2];
-                        pz[k2] = pz[k2 - 1] + eq * DSz[k2];
-                    }
-                    double *Jxt = Jt + jofs[0], *Jyt = Jt + jofs[1], *Jzt = Jt + jofs[2];
-                    const int rx = (mz + 2) * jpl[0] + (my + 2) * jrow[0] + (mx + 2);
-                    const int ry = (mz + 2) * jpl[1] + (my + 2) * jrow[1] + (mx + 2);
-                    const int rz = (mz + 2) * jpl[2] + (my + 2) * jrow[2] + (mx + 2);
-                    const int ni = cx ? 3 : 2, nj = cy ? 3 : 2, nk = cz ? 3 : 2;
-                    const int mi = cx ? 4 : 3, mj = cy ? 4 : 3, mk = cz ? 4 : 3;
-                    // Jx: dual x (prefix index i), transverse (j, k)
-#pragma unroll
-                    for (int kk = 0; kk < 4; ++kk) {
-                        if (kk >= mk) break;
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            if (j >= mj) break;
-                            const W tr = Ay[j] * S0z[kk] + By_[j] * DSz[kk];
-#pragma unroll
-                            for (int i = 0; i < 3; ++i) {
-                                if (i >= ni) break;
-                                atomicAdd(&Jxt[rx + kk * jpl[0] + j * jrow[0] + i], (double)(px[i] * tr));
-                            }
-                        }
-                    }
-                    // Jy: dual y (prefix index j), transverse (i, k)
-#pragma unroll
-                    for (int kk = 0; kk < 4; ++kk) {
-                        if (kk >= mk) break;
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            if (i >= mi) break;
-                            const W tr = Ax[i] * S0z[kk] + Bx_[i] * DSz[kk];
-#pragma unroll
-                            for (int j = 0; j < 3; ++j) {
-                                if (j >= nj) break;
-                                atomicAdd(&Jyt[ry + kk * jpl[1] + j * jrow[1] + i], (double)(py[j] * tr));
-                            }
-                        }
-                    }
-                    // Jz: dual z (prefix index k), transverse (i, j)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        if (j >= mj) break;
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            if (i >= mi) break;
-                            const W tr = Ax[i] * S0y[j] + Bx_[i] * DSy[j];
-#pragma unroll
-                            for (int kk = 0; kk < 3; ++kk) {
-                                if (kk >= nk) break;
-                                atomicAdd(&Jzt[rz + kk * jpl[2] + j * jrow[2] + i], (double)(pz[kk] * tr));
-                            }
-                        }
+                    defer = cx || cy || cz;
+                    if (!defer) {
+                        const W qw = (W)wgt;
+                        deposit_window<false>(Jxt, Jyt, Jzt, jpl, jrow, mx, my, mz, false, false, false, S0x,
+                                              DSx, S0y, DSy, S0z, DSz, (W)cx_ * qw, (W)cy_ * qw, (W)cz_ * qw);
                     }
                 }
-                const int sx_ = x1 < T(0) ? -1 : (x1 >= (T)P0 ? 1 : 0);
-                const int sy_ = y1 < T(0) ? -1 : (y1 >= (T)P1 ? 1 : 0);
-                const int sz_ = z1 < T(0) ? -1 : (z1 >= (T)P2 ? 1 : 0);
-                x1 -= (T)(sx_ * P0);
-                y1 -= (T)(sy_ * P1);
-                z1 -= (T)(sz_ * P2);
-                if (x1 > Pmax0) x1 = Pmax0;
-                if (y1 > Pmax1) y1 = Pmax1;
-                if (z1 > Pmax2) z1 = Pmax2;
-                code = (uint8_t)((sx_ + 1) + 3 * (sy_ + 1) + 9 * (sz_ + 1));
+                code = place(x1, y1, z1);
             }
-            X0[k] = x1;
-            X1[k] = y1;
-            X2[k] = z1;
+            // a deferred particle keeps its old position in memory until its
+            // deposit (stores stay unconditional: the same value is rewritten)
+            X0[k] = defer ? xl : x1;
+            X1[k] = defer ? yl : y1;
+            X2[k] = defer ? zl : z1;
             U0[k] = ux;
             U1[k] = uy;
             U2[k] = uz;
             Cd[k] = code;
-            left |= code != kStay3;
+            left |= !defer && code != kStay3;
+
+            // ---- deferred list: batches of 64 on the full window ---------------
+            // (lanes past the item's end repeat its last particle and are not
+            // listed: the real lane lists it)
+            const bool listed = defer && kr < cnt;
+            const uint64_t dm = __ballot(listed);
+            const int c = __popcll(dm);
+            if (qn + c > kWave) {
+                push_deferred(ln < qn, s_q[wv][ln]);
+                qn = 0;
+            }
+            // rank among the listed lanes below this one
+            const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(dm >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)dm, 0u));
+            if (listed) s_q[wv][qn + rank] = k;
+            qn += c;
+        }
+
+        // ---- what is left on the deferred lists of all waves, 64 per wave ---
+        if (ln == 0) s_qn[wv] = qn;
+        __syncthreads();
+        {
+            int pre[NW + 1];
+            pre[0] = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) pre[w + 1] = pre[w] + __builtin_amdgcn_readfirstlane(s_qn[w]);
+            const int L = pre[NW];
+            for (int e0 = wv * kWave; e0 < L; e0 += BLOCK) {
+                const int e = e0 + ln;
+                // source wave and position of entry e (selects, no indexed registers)
+                int src = 0, off = e;
+#pragma unroll
+                for (int w = 1; w < NW; ++w)
+                    if (e >= pre[w]) {
+                        src = w;
+                        off = e - pre[w];
+                    }
+                const bool valid = e < L;
+                const int k = s_q[src][valid ? off : 0];  // always an in-range entry
+                push_deferred(valid, k);
+            }
         }
         if (__ballot(left) && ln == 0) *glb(S.moved + p) = 1;
         if (err)

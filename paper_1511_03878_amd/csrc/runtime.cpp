@@ -1736,14 +1736,17 @@ void BatchImpl<T>::build_tables()
                 m->P[0] != members[0]->P[0] || m->P[1] != members[0]->P[1] || m->P[2] != members[0]->P[2])
                 patch_const = 0;
     }
-    // chunk: enough items to fill every CU several times over
+    // chunk: enough items to fill every CU several times over, at most 4096
+    // particles in 2-D (laser box: 4096 beat 8192 and 16384) and 16384 in 3-D
+    // (blob box: one item per 8^3 patch saves the per-item staging, flush and
+    // deferred-list batches; 22.0 ms per launch against 22.7 ms at 4096)
     chunk = 0;
     for (auto *m : members) chunk = std::max(chunk, (int)m->desc.chunk);
     if (chunk == 0) {
         const int64_t target = (int64_t)cu_count() * 8;
         int64_t c = particles / std::max<int64_t>(target, 1);
         c = std::max<int64_t>(c, 256);
-        c = std::min<int64_t>(c, 4096);
+        c = std::min<int64_t>(c, nd == 3 ? 16384 : 4096);
         chunk = (int)c;
     }
     for (auto *m : members) items += m->max_items(chunk);
