@@ -94,10 +94,10 @@ def _options(name, wl):
     return {}
 
 
-def _sim_for(wl, name, precision):
+def _sim_for(wl, name, precision, **extra):
     from paper_1511_03878_amd.sim import Sim
     opts = _options(name, wl)
-    sim = Sim.from_workload(wl, precision=precision, **opts.get("tune", {}))
+    sim = Sim.from_workload(wl, precision=precision, **opts.get("tune", {}), **extra)
     if "window" in opts:
         sim.set_window(*opts["window"])
     if "merge" in opts:
@@ -186,6 +186,25 @@ def _imbalance(sim):
 
 # ---------------------------------------------------------------------------
 # extra measurements
+
+def _det_window(wl, args):
+    """The headline workload again with deterministic deposition (same warm-up
+    and window): the cost of bitwise-reproducible currents."""
+    import torch
+    sim = _sim_for(wl, args.workload, args.precision, deterministic=1)
+    if args.pre_steps > 0:
+        sim.step(args.pre_steps)
+    if args.warmup > 0:
+        sim.step(args.warmup)
+    sim.sync()
+    val, ms, _, roof = _timed_window(sim, args.steps, wl["grid"]["ndim"], args.precision, args.workload,
+                                     kernel_timing=not args.no_kernel_timing)
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return {"value": val, "ms_per_step": ms, "unit": "particle-steps/s",
+            "kernel_ms_per_launch": roof["kernel_ms_per_launch"] if roof else None,
+            "note": "64-bit fixed-point current summed with integer atomics; runs repeat bit for bit"}
 
 def _lwfa_late(precision, pre_steps=1000, steps=200):
     """The laser box timed after its first `pre_steps` steps (wake formed,
@@ -373,6 +392,11 @@ def main():
                     help="untimed steps of the headline instance before its warm-up (e.g. the laser "
                          "box after step 1000)")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--deterministic", action="store_true",
+                    help="run the headline with deterministic deposition (fixed-point current "
+                         "accumulators, bitwise reproducible)")
+    ap.add_argument("--no-det", action="store_true",
+                    help="skip the extra window of the headline workload in deterministic mode")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first time an elementwise kernel that reads and writes MIB MiB (calibrates "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE against a known byte count)")
@@ -406,7 +430,7 @@ def main():
     wl, desc = _workload(args.workload)
     ndim = wl["grid"]["ndim"]
     t_setup = time.perf_counter()
-    sim = _sim_for(wl, args.workload, args.precision)
+    sim = _sim_for(wl, args.workload, args.precision, deterministic=int(args.deterministic))
     sim.sync()
     _log(f"workload loaded on the device in {time.perf_counter() - t_setup:.1f} s: {desc}")
     if args.pre_steps > 0:
@@ -441,11 +465,15 @@ def main():
     }
     if args.pre_steps:
         out["config"]["steps_before_warmup"] = args.pre_steps
+    out["config"]["deterministic"] = bool(args.deterministic)
     if copy_cal:
         out["copy_calibration"] = copy_cal
     sim.close()
     del sim
     torch.cuda.empty_cache()
+    if not args.no_det and not args.deterministic:
+        _log("headline workload in deterministic mode")
+        out["deterministic_mode"] = _det_window(wl, args)
     if not args.no_late:
         _log("laser box after step 1000")
         out["lwfa_late"] = _lwfa_late(args.precision)

@@ -100,7 +100,7 @@ typedef struct {
     double q, m;           /* species charge and mass */
     double capacity_factor;/* slots per patch = max(min_capacity, factor * count); 0 = 3 */
     int32_t min_capacity;  /* 0 = the mean patch occupancy (at least 64) */
-    int32_t chunk;         /* max particles per work item; 0 = chosen from the load */
+    int32_t chunk;         /* max particles per work item, at most 16384; 0 = chosen from the load */
     int32_t block;         /* threads per particle workgroup: 256, 512 or 1024; 0 = 512 (FP32) / 1024 (FP64) */
     int32_t field_tile;    /* Yee tile shape preset 0..5 (0 = default for the precision) */
     int32_t lane_stride;   /* particles between adjacent lanes of the particle kernel, 1..64;
@@ -113,6 +113,13 @@ typedef struct {
                               differences of sixth order on the same grid (every axis periodic,
                               dt < (sum_m |c_m|)^(-1) (sum 1/d^2)^(-1/2) with
                               c = 75/64, -25/384, 3/640) */
+    int32_t deterministic; /* 1: currents are summed in 64-bit fixed point across work items
+                              (integer atomics), so a run repeats bit for bit and gives the same
+                              bits alone and in a batch; needs 24 more bytes per field node and
+                              holds while at most 32768 particles deposit at one node in a step.
+                              0: work items add their current tiles
+                              through float atomics (faster; summation order varies at the
+                              rounding level).  The paper does not treat summation order. */
 } PicSimDesc;
 
 /* Diagnostics of a simulation (pic_diag_get synchronises the stream). */

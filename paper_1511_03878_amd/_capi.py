@@ -48,7 +48,7 @@ class SimDesc(C.Structure):
         ("capacity_factor", C.c_double), ("min_capacity", C.c_int32), ("chunk", C.c_int32),
         ("block", C.c_int32), ("field_tile", C.c_int32), ("lane_stride", C.c_int32),
         ("graph", C.c_int32), ("patch_order", C.c_int32),
-        ("maxwell_order", C.c_int32),
+        ("maxwell_order", C.c_int32), ("deterministic", C.c_int32),
     ]
 
 

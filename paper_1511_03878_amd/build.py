@@ -13,7 +13,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpic.so")
 
 SOURCES = ["k_particles.hip", "k_particles3d.hip", "k_maxwell.hip", "k_maxwell3d.hip", "k_rebin.hip",
-           "k_window.hip", "k_merge.hip", "k_diag.hip", "k_noalloc.hip", "k_init.hip", "runtime.cpp", "order.cpp", "capi.cpp"]
+           "k_window.hip", "k_merge.hip", "k_diag.hip", "k_noalloc.hip", "k_init.hip", "k_current.hip", "runtime.cpp", "order.cpp", "capi.cpp"]
 
 FLAGS = [
     "-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

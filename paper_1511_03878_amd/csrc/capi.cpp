@@ -474,6 +474,7 @@ int pic_estimate_bytes(const PicSimDesc *d, int64_t nparticles, int64_t laser_st
     b += npatch * (4 * 7 + 4 * ndir + 4 * (3 * ndir - 1) + 8 + 8 + 4);
     b += max_tiles * 8 + 8 * 4 * 4096 + 4096;          // tile partials, history, state
     b += 8 * fsize;                                    // charge density at load (diagnostics)
+    if (d->deterministic) b += 3 * 8 * fsize;          // fixed-point current accumulators
     b += laser_steps * d->n[1] * s * 2;
     *bytes = b;
     return PIC_OK;

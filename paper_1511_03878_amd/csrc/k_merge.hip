@@ -197,6 +197,9 @@ __device__ void write_pair(const SimDev<T> &S, int64_t base, int64_t lst, const 
     double ct = ut > 0.0 ? pn / (W * ut) : 0.0;
     if (ct > 1.0) ct = 1.0;
     const double st = sqrt(1.0 - ct * ct);
+    // the pair's weight can exceed every earlier weight: raise the bound
+    // behind the fixed-point current scale
+    raise_wmax(S, (double)(T)(0.5 * W));
     for (int h = 0; h < 2; ++h) {
         const int64_t t = dst + h;
         const double sg = h == 0 ? 1.0 : -1.0;

@@ -2,7 +2,8 @@
 // one patch): stage the patch's E and B into LDS, then per particle gather
 // with quadratic shapes, relativistic Boris push, move, classify the
 // destination patch, and deposit the charge-conserving (Esirkepov) current
-// into an LDS tile that is flushed to the global current once per item.
+// into a 64-bit fixed-point LDS tile (exact integer sums, independent of the
+// order of the atomics) that is flushed to the global current once per item.
 //
 // The paper's patches (section 3.1) are small independent structures of
 // fields and particles; here one workgroup owns one patch chunk at a time,
@@ -48,7 +49,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
     extern __shared__ __align__(16) unsigned char smem_raw[];
     // current tile first (FP64 accumulation for either storage precision:
     // LDS float atomics are much slower here than FP64 ones), then fields
-    double *Jt = reinterpret_cast<double *>(smem_raw);
+    long long *Jt = reinterpret_cast<long long *>(smem_raw);
     T *Ft = reinterpret_cast<T *>(Jt + 3 * jstride);
     __shared__ int s_item[2];
 
@@ -100,6 +101,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
         const T rdx = dt / S.d[0], rdy = dt / S.d[1];
         const double cx_ = -(double)q * (double)S.d[0] / (double)dt;
         const double cy_ = -(double)q * (double)S.d[1] / (double)dt;
+        const double fs = fix_scale(S), fsinv = 1.0 / fs;  // fixed-point scale of the current
         const T Pmax0 = below((T)P0), Pmax1 = below((T)P1);
         const bool edge_lo = !per0 && pxi == 0, edge_hi = !per0 && pxi == S.np[0] - 1;
         if (si != kin_sim) {
@@ -176,7 +178,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
                     for (int c = 0; c < 6; ++c) Ft[c * fstride + t] = ok[r][c] ? v[r][c] : T(0);
             }
         }
-        for (int t = tid; t < 3 * jstride; t += BLOCK) Jt[t] = 0.0;
+        for (int t = tid; t < 3 * jstride; t += BLOCK) Jt[t] = 0;
         __syncthreads();
         if (tid == 0) s_item[slot] = next;  // read after the item's last barrier
 
@@ -258,7 +260,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
                 const bool cy = window4(yl, (double)dyl, my, S0y, DSy);
                 const double qw = (double)wgt;
                 const double az = (double)q * qw * (double)(uz * ig1);
-                double *Jxt = Jt, *Jyt = Jt + jstride, *Jzt = Jt + 2 * jstride;
+                long long *Jxt = Jt, *Jyt = Jt + jstride, *Jzt = Jt + 2 * jstride;
                 const int r0 = (my + 2) * jw + (mx + 2);
                 // time-averaged transverse weights
                 double wx[4], wy[4];
@@ -278,26 +280,26 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
                     py[2] = py[1] + cy_ * qw * DSy[2];
 #pragma unroll
                     for (int j = 0; j < 3; ++j) {
-                        atomicAdd(&Jxt[r0 + j * jw + 0], px[0] * wy[j]);
-                        atomicAdd(&Jxt[r0 + j * jw + 1], px[1] * wy[j]);
-                        if (cx) atomicAdd(&Jxt[r0 + j * jw + 2], px[2] * wy[j]);
+                        fix_add(&Jxt[r0 + j * jw + 0], px[0] * wy[j], fs);
+                        fix_add(&Jxt[r0 + j * jw + 1], px[1] * wy[j], fs);
+                        if (cx) fix_add(&Jxt[r0 + j * jw + 2], px[2] * wy[j], fs);
                     }
                     if (cy) {
-                        atomicAdd(&Jxt[r0 + 3 * jw + 0], px[0] * wy[3]);
-                        atomicAdd(&Jxt[r0 + 3 * jw + 1], px[1] * wy[3]);
-                        if (cx) atomicAdd(&Jxt[r0 + 3 * jw + 2], px[2] * wy[3]);
+                        fix_add(&Jxt[r0 + 3 * jw + 0], px[0] * wy[3], fs);
+                        fix_add(&Jxt[r0 + 3 * jw + 1], px[1] * wy[3], fs);
+                        if (cx) fix_add(&Jxt[r0 + 3 * jw + 2], px[2] * wy[3], fs);
                     }
                     // Jy on dual y nodes: running sums along y, times wx
 #pragma unroll
                     for (int i = 0; i < 3; ++i) {
-                        atomicAdd(&Jyt[r0 + 0 * jw + i], py[0] * wx[i]);
-                        atomicAdd(&Jyt[r0 + 1 * jw + i], py[1] * wx[i]);
-                        if (cy) atomicAdd(&Jyt[r0 + 2 * jw + i], py[2] * wx[i]);
+                        fix_add(&Jyt[r0 + 0 * jw + i], py[0] * wx[i], fs);
+                        fix_add(&Jyt[r0 + 1 * jw + i], py[1] * wx[i], fs);
+                        if (cy) fix_add(&Jyt[r0 + 2 * jw + i], py[2] * wx[i], fs);
                     }
                     if (cx) {
-                        atomicAdd(&Jyt[r0 + 0 * jw + 3], py[0] * wx[3]);
-                        atomicAdd(&Jyt[r0 + 1 * jw + 3], py[1] * wx[3]);
-                        if (cy) atomicAdd(&Jyt[r0 + 2 * jw + 3], py[2] * wx[3]);
+                        fix_add(&Jyt[r0 + 0 * jw + 3], py[0] * wx[3], fs);
+                        fix_add(&Jyt[r0 + 1 * jw + 3], py[1] * wx[3], fs);
+                        if (cy) fix_add(&Jyt[r0 + 2 * jw + 3], py[2] * wx[3], fs);
                     }
                 }
                 if (az != 0.0) {
@@ -313,14 +315,14 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
                     for (int j = 0; j < 3; ++j) {
 #pragma unroll
                         for (int i = 0; i < 3; ++i)
-                            atomicAdd(&Jzt[r0 + j * jw + i], ax_[i] * S0y[j] + bx_[i] * DSy[j]);
-                        if (cx) atomicAdd(&Jzt[r0 + j * jw + 3], ax_[3] * S0y[j] + bx_[3] * DSy[j]);
+                            fix_add(&Jzt[r0 + j * jw + i], ax_[i] * S0y[j] + bx_[i] * DSy[j], fs);
+                        if (cx) fix_add(&Jzt[r0 + j * jw + 3], ax_[3] * S0y[j] + bx_[3] * DSy[j], fs);
                     }
                     if (cy) {
 #pragma unroll
                         for (int i = 0; i < 3; ++i)
-                            atomicAdd(&Jzt[r0 + 3 * jw + i], ax_[i] * S0y[3] + bx_[i] * DSy[3]);
-                        if (cx) atomicAdd(&Jzt[r0 + 3 * jw + 3], ax_[3] * S0y[3] + bx_[3] * DSy[3]);
+                            fix_add(&Jzt[r0 + 3 * jw + i], ax_[i] * S0y[3] + bx_[i] * DSy[3], fs);
+                        if (cx) fix_add(&Jzt[r0 + 3 * jw + 3], ax_[3] * S0y[3] + bx_[3] * DSy[3], fs);
                     }
                 }
 
@@ -350,14 +352,25 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
         // ---- flush the current tile -------------------------------------------
         {
             const gptr_t<T> Jgx = glb(S.J[par][0]), Jgy = glb(S.J[par][1]), Jgz = glb(S.J[par][2]);
+            const bool det = S.det != 0;
             for (int t = tid; t < jw * jh; t += BLOCK) {
                 const int gi = ox - 2 + t % jw, gj = oy - 2 + t / jw;
                 const int ip = axis_node(gi, n0, per0, 0), id = axis_node(gi, n0, per0, 1);
                 const int jp = axis_node(gj, n1, per1, 0), jd = axis_node(gj, n1, per1, 1);
-                const T vx = (T)Jt[t], vy = (T)Jt[jstride + t], vz = (T)Jt[2 * jstride + t];
-                if (vx != T(0) && id >= 0 && jp >= 0) gadd(Jgx + (id + fn0 * jp), vx);
-                if (vy != T(0) && ip >= 0 && jd >= 0) gadd(Jgy + (ip + fn0 * jd), vy);
-                if (vz != T(0) && ip >= 0 && jp >= 0) gadd(Jgz + (ip + fn0 * jp), vz);
+                const long long vx = Jt[t], vy = Jt[jstride + t], vz = Jt[2 * jstride + t];
+                const bool kx = vx != 0 && id >= 0 && jp >= 0, ky = vy != 0 && ip >= 0 && jd >= 0;
+                const bool kz = vz != 0 && ip >= 0 && jp >= 0;
+                // deterministic: integer adds to the fixed-point accumulators;
+                // else the values in storage precision through float atomics
+                if (det) {
+                    if (kx) gadd(glb(S.Jacc[0]) + (id + fn0 * jp), (int64_t)vx);
+                    if (ky) gadd(glb(S.Jacc[1]) + (ip + fn0 * jd), (int64_t)vy);
+                    if (kz) gadd(glb(S.Jacc[2]) + (ip + fn0 * jp), (int64_t)vz);
+                } else {
+                    if (kx) gadd(Jgx + (id + fn0 * jp), (T)((double)vx * fsinv));
+                    if (ky) gadd(Jgy + (ip + fn0 * jd), (T)((double)vy * fsinv));
+                    if (kz) gadd(Jgz + (ip + fn0 * jp), (T)((double)vz * fsinv));
+                }
             }
         }
         __syncthreads();
@@ -373,7 +386,7 @@ size_t lds_bytes(int maxP0, int maxP1, int &fstride, int &jstride)
 {
     fstride = (maxP0 + 3) * (maxP1 + 3);
     jstride = (maxP0 + 5) * (maxP1 + 5);
-    return sizeof(double) * (size_t)(3 * jstride) + sizeof(T) * (size_t)(6 * fstride);
+    return sizeof(int64_t) * (size_t)(3 * jstride) + sizeof(T) * (size_t)(6 * fstride);
 }
 
 }  // namespace

@@ -2,8 +2,9 @@
 // item (a chunk of one patch) stage the patch's E and B into LDS, then per
 // particle gather with quadratic shapes on 27 nodes, relativistic Boris push,
 // move, classify the destination among the 26 neighbours, and deposit the
-// charge-conserving (Esirkepov) current into an FP64 LDS tile that is
-// flushed to the global current once per item.
+// charge-conserving (Esirkepov) current into a 64-bit fixed-point LDS tile
+// (exact integer sums, so the tile does not depend on the order of the
+// atomics) that is flushed to the global current once per item.
 //
 // Deposit in two classes.  A particle whose nearest node changes on no axis
 // has a fixed window (2 x 3 x 3 entries per current component, 54 LDS
@@ -22,7 +23,7 @@
 // component sits on primal nodes the gather reads nodes -1 .. P+1 (P + 3),
 // where it sits half a cell up -1 .. P (P + 2); the current J_a spans dual
 // nodes -2 .. P+1 along a (P + 4) and primal nodes -2 .. P+2 across (P + 5).
-// For 8^3-cell patches the two tiles take 76 KB (FP32 fields, FP64
+// For 8^3-cell patches the two tiles take 76 KB (FP32 fields, 64-bit
 // currents), so two workgroups share a CU.  Patch shapes 8 x 8 x 8 and
 // 8 x 8 x 4 are compiled with constant tile pitches (LDS offsets become
 // instruction immediates); other shapes take the general kernel.
@@ -57,7 +58,7 @@ __device__ __forceinline__ T gather27(const T *tile, int fw, int fwh, int i0, in
     return acc;
 }
 
-// Esirkepov deposit of one particle into the FP64 current tiles:
+// Esirkepov deposit of one particle into the fixed-point current tiles (fs: scale):
 // W_a = DS_a (S0_b S0_c + DS_b S0_c / 2 + S0_b DS_c / 2 + DS_b DS_c / 3)
 //     = DS_a (A_b S0_c + B_b DS_c) with A = S0 + DS / 2, B = S0 / 2 + DS / 3,
 // and J_a is the running sum of -q w (d_a / dt) W_a along a (cq, dq, eq hold
@@ -66,11 +67,11 @@ __device__ __forceinline__ T gather27(const T *tile, int fw, int fwh, int i0, in
 // fixed window of a particle whose nearest node changed on no axis (2 x 3 x 3
 // entries per component); FULL = true takes each lane's own extents.
 template <bool FULL, typename W>
-__device__ __forceinline__ void deposit_window(double *Jxt, double *Jyt, double *Jzt, const int jpl[3],
+__device__ __forceinline__ void deposit_window(long long *Jxt, long long *Jyt, long long *Jzt, const int jpl[3],
                                                const int jrow[3], int mx, int my, int mz, bool cx, bool cy,
                                                bool cz, const W S0x[4], const W DSx[4], const W S0y[4],
                                                const W DSy[4], const W S0z[4], const W DSz[4], W cq, W dq,
-                                               W eq)
+                                               W eq, double fs)
 {
     W Ax[4], Bx[4], Ay[4], By[4];
 #pragma unroll
@@ -107,7 +108,7 @@ __device__ __forceinline__ void deposit_window(double *Jxt, double *Jyt, double 
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 if (i >= ni) break;
-                atomicAdd(&Jxt[rx + kk * jpl[0] + j * jrow[0] + i], (double)(px[i] * tr));
+                fix_add(&Jxt[rx + kk * jpl[0] + j * jrow[0] + i], (double)(px[i] * tr), fs);
             }
         }
     }
@@ -122,7 +123,7 @@ __device__ __forceinline__ void deposit_window(double *Jxt, double *Jyt, double 
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
                 if (j >= nj) break;
-                atomicAdd(&Jyt[ry + kk * jpl[1] + j * jrow[1] + i], (double)(py[j] * tr));
+                fix_add(&Jyt[ry + kk * jpl[1] + j * jrow[1] + i], (double)(py[j] * tr), fs);
             }
         }
     }
@@ -137,7 +138,7 @@ __device__ __forceinline__ void deposit_window(double *Jxt, double *Jyt, double 
 #pragma unroll
             for (int kk = 0; kk < 3; ++kk) {
                 if (kk >= nk) break;
-                atomicAdd(&Jzt[rz + kk * jpl[2] + j * jrow[2] + i], (double)(pz[kk] * tr));
+                fix_add(&Jzt[rz + kk * jpl[2] + j * jrow[2] + i], (double)(pz[kk] * tr), fs);
             }
         }
     }
@@ -219,7 +220,7 @@ __global__ __launch_bounds__(BLOCK, (BLOCK == 512 && sizeof(T) == 4) ? 4 : 1) vo
             }
         }
         const int jtot = jofs[2] + jpl[2] * jext(P2, 2, 2);
-        double *Jt = reinterpret_cast<double *>(smem_raw);
+        long long *Jt = reinterpret_cast<long long *>(smem_raw);
         T *Ft = reinterpret_cast<T *>(Jt + jtot);
         const int n0 = S.n[0], n1 = S.n[1], n2 = S.n[2];
         const int fn0 = S.fn[0], fn1 = S.fn[1];
@@ -283,7 +284,7 @@ __global__ __launch_bounds__(BLOCK, (BLOCK == 512 && sizeof(T) == 4) ? 4 : 1) vo
                 }
             }
         }
-        for (int t = tid; t < jtot; t += BLOCK) Jt[t] = 0.0;
+        for (int t = tid; t < jtot; t += BLOCK) Jt[t] = 0;
         __syncthreads();
         if (tid == 0) s_item[slot] = next;  // read after the item's last barrier
 
@@ -296,7 +297,8 @@ __global__ __launch_bounds__(BLOCK, (BLOCK == 512 && sizeof(T) == 4) ? 4 : 1) vo
         const T Pmax0 = below((T)P0), Pmax1 = below((T)P1), Pmax2 = below((T)P2);
         uint32_t err = 0;
         bool left = false;
-        double *Jxt = Jt + jofs[0], *Jyt = Jt + jofs[1], *Jzt = Jt + jofs[2];
+        long long *Jxt = Jt + jofs[0], *Jyt = Jt + jofs[1], *Jzt = Jt + jofs[2];
+        const double fs = fix_scale(S), fsinv = 1.0 / fs;  // fixed-point scale of the current
 
         // new position inside the patch (wrapped by one patch edge, kept
         // below P in storage precision) and the destination code
@@ -329,7 +331,7 @@ __global__ __launch_bounds__(BLOCK, (BLOCK == 512 && sizeof(T) == 4) ? 4 : 1) vo
             const bool cz = window4(zl, (double)dzl, mz, S0z, DSz);
             if (valid)
                 deposit_window<true>(Jxt, Jyt, Jzt, jpl, jrow, mx, my, mz, cx, cy, cz, S0x, DSx, S0y, DSy,
-                                     S0z, DSz, (W)cx_ * qw, (W)cy_ * qw, (W)cz_ * qw);
+                                     S0z, DSz, (W)cx_ * qw, (W)cy_ * qw, (W)cz_ * qw, fs);
             T x1 = xl + dxl, y1 = yl + dyl, z1 = zl + dzl;
             const uint8_t code = place(x1, y1, z1);
             if (valid) {
@@ -411,7 +413,7 @@ __global__ __launch_bounds__(BLOCK, (BLOCK == 512 && sizeof(T) == 4) ? 4 : 1) vo
             } else {
                 if (dxl != T(0) || dyl != T(0) || dzl != T(0)) {
                     // weights and products in W (FP32 for FP32 storage: fewer live
-                    // registers, so more waves fit); sums in the FP64 tile
+                    // registers, so more waves fit); sums in the fixed-point tile
                     int mx, my, mz;
                     W S0x[4], DSx[4], S0y[4], DSy[4], S0z[4], DSz[4];
                     const bool cx = window4(xl, (double)dxl, mx, S0x, DSx);
@@ -421,7 +423,8 @@ __global__ __launch_bounds__(BLOCK, (BLOCK == 512 && sizeof(T) == 4) ? 4 : 1) vo
                     if (!defer) {
                         const W qw = (W)wgt;
                         deposit_window<false>(Jxt, Jyt, Jzt, jpl, jrow, mx, my, mz, false, false, false, S0x,
-                                              DSx, S0y, DSy, S0z, DSz, (W)cx_ * qw, (W)cy_ * qw, (W)cz_ * qw);
+                                              DSx, S0y, DSy, S0z, DSz, (W)cx_ * qw, (W)cy_ * qw, (W)cz_ * qw,
+                                              fs);
                     }
                 }
                 code = place(x1, y1, z1);
@@ -484,8 +487,11 @@ __global__ __launch_bounds__(BLOCK, (BLOCK == 512 && sizeof(T) == 4) ? 4 : 1) vo
         __syncthreads();
 
         // ---- flush the current tile (nodes [o-2, o+P+2] on every axis) ------
+        // deterministic: integer adds to the fixed-point accumulators; else
+        // the tile's values in storage precision through float atomics
         {
             const gptr_t<T> Jgx = glb(S.J[par][0]), Jgy = glb(S.J[par][1]), Jgz = glb(S.J[par][2]);
+            const bool det = S.det != 0;
             for (int t = tid; t < jstride; t += BLOCK) {
                 const int a = t % jw, b = (t / jw) % jh, c = t / jwh;
                 const int gi = axis_node(ox - 2 + a, n0, 1, 0);
@@ -493,12 +499,18 @@ __global__ __launch_bounds__(BLOCK, (BLOCK == 512 && sizeof(T) == 4) ? 4 : 1) vo
                 const int gk = axis_node(oz - 2 + c, n2, 1, 0);
                 const int64_t k = gi + (int64_t)fn0 * (gj + (int64_t)fn1 * gk);
                 // entries outside a component's tile hold no current
-                const T vx = a < jrow[0] ? (T)Jt[jofs[0] + c * jpl[0] + b * jrow[0] + a] : T(0);
-                const T vy = b < jext(P1, 1, 1) ? (T)Jt[jofs[1] + c * jpl[1] + b * jrow[1] + a] : T(0);
-                const T vz = c < jext(P2, 2, 2) ? (T)Jt[jofs[2] + c * jpl[2] + b * jrow[2] + a] : T(0);
-                if (vx != T(0)) gadd(Jgx + k, vx);
-                if (vy != T(0)) gadd(Jgy + k, vy);
-                if (vz != T(0)) gadd(Jgz + k, vz);
+                const long long vx = a < jrow[0] ? Jt[jofs[0] + c * jpl[0] + b * jrow[0] + a] : 0;
+                const long long vy = b < jext(P1, 1, 1) ? Jt[jofs[1] + c * jpl[1] + b * jrow[1] + a] : 0;
+                const long long vz = c < jext(P2, 2, 2) ? Jt[jofs[2] + c * jpl[2] + b * jrow[2] + a] : 0;
+                if (det) {
+                    if (vx) gadd(glb(S.Jacc[0]) + k, (int64_t)vx);
+                    if (vy) gadd(glb(S.Jacc[1]) + k, (int64_t)vy);
+                    if (vz) gadd(glb(S.Jacc[2]) + k, (int64_t)vz);
+                } else {
+                    if (vx) gadd(Jgx + k, (T)((double)vx * fsinv));
+                    if (vy) gadd(Jgy + k, (T)((double)vy * fsinv));
+                    if (vz) gadd(Jgz + k, (T)((double)vz * fsinv));
+                }
             }
         }
         __syncthreads();
@@ -516,7 +528,7 @@ size_t particles3d_lds_bytes(int precision, int P0, int P1, int P2)
     size_t js = 0, fs = 0;
     for (int c = 0; c < 3; ++c) js += (size_t)jext(P0, c, 0) * jext(P1, c, 1) * jext(P2, c, 2);
     for (int c = 0; c < 6; ++c) fs += (size_t)fext(P0, c, 0) * fext(P1, c, 1) * fext(P2, c, 2);
-    return sizeof(double) * js + (size_t)(precision / 8) * fs;
+    return sizeof(int64_t) * js + (size_t)(precision / 8) * fs;
 }
 
 namespace {

@@ -129,6 +129,7 @@ __global__ __launch_bounds__(kWB) void k_window2d(const SimDev<T> *__restrict__ 
         if (ninj <= 0) continue;
         // the cold lattice of the new column, in (cell row, cell column, b, a) order
         const int64_t id0 = st->next_id + (int64_t)py * ninj;
+        double wloc = 0.0;  // largest injected weight of this thread
         for (int t = tid; t < ninj; t += kWB) {
             const int jl = t / per_row, rem = t - jl * per_row;
             int k = rem / ppc;
@@ -149,9 +150,12 @@ __global__ __launch_bounds__(kWB) void k_window2d(const SimDev<T> *__restrict__ 
             glb(S.u[1])[slot] = T(0);
             glb(S.u[2])[slot] = T(0);
             glb(S.w)[slot] = (T)(dens / ppc);
+            wloc = fmax(wloc, fabs((double)(T)(dens / ppc)));
             glb(S.id)[slot] = id0 + t;
             glb(S.code)[slot] = (uint8_t)kStay2;
         }
+        // the bound behind the fixed-point current scale covers the new weights
+        if (wloc > 0.0) raise_wmax(S, wloc);
     }
 }
 

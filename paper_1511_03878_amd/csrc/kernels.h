@@ -145,6 +145,17 @@ void launch_rebin(const SimDev<T> *sims, int nsims, const int *patch_prefix, int
 template <typename T>
 void launch_relayout(const SimDev<T> *src, const SimDev<T> *dst, int npatch, hipStream_t st);
 
+// Fixed-point current (k_current.hip).  launch_wmax raises the simulation's
+// weight bound to the largest |w| of its particles (after a load).
+// launch_jfix converts the deterministic accumulators of the listed
+// simulations into J[step & 1] and clears them (prefix: exclusive prefix of
+// their node counts, nlist + 1 entries; total = prefix[nlist]).
+template <typename T>
+void launch_wmax(const SimDev<T> *sim, int npatch, hipStream_t st);
+template <typename T>
+void launch_jfix(const SimDev<T> *sims, const int *list, const int64_t *prefix, int nlist, int64_t total,
+                 hipStream_t st);
+
 // Diagnostics (k_diag.hip).  fill_doubles clears with a kernel (safe under
 // graph capture).  launch_rho adds the particles' charge density on primal
 // nodes (2-D or 3-D) into `out` (fn[0] fn[1] fn[2] doubles, cleared by the

@@ -56,6 +56,8 @@ struct SimState {
     uint32_t wpend;      // the step in flight jumped (applied when the step closes)
     uint32_t pad2;
     int64_t merged;      // particles taken out by merging so far
+    uint64_t wmax_bits;  // bound on |weight| of every particle (FP64 bits; set at load, raised by
+                         // merging and window injection)
 };
 
 template <typename T>
@@ -83,6 +85,11 @@ struct SimDev {
     // has already advanced) and two current buffers (deposit into J[step & 1])
     T *F[2][6];
     T *J[2][3];
+    // deterministic deposition: the particle kernel adds its current tiles to
+    // these fixed-point accumulators (integer sums do not depend on order);
+    // a conversion pass turns them into J[step & 1] and clears them
+    int det;
+    int64_t *Jacc[3];
     // particles
     T *x[3], *u[3], *w;
     int64_t *id;
@@ -194,6 +201,53 @@ __device__ __forceinline__ int find_sim(const int *prefix, int nsims, int g)
         if (prefix[mid] <= g) lo = mid; else hi = mid - 1;
     }
     return lo;
+}
+
+
+// ---- fixed-point current ---------------------------------------------------
+// Current tiles accumulate integers: a contribution c enters as round(c 2^s)
+// with 2^(48 - s) above |q| w_max, which bounds every contribution one
+// particle makes to one node of one component: Esirkepov's running sum of
+// the shape differences along a is the change of a discrete shape CDF whose
+// slope is at most one, so it is at most the move d_a in cells, and
+// (-q w Delta_a / dt) d_a = -q w v_a with |v_a| < 1; the time-averaged
+// transverse weights lie in [0, 1]; the 2-D out-of-plane current is q w v_z
+// times such weights.  One item's sum at a node stays below 2^62 for items
+// of up to 2^14 particles; the deterministic accumulators hold the sum over
+// every particle depositing at a node in one step, below 2^63 while those
+// number at most 2^15.  One unit is at most 2^-47 |q| w_max.  The integer of
+// a double below 2^51 in magnitude is read from the low mantissa bits of
+// v + 1.5 * 2^52 (the addition rounds to nearest).
+constexpr double kFixMagic = 6755399441055744.0;  // 1.5 * 2^52
+constexpr long long kFixMagicBits = 0x4338000000000000LL;
+
+template <typename T>
+__device__ __forceinline__ double fix_scale(const SimDev<T> &S)
+{
+    const double wmax = __longlong_as_double((long long)glb(S.st)->wmax_bits);
+    const double cb = fabs((double)S.q) * wmax;
+    if (!(cb > 0.0) || !(cb < 1e300)) return 1.0;
+    return ldexp(1.0, 48 - (ilogb(cb) + 1));
+}
+
+__device__ __forceinline__ long long to_fix(double c, double scale)
+{
+    return __double_as_longlong(fma(c, scale, kFixMagic)) - kFixMagicBits;
+}
+
+// LDS atomic add of a contribution to a fixed-point tile entry
+__device__ __forceinline__ void fix_add(long long *p, double c, double scale)
+{
+    atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)to_fix(c, scale));
+}
+
+// Raise the simulation's weight bound to |w| (FP64 bits of non-negative
+// numbers order like the numbers).
+template <typename T>
+__device__ __forceinline__ void raise_wmax(const SimDev<T> &S, double w)
+{
+    atomicMax(reinterpret_cast<unsigned long long *>(&S.st->wmax_bits),
+              (unsigned long long)__double_as_longlong(fabs(w)));
 }
 
 }  // namespace pic

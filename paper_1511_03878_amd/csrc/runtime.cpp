@@ -107,6 +107,9 @@ int validate_desc(const PicSimDesc &d, std::string &why)
     if (!(d.m > 0.0) || !std::isfinite(d.q)) { why = "species mass must be positive"; return PIC_EINVAL; }
     if (d.capacity_factor != 0.0 && !(d.capacity_factor >= 1.0)) { why = "capacity_factor must be >= 1"; return PIC_EINVAL; }
     if (d.min_capacity < 0 || d.chunk < 0) { why = "negative min_capacity or chunk"; return PIC_EINVAL; }
+    // the fixed-point current tile of one item sums at most chunk contributions below 2^48
+    if (d.chunk > 16384) { why = "chunk must be at most 16384"; return PIC_EINVAL; }
+    if (d.deterministic != 0 && d.deterministic != 1) { why = "deterministic must be 0 or 1"; return PIC_EINVAL; }
     if (d.field_tile < 0 || d.field_tile > 5) { why = "field_tile must be 0..5"; return PIC_EINVAL; }
     if (d.lane_stride < 0 || d.lane_stride > 64) { why = "lane_stride must be 0..64"; return PIC_EINVAL; }
     if (d.block != 0 && d.block != 256 && d.block != 512 && d.block != 1024) { why = "block must be 0, 256, 512 or 1024"; return PIC_EINVAL; }
@@ -162,6 +165,8 @@ SimImpl<T>::SimImpl(const PicSimDesc &d, const PicAllocator *a, hipStream_t s)
             for (int c = 0; c < 6; ++c) F[b][c] = (T *)alloc.get(sizeof(T) * fsize);
         for (int b = 0; b < 2; ++b)
             for (int c = 0; c < 3; ++c) J[b][c] = (T *)alloc.get(sizeof(T) * fsize);
+        if (desc.deterministic)
+            for (int c = 0; c < 3; ++c) Jacc[c] = (int64_t *)alloc.get(sizeof(int64_t) * fsize);
         st = (SimState *)alloc.get(sizeof(SimState));
         hist = (double *)alloc.get(sizeof(double) * kHistLen * 4);
         counts_d = (int32_t *)alloc.get(sizeof(int32_t) * npatch);
@@ -200,6 +205,8 @@ SimImpl<T>::SimImpl(const PicSimDesc &d, const PicAllocator *a, hipStream_t s)
         for (int b = 0; b < 2; ++b)
             for (int c = 0; c < 3; ++c)
                 hipcheck(hipMemsetAsync(J[b][c], 0, sizeof(T) * fsize, stream), "memset J");
+        for (int c = 0; c < 3; ++c)
+            if (Jacc[c]) hipcheck(hipMemsetAsync(Jacc[c], 0, sizeof(int64_t) * fsize, stream), "memset Jacc");
         hipcheck(hipMemsetAsync(st, 0, sizeof(SimState), stream), "memset state");
         hipcheck(hipMemsetAsync(hist, 0, sizeof(double) * kHistLen * 4, stream), "memset hist");
         hipcheck(hipMemsetAsync(counts_d, 0, sizeof(int32_t) * npatch, stream), "memset counts");
@@ -319,6 +326,10 @@ void SimImpl<T>::release()
         for (int c = 0; c < 6; ++c) alloc.put(F[b][c]);
     for (int b = 0; b < 2; ++b)
         for (int c = 0; c < 3; ++c) alloc.put(J[b][c]);
+    for (int c = 0; c < 3; ++c) {
+        alloc.put(Jacc[c]);
+        Jacc[c] = nullptr;
+    }
     alloc.put(st);
     alloc.put(hist);
     alloc.put(counts_d);
@@ -456,6 +467,8 @@ void SimImpl<T>::refresh_view()
         for (int c = 0; c < 6; ++c) V.F[b][c] = F[b][c];
     for (int b = 0; b < 2; ++b)
         for (int c = 0; c < 3; ++c) V.J[b][c] = J[b][c];
+    V.det = desc.deterministic ? 1 : 0;
+    for (int c = 0; c < 3; ++c) V.Jacc[c] = Jacc[c];
     V.x[0] = px[0]; V.x[1] = px[1]; V.x[2] = nd == 3 ? px[2] : nullptr;
     V.sx[0] = sx[0]; V.sx[1] = sx[1]; V.sx[2] = nd == 3 ? sx[2] : nullptr;
     for (int a = 0; a < 3; ++a) { V.u[a] = pu[a]; V.su[a] = su[a]; }
@@ -543,6 +556,9 @@ void SimImpl<T>::finish_load(const std::vector<int32_t> &counts, int64_t total)
     std::memset(&s0, 0, sizeof(s0));
     s0.next_id = total;
     hipcheck(hipMemcpyAsync(st, &s0, sizeof(s0), hipMemcpyHostToDevice, stream), "state");
+    // the weight bound behind the fixed-point scale of the current
+    launch_wmax<T>(view_d, npatch, stream);
+    hipcheck(hipGetLastError(), "weight bound launch");
     hipcheck(hipStreamSynchronize(stream), "sync");
     relayouts = 0;
     if (solo) solo->dirty = true;
@@ -1225,6 +1241,8 @@ void SimImpl<T>::state_load(const void *blob, size_t size)
     s0.wshift = h.wshift;
     s0.next_id = h.next_id;
     hipcheck(hipMemcpyAsync(st, &s0, sizeof(s0), hipMemcpyHostToDevice, stream), "restore");
+    launch_wmax<T>(view_d, npatch, stream);
+    hipcheck(hipGetLastError(), "weight bound launch");
     hipcheck(hipMemsetAsync(kpart, 0, sizeof(double) * npatch, stream), "restore");
     hipcheck(hipStreamSynchronize(stream), "sync");
     if (solo) solo->dirty = true;
@@ -1650,6 +1668,10 @@ void BatchImpl<T>::free_tables()
     table_bufs.clear();
     sims_d = nullptr;
     patch_prefix_d = tile_prefix_d = nullptr;
+    det_list_d = nullptr;
+    det_prefix_d = nullptr;
+    ndet = 0;
+    det_nodes = 0;
     items_d = nullptr;
     stamps_d = nullptr;
     nitems_d = head_d = stamp_n_d = nullptr;
@@ -1776,6 +1798,22 @@ void BatchImpl<T>::build_tables()
         return p;
     };
     sims_d = (SimDev<T> *)get(sizeof(SimDev<T>) * std::max(ns, 1));
+    std::vector<int> dl;
+    std::vector<int64_t> dp(1, 0);
+    for (int i = 0; i < ns; ++i)
+        if (members[i]->desc.deterministic) {
+            dl.push_back(i);
+            dp.push_back(dp.back() + members[i]->fsize);
+        }
+    ndet = (int)dl.size();
+    det_nodes = dp.back();
+    det_list_d = (int *)get(sizeof(int) * std::max(ndet, 1));
+    det_prefix_d = (int64_t *)get(sizeof(int64_t) * (ndet + 1));
+    if (ndet) {
+        hipcheck(hipMemcpyAsync(det_list_d, dl.data(), sizeof(int) * ndet, hipMemcpyHostToDevice, stream), "det list");
+        hipcheck(hipMemcpyAsync(det_prefix_d, dp.data(), sizeof(int64_t) * (ndet + 1), hipMemcpyHostToDevice, stream),
+                 "det prefix");
+    }
     patch_prefix_d = (int *)get(sizeof(int) * (ns + 1));
     tile_prefix_d = (int *)get(sizeof(int) * (ns + 1));
     items_d = (Item *)get(sizeof(Item) * items);
@@ -1861,6 +1899,8 @@ void BatchImpl<T>::launch_one_step()
     else
         launch_particles<T>(sims_d, items_d, nitems_d, head_d, grid_particles, block, maxP0, maxP1,
                             patch_const, stamps, stream, tm.pair(1));
+    // deterministic members: fixed-point accumulators -> J[step & 1]
+    if (ndet) launch_jfix<T>(sims_d, det_list_d, det_prefix_d, ndet, det_nodes, stream);
     // the field update (fields, currents, tile energies) and the re-binning
     // (particles, counts) touch disjoint data: run them side by side
     const bool fork = ensure_side();

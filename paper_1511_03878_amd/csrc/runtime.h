@@ -116,6 +116,7 @@ struct SimImpl : SimBase {
     int64_t fsize = 0;
     T *F[2][6] = {};
     T *J[2][3] = {};
+    int64_t *Jacc[3] = {};  // fixed-point current accumulators (deterministic deposition only)
     SimState *st = nullptr;
     double *hist = nullptr;
     int32_t *counts_d = nullptr, *newcount_d = nullptr, *kcnt_d = nullptr, *nleave_d = nullptr;
@@ -223,6 +224,12 @@ struct BatchImpl : BatchBase {
     std::vector<void *> table_bufs;
     SimDev<T> *sims_d = nullptr;
     int *patch_prefix_d = nullptr, *tile_prefix_d = nullptr;
+    // members with deterministic deposition: their indices and the exclusive
+    // prefix of their field-node counts (for the accumulator conversion)
+    int ndet = 0;
+    int64_t det_nodes = 0;
+    int *det_list_d = nullptr;
+    int64_t *det_prefix_d = nullptr;
     Item *items_d = nullptr;
     int *nitems_d = nullptr, *head_d = nullptr;
     ItemStamp *stamps_d = nullptr;  // per-item records of the last stamped particle launch

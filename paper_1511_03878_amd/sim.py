@@ -82,7 +82,7 @@ def current_stream_handle() -> int:
 def make_desc(grid: dict, precision: int, chunk: int = 0, block: int = 0,
               capacity_factor: float = 0.0, min_capacity: int = 0,
               field_tile: int = 0, lane_stride: int = 0, graph: int = 0,
-              patch_order: int = 0, maxwell_order: int = 0) -> _capi.SimDesc:
+              patch_order: int = 0, maxwell_order: int = 0, deterministic: int = 0) -> _capi.SimDesc:
     nd = int(grid["ndim"])
     n = list(grid["n"]) + [1] * (3 - len(grid["n"]))
     d = list(grid["d"]) + [1.0] * (3 - len(grid["d"]))
@@ -94,7 +94,7 @@ def make_desc(grid: dict, precision: int, chunk: int = 0, block: int = 0,
                          float(grid.get("q", -1.0)), float(grid.get("m", 1.0)),
                          float(capacity_factor), int(min_capacity), int(chunk), int(block),
                          int(field_tile), int(lane_stride), int(graph), int(patch_order),
-                         int(maxwell_order))
+                         int(maxwell_order), int(deterministic))
 
 
 def estimate_bytes(grid: dict, precision: int, nparticles: int, laser_steps: int = 0,

@@ -53,6 +53,7 @@ def _desc(**kw):
         d["capacity_factor"], d["min_capacity"], d["chunk"], d["block"], d["field_tile"],
         d["lane_stride"])
     s.maxwell_order = d.get("maxwell_order", 0)
+    s.deterministic = d.get("deterministic", 0)
     return s
 
 
@@ -70,6 +71,8 @@ def _desc(**kw):
     (dict(lane_stride=65), -1),
     (dict(n=(2, 64, 1), patch=(2, 16, 1)), -1),  # fewer than 4 cells
     (dict(maxwell_order=4), -1),
+    (dict(deterministic=2), -1),
+    (dict(chunk=16385), -1),                 # the fixed-point current tile of one item
     (dict(maxwell_order=6, periodic=(0, 1, 1)), -1),  # sixth order needs periodic axes
     (dict(maxwell_order=6, dt=0.06), -1),    # within the Yee limit, above the sixth-order one
     (dict(maxwell_order=6, ndim=3, n=(16, 16, 16), patch=(8, 8, 8), d=(0.1, 0.1, 0.1),
@@ -90,3 +93,12 @@ def test_null_arguments_are_rejected(lib):
     assert lib.pic_strerror(-5) == b"patch capacity overflow"
     h = C.c_void_p()
     assert lib.pic_batch_create(2, 48, None, C.byref(h)) == -1
+
+
+def test_deterministic_mode_charges_its_accumulators(lib):
+    """Deterministic deposition holds three 64-bit accumulators per field node:
+    the byte estimate (used for admission by the server) grows by exactly that."""
+    out0, out1 = C.c_int64(), C.c_int64()
+    assert lib.pic_estimate_bytes(C.byref(_desc()), 100000, 0, C.byref(out0)) == 0
+    assert lib.pic_estimate_bytes(C.byref(_desc(deterministic=1)), 100000, 0, C.byref(out1)) == 0
+    assert out1.value - out0.value == 3 * 8 * 64 * 64
