@@ -37,8 +37,10 @@ __device__ __forceinline__ T gather9(const T *tile, int fw, int i0, int j0, cons
 
 // PC > 0: every simulation of the launch has PC x PC-cell patches, so tile
 // strides are compile-time constants and LDS offsets fold into instructions.
+// FP32 512-thread workgroups are held to 128 VGPRs (4 waves per SIMD): two of
+// them then share a CU, which their two 62 KB LDS tiles allow.
 template <typename T, int BLOCK, int PC>
-__global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restrict__ sims,
+__global__ __launch_bounds__(BLOCK, (BLOCK == 512 && sizeof(T) == 4) ? 4 : 1) void k_particles2d(const SimDev<T> *__restrict__ sims,
                                                        const Item *__restrict__ items,
                                                        const int *__restrict__ nitems,
                                                        int *__restrict__ head, int fstride_rt,
@@ -259,7 +261,8 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
                 const bool cx = window4(xl, (double)dxl, mx, S0x, DSx);
                 const bool cy = window4(yl, (double)dyl, my, S0y, DSy);
                 const double qw = (double)wgt;
-                const double az = (double)q * qw * (double)(uz * ig1);
+                // factors of the current carry the fixed-point scale fs
+                const double az = (double)q * qw * (double)(uz * ig1) * fs;
                 long long *Jxt = Jt, *Jyt = Jt + jstride, *Jzt = Jt + 2 * jstride;
                 const int r0 = (my + 2) * jw + (mx + 2);
                 // time-averaged transverse weights
@@ -272,34 +275,35 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
                 if (dxl != T(0) || dyl != T(0)) {
                     // Jx on dual x nodes: running sums of -q w (dx/dt) DSx, times wy
                     double px[3], py[3];
-                    px[0] = cx_ * qw * DSx[0];
-                    px[1] = px[0] + cx_ * qw * DSx[1];
-                    px[2] = px[1] + cx_ * qw * DSx[2];
-                    py[0] = cy_ * qw * DSy[0];
-                    py[1] = py[0] + cy_ * qw * DSy[1];
-                    py[2] = py[1] + cy_ * qw * DSy[2];
+                    const double cq = cx_ * qw * fs, dq = cy_ * qw * fs;
+                    px[0] = cq * DSx[0];
+                    px[1] = px[0] + cq * DSx[1];
+                    px[2] = px[1] + cq * DSx[2];
+                    py[0] = dq * DSy[0];
+                    py[1] = py[0] + dq * DSy[1];
+                    py[2] = py[1] + dq * DSy[2];
 #pragma unroll
                     for (int j = 0; j < 3; ++j) {
-                        fix_add(&Jxt[r0 + j * jw + 0], px[0] * wy[j], fs);
-                        fix_add(&Jxt[r0 + j * jw + 1], px[1] * wy[j], fs);
-                        if (cx) fix_add(&Jxt[r0 + j * jw + 2], px[2] * wy[j], fs);
+                        fix_add_prod(&Jxt[r0 + j * jw + 0], px[0], wy[j]);
+                        fix_add_prod(&Jxt[r0 + j * jw + 1], px[1], wy[j]);
+                        if (cx) fix_add_prod(&Jxt[r0 + j * jw + 2], px[2], wy[j]);
                     }
                     if (cy) {
-                        fix_add(&Jxt[r0 + 3 * jw + 0], px[0] * wy[3], fs);
-                        fix_add(&Jxt[r0 + 3 * jw + 1], px[1] * wy[3], fs);
-                        if (cx) fix_add(&Jxt[r0 + 3 * jw + 2], px[2] * wy[3], fs);
+                        fix_add_prod(&Jxt[r0 + 3 * jw + 0], px[0], wy[3]);
+                        fix_add_prod(&Jxt[r0 + 3 * jw + 1], px[1], wy[3]);
+                        if (cx) fix_add_prod(&Jxt[r0 + 3 * jw + 2], px[2], wy[3]);
                     }
                     // Jy on dual y nodes: running sums along y, times wx
 #pragma unroll
                     for (int i = 0; i < 3; ++i) {
-                        fix_add(&Jyt[r0 + 0 * jw + i], py[0] * wx[i], fs);
-                        fix_add(&Jyt[r0 + 1 * jw + i], py[1] * wx[i], fs);
-                        if (cy) fix_add(&Jyt[r0 + 2 * jw + i], py[2] * wx[i], fs);
+                        fix_add_prod(&Jyt[r0 + 0 * jw + i], py[0], wx[i]);
+                        fix_add_prod(&Jyt[r0 + 1 * jw + i], py[1], wx[i]);
+                        if (cy) fix_add_prod(&Jyt[r0 + 2 * jw + i], py[2], wx[i]);
                     }
                     if (cx) {
-                        fix_add(&Jyt[r0 + 0 * jw + 3], py[0] * wx[3], fs);
-                        fix_add(&Jyt[r0 + 1 * jw + 3], py[1] * wx[3], fs);
-                        if (cy) fix_add(&Jyt[r0 + 2 * jw + 3], py[2] * wx[3], fs);
+                        fix_add_prod(&Jyt[r0 + 0 * jw + 3], py[0], wx[3]);
+                        fix_add_prod(&Jyt[r0 + 1 * jw + 3], py[1], wx[3]);
+                        if (cy) fix_add_prod(&Jyt[r0 + 2 * jw + 3], py[2], wx[3]);
                     }
                 }
                 if (az != 0.0) {
@@ -315,14 +319,14 @@ __global__ __launch_bounds__(BLOCK) void k_particles2d(const SimDev<T> *__restri
                     for (int j = 0; j < 3; ++j) {
 #pragma unroll
                         for (int i = 0; i < 3; ++i)
-                            fix_add(&Jzt[r0 + j * jw + i], ax_[i] * S0y[j] + bx_[i] * DSy[j], fs);
-                        if (cx) fix_add(&Jzt[r0 + j * jw + 3], ax_[3] * S0y[j] + bx_[3] * DSy[j], fs);
+                            fix_add_2prod(&Jzt[r0 + j * jw + i], ax_[i], S0y[j], bx_[i], DSy[j]);
+                        if (cx) fix_add_2prod(&Jzt[r0 + j * jw + 3], ax_[3], S0y[j], bx_[3], DSy[j]);
                     }
                     if (cy) {
 #pragma unroll
                         for (int i = 0; i < 3; ++i)
-                            fix_add(&Jzt[r0 + 3 * jw + i], ax_[i] * S0y[3] + bx_[i] * DSy[3], fs);
-                        if (cx) fix_add(&Jzt[r0 + 3 * jw + 3], ax_[3] * S0y[3] + bx_[3] * DSy[3], fs);
+                            fix_add_2prod(&Jzt[r0 + 3 * jw + i], ax_[i], S0y[3], bx_[i], DSy[3]);
+                        if (cx) fix_add_2prod(&Jzt[r0 + 3 * jw + 3], ax_[3], S0y[3], bx_[3], DSy[3]);
                     }
                 }
 

@@ -91,6 +91,15 @@ __device__ __forceinline__ void deposit_window(long long *Jxt, long long *Jyt, l
         py[k2] = py[k2 - 1] + dq * DSy[k2];
         pz[k2] = pz[k2 - 1] + eq * DSz[k2];
     }
+    // running sums carry the fixed-point scale (FP64: each atomic's integer
+    // then comes from one fused multiply-add)
+    double pxd[3], pyd[3], pzd[3];
+#pragma unroll
+    for (int k2 = 0; k2 < 3; ++k2) {
+        pxd[k2] = (double)px[k2] * fs;
+        pyd[k2] = (double)py[k2] * fs;
+        pzd[k2] = (double)pz[k2] * fs;
+    }
     const int rx = (mz + 2) * jpl[0] + (my + 2) * jrow[0] + (mx + 2);
     const int ry = (mz + 2) * jpl[1] + (my + 2) * jrow[1] + (mx + 2);
     const int rz = (mz + 2) * jpl[2] + (my + 2) * jrow[2] + (mx + 2);
@@ -108,7 +117,7 @@ __device__ __forceinline__ void deposit_window(long long *Jxt, long long *Jyt, l
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 if (i >= ni) break;
-                fix_add(&Jxt[rx + kk * jpl[0] + j * jrow[0] + i], (double)(px[i] * tr), fs);
+                fix_add_prod(&Jxt[rx + kk * jpl[0] + j * jrow[0] + i], pxd[i], (double)tr);
             }
         }
     }
@@ -123,7 +132,7 @@ __device__ __forceinline__ void deposit_window(long long *Jxt, long long *Jyt, l
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
                 if (j >= nj) break;
-                fix_add(&Jyt[ry + kk * jpl[1] + j * jrow[1] + i], (double)(py[j] * tr), fs);
+                fix_add_prod(&Jyt[ry + kk * jpl[1] + j * jrow[1] + i], pyd[j], (double)tr);
             }
         }
     }
@@ -138,11 +147,15 @@ __device__ __forceinline__ void deposit_window(long long *Jxt, long long *Jyt, l
 #pragma unroll
             for (int kk = 0; kk < 3; ++kk) {
                 if (kk >= nk) break;
-                fix_add(&Jzt[rz + kk * jpl[2] + j * jrow[2] + i], (double)(pz[kk] * tr), fs);
+                fix_add_prod(&Jzt[rz + kk * jpl[2] + j * jrow[2] + i], pzd[kk], (double)tr);
             }
         }
     }
 }
+
+// A wave deposits its deferred list once it would pass this many entries
+// (at most 64, the list's size).
+constexpr int kDeferBatch = 64;
 
 // Per-component tile geometry: entries of component c along axis a.
 __host__ __device__ constexpr int fext(int P, int c, int a)
@@ -446,7 +459,7 @@ __global__ __launch_bounds__(BLOCK, (BLOCK == 512 && sizeof(T) == 4) ? 4 : 1) vo
             const bool listed = defer && kr < cnt;
             const uint64_t dm = __ballot(listed);
             const int c = __popcll(dm);
-            if (qn + c > kWave) {
+            if (qn + c > kDeferBatch) {
                 push_deferred(ln < qn, s_q[wv][ln]);
                 qn = 0;
             }

@@ -241,6 +241,21 @@ __device__ __forceinline__ void fix_add(long long *p, double c, double scale)
     atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)to_fix(c, scale));
 }
 
+// The same for a contribution a b whose factors already carry the scale:
+// one fused multiply-add rounds the exact product to an integer.
+__device__ __forceinline__ void fix_add_prod(long long *p, double a, double b)
+{
+    const long long v = __double_as_longlong(fma(a, b, kFixMagic)) - kFixMagicBits;
+    atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)v);
+}
+
+// ... and for a b + c d (two roundings to an integer: within one unit)
+__device__ __forceinline__ void fix_add_2prod(long long *p, double a, double b, double c, double d)
+{
+    const long long v = __double_as_longlong(fma(a, b, fma(c, d, kFixMagic))) - kFixMagicBits;
+    atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)v);
+}
+
 // Raise the simulation's weight bound to |w| (FP64 bits of non-negative
 // numbers order like the numbers).
 template <typename T>
