@@ -57,3 +57,14 @@ def test_traffic_is_reported_only_for_the_measured_source():
         else:
             assert got is None
     assert bench._measured_traffic("k_particles2d", "no_such_workload", 32, 2) is None
+
+
+def test_smoke_workload_loads_in_the_oracle():
+    """__graft_entry__.smoke() loads its thermal box from the species
+    description on both sides; the oracle's loader must accept it (host)."""
+    import oracle
+    from paper_1511_03878_amd import workloads as W
+    wl = W.uniform_2d(n=(64, 64), patch=(16, 16), ppc=8)
+    o = oracle.Sim(wl["grid"])
+    o.particles_init(wl["species"])
+    assert o.particles()[2].size == 64 * 64 * 8
