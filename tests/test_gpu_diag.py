@@ -62,7 +62,10 @@ def test_residuals_2d_periodic(precision, tol):
     g = gpu_sim(wl, precision)
     r0 = g.residuals()
     assert r0["step"] == 0 and math.isnan(r0["continuity"])
-    assert r0["gauss"] <= 1e-15  # E = 0 and rho = rho^0 at load
+    # E = 0 and rho = rho^0 at load, up to the order of the FP64 atomic sums
+    # of rho (16 particles x 9 nodes of same-sign terms per node: relative
+    # difference below 144 x 2^-53 = 1.6e-14)
+    assert r0["gauss"] <= 2e-14
     g.step(5)
     x0, _, w0, _ = g.particles()
     ra = g.residuals()
