@@ -471,7 +471,7 @@ int pic_estimate_bytes(const PicSimDesc *d, int64_t nparticles, int64_t laser_st
     int64_t b = 18 * fsize * s;                        // two E, B buffers, two J buffers
     b += slots * per_slot;
     // counts, keys, neighbour table, partials, offsets
-    b += npatch * (4 * 7 + 4 * ndir + 4 * (3 * ndir - 1) + 8 + 8 + 4);
+    b += npatch * (4 * 7 + 4 * ndir + 4 * (ndir + 1) + 4 * (3 * ndir - 1) + 8 + 8 + 4);
     b += max_tiles * 8 + 8 * 4 * 4096 + 4096;          // tile partials, history, state
     b += 8 * fsize;                                    // charge density at load (diagnostics)
     if (d->deterministic) b += 3 * 8 * fsize;          // fixed-point current accumulators

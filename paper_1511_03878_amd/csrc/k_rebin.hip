@@ -40,15 +40,22 @@ __global__ __launch_bounds__(kRC) void k_rebin_count(const SimDev<T> *__restrict
     for (int gp = blockIdx.x; gp < total; gp += gridDim.x) {
         const int s = find_sim(patch_prefix, nsims, gp);
         const SimDev<T> &S = sims[s];
-        if (!glb(S.st)->active) continue;
         const int p = gp - patch_prefix[s];
-        if (!*glb(S.moved + p)) {
+        // the state the patch's count needs, loaded together
+        const uint32_t active = glb(S.st)->active;
+        const int moved = *glb(S.moved + p);
+        const int n = glb(S.count)[p];
+        const int64_t base = glb(S.off)[p];
+        const int key = threadIdx.x < ND ? nb_row<ND>(S.nbt, p)[threadIdx.x] : 0;
+        if (!active) continue;
+        if (!moved) {
             // no particle of the patch changed patch or was removed: no leavers
             if (threadIdx.x < ND) glb(S.kcnt)[p * ND + threadIdx.x] = 0;
+            if (threadIdx.x <= ND) glb(S.kofs)[p * (ND + 1) + threadIdx.x] = 0;
             if (threadIdx.x == 0) glb(S.nleave)[p] = 0;
             continue;
         }
-        count_patch<T, ND, kRC / 64>(S, p, sm);
+        count_patch<T, ND, kRC / 64>(S, p, n, base, key, sm);
     }
 }
 
@@ -88,7 +95,7 @@ __global__ __launch_bounds__(kRB) void k_rebin_scatter(const SimDev<T> *__restri
                                                        int total)
 {
     constexpr int NS = ND - 1;  // at most this many distinct source patches
-    __shared__ int s_src[NS], s_skey[NS], s_scnt[NS];
+    __shared__ int s_scnt[NS];
     __shared__ int64_t s_sbase[NS];
     __shared__ int s_ns;
     __shared__ int s_key[ND];
@@ -100,10 +107,26 @@ __global__ __launch_bounds__(kRB) void k_rebin_scatter(const SimDev<T> *__restri
     for (int gp = blockIdx.x; gp < total; gp += gridDim.x) {
         const int s = find_sim(patch_prefix, nsims, gp);
         const SimDev<T> &S = sims[s];
-        if (!glb(S.st)->active || (glb(S.st)->flags & kFlagPending)) continue;
         const int q = gp - patch_prefix[s];
+        // everything that depends on q alone, loaded together: the state,
+        // the patch's counts, and per thread one entry of its neighbour row
+        // (threads below NS: a source and its key; threads 64 .. 64 + ND: a
+        // direction's key)
+        const uint32_t active = glb(S.st)->active, flags = glb(S.st)->flags;
         const int n = glb(S.count)[q], np = glb(S.newcount)[q], nH = glb(S.nhole)[q], A = glb(S.narrive)[q];
-        if (A == 0 && np == n && glb(S.nleave)[q] == 0) {
+        const int L = glb(S.nleave)[q], nstaged = glb(S.kofs)[q * (ND + 1) + ND];
+        const int64_t base = glb(S.off)[q];
+        const gptr_t<const int32_t> row = nb_row<ND>(S.nbt, q);
+        int r_ns = 0, r_a = 0, r_b = 0;
+        if (tid < NS) {
+            r_ns = row[ND];
+            r_a = row[ND + 1 + tid];
+            r_b = row[2 * ND + tid];
+        } else if (tid >= 64 && tid < 64 + ND) {
+            r_a = row[tid - 64];
+        }
+        if (!active || (flags & kFlagPending)) continue;
+        if (A == 0 && np == n && L == 0) {
             // nothing arrives and nothing leaves
             if (tid == 0) {
                 if (q == 0) glb(S.st)->rebinned = 1u;
@@ -111,28 +134,20 @@ __global__ __launch_bounds__(kRB) void k_rebin_scatter(const SimDev<T> *__restri
             }
             continue;
         }
-        const int64_t base = glb(S.off)[q];
-        const gptr_t<const int32_t> row = nb_row<ND>(S.nbt, q);
         if (tid < NS) {
             // one thread per source: its count and staging base for this patch
-            const int ns = row[ND];
-            if (tid < ns) {
-                const int sp = row[ND + 1 + tid], k = row[2 * ND + tid];
-                int koff = 0;
-                for (int e = 0; e < k; ++e) koff += glb(S.kcnt)[sp * ND + e];
-                s_src[tid] = sp;
-                s_skey[tid] = k;
+            if (tid < r_ns) {
+                const int sp = r_a, k = r_b;
                 s_scnt[tid] = glb(S.kcnt)[sp * ND + k];
-                s_sbase[tid] = glb(S.off)[sp] + koff;
+                s_sbase[tid] = glb(S.off)[sp] + glb(S.kofs)[sp * (ND + 1) + k];
             }
             if (tid == 0) {
-                s_ns = ns;
+                s_ns = r_ns;
                 s_run = 0;
                 if (q == 0) glb(S.st)->rebinned = 1u;
             }
-
         } else if (tid >= 64 && tid < 64 + ND) {
-            s_key[tid - 64] = row[tid - 64];
+            s_key[tid - 64] = r_a;
         }
         __syncthreads();
         // arrivals (sources in ascending id, each in its slot order): holes
@@ -173,9 +188,7 @@ __global__ __launch_bounds__(kRB) void k_rebin_scatter(const SimDev<T> *__restri
         if (tid == 0) {
             glb(S.count)[q] = np;
             *glb(S.moved + q) = 0;
-            int staged = 0;
-            for (int k = 0; k < ND; ++k) staged += glb(S.kcnt)[q * ND + k];
-            const int removed = glb(S.nleave)[q] - staged;
+            const int removed = L - nstaged;
             if (removed)
                 __hip_atomic_fetch_add(&glb(S.st)->removed, (uint64_t)removed, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);

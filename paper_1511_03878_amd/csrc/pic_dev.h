@@ -103,6 +103,8 @@ struct SimDev {
     int32_t *count;
     int32_t *newcount;
     int32_t *kcnt;     // per patch: leavers per canonical direction key (kNDir2)
+    int32_t *kofs;     // per patch: ND + 1 entries, the staging offset of each key's leavers, then
+                       // the number of staged leavers (the removed ones follow them)
     int32_t *nleave;   // per patch: all leavers (incl. removed)
     int32_t *narrive;  // per patch: arrivals (set by the capacity check)
     int32_t *nhole;    // per patch: vacated slots below the new count

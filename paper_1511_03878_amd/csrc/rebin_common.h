@@ -52,7 +52,7 @@ __device__ __forceinline__ void copy_particle(const SimDev<T> &S, int64_t from, 
 // entries at a time (one lane per particle, so the particle loads of 64
 // leavers are in flight together).
 constexpr int kRC = 512;  // threads of the count workgroup of the re-binning kernel (measured: 256 and 1024 slower)
-constexpr int kU = 32;    // 64-slot chunks per batch of code loads
+constexpr int kU = 16;    // 64-slot chunks per batch of code loads (63 VGPRs: 8 waves per SIMD)
 constexpr int kRing = 128;
 
 template <typename T>
@@ -78,9 +78,13 @@ struct CountSmem {
 // Leavers of patch p: per-key counts (kcnt, nleave), the vacated slots in
 // ascending order (holes) and the staged copies of the leavers, grouped by
 // destination key in slot order.  Called by every thread of a workgroup of
-// NWV waves (contains barriers).
+// NWV waves (contains barriers).  n and base are the patch's count and first
+// slot, key (threads tid < ND) the canonical key of direction tid: the caller
+// loads them together with its own checks, so that their latencies overlap,
+// and the first codes are loaded before the key table is built.
 template <typename T, int ND, int NWV>
-__device__ __forceinline__ void count_patch(const SimDev<T> &S, int p, CountSmem<ND, NWV> &sm)
+__device__ __forceinline__ void count_patch(const SimDev<T> &S, int p, int n, int64_t base, int key,
+                                            CountSmem<ND, NWV> &sm)
 {
     constexpr int kKeys = ND + 1;  // ND direction keys + removed
     constexpr int kThreads = NWV * 64;
@@ -93,39 +97,40 @@ __device__ __forceinline__ void count_patch(const SimDev<T> &S, int p, CountSmem
         else __syncthreads();
     };
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int n = glb(S.count)[p];
-    const int64_t base = glb(S.off)[p];
     const gptr_t<const uint8_t> code = glb((const uint8_t *)S.code) + base;
-    for (int e = tid; e < 256; e += kThreads) {
-        int kb = 0;
-        if (e < ND) kb = nb_row<ND>(S.nbt, p)[e] + 1;
-        else if (e == kRemoved) kb = ND + 1;
-        sm.kb[e] = (uint8_t)kb;
-    }
-    group_sync();
-
     const int per = ((n + kThreads - 1) / kThreads) * 64;
     const int lo = min(n, wave * per), hi = min(n, lo + per);
     const bool one = hi - lo <= 64 * kU;
-    // keys + 1 of the batch, four 64-slot chunks per register
+    // codes of a batch, then keys + 1 of the batch, four 64-slot chunks per register
+    uint8_t t[kU];
     uint32_t cw[kU / 4];
-    auto load = [&](int q0) {
+    auto fetch = [&](int q0) {
         const gptr_t<const uint8_t> cp = code + q0 + lane;
         const int left = hi - q0 - lane;  // chunk u holds a slot while 64 u < left
-        uint8_t t[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u) t[u] = 64 * u < left ? cp[64 * u] : uint8_t(ND / 2);
+    };
+    auto translate = [&]() {
 #pragma unroll
         for (int u = 0; u < kU; u += 4)
             cw[u / 4] = (uint32_t)sm.kb[t[u]] | ((uint32_t)sm.kb[t[u + 1]] << 8) |
                         ((uint32_t)sm.kb[t[u + 2]] << 16) | ((uint32_t)sm.kb[t[u + 3]] << 24);
     };
     auto key1 = [&](int u) { return (int)((cw[u / 4] >> (8 * (u % 4))) & 0xffu); };
+    fetch(lo);
+    for (int e = tid; e < 256; e += kThreads) {
+        int kb = 0;
+        if (e < ND) kb = key + 1;  // e == tid here (ND < kThreads)
+        else if (e == kRemoved) kb = ND + 1;
+        sm.kb[e] = (uint8_t)kb;
+    }
+    group_sync();
 
     // ---- walk 1: leavers per key in [lo, hi) ------------------------------
     int cnt = 0;
     for (int q0 = lo; q0 < hi; q0 += 64 * kU) {
-        load(q0);
+        if (q0 != lo) fetch(q0);
+        translate();
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
             if (q0 + 64 * u >= hi) break;
@@ -157,6 +162,7 @@ __device__ __forceinline__ void count_patch(const SimDev<T> &S, int p, CountSmem
         int tot = 0;
         for (int w = 0; w < NWV; ++w) tot += sm.wc[w][lane];
         if (lane < ND) glb(S.kcnt)[p * ND + lane] = tot;
+        if (lane < kKeys) glb(S.kofs)[p * kKeys + lane] = run;  // wave 0: the key's offset
         if (lane == kKeys) glb(S.nleave)[p] = tot;
     }
 
@@ -165,7 +171,10 @@ __device__ __forceinline__ void count_patch(const SimDev<T> &S, int p, CountSmem
         int2 *ring = sm.ring[wave];
         int head = 0, tail = 0;
         for (int q0 = lo; q0 < hi; q0 += 64 * kU) {
-            if (!one) load(q0);
+            if (!one) {
+                fetch(q0);
+                translate();
+            }
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
                 if (q0 + 64 * u >= hi) break;

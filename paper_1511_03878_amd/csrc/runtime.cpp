@@ -172,6 +172,7 @@ SimImpl<T>::SimImpl(const PicSimDesc &d, const PicAllocator *a, hipStream_t s)
         counts_d = (int32_t *)alloc.get(sizeof(int32_t) * npatch);
         newcount_d = (int32_t *)alloc.get(sizeof(int32_t) * npatch);
         kcnt_d = (int32_t *)alloc.get(sizeof(int32_t) * npatch * ndir);
+        kofs_d = (int32_t *)alloc.get(sizeof(int32_t) * npatch * (ndir + 1));
         nleave_d = (int32_t *)alloc.get(sizeof(int32_t) * npatch);
         narrive_d = (int32_t *)alloc.get(sizeof(int32_t) * npatch);
         nhole_d = (int32_t *)alloc.get(sizeof(int32_t) * npatch);
@@ -337,6 +338,7 @@ void SimImpl<T>::release()
     wdens_d = nullptr;
     alloc.put(newcount_d);
     alloc.put(kcnt_d);
+    alloc.put(kofs_d);
     alloc.put(nleave_d);
     alloc.put(narrive_d);
     alloc.put(nhole_d);
@@ -474,7 +476,7 @@ void SimImpl<T>::refresh_view()
     for (int a = 0; a < 3; ++a) { V.u[a] = pu[a]; V.su[a] = su[a]; }
     V.w = pw; V.sw = sw; V.id = pid; V.sid = sid; V.code = code; V.holes = holes;
     V.cap = cap_d; V.off = off_d; V.count = counts_d; V.newcount = newcount_d;
-    V.kcnt = kcnt_d; V.nleave = nleave_d; V.narrive = narrive_d; V.nhole = nhole_d;
+    V.kcnt = kcnt_d; V.kofs = kofs_d; V.nleave = nleave_d; V.narrive = narrive_d; V.nhole = nhole_d;
     V.moved = moved_d;
     V.porder = porder_d;
     V.laser_ey = laser_ey; V.laser_ez = laser_ez; V.laser_steps = laser_steps;

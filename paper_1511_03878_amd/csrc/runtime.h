@@ -119,7 +119,7 @@ struct SimImpl : SimBase {
     int64_t *Jacc[3] = {};  // fixed-point current accumulators (deterministic deposition only)
     SimState *st = nullptr;
     double *hist = nullptr;
-    int32_t *counts_d = nullptr, *newcount_d = nullptr, *kcnt_d = nullptr, *nleave_d = nullptr;
+    int32_t *counts_d = nullptr, *newcount_d = nullptr, *kcnt_d = nullptr, *kofs_d = nullptr, *nleave_d = nullptr;
     int32_t *narrive_d = nullptr, *nhole_d = nullptr, *moved_d = nullptr, *porder_d = nullptr;
     int *prefix_d = nullptr, *tprefix_d = nullptr;
     int32_t *nbt_d = nullptr;
