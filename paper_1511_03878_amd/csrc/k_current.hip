@@ -27,8 +27,8 @@ __global__ __launch_bounds__(kCB) void k_wmax(const SimDev<T> *__restrict__ sp)
     double m = 0.0;
     for (int p = blockIdx.x; p < S.npatch; p += gridDim.x) {
         const int n = glb(S.count)[p];
-        const gptr_t<const T> w = glb((const T *)S.w) + glb(S.off)[p];
-        for (int k = threadIdx.x; k < n; k += kCB) m = fmax(m, fabs((double)w[k]));
+        const gptr_t<const T> M = glb((const T *)S.mom) + 4 * glb(S.off)[p];
+        for (int k = threadIdx.x; k < n; k += kCB) m = fmax(m, fabs((double)M[4 * k + 3]));
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));

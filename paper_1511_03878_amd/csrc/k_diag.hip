@@ -45,14 +45,14 @@ __global__ void k_rho(const SimDev<T> *__restrict__ S, double *__restrict__ out)
     const int64_t base = S->off[p];
     const int o[3] = {(p % S->np[0]) * S->P[0], ((p / S->np[0]) % S->np[1]) * S->P[1],
                       (p / (S->np[0] * S->np[1])) * S->P[2]};
-    const gptr_t<const T> X0 = glb((const T *)S->x[0]) + base, X1 = glb((const T *)S->x[1]) + base;
-    const gptr_t<const T> X2 = ND == 3 ? glb((const T *)S->x[2]) + base : X1;
-    const gptr_t<const T> Wt = glb((const T *)S->w) + base;
+    constexpr int PW = ND == 3 ? 4 : 2;
+    const gptr_t<const T> X = glb((const T *)S->pos) + PW * base;
+    const gptr_t<const T> M = glb((const T *)S->mom) + 4 * base;
     const double q = (double)S->q;
     const int64_t fn0 = S->fn[0], fn1 = S->fn[1];
     for (int k = threadIdx.x; k < n; k += blockDim.x) {
-        const double xs[3] = {(double)X0[k], (double)X1[k], ND == 3 ? (double)X2[k] : 0.0};
-        const double qw = q * (double)Wt[k];
+        const double xs[3] = {(double)X[PW * k], (double)X[PW * k + 1], ND == 3 ? (double)X[PW * k + 2] : 0.0};
+        const double qw = q * (double)M[4 * k + 3];
         int i0[3];
         double w[3][3];
         for (int a = 0; a < ND; ++a) {

@@ -135,10 +135,9 @@ __global__ void k_init_fill(InitSpec sp, int64_t nseg, const int64_t *__restrict
                     T loc = (T)(x[a] - (double)o[a]);
                     if (loc > pmax[a]) loc = pmax[a];
                     if (loc < T(0)) loc = T(0);
-                    S->x[a][slot] = loc;
+                    S->pos[slot * S->pw + a] = loc;
                 }
-                for (int a = 0; a < 3; ++a) S->u[a][slot] = (T)u[a];
-                S->w[slot] = (T)w;
+                v4(S->mom)[slot] = Vec4<T>{(T)u[0], (T)u[1], (T)u[2], (T)w};
                 S->id[slot] = g;
                 S->code[slot] = (uint8_t)(sp.nd == 3 ? kStay3 : kStay2);
             }

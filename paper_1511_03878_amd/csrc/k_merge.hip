@@ -81,17 +81,21 @@ __device__ void cluster_cell(const SimDev<T> &S, int64_t base, int64_t lst, cons
                              int k, int iters, uint8_t *asg)
 {
 #pragma clang fp contract(off)
-    const gptr_t<const T> U0 = glb((const T *)S.su[0]) + lst, U1 = glb((const T *)S.su[1]) + lst,
-                          U2 = glb((const T *)S.su[2]) + lst, Wt = glb((const T *)S.sw) + lst;
+    // staged members: momentum and weight at sM[4 (lst + i) + c]
+    const gptr_t<const T> Mm = glb((const T *)S.smom) + 4 * lst;
+    auto U0 = [&](int64_t i) { return Mm[4 * i]; };
+    auto U1 = [&](int64_t i) { return Mm[4 * i + 1]; };
+    auto U2 = [&](int64_t i) { return Mm[4 * i + 2]; };
+    auto Wt = [&](int64_t i) { return Mm[4 * i + 3]; };
     double cx[kKMax], cy[kKMax], cz[kKMax];
 #pragma unroll
     for (int j = 0; j < kKMax; ++j) {
         cx[j] = cy[j] = cz[j] = 0.0;
         if (j < k) {
             const int64_t q = (int64_t)j * n / k;
-            cx[j] = (double)U0[q];
-            cy[j] = (double)U1[q];
-            cz[j] = (double)U2[q];
+            cx[j] = (double)U0(q);
+            cy[j] = (double)U1(q);
+            cz[j] = (double)U2(q);
         }
     }
     for (int it = 0; it < iters; ++it) {
@@ -99,8 +103,8 @@ __device__ void cluster_cell(const SimDev<T> &S, int64_t base, int64_t lst, cons
 #pragma unroll
         for (int j = 0; j < kKMax; ++j) sw[j] = sx[j] = sy[j] = sz[j] = 0.0;
         for (int i = 0; i < n; ++i) {
-            const double ux = U0[i], uy = U1[i], uz = U2[i];
-            const double w = Wt[i];
+            const double ux = U0(i), uy = U1(i), uz = U2(i);
+            const double w = Wt(i);
             int best = 0;
             double bd = 0.0;
 #pragma unroll
@@ -158,16 +162,18 @@ __device__ void write_pair(const SimDev<T> &S, int64_t base, int64_t lst, const 
     for (int i = 0; i < n; ++i) {
         if (member_cluster(S, base, mem, asg, i) != j) continue;
         const int64_t q = lst + i;
-        const double w = glb(S.sw)[q];
-        const double ux = glb(S.su[0])[q], uy = glb(S.su[1])[q], uz = glb(S.su[2])[q];
+        const Vec4<T> mq = v4(S.smom)[q];
+        const double w = mq.w;
+        const double ux = mq.x, uy = mq.y, uz = mq.z;
         const double g = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
         W += w;
         E += w * g;
         P0 += w * ux;
         P1 += w * uy;
         P2 += w * uz;
-        X0 += w * (double)glb(S.sx[0])[q];
-        X1 += w * (double)glb(S.sx[1])[q];
+        const Vec2<T> xq = v2(S.spos)[q];
+        X0 += w * (double)xq.x;
+        X1 += w * (double)xq.y;
         const int64_t id = glb(S.sid)[q];
         if (id < id0) {
             id1 = id0;
@@ -203,10 +209,10 @@ __device__ void write_pair(const SimDev<T> &S, int64_t base, int64_t lst, const 
     for (int h = 0; h < 2; ++h) {
         const int64_t t = dst + h;
         const double sg = h == 0 ? 1.0 : -1.0;
-        for (int a = 0; a < 3; ++a) glb(S.u[a])[t] = (T)(ut * (ct * e1[a] + sg * st * e2[a]));
-        glb(S.x[0])[t] = (T)(X0 / W);
-        glb(S.x[1])[t] = (T)(X1 / W);
-        glb(S.w)[t] = (T)(0.5 * W);
+        T ua[3];
+        for (int a = 0; a < 3; ++a) ua[a] = (T)(ut * (ct * e1[a] + sg * st * e2[a]));
+        v4(S.mom)[t] = Vec4<T>{ua[0], ua[1], ua[2], (T)(0.5 * W)};
+        v2(S.pos)[t] = Vec2<T>{(T)(X0 / W), (T)(X1 / W)};
         glb(S.id)[t] = h == 0 ? id0 : id1;
     }
 }
@@ -240,7 +246,8 @@ __global__ __launch_bounds__(kMB) void k_merge2d(const SimDev<T> *__restrict__ s
         if (n <= cmax) continue;
         const int64_t base = glb(S.off)[p];
         auto cell_of = [&](int i) {
-            int cx = (int)floor(glb(S.x[0])[base + i]), cy = (int)floor(glb(S.x[1])[base + i]);
+            const Vec2<T> xi = v2(S.pos)[base + i];
+            int cx = (int)floor(xi.x), cy = (int)floor(xi.y);
             cx = min(max(cx, 0), P0 - 1);
             cy = min(max(cy, 0), P1 - 1);
             return cx + P0 * cy;
@@ -282,10 +289,8 @@ __global__ __launch_bounds__(kMB) void k_merge2d(const SimDev<T> *__restrict__ s
                     const int at_ = s_pos[c] + rank;
                     mem[at_] = i;
                     const int64_t src = base + i, dst = base + at_;
-                    glb(S.sx[0])[dst] = glb(S.x[0])[src];
-                    glb(S.sx[1])[dst] = glb(S.x[1])[src];
-                    for (int a = 0; a < 3; ++a) glb(S.su[a])[dst] = glb(S.u[a])[src];
-                    glb(S.sw)[dst] = glb(S.w)[src];
+                    v2(S.spos)[dst] = v2(S.pos)[src];
+                    v4(S.smom)[dst] = v4(S.mom)[src];
                     glb(S.sid)[dst] = glb(S.id)[src];
                 }
                 __syncthreads();
@@ -338,16 +343,13 @@ __global__ __launch_bounds__(kMB) void k_merge2d(const SimDev<T> *__restrict__ s
             const bool kp = i < n && glb(S.code)[base + i] == kKeep;
             const uint64_t b = __ballot(kp);
             if (lane == 0) s_w[wave] = __popcll(b);
-            T vx0 = T(0), vx1 = T(0), vu0 = T(0), vu1 = T(0), vu2 = T(0), vw = T(0);
+            Vec2<T> vx{T(0), T(0)};
+            Vec4<T> vm{T(0), T(0), T(0), T(0)};
             int64_t vid = 0;
             if (kp) {
                 const int64_t src = base + i;
-                vx0 = glb(S.x[0])[src];
-                vx1 = glb(S.x[1])[src];
-                vu0 = glb(S.u[0])[src];
-                vu1 = glb(S.u[1])[src];
-                vu2 = glb(S.u[2])[src];
-                vw = glb(S.w)[src];
+                vx = v2(S.pos)[src];
+                vm = v4(S.mom)[src];
                 vid = glb(S.id)[src];
             }
             __syncthreads();
@@ -355,12 +357,8 @@ __global__ __launch_bounds__(kMB) void k_merge2d(const SimDev<T> *__restrict__ s
                 int r = s_run + __popcll(b & lt);
                 for (int w = 0; w < wave; ++w) r += s_w[w];
                 const int64_t dst = base + r;
-                glb(S.x[0])[dst] = vx0;
-                glb(S.x[1])[dst] = vx1;
-                glb(S.u[0])[dst] = vu0;
-                glb(S.u[1])[dst] = vu1;
-                glb(S.u[2])[dst] = vu2;
-                glb(S.w)[dst] = vw;
+                v2(S.pos)[dst] = vx;
+                v4(S.mom)[dst] = vm;
                 glb(S.id)[dst] = vid;
             }
             __syncthreads();

@@ -94,9 +94,9 @@ __global__ __launch_bounds__(BLOCK, (BLOCK == 512 && sizeof(T) == 4) ? 4 : 1) vo
 
         T *const *Fc = S.F[par];
         // the item's particles through 32-bit offsets from per-item bases
-        const gptr_t<T> X0 = glb(S.x[0]) + base, X1 = glb(S.x[1]) + base;
-        const gptr_t<T> U0 = glb(S.u[0]) + base, U1 = glb(S.u[1]) + base, U2 = glb(S.u[2]) + base;
-        const gptr_t<const T> Wt = glb((const T *)S.w) + base;
+        // (positions x, y and momenta with weight u_x, u_y, u_z, w: one access each)
+        const gptr_t<Vec2<T>> Pp = v2(S.pos) + base;
+        const gptr_t<Vec4<T>> Mp = v4(S.mom) + base;
         const gptr_t<uint8_t> Cd = glb(S.code) + base;
         const T dt = S.dt, q = S.q, m = S.m;
         const T eps = q * dt / (T(2) * m);
@@ -143,8 +143,10 @@ __global__ __launch_bounds__(BLOCK, (BLOCK == 512 && sizeof(T) == 4) ? 4 : 1) vo
         T nx_, ny_, nux, nuy, nuz, nw_;
         auto load_unit = [&](int u) {
             const uint32_t kn = min(unit_particle(u), cnt - 1);  // unsigned: base + 32-bit offset addressing
-            nx_ = *at(X0, kn); ny_ = *at(X1, kn);
-            nux = *at(U0, kn); nuy = *at(U1, kn); nuz = *at(U2, kn); nw_ = *at(Wt, kn);
+            const Vec2<T> pv = *at(Pp, kn);
+            const Vec4<T> mv = *at(Mp, kn);
+            nx_ = pv.x; ny_ = pv.y;
+            nux = mv.x; nuy = mv.y; nuz = mv.z; nw_ = mv.w;
         };
         load_unit(wv);
         // ---- stage E, B of nodes [ox-1, ox+P0+1] x [oy-1, oy+P1+1] --------
@@ -190,6 +192,7 @@ __global__ __launch_bounds__(BLOCK, (BLOCK == 512 && sizeof(T) == 4) ? 4 : 1) vo
             const T xl = nx_, yl = ny_;
             T ux = nux, uy = nuy, uz = nuz;
             const T wgt = kr < cnt ? nw_ : T(0);
+            const T wst = nw_;  // stored back as loaded (lanes past the end repeat the last particle)
             load_unit(u + NW);
 
             // ---- gather ---------------------------------------------------
@@ -339,11 +342,8 @@ __global__ __launch_bounds__(BLOCK, (BLOCK == 512 && sizeof(T) == 4) ? 4 : 1) vo
                 if (y1 > Pmax1) y1 = Pmax1;
                 code = gone ? kRemoved : (uint8_t)((sx_ + 1) + 3 * (sy_ + 1));
             }
-            *at(X0, k) = x1;
-            *at(X1, k) = y1;
-            *at(U0, k) = ux;
-            *at(U1, k) = uy;
-            *at(U2, k) = uz;
+            *at(Pp, k) = Vec2<T>{x1, y1};
+            *at(Mp, k) = Vec4<T>{ux, uy, uz, wst};
             *at(Cd, k) = code;
             left |= code != kStay2;
         }

@@ -243,9 +243,10 @@ __global__ __launch_bounds__(BLOCK, (BLOCK == 512 && sizeof(T) == 4) ? 4 : 1) vo
         }
         kin_p = p;
 
-        const gptr_t<T> X0 = glb(S.x[0]) + base, X1 = glb(S.x[1]) + base, X2 = glb(S.x[2]) + base;
-        const gptr_t<T> U0 = glb(S.u[0]) + base, U1 = glb(S.u[1]) + base, U2 = glb(S.u[2]) + base;
-        const gptr_t<const T> Wt = glb((const T *)S.w) + base;
+        // (positions x, y, z, unused and momenta with weight u_x, u_y, u_z, w:
+        // one access each)
+        const gptr_t<Vec4<T>> Pp = v4(S.pos) + base;
+        const gptr_t<Vec4<T>> Mp = v4(S.mom) + base;
         const gptr_t<uint8_t> Cd = glb(S.code) + base;
 
         // lane mapping, remainder units and prefetch as in 2-D: no lane
@@ -263,8 +264,10 @@ __global__ __launch_bounds__(BLOCK, (BLOCK == 512 && sizeof(T) == 4) ? 4 : 1) vo
         T nx_, ny_, nz_, nux, nuy, nuz, nw_;
         auto load_unit = [&](int u) {
             const int kn = min(unit_particle(u), cnt - 1);
-            nx_ = X0[kn]; ny_ = X1[kn]; nz_ = X2[kn];
-            nux = U0[kn]; nuy = U1[kn]; nuz = U2[kn]; nw_ = Wt[kn];
+            const Vec4<T> pv = Pp[kn];
+            const Vec4<T> mv = Mp[kn];
+            nx_ = pv.x; ny_ = pv.y; nz_ = pv.z;
+            nux = mv.x; nuy = mv.y; nuz = mv.z; nw_ = mv.w;
         };
         load_unit(wv);
 
@@ -332,9 +335,11 @@ __global__ __launch_bounds__(BLOCK, (BLOCK == 512 && sizeof(T) == 4) ? 4 : 1) vo
         // memory; deposit on the full window, then store position and code.
         auto push_deferred = [&](bool valid, int kq) {
             const int k = valid ? kq : 0;
-            const T xl = X0[k], yl = X1[k], zl = X2[k];
-            const T ux = U0[k], uy = U1[k], uz = U2[k];
-            const W qw = valid ? (W)Wt[k] : W(0);
+            const Vec4<T> pk = Pp[k];
+            const Vec4<T> mk = Mp[k];
+            const T xl = pk.x, yl = pk.y, zl = pk.z;
+            const T ux = mk.x, uy = mk.y, uz = mk.z;
+            const W qw = valid ? (W)mk.w : W(0);
             const T ig1 = rsq_(T(1) + (ux * ux + uy * uy + uz * uz));
             const T dxl = rdx * ux * ig1, dyl = rdy * uy * ig1, dzl = rdz * uz * ig1;
             int mx, my, mz;
@@ -348,9 +353,7 @@ __global__ __launch_bounds__(BLOCK, (BLOCK == 512 && sizeof(T) == 4) ? 4 : 1) vo
             T x1 = xl + dxl, y1 = yl + dyl, z1 = zl + dzl;
             const uint8_t code = place(x1, y1, z1);
             if (valid) {
-                X0[k] = x1;
-                X1[k] = y1;
-                X2[k] = z1;
+                Pp[k] = Vec4<T>{x1, y1, z1, T(0)};
                 Cd[k] = code;
                 left |= code != kStay3;
             }
@@ -362,6 +365,7 @@ __global__ __launch_bounds__(BLOCK, (BLOCK == 512 && sizeof(T) == 4) ? 4 : 1) vo
             const T xl = nx_, yl = ny_, zl = nz_;
             T ux = nux, uy = nuy, uz = nuz;
             const T wgt = kr < cnt ? nw_ : T(0);
+            const T wst = nw_;  // stored back as loaded (lanes past the end repeat the last particle)
             load_unit(u + NW);
 
             // ---- gather -------------------------------------------------
@@ -444,12 +448,8 @@ __global__ __launch_bounds__(BLOCK, (BLOCK == 512 && sizeof(T) == 4) ? 4 : 1) vo
             }
             // a deferred particle keeps its old position in memory until its
             // deposit (stores stay unconditional: the same value is rewritten)
-            X0[k] = defer ? xl : x1;
-            X1[k] = defer ? yl : y1;
-            X2[k] = defer ? zl : z1;
-            U0[k] = ux;
-            U1[k] = uy;
-            U2[k] = uz;
+            Pp[k] = Vec4<T>{defer ? xl : x1, defer ? yl : y1, defer ? zl : z1, T(0)};
+            Mp[k] = Vec4<T>{ux, uy, uz, wst};
             Cd[k] = code;
             left |= !defer && code != kStay3;
 

@@ -448,13 +448,9 @@ __global__ void k_relayout(const SimDev<T> *__restrict__ src, const SimDev<T> *_
     const int n = src->count[p];
     const int64_t a = src->off[p], b = dst->off[p];
     for (int k = threadIdx.x; k < n; k += blockDim.x) {
-        dst->x[0][b + k] = src->x[0][a + k];
-        dst->x[1][b + k] = src->x[1][a + k];
-        if (src->ndim == 3) dst->x[2][b + k] = src->x[2][a + k];
-        dst->u[0][b + k] = src->u[0][a + k];
-        dst->u[1][b + k] = src->u[1][a + k];
-        dst->u[2][b + k] = src->u[2][a + k];
-        dst->w[b + k] = src->w[a + k];
+        if (src->pw == 4) v4(dst->pos)[b + k] = v4(src->pos)[a + k];
+        else v2(dst->pos)[b + k] = v2(src->pos)[a + k];
+        v4(dst->mom)[b + k] = v4(src->mom)[a + k];
         dst->id[b + k] = src->id[a + k];
         dst->code[b + k] = src->code[a + k];
     }

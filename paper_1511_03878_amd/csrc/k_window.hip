@@ -144,12 +144,10 @@ __global__ __launch_bounds__(kWB) void k_window2d(const SimDev<T> *__restrict__ 
             const int b = m / S.wppc[0], a = m - b * S.wppc[0];
             const double dens = column_density(S.wdens, S.wncols, col0 + il);
             const int64_t slot = seg + t;
-            glb(S.x[0])[slot] = (T)((double)il + ((double)a + 0.5) / S.wppc[0]);
-            glb(S.x[1])[slot] = (T)((double)jl + ((double)b + 0.5) / S.wppc[1]);
-            glb(S.u[0])[slot] = T(0);
-            glb(S.u[1])[slot] = T(0);
-            glb(S.u[2])[slot] = T(0);
-            glb(S.w)[slot] = (T)(dens / ppc);
+            // (the window is 2-D: two position entries per slot)
+            v2(S.pos)[slot] = Vec2<T>{(T)((double)il + ((double)a + 0.5) / S.wppc[0]),
+                                   (T)((double)jl + ((double)b + 0.5) / S.wppc[1])};
+            v4(S.mom)[slot] = Vec4<T>{T(0), T(0), T(0), (T)(dens / ppc)};
             wloc = fmax(wloc, fabs((double)(T)(dens / ppc)));
             glb(S.id)[slot] = id0 + t;
             glb(S.code)[slot] = (uint8_t)kStay2;

@@ -90,12 +90,17 @@ struct SimDev {
     // a conversion pass turns them into J[step & 1] and clears them
     int det;
     int64_t *Jacc[3];
-    // particles
-    T *x[3], *u[3], *w;
+    // particles, slot k: position pos[pw k + a] (pw = 2 in 2-D: x, y; pw = 4
+    // in 3-D: x, y, z and an unused entry), momentum and weight mom[4 k + c]
+    // (u_x, u_y, u_z, w).  One particle is two short runs of memory, so the
+    // re-binning moves it with three scattered accesses (pos, mom, id)
+    // instead of one per component.
+    T *pos, *mom;
+    int pw;
     int64_t *id;
     uint8_t *code;
-    // staging copy for leavers
-    T *sx[3], *su[3], *sw;
+    // staging copy for leavers (same layout)
+    T *spos, *smom;
     int64_t *sid;
     int32_t *holes;
     const int32_t *cap;
@@ -185,6 +190,25 @@ __device__ __forceinline__ gptr_t<T> at(gptr_t<T> base, uint32_t i)
 {
     typedef __attribute__((address_space(1))) char gchar;
     return (gptr_t<T>)((gchar *)base + i * (uint32_t)sizeof(T));
+}
+
+// Two and four consecutive particle components, loaded or stored as one
+// access (vector types of the compiler: copies through address-space
+// pointers need no constructors).
+template <typename T>
+using Vec2 = T __attribute__((ext_vector_type(2)));
+template <typename T>
+using Vec4 = T __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__device__ __forceinline__ gptr_t<Vec2<T>> v2(T *p)
+{
+    return (gptr_t<Vec2<T>>)glb(p);
+}
+template <typename T>
+__device__ __forceinline__ gptr_t<Vec4<T>> v4(T *p)
+{
+    return (gptr_t<Vec4<T>>)glb(p);
 }
 
 template <typename T>

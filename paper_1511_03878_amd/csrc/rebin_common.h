@@ -23,21 +23,13 @@ template <typename T>
 __device__ __forceinline__ void copy_particle(const SimDev<T> &S, int64_t from, int64_t to,
                                               bool from_stage, bool to_stage)
 {
-    T *const *fx = from_stage ? S.sx : S.x;
-    T *const *fu = from_stage ? S.su : S.u;
-    const T *fw = from_stage ? S.sw : S.w;
+    T *fP = from_stage ? S.spos : S.pos, *fM = from_stage ? S.smom : S.mom;
+    T *tP = to_stage ? S.spos : S.pos, *tM = to_stage ? S.smom : S.mom;
     const int64_t *fi = from_stage ? S.sid : S.id;
-    T *const *tx = to_stage ? S.sx : S.x;
-    T *const *tu = to_stage ? S.su : S.u;
-    T *tw = to_stage ? S.sw : S.w;
     int64_t *ti = to_stage ? S.sid : S.id;
-    glb(tx[0])[to] = glb(fx[0])[from];
-    glb(tx[1])[to] = glb(fx[1])[from];
-    if (S.ndim == 3) glb(tx[2])[to] = glb(fx[2])[from];
-    glb(tu[0])[to] = glb(fu[0])[from];
-    glb(tu[1])[to] = glb(fu[1])[from];
-    glb(tu[2])[to] = glb(fu[2])[from];
-    glb(tw)[to] = glb(fw)[from];
+    if (S.pw == 4) v4(tP)[to] = v4(fP)[from];
+    else v2(tP)[to] = v2(fP)[from];
+    v4(tM)[to] = v4(fM)[from];
     glb(ti)[to] = glb(fi)[from];
 }
 

@@ -402,16 +402,11 @@ std::vector<void *> SimImpl<T>::layout_particles(const std::vector<int32_t> &nee
             part_bufs.push_back(p);
             return p;
         };
-        for (int a = 0; a < nd; ++a) {
-            px[a] = (T *)get(sizeof(T) * total);
-            sx[a] = (T *)get(sizeof(T) * total);
-        }
-        for (int a = 0; a < 3; ++a) {
-            pu[a] = (T *)get(sizeof(T) * total);
-            su[a] = (T *)get(sizeof(T) * total);
-        }
-        pw = (T *)get(sizeof(T) * total);
-        sw = (T *)get(sizeof(T) * total);
+        pwid = nd == 3 ? 4 : 2;
+        pP = (T *)get(sizeof(T) * total * pwid);
+        sP = (T *)get(sizeof(T) * total * pwid);
+        pM = (T *)get(sizeof(T) * total * 4);
+        sM = (T *)get(sizeof(T) * total * 4);
         pid = (int64_t *)get(sizeof(int64_t) * total);
         sid = (int64_t *)get(sizeof(int64_t) * total);
         code = (uint8_t *)get(total);
@@ -471,10 +466,8 @@ void SimImpl<T>::refresh_view()
         for (int c = 0; c < 3; ++c) V.J[b][c] = J[b][c];
     V.det = desc.deterministic ? 1 : 0;
     for (int c = 0; c < 3; ++c) V.Jacc[c] = Jacc[c];
-    V.x[0] = px[0]; V.x[1] = px[1]; V.x[2] = nd == 3 ? px[2] : nullptr;
-    V.sx[0] = sx[0]; V.sx[1] = sx[1]; V.sx[2] = nd == 3 ? sx[2] : nullptr;
-    for (int a = 0; a < 3; ++a) { V.u[a] = pu[a]; V.su[a] = su[a]; }
-    V.w = pw; V.sw = sw; V.id = pid; V.sid = sid; V.code = code; V.holes = holes;
+    V.pos = pP; V.spos = sP; V.mom = pM; V.smom = sM; V.pw = pwid;
+    V.id = pid; V.sid = sid; V.code = code; V.holes = holes;
     V.cap = cap_d; V.off = off_d; V.count = counts_d; V.newcount = newcount_d;
     V.kcnt = kcnt_d; V.kofs = kofs_d; V.nleave = nleave_d; V.narrive = narrive_d; V.nhole = nhole_d;
     V.moved = moved_d;
@@ -516,10 +509,7 @@ void SimImpl<T>::set_particles(int64_t cnt, const double *const xs[3], const dou
     // canonical initial order: id order inside each patch
     std::vector<int64_t> pos(off_h.begin(), off_h.end() - 1);
     const int64_t tot = total_cap;
-    std::vector<T> hx[3], hu[3];
-    for (int a = 0; a < nd; ++a) hx[a].assign(tot, T(0));
-    for (auto &a : hu) a.assign(tot, T(0));
-    std::vector<T> hw(tot, T(0));
+    std::vector<T> hP((size_t)tot * pwid, T(0)), hM((size_t)tot * 4, T(0));
     std::vector<int64_t> hid(tot, -1);
     const T pmax[3] = {std::nextafter((T)P[0], (T)0), std::nextafter((T)P[1], (T)0),
                        std::nextafter((T)P[2], (T)0)};
@@ -531,17 +521,14 @@ void SimImpl<T>::set_particles(int64_t cnt, const double *const xs[3], const dou
             T loc = (T)(xs[a][k] - (double)o[a]);
             if (loc > pmax[a]) loc = pmax[a];
             if (loc < T(0)) loc = T(0);
-            hx[a][t] = loc;
+            hP[(size_t)t * pwid + a] = loc;
         }
-        for (int a = 0; a < 3; ++a) hu[a][t] = us[a] ? (T)us[a][k] : T(0);
-        hw[t] = (T)w[k];
+        for (int a = 0; a < 3; ++a) hM[(size_t)t * 4 + a] = us[a] ? (T)us[a][k] : T(0);
+        hM[(size_t)t * 4 + 3] = (T)w[k];
         hid[t] = k;
     }
-    for (int a = 0; a < nd; ++a)
-        hipcheck(hipMemcpyAsync(px[a], hx[a].data(), sizeof(T) * tot, hipMemcpyHostToDevice, stream), "x");
-    for (int a = 0; a < 3; ++a)
-        hipcheck(hipMemcpyAsync(pu[a], hu[a].data(), sizeof(T) * tot, hipMemcpyHostToDevice, stream), "u");
-    hipcheck(hipMemcpyAsync(pw, hw.data(), sizeof(T) * tot, hipMemcpyHostToDevice, stream), "w");
+    hipcheck(hipMemcpyAsync(pP, hP.data(), sizeof(T) * hP.size(), hipMemcpyHostToDevice, stream), "x");
+    hipcheck(hipMemcpyAsync(pM, hM.data(), sizeof(T) * hM.size(), hipMemcpyHostToDevice, stream), "u, w");
     hipcheck(hipMemcpyAsync(pid, hid.data(), sizeof(int64_t) * tot, hipMemcpyHostToDevice, stream), "id");
     hipcheck(hipMemsetAsync(code, ndir / 2, tot, stream), "code");
     finish_load(counts, cnt);
@@ -642,9 +629,8 @@ void SimImpl<T>::particles_init()
     std::vector<void *> old = layout_particles(counts);
     for (void *p : old) alloc.put(p);
     const int64_t tot = total_cap;
-    for (int a = 0; a < nd; ++a) hipcheck(hipMemsetAsync(px[a], 0, sizeof(T) * tot, stream), "clear x");
-    for (int a = 0; a < 3; ++a) hipcheck(hipMemsetAsync(pu[a], 0, sizeof(T) * tot, stream), "clear u");
-    hipcheck(hipMemsetAsync(pw, 0, sizeof(T) * tot, stream), "clear w");
+    hipcheck(hipMemsetAsync(pP, 0, sizeof(T) * tot * pwid, stream), "clear x");
+    hipcheck(hipMemsetAsync(pM, 0, sizeof(T) * tot * 4, stream), "clear u, w");
     hipcheck(hipMemsetAsync(pid, 0xff, sizeof(int64_t) * tot, stream), "clear id");
     hipcheck(hipMemsetAsync(code, ndir / 2, tot, stream), "code");
     int64_t *first_d = (int64_t *)alloc.get(sizeof(int64_t) * nseg);
@@ -1038,23 +1024,33 @@ void SimImpl<T>::get_particles(double *xo[3], double *uo[3], double *wo, int64_t
     const int64_t live = std::accumulate(c.begin(), c.end(), int64_t(0));
     if ((int64_t)cnt < live) throw Error(PIC_EINVAL, "output arrays too small");
     const int64_t tot = total_cap;
-    std::vector<T> tmp(tot);
+    std::vector<T> tmp;
     std::vector<int64_t> itmp;
-    auto fetch = [&](const T *src, double *dst, int axis) {
-        hipcheck(hipMemcpyAsync(tmp.data(), src, sizeof(T) * tot, hipMemcpyDeviceToHost, stream), "particles");
-        hipcheck(hipStreamSynchronize(stream), "sync");
+    // component comp of an interleaved array of width wid (downloaded once)
+    auto fetch = [&](const std::vector<T> &buf, int wid, int comp, double *dst, int axis) {
         int64_t o = 0;
         for (int p = 0; p < npatch; ++p) {
             const double org = axis == 0 ? (double)((p % np[0]) * P[0])
                              : axis == 1 ? (double)(((p / np[0]) % np[1]) * P[1])
                              : axis == 2 ? (double)((p / (np[0] * np[1])) * P[2]) : 0.0;
-            for (int k = 0; k < c[p]; ++k) dst[o++] = org + (double)tmp[off_h[p] + k];
+            for (int k = 0; k < c[p]; ++k) dst[o++] = org + (double)buf[(size_t)(off_h[p] + k) * wid + comp];
         }
     };
-    for (int a = 0; a < nd; ++a) if (xo[a]) fetch(px[a], xo[a], a);
+    auto download = [&](const T *src, int wid) {
+        tmp.resize((size_t)tot * wid);
+        hipcheck(hipMemcpyAsync(tmp.data(), src, sizeof(T) * tmp.size(), hipMemcpyDeviceToHost, stream), "particles");
+        hipcheck(hipStreamSynchronize(stream), "sync");
+    };
+    if (xo[0] || xo[1] || (nd == 3 && xo[2])) {
+        download(pP, pwid);
+        for (int a = 0; a < nd; ++a) if (xo[a]) fetch(tmp, pwid, a, xo[a], a);
+    }
     if (nd == 2 && xo[2]) std::fill(xo[2], xo[2] + live, 0.0);
-    for (int a = 0; a < 3; ++a) if (uo[a]) fetch(pu[a], uo[a], 3);
-    if (wo) fetch(pw, wo, 3);
+    if (uo[0] || uo[1] || uo[2] || wo) {
+        download(pM, 4);
+        for (int a = 0; a < 3; ++a) if (uo[a]) fetch(tmp, 4, a, uo[a], 3);
+        if (wo) fetch(tmp, 4, 3, wo, 3);
+    }
     if (ido) {
         itmp.resize(tot);
         hipcheck(hipMemcpyAsync(itmp.data(), pid, sizeof(int64_t) * tot, hipMemcpyDeviceToHost, stream), "ids");
@@ -1150,18 +1146,24 @@ void SimImpl<T>::state_save(void *blob)
     hipcheck(hipStreamSynchronize(stream), "sync");
     // particles: compact each array patch by patch
     const int64_t tot = total_cap;
-    std::vector<T> tmp(tot);
-    auto pack = [&](const T *src) {
-        hipcheck(hipMemcpyAsync(tmp.data(), src, sizeof(T) * tot, hipMemcpyDeviceToHost, stream), "checkpoint");
+    // (the checkpoint holds one array per component: x..., u_x, u_y, u_z, w)
+    std::vector<T> tmp;
+    auto download = [&](const T *src, int wid) {
+        tmp.resize((size_t)tot * wid);
+        hipcheck(hipMemcpyAsync(tmp.data(), src, sizeof(T) * tmp.size(), hipMemcpyDeviceToHost, stream), "checkpoint");
         hipcheck(hipStreamSynchronize(stream), "sync");
-        for (int p = 0; p < npatch; ++p) {
-            std::memcpy(o, tmp.data() + off_h[p], sizeof(T) * c[p]);
-            o += sizeof(T) * c[p];
-        }
     };
-    for (int a = 0; a < nd; ++a) pack(px[a]);
-    for (int a = 0; a < 3; ++a) pack(pu[a]);
-    pack(pw);
+    auto pack = [&](int wid, int comp) {
+        for (int p = 0; p < npatch; ++p)
+            for (int k = 0; k < c[p]; ++k) {
+                std::memcpy(o, &tmp[(size_t)(off_h[p] + k) * wid + comp], sizeof(T));
+                o += sizeof(T);
+            }
+    };
+    download(pP, pwid);
+    for (int a = 0; a < nd; ++a) pack(pwid, a);
+    download(pM, 4);
+    for (int a = 0; a < 4; ++a) pack(4, a);
     std::vector<int64_t> itmp(tot);
     hipcheck(hipMemcpyAsync(itmp.data(), pid, sizeof(int64_t) * tot, hipMemcpyDeviceToHost, stream), "checkpoint");
     hipcheck(hipStreamSynchronize(stream), "sync");
@@ -1212,19 +1214,24 @@ void SimImpl<T>::state_load(const void *blob, size_t size)
     std::vector<void *> old = layout_particles(c);
     for (void *p : old) alloc.put(p);
     const int64_t tot = total_cap;
-    std::vector<T> tmp(tot);
-    auto unpack = [&](T *dst) {
-        std::fill(tmp.begin(), tmp.end(), T(0));
-        for (int p = 0; p < npatch; ++p) {
-            std::memcpy(tmp.data() + off_h[p], i, sizeof(T) * c[p]);
-            i += sizeof(T) * c[p];
-        }
-        hipcheck(hipMemcpyAsync(dst, tmp.data(), sizeof(T) * tot, hipMemcpyHostToDevice, stream), "restore");
+    std::vector<T> tmp;
+    auto unpack = [&](int wid, int comp) {
+        for (int p = 0; p < npatch; ++p)
+            for (int k = 0; k < c[p]; ++k) {
+                std::memcpy(&tmp[(size_t)(off_h[p] + k) * wid + comp], i, sizeof(T));
+                i += sizeof(T);
+            }
+    };
+    auto upload = [&](T *dst) {
+        hipcheck(hipMemcpyAsync(dst, tmp.data(), sizeof(T) * tmp.size(), hipMemcpyHostToDevice, stream), "restore");
         hipcheck(hipStreamSynchronize(stream), "sync");
     };
-    for (int a = 0; a < nd; ++a) unpack(px[a]);
-    for (int a = 0; a < 3; ++a) unpack(pu[a]);
-    unpack(pw);
+    tmp.assign((size_t)tot * pwid, T(0));
+    for (int a = 0; a < nd; ++a) unpack(pwid, a);
+    upload(pP);
+    tmp.assign((size_t)tot * 4, T(0));
+    for (int a = 0; a < 4; ++a) unpack(4, a);
+    upload(pM);
     std::vector<int64_t> itmp(tot, -1);
     for (int p = 0; p < npatch; ++p) {
         std::memcpy(itmp.data() + off_h[p], i, sizeof(int64_t) * c[p]);

@@ -137,7 +137,9 @@ struct SimImpl : SimBase {
     PicSpeciesDesc species{};
     // particle layout
     std::vector<void *> part_bufs;
-    T *px[3] = {}, *sx[3] = {}, *pu[3] = {}, *su[3] = {}, *pw = nullptr, *sw = nullptr;
+    // interleaved: positions pwid per slot, momenta and weight 4 per slot (see SimDev)
+    T *pP = nullptr, *sP = nullptr, *pM = nullptr, *sM = nullptr;
+    int pwid = 2;
     int64_t *pid = nullptr, *sid = nullptr;
     uint8_t *code = nullptr;
     int32_t *holes = nullptr, *cap_d = nullptr;
