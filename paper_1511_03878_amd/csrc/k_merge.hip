@@ -34,6 +34,9 @@ namespace {
 constexpr int kMB = 256;          // threads per workgroup
 constexpr int kMaxCells = 4096;   // cells per patch (64 x 64)
 constexpr int kKMax = 16;         // clusters per cell (cmax <= 32)
+// The kernel is built for at most KMAX = 4, 8 or 16 clusters (the smallest
+// that holds cmax / 2): a cell's centroids and sums live in registers, and
+// fewer of them leave room for more waves per SIMD (cmax 8: 4 clusters).
 constexpr uint8_t kKeep = 0xFF;   // a particle that stays as it is
 constexpr int kAsgLDS = 32768;    // members whose clusters are also kept in LDS (per patch)
 
@@ -74,9 +77,9 @@ __device__ int block_scan(int *a, int n, int *s_w)
 // slots lst .. lst + n (member order), their own slots in mem[0..n) (relative
 // to the patch segment).  Each round assigns a member and adds it to its
 // cluster's sums in one pass (the sums of a cluster still grow in member
-// order), centroids and sums in registers (k <= kKMax); the final round's
+// order), centroids and sums in registers (k <= KMAX); the final round's
 // cluster of every member goes to code[] at its own slot.
-template <typename T>
+template <typename T, int KMAX>
 __device__ void cluster_cell(const SimDev<T> &S, int64_t base, int64_t lst, const int32_t *mem, int n,
                              int k, int iters, uint8_t *asg)
 {
@@ -87,9 +90,9 @@ __device__ void cluster_cell(const SimDev<T> &S, int64_t base, int64_t lst, cons
     auto U1 = [&](int64_t i) { return Mm[4 * i + 1]; };
     auto U2 = [&](int64_t i) { return Mm[4 * i + 2]; };
     auto Wt = [&](int64_t i) { return Mm[4 * i + 3]; };
-    double cx[kKMax], cy[kKMax], cz[kKMax];
+    double cx[KMAX], cy[KMAX], cz[KMAX];
 #pragma unroll
-    for (int j = 0; j < kKMax; ++j) {
+    for (int j = 0; j < KMAX; ++j) {
         cx[j] = cy[j] = cz[j] = 0.0;
         if (j < k) {
             const int64_t q = (int64_t)j * n / k;
@@ -99,16 +102,16 @@ __device__ void cluster_cell(const SimDev<T> &S, int64_t base, int64_t lst, cons
         }
     }
     for (int it = 0; it < iters; ++it) {
-        double sw[kKMax], sx[kKMax], sy[kKMax], sz[kKMax];
+        double sw[KMAX], sx[KMAX], sy[KMAX], sz[KMAX];
 #pragma unroll
-        for (int j = 0; j < kKMax; ++j) sw[j] = sx[j] = sy[j] = sz[j] = 0.0;
+        for (int j = 0; j < KMAX; ++j) sw[j] = sx[j] = sy[j] = sz[j] = 0.0;
         for (int i = 0; i < n; ++i) {
             const double ux = U0(i), uy = U1(i), uz = U2(i);
             const double w = Wt(i);
             int best = 0;
             double bd = 0.0;
 #pragma unroll
-            for (int j = 0; j < kKMax; ++j) {
+            for (int j = 0; j < KMAX; ++j) {
                 if (j < k) {
                     const double dx = ux - cx[j], dy = uy - cy[j], dz = uz - cz[j];
                     const double d2 = dx * dx + dy * dy + dz * dz;
@@ -119,7 +122,7 @@ __device__ void cluster_cell(const SimDev<T> &S, int64_t base, int64_t lst, cons
                 }
             }
 #pragma unroll
-            for (int j = 0; j < kKMax; ++j)
+            for (int j = 0; j < KMAX; ++j)
                 if (j == best) {
                     sw[j] += w;
                     sx[j] += w * ux;
@@ -132,7 +135,7 @@ __device__ void cluster_cell(const SimDev<T> &S, int64_t base, int64_t lst, cons
             }
         }
 #pragma unroll
-        for (int j = 0; j < kKMax; ++j)
+        for (int j = 0; j < KMAX; ++j)
             if (j < k && sw[j] > 0.0) {
                 cx[j] = sx[j] / sw[j];
                 cy[j] = sy[j] / sw[j];
@@ -217,7 +220,7 @@ __device__ void write_pair(const SimDev<T> &S, int64_t base, int64_t lst, const 
     }
 }
 
-template <typename T>
+template <typename T, int KMAX>
 __global__ __launch_bounds__(kMB) void k_merge2d(const SimDev<T> *__restrict__ sp, int cmax, int iters,
                                                  int forced)
 {
@@ -239,7 +242,7 @@ __global__ __launch_bounds__(kMB) void k_merge2d(const SimDev<T> *__restrict__ s
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int P0 = S.P[0], P1 = S.P[1], ncell = P0 * P1;
-    const int k = cmax / 2;
+    const int k = min(cmax / 2, KMAX);  // (the host picks KMAX >= cmax / 2)
     int64_t taken = 0;
     for (int p = blockIdx.x; p < S.npatch; p += gridDim.x) {
         const int n = glb(S.count)[p];
@@ -315,8 +318,8 @@ __global__ __launch_bounds__(kMB) void k_merge2d(const SimDev<T> *__restrict__ s
             if (nc > cmax) {
                 const int32_t *m = (const int32_t *)&mem[s_pos[c]];
                 uint8_t *asg = in_lds ? &s_asg[s_pos[c]] : nullptr;
-                cluster_cell(S, base, base + s_pos[c], m, nc, k, iters, asg);
-                int size[kKMax];
+                cluster_cell<T, KMAX>(S, base, base + s_pos[c], m, nc, k, iters, asg);
+                int size[KMAX];
                 for (int j = 0; j < k; ++j) size[j] = 0;
                 for (int i = 0; i < nc; ++i) {
                     const int cj = member_cluster(S, base, m, asg, i);
@@ -375,7 +378,7 @@ __global__ __launch_bounds__(kMB) void k_merge2d(const SimDev<T> *__restrict__ s
             const uint8_t *asg = in_lds ? &s_asg[s_pos[c]] : nullptr;
             // (without the LDS copy, members of clusters of one or two read as
             // kKeep and are not counted: those clusters make no pair either way)
-            int size[kKMax];
+            int size[KMAX];
             for (int j = 0; j < k; ++j) size[j] = 0;
             for (int i = 0; i < nc; ++i) {
                 const int cj = member_cluster(S, base, m, asg, i);
@@ -404,12 +407,19 @@ __global__ __launch_bounds__(kMB) void k_merge2d(const SimDev<T> *__restrict__ s
 }  // namespace
 
 template <typename T>
-void launch_merge(const SimDev<T> *sim, int npatch, int cmax, int iters, int forced, hipStream_t st)
+void launch_merge(const SimDev<T> *sim, int npatch, int cmax, int iters, int forced, int cmax_bound,
+                  hipStream_t st)
 {
-    hipLaunchKernelGGL((k_merge2d<T>), dim3(std::min(npatch, 2048)), dim3(kMB), 0, st, sim, cmax, iters, forced);
+    const dim3 grid(std::min(npatch, 2048)), block(kMB);
+    if (cmax_bound / 2 <= 4)
+        hipLaunchKernelGGL((k_merge2d<T, 4>), grid, block, 0, st, sim, cmax, iters, forced);
+    else if (cmax_bound / 2 <= 8)
+        hipLaunchKernelGGL((k_merge2d<T, 8>), grid, block, 0, st, sim, cmax, iters, forced);
+    else
+        hipLaunchKernelGGL((k_merge2d<T, kKMax>), grid, block, 0, st, sim, cmax, iters, forced);
 }
 
-template void launch_merge<float>(const SimDev<float> *, int, int, int, int, hipStream_t);
-template void launch_merge<double>(const SimDev<double> *, int, int, int, int, hipStream_t);
+template void launch_merge<float>(const SimDev<float> *, int, int, int, int, int, hipStream_t);
+template void launch_merge<double>(const SimDev<double> *, int, int, int, int, int, hipStream_t);
 
 }  // namespace pic

@@ -123,7 +123,8 @@ constexpr int kWindowMaxPatchColumns = 4096;
 // step in flight is a merge step (cmax, iters then come from the simulation);
 // forced = 1: merge now with the given cmax (4..32) and iters.
 template <typename T>
-void launch_merge(const SimDev<T> *sim, int npatch, int cmax, int iters, int forced, hipStream_t st);
+void launch_merge(const SimDev<T> *sim, int npatch, int cmax, int iters, int forced, int cmax_bound,
+                  hipStream_t st);
 
 // Fused Yee update (half B, E, half B) with face conditions; clears the
 // other J buffer and accumulates the field energy of the incoming E, B.

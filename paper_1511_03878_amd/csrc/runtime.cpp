@@ -909,6 +909,9 @@ void SimImpl<T>::set_merge(int every, int cmax, int iters)
     merge_iters = iters;
     refresh_view();
     hipcheck(hipStreamSynchronize(stream), "sync");
+    // the step pass launches the merge kernel built for this cmax (a captured
+    // graph holds the launch of the earlier setting)
+    if (solo) solo->dirty = true;
 }
 
 template <typename T>
@@ -921,7 +924,7 @@ int64_t SimImpl<T>::merge_now(int cmax, int iters)
     const SimState s0 = read_state();
     if (s0.flags & kFlagPending) throw Error(PIC_ESTATE, "a re-binning is pending");
     if (!cap_d) return 0;
-    launch_merge<T>(view_d, npatch, cmax, iters, 1, stream);
+    launch_merge<T>(view_d, npatch, cmax, iters, 1, cmax, stream);
     hipcheck(hipGetLastError(), "merge launch");
     const SimState s1 = read_state();
     return s1.merged - s0.merged;
@@ -1886,7 +1889,7 @@ void BatchImpl<T>::launch_close_queue_pass()
     // merges, then window jumps, of the steps that close in this pass
     for (size_t i = 0; i < members.size(); ++i)
         if (members[i]->merge_every > 0 && members[i]->cap_d)
-            launch_merge<T>(sims_d + i, members[i]->npatch, 0, 0, 0, stream);
+            launch_merge<T>(sims_d + i, members[i]->npatch, 0, 0, 0, members[i]->merge_cmax, stream);
     for (size_t i = 0; i < members.size(); ++i)
         if (members[i]->win_on && members[i]->cap_d)
             launch_window<T>(sims_d + i, members[i]->fn[1], members[i]->np[1], stream);
