@@ -465,8 +465,9 @@ int pic_estimate_bytes(const PicSimDesc *d, int64_t nparticles, int64_t laser_st
     const int64_t floor_cap = d->min_capacity ? d->min_capacity : mean;
     // capacity policy: max(factor x count, floor) per patch, rounded up to 64
     int64_t slots = std::max<int64_t>((int64_t)(factor * nparticles), floor_cap * npatch) + 64 * npatch;
-    // particles + staging (3-D positions padded to four entries), code, hole list
-    const int64_t per_slot = 2 * ((three ? 8 : 6) * s + 8) + 1 + 4;
+    // particles + staging (3-D: position with the id and momentum with the
+    // weight, four entries each; 2-D: six entries and the id), code, hole list
+    const int64_t per_slot = 2 * (three ? 8 * s : 6 * s + 8) + 1 + 4;
     const int64_t max_tiles = three ? (fsize + 255) / 256 : ((fx + 15) / 16) * ((fy + 3) / 4);
     int64_t b = 18 * fsize * s;                        // two E, B buffers, two J buffers
     b += slots * per_slot;

@@ -138,7 +138,8 @@ __global__ void k_init_fill(InitSpec sp, int64_t nseg, const int64_t *__restrict
                     S->pos[slot * S->pw + a] = loc;
                 }
                 v4(S->mom)[slot] = Vec4<T>{(T)u[0], (T)u[1], (T)u[2], (T)w};
-                S->id[slot] = g;
+                if (sp.nd == 3) S->pos[slot * 4 + 3] = id_pad<T>(g);
+                else S->id[slot] = g;
                 S->code[slot] = (uint8_t)(sp.nd == 3 ? kStay3 : kStay2);
             }
         }

@@ -243,8 +243,9 @@ __global__ __launch_bounds__(BLOCK, (BLOCK == 512 && sizeof(T) == 4) ? 4 : 1) vo
         }
         kin_p = p;
 
-        // (positions x, y, z, unused and momenta with weight u_x, u_y, u_z, w:
-        // one access each)
+        // (positions x, y, z with the id and momenta with weight u_x, u_y,
+        // u_z, w: one access each; the id and the weight are stored back as
+        // loaded)
         const gptr_t<Vec4<T>> Pp = v4(S.pos) + base;
         const gptr_t<Vec4<T>> Mp = v4(S.mom) + base;
         const gptr_t<uint8_t> Cd = glb(S.code) + base;
@@ -261,12 +262,12 @@ __global__ __launch_bounds__(BLOCK, (BLOCK == 512 && sizeof(T) == 4) ? 4 : 1) vo
             return u < ufull ? kWave * S_ * (u / S_) + ln * S_ + (u % S_)
                              : kWave * S_ * npass + kWave * (u - ufull) + ln;
         };
-        T nx_, ny_, nz_, nux, nuy, nuz, nw_;
+        T nx_, ny_, nz_, nid, nux, nuy, nuz, nw_;
         auto load_unit = [&](int u) {
             const int kn = min(unit_particle(u), cnt - 1);
             const Vec4<T> pv = Pp[kn];
             const Vec4<T> mv = Mp[kn];
-            nx_ = pv.x; ny_ = pv.y; nz_ = pv.z;
+            nx_ = pv.x; ny_ = pv.y; nz_ = pv.z; nid = pv.w;
             nux = mv.x; nuy = mv.y; nuz = mv.z; nw_ = mv.w;
         };
         load_unit(wv);
@@ -353,7 +354,7 @@ __global__ __launch_bounds__(BLOCK, (BLOCK == 512 && sizeof(T) == 4) ? 4 : 1) vo
             T x1 = xl + dxl, y1 = yl + dyl, z1 = zl + dzl;
             const uint8_t code = place(x1, y1, z1);
             if (valid) {
-                Pp[k] = Vec4<T>{x1, y1, z1, T(0)};
+                Pp[k] = Vec4<T>{x1, y1, z1, pk.w};
                 Cd[k] = code;
                 left |= code != kStay3;
             }
@@ -365,7 +366,7 @@ __global__ __launch_bounds__(BLOCK, (BLOCK == 512 && sizeof(T) == 4) ? 4 : 1) vo
             const T xl = nx_, yl = ny_, zl = nz_;
             T ux = nux, uy = nuy, uz = nuz;
             const T wgt = kr < cnt ? nw_ : T(0);
-            const T wst = nw_;  // stored back as loaded (lanes past the end repeat the last particle)
+            const T wst = nw_, ist = nid;  // stored back as loaded (lanes past the end repeat the last particle)
             load_unit(u + NW);
 
             // ---- gather -------------------------------------------------
@@ -448,7 +449,7 @@ __global__ __launch_bounds__(BLOCK, (BLOCK == 512 && sizeof(T) == 4) ? 4 : 1) vo
             }
             // a deferred particle keeps its old position in memory until its
             // deposit (stores stay unconditional: the same value is rewritten)
-            Pp[k] = Vec4<T>{defer ? xl : x1, defer ? yl : y1, defer ? zl : z1, T(0)};
+            Pp[k] = Vec4<T>{defer ? xl : x1, defer ? yl : y1, defer ? zl : z1, ist};
             Mp[k] = Vec4<T>{ux, uy, uz, wst};
             Cd[k] = code;
             left |= !defer && code != kStay3;

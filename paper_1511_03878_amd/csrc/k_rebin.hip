@@ -448,10 +448,13 @@ __global__ void k_relayout(const SimDev<T> *__restrict__ src, const SimDev<T> *_
     const int n = src->count[p];
     const int64_t a = src->off[p], b = dst->off[p];
     for (int k = threadIdx.x; k < n; k += blockDim.x) {
-        if (src->pw == 4) v4(dst->pos)[b + k] = v4(src->pos)[a + k];
-        else v2(dst->pos)[b + k] = v2(src->pos)[a + k];
         v4(dst->mom)[b + k] = v4(src->mom)[a + k];
-        dst->id[b + k] = src->id[a + k];
+        if (src->pw == 4) {
+            v4(dst->pos)[b + k] = v4(src->pos)[a + k];  // (with the id)
+        } else {
+            v2(dst->pos)[b + k] = v2(src->pos)[a + k];
+            dst->id[b + k] = src->id[a + k];
+        }
         dst->code[b + k] = src->code[a + k];
     }
 }

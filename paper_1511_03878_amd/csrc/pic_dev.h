@@ -91,10 +91,11 @@ struct SimDev {
     int det;
     int64_t *Jacc[3];
     // particles, slot k: position pos[pw k + a] (pw = 2 in 2-D: x, y; pw = 4
-    // in 3-D: x, y, z and an unused entry), momentum and weight mom[4 k + c]
-    // (u_x, u_y, u_z, w).  One particle is two short runs of memory, so the
-    // re-binning moves it with three scattered accesses (pos, mom, id)
-    // instead of one per component.
+    // in 3-D: x, y, z and the id, see pad_id), momentum and weight
+    // mom[4 k + c] (u_x, u_y, u_z, w), the id in 2-D id[k] (null in 3-D).
+    // One particle is two or three short runs of memory, so the re-binning
+    // moves it with two (3-D) or three (2-D) scattered accesses instead of
+    // one per component.
     T *pos, *mom;
     int pw;
     int64_t *id;
@@ -190,6 +191,22 @@ __device__ __forceinline__ gptr_t<T> at(gptr_t<T> base, uint32_t i)
 {
     typedef __attribute__((address_space(1))) char gchar;
     return (gptr_t<T>)((gchar *)base + i * (uint32_t)sizeof(T));
+}
+
+// A 3-D particle's id in the fourth entry of its position vector, as bits:
+// all 64 in FP64 storage, the low 32 in FP32 storage (a 3-D FP32 simulation
+// holds fewer than 2^32 particles: the library refuses more).
+template <typename T>
+__host__ __device__ __forceinline__ T id_pad(int64_t id)
+{
+    if constexpr (sizeof(T) == 8) return __builtin_bit_cast(T, id);
+    else return __builtin_bit_cast(T, (uint32_t)id);
+}
+template <typename T>
+__host__ __device__ __forceinline__ int64_t pad_id(T v)
+{
+    if constexpr (sizeof(T) == 8) return __builtin_bit_cast(int64_t, v);
+    else return (int64_t)__builtin_bit_cast(uint32_t, v);
 }
 
 // Two and four consecutive particle components, loaded or stored as one

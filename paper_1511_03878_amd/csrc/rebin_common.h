@@ -27,10 +27,13 @@ __device__ __forceinline__ void copy_particle(const SimDev<T> &S, int64_t from, 
     T *tP = to_stage ? S.spos : S.pos, *tM = to_stage ? S.smom : S.mom;
     const int64_t *fi = from_stage ? S.sid : S.id;
     int64_t *ti = to_stage ? S.sid : S.id;
-    if (S.pw == 4) v4(tP)[to] = v4(fP)[from];
-    else v2(tP)[to] = v2(fP)[from];
     v4(tM)[to] = v4(fM)[from];
-    glb(ti)[to] = glb(fi)[from];
+    if (S.pw == 4) {
+        v4(tP)[to] = v4(fP)[from];  // (with the id)
+    } else {
+        v2(tP)[to] = v2(fP)[from];
+        glb(ti)[to] = glb(fi)[from];
+    }
 }
 
 // Count pass.  Each wave of the workgroup owns a contiguous range of the

@@ -407,8 +407,9 @@ std::vector<void *> SimImpl<T>::layout_particles(const std::vector<int32_t> &nee
         sP = (T *)get(sizeof(T) * total * pwid);
         pM = (T *)get(sizeof(T) * total * 4);
         sM = (T *)get(sizeof(T) * total * 4);
-        pid = (int64_t *)get(sizeof(int64_t) * total);
-        sid = (int64_t *)get(sizeof(int64_t) * total);
+        // (in 3-D the id rides in the position vector)
+        pid = nd == 2 ? (int64_t *)get(sizeof(int64_t) * total) : nullptr;
+        sid = nd == 2 ? (int64_t *)get(sizeof(int64_t) * total) : nullptr;
         code = (uint8_t *)get(total);
         holes = (int32_t *)get(sizeof(int32_t) * total);
         cap_d = (int32_t *)get(sizeof(int32_t) * npatch);
@@ -495,6 +496,8 @@ void SimImpl<T>::set_particles(int64_t cnt, const double *const xs[3], const dou
         for (int a = 0; a < nd; ++a)
             if (!(xs[a][k] >= 0.0 && xs[a][k] < (double)n[a]))
                 throw Error(PIC_EINVAL, "particle " + std::to_string(k) + " outside the domain");
+    if (nd == 3 && sizeof(T) == 4 && cnt >= ((int64_t)1 << 32))
+        throw Error(PIC_EINVAL, "a 3-D FP32 simulation holds fewer than 2^32 particles");
     // cell and patch of each particle, and counts
     auto cell_of = [&](int64_t k, int a) { return a < nd ? std::min((int)std::floor(xs[a][k]), n[a] - 1) : 0; };
     std::vector<int32_t> pp(cnt), counts(npatch, 0);
@@ -525,11 +528,12 @@ void SimImpl<T>::set_particles(int64_t cnt, const double *const xs[3], const dou
         }
         for (int a = 0; a < 3; ++a) hM[(size_t)t * 4 + a] = us[a] ? (T)us[a][k] : T(0);
         hM[(size_t)t * 4 + 3] = (T)w[k];
-        hid[t] = k;
+        if (nd == 3) hP[(size_t)t * 4 + 3] = id_pad<T>(k);
+        else hid[t] = k;
     }
     hipcheck(hipMemcpyAsync(pP, hP.data(), sizeof(T) * hP.size(), hipMemcpyHostToDevice, stream), "x");
     hipcheck(hipMemcpyAsync(pM, hM.data(), sizeof(T) * hM.size(), hipMemcpyHostToDevice, stream), "u, w");
-    hipcheck(hipMemcpyAsync(pid, hid.data(), sizeof(int64_t) * tot, hipMemcpyHostToDevice, stream), "id");
+    if (pid) hipcheck(hipMemcpyAsync(pid, hid.data(), sizeof(int64_t) * tot, hipMemcpyHostToDevice, stream), "id");
     hipcheck(hipMemsetAsync(code, ndir / 2, tot, stream), "code");
     finish_load(counts, cnt);
 }
@@ -624,6 +628,8 @@ void SimImpl<T>::particles_init()
         if (pcount[p] > INT32_MAX / 4) throw Error(PIC_EOVERFLOW, "too many particles in one patch");
     }
     if (total >= ((int64_t)1 << 41)) throw Error(PIC_EINVAL, "too many particles");
+    if (nd == 3 && sizeof(T) == 4 && total >= ((int64_t)1 << 32))
+        throw Error(PIC_EINVAL, "a 3-D FP32 simulation holds fewer than 2^32 particles");
     for (int p = 0; p < npatch; ++p) counts[p] = (int32_t)pcount[p];
     lane_stride = desc.lane_stride ? desc.lane_stride : default_lane_stride(nd);
     std::vector<void *> old = layout_particles(counts);
@@ -631,7 +637,7 @@ void SimImpl<T>::particles_init()
     const int64_t tot = total_cap;
     hipcheck(hipMemsetAsync(pP, 0, sizeof(T) * tot * pwid, stream), "clear x");
     hipcheck(hipMemsetAsync(pM, 0, sizeof(T) * tot * 4, stream), "clear u, w");
-    hipcheck(hipMemsetAsync(pid, 0xff, sizeof(int64_t) * tot, stream), "clear id");
+    if (pid) hipcheck(hipMemsetAsync(pid, 0xff, sizeof(int64_t) * tot, stream), "clear id");
     hipcheck(hipMemsetAsync(code, ndir / 2, tot, stream), "code");
     int64_t *first_d = (int64_t *)alloc.get(sizeof(int64_t) * nseg);
     int32_t *slot_d = nullptr;
@@ -1054,7 +1060,13 @@ void SimImpl<T>::get_particles(double *xo[3], double *uo[3], double *wo, int64_t
         for (int a = 0; a < 3; ++a) if (uo[a]) fetch(tmp, 4, a, uo[a], 3);
         if (wo) fetch(tmp, 4, 3, wo, 3);
     }
-    if (ido) {
+    if (ido && nd == 3) {
+        // (ids ride in the position vectors)
+        download(pP, 4);
+        int64_t o = 0;
+        for (int p = 0; p < npatch; ++p)
+            for (int k = 0; k < c[p]; ++k) ido[o++] = pad_id<T>(tmp[(size_t)(off_h[p] + k) * 4 + 3]);
+    } else if (ido) {
         itmp.resize(tot);
         hipcheck(hipMemcpyAsync(itmp.data(), pid, sizeof(int64_t) * tot, hipMemcpyDeviceToHost, stream), "ids");
         hipcheck(hipStreamSynchronize(stream), "sync");
@@ -1165,11 +1177,16 @@ void SimImpl<T>::state_save(void *blob)
     };
     download(pP, pwid);
     for (int a = 0; a < nd; ++a) pack(pwid, a);
+    std::vector<int64_t> itmp(tot);
+    if (nd == 3) {
+        // (3-D ids ride in the position vectors)
+        for (int64_t k = 0; k < tot; ++k) itmp[k] = pad_id<T>(tmp[(size_t)k * 4 + 3]);
+    } else {
+        hipcheck(hipMemcpyAsync(itmp.data(), pid, sizeof(int64_t) * tot, hipMemcpyDeviceToHost, stream), "checkpoint");
+        hipcheck(hipStreamSynchronize(stream), "sync");
+    }
     download(pM, 4);
     for (int a = 0; a < 4; ++a) pack(4, a);
-    std::vector<int64_t> itmp(tot);
-    hipcheck(hipMemcpyAsync(itmp.data(), pid, sizeof(int64_t) * tot, hipMemcpyDeviceToHost, stream), "checkpoint");
-    hipcheck(hipStreamSynchronize(stream), "sync");
     for (int p = 0; p < npatch; ++p) {
         std::memcpy(o, itmp.data() + off_h[p], sizeof(int64_t) * c[p]);
         o += sizeof(int64_t) * c[p];
@@ -1229,18 +1246,30 @@ void SimImpl<T>::state_load(const void *blob, size_t size)
         hipcheck(hipMemcpyAsync(dst, tmp.data(), sizeof(T) * tmp.size(), hipMemcpyHostToDevice, stream), "restore");
         hipcheck(hipStreamSynchronize(stream), "sync");
     };
+    // the ids follow the position and momentum arrays in the checkpoint
+    std::vector<int64_t> itmp(tot, -1);
+    {
+        const char *ids = i + (size_t)live * sizeof(T) * (nd + 4);
+        for (int p = 0; p < npatch; ++p) {
+            std::memcpy(itmp.data() + off_h[p], ids, sizeof(int64_t) * c[p]);
+            ids += sizeof(int64_t) * c[p];
+        }
+    }
+    if (nd == 3 && sizeof(T) == 4)
+        for (int p = 0; p < npatch; ++p)
+            for (int k = 0; k < c[p]; ++k)
+                if (itmp[off_h[p] + k] < 0 || itmp[off_h[p] + k] >= ((int64_t)1 << 32))
+                    throw Error(PIC_EINVAL, "corrupt checkpoint");
     tmp.assign((size_t)tot * pwid, T(0));
     for (int a = 0; a < nd; ++a) unpack(pwid, a);
+    if (nd == 3)
+        for (int64_t k = 0; k < tot; ++k) tmp[(size_t)k * 4 + 3] = id_pad<T>(itmp[k]);
     upload(pP);
     tmp.assign((size_t)tot * 4, T(0));
     for (int a = 0; a < 4; ++a) unpack(4, a);
     upload(pM);
-    std::vector<int64_t> itmp(tot, -1);
-    for (int p = 0; p < npatch; ++p) {
-        std::memcpy(itmp.data() + off_h[p], i, sizeof(int64_t) * c[p]);
-        i += sizeof(int64_t) * c[p];
-    }
-    hipcheck(hipMemcpyAsync(pid, itmp.data(), sizeof(int64_t) * tot, hipMemcpyHostToDevice, stream), "restore");
+    i += (size_t)live * sizeof(int64_t);
+    if (pid) hipcheck(hipMemcpyAsync(pid, itmp.data(), sizeof(int64_t) * tot, hipMemcpyHostToDevice, stream), "restore");
     hipcheck(hipMemsetAsync(code, ndir / 2, tot, stream), "restore");
     hipcheck(hipMemcpyAsync(counts_d, c.data(), sizeof(int32_t) * npatch, hipMemcpyHostToDevice, stream), "restore");
     h2d(hist, sizeof(double) * kHistLen * 4);
