@@ -185,7 +185,9 @@ void pic_sim_destroy(PicSim *s);
  * weights (density contributed, in units of the reference density).  z and
  * uz may be NULL in 2-D (uz NULL = 0).  Replaces any previous particles and
  * resets the step counter to 0.  Values are rounded to the handle's
- * precision; positions are stored as offsets from their patch origin. */
+ * precision; positions are stored as offsets from their patch origin.  A 3-D
+ * FP32 handle holds fewer than 2^32 particles (its ids are stored in 32 bits):
+ * PIC_EINVAL for more, as for pic_particles_init. */
 int pic_particles_set(PicSim *s, int64_t n, const double *x, const double *y, const double *z,
                       const double *ux, const double *uy, const double *uz, const double *w);
 
@@ -242,7 +244,9 @@ typedef struct {
 int pic_species_add(PicSim *s, const PicSpeciesDesc *d, int32_t *sid);
 /* Generate species sid's particles on the device as described above; replaces
  * any previous particles and resets the step counter to 0, like
- * pic_particles_set.  PIC_ESTATE without a species or in a batch. */
+ * pic_particles_set.  PIC_ESTATE without a species or in a batch; PIC_EINVAL
+ * when the description gives 2^41 particles or more (2^32 for a 3-D FP32
+ * handle). */
 int pic_particles_init(PicSim *s, int32_t sid);
 
 /* A Gaussian laser pulse driving the open x = 0 face of a 2-D box (the LWFA
