@@ -106,3 +106,16 @@ def test_boundary_argument_errors():
     per = Sim(W.uniform_2d(n=(32, 32))["grid"], 64)
     with pytest.raises(PicError):
         per.add_laser(wl["laser"])
+
+
+def test_3d_fp32_refuses_two_to_the_32_particles():
+    # 3-D FP32 handles store ids in 32 bits: a description giving 2^32 or more
+    # particles (here 128 per cell of the 512 x 256 x 256 box, plus the blob)
+    # is refused before any particle array is allocated
+    _announce("3-D FP32: a species of 2^32 particles or more is refused")
+    wl = W.blob_3d(patch=(8, 8, 8), ppc0=128)
+    s = Sim(wl["grid"], 32)
+    s.add_species(wl["species"])
+    with pytest.raises(PicError):
+        s.particles_init()
+    s.close()
