@@ -208,11 +208,43 @@ __global__ __launch_bounds__(kRB) void k_rebin_scatter(const SimDev<T> *__restri
 // the chunks are placed in order of decreasing size, so that persistent
 // workgroups pulling from the queue start with the largest items (the
 // single-GPU counterpart of evening out load by exchanging patches).
+// Batches of more than kCntCache patches build the queue with two grid
+// kernels instead (k_queue_hist, k_queue_place): one workgroup would walk
+// their patch counts in many dependent rounds.
 
 constexpr int kQB = 1024;   // threads of the single queue workgroup
 constexpr int kQW = kQB / 64;
 constexpr int kBuckets = 1024;
 constexpr int kCntCache = 8192;
+constexpr int kQS = 256;    // threads of a grid queue workgroup
+static_assert(2 * kBuckets + kMaxBatch == kQueueScratch, "queue scratch layout");
+static_assert(kBuckets % kQS == 0, "buckets per thread");
+
+// bucket of a chunk of c particles (0: full chunks; larger chunks first)
+__device__ __forceinline__ int chunk_bucket(int c, int chunk)
+{
+    return kBuckets - 1 - (int)(((int64_t)(c - 1) * kBuckets) / chunk);
+}
+
+// patch at queue position gp of simulation s (curve order when the
+// simulation asks for it, else patch id order)
+template <typename T>
+__device__ __forceinline__ int queue_patch(const SimDev<T> *sims, const int *pp, int gp, int s)
+{
+    const int lp = gp - pp[s];
+    const int32_t *po = sims[s].porder;
+    return po ? (int)glb(po)[lp] : lp;
+}
+
+__device__ __forceinline__ int wave_incl_scan(int v, int lane)
+{
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(v, o, 64);
+        if (lane >= o) v += y;
+    }
+    return v;
+}
 
 template <typename T>
 __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict__ sims,
@@ -304,17 +336,23 @@ __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict
         }
         __syncthreads();
     }
+    if (qa.total_patches > kCntCache) {
+        // the grid kernels build the queue: clear their bucket counts and
+        // cursors and the pushed counters they add to, and hand them each
+        // simulation's participation and step parity
+        const gptr_t<int> sc = glb(qa.scratch);
+        for (int b = tid; b < 2 * kBuckets; b += kQB) sc[b] = 0;
+        for (int s = tid; s < nsims; s += kQB) {
+            sc[2 * kBuckets + s] = s_act[s] | (int)s_par[s] << 1;
+            if (s_act[s]) glb(sims[s].st)->pushed = 0;
+        }
+        return;
+    }
     for (int b = tid; b < kBuckets; b += kQB) s_hist[b] = 0;
     for (int i = tid; i <= nsims; i += kQB) s_pp[i] = qa.patch_prefix[i];
     __syncthreads();
 
-    // queue position gp of simulation s -> its patch (curve order when the
-    // simulation asks for it, else patch id order)
-    auto patch_at = [&](int gp, int s) {
-        const int lp = gp - s_pp[s];
-        const int32_t *po = sims[s].porder;
-        return po ? (int)glb(po)[lp] : lp;
-    };
+    auto patch_at = [&](int gp, int s) { return queue_patch(sims, s_pp, gp, s); };
     // ---- particle counts of the first kCntCache patches, loaded together ----------
     const int total = s_pp[nsims];
     const int ncache = min(total, kCntCache);
@@ -356,15 +394,7 @@ __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict
     // LDS atomic on its own bucket.  Items of one bucket land in arbitrary
     // order.
     const int chunk = qa.chunk;
-    auto bucket = [&](int c) { return kBuckets - 1 - (int)(((int64_t)(c - 1) * kBuckets) / chunk); };
-    auto wave_incl_scan = [&](int v) {
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(v, o, 64);
-            if (lane >= o) v += y;
-        }
-        return v;
-    };
+    auto bucket = [&](int c) { return chunk_bucket(c, chunk); };
     for (int g0 = 0; g0 < total; g0 += kQB) {
         const int gp = g0 + tid;
         int s = 0, n = 0;
@@ -384,7 +414,7 @@ __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict
             todo &= ~same;
         }
         const int nfull = n / chunk, rem = n - nfull * chunk;
-        const int fsum = __shfl(wave_incl_scan(nfull), 63, 64);
+        const int fsum = __shfl(wave_incl_scan(nfull, lane), 63, 64);
         if (lane == 0 && fsum) atomicAdd(&s_hist[0], fsum);
         if (rem) atomicAdd(&s_hist[bucket(rem)], 1);
     }
@@ -393,7 +423,7 @@ __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict
         if (s_act[s]) glb(sims[s].st)->pushed = s_pushed[s];
     // exclusive scan of the histogram (one bucket per thread)
     const int v = s_hist[tid];
-    int incl = wave_incl_scan(v);
+    int incl = wave_incl_scan(v, lane);
     if (lane == 63) s_wsum[wave] = incl;
     __syncthreads();
     int woff = 0;
@@ -424,7 +454,7 @@ __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict
             n = count_of(gp, s);
         }
         const int nfull = n / chunk, rem = n - nfull * chunk;
-        const int incl_f = wave_incl_scan(nfull);
+        const int incl_f = wave_incl_scan(nfull, lane);
         const int fsum = __shfl(incl_f, 63, 64);
         int fbase = 0;
         if (lane == 0 && fsum) fbase = atomicAdd(&s_hist[0], fsum);
@@ -434,6 +464,153 @@ __global__ __launch_bounds__(kQB) void k_close_queue(const SimDev<T> *__restrict
         if (rem) put(atomicAdd(&s_hist[bucket(rem)], 1), s, p, o + (int64_t)nfull * chunk, rem);
     }
     if (tid == 0) {
+        *glb(qa.nitems) = min(ntot, qa.max_items);
+        *glb(qa.head) = 0;
+    }
+}
+
+// ---- grid-wide queue build (batches of more than kCntCache patches) -------------
+//
+// k_queue_hist: each workgroup counts the chunks of its patches per bucket
+// and the particles pushed per simulation in LDS, then adds its nonzero
+// counts to the global ones (one atomic per bucket or simulation).
+// k_queue_place: every workgroup scans the global bucket counts itself, then,
+// round by round, ranks its chunks per bucket in LDS, takes one run of places
+// per nonzero bucket from a global cursor and writes its items there.  Items
+// of one bucket land in arbitrary order, as in the one-workgroup build.
+
+template <typename T>
+__global__ __launch_bounds__(kQS) void k_queue_hist(const SimDev<T> *__restrict__ sims, QueueArgs qa)
+{
+    __shared__ int s_hist[kBuckets];
+    __shared__ int s_pp[kMaxBatch + 1];
+    __shared__ uint8_t s_act[kMaxBatch];
+    __shared__ unsigned long long s_pushed[kMaxBatch];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int nsims = qa.nsims, chunk = qa.chunk;
+    const gptr_t<int> sc = glb(qa.scratch);
+    for (int b = tid; b < kBuckets; b += kQS) s_hist[b] = 0;
+    for (int i = tid; i <= nsims; i += kQS) s_pp[i] = qa.patch_prefix[i];
+    for (int s = tid; s < nsims; s += kQS) {
+        s_act[s] = (uint8_t)(sc[2 * kBuckets + s] & 1);
+        s_pushed[s] = 0;
+    }
+    __syncthreads();
+    const int total = s_pp[nsims];
+    for (int g0 = blockIdx.x * kQS; g0 < total; g0 += gridDim.x * kQS) {
+        const int gp = g0 + tid;
+        int s = 0, n = 0;
+        if (gp < total) {
+            s = find_sim(s_pp, nsims, gp);
+            if (s_act[s]) n = glb((const int32_t *)sims[s].count)[queue_patch(sims, s_pp, gp, s)];
+        }
+        uint64_t todo = __ballot(n > 0);
+        while (todo) {
+            const int sl = __shfl(s, __ffsll((unsigned long long)todo) - 1, 64);
+            const uint64_t same = __ballot(n > 0 && s == sl);
+            long long v = (n > 0 && s == sl) ? n : 0;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (lane == 0) atomicAdd(&s_pushed[sl], (unsigned long long)v);
+            todo &= ~same;
+        }
+        const int nfull = n / chunk, rem = n - nfull * chunk;
+        const int fsum = __shfl(wave_incl_scan(nfull, lane), 63, 64);
+        if (lane == 0 && fsum) atomicAdd(&s_hist[0], fsum);
+        if (rem) atomicAdd(&s_hist[chunk_bucket(rem, chunk)], 1);
+    }
+    __syncthreads();
+    for (int b = tid; b < kBuckets; b += kQS)
+        if (s_hist[b]) __hip_atomic_fetch_add(&sc[b], s_hist[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int s = tid; s < nsims; s += kQS)
+        if (s_pushed[s])
+            __hip_atomic_fetch_add(&glb(sims[s].st)->pushed, (int64_t)s_pushed[s], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kQS) void k_queue_place(const SimDev<T> *__restrict__ sims, QueueArgs qa)
+{
+    constexpr int kPer = kBuckets / kQS;
+    __shared__ int s_scan[kBuckets];  // first place of each bucket
+    __shared__ int s_cnt[kBuckets];   // this round's chunks per bucket
+    __shared__ int s_base[kBuckets];  // this round's first place in each bucket
+    __shared__ int s_pp[kMaxBatch + 1];
+    __shared__ uint8_t s_flag[kMaxBatch];
+    __shared__ int s_wsum[kQS / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nsims = qa.nsims, chunk = qa.chunk;
+    const gptr_t<int> sc = glb(qa.scratch);
+    // exclusive scan of the bucket counts: kPer consecutive buckets per thread
+    int v[kPer], sum = 0;
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        v[r] = sc[tid * kPer + r];
+        sum += v[r];
+    }
+    for (int i = tid; i <= nsims; i += kQS) s_pp[i] = qa.patch_prefix[i];
+    for (int s = tid; s < nsims; s += kQS) s_flag[s] = (uint8_t)sc[2 * kBuckets + s];
+    const int incl = wave_incl_scan(sum, lane);
+    if (lane == 63) s_wsum[wave] = incl;
+    __syncthreads();
+    int run = incl - sum, ntot = 0;
+    for (int w = 0; w < kQS / 64; ++w) {
+        if (w < wave) run += s_wsum[w];
+        ntot += s_wsum[w];
+    }
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        s_scan[tid * kPer + r] = run;
+        s_cnt[tid * kPer + r] = 0;
+        run += v[r];
+    }
+    __syncthreads();
+    const gptr_t<int> items = glb(reinterpret_cast<int *>(qa.items));
+    auto put = [&](int pos, int s, int p, int64_t slot, int c) {
+        if (pos >= qa.max_items) return;
+        const gptr_t<int> it = items + 4 * (int64_t)pos;
+        it[0] = s | ((int)(s_flag[s] >> 1) << 30);
+        it[1] = p;
+        it[2] = (int)slot;
+        it[3] = c;
+    };
+    const int total = s_pp[nsims];
+    for (int g0 = blockIdx.x * kQS; g0 < total; g0 += gridDim.x * kQS) {
+        const int gp = g0 + tid;
+        int s = 0, p = 0, n = 0;
+        int64_t o = 0;
+        if (gp < total) {
+            s = find_sim(s_pp, nsims, gp);
+            if (s_flag[s] & 1) {
+                p = queue_patch(sims, s_pp, gp, s);
+                n = glb((const int32_t *)sims[s].count)[p];
+                o = glb((const int64_t *)sims[s].off)[p];
+            }
+        }
+        // ranks inside this round: full chunks by a wave scan, partial ones
+        // by an LDS atomic on their bucket
+        const int nfull = n / chunk, rem = n - nfull * chunk;
+        const int incl_f = wave_incl_scan(nfull, lane);
+        const int fsum = __shfl(incl_f, 63, 64);
+        int fr = 0;
+        if (lane == 0 && fsum) fr = atomicAdd(&s_cnt[0], fsum);
+        fr = __shfl(fr, 0, 64) + incl_f - nfull;
+        const int b = rem ? chunk_bucket(rem, chunk) : 0;
+        const int rr = rem ? atomicAdd(&s_cnt[b], 1) : 0;
+        __syncthreads();
+        for (int k = tid; k < kBuckets; k += kQS) {
+            const int c = s_cnt[k];
+            s_base[k] = c ? __hip_atomic_fetch_add(&sc[kBuckets + k], c, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT)
+                          : 0;
+            s_cnt[k] = 0;
+        }
+        __syncthreads();
+        const int fb = s_scan[0] + s_base[0] + fr;
+        for (int k = 0; k < nfull; ++k) put(fb + k, s, p, o + (int64_t)k * chunk, chunk);
+        if (rem) put(s_scan[b] + s_base[b] + rr, s, p, o + (int64_t)nfull * chunk, rem);
+    }
+    if (blockIdx.x == 0 && tid == 0) {
         *glb(qa.nitems) = min(ntot, qa.max_items);
         *glb(qa.head) = 0;
     }
@@ -476,8 +653,15 @@ __global__ void k_scatter_codes(const uint8_t *__restrict__ packed,
 template <typename T>
 void launch_close_queue(const SimDev<T> *sims, const QueueArgs &q, hipStream_t st, Ev2 ev)
 {
-    hipExtLaunchKernelGGL((k_close_queue<T>), dim3(1), dim3(kQB), 0, st, ev.start, ev.stop, 0, sims,
-                          q);
+    if (q.total_patches <= kCntCache) {
+        hipExtLaunchKernelGGL((k_close_queue<T>), dim3(1), dim3(kQB), 0, st, ev.start, ev.stop, 0, sims,
+                              q);
+        return;
+    }
+    const int grid = std::min((q.total_patches + kQS - 1) / kQS, 1024);
+    hipExtLaunchKernelGGL((k_close_queue<T>), dim3(1), dim3(kQB), 0, st, ev.start, nullptr, 0, sims, q);
+    hipLaunchKernelGGL((k_queue_hist<T>), dim3(grid), dim3(kQS), 0, st, sims, q);
+    hipExtLaunchKernelGGL((k_queue_place<T>), dim3(grid), dim3(kQS), 0, st, nullptr, ev.stop, 0, sims, q);
 }
 
 template <typename T, int ND>

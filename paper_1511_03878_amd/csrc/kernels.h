@@ -74,7 +74,13 @@ struct QueueArgs {
     int *head;
     int max_items;
     int chunk;                // max particles per item
+    int total_patches;        // patch_prefix[nsims]
+    // scratch of the grid-wide queue build (kQueueScratch ints): bucket
+    // counts, bucket cursors, then one participation word per simulation
+    int *scratch;
 };
+// ints of QueueArgs::scratch (two sets of 1024 buckets and kMaxBatch words)
+constexpr int kQueueScratch = 2 * 1024 + kMaxBatch;
 
 // Close the steps whose re-binning was applied (energy reduction, history,
 // step counter, budget) and build the work queue of the next step.

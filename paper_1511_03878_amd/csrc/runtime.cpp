@@ -1716,6 +1716,7 @@ void BatchImpl<T>::free_tables()
     items_d = nullptr;
     stamps_d = nullptr;
     nitems_d = head_d = stamp_n_d = nullptr;
+    qscratch_d = nullptr;
     table_cap_items = 0;
 }
 
@@ -1862,6 +1863,7 @@ void BatchImpl<T>::build_tables()
     nitems_d = (int *)get(sizeof(int) * 4);
     head_d = nitems_d + 1;
     stamp_n_d = nitems_d + 2;
+    qscratch_d = (int *)get(sizeof(int) * kQueueScratch);
     table_cap_items = (int)items;
     std::vector<SimDev<T>> views(ns);
     for (int i = 0; i < ns; ++i) {
@@ -1908,6 +1910,8 @@ QueueArgs BatchImpl<T>::queue_args() const
     qa.head = head_d;
     qa.max_items = table_cap_items;
     qa.chunk = chunk;
+    qa.total_patches = total_patches;
+    qa.scratch = qscratch_d;
     return qa;
 }
 

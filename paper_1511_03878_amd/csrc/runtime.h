@@ -234,6 +234,7 @@ struct BatchImpl : BatchBase {
     int64_t *det_prefix_d = nullptr;
     Item *items_d = nullptr;
     int *nitems_d = nullptr, *head_d = nullptr;
+    int *qscratch_d = nullptr;  // grid-wide queue build: bucket counts and cursors, participation
     ItemStamp *stamps_d = nullptr;  // per-item records of the last stamped particle launch
     int *stamp_n_d = nullptr;       // its item count
     int table_cap_items = 0;

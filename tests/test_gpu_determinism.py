@@ -92,6 +92,37 @@ def test_alone_and_in_a_batch_give_the_same_bits():
     _assert_same(_state(a), ref)
 
 
+def test_batch_of_more_patches_than_the_queue_cache_gives_the_bits_alone():
+    # alone: 1024 patches, queue built by one workgroup; nine in a batch:
+    # 9216 patches, queue built by the grid-wide kernels (chunks of 48
+    # particles: full chunks and remainders in several buckets)
+    _announce("deterministic fp32: 128x128 box of 4x4-cell patches alone vs nine in a batch, 12 steps")
+    wls = [W.to_float32_state(W.uniform_2d(n=(128, 128), patch=(4, 4), ppc=16, T_keV=20.0, seed=100 + k))
+           for k in range(9)]
+    refs = []
+    for wl in wls[:2]:
+        s = gpu_sim(wl, 32, deterministic=1, chunk=48)
+        s.step(12)
+        refs.append(_state(s))
+        s.close()
+    b = Batch(32)
+    sims = [Sim.from_workload(wl, precision=32, deterministic=1, chunk=48) for wl in wls]
+    for s in sims:
+        b.add(s, 12)
+    done = 0
+    for _ in range(10):
+        done += b.step(12)
+        if done == len(sims):
+            break
+    assert done == len(sims)
+    for s, ref in zip(sims, refs):
+        assert s.diag()["step"] == 12
+        _assert_same(_state(s), ref)
+    for s in sims:
+        _, _, pushed = s.history(0, 12)
+        assert (pushed == 16 * 128 * 128).all(), pushed
+
+
 def test_checkpoint_resume_is_bitwise_equal():
     _announce("deterministic fp32: 12 steps against 5 + save/load + 7")
     wl = _thermal_2d()

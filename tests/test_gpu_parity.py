@@ -63,6 +63,28 @@ def test_uniform_fp32_one_step_matches_oracle(c1):
     assert rel_l2(jg, jo) < 1e-5
 
 
+def test_box_of_16384_patches_matches_oracle_fp64():
+    # more patches than the one-workgroup queue build caches (8192): the
+    # work queue comes from the grid-wide histogram and placement kernels
+    _announce("uniform 512x512, 4x4-cell patches (16384), 4 ppc, 20 keV, fp64, 6 steps")
+    wl = W.uniform_2d(n=(512, 512), patch=(4, 4), ppc=4, T_keV=20.0)
+    g = gpu_sim(wl, 64, chunk=24)
+    g.step(6)
+    o = oracle_run(wl, 6)
+    e, b = compare_fields(g, o)
+    assert e < 1e-11 and b < 1e-11, (e, b)
+    assert np.array_equal(g.counts(), o.counts())
+    gx, gu, gw, gid = g.particles()
+    ox, ou, ow, oid = o.particles()
+    assert np.array_equal(gid, oid)
+    for a in range(2):
+        assert np.abs(gx[a] - ox[a]).max() < 1e-11
+    U, K, pushed = g.history(0, 6)
+    assert (pushed == wl["w"].size).all(), pushed
+    Uo, Ko = o.energy()
+    assert abs(K[5] - Ko) <= 1e-12 * abs(Ko)
+
+
 def test_maxwell_only_matches_oracle_fp64():
     _announce("vacuum fields 96x64 fp64, 20 steps")
     grid = dict(ndim=2, n=[96, 64], d=[0.1, 0.13], dt=W.cfl_dt((0.1, 0.13)), patch=[16, 16],
