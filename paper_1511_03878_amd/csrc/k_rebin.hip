@@ -29,14 +29,16 @@ namespace pic {
 
 namespace {
 
-constexpr int kRB = 256;  // threads per re-binning workgroup
-constexpr int kNW = kRB / 64;
+// threads of a scatter workgroup: 2-D, and 3-D (about a hundred arrivals per
+// patch, one per thread; measured faster than 256 beside the field update)
+constexpr int kRB = 256;
+constexpr int kRB3 = 128;
 
-template <typename T, int ND>
-__global__ __launch_bounds__(kRC) void k_rebin_count(const SimDev<T> *__restrict__ sims, int nsims,
-                                                     const int *__restrict__ patch_prefix, int total)
+template <typename T, int ND, int NT>
+__global__ __launch_bounds__(NT) void k_rebin_count(const SimDev<T> *__restrict__ sims, int nsims,
+                                                    const int *__restrict__ patch_prefix, int total)
 {
-    __shared__ CountSmem<ND, kRC / 64> sm;
+    __shared__ CountSmem<ND, NT / 64> sm;
     for (int gp = blockIdx.x; gp < total; gp += gridDim.x) {
         const int s = find_sim(patch_prefix, nsims, gp);
         const SimDev<T> &S = sims[s];
@@ -55,7 +57,7 @@ __global__ __launch_bounds__(kRC) void k_rebin_count(const SimDev<T> *__restrict
             if (threadIdx.x == 0) glb(S.nleave)[p] = 0;
             continue;
         }
-        count_patch<T, ND, kRC / 64>(S, p, n, base, key, sm);
+        count_patch<T, ND, NT / 64>(S, p, n, base, key, sm);
     }
 }
 
@@ -89,12 +91,14 @@ __global__ __launch_bounds__(256) void k_rebin_check(const SimDev<T> *__restrict
         __hip_atomic_fetch_or(&glb(S.st)->flags, kFlagPending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <typename T, int ND>
-__global__ __launch_bounds__(kRB) void k_rebin_scatter(const SimDev<T> *__restrict__ sims, int nsims,
+template <typename T, int ND, int NT>
+__global__ __launch_bounds__(NT) void k_rebin_scatter(const SimDev<T> *__restrict__ sims, int nsims,
                                                        const int *__restrict__ patch_prefix,
                                                        int total)
 {
     constexpr int NS = ND - 1;  // at most this many distinct source patches
+    constexpr int kNW = NT / 64;
+    static_assert(NT >= 64 + ND, "threads 64 .. 64 + ND hold the direction keys");
     __shared__ int s_scnt[NS];
     __shared__ int64_t s_sbase[NS];
     __shared__ int s_ns;
@@ -153,7 +157,7 @@ __global__ __launch_bounds__(kRB) void k_rebin_scatter(const SimDev<T> *__restri
         // arrivals (sources in ascending id, each in its slot order): holes
         // first, then appended from slot n; one thread per arrival, so the
         // copies of all sources are in flight together
-        for (int a = tid; a < A; a += kRB) {
+        for (int a = tid; a < A; a += NT) {
             int i = 0, a0 = 0;
             while (i + 1 < s_ns && a >= a0 + s_scnt[i]) a0 += s_scnt[i++];
             const int target = a < nH ? glb(S.holes)[base + a] : n + (a - nH);
@@ -161,7 +165,7 @@ __global__ __launch_bounds__(kRB) void k_rebin_scatter(const SimDev<T> *__restri
         }
         // stayers in [n', n) fill the remaining holes
         if (np < n) {
-            for (int c0 = np; c0 < n; c0 += kRB) {
+            for (int c0 = np; c0 < n; c0 += NT) {
                 const int k = c0 + tid;
                 bool stay = false;
                 if (k < n) {
@@ -669,11 +673,13 @@ static void launch_rebin_nd(const SimDev<T> *sims, int nsims, const int *patch_p
                             int total_patches, int grid, hipStream_t st, Ev2 ev)
 {
     // one count workgroup per patch (the hardware balances uneven patches)
-    hipExtLaunchKernelGGL((k_rebin_count<T, ND>), dim3(std::min(total_patches, 1 << 20)), dim3(kRC),
+    constexpr int NT = ND == kNDir3 ? kRC3 : kRC;
+    hipExtLaunchKernelGGL((k_rebin_count<T, ND, NT>), dim3(std::min(total_patches, 1 << 20)), dim3(NT),
                           0, st, ev.start, nullptr, 0, sims, nsims, patch_prefix, total_patches);
     hipLaunchKernelGGL((k_rebin_check<T, ND>), dim3((total_patches + 255) / 256), dim3(256), 0, st,
                        sims, nsims, patch_prefix, total_patches);
-    hipExtLaunchKernelGGL((k_rebin_scatter<T, ND>), dim3(grid), dim3(kRB), 0, st, nullptr, ev.stop, 0,
+    constexpr int NB = ND == kNDir3 ? kRB3 : kRB;
+    hipExtLaunchKernelGGL((k_rebin_scatter<T, ND, NB>), dim3(grid), dim3(NB), 0, st, nullptr, ev.stop, 0,
                           sims, nsims, patch_prefix, total_patches);
 }
 

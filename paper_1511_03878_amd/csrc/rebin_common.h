@@ -46,7 +46,11 @@ __device__ __forceinline__ void copy_particle(const SimDev<T> &S, int64_t from, 
 // the staged leavers are queued in a per-wave LDS ring, which is drained 64
 // entries at a time (one lane per particle, so the particle loads of 64
 // leavers are in flight together).
-constexpr int kRC = 512;  // threads of the count workgroup of the re-binning kernel (measured: 256 and 1024 slower)
+// threads of the count workgroup: 2-D (measured: 256 and 1024 slower), and
+// 3-D, one wave per patch (about a hundred leavers per 8^3 patch; beside the
+// field update the small workgroups keep more patches in flight)
+constexpr int kRC = 512;
+constexpr int kRC3 = 64;
 constexpr int kU = 16;    // 64-slot chunks per batch of code loads (63 VGPRs: 8 waves per SIMD)
 constexpr int kRing = 128;
 
@@ -83,8 +87,7 @@ __device__ __forceinline__ void count_patch(const SimDev<T> &S, int p, int n, in
 {
     constexpr int kKeys = ND + 1;  // ND direction keys + removed
     constexpr int kThreads = NWV * 64;
-    // (NWV == 1 would give one wave per patch, synchronised by wave barriers
-    // only; a whole workgroup per patch measured faster)
+    // (NWV == 1: one wave per patch, synchronised by wave barriers only)
     const int tid = NWV == 1 ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
     const int lane = threadIdx.x & 63, wave = NWV == 1 ? 0 : (int)(threadIdx.x >> 6);
     auto group_sync = [&]() {
