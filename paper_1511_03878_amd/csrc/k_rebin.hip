@@ -29,10 +29,9 @@ namespace pic {
 
 namespace {
 
-// threads of a scatter workgroup: 2-D, and 3-D (about a hundred arrivals per
-// patch, one per thread; measured faster than 256 beside the field update)
-constexpr int kRB = 256;
-constexpr int kRB3 = 128;
+// threads of a scatter workgroup (one arrival per thread; measured faster
+// than 256 beside the field update, in 2-D and 3-D)
+constexpr int kRB = 128;
 
 template <typename T, int ND, int NT>
 __global__ __launch_bounds__(NT) void k_rebin_count(const SimDev<T> *__restrict__ sims, int nsims,
@@ -678,8 +677,7 @@ static void launch_rebin_nd(const SimDev<T> *sims, int nsims, const int *patch_p
                           0, st, ev.start, nullptr, 0, sims, nsims, patch_prefix, total_patches);
     hipLaunchKernelGGL((k_rebin_check<T, ND>), dim3((total_patches + 255) / 256), dim3(256), 0, st,
                        sims, nsims, patch_prefix, total_patches);
-    constexpr int NB = ND == kNDir3 ? kRB3 : kRB;
-    hipExtLaunchKernelGGL((k_rebin_scatter<T, ND, NB>), dim3(grid), dim3(NB), 0, st, nullptr, ev.stop, 0,
+    hipExtLaunchKernelGGL((k_rebin_scatter<T, ND, kRB>), dim3(grid), dim3(kRB), 0, st, nullptr, ev.stop, 0,
                           sims, nsims, patch_prefix, total_patches);
 }
 

@@ -46,10 +46,10 @@ __device__ __forceinline__ void copy_particle(const SimDev<T> &S, int64_t from, 
 // the staged leavers are queued in a per-wave LDS ring, which is drained 64
 // entries at a time (one lane per particle, so the particle loads of 64
 // leavers are in flight together).
-// threads of the count workgroup: 2-D (measured: 256 and 1024 slower), and
-// 3-D, one wave per patch (about a hundred leavers per 8^3 patch; beside the
-// field update the small workgroups keep more patches in flight)
-constexpr int kRC = 512;
+// threads of the count workgroup: 2-D, and 3-D one wave per patch (about a
+// hundred leavers per 8^3 patch); measured beside the field update, smaller
+// workgroups keep more patches in flight (2-D: 512 and 128 slower than 256)
+constexpr int kRC = 256;
 constexpr int kRC3 = 64;
 constexpr int kU = 16;    // 64-slot chunks per batch of code loads (63 VGPRs: 8 waves per SIMD)
 constexpr int kRing = 128;
