@@ -112,12 +112,22 @@ int particles3d_occupancy(int block, int maxP0, int maxP1, int maxP2, int shape)
 size_t particles3d_lds_bytes(int precision, int P0, int P1, int P2);
 int particles3d_shape(int P0, int P1, int P2);
 
-// 3-D Yee update on a periodic box (three passes; tiles are blocks of 256
-// nodes), with the field energy of the incoming E, B per tile.
+// 3-D field update on a periodic box, with the field energy of the incoming
+// E, B per tile.  Yee: one fused kernel over blocks of kYee3X x kYee3Y x
+// kYee3Z nodes; sixth order: three passes over runs of kMaxwell3dTile nodes.
+// yee / hi_order: the batch holds simulations of that solver.
 template <typename T>
 void launch_maxwell3d(const SimDev<T> *sims, int nsims, const int *tile_prefix, int total_tiles,
-                      int grid, hipStream_t st, Ev2 ev = {});
+                      int grid, bool yee, bool hi_order, hipStream_t st, Ev2 ev = {});
 constexpr int kMaxwell3dTile = 256;
+constexpr int kYee3X = 16, kYee3Y = 8, kYee3Z = 8;
+// field-update tiles of a 3-D simulation with fn nodes per axis
+inline int64_t maxwell3d_tiles(const int fn[3], int order)
+{
+    if (order == 6) return ((int64_t)fn[0] * fn[1] * fn[2] + kMaxwell3dTile - 1) / kMaxwell3dTile;
+    return (int64_t)((fn[0] + kYee3X - 1) / kYee3X) * ((fn[1] + kYee3Y - 1) / kYee3Y) *
+           ((fn[2] + kYee3Z - 1) / kYee3Z);
+}
 
 // Moving-window jump of one simulation (2-D): a no-op unless the step in
 // flight ends with a jump.  fn1 = field rows, npy = patch rows.

@@ -194,7 +194,7 @@ SimImpl<T>::SimImpl(const PicSimDesc &d, const PicAllocator *a, hipStream_t s)
         view_d = (SimDev<T> *)alloc.get(sizeof(SimDev<T>));
         // per-tile energy partials, sized for the smallest Yee tile preset (16 x 4)
         // in 2-D and for blocks of nodes in 3-D
-        max_tiles = nd == 3 ? (fsize + kMaxwell3dTile - 1) / kMaxwell3dTile
+        max_tiles = nd == 3 ? std::max(maxwell3d_tiles(fn, 2), maxwell3d_tiles(fn, 6))
                             : (int64_t)((fn[0] + 15) / 16) * ((fn[1] + 3) / 4);
         upart = (double *)alloc.get(sizeof(double) * max_tiles);
         kpart = (double *)alloc.get(sizeof(double) * npatch);
@@ -1773,7 +1773,7 @@ void BatchImpl<T>::build_tables()
         SimImpl<T> *m = members[i];
         pp[i + 1] = pp[i] + m->npatch;
         // Yee tiles: TX x TY node tiles in 2-D, blocks of nodes in 3-D
-        const int ntiles = nd == 3 ? (int)((m->fsize + kMaxwell3dTile - 1) / kMaxwell3dTile)
+        const int ntiles = nd == 3 ? (int)maxwell3d_tiles(m->fn, m->desc.maxwell_order)
                                    : ((m->fn[0] + tx - 1) / tx) * ((m->fn[1] + ty - 1) / ty);
         tp[i + 1] = tp[i] + ntiles;
         const int own[2] = {0, ntiles};
@@ -1959,7 +1959,8 @@ void BatchImpl<T>::launch_one_step()
         fs = side_stream;
     }
     if (nd == 3)
-        launch_maxwell3d<T>(sims_d, ns, tile_prefix_d, total_tiles, grid_maxwell, fs, tm.pair(2));
+        launch_maxwell3d<T>(sims_d, ns, tile_prefix_d, total_tiles, grid_maxwell, yee_any, hi_order, fs,
+                            tm.pair(2));
     else
         launch_maxwell<T>(sims_d, ns, tile_prefix_d, total_tiles, grid_maxwell, tile_preset, yee_any, hi_order,
                           fs, tm.pair(2));

@@ -45,6 +45,45 @@ def test_blob3d_fp64_ten_steps_match_oracle():
     assert abs(U[0] - Uo) <= 1e-10 * abs(Uo) and abs(K[0] - Ko) <= 1e-10 * abs(Ko)
 
 
+def test_fields3d_blocks_with_ragged_edges_match_oracle_fp64():
+    # vacuum fields on a grid that no axis divides into whole field-update
+    # blocks (16 x 8 x 8 nodes): the last block of each axis is partial and
+    # its halo wraps round the periodic box
+    _announce("3-D vacuum fields 24x12x20 fp64, 12 steps")
+    grid = dict(ndim=3, n=[24, 12, 20], d=[0.1, 0.13, 0.11], dt=W.cfl_dt((0.1, 0.13, 0.11)),
+                patch=[4, 4, 4], periodic=[1, 1, 1], q=-1.0, m=1.0)
+    from paper_1511_03878_amd.sim import Sim
+    g = Sim(grid, 64)
+    g.set_particles([np.zeros(0)] * 3, [np.zeros(0)] * 3, np.zeros(0))
+    o = oracle.Sim(grid)
+    rng = np.random.default_rng(12)
+    for c in ("Ex", "Ey", "Ez", "Bx", "By", "Bz"):
+        f = rng.standard_normal((20, 12, 24))
+        g.set_field(c, f)
+        o.set_field(c, f)
+    g.step(12)
+    o.step(12)
+    e, b = compare_fields(g, o)
+    assert e < 1e-12 and b < 1e-12, (e, b)
+    U, _, _ = g.history(11, 1)
+    Uo, _ = o.energy()
+    assert abs(U[0] - Uo) <= 1e-12 * abs(Uo)
+
+
+def test_blob3d_ragged_blocks_fp64_five_steps_match_oracle():
+    _announce("3-D blob 24x12x20, 4x4x4 patches, fp64, 5 steps")
+    wl = W.blob_3d(n=(24, 12, 20), d=(0.1, 0.1, 0.1), patch=(4, 4, 4), ppc0=2, blob_radius=3.0, T_keV=20.0)
+    g = gpu_sim(wl, 64)
+    g.step(5)
+    o = oracle_run(wl, 5)
+    e, b = compare_fields(g, o)
+    assert e < 1e-11 and b < 1e-11, (e, b)
+    assert np.array_equal(g.counts(), o.counts())
+    J = [g.field(c) for c in ("Jx", "Jy", "Jz")]
+    Jo = [o.field(c) for c in ("Jx", "Jy", "Jz")]
+    assert rel_l2(J, Jo) < 1e-11
+
+
 def test_blob3d_cubic_patches_fp32_one_step():
     _announce("3-D blob 32x16x16, 8x8x8 patches, fp32, 1 step")
     wl = W.to_float32_state(_blob(patch=(8, 8, 8)))
