@@ -468,7 +468,9 @@ int pic_estimate_bytes(const PicSimDesc *d, int64_t nparticles, int64_t laser_st
     // particles + staging (3-D: position with the id and momentum with the
     // weight, four entries each; 2-D: six entries and the id), code, hole list
     const int64_t per_slot = 2 * (three ? 8 * s : 6 * s + 8) + 1 + 4;
-    const int64_t max_tiles = three ? (fsize + 255) / 256 : ((fx + 15) / 16) * ((fy + 3) / 4);
+    const int fn3[3] = {(int)fx, (int)fy, (int)fz};
+    const int64_t max_tiles = three ? std::max(maxwell3d_tiles(fn3, 2), maxwell3d_tiles(fn3, 6))
+                                    : ((fx + 15) / 16) * ((fy + 3) / 4);
     int64_t b = 18 * fsize * s;                        // two E, B buffers, two J buffers
     b += slots * per_slot;
     // counts, keys, neighbour table, partials, offsets
