@@ -1947,11 +1947,8 @@ void BatchImpl<T>::launch_one_step()
     // deterministic members: fixed-point accumulators -> J[step & 1]
     if (ndet) launch_jfix<T>(sims_d, det_list_d, det_prefix_d, ndet, det_nodes, stream);
     // the field update (fields, currents, tile energies) and the re-binning
-    // (particles, counts) touch disjoint data: in 2-D they run side by side;
-    // in 3-D the re-binning's one-wave count workgroups fill the chip and the
-    // two measured faster one after the other (17.45 against 17.70 ms per
-    // step on the 3-D blob box)
-    const bool fork = nd != 3 && ensure_side();
+    // (particles, counts) touch disjoint data: run them side by side
+    const bool fork = ensure_side();
     hipStream_t fs = stream;
     if (fork) {
         hipcheck(hipEventRecord(ev_fork, stream), "fork");
