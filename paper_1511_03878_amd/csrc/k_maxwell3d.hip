@@ -190,38 +190,40 @@ __global__ __launch_bounds__(kMB) void k_maxwell3d_e(const SimDev<T> *__restrict
     }
 }
 
-// ---- fused Yee update of a block of nodes -------------------------------------
+// ---- fused Yee update of a column of node planes ------------------------------
 //
-// Block [X, X + BX) x [Y, Y + BY) x [Z, Z + BZ) of the nodes.  E is staged on
-// [X - 1, X + BX + 2) per axis and B on [X - 1, X + BX + 1) (periodic, so a
-// block at the grid's end reads its halo from the start), then in LDS
-//   B' = B - dt/2 curl E          on the whole B tile (in place),
-//   E' = E + dt (curl B' - J)     on [X, X + BX + 1) per axis (in place; J
-//                                  is loaded into registers with the tiles),
-//   B'' = B' - dt/2 curl E'       on the block,
-// and E', B'' of the block are written to the other field buffer and the
-// block's nodes of the other J buffer cleared: the three passes' arithmetic
-// in the same order, with HBM reads of E, B and J once per node plus the
-// halo.  Both tiles start at X - 1, so a node has the same local coordinates
-// in each.  Nodes of a block past the grid's end (n not a multiple of the
-// block) are computed from wrapped data and not written.
-constexpr int kYT = 256;                                          // threads
-constexpr int kEX = kYee3X + 3, kEY = kYee3Y + 3, kEZ = kYee3Z + 3;  // E tile
-constexpr int kBX = kYee3X + 2, kBY = kYee3Y + 2, kBZ = kYee3Z + 2;  // B tile
-constexpr int kEN = kEX * kEY * kEZ, kBN = kBX * kBY * kBZ;
-constexpr int kE2X = kYee3X + 1, kE2Y = kYee3Y + 1, kE2Z = kYee3Z + 1;  // E' nodes
-constexpr int kE2N = kE2X * kE2Y * kE2Z;
-constexpr int kON = kYee3X * kYee3Y * kYee3Z;  // the block's own nodes
-constexpr int kRE = (kEN + kYT - 1) / kYT, kRB = (kBN + kYT - 1) / kYT, kRJ = (kE2N + kYT - 1) / kYT;
-static_assert(kON % kYT == 0, "own nodes per thread");
+// Block [X, X + BX) x [Y, Y + BY) x [Z, Z + BZ) of the nodes, taken plane by
+// plane along z.  Per plane, E is staged on [X - 1, X + BX + 2) x [Y - 1,
+// Y + BY + 2) and B on [X - 1, X + BX + 1) x [Y - 1, Y + BY + 1) (periodic,
+// so a block at the grid's end reads its halo from the start); three E
+// planes (z, z + 1, z + 2) and two B planes (z, z + 1) rotate in LDS.  For
+// output plane z:
+//   B' = B - dt/2 curl E        on plane z + 1 (in place; needs E of z + 1, z + 2),
+//   E' = E + dt (curl B' - J)   on plane z + 1 over [X, X + BX + 1) x [Y, Y + BY + 1)
+//                                (in place; needs B' of z, z + 1; J loaded per node),
+//   B'' = B' - dt/2 curl E'     on plane z over the block (needs E' of z, z + 1),
+// and E', B'' of plane z are written to the other field buffer and its nodes
+// of the other J buffer cleared: the three passes' arithmetic in the same
+// order, reading E, B and J once per node plus an x-y halo (z needs none
+// beyond the two planes before the first).  Both plane tiles start at X - 1,
+// Y - 1, so a node has the same local coordinates in each.  Nodes past the
+// grid's end (n not a multiple of the block) are computed from wrapped data
+// and not written.
+constexpr int kYT = 256;                              // threads
+constexpr int kEX = kYee3X + 3, kEY = kYee3Y + 3;     // E plane tile
+constexpr int kBX = kYee3X + 2, kBY = kYee3Y + 2;     // B plane tile
+constexpr int kE2X = kYee3X + 1, kE2Y = kYee3Y + 1;   // E' nodes of a plane
+constexpr int kEP = kEX * kEY, kBP = kBX * kBY, kE2P = kE2X * kE2Y, kOP = kYee3X * kYee3Y;
+constexpr int kRE = (kEP + kYT - 1) / kYT, kRB = (kBP + kYT - 1) / kYT, kRJ = (kE2P + kYT - 1) / kYT;
+static_assert(kOP % kYT == 0, "own nodes of a plane per thread");
 
 template <typename T>
 __global__ __launch_bounds__(kYT) void k_maxwell3d_yee(const SimDev<T> *__restrict__ sims, int nsims,
                                                        const int *__restrict__ tile_prefix, int total)
 {
-    __shared__ T sE[3][kEN];
-    __shared__ T sB[3][kBN];
-    __shared__ int s_wrap[kEX + kEY + kEZ];  // wrapped node index of each local index, per axis
+    __shared__ T sE[3][3][kEP];  // [plane slot][component][node]
+    __shared__ T sB[2][3][kBP];
+    __shared__ int s_wrap[kEX + kEY];  // wrapped node index of each local index, x then y
     __shared__ double s_red[kYT / 64];
     const int tid = threadIdx.x;
     const TileWalk tw = tile_walk(total);
@@ -232,9 +234,9 @@ __global__ __launch_bounds__(kYT) void k_maxwell3d_yee(const SimDev<T> *__restri
         const int lt = tile - tile_prefix[s];
         const int fn0 = S.fn[0], fn1 = S.fn[1], fn2 = S.fn[2];
         const int nbx = (fn0 + kYee3X - 1) / kYee3X, nby = (fn1 + kYee3Y - 1) / kYee3Y;
-        // global index of local index 0 on each axis
-        const int x0 = (lt % nbx) * kYee3X - 1, y0 = ((lt / nbx) % nby) * kYee3Y - 1,
-                  z0 = (lt / (nbx * nby)) * kYee3Z - 1;
+        // global index of local index 0 along x and y; the block's planes
+        const int x0 = (lt % nbx) * kYee3X - 1, y0 = ((lt / nbx) % nby) * kYee3Y - 1;
+        const int zs = (lt / (nbx * nby)) * kYee3Z, ze = min(zs + kYee3Z, fn2);
         const int64_t stepn = glb(S.st)->step;
         T *const *Fc = S.F[stepn & 1];
         T *const *Fn = S.F[(stepn + 1) & 1];
@@ -242,120 +244,105 @@ __global__ __launch_bounds__(kYT) void k_maxwell3d_yee(const SimDev<T> *__restri
         T *const *Jn = S.J[(stepn + 1) & 1];
         const T dt = S.dt, h = T(0.5) * S.dt;
         const T ix = T(1) / S.d[0], iy = T(1) / S.d[1], iz = T(1) / S.d[2];
-        for (int i = tid; i < kEX + kEY + kEZ; i += kYT) {
-            int g, n;
-            if (i < kEX) {
-                g = x0 + i;
-                n = fn0;
-            } else if (i < kEX + kEY) {
-                g = y0 + i - kEX;
-                n = fn1;
-            } else {
-                g = z0 + i - kEX - kEY;
-                n = fn2;
-            }
-            g %= n;
+        for (int i = tid; i < kEX + kEY; i += kYT) {
+            const int n = i < kEX ? fn0 : fn1;
+            int g = (i < kEX ? x0 + i : y0 + i - kEX) % n;
             s_wrap[i] = g < 0 ? g + n : g;
         }
         __syncthreads();
-        const int *wx = s_wrap, *wy = s_wrap + kEX, *wz = s_wrap + kEX + kEY;
-        auto gidx = [&](int lx, int ly, int lz) {
-            return ((int64_t)wz[lz] * fn1 + wy[ly]) * fn0 + wx[lx];
+        const int *wx = s_wrap, *wy = s_wrap + kEX;
+        auto zrow = [&](int z) {  // first node of wrapped plane z, in rows of fn0
+            z %= fn2;
+            return (int64_t)(z < 0 ? z + fn2 : z) * fn1;
         };
-        // ---- stage E, B; J of the E' nodes into registers (every load from an
-        // in-range index; duplicates write the same value) -------------------------
-        {
-            const gptr_t<const T> E0 = glb((const T *)Fc[0]), E1 = glb((const T *)Fc[1]),
-                                  E2 = glb((const T *)Fc[2]);
+        // stage plane z of E (or B) into slot sl (every load from an in-range
+        // index; duplicates write the same value)
+        auto load_e = [&](int sl, int z) {
+            const int64_t zr = zrow(z);
 #pragma unroll
             for (int r = 0; r < kRE; ++r) {
-                const int i = min(tid + r * kYT, kEN - 1);
-                const int64_t g = gidx(i % kEX, (i / kEX) % kEY, i / (kEX * kEY));
-                sE[0][i] = E0[g];
-                sE[1][i] = E1[g];
-                sE[2][i] = E2[g];
+                const int i = min(tid + r * kYT, kEP - 1);
+                const int64_t g = (zr + wy[i / kEX]) * fn0 + wx[i % kEX];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) sE[sl][c][i] = glb((const T *)Fc[c])[g];
             }
-            const gptr_t<const T> B0 = glb((const T *)Fc[3]), B1 = glb((const T *)Fc[4]),
-                                  B2 = glb((const T *)Fc[5]);
+        };
+        auto load_b = [&](int sl, int z) {
+            const int64_t zr = zrow(z);
 #pragma unroll
             for (int r = 0; r < kRB; ++r) {
-                const int i = min(tid + r * kYT, kBN - 1);
-                const int64_t g = gidx(i % kBX, (i / kBX) % kBY, i / (kBX * kBY));
-                sB[0][i] = B0[g];
-                sB[1][i] = B1[g];
-                sB[2][i] = B2[g];
+                const int i = min(tid + r * kYT, kBP - 1);
+                const int64_t g = (zr + wy[i / kBX]) * fn0 + wx[i % kBX];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) sB[sl][c][i] = glb((const T *)Fc[3 + c])[g];
             }
-        }
+        };
+        // J of plane z at the E' nodes, into registers
         T jr[3][kRJ];
-        {
-            const gptr_t<const T> J0 = glb((const T *)Jc[0]), J1 = glb((const T *)Jc[1]),
-                                  J2 = glb((const T *)Jc[2]);
+        auto load_j = [&](int z) {
+            const int64_t zr = zrow(z);
 #pragma unroll
             for (int r = 0; r < kRJ; ++r) {
-                const int j = min(tid + r * kYT, kE2N - 1);
-                const int64_t g = gidx(j % kE2X + 1, (j / kE2X) % kE2Y + 1, j / (kE2X * kE2Y) + 1);
-                jr[0][r] = J0[g];
-                jr[1][r] = J1[g];
-                jr[2][r] = J2[g];
+                const int j = min(tid + r * kYT, kE2P - 1);
+                const int64_t g = (zr + wy[j / kE2X + 1]) * fn0 + wx[j % kE2X + 1];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) jr[c][r] = glb((const T *)Jc[c])[g];
             }
-        }
-        __syncthreads();
-
-        // ---- B' on the B tile, and the energy of E^n, B^n over the block ----------
+        };
+        // B' of the plane in B slot bs from E slots ec (same plane) and en (the
+        // next); with `own`, the energy of the plane's incoming E, B over the block
         double esum = 0.0;
+        auto bprime = [&](int bs, int ec, int en, bool own_plane) {
 #pragma unroll
-        for (int r = 0; r < kRB; ++r) {
-            const int i = tid + r * kYT;
-            if (i < kBN) {
-                const int lx = i % kBX, ly = (i / kBX) % kBY, lz = i / (kBX * kBY);
-                const int e = (lz * kEY + ly) * kEX + lx;
-                const T ex = sE[0][e], ey = sE[1][e], ez = sE[2][e];
-                const T bx = sB[0][i], by = sB[1][i], bz = sB[2][i];
-                const bool own = lx >= 1 && lx <= kYee3X && ly >= 1 && ly <= kYee3Y && lz >= 1 &&
-                                 lz <= kYee3Z && x0 + lx < fn0 && y0 + ly < fn1 && z0 + lz < fn2;
-                if (own)
-                    esum += (double)ex * ex + (double)ey * ey + (double)ez * ez + (double)bx * bx +
-                            (double)by * by + (double)bz * bz;
-                sB[0][i] = bx - h * ((sE[2][e + kEX] - ez) * iy - (sE[1][e + kEX * kEY] - ey) * iz);
-                sB[1][i] = by - h * ((sE[0][e + kEX * kEY] - ex) * iz - (sE[2][e + 1] - ez) * ix);
-                sB[2][i] = bz - h * ((sE[1][e + 1] - ey) * ix - (sE[0][e + kEX] - ex) * iy);
+            for (int r = 0; r < kRB; ++r) {
+                const int i = tid + r * kYT;
+                if (i < kBP) {
+                    const int lx = i % kBX, ly = i / kBX;
+                    const int e = ly * kEX + lx;
+                    const T ex = sE[ec][0][e], ey = sE[ec][1][e], ez = sE[ec][2][e];
+                    const T bx = sB[bs][0][i], by = sB[bs][1][i], bz = sB[bs][2][i];
+                    if (own_plane && lx >= 1 && lx <= kYee3X && ly >= 1 && ly <= kYee3Y && x0 + lx < fn0 &&
+                        y0 + ly < fn1)
+                        esum += (double)ex * ex + (double)ey * ey + (double)ez * ez + (double)bx * bx +
+                                (double)by * by + (double)bz * bz;
+                    sB[bs][0][i] = bx - h * ((sE[ec][2][e + kEX] - ez) * iy - (sE[en][1][e] - ey) * iz);
+                    sB[bs][1][i] = by - h * ((sE[en][0][e] - ex) * iz - (sE[ec][2][e + 1] - ez) * ix);
+                    sB[bs][2][i] = bz - h * ((sE[ec][1][e + 1] - ey) * ix - (sE[ec][0][e + kEX] - ex) * iy);
+                }
             }
-        }
-        __syncthreads();
-
-        // ---- E' on [X, X + BX + 1) per axis -----------------------------------------
+        };
+        // E' of the plane in E slot es from B' slots bc (same plane) and bp (the previous)
+        auto eprime = [&](int es, int bc, int bp) {
 #pragma unroll
-        for (int r = 0; r < kRJ; ++r) {
-            const int j = tid + r * kYT;
-            if (j < kE2N) {
-                const int lx = j % kE2X + 1, ly = (j / kE2X) % kE2Y + 1, lz = j / (kE2X * kE2Y) + 1;
-                const int e = (lz * kEY + ly) * kEX + lx;
-                const int b = (lz * kBY + ly) * kBX + lx;
-                const T bx = sB[0][b], by = sB[1][b], bz = sB[2][b];
-                sE[0][e] = sE[0][e] + dt * ((bz - sB[2][b - kBX]) * iy - (by - sB[1][b - kBX * kBY]) * iz - jr[0][r]);
-                sE[1][e] = sE[1][e] + dt * ((bx - sB[0][b - kBX * kBY]) * iz - (bz - sB[2][b - 1]) * ix - jr[1][r]);
-                sE[2][e] = sE[2][e] + dt * ((by - sB[1][b - 1]) * ix - (bx - sB[0][b - kBX]) * iy - jr[2][r]);
+            for (int r = 0; r < kRJ; ++r) {
+                const int j = tid + r * kYT;
+                if (j < kE2P) {
+                    const int lx = j % kE2X + 1, ly = j / kE2X + 1;
+                    const int e = ly * kEX + lx, b = ly * kBX + lx;
+                    const T bx = sB[bc][0][b], by = sB[bc][1][b], bz = sB[bc][2][b];
+                    sE[es][0][e] = sE[es][0][e] + dt * ((bz - sB[bc][2][b - kBX]) * iy - (by - sB[bp][1][b]) * iz - jr[0][r]);
+                    sE[es][1][e] = sE[es][1][e] + dt * ((bx - sB[bp][0][b]) * iz - (bz - sB[bc][2][b - 1]) * ix - jr[1][r]);
+                    sE[es][2][e] = sE[es][2][e] + dt * ((by - sB[bc][1][b - 1]) * ix - (bx - sB[bc][0][b - kBX]) * iy - jr[2][r]);
+                }
             }
-        }
-        __syncthreads();
-
-        // ---- B'' on the block; write E', B'' and clear the other J ---------------
-        {
+        };
+        // B'' of plane z from B' (slot bc) and E' of planes z (ec), z + 1 (en);
+        // write E', B'' and clear the other J
+        auto write_plane = [&](int z, int ec, int en, int bc) {
             const gptr_t<T> E0 = glb(Fn[0]), E1 = glb(Fn[1]), E2 = glb(Fn[2]);
             const gptr_t<T> B0 = glb(Fn[3]), B1 = glb(Fn[4]), B2 = glb(Fn[5]);
             const gptr_t<T> J0 = glb(Jn[0]), J1 = glb(Jn[1]), J2 = glb(Jn[2]);
 #pragma unroll
-            for (int r = 0; r < kON / kYT; ++r) {
+            for (int r = 0; r < kOP / kYT; ++r) {
                 const int o = tid + r * kYT;
-                const int lx = o % kYee3X + 1, ly = (o / kYee3X) % kYee3Y + 1, lz = o / (kYee3X * kYee3Y) + 1;
-                if (x0 + lx >= fn0 || y0 + ly >= fn1 || z0 + lz >= fn2) continue;
-                const int e = (lz * kEY + ly) * kEX + lx;
-                const int b = (lz * kBY + ly) * kBX + lx;
-                const T ex = sE[0][e], ey = sE[1][e], ez = sE[2][e];
-                const int64_t g = ((int64_t)(z0 + lz) * fn1 + (y0 + ly)) * fn0 + (x0 + lx);
-                B0[g] = sB[0][b] - h * ((sE[2][e + kEX] - ez) * iy - (sE[1][e + kEX * kEY] - ey) * iz);
-                B1[g] = sB[1][b] - h * ((sE[0][e + kEX * kEY] - ex) * iz - (sE[2][e + 1] - ez) * ix);
-                B2[g] = sB[2][b] - h * ((sE[1][e + 1] - ey) * ix - (sE[0][e + kEX] - ex) * iy);
+                const int lx = o % kYee3X + 1, ly = o / kYee3X + 1;
+                if (x0 + lx >= fn0 || y0 + ly >= fn1) continue;
+                const int e = ly * kEX + lx, b = ly * kBX + lx;
+                const T ex = sE[ec][0][e], ey = sE[ec][1][e], ez = sE[ec][2][e];
+                const int64_t g = ((int64_t)z * fn1 + (y0 + ly)) * fn0 + (x0 + lx);
+                B0[g] = sB[bc][0][b] - h * ((sE[ec][2][e + kEX] - ez) * iy - (sE[en][1][e] - ey) * iz);
+                B1[g] = sB[bc][1][b] - h * ((sE[en][0][e] - ex) * iz - (sE[ec][2][e + 1] - ez) * ix);
+                B2[g] = sB[bc][2][b] - h * ((sE[ec][1][e + 1] - ey) * ix - (sE[ec][0][e + kEX] - ex) * iy);
                 E0[g] = ex;
                 E1[g] = ey;
                 E2[g] = ez;
@@ -363,6 +350,41 @@ __global__ __launch_bounds__(kYT) void k_maxwell3d_yee(const SimDev<T> *__restri
                 J1[g] = T(0);
                 J2[g] = T(0);
             }
+        };
+
+        // ---- first plane: E of zs - 1 .. zs + 1, B of zs - 1, zs, J of zs ---------
+        load_e(0, zs - 1);
+        load_e(1, zs);
+        load_e(2, zs + 1);
+        load_b(0, zs - 1);
+        load_b(1, zs);
+        load_j(zs);
+        __syncthreads();
+        bprime(0, 0, 1, false);  // B'(zs - 1)
+        bprime(1, 1, 2, true);   // B'(zs), energy of plane zs
+        __syncthreads();
+        eprime(1, 1, 0);  // E'(zs)
+        __syncthreads();
+        // E slots: ec = E'(z), en = E(z + 1) raw, ef free; B slots: bc = B'(z), bf free
+        int ec = 1, en = 2, ef = 0, bc = 1, bf = 0;
+        for (int z = zs; z < ze; ++z) {
+            load_e(ef, z + 2);
+            load_b(bf, z + 1);
+            load_j(z + 1);
+            __syncthreads();
+            bprime(bf, en, ef, z + 1 < ze);  // B'(z + 1)
+            __syncthreads();
+            eprime(en, bf, bc);  // E'(z + 1)
+            __syncthreads();
+            write_plane(z, ec, en, bc);
+            __syncthreads();  // before the next planes are loaded into the freed slots
+            const int t = ec;
+            ec = en;
+            en = ef;
+            ef = t;
+            const int u = bc;
+            bc = bf;
+            bf = u;
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) esum += __shfl_xor(esum, o, 64);
@@ -373,7 +395,7 @@ __global__ __launch_bounds__(kYT) void k_maxwell3d_yee(const SimDev<T> *__restri
             for (int w = 0; w < kYT / 64; ++w) tot += s_red[w];
             glb(S.upart)[lt] = 0.5 * S.vcell * tot;
         }
-        // (the next block's wrap table and tiles are written after the
+        // (the next block's wrap table and planes are written after the
         // barrier that follows it)
     }
 }

@@ -114,13 +114,14 @@ int particles3d_shape(int P0, int P1, int P2);
 
 // 3-D field update on a periodic box, with the field energy of the incoming
 // E, B per tile.  Yee: one fused kernel over blocks of kYee3X x kYee3Y x
-// kYee3Z nodes; sixth order: three passes over runs of kMaxwell3dTile nodes.
+// kYee3Z nodes, taken plane by plane along z; sixth order: three passes over
+// runs of kMaxwell3dTile nodes.
 // yee / hi_order: the batch holds simulations of that solver.
 template <typename T>
 void launch_maxwell3d(const SimDev<T> *sims, int nsims, const int *tile_prefix, int total_tiles,
                       int grid, bool yee, bool hi_order, hipStream_t st, Ev2 ev = {});
 constexpr int kMaxwell3dTile = 256;
-constexpr int kYee3X = 16, kYee3Y = 8, kYee3Z = 8;
+constexpr int kYee3X = 32, kYee3Y = 8, kYee3Z = 32;
 // field-update tiles of a 3-D simulation with fn nodes per axis
 inline int64_t maxwell3d_tiles(const int fn[3], int order)
 {
