@@ -47,7 +47,7 @@ def test_blob3d_fp64_ten_steps_match_oracle():
 
 def test_fields3d_blocks_with_ragged_edges_match_oracle_fp64():
     # vacuum fields on a grid that no axis divides into whole field-update
-    # blocks (16 x 8 x 8 nodes): the last block of each axis is partial and
+    # blocks (32 x 8 x 32 nodes): the last block of each axis is partial and
     # its halo wraps round the periodic box
     _announce("3-D vacuum fields 24x12x20 fp64, 12 steps")
     grid = dict(ndim=3, n=[24, 12, 20], d=[0.1, 0.13, 0.11], dt=W.cfl_dt((0.1, 0.13, 0.11)),
